@@ -1,0 +1,207 @@
+"""Blind-Match on top of the oracle CKKS: packing, Alg. 1 (Input Ciphertext
+Expansion), Alg. 2 (HE-C^3), scores and top-1.
+
+TEST INFRASTRUCTURE ONLY (see ckks.py).
+
+Notation follows the paper (Sec. 3.3-3.4): m = d is the feature length,
+N_in = k the number of parts, c = m / N_in the chunk length.  Slots are
+0-indexed.  Readings of passages the paper leaves open:
+
+  * the query is tiled into every slot, slot s holding q[s mod d];
+  * mask_i (Sec. 3.3.1, the redefined mask) is periodic in d with ones where
+    floor((s mod d) / c) == i, encoded at scale q_top so that the rescale after
+    Mul(P) returns the scale to exactly Delta;
+  * Alg. 1 is read 0-indexed: for i < k and t < log2 k, rotate by -c 2^t when
+    bit t of i is 0 and by +c 2^t when it is 1, adding after each rotation;
+  * the accumulator of Alg. 2 starts as the trivial zero ciphertext;
+  * schedule S1 is Alg. 2 as printed (relinearise and rescale every part);
+    S2 sums the degree-2 tensors of all parts and relinearises and rescales
+    once (same message, different rounding, so different bits).
+  * gallery group g, part i, slot s holds x_{g T + floor(s/c)}[i c + s mod c],
+    T = n / c templates per group, zeros past the last template; the score of
+    template g T + b is read at slot b c of group g's output.
+"""
+import math
+
+import numpy as np
+
+from . import ckks
+
+S1, S2 = 1, 2
+
+
+def log2_exact(v):
+    e = int(v).bit_length() - 1
+    if v <= 0 or (1 << e) != v:
+        raise ValueError("%d is not a power of two" % v)
+    return e
+
+
+def layout(params, d, k):
+    log2_exact(d)
+    log2_exact(k)
+    if d % k or d > params.n:
+        raise ValueError("need k | d and d <= n")
+    c = d // k
+    T = params.n // c
+    return c, T
+
+
+def rotations_needed(params, d, k):
+    """Rotation amounts Alg. 1 and Alg. 2 use for one (d, k) shape."""
+    c, _ = layout(params, d, k)
+    rots = [1 << t for t in range(log2_exact(c))]
+    for t in range(log2_exact(k)):
+        rots += [c << t, -(c << t)]
+    return rots
+
+
+def pack_query(params, q, d):
+    q = np.asarray(q, dtype=np.float64)
+    s = np.arange(params.n)
+    return q[s % d]
+
+
+def pack_gallery(params, X, d, k):
+    """List over groups of k slot vectors (real, length n)."""
+    X = np.asarray(X, dtype=np.float64)
+    R = X.shape[0]
+    c, T = layout(params, d, k)
+    G = -(-R // T)
+    s = np.arange(params.n)
+    b, u = s // c, s % c
+    groups = []
+    for g in range(G):
+        parts = []
+        for i in range(k):
+            tid = g * T + b
+            valid = tid < R
+            v = np.zeros(params.n)
+            v[valid] = X[tid[valid], i * c + u[valid]]
+            parts.append(v)
+        groups.append(parts)
+    return groups
+
+
+def mask_slots(params, d, k, i):
+    c, _ = layout(params, d, k)
+    s = np.arange(params.n)
+    return ((s % d) // c == i).astype(np.float64)
+
+
+def mask_coeffs(params, d, k, limbs_query):
+    """Integer plaintexts of mask_0..mask_{k-1} at scale q_top of the query."""
+    qtop = params.q[limbs_query - 1]
+    return [ckks.encode(mask_slots(params, d, k, i), float(qtop), params.N) for i in range(k)], \
+        float(qtop)
+
+
+def gallery_limbs(params, k):
+    return len(params.q) if k == 1 else len(params.q) - 1
+
+
+def encrypt_query_coeffs(params, keys, m, seed, ct_id):
+    return ckks.encrypt(params, keys.pk, m, len(params.q), params.scale, seed, ct_id)
+
+
+def expand(params, keys, cq, d, k, masks, mask_scale):
+    """Alg. 1: C_i = Res(Mul(P)(C_q, mask_i)), then log2 k rotate-and-add steps."""
+    c, _ = layout(params, d, k)
+    out = []
+    for i in range(k):
+        ci = ckks.rescale(params, ckks.pmul(params, cq, masks[i], mask_scale))
+        for t in range(log2_exact(k)):
+            r = c << t
+            step = -r if ((i >> t) & 1) == 0 else r
+            ci = ckks.hadd(params, ci, ckks.rotate(params, ci, step, keys.gks))
+        out.append(ci)
+    return out
+
+
+def hec3(params, keys, cu, cs, d, k, schedule):
+    """Alg. 2 on one gallery group: accumulate the products of the k parts,
+    then log2(c) steps of C_out += Rot(C_out, 2^t)."""
+    c, _ = layout(params, d, k)
+    acc = None
+    if schedule == S1:
+        for i in range(k):
+            term = ckks.rescale(params, ckks.relinearize(
+                params, ckks.tensor(params, cu[i], cs[i]), keys.rlk))
+            acc = term if acc is None else ckks.hadd(params, acc, term)
+    elif schedule == S2:
+        deg2 = None
+        for i in range(k):
+            t = ckks.tensor(params, cu[i], cs[i])
+            deg2 = t if deg2 is None else ckks.hadd(params, deg2, t)
+        acc = ckks.rescale(params, ckks.relinearize(params, deg2, keys.rlk))
+    else:
+        raise ValueError("schedule")
+    for t in range(log2_exact(c)):
+        acc = ckks.hadd(params, acc, ckks.rotate(params, acc, 1 << t, keys.gks))
+    return acc
+
+
+def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None,
+          out_limbs=None, groups=None):
+    """Whole server side: expansion (k > 1) then HE-C^3 per gallery group.
+    `gallery` is a list over groups of k ciphertexts.  Optionally only the
+    listed `groups` are evaluated (sampled parity at large sizes)."""
+    if k == 1:
+        cu = [cq]
+    else:
+        cu = expand(params, keys, cq, d, k, masks, mask_scale)
+    idx = range(len(gallery)) if groups is None else groups
+    outs = {}
+    for g in idx:
+        o = hec3(params, keys, cu, gallery[g], d, k, schedule)
+        if out_limbs is not None and out_limbs < o.limbs:
+            o = ckks.drop_limbs(o, out_limbs)
+        outs[g] = o
+    return outs
+
+
+def scores_from_slots(params, slots_by_group, d, k, R):
+    """Template g T + b is scored at slot b c of group g."""
+    c, T = layout(params, d, k)
+    out = np.full(R, np.nan)
+    for g, z in slots_by_group.items():
+        b = np.arange(T)
+        tid = g * T + b
+        ok = tid < R
+        out[tid[ok]] = np.real(z[b[ok] * c])
+    return out
+
+
+def top1(scores, threshold=None):
+    """Index of the largest score (lowest index on ties); -1 if it is below
+    the threshold (the client's rejection rule in Sec. 3.5)."""
+    s = np.asarray(scores, dtype=np.float64)
+    best = int(np.argmax(s))          # argmax returns the first maximal index
+    if threshold is not None and s[best] < threshold:
+        return -1, float(s[best])
+    return best, float(s[best])
+
+
+# --------------------------------------------------------------------------
+# the paper's cost model (Props. 1-3 and F(N_in), Sec. 4)
+# --------------------------------------------------------------------------
+
+TABLE1 = {  # Table 1: mean ms per op at N = 8192 for levels 3, 2, 1
+    3: dict(Add=0.44, MulC=7.87, MulP=1.25, Rot=7.50, Res=1.30),
+    2: dict(Add=0.33, MulC=5.49, MulP=0.97, Rot=5.33, Res=0.95),
+    1: dict(Add=0.09, MulC=3.13, MulP=0.76, Rot=2.95, Res=0.60),
+}
+
+
+def cost_F(n_in, m=128, m_prime=32, l=3, table=TABLE1):
+    """F(N_in): Prop. 1 (expansion) at levels l and l-1, Prop. 2 (HE-C^3) at
+    l-1 and l-2, Prop. 3 (compression) at l-2, as the combined formula of
+    Sec. 4 writes them."""
+    T = table
+    lg = math.log2
+    groups = math.ceil(m_prime / n_in)
+    exp_t = n_in * ((T[l]["MulP"] + T[l]["Res"]) + lg(n_in) * (T[l - 1]["Rot"] + T[l - 1]["Add"]))
+    hec3_t = groups * (n_in * (T[l - 1]["MulC"] + T[l - 1]["Res"] + T[l - 2]["Add"])
+                       + (lg(m) - lg(n_in)) * (T[l - 2]["Rot"] + T[l - 2]["Add"]))
+    comp_t = groups * (T[l - 2]["MulP"] + T[l - 2]["Rot"] + T[l - 2]["Add"])
+    return exp_t + hec3_t + comp_t

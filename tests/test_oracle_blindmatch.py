@@ -1,0 +1,171 @@
+"""Pins of the oracle's Blind-Match layer: the slot simulator, the FP64 cosine,
+the paper's packing example and cost-model values."""
+import os
+
+import numpy as np
+import pytest
+
+import slot_sim
+from oracle import ckks, blindmatch as bm
+from workloads import tiny_gallery
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(log_n=6):
+    base = ckks.PRESET_PRIMES[2]
+    return ckks.Params(log_n=log_n, q=base["q"], p=base["p"], alpha=2, log_scale=50)
+
+
+# ---------------------------------------------------------------- cost model
+
+def _read_golden():
+    table, F = {}, {}
+    with open(os.path.join(GOLDEN, "table1_cost_model.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            parts = line.split()
+            if parts[0] == "F":
+                F[int(parts[1])] = float(parts[2])
+            else:
+                lv = int(parts[0])
+                table[lv] = dict(zip(["Add", "MulC", "MulP", "Rot", "Res"], map(float, parts[1:])))
+    return table, F
+
+
+def test_cost_model_reproduces_printed_F():
+    table, F = _read_golden()
+    for n_in, want in F.items():
+        assert abs(bm.cost_F(n_in, m=128, m_prime=32, l=3, table=table) - want) < 5e-3
+    assert min(F, key=lambda k: bm.cost_F(k, table=table)) == 4
+
+
+def test_packing_example():
+    with open(os.path.join(GOLDEN, "packing_example.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    slots, m, n_in, want = map(int, rows[0])
+    # the paper's ring has `slots` real slots; templates per group = slots / (m / N_in)
+    assert slots // (m // n_in) == want
+
+
+# ---------------------------------------------------------------- slot simulator
+
+@pytest.mark.parametrize("d,k", [(8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (32, 16)])
+def test_slot_sim_expansion_tiles_chunks(d, k):
+    n = 64
+    rng = np.random.default_rng(d * 100 + k)
+    q = rng.standard_normal(d)
+    qs = q[np.arange(n) % d]
+    c = d // k
+    out = slot_sim.expand(qs, d, k)
+    for i in range(k):
+        assert np.allclose(out[i], q[i * c + np.arange(n) % c])
+
+
+@pytest.mark.parametrize("d,k", [(8, 1), (8, 2), (8, 8), (16, 4)])
+def test_slot_sim_hec3_gives_inner_products(d, k):
+    P = tiny(log_n=7)
+    n = P.n
+    rng = np.random.default_rng(d + k)
+    c, T = bm.layout(P, d, k)
+    X = rng.standard_normal((T, d))
+    q = rng.standard_normal(d)
+    gal = bm.pack_gallery(P, X, d, k)
+    assert len(gal) == 1
+    acc = slot_sim.hec3(slot_sim.expand(bm.pack_query(P, q, d), d, k), gal[0], d, k)
+    for b in range(T):
+        assert abs(acc[b * c] - X[b] @ q) < 1e-12
+
+
+def test_rotations_needed_cover_both_algorithms():
+    P = tiny(log_n=7)
+    # c = 4: Alg. 2 rotates by 1, 2; Alg. 1 by -+4 and -+8
+    assert sorted(bm.rotations_needed(P, 16, 4)) == sorted([1, 2, 4, -4, 8, -8])
+
+
+# ---------------------------------------------------------------- encrypted vs simulated
+
+@pytest.fixture(scope="module")
+def tiny_setup():
+    P = tiny(log_n=6)
+    rots = set()
+    for d, k in [(8, 1), (8, 2), (8, 4), (16, 4), (32, 1)]:
+        rots.update(bm.rotations_needed(P, d, k))
+    keys = ckks.keygen(P, 0xB11D, rotations=sorted(rots))
+    return P, keys
+
+
+@pytest.mark.parametrize("d,k,schedule", [(8, 1, bm.S1), (8, 2, bm.S1), (8, 2, bm.S2),
+                                          (8, 4, bm.S1), (8, 4, bm.S2), (16, 4, bm.S2)])
+def test_encrypted_match_equals_slot_sim(tiny_setup, d, k, schedule):
+    P, keys = tiny_setup
+    rng = np.random.default_rng(d * 7 + k + schedule)
+    c, T = bm.layout(P, d, k)
+    R = 2 * T - 1                                     # two groups, last one ragged
+    X = rng.standard_normal((R, d)) / np.sqrt(d)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    qslots = bm.pack_query(P, q, d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(qslots, P.scale, P.N), len(P.q), P.scale, 1, 1)
+    lg = bm.gallery_limbs(P, k)
+    gal_slots = bm.pack_gallery(P, X, d, k)
+    gallery = [[ckks.encrypt(P, keys.pk, ckks.encode(v, P.scale, P.N), lg, P.scale, 1, 100 + 10 * g + i)
+                for i, v in enumerate(parts)] for g, parts in enumerate(gal_slots)]
+    masks, mscale = bm.mask_coeffs(P, d, k, len(P.q))
+    outs = bm.match(P, keys, cq, gallery, d, k, schedule, masks, mscale, out_limbs=2)
+    sim_u = slot_sim.expand(qslots, d, k)
+    for g, o in outs.items():
+        assert o.limbs == 2
+        got = ckks.decrypt_decode(P, keys.s, o)
+        want = slot_sim.hec3(sim_u, gal_slots[g], d, k)
+        assert np.max(np.abs(got - want)) < 1e-8
+    scores = bm.scores_from_slots(P, {g: ckks.decrypt_decode(P, keys.s, o) for g, o in outs.items()},
+                                  d, k, R)
+    assert np.max(np.abs(scores - X @ q)) < 1e-8
+
+
+def test_full_vector_inner_product_special_case(tiny_setup):
+    """k = 1 and d = n: one template fills the ciphertext and the rotate-and-sum
+    is the textbook sum of all slots."""
+    P, keys = tiny_setup
+    d = P.n
+    rng = np.random.default_rng(99)
+    x = rng.standard_normal(d) / np.sqrt(d)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(q, P.scale, P.N), len(P.q), P.scale, 2, 1)
+    cx = ckks.encrypt(P, keys.pk, ckks.encode(x, P.scale, P.N), len(P.q), P.scale, 2, 2)
+    out = bm.hec3(P, keys, [cq], [cx], d, 1, bm.S1)
+    got = ckks.decrypt_decode(P, keys.s, out)
+    assert np.max(np.abs(got - np.sum(q * x))) < 1e-8
+
+
+def test_top1_rules():
+    assert bm.top1([0.1, 0.5, 0.5, 0.2]) == (1, 0.5)
+    assert bm.top1([0.1, 0.3], threshold=0.4)[0] == -1
+    assert bm.top1([0.1, 0.3], threshold=0.3)[0] == 1
+
+
+# ---------------------------------------------------------------- the N = 2^12 workload
+
+def test_c1_end_to_end_scores_and_top1():
+    P = ckks.Params.preset(1)
+    w = tiny_gallery(seed=1)
+    d, k = 16, 1
+    keys = ckks.keygen(P, 0xB11D, rotations=bm.rotations_needed(P, d, k))
+    X = w["gallery"].astype(np.float64)
+    for qv in (w["query"], w["query_known"]):
+        qv = qv.astype(np.float64)
+        cq = ckks.encrypt(P, keys.pk, ckks.encode(bm.pack_query(P, qv, d), P.scale, P.N),
+                          len(P.q), P.scale, 0xB11D, 1)
+        gal = bm.pack_gallery(P, X, d, k)
+        assert len(gal) == 1
+        gallery = [[ckks.encrypt(P, keys.pk, ckks.encode(gal[0][0], P.scale, P.N), len(P.q),
+                                 P.scale, 0xB11D, 1000)]]
+        outs = bm.match(P, keys, cq, gallery, d, k, bm.S1)
+        assert outs[0].limbs == 2
+        z = {0: ckks.decrypt_decode(P, keys.s, outs[0])}
+        scores = bm.scores_from_slots(P, z, d, k, X.shape[0])
+        cos = (X @ qv) / (np.linalg.norm(X, axis=1) * np.linalg.norm(qv))
+        assert np.max(np.abs(scores - cos)) < 1e-4
+        assert bm.top1(scores)[0] == int(np.argmax(cos))
+    assert bm.top1(scores)[0] == w["known"]
