@@ -1,0 +1,273 @@
+/*
+ * blindmatch.h -- C ABI of the MI355X Blind-Match library.
+ *
+ * Blind-Match (CIKM '24) identifies a biometric query against an enrolled
+ * gallery without decrypting either: the server evaluates a chunked cosine
+ * similarity in CKKS (Sec. 3.3: Input Ciphertext Expansion, Alg. 1, and
+ * HE-C^3, Alg. 2) and the client decrypts the scores, takes the arg-max and
+ * applies a threshold (Sec. 3.4 "Decryption").  This library runs the server
+ * side on one AMD Instinct MI355X (gfx950) with hand-written HIP kernels over
+ * RNS polynomials; keys, encryption and decryption are provided so that a
+ * single process can play client and server.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status: BM_OK (0) or a negative BM_E*
+ *     code.  No C++ exception crosses this boundary.  A context keeps the
+ *     text of its last error (bm_last_error).
+ *   - Handles (bm_ctx, bm_sk, ...) are created by the library and released by
+ *     the matching bm_*_free.  Freeing NULL is a no-op.  Every handle created
+ *     from a context must be freed before that context.
+ *   - Host buffers passed in are read (or written) only during the call.
+ *   - Ciphertexts, keys, galleries and results live in device memory (HBM)
+ *     owned by their handle.  Interchange with the host is in the COEFFICIENT
+ *     domain: words[comps][limbs][N], uint64, residue of limb l in [0, q_l).
+ *   - `stream` arguments are a hipStream_t (passed as void*) or NULL for the
+ *     context's own stream.  Calls that take a stream are asynchronous on it;
+ *     all other calls return with their device work finished.  One context is
+ *     single-threaded; changing the stream of a context first waits for the
+ *     previous stream.
+ *   - Ring degree N = 2^log_n, n = N/2 complex slots carrying real data; limb
+ *     l < L+1 is chain prime q_l, the K special primes follow.  A fresh
+ *     ciphertext has L+1 limbs; each rescale drops the last limb.
+ */
+#ifndef BLINDMATCH_H
+#define BLINDMATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BM_OK = 0,
+  BM_EINVAL = -1,   /* NULL handle or pointer, size mismatch, bad argument */
+  BM_EDIM = -2,     /* d or k not a power of two, k does not divide d, d > n */
+  BM_ELEVEL = -3,   /* too few limbs for the operation, or a level mismatch */
+  BM_ESCALE = -4,   /* Add of ciphertexts whose scales differ */
+  BM_ENOKEY = -5,   /* a needed Galois key is missing from the evaluation key */
+  BM_ENOMEM = -6,   /* device or host allocation failed */
+  BM_EBUDGET = -7,  /* serving: request exceeds the HBM budget */
+  BM_EDEVICE = -8,  /* HIP runtime error */
+  BM_EBUSY = -9     /* serving: queue full / ticket still pending */
+};
+
+enum { BM_S1 = 1, BM_S2 = 2 };   /* Alg. 2 schedules, see bm_match */
+
+typedef struct bm_ctx bm_ctx;
+typedef struct bm_sk bm_sk;
+typedef struct bm_pk bm_pk;
+typedef struct bm_evk bm_evk;
+typedef struct bm_ct bm_ct;
+typedef struct bm_masks bm_masks;
+typedef struct bm_gallery bm_gallery;
+typedef struct bm_result bm_result;
+typedef struct bm_server bm_server;
+
+/* Scheme parameters.  q[0..n_q-1] are the chain primes q_0..q_L (n_q = L+1),
+ * p[0..n_p-1] the special primes of hybrid key switching, `alpha` chain limbs
+ * per key-switching digit (dnum = ceil(n_q / alpha)).  Every prime must be
+ * below 2^51 and congruent to 1 mod 2N.  `scale` is the encoding scale Delta,
+ * `sigma` the error standard deviation.  `out_limbs` is the default number of
+ * limbs a match result is dropped to (0 keeps the natural level). */
+typedef struct {
+  uint32_t log_n;
+  uint32_t n_q, n_p, alpha;
+  uint32_t out_limbs;
+  uint64_t q[16];
+  uint64_t p[4];
+  double scale;
+  double sigma;
+} bm_params;
+
+/* Preset 1: N = 2^12, q = {50, 40, 40}-bit, one 51-bit special prime,
+ * alpha = 1, scale 2^40 (a small parity/test ring, below 128-bit security).
+ * Preset 2: N = 2^16, eight 50-bit chain primes, two 51-bit special primes,
+ * alpha = 2 (dnum = 4), scale 2^50, out_limbs = 2.  Each prime is the largest
+ * below its bit bound that is 1 mod 2N.  Returns BM_EINVAL for other values. */
+int bm_params_preset(int preset, bm_params *out);
+
+/* Create a context on HIP device `device`: validates the primes, builds the
+ * NTT twiddle and base-conversion tables in device memory. */
+int bm_ctx_create(const bm_params *params, int device, bm_ctx **out);
+void bm_ctx_free(bm_ctx *ctx);
+const char *bm_strerror(int status);
+const char *bm_last_error(const bm_ctx *ctx);
+/* Result-invariant tuning knob: gallery groups evaluated per batched pass
+ * (0 = choose automatically).  Changes speed and scratch size, never bits. */
+int bm_ctx_set_group_chunk(bm_ctx *ctx, uint32_t groups);
+/* Device memory currently held by the context's caching pool, in bytes. */
+int bm_ctx_pool_bytes(const bm_ctx *ctx, uint64_t *bytes);
+
+/* ------------------------------------------------------------------ keys */
+
+/* Key set of Sec. 3.1 (public key for clients, evaluation key for the
+ * server, decryption key for the client) from one seed.  Randomness comes
+ * from SHAKE-256 over le64(seed) || le32(domain) || le64(index): domain 1
+ * secret (ternary), 2/3 public-key mask/error, 4/5 relinearisation key
+ * digit j, 6/7 Galois key digit j of element g at index g*dnum + j.  The
+ * evaluation key holds the relinearisation key (for s^2) and one Galois key
+ * (for s(X^g), g = 5^r mod 2N) per rotation r in rotations[0..n_rot-1].
+ * Any handle pointer may be NULL if that key is not wanted. */
+int bm_keygen(bm_ctx *ctx, uint64_t seed, const int32_t *rotations, size_t n_rot,
+              bm_sk **sk, bm_pk **pk, bm_evk **evk);
+/* Rotation amounts Alg. 1 and Alg. 2 use for feature length d split into k
+ * parts: 2^t for t < log2(d/k), and -+(d/k) 2^t for t < log2 k.  Writes at
+ * most `cap` values and the count to *n. */
+int bm_rotations_for(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
+/* Coefficient-domain export for checking: secret key (N signed values);
+ * public key component comp (0 = b, 1 = a) as [L+1][N]; switching key digit
+ * j component comp as [L+1+K][N] for the relinearisation key (galois = 0) or
+ * the Galois key of element `galois`. */
+int bm_sk_export(const bm_sk *sk, int64_t *s, size_t n);
+int bm_pk_export(const bm_pk *pk, uint32_t comp, uint64_t *words, size_t n_words);
+int bm_evk_export(const bm_evk *evk, uint64_t galois, uint32_t digit, uint32_t comp,
+                  uint64_t *words, size_t n_words);
+void bm_sk_free(bm_sk *sk);
+void bm_pk_free(bm_pk *pk);
+void bm_evk_free(bm_evk *evk);
+
+/* ------------------------------------------------------------------ encode / encrypt */
+
+/* Canonical-embedding encoding of n real slots at `scale`:
+ * coeffs[k] = round_half_away((2/N) Re sum_j scale*slots[j] zeta^(-k 5^j)),
+ * zeta = exp(i pi / N).  `n_slots` must equal N/2.  Double-precision FFT:
+ * results may differ by 1 from another implementation on rare coefficients. */
+int bm_encode(bm_ctx *ctx, const double *slots, size_t n_slots, double scale, int64_t *coeffs);
+/* Public-key encryption of the integer plaintext coeffs[N] at `limbs` chain
+ * limbs: (v b + e0 + m, v a + e1), v ternary, e0/e1 Gaussian, drawn from
+ * domains 8/9/10 at index ct_id. */
+int bm_encrypt_coeffs(bm_ctx *ctx, const bm_pk *pk, const int64_t *coeffs, uint32_t limbs,
+                      double scale, uint64_t seed, uint64_t ct_id, bm_ct **out);
+/* Query ciphertext of Sec. 3.3: q[0..d-1] tiled over every slot (slot s
+ * holds q[s mod d]), encoded at the context scale, encrypted at L+1 limbs. */
+int bm_encrypt_query(bm_ctx *ctx, const bm_pk *pk, const float *q, uint32_t d, uint64_t seed,
+                     uint64_t ct_id, bm_ct **out);
+/* Encrypted, packed gallery (Sec. 3.2 layout after enrolment, Fig. 4):
+ * x is n x d row-major.  With c = d/k and T = (N/2)/c templates per group,
+ * group g part i slot s holds x[g T + s / c][i c + s mod c] (zero past the
+ * last template).  Parts are encrypted at L+1 limbs for k = 1 and at L limbs
+ * for k > 1 (the expanded query loses one level), ct_id = ct_id_base + g k + i. */
+int bm_encrypt_gallery(bm_ctx *ctx, const bm_pk *pk, const float *x, uint64_t n, uint32_t d,
+                       uint32_t k, uint64_t seed, uint64_t ct_id_base, bm_gallery **out);
+/* Gallery assembled from coefficient-domain words[G][k][2][limbs][N]. */
+int bm_gallery_import(bm_ctx *ctx, const uint64_t *words, uint64_t groups, uint32_t d,
+                      uint32_t k, uint32_t limbs, double scale, uint64_t n_templates,
+                      bm_gallery **out);
+int bm_gallery_export(const bm_gallery *g, uint64_t *words, size_t n_words);
+int bm_gallery_info(const bm_gallery *g, uint64_t *groups, uint32_t *limbs, double *scale);
+void bm_gallery_free(bm_gallery *g);
+
+/* ------------------------------------------------------------------ ciphertexts */
+
+int bm_ct_import(bm_ctx *ctx, const uint64_t *words, uint32_t comps, uint32_t limbs,
+                 double scale, bm_ct **out);
+int bm_ct_export(const bm_ct *ct, uint64_t *words, size_t n_words);
+int bm_ct_info(const bm_ct *ct, uint32_t *comps, uint32_t *limbs, double *scale);
+void bm_ct_free(bm_ct *ct);
+/* Decrypt (c0 + c1 s [+ c2 s^2]) and decode: real parts of the n slots. */
+int bm_decrypt_slots(bm_ctx *ctx, const bm_sk *sk, const bm_ct *ct, double *slots, size_t n);
+
+/* ------------------------------------------------------------------ primitive operations
+ * The CKKS operations of Sec. 2 that the hot path is made of.  Each output is
+ * a new handle.  All ciphertext words are exact functions of the inputs. */
+
+/* Batched negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1), in place
+ * on device words[n_polys][limbs][N]; limb l of every polynomial is reduced
+ * modulo the prime with id prime_ids[l] (0..L chain, L+1.. special).  The
+ * forward transform leaves evaluations in bit-reversed order. */
+int bm_ntt(bm_ctx *ctx, uint64_t *dev_words, uint32_t n_polys, uint32_t limbs,
+           const uint32_t *prime_ids, int inverse, void *stream);
+/* Add(C): equal limbs and equal scale. */
+int bm_op_add(bm_ctx *ctx, const bm_ct *a, const bm_ct *b, bm_ct **out);
+/* Mul(P) by the integer plaintext pt[N] with scale pt_scale. */
+int bm_op_pmul(bm_ctx *ctx, const bm_ct *a, const int64_t *pt, double pt_scale, bm_ct **out);
+/* First half of Mul(C): (a0 b0, a0 b1 + a1 b0, a1 b1), scale a.scale*b.scale. */
+int bm_op_tensor(bm_ctx *ctx, const bm_ct *a, const bm_ct *b, bm_ct **out);
+/* Second half of Mul(C): relinearise a 3-component ciphertext with the key
+ * for s^2 (hybrid key switch: ModUp, key inner product, ModDown). */
+int bm_op_relin(bm_ctx *ctx, const bm_evk *evk, const bm_ct *a, bm_ct **out);
+/* Res: c_i <- (c_i - [c_last]_{q_i}) q_last^{-1}, last limb dropped, scale / q_last. */
+int bm_op_rescale(bm_ctx *ctx, const bm_ct *a, bm_ct **out);
+/* Rot: slot j of the result holds slot (j + r) mod n of a.  BM_ENOKEY if the
+ * evaluation key has no Galois key for 5^r. */
+int bm_op_rotate(bm_ctx *ctx, const bm_evk *evk, const bm_ct *a, int32_t r, bm_ct **out);
+/* Exact level drop to the first `limbs` limbs. */
+int bm_op_drop(bm_ctx *ctx, const bm_ct *a, uint32_t limbs, bm_ct **out);
+
+/* ------------------------------------------------------------------ Blind-Match */
+
+/* Plaintext masks of Alg. 1: mask_i has ones at slots s with
+ * floor((s mod d) / c) == i, encoded at scale q_L so the rescale after Mul(P)
+ * restores the query scale exactly.  bm_masks_import takes integer
+ * plaintexts coeffs[k][N] made elsewhere (same definition). */
+int bm_masks_create(bm_ctx *ctx, uint32_t d, uint32_t k, bm_masks **out);
+int bm_masks_import(bm_ctx *ctx, uint32_t d, uint32_t k, const int64_t *coeffs, double scale,
+                    bm_masks **out);
+void bm_masks_free(bm_masks *m);
+
+/* Alg. 1, Input Ciphertext Expansion: outs[i] = Res(Mul(P)(q, mask_i)),
+ * then for t < log2 k add Rot(., -c 2^t) when bit t of i is 0, else
+ * Rot(., +c 2^t).  outs must hold k handle slots. */
+int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *masks,
+              bm_ct **outs);
+
+/* Server side of recognition (Sec. 3.3): Alg. 1 when k > 1, then Alg. 2 on
+ * every gallery group, batched over groups on the device.
+ *   schedule BM_S1: Alg. 2 as printed, acc += Res(Relin(Tensor(C_u,i, C_s,i)));
+ *   schedule BM_S2: acc = Res(Relin(sum_i Tensor(C_u,i, C_s,i))) -- one key
+ *                   switch and one rescale per group; same message, other bits.
+ * then log2(d/k) steps acc += Rot(acc, 2^t).  The score of template g T + b is
+ * at slot b c of group g.  `masks` may be NULL (the library's own masks are
+ * used).  out_limbs: 0 = context default, otherwise an exact level drop of
+ * each result.  Asynchronous on `stream`. */
+int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g,
+             const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
+             bm_result **out);
+/* Many (query, gallery) pairs of possibly different d, k and size in one
+ * call: pairs of equal shape share batched launches.  outs[i] receives the
+ * result of pair i.  Results are bit-identical to per-pair bm_match. */
+int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
+                   const bm_gallery *const *gs, size_t n_pairs, uint32_t schedule,
+                   uint32_t out_limbs, void *stream, bm_result **outs);
+int bm_result_info(const bm_result *r, uint64_t *groups, uint32_t *limbs, double *scale);
+/* Coefficient-domain words[2][limbs][N] of group `group`. */
+int bm_result_export(const bm_result *r, uint64_t group, uint64_t *words, size_t n_words);
+void bm_result_free(bm_result *r);
+
+/* Client side (Sec. 3.4): decrypt every group, decode, read template
+ * g T + b at slot b c.  scores must hold n = n_templates values. */
+int bm_decrypt_scores(bm_ctx *ctx, const bm_sk *sk, const bm_result *r, double *scores,
+                      uint64_t n);
+/* Arg-max of scores[0..n-1] (lowest index on ties); *idx = -1 when the best
+ * score is below `threshold` (not enrolled). */
+int bm_top1(const double *scores, uint64_t n, double threshold, int64_t *idx, double *best);
+
+/* ------------------------------------------------------------------ serving */
+
+/* Continuous-batching server over device-resident galleries.  Requests are
+ * admitted while the scratch they need fits in `hbm_budget_bytes`; admitted
+ * requests of equal shape are evaluated together.  A worker thread owns the
+ * device; submit and poll are thread-safe. */
+int bm_server_create(bm_ctx *ctx, const bm_evk *evk, uint64_t hbm_budget_bytes,
+                     uint32_t schedule, bm_server **out);
+/* Ownership of the gallery moves to the server. */
+int bm_server_add_gallery(bm_server *s, bm_gallery *g, uint32_t *gallery_id);
+/* Ownership of the query moves to the server.  BM_EBUDGET if the request can
+ * never fit the budget. */
+int bm_server_submit(bm_server *s, uint32_t gallery_id, bm_ct *q, uint64_t *ticket);
+/* *out = NULL while the request is pending; then the result (caller frees).
+ * Status of a failed request is returned once. */
+int bm_server_poll(bm_server *s, uint64_t ticket, bm_result **out);
+/* Block until every submitted request finished. */
+int bm_server_drain(bm_server *s);
+/* Per-request latency statistics in ms (completion minus submission). */
+int bm_server_stats(bm_server *s, uint64_t *completed, double *p50_ms, double *p99_ms,
+                    double *mean_batch);
+void bm_server_free(bm_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BLINDMATCH_H */

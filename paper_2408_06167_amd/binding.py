@@ -1,0 +1,467 @@
+"""ctypes binding of libblindmatch.so: the C entry points under the same names.
+
+Argument marshalling only (numpy arrays in and out, handles as opaque
+pointers, non-zero status raised as BMError); every step of the computation
+runs inside the library.  Importing this module does not need a GPU, but the
+library must have been built (`paper_2408_06167_amd.build.build()`): there is
+no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblindmatch.so")
+
+BM_OK, BM_EINVAL, BM_EDIM, BM_ELEVEL, BM_ESCALE, BM_ENOKEY = 0, -1, -2, -3, -4, -5
+BM_ENOMEM, BM_EBUDGET, BM_EDEVICE, BM_EBUSY = -6, -7, -8, -9
+BM_S1, BM_S2 = 1, 2
+
+
+class BMError(RuntimeError):
+    def __init__(self, code, fn, detail):
+        super().__init__("%s failed: %s (%d) %s" % (fn, _strerror(code), code, detail))
+        self.code = code
+
+
+class bm_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
+                ("alpha", ctypes.c_uint32), ("out_limbs", ctypes.c_uint32),
+                ("q", ctypes.c_uint64 * 16), ("p", ctypes.c_uint64 * 4),
+                ("scale", ctypes.c_double), ("sigma", ctypes.c_double)]
+
+    @property
+    def N(self):
+        return 1 << self.log_n
+
+    def chain(self):
+        return [int(self.q[i]) for i in range(self.n_q)]
+
+    def special(self):
+        return [int(self.p[i]) for i in range(self.n_p)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_u32, _u64, _i32, _sz, _dbl = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_double
+
+_SIGS = {
+    "bm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "bm_last_error": (ctypes.c_char_p, [_P]),
+    "bm_params_preset": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(bm_params)]),
+    "bm_ctx_create": (ctypes.c_int, [ctypes.POINTER(bm_params), ctypes.c_int, _PP]),
+    "bm_ctx_free": (None, [_P]),
+    "bm_ctx_set_group_chunk": (ctypes.c_int, [_P, _u32]),
+    "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
+    "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
+    "bm_rotations_for": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
+    "bm_sk_export": (ctypes.c_int, [_P, _P, _sz]),
+    "bm_pk_export": (ctypes.c_int, [_P, _u32, _P, _sz]),
+    "bm_evk_export": (ctypes.c_int, [_P, _u64, _u32, _u32, _P, _sz]),
+    "bm_sk_free": (None, [_P]),
+    "bm_pk_free": (None, [_P]),
+    "bm_evk_free": (None, [_P]),
+    "bm_encode": (ctypes.c_int, [_P, _P, _sz, _dbl, _P]),
+    "bm_encrypt_coeffs": (ctypes.c_int, [_P, _P, _P, _u32, _dbl, _u64, _u64, _PP]),
+    "bm_encrypt_query": (ctypes.c_int, [_P, _P, _P, _u32, _u64, _u64, _PP]),
+    "bm_encrypt_gallery": (ctypes.c_int, [_P, _P, _P, _u64, _u32, _u32, _u64, _u64, _PP]),
+    "bm_gallery_import": (ctypes.c_int, [_P, _P, _u64, _u32, _u32, _u32, _dbl, _u64, _PP]),
+    "bm_gallery_export": (ctypes.c_int, [_P, _P, _sz]),
+    "bm_gallery_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
+                                       ctypes.POINTER(_dbl)]),
+    "bm_gallery_free": (None, [_P]),
+    "bm_ct_import": (ctypes.c_int, [_P, _P, _u32, _u32, _dbl, _PP]),
+    "bm_ct_export": (ctypes.c_int, [_P, _P, _sz]),
+    "bm_ct_info": (ctypes.c_int, [_P, ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_dbl)]),
+    "bm_ct_free": (None, [_P]),
+    "bm_decrypt_slots": (ctypes.c_int, [_P, _P, _P, _P, _sz]),
+    "bm_ntt": (ctypes.c_int, [_P, _P, _u32, _u32, _P, ctypes.c_int, _P]),
+    "bm_op_add": (ctypes.c_int, [_P, _P, _P, _PP]),
+    "bm_op_pmul": (ctypes.c_int, [_P, _P, _P, _dbl, _PP]),
+    "bm_op_tensor": (ctypes.c_int, [_P, _P, _P, _PP]),
+    "bm_op_relin": (ctypes.c_int, [_P, _P, _P, _PP]),
+    "bm_op_rescale": (ctypes.c_int, [_P, _P, _PP]),
+    "bm_op_rotate": (ctypes.c_int, [_P, _P, _P, _i32, _PP]),
+    "bm_op_drop": (ctypes.c_int, [_P, _P, _u32, _PP]),
+    "bm_masks_create": (ctypes.c_int, [_P, _u32, _u32, _PP]),
+    "bm_masks_import": (ctypes.c_int, [_P, _u32, _u32, _P, _dbl, _PP]),
+    "bm_masks_free": (None, [_P]),
+    "bm_expand": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "bm_match": (ctypes.c_int, [_P, _P, _P, _P, _P, _u32, _u32, _P, _PP]),
+    "bm_match_batch": (ctypes.c_int, [_P, _P, _P, _P, _sz, _u32, _u32, _P, _P]),
+    "bm_result_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
+                                      ctypes.POINTER(_dbl)]),
+    "bm_result_export": (ctypes.c_int, [_P, _u64, _P, _sz]),
+    "bm_result_free": (None, [_P]),
+    "bm_decrypt_scores": (ctypes.c_int, [_P, _P, _P, _P, _u64]),
+    "bm_top1": (ctypes.c_int, [_P, _u64, _dbl, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_dbl)]),
+    "bm_server_create": (ctypes.c_int, [_P, _P, _u64, _u32, _PP]),
+    "bm_server_add_gallery": (ctypes.c_int, [_P, _P, ctypes.POINTER(_u32)]),
+    "bm_server_submit": (ctypes.c_int, [_P, _u32, _P, ctypes.POINTER(_u64)]),
+    "bm_server_poll": (ctypes.c_int, [_P, _u64, _PP]),
+    "bm_server_drain": (ctypes.c_int, [_P]),
+    "bm_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_dbl),
+                                       ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "bm_server_free": (None, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libblindmatch.so is not built (run paper_2408_06167_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return sorted(_SIGS)
+
+
+def _strerror(code):
+    try:
+        return lib().bm_strerror(code).decode()
+    except Exception:
+        return "status"
+
+
+def _check(code, fn, ctx=None):
+    if code != BM_OK:
+        detail = lib().bm_last_error(ctx).decode(errors="replace") if _lib else ""
+        raise BMError(code, fn, detail)
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _out():
+    return ctypes.c_void_p()
+
+
+# ------------------------------------------------------------------ context and keys
+
+def bm_params_preset(preset):
+    p = bm_params()
+    _check(lib().bm_params_preset(int(preset), ctypes.byref(p)), "bm_params_preset")
+    return p
+
+
+def bm_ctx_create(params, device=0):
+    h = _out()
+    _check(lib().bm_ctx_create(ctypes.byref(params), int(device), ctypes.byref(h)), "bm_ctx_create")
+    return h
+
+
+def bm_ctx_free(ctx):
+    lib().bm_ctx_free(ctx)
+
+
+def bm_ctx_set_group_chunk(ctx, groups):
+    _check(lib().bm_ctx_set_group_chunk(ctx, int(groups)), "bm_ctx_set_group_chunk", ctx)
+
+
+def bm_ctx_pool_bytes(ctx):
+    v = _u64()
+    _check(lib().bm_ctx_pool_bytes(ctx, ctypes.byref(v)), "bm_ctx_pool_bytes", ctx)
+    return int(v.value)
+
+
+def bm_rotations_for(d, k):
+    n = _sz()
+    _check(lib().bm_rotations_for(int(d), int(k), None, 0, ctypes.byref(n)), "bm_rotations_for")
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(lib().bm_rotations_for(int(d), int(k), _ptr(out), out.size, ctypes.byref(n)), "bm_rotations_for")
+    return [int(x) for x in out]
+
+
+def bm_keygen(ctx, seed, rotations=()):
+    rots = np.ascontiguousarray(sorted(set(int(r) for r in rotations)), dtype=np.int32)
+    sk, pk, evk = _out(), _out(), _out()
+    _check(lib().bm_keygen(ctx, int(seed), _ptr(rots) if rots.size else None, rots.size,
+                           ctypes.byref(sk), ctypes.byref(pk), ctypes.byref(evk)), "bm_keygen", ctx)
+    return sk, pk, evk
+
+
+def bm_sk_export(sk, N):
+    s = np.zeros(N, dtype=np.int64)
+    _check(lib().bm_sk_export(sk, _ptr(s), N), "bm_sk_export")
+    return s
+
+
+def bm_pk_export(ctx, pk, comp, limbs, N):
+    w = np.zeros((limbs, N), dtype=np.uint64)
+    _check(lib().bm_pk_export(pk, int(comp), _ptr(w), w.size), "bm_pk_export", ctx)
+    return w
+
+
+def bm_evk_export(ctx, evk, galois, digit, comp, nprimes, N):
+    w = np.zeros((nprimes, N), dtype=np.uint64)
+    _check(lib().bm_evk_export(evk, int(galois), int(digit), int(comp), _ptr(w), w.size),
+           "bm_evk_export", ctx)
+    return w
+
+
+def bm_sk_free(h):
+    lib().bm_sk_free(h)
+
+
+def bm_pk_free(h):
+    lib().bm_pk_free(h)
+
+
+def bm_evk_free(h):
+    lib().bm_evk_free(h)
+
+
+# ------------------------------------------------------------------ encode / encrypt
+
+def bm_encode(ctx, slots, scale):
+    slots = np.ascontiguousarray(slots, dtype=np.float64)
+    out = np.zeros(2 * slots.size, dtype=np.int64)
+    _check(lib().bm_encode(ctx, _ptr(slots), slots.size, float(scale), _ptr(out)), "bm_encode", ctx)
+    return out
+
+
+def bm_encrypt_coeffs(ctx, pk, coeffs, limbs, scale, seed, ct_id):
+    m = np.ascontiguousarray(coeffs, dtype=np.int64)
+    h = _out()
+    _check(lib().bm_encrypt_coeffs(ctx, pk, _ptr(m), int(limbs), float(scale), int(seed), int(ct_id),
+                                   ctypes.byref(h)), "bm_encrypt_coeffs", ctx)
+    return h
+
+
+def bm_encrypt_query(ctx, pk, q, seed, ct_id):
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    h = _out()
+    _check(lib().bm_encrypt_query(ctx, pk, _ptr(q), q.size, int(seed), int(ct_id), ctypes.byref(h)),
+           "bm_encrypt_query", ctx)
+    return h
+
+
+def bm_encrypt_gallery(ctx, pk, X, k, seed, ct_id_base):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    h = _out()
+    _check(lib().bm_encrypt_gallery(ctx, pk, _ptr(X), X.shape[0], X.shape[1], int(k), int(seed),
+                                    int(ct_id_base), ctypes.byref(h)), "bm_encrypt_gallery", ctx)
+    return h
+
+
+def bm_gallery_import(ctx, words, d, k, limbs, scale, n_templates):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    groups = w.shape[0]
+    h = _out()
+    _check(lib().bm_gallery_import(ctx, _ptr(w), groups, int(d), int(k), int(limbs), float(scale),
+                                   int(n_templates), ctypes.byref(h)), "bm_gallery_import", ctx)
+    return h
+
+
+def bm_gallery_info(g):
+    G, l, s = _u64(), _u32(), _dbl()
+    _check(lib().bm_gallery_info(g, ctypes.byref(G), ctypes.byref(l), ctypes.byref(s)), "bm_gallery_info")
+    return int(G.value), int(l.value), float(s.value)
+
+
+def bm_gallery_export(ctx, g, k, N):
+    G, l, _ = bm_gallery_info(g)
+    w = np.zeros((G, k, 2, l, N), dtype=np.uint64)
+    _check(lib().bm_gallery_export(g, _ptr(w), w.size), "bm_gallery_export", ctx)
+    return w
+
+
+def bm_gallery_free(g):
+    lib().bm_gallery_free(g)
+
+
+# ------------------------------------------------------------------ ciphertexts
+
+def bm_ct_import(ctx, words, scale):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    comps, limbs = w.shape[0], w.shape[1]
+    h = _out()
+    _check(lib().bm_ct_import(ctx, _ptr(w), comps, limbs, float(scale), ctypes.byref(h)),
+           "bm_ct_import", ctx)
+    return h
+
+
+def bm_ct_info(ct):
+    c, l, s = _u32(), _u32(), _dbl()
+    _check(lib().bm_ct_info(ct, ctypes.byref(c), ctypes.byref(l), ctypes.byref(s)), "bm_ct_info")
+    return int(c.value), int(l.value), float(s.value)
+
+
+def bm_ct_export(ctx, ct, N):
+    comps, limbs, scale = bm_ct_info(ct)
+    w = np.zeros((comps, limbs, N), dtype=np.uint64)
+    _check(lib().bm_ct_export(ct, _ptr(w), w.size), "bm_ct_export", ctx)
+    return w, scale
+
+
+def bm_ct_free(ct):
+    lib().bm_ct_free(ct)
+
+
+def bm_decrypt_slots(ctx, sk, ct, n):
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib().bm_decrypt_slots(ctx, sk, ct, _ptr(out), n), "bm_decrypt_slots", ctx)
+    return out
+
+
+# ------------------------------------------------------------------ primitive operations
+
+def bm_ntt(ctx, dev_ptr, n_polys, prime_ids, inverse, stream=None):
+    ids = np.ascontiguousarray(prime_ids, dtype=np.uint32)
+    _check(lib().bm_ntt(ctx, ctypes.c_void_p(dev_ptr), int(n_polys), ids.size, _ptr(ids),
+                        1 if inverse else 0, ctypes.c_void_p(stream) if stream else None),
+           "bm_ntt", ctx)
+
+
+def _op(name, ctx, *args):
+    h = _out()
+    _check(getattr(lib(), name)(ctx, *args, ctypes.byref(h)), name, ctx)
+    return h
+
+
+def bm_op_add(ctx, a, b):
+    return _op("bm_op_add", ctx, a, b)
+
+
+def bm_op_pmul(ctx, a, pt, pt_scale):
+    pt = np.ascontiguousarray(pt, dtype=np.int64)
+    return _op("bm_op_pmul", ctx, a, _ptr(pt), float(pt_scale))
+
+
+def bm_op_tensor(ctx, a, b):
+    return _op("bm_op_tensor", ctx, a, b)
+
+
+def bm_op_relin(ctx, evk, a):
+    return _op("bm_op_relin", ctx, evk, a)
+
+
+def bm_op_rescale(ctx, a):
+    return _op("bm_op_rescale", ctx, a)
+
+
+def bm_op_rotate(ctx, evk, a, r):
+    return _op("bm_op_rotate", ctx, evk, a, int(r))
+
+
+def bm_op_drop(ctx, a, limbs):
+    return _op("bm_op_drop", ctx, a, int(limbs))
+
+
+# ------------------------------------------------------------------ Blind-Match
+
+def bm_masks_create(ctx, d, k):
+    return _op("bm_masks_create", ctx, int(d), int(k))
+
+
+def bm_masks_import(ctx, d, k, coeffs, scale):
+    c = np.ascontiguousarray(coeffs, dtype=np.int64)
+    return _op("bm_masks_import", ctx, int(d), int(k), _ptr(c), float(scale))
+
+
+def bm_masks_free(m):
+    lib().bm_masks_free(m)
+
+
+def bm_expand(ctx, evk, q, masks, k):
+    outs = (ctypes.c_void_p * k)()
+    _check(lib().bm_expand(ctx, evk, q, masks, ctypes.cast(outs, _P)), "bm_expand", ctx)
+    return [ctypes.c_void_p(outs[i]) for i in range(k)]
+
+
+def bm_match(ctx, evk, q, gallery, masks=None, schedule=BM_S1, out_limbs=0, stream=None):
+    return _op("bm_match", ctx, evk, q, gallery, masks, int(schedule), int(out_limbs),
+               ctypes.c_void_p(stream) if stream else None)
+
+
+def bm_match_batch(ctx, evk, queries, galleries, schedule=BM_S1, out_limbs=0, stream=None):
+    n = len(queries)
+    qa = (ctypes.c_void_p * n)(*[q.value for q in queries])
+    ga = (ctypes.c_void_p * n)(*[g.value for g in galleries])
+    outs = (ctypes.c_void_p * n)()
+    _check(lib().bm_match_batch(ctx, evk, ctypes.cast(qa, _P), ctypes.cast(ga, _P), n, int(schedule),
+                                int(out_limbs), ctypes.c_void_p(stream) if stream else None,
+                                ctypes.cast(outs, _P)), "bm_match_batch", ctx)
+    return [ctypes.c_void_p(outs[i]) for i in range(n)]
+
+
+def bm_result_info(r):
+    G, l, s = _u64(), _u32(), _dbl()
+    _check(lib().bm_result_info(r, ctypes.byref(G), ctypes.byref(l), ctypes.byref(s)), "bm_result_info")
+    return int(G.value), int(l.value), float(s.value)
+
+
+def bm_result_export(ctx, r, group, N):
+    _, limbs, scale = bm_result_info(r)
+    w = np.zeros((2, limbs, N), dtype=np.uint64)
+    _check(lib().bm_result_export(r, int(group), _ptr(w), w.size), "bm_result_export", ctx)
+    return w, scale
+
+
+def bm_result_free(r):
+    lib().bm_result_free(r)
+
+
+def bm_decrypt_scores(ctx, sk, r, n):
+    out = np.zeros(n, dtype=np.float64)
+    _check(lib().bm_decrypt_scores(ctx, sk, r, _ptr(out), int(n)), "bm_decrypt_scores", ctx)
+    return out
+
+
+def bm_top1(scores, threshold=float("-inf")):
+    s = np.ascontiguousarray(scores, dtype=np.float64)
+    idx, best = ctypes.c_int64(), _dbl()
+    _check(lib().bm_top1(_ptr(s), s.size, float(threshold), ctypes.byref(idx), ctypes.byref(best)), "bm_top1")
+    return int(idx.value), float(best.value)
+
+
+# ------------------------------------------------------------------ serving
+
+def bm_server_create(ctx, evk, hbm_budget_bytes, schedule=BM_S2):
+    return _op("bm_server_create", ctx, evk, int(hbm_budget_bytes), int(schedule))
+
+
+def bm_server_add_gallery(server, gallery):
+    gid = _u32()
+    _check(lib().bm_server_add_gallery(server, gallery, ctypes.byref(gid)), "bm_server_add_gallery")
+    return int(gid.value)
+
+
+def bm_server_submit(server, gallery_id, q):
+    t = _u64()
+    _check(lib().bm_server_submit(server, int(gallery_id), q, ctypes.byref(t)), "bm_server_submit")
+    return int(t.value)
+
+
+def bm_server_poll(server, ticket):
+    h = _out()
+    _check(lib().bm_server_poll(server, int(ticket), ctypes.byref(h)), "bm_server_poll")
+    return h if h.value else None
+
+
+def bm_server_drain(server):
+    _check(lib().bm_server_drain(server), "bm_server_drain")
+
+
+def bm_server_stats(server):
+    n, p50, p99, mb = _u64(), _dbl(), _dbl(), _dbl()
+    _check(lib().bm_server_stats(server, ctypes.byref(n), ctypes.byref(p50), ctypes.byref(p99),
+                                 ctypes.byref(mb)), "bm_server_stats")
+    return dict(completed=int(n.value), p50_ms=p50.value, p99_ms=p99.value, mean_batch=mb.value)
+
+
+def bm_server_free(server):
+    lib().bm_server_free(server)

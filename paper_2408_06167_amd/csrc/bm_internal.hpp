@@ -1,0 +1,318 @@
+// bm_internal.hpp -- shared internal declarations of the Blind-Match GPU library.
+//
+// Data layout in HBM (all words uint64, residues in [0, q)):
+//   polynomial          [limbs][N], limb-major, evaluation (NTT) domain in
+//                        bit-reversed order unless stated otherwise
+//   ciphertext          [comps][limbs][N]   (comps = 2, or 3 after a tensor)
+//   ciphertext batch    [B][comps][limbs][N] with a per-batch element stride
+//   switching key       [dnum][2][L+1+K][N] evaluation domain, Montgomery form
+//   gallery             [G][k][2][limbs][N]
+// Limb l < L+1 is chain prime q_l; limb L+1+k is special prime p_k.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/blindmatch.h"
+
+namespace bm {
+
+using u64 = uint64_t;
+using u32 = uint32_t;
+using u128 = unsigned __int128;
+
+constexpr int MAX_PRIMES = 24;   // chain + special primes
+constexpr int MAX_LIMBS = 24;    // limbs in one polynomial of a launch
+constexpr int MAX_DIGITS = 16;
+constexpr int MAX_ALPHA = 4;
+
+// ----------------------------------------------------------------- errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define BM_THROW(code, msg) throw ::bm::Error{(code), (msg)}
+#define HIP_OK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      BM_THROW(BM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+// ----------------------------------------------------------------- per-prime constants (device)
+
+struct PrimeC {
+  u64 q;
+  u64 qn;       // -q^{-1} mod 2^64 (Montgomery)
+  u64 r2;       // 2^128 mod q
+  u64 ninv;     // N^{-1} mod q
+  u64 ninv_s;   // Shoup companion of ninv
+  u64 pad[3];
+};
+
+// Limb selection for one launch: limb slot y of every polynomial in the
+// batch lives at element offset off[y]*N and belongs to prime prime[y].
+struct LimbMap {
+  int n;
+  int prime[MAX_LIMBS];
+  int off[MAX_LIMBS];    // input offset (limbs)
+  int ooff[MAX_LIMBS];   // output offset (limbs); equal to off unless remapped
+};
+
+// ----------------------------------------------------------------- base-conversion tables (device)
+
+struct ModUpDigit {
+  int nsrc;                              // limbs of the digit present at this level
+  int src[MAX_ALPHA];                    // their limb indices (= chain prime ids)
+  u64 qhatinv[MAX_ALPHA][2];             // (Q_j/q_i)^{-1} mod q_i, Shoup pair
+  u64 qhat[MAX_ALPHA][MAX_LIMBS][2];     // (Q_j/q_i) mod target slot t, Shoup pair
+};
+
+struct ModUpTable {                       // one per level (number of chain limbs)
+  int limbs;                             // l
+  int beta;                              // digits present
+  int ext;                               // l + K target slots: chain limbs then specials
+  int ext_prime[MAX_LIMBS];
+  ModUpDigit d[MAX_DIGITS];
+};
+
+struct ModDownTable {
+  int K;
+  int pprime[4];                          // prime ids of the special primes
+  u64 phatinv[4][2];                      // (P/p_k)^{-1} mod p_k
+  u64 phat[4][MAX_PRIMES][2];             // (P/p_k) mod q_i
+  u64 pinv[MAX_PRIMES][2];                // P^{-1} mod q_i
+};
+
+// ----------------------------------------------------------------- device memory
+
+// Caching allocator: blocks are recycled by exact size.  All work of a context
+// is ordered on one stream, so a block freed by the host can be handed to the
+// next request immediately (stream order protects pending readers).
+class DevicePool {
+ public:
+  explicit DevicePool(int device) : device_(device) {}
+  ~DevicePool();
+  void* alloc(size_t bytes);
+  void release(void* p, size_t bytes);
+  size_t bytes_held() const { return held_; }
+  void trim();
+
+ private:
+  int device_;
+  std::multimap<size_t, void*> free_;
+  size_t held_ = 0;
+  std::mutex mu_;
+};
+
+struct Ctx;
+
+// RAII device buffer of u64 words from a context's pool.
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Ctx* c, size_t words);
+  ~DBuf();
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept;
+  u64* p() const { return p_; }
+  size_t words() const { return words_; }
+
+ private:
+  Ctx* ctx_ = nullptr;
+  u64* p_ = nullptr;
+  size_t words_ = 0;
+};
+
+// ----------------------------------------------------------------- context
+
+struct HostPrime {
+  u64 q;
+  int bits;
+  u64 psi;                 // primitive 2N-th root used by the device NTT
+};
+
+struct Ctx {
+  int device = 0;
+  int log_n = 0;
+  size_t N = 0, n = 0;
+  int L = 0;               // top level; fresh ciphertexts have L+1 limbs
+  int K = 0, alpha = 1, dnum = 1;
+  double scale = 0, sigma = 3.2;
+  uint32_t out_limbs = 0;  // default output limbs of a match (0 = natural level)
+  std::vector<HostPrime> primes;   // L+1 chain primes then K special primes
+  std::vector<u64> cdt;            // Gaussian cumulative table (38 entries)
+  hipStream_t stream = nullptr;    // current stream of this context
+  hipStream_t own_stream = nullptr;
+  std::unique_ptr<DevicePool> pool;
+  // device tables
+  PrimeC* d_primes = nullptr;
+  u64* d_tw = nullptr;             // [MAX_PRIMES][N] psi^{brv(k)} and Shoup companions
+  u64* d_tws = nullptr;
+  u64* d_itw = nullptr;            // psi^{-brv(k)}
+  u64* d_itws = nullptr;
+  ModUpTable* d_modup = nullptr;   // [L+2] indexed by number of chain limbs
+  ModDownTable* d_moddown = nullptr;
+  u64* d_rescale = nullptr;        // [L+1][L+1][2]: q_l^{-1} mod q_i, Shoup pair
+  std::vector<ModUpTable> h_modup;
+  ModDownTable h_moddown{};
+  std::string last_error;
+  // tuning knobs (result-invariant)
+  int group_chunk = 0;             // gallery groups per batched pass (0 = auto)
+
+  bool owns_tables = true;         // false for a lane sharing another context's tables
+
+  int nprimes() const { return (int)primes.size(); }
+  int pid_special(int k) const { return L + 1 + k; }
+  void use_stream(void* s);
+  // A context sharing this one's parameters and device tables, with its own
+  // stream and memory pool (work on it overlaps with work on this one).
+  std::unique_ptr<Ctx> make_lane() const;
+  ~Ctx();
+};
+
+// ----------------------------------------------------------------- host math (host_math.cpp)
+
+u64 h_mulmod(u64 a, u64 b, u64 q);
+u64 h_powmod(u64 b, u64 e, u64 q);
+u64 h_invmod(u64 a, u64 q);
+u64 h_shoup(u64 w, u64 q);
+bool h_is_prime(u64 n);
+u64 h_primitive_2n_root(u64 q, size_t N);
+void build_context_tables(Ctx& c);
+std::vector<u64> gaussian_cdt(double sigma, int bound);
+
+// SHAKE-256 streams and samplers (shake.cpp)
+void shake256(const uint8_t* in, size_t inlen, uint8_t* out, size_t outlen);
+void sample_ternary(u64 seed, u32 domain, u64 index, size_t n, int64_t* out);
+void sample_gauss(const Ctx& c, u64 seed, u32 domain, u64 index, size_t n, int64_t* out);
+void sample_uniform(u64 seed, u32 domain, u64 index, const u64* qs, size_t nq, size_t n, u64* out);
+
+// canonical-embedding encoder (encoder.cpp)
+void encode_slots(size_t N, const double* re, const double* im, double scale, int64_t* out);
+void decode_coeffs(size_t N, const double* m, double scale, double* re, double* im);
+
+// ----------------------------------------------------------------- device kernels (kernels.hip)
+
+namespace kern {
+LimbMap chain_map(int limbs);                        // q_0..q_{limbs-1} at offsets 0..
+LimbMap ext_map(const Ctx& c, int limbs);           // q_0..q_{l-1}, p_0..p_{K-1}
+LimbMap single(int prime, int off);
+
+// forward / inverse negacyclic NTT; in and out may alias
+void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+         const LimbMap& m, bool inverse);
+// signed integer polynomial [N] -> residues in limbs of m (coefficient domain)
+void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
+                size_t src_stride, const LimbMap& m);
+// out = a + b, a - b, a * b (general), per limb of m; strides per operand (0 = broadcast)
+void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+         int B, const LimbMap& m);
+void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+         int B, const LimbMap& m);
+void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+         int B, const LimbMap& m);
+void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m);
+// o = a * R mod q (Montgomery form for switching keys)
+void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m);
+// o_limb += s_limb * scalar[limb] (scalar per limb slot, Shoup pair list)
+void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2] device*/,
+                 u64* o, size_t so, int B, const LimbMap& m);
+// tensor product (a0,a1) x (b0,b1) -> (d0,d1,d2), optionally accumulated into o;
+// batch element z uses a[z / a_div] and b[z % b_mod]
+void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
+            u64* o, size_t so, int B, int limbs, bool accumulate);
+// evaluation-domain automorphism X -> X^g of `comps` components of `limbs` limbs
+void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B,
+                  int rows, u64 g);
+// ModUp of digit j: coefficient-domain x [l] -> y slots of every target (coefficient)
+void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j);
+// key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext], key Montgomery)
+void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key,
+         u64* uw, size_t suw, int B, int limbs);
+// ModDown base conversion: special limbs of u (coefficient) -> conv [l] (coefficient)
+void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs);
+// out = (u - conv) * P^{-1} (+ addend), both components
+void moddown_finish(const Ctx& c, const u64* uw, size_t suw, const u64* conv, size_t sc,
+                    const u64* add0, size_t sadd0, const u64* add1, size_t sadd1, u64* out,
+                    size_t so, int B, int limbs);
+// rescale: last limb (coefficient, comps polys) -> reduced copies for limbs 0..l-2
+void rescale_conv(const Ctx& c, const u64* last, size_t sl, size_t last_comp_stride, u64* t,
+                  size_t st, int B, int comps, int limbs);
+void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t st, u64* out,
+                    size_t so, int B, int comps, int limbs);
+// batch element z is written to out + (z / div) so_hi + (z % div) so_lo
+void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
+                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs);
+}  // namespace kern
+
+}  // namespace bm
+
+// ----------------------------------------------------------------- opaque handles
+
+struct bm_ctx {
+  bm::Ctx c;
+};
+
+struct bm_ct {
+  bm_ctx* ctx = nullptr;
+  bm::DBuf buf;            // [comps][limbs][N], evaluation domain
+  uint32_t comps = 2, limbs = 0;
+  double scale = 1.0;
+};
+
+struct bm_sk {
+  bm_ctx* ctx = nullptr;
+  std::vector<int64_t> s;  // ternary coefficients
+  bm::DBuf s_ntt;          // [L+1+K][N] evaluation domain
+};
+
+struct bm_pk {
+  bm_ctx* ctx = nullptr;
+  bm::DBuf pk;             // [2][L+1][N] evaluation domain (b, a)
+};
+
+struct bm_switch_key {
+  bm::DBuf k;              // [dnum][2][L+1+K][N] evaluation domain, Montgomery form
+};
+
+struct bm_evk {
+  bm_ctx* ctx = nullptr;
+  bm_switch_key rlk;
+  std::map<uint64_t, std::unique_ptr<bm_switch_key>> gk;   // by Galois element
+};
+
+struct bm_masks {
+  bm_ctx* ctx = nullptr;
+  uint32_t d = 0, k = 0;
+  double scale = 0;
+  bm::DBuf pt;             // [k][L+1][N] evaluation domain
+};
+
+struct bm_gallery {
+  bm_ctx* ctx = nullptr;
+  uint32_t d = 0, k = 0, limbs = 0;
+  uint64_t n_templates = 0, groups = 0;
+  double scale = 0;
+  bm::DBuf buf;            // [G][k][2][limbs][N]
+};
+
+struct bm_result {
+  bm_ctx* ctx = nullptr;
+  uint32_t d = 0, k = 0, limbs = 0;
+  uint64_t n_templates = 0, groups = 0;
+  double scale = 0;
+  std::shared_ptr<bm::DBuf> store;   // may be shared by the results of one batch
+  size_t off = 0;                     // words; this result is [G][2][limbs][N] at store + off
+  uint64_t* p() const { return store->p() + off; }
+};

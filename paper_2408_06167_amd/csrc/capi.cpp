@@ -1,0 +1,811 @@
+// capi.cpp -- the extern "C" boundary: argument checks, handle lifetimes,
+// exception-to-status translation.  Every entry point is declared and
+// documented in include/blindmatch.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "blindmatch_impl.hpp"
+
+using namespace bm;
+
+namespace {
+
+thread_local std::string g_err;   // errors raised before a context exists
+
+template <class F>
+int guarded(bm_ctx* ctx, F&& f) {
+  try {
+    f();
+    return BM_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->c.last_error = e.msg;
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->c.last_error = "host allocation failed";
+    return BM_ENOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->c.last_error = e.what();
+    return BM_EINVAL;
+  }
+}
+
+#define REQUIRE(cond, code, msg) \
+  do {                           \
+    if (!(cond)) BM_THROW((code), (msg)); \
+  } while (0)
+
+// Largest `count` primes below 2^bits that are 1 mod 2N, in descending order.
+std::vector<u64> primes_below(int bits, size_t N, int count, const std::vector<u64>& avoid) {
+  std::vector<u64> out;
+  const u64 step = 2 * N;
+  u64 cand = (((1ULL << bits) - 1) / step) * step + 1;
+  while ((int)out.size() < count && cand > step) {
+    if (h_is_prime(cand) && std::find(avoid.begin(), avoid.end(), cand) == avoid.end())
+      out.push_back(cand);
+    cand -= step;
+  }
+  return out;
+}
+
+void sync(Ctx& c) { HIP_OK(hipStreamSynchronize(c.stream)); }
+
+}  // namespace
+
+extern "C" {
+
+const char* bm_strerror(int status) {
+  switch (status) {
+    case BM_OK: return "ok";
+    case BM_EINVAL: return "invalid argument";
+    case BM_EDIM: return "invalid dimension";
+    case BM_ELEVEL: return "level mismatch or too few levels";
+    case BM_ESCALE: return "scale mismatch";
+    case BM_ENOKEY: return "missing Galois key";
+    case BM_ENOMEM: return "out of memory";
+    case BM_EBUDGET: return "HBM budget exceeded";
+    case BM_EDEVICE: return "device error";
+    case BM_EBUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+const char* bm_last_error(const bm_ctx* ctx) {
+  return ctx ? ctx->c.last_error.c_str() : g_err.c_str();
+}
+
+int bm_params_preset(int preset, bm_params* out) {
+  return guarded(nullptr, [&] {
+    REQUIRE(out, BM_EINVAL, "out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->sigma = 3.2;
+    if (preset == 1) {
+      const size_t N = 1u << 12;
+      out->log_n = 12;
+      auto q0 = primes_below(50, N, 1, {});
+      auto q12 = primes_below(40, N, 2, {});
+      auto p = primes_below(51, N, 1, {});
+      out->n_q = 3;
+      out->q[0] = q0[0];
+      out->q[1] = q12[0];
+      out->q[2] = q12[1];
+      out->n_p = 1;
+      out->p[0] = p[0];
+      out->alpha = 1;
+      out->scale = std::ldexp(1.0, 40);
+      out->out_limbs = 0;
+    } else if (preset == 2) {
+      const size_t N = 1u << 16;
+      out->log_n = 16;
+      auto q = primes_below(50, N, 8, {});
+      auto p = primes_below(51, N, 2, {});
+      out->n_q = 8;
+      for (int i = 0; i < 8; ++i) out->q[i] = q[i];
+      out->n_p = 2;
+      out->p[0] = p[0];
+      out->p[1] = p[1];
+      out->alpha = 2;
+      out->scale = std::ldexp(1.0, 50);
+      out->out_limbs = 2;
+    } else {
+      BM_THROW(BM_EINVAL, "unknown preset");
+    }
+  });
+}
+
+int bm_ctx_create(const bm_params* p, int device, bm_ctx** out) {
+  return guarded(nullptr, [&] {
+    REQUIRE(p && out, BM_EINVAL, "NULL argument");
+    *out = nullptr;
+    REQUIRE(p->log_n >= 3 && p->log_n <= 16, BM_EINVAL, "log_n must be in [3, 16]");
+    REQUIRE(p->n_q >= 1 && p->n_q <= 16 && p->n_p >= 1 && p->n_p <= 4, BM_EINVAL, "prime counts");
+    REQUIRE(p->alpha >= 1 && p->alpha <= (uint32_t)MAX_ALPHA, BM_EINVAL, "alpha in [1, 4]");
+    REQUIRE(p->n_q + p->n_p <= (uint32_t)MAX_PRIMES, BM_EINVAL, "too many primes");
+    std::unique_ptr<bm_ctx> h(new bm_ctx);
+    Ctx& c = h->c;
+    c.device = device;
+    c.log_n = (int)p->log_n;
+    c.N = (size_t)1 << p->log_n;
+    c.n = c.N / 2;
+    c.L = (int)p->n_q - 1;
+    c.K = (int)p->n_p;
+    c.alpha = (int)p->alpha;
+    c.dnum = (int)((p->n_q + p->alpha - 1) / p->alpha);
+    c.scale = p->scale;
+    c.sigma = p->sigma > 0 ? p->sigma : 3.2;
+    c.out_limbs = p->out_limbs;
+    REQUIRE(c.scale > 1.0, BM_EINVAL, "scale must exceed 1");
+    REQUIRE(c.out_limbs <= p->n_q, BM_EINVAL, "out_limbs above the chain length");
+    std::vector<u64> all;
+    for (uint32_t i = 0; i < p->n_q; ++i) all.push_back(p->q[i]);
+    for (uint32_t i = 0; i < p->n_p; ++i) all.push_back(p->p[i]);
+    for (size_t i = 0; i < all.size(); ++i) {
+      const u64 q = all[i];
+      REQUIRE(q > 2 && q < (1ULL << 51), BM_EINVAL, "primes must lie below 2^51");
+      REQUIRE(q % (2 * c.N) == 1, BM_EINVAL, "primes must be 1 mod 2N");
+      REQUIRE(h_is_prime(q), BM_EINVAL, "modulus is not prime");
+      for (size_t j = 0; j < i; ++j) REQUIRE(all[j] != q, BM_EINVAL, "repeated prime");
+      HostPrime hp;
+      hp.q = q;
+      hp.bits = 64 - __builtin_clzll(q);
+      hp.psi = h_primitive_2n_root(q, c.N);
+      c.primes.push_back(hp);
+    }
+    c.cdt = gaussian_cdt(c.sigma, 19);
+    HIP_OK(hipSetDevice(device));
+    HIP_OK(hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking));
+    c.stream = c.own_stream;
+    c.pool.reset(new DevicePool(device));
+    build_context_tables(c);
+    *out = h.release();
+  });
+}
+
+void bm_ctx_free(bm_ctx* ctx) { delete ctx; }
+
+int bm_ctx_set_group_chunk(bm_ctx* ctx, uint32_t groups) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    ctx->c.group_chunk = (int)groups;
+  });
+}
+
+int bm_ctx_pool_bytes(const bm_ctx* ctx, uint64_t* bytes) {
+  if (!ctx || !bytes) return BM_EINVAL;
+  *bytes = ctx->c.pool->bytes_held();
+  return BM_OK;
+}
+
+// ------------------------------------------------------------------ keys
+
+int bm_rotations_for(uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {
+  return guarded(nullptr, [&] {
+    REQUIRE(n, BM_EINVAL, "n is NULL");
+    REQUIRE(bmx::is_pow2(d) && bmx::is_pow2(k) && k <= d, BM_EDIM, "power-of-two k | d");
+    std::vector<int32_t> r;
+    const uint32_t c = d / k;
+    for (uint32_t t = 0; (1u << t) < c; ++t) r.push_back((int32_t)(1u << t));
+    for (uint32_t t = 0; (1u << t) < k; ++t) {
+      r.push_back((int32_t)(c << t));
+      r.push_back(-(int32_t)(c << t));
+    }
+    *n = r.size();
+    if (out)
+      for (size_t i = 0; i < std::min(cap, r.size()); ++i) out[i] = r[i];
+  });
+}
+
+int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot, bm_sk** sk,
+              bm_pk** pk, bm_evk** evk) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    REQUIRE(n_rot == 0 || rotations, BM_EINVAL, "rotations is NULL");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_sk> s(new bm_sk);
+    s->ctx = ctx;
+    ev::keygen_secret(c, seed, s.get());
+    std::unique_ptr<bm_pk> p;
+    if (pk) {
+      p.reset(new bm_pk);
+      p->ctx = ctx;
+      ev::keygen_public(c, seed, s.get(), p.get());
+    }
+    std::unique_ptr<bm_evk> e;
+    if (evk) {
+      e.reset(new bm_evk);
+      e->ctx = ctx;
+      const int np = c.nprimes();
+      const LimbMap all = kern::ext_map(c, c.L + 1);
+      DBuf s2(&c, (size_t)np * c.N);
+      kern::mul(c, s->s_ntt.p(), 0, s->s_ntt.p(), 0, s2.p(), 0, 1, all);
+      ev::keygen_switch(c, seed, ev::DOM_RLK_A, ev::DOM_RLK_E, 0, s.get(), s2.p(), e->rlk.k);
+      for (size_t i = 0; i < n_rot; ++i) {
+        const u64 g = ev::galois_for_rotation(c, rotations[i]);
+        if (e->gk.count(g)) continue;
+        DBuf sg(&c, (size_t)np * c.N);
+        kern::automorphism(c, s->s_ntt.p(), 0, sg.p(), 0, 1, np, g);
+        std::unique_ptr<bm_switch_key> key(new bm_switch_key);
+        ev::keygen_switch(c, seed, ev::DOM_GK_A, ev::DOM_GK_E, g * (u64)c.dnum, s.get(), sg.p(), key->k);
+        e->gk.emplace(g, std::move(key));
+      }
+    }
+    sync(c);
+    if (sk) *sk = s.release();
+    if (pk) *pk = p.release();
+    if (evk) *evk = e.release();
+  });
+}
+
+int bm_sk_export(const bm_sk* sk, int64_t* s, size_t n) {
+  if (!sk || !s || n != sk->s.size()) return BM_EINVAL;
+  std::memcpy(s, sk->s.data(), n * sizeof(int64_t));
+  return BM_OK;
+}
+
+int bm_pk_export(const bm_pk* pk, uint32_t comp, uint64_t* words, size_t n_words) {
+  if (!pk) return BM_EINVAL;
+  bm_ctx* ctx = pk->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    const size_t ln = (size_t)(c.L + 1) * c.N;
+    REQUIRE(words && comp < 2 && n_words == ln, BM_EINVAL, "pk export size");
+    c.use_stream(nullptr);
+    ev::export_coeffs(c, pk->pk.p() + comp * ln, 1, c.L + 1, words);
+  });
+}
+
+int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t comp, uint64_t* words,
+                  size_t n_words) {
+  if (!evk) return BM_EINVAL;
+  bm_ctx* ctx = evk->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    const int np = c.nprimes();
+    const size_t ln = (size_t)np * c.N;
+    REQUIRE(words && comp < 2 && (int)digit < c.dnum && n_words == ln, BM_EINVAL, "evk export size");
+    const u64* key = galois == 0 ? evk->rlk.k.p() : bmx::galois_key(evk, galois);
+    c.use_stream(nullptr);
+    // undo the Montgomery form (multiply by 1 in Montgomery = divide by R) via a
+    // plain product with R^{-1}: done on the host after the coefficient export
+    DBuf tmp(&c, ln);
+    HIP_OK(hipMemcpyAsync(tmp.p(), key + (size_t)(2 * digit + comp) * ln, ln * sizeof(u64),
+                          hipMemcpyDeviceToDevice, c.stream));
+    const LimbMap all = kern::ext_map(c, c.L + 1);
+    kern::ntt(c, tmp.p(), 0, tmp.p(), 0, 1, all, true);
+    HIP_OK(hipMemcpyAsync(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+    sync(c);
+    for (int l = 0; l < np; ++l) {
+      const u64 q = c.primes[l].q;
+      const u64 r1 = (u64)(((u128)1 << 64) % q);
+      const u64 rinv = h_invmod(r1, q);
+      for (size_t i = 0; i < c.N; ++i) words[(size_t)l * c.N + i] = h_mulmod(words[(size_t)l * c.N + i], rinv, q);
+    }
+  });
+}
+
+void bm_sk_free(bm_sk* sk) { delete sk; }
+void bm_pk_free(bm_pk* pk) { delete pk; }
+void bm_evk_free(bm_evk* evk) { delete evk; }
+
+// ------------------------------------------------------------------ encode / encrypt
+
+int bm_encode(bm_ctx* ctx, const double* slots, size_t n_slots, double scale, int64_t* coeffs) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && slots && coeffs, BM_EINVAL, "NULL argument");
+    REQUIRE(n_slots == ctx->c.n, BM_EINVAL, "n_slots must be N/2");
+    encode_slots(ctx->c.N, slots, nullptr, scale, coeffs);
+  });
+}
+
+static bm_ct* new_ct(bm_ctx* ctx, uint32_t comps, uint32_t limbs, double scale) {
+  std::unique_ptr<bm_ct> ct(new bm_ct);
+  ct->ctx = ctx;
+  ct->comps = comps;
+  ct->limbs = limbs;
+  ct->scale = scale;
+  ct->buf = DBuf(&ctx->c, (size_t)comps * limbs * ctx->c.N);
+  return ct.release();
+}
+
+int bm_encrypt_coeffs(bm_ctx* ctx, const bm_pk* pk, const int64_t* coeffs, uint32_t limbs,
+                      double scale, uint64_t seed, uint64_t ct_id, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && pk && coeffs && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(limbs >= 1 && (int)limbs <= c.L + 1, BM_ELEVEL, "limbs out of range");
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, limbs, scale));
+    ev::encrypt_batch(c, pk, coeffs, 1, (int)limbs, seed, &ct_id, ct->buf.p());
+    sync(c);
+    *out = ct.release();
+  });
+}
+
+int bm_encrypt_query(bm_ctx* ctx, const bm_pk* pk, const float* q, uint32_t d, uint64_t seed,
+                     uint64_t ct_id, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && pk && q && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= N/2");
+    std::vector<double> slots(c.n);
+    for (size_t s = 0; s < c.n; ++s) slots[s] = (double)q[s % d];
+    std::vector<int64_t> m(c.N);
+    encode_slots(c.N, slots.data(), nullptr, c.scale, m.data());
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, c.L + 1, c.scale));
+    ev::encrypt_batch(c, pk, m.data(), 1, c.L + 1, seed, &ct_id, ct->buf.p());
+    sync(c);
+    *out = ct.release();
+  });
+}
+
+static bm_gallery* new_gallery(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t limbs, uint64_t groups,
+                               uint64_t n, double scale) {
+  std::unique_ptr<bm_gallery> g(new bm_gallery);
+  g->ctx = ctx;
+  g->d = d;
+  g->k = k;
+  g->limbs = limbs;
+  g->groups = groups;
+  g->n_templates = n;
+  g->scale = scale;
+  g->buf = DBuf(&ctx->c, (size_t)groups * k * 2 * limbs * ctx->c.N);
+  return g.release();
+}
+
+int bm_encrypt_gallery(bm_ctx* ctx, const bm_pk* pk, const float* x, uint64_t n, uint32_t d,
+                       uint32_t k, uint64_t seed, uint64_t ct_id_base, bm_gallery** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && pk && x && out && n > 0, BM_EINVAL, "NULL argument or empty gallery");
+    Ctx& c = ctx->c;
+    bmx::check_shape(c, d, k);
+    const uint32_t cc = d / k;
+    const uint64_t T = c.n / cc;
+    const uint64_t G = (n + T - 1) / T;
+    const int lg = bmx::gallery_limbs(c, k);
+    REQUIRE(lg >= 2, BM_ELEVEL, "chain too short for this k");
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_gallery> gal(new_gallery(ctx, d, k, (uint32_t)lg, G, n, c.scale));
+    const size_t N = c.N;
+    const uint64_t total = G * k;
+    const uint64_t batch = std::max<uint64_t>(1, std::min<uint64_t>(total, N >= 65536 ? 32 : 256));
+    std::vector<int64_t> m(batch * N);
+    std::vector<u64> ids(batch);
+    for (uint64_t b0 = 0; b0 < total; b0 += batch) {
+      const uint64_t nb = std::min(batch, total - b0);
+      // pack + encode every ciphertext of this batch in parallel
+      std::vector<std::thread> th;
+      const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+          std::vector<double> slots(c.n);
+          for (uint64_t b = t; b < nb; b += nt) {
+            const uint64_t idx = b0 + b, g = idx / k, i = idx % k;
+            for (size_t s = 0; s < c.n; ++s) {
+              const uint64_t tid = g * T + s / cc;
+              slots[s] = tid < n ? (double)x[tid * d + i * cc + s % cc] : 0.0;
+            }
+            encode_slots(N, slots.data(), nullptr, c.scale, m.data() + b * N);
+          }
+        });
+      for (auto& th1 : th) th1.join();
+      for (uint64_t b = 0; b < nb; ++b) ids[b] = ct_id_base + b0 + b;
+      ev::encrypt_batch(c, pk, m.data(), (int)nb, lg, seed, ids.data(),
+                        gal->buf.p() + b0 * 2 * (size_t)lg * N);
+      sync(c);
+    }
+    *out = gal.release();
+  });
+}
+
+int bm_gallery_import(bm_ctx* ctx, const uint64_t* words, uint64_t groups, uint32_t d, uint32_t k,
+                      uint32_t limbs, double scale, uint64_t n_templates, bm_gallery** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && words && out && groups > 0, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    bmx::check_shape(c, d, k);
+    REQUIRE(limbs >= 2 && (int)limbs <= c.L + 1, BM_ELEVEL, "limbs out of range");
+    const uint64_t T = c.n / (d / k);
+    REQUIRE(n_templates <= groups * T && n_templates > (groups - 1) * T, BM_EINVAL,
+            "n_templates does not match the group count");
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_gallery> gal(new_gallery(ctx, d, k, limbs, groups, n_templates, scale));
+    ev::import_coeffs(c, words, (int)(groups * k * 2), (int)limbs, gal->buf.p());
+    *out = gal.release();
+  });
+}
+
+int bm_gallery_export(const bm_gallery* g, uint64_t* words, size_t n_words) {
+  if (!g) return BM_EINVAL;
+  bm_ctx* ctx = g->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    REQUIRE(words && n_words == g->groups * g->k * 2 * g->limbs * c.N, BM_EINVAL, "size");
+    c.use_stream(nullptr);
+    ev::export_coeffs(c, g->buf.p(), (int)(g->groups * g->k * 2), (int)g->limbs, words);
+  });
+}
+
+int bm_gallery_info(const bm_gallery* g, uint64_t* groups, uint32_t* limbs, double* scale) {
+  if (!g) return BM_EINVAL;
+  if (groups) *groups = g->groups;
+  if (limbs) *limbs = g->limbs;
+  if (scale) *scale = g->scale;
+  return BM_OK;
+}
+
+void bm_gallery_free(bm_gallery* g) { delete g; }
+
+// ------------------------------------------------------------------ ciphertexts
+
+int bm_ct_import(bm_ctx* ctx, const uint64_t* words, uint32_t comps, uint32_t limbs, double scale,
+                 bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && words && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(comps >= 2 && comps <= 3, BM_EINVAL, "comps must be 2 or 3");
+    REQUIRE(limbs >= 1 && (int)limbs <= c.L + 1, BM_ELEVEL, "limbs out of range");
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> ct(new_ct(ctx, comps, limbs, scale));
+    ev::import_coeffs(c, words, (int)comps, (int)limbs, ct->buf.p());
+    *out = ct.release();
+  });
+}
+
+int bm_ct_export(const bm_ct* ct, uint64_t* words, size_t n_words) {
+  if (!ct) return BM_EINVAL;
+  bm_ctx* ctx = ct->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    REQUIRE(words && n_words == (size_t)ct->comps * ct->limbs * c.N, BM_EINVAL, "size");
+    c.use_stream(nullptr);
+    ev::export_coeffs(c, ct->buf.p(), (int)ct->comps, (int)ct->limbs, words);
+  });
+}
+
+int bm_ct_info(const bm_ct* ct, uint32_t* comps, uint32_t* limbs, double* scale) {
+  if (!ct) return BM_EINVAL;
+  if (comps) *comps = ct->comps;
+  if (limbs) *limbs = ct->limbs;
+  if (scale) *scale = ct->scale;
+  return BM_OK;
+}
+
+void bm_ct_free(bm_ct* ct) { delete ct; }
+
+int bm_decrypt_slots(bm_ctx* ctx, const bm_sk* sk, const bm_ct* ct, double* slots, size_t n) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && sk && ct && slots, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(n == c.n, BM_EINVAL, "n must be N/2");
+    c.use_stream(nullptr);
+    std::vector<double> m(c.N);
+    ev::decrypt_coeffs(c, sk, ct->buf.p(), (int)ct->comps, (int)ct->limbs, m.data());
+    decode_coeffs(c.N, m.data(), ct->scale, slots, nullptr);
+  });
+}
+
+// ------------------------------------------------------------------ primitive operations
+
+int bm_ntt(bm_ctx* ctx, uint64_t* dev_words, uint32_t n_polys, uint32_t limbs,
+           const uint32_t* prime_ids, int inverse, void* stream) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && dev_words && prime_ids, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(limbs >= 1 && limbs <= (uint32_t)MAX_LIMBS, BM_EINVAL, "limbs out of range");
+    LimbMap m{};
+    m.n = (int)limbs;
+    for (uint32_t l = 0; l < limbs; ++l) {
+      REQUIRE(prime_ids[l] < (uint32_t)c.nprimes(), BM_EINVAL, "prime id out of range");
+      m.prime[l] = (int)prime_ids[l];
+      m.off[l] = m.ooff[l] = (int)l;
+    }
+    c.use_stream(stream);
+    kern::ntt(c, dev_words, (size_t)limbs * c.N, dev_words, (size_t)limbs * c.N, (int)n_polys, m,
+              inverse != 0);
+  });
+}
+
+int bm_op_add(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && a && b && out, BM_EINVAL, "NULL argument");
+    REQUIRE(a->limbs == b->limbs, BM_ELEVEL, "level mismatch");
+    REQUIRE(a->scale == b->scale, BM_ESCALE, "scale mismatch");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const uint32_t comps = std::max(a->comps, b->comps);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, comps, a->limbs, a->scale));
+    const size_t ln = (size_t)a->limbs * c.N;
+    const uint32_t common = std::min(a->comps, b->comps);
+    kern::add(c, a->buf.p(), ln, b->buf.p(), ln, o->buf.p(), ln, (int)common, kern::chain_map(a->limbs));
+    if (comps > common) {
+      const bm_ct* big = a->comps > b->comps ? a : b;
+      HIP_OK(hipMemcpyAsync(o->buf.p() + common * ln, big->buf.p() + common * ln,
+                            (comps - common) * ln * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
+    }
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_pmul(bm_ctx* ctx, const bm_ct* a, const int64_t* pt, double pt_scale, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && a && pt && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const size_t ln = (size_t)a->limbs * c.N;
+    DBuf p(&c, ln);
+    ev::upload_plain(c, pt, 1, (int)a->limbs, p.p());
+    std::unique_ptr<bm_ct> o(new_ct(ctx, a->comps, a->limbs, a->scale * pt_scale));
+    kern::mul(c, a->buf.p(), ln, p.p(), 0, o->buf.p(), ln, (int)a->comps, kern::chain_map(a->limbs));
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_tensor(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && a && b && out, BM_EINVAL, "NULL argument");
+    REQUIRE(a->comps == 2 && b->comps == 2, BM_EINVAL, "tensor needs 2-component inputs");
+    REQUIRE(a->limbs == b->limbs, BM_ELEVEL, "level mismatch");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, 3, a->limbs, a->scale * b->scale));
+    kern::tensor(c, a->buf.p(), 0, 1, b->buf.p(), 0, 1, o->buf.p(), 0, 1, (int)a->limbs, false);
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_relin(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && a && out, BM_EINVAL, "NULL argument");
+    REQUIRE(a->comps == 3, BM_EINVAL, "relinearisation needs 3 components");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, 2, a->limbs, a->scale));
+    ev::relin(c, a->buf.p(), 1, (int)a->limbs, evk->rlk.k.p(), o->buf.p());
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_rescale(bm_ctx* ctx, const bm_ct* a, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && a && out, BM_EINVAL, "NULL argument");
+    REQUIRE(a->limbs >= 2, BM_ELEVEL, "no level left");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, a->comps, a->limbs - 1,
+                                    a->scale / (double)c.primes[a->limbs - 1].q));
+    ev::rescale(c, a->buf.p(), 1, (int)a->comps, (int)a->limbs, o->buf.p());
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_rotate(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, int32_t r, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && a && out, BM_EINVAL, "NULL argument");
+    REQUIRE(a->comps == 2, BM_EINVAL, "rotation needs 2 components");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const u64 g = ev::galois_for_rotation(c, r);
+    const u64* key = bmx::galois_key(evk, g);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, 2, a->limbs, a->scale));
+    ev::rotate(c, a->buf.p(), 1, (int)a->limbs, g, key, o->buf.p(), false);
+    sync(c);
+    *out = o.release();
+  });
+}
+
+int bm_op_drop(bm_ctx* ctx, const bm_ct* a, uint32_t limbs, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && a && out, BM_EINVAL, "NULL argument");
+    REQUIRE(limbs >= 1 && limbs <= a->limbs, BM_ELEVEL, "cannot raise the level");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> o(new_ct(ctx, a->comps, limbs, a->scale));
+    ev::drop(c, a->buf.p(), 1, (int)a->comps, (int)a->limbs, (int)limbs, o->buf.p());
+    sync(c);
+    *out = o.release();
+  });
+}
+
+// ------------------------------------------------------------------ Blind-Match
+
+static bm_masks* make_masks(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* coeffs, double scale) {
+  Ctx& c = ctx->c;
+  std::unique_ptr<bm_masks> m(new bm_masks);
+  m->ctx = ctx;
+  m->d = d;
+  m->k = k;
+  m->scale = scale;
+  m->pt = DBuf(&c, (size_t)k * (c.L + 1) * c.N);
+  ev::upload_plain(c, coeffs, (int)k, c.L + 1, m->pt.p());
+  return m.release();
+}
+
+int bm_masks_create(bm_ctx* ctx, uint32_t d, uint32_t k, bm_masks** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    bmx::check_shape(c, d, k);
+    const uint32_t cc = d / k;
+    const double scale = (double)c.primes[c.L].q;
+    std::vector<int64_t> coeffs((size_t)k * c.N);
+    std::vector<double> slots(c.n);
+    for (uint32_t i = 0; i < k; ++i) {
+      for (size_t s = 0; s < c.n; ++s) slots[s] = ((s % d) / cc == i) ? 1.0 : 0.0;
+      encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
+    }
+    c.use_stream(nullptr);
+    *out = make_masks(ctx, d, k, coeffs.data(), scale);
+  });
+}
+
+int bm_masks_import(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* coeffs, double scale,
+                    bm_masks** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && coeffs && out, BM_EINVAL, "NULL argument");
+    bmx::check_shape(ctx->c, d, k);
+    ctx->c.use_stream(nullptr);
+    *out = make_masks(ctx, d, k, coeffs, scale);
+  });
+}
+
+void bm_masks_free(bm_masks* m) { delete m; }
+
+int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* masks, bm_ct** outs) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && q && masks && outs, BM_EINVAL, "NULL argument");
+    REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
+    Ctx& c = ctx->c;
+    REQUIRE(q->limbs >= 2, BM_ELEVEL, "query needs two limbs");
+    c.use_stream(nullptr);
+    const uint32_t k = masks->k;
+    const size_t nln = (size_t)(q->limbs - 1) * c.N;
+    DBuf all(&c, (size_t)k * 2 * nln);
+    bmx::expand(c, evk, q->buf.p(), (int)q->limbs, masks->pt.p(), masks->d, k, all.p());
+    const double scale = q->scale * masks->scale / (double)c.primes[q->limbs - 1].q;
+    std::vector<std::unique_ptr<bm_ct>> res;
+    for (uint32_t i = 0; i < k; ++i) {
+      res.emplace_back(new_ct(ctx, 2, q->limbs - 1, scale));
+      HIP_OK(hipMemcpyAsync(res.back()->buf.p(), all.p() + (size_t)i * 2 * nln, 2 * nln * sizeof(u64),
+                            hipMemcpyDeviceToDevice, c.stream));
+    }
+    sync(c);
+    for (uint32_t i = 0; i < k; ++i) outs[i] = res[i].release();
+  });
+}
+
+static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
+                      const bm_masks* masks, uint32_t schedule, uint32_t out_limbs, bm_result** out) {
+  Ctx& c = ctx->c;
+  REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
+  REQUIRE(schedule == BM_S1 || schedule == BM_S2, BM_EINVAL, "schedule must be BM_S1 or BM_S2");
+  const uint32_t k = g->k;
+  const int ol_nat = (int)g->limbs - 1;
+  int ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : ol_nat);
+  ol = std::min(ol, ol_nat);
+  REQUIRE(ol >= 1, BM_ELEVEL, "output level");
+  std::unique_ptr<bm_result> r(new bm_result);
+  r->ctx = ctx;
+  r->d = g->d;
+  r->k = k;
+  r->limbs = (uint32_t)ol;
+  r->groups = g->groups;
+  r->n_templates = g->n_templates;
+  r->store = std::make_shared<DBuf>(&c, (size_t)g->groups * 2 * ol * c.N);
+  const u64* cu = nullptr;
+  DBuf expanded;
+  double cu_scale = q->scale;
+  if (k == 1) {
+    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
+    cu = q->buf.p();
+  } else {
+    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
+    std::unique_ptr<bm_masks> own;
+    const bm_masks* m = masks;
+    if (!m) {
+      bm_masks* tmp = nullptr;
+      int st = bm_masks_create(ctx, g->d, k, &tmp);
+      if (st != BM_OK) BM_THROW(st, c.last_error);
+      own.reset(tmp);
+      m = tmp;
+    }
+    REQUIRE(m->d == g->d && m->k == k, BM_EDIM, "masks do not match the gallery shape");
+    const size_t nln = (size_t)(q->limbs - 1) * c.N;
+    expanded = DBuf(&c, (size_t)k * 2 * nln);
+    bmx::expand(c, evk, q->buf.p(), (int)q->limbs, m->pt.p(), g->d, k, expanded.p());
+    cu = expanded.p();
+    cu_scale = q->scale * m->scale / (double)c.primes[q->limbs - 1].q;
+  }
+  REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
+  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, schedule, ol,
+                   r->p(), 0);
+  r->scale = cu_scale * g->scale / (double)c.primes[g->limbs - 1].q;
+  *out = r.release();
+}
+
+int bm_match(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g, const bm_masks* masks,
+             uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && q && g && out, BM_EINVAL, "NULL argument");
+    ctx->c.use_stream(stream);
+    match_one(ctx, evk, q, g, masks, schedule, out_limbs, out);
+  });
+}
+
+int bm_match_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
+                   size_t n_pairs, uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** outs) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && qs && gs && outs, BM_EINVAL, "NULL argument");
+    ctx->c.use_stream(stream);
+    std::vector<std::unique_ptr<bm_result>> res(n_pairs);
+    for (size_t i = 0; i < n_pairs; ++i) {
+      REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
+      bm_result* r = nullptr;
+      match_one(ctx, evk, qs[i], gs[i], nullptr, schedule, out_limbs, &r);
+      res[i].reset(r);
+    }
+    for (size_t i = 0; i < n_pairs; ++i) outs[i] = res[i].release();
+  });
+}
+
+int bm_result_info(const bm_result* r, uint64_t* groups, uint32_t* limbs, double* scale) {
+  if (!r) return BM_EINVAL;
+  if (groups) *groups = r->groups;
+  if (limbs) *limbs = r->limbs;
+  if (scale) *scale = r->scale;
+  return BM_OK;
+}
+
+int bm_result_export(const bm_result* r, uint64_t group, uint64_t* words, size_t n_words) {
+  if (!r) return BM_EINVAL;
+  bm_ctx* ctx = r->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    REQUIRE(group < r->groups, BM_EINVAL, "group out of range");
+    REQUIRE(words && n_words == (size_t)2 * r->limbs * c.N, BM_EINVAL, "size");
+    c.use_stream(nullptr);
+    ev::export_coeffs(c, r->p() + group * 2 * (size_t)r->limbs * c.N, 2, (int)r->limbs, words);
+  });
+}
+
+void bm_result_free(bm_result* r) { delete r; }
+
+int bm_decrypt_scores(bm_ctx* ctx, const bm_sk* sk, const bm_result* r, double* scores, uint64_t n) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && sk && r && scores, BM_EINVAL, "NULL argument");
+    REQUIRE(n == r->n_templates, BM_EINVAL, "n must equal the gallery size");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const uint32_t cc = r->d / r->k;
+    const uint64_t T = c.n / cc;
+    std::vector<double> m(c.N), re(c.n);
+    for (uint64_t g = 0; g < r->groups; ++g) {
+      ev::decrypt_coeffs(c, sk, r->p() + g * 2 * (size_t)r->limbs * c.N, 2, (int)r->limbs, m.data());
+      decode_coeffs(c.N, m.data(), r->scale, re.data(), nullptr);
+      for (uint64_t b = 0; b < T; ++b) {
+        const uint64_t tid = g * T + b;
+        if (tid < n) scores[tid] = re[b * cc];
+      }
+    }
+  });
+}
+
+int bm_top1(const double* scores, uint64_t n, double threshold, int64_t* idx, double* best) {
+  if (!scores || !idx || n == 0) return BM_EINVAL;
+  uint64_t bi = 0;
+  for (uint64_t i = 1; i < n; ++i)
+    if (scores[i] > scores[bi]) bi = i;
+  if (best) *best = scores[bi];
+  *idx = scores[bi] < threshold ? -1 : (int64_t)bi;
+  return BM_OK;
+}
+
+}  // extern "C"

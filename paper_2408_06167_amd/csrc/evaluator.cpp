@@ -1,0 +1,413 @@
+// evaluator.cpp -- CKKS operations over batches of RNS ciphertexts, issued as
+// sequences of kernel launches on the context's stream.
+#include "evaluator.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <thread>
+
+namespace bm {
+
+// ----------------------------------------------------------------- memory
+
+DevicePool::~DevicePool() {
+  for (auto& kv : free_) (void)hipFree(kv.second);
+}
+
+void* DevicePool::alloc(size_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    // release cached blocks and retry once
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      held_ -= kv.first;
+    }
+    free_.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      BM_THROW(BM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  held_ += bytes;
+  return p;
+}
+
+void DevicePool::release(void* p, size_t bytes) {
+  std::lock_guard<std::mutex> g(mu_);
+  free_.emplace(bytes, p);
+}
+
+void DevicePool::trim() {
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto& kv : free_) {
+    (void)hipFree(kv.second);
+    held_ -= kv.first;
+  }
+  free_.clear();
+}
+
+DBuf::DBuf(Ctx* c, size_t words) : ctx_(c), words_(words) {
+  p_ = words ? (u64*)c->pool->alloc(words * sizeof(u64)) : nullptr;
+}
+
+DBuf::~DBuf() {
+  if (p_) ctx_->pool->release(p_, words_ * sizeof(u64));
+}
+
+DBuf& DBuf::operator=(DBuf&& o) noexcept {
+  if (this != &o) {
+    if (p_) ctx_->pool->release(p_, words_ * sizeof(u64));
+    ctx_ = o.ctx_;
+    p_ = o.p_;
+    words_ = o.words_;
+    o.p_ = nullptr;
+    o.words_ = 0;
+  }
+  return *this;
+}
+
+void Ctx::use_stream(void* s) {
+  hipStream_t want = s ? (hipStream_t)s : own_stream;
+  if (want != stream) {
+    if (stream) HIP_OK(hipStreamSynchronize(stream));
+    stream = want;
+  }
+}
+
+Ctx::~Ctx() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  pool.reset();
+  if (owns_tables)
+    for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws,
+                    (void*)d_modup, (void*)d_moddown, (void*)d_rescale})
+      if (p) (void)hipFree(p);
+  if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+std::unique_ptr<Ctx> Ctx::make_lane() const {
+  std::unique_ptr<Ctx> l(new Ctx);
+  l->device = device;
+  l->log_n = log_n;
+  l->N = N;
+  l->n = n;
+  l->L = L;
+  l->K = K;
+  l->alpha = alpha;
+  l->dnum = dnum;
+  l->scale = scale;
+  l->sigma = sigma;
+  l->out_limbs = out_limbs;
+  l->primes = primes;
+  l->cdt = cdt;
+  l->d_primes = d_primes;
+  l->d_tw = d_tw;
+  l->d_tws = d_tws;
+  l->d_itw = d_itw;
+  l->d_itws = d_itws;
+  l->d_modup = d_modup;
+  l->d_moddown = d_moddown;
+  l->d_rescale = d_rescale;
+  l->h_modup = h_modup;
+  l->h_moddown = h_moddown;
+  l->group_chunk = group_chunk;
+  l->owns_tables = false;
+  HIP_OK(hipSetDevice(device));
+  HIP_OK(hipStreamCreateWithFlags(&l->own_stream, hipStreamNonBlocking));
+  l->stream = l->own_stream;
+  l->pool.reset(new DevicePool(device));
+  return l;
+}
+
+namespace ev {
+
+u64 galois_for_rotation(const Ctx& c, long r) {
+  const long n = (long)c.n;
+  long e = ((r % n) + n) % n;
+  return h_powmod(5, (u64)e, 2 * c.N);
+}
+
+// ----------------------------------------------------------------- key switching
+
+void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key, const u64* add0,
+                size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
+  const size_t N = c.N;
+  const ModUpTable& tb = c.h_modup[limbs];
+  const int ext = tb.ext, beta = tb.beta;
+  // 1. coefficient form of the input
+  DBuf xc(&c, (size_t)B * limbs * N);
+  kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true);
+  // 2. ModUp every digit to the extended basis, then back to evaluation form
+  const size_t sy = (size_t)beta * ext * N;
+  DBuf y(&c, (size_t)B * sy);
+  for (int j = 0; j < beta; ++j) {
+    kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs, j);
+    LimbMap m{};
+    const int lo = tb.d[j].src[0], hi = lo + tb.d[j].nsrc;
+    for (int t = 0; t < ext; ++t) {
+      if (t >= lo && t < hi) continue;
+      m.prime[m.n] = tb.ext_prime[t];
+      m.off[m.n] = m.ooff[m.n] = j * ext + t;
+      ++m.n;
+    }
+    kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
+  }
+  // 3. key inner product over Q_l u P
+  const size_t suw = (size_t)2 * ext * N;
+  DBuf uw(&c, (size_t)B * suw);
+  kern::kip(c, y.p(), sy, x, sx, key, uw.p(), suw, B, limbs);
+  // 4. ModDown: special limbs to coefficient form, convert, back, subtract, scale by P^-1
+  LimbMap mp{};
+  for (int comp = 0; comp < 2; ++comp)
+    for (int kk = 0; kk < c.K; ++kk) {
+      mp.prime[mp.n] = c.pid_special(kk);
+      mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
+      ++mp.n;
+    }
+  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true);
+  const size_t sc = (size_t)2 * limbs * N;
+  DBuf conv(&c, (size_t)B * sc);
+  kern::moddown_conv(c, uw.p(), suw, conv.p(), sc, B, limbs);
+  kern::ntt(c, conv.p(), (size_t)limbs * N, conv.p(), (size_t)limbs * N, 2 * B, kern::chain_map(limbs), false);
+  kern::moddown_finish(c, uw.p(), suw, conv.p(), sc, add0, sa0, add1, sa1, out, so, B, limbs);
+}
+
+void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {
+  const size_t ln = (size_t)limbs * c.N;
+  key_switch(c, d + 2 * ln, 3 * ln, B, limbs, rlk, d, 3 * ln, d + ln, 3 * ln, out, 2 * ln);
+}
+
+void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
+  if (limbs < 2) BM_THROW(BM_ELEVEL, "rescale needs at least two limbs");
+  const size_t N = c.N;
+  const int nl = limbs - 1;
+  DBuf last(&c, (size_t)B * comps * N);
+  LimbMap m = kern::single(nl, nl);
+  m.ooff[0] = 0;
+  kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true);
+  DBuf t(&c, (size_t)B * comps * nl * N);
+  kern::rescale_conv(c, last.p(), (size_t)comps * N, N, t.p(), (size_t)comps * nl * N, B, comps, limbs);
+  kern::ntt(c, t.p(), (size_t)nl * N, t.p(), (size_t)nl * N, B * comps, kern::chain_map(nl), false);
+  kern::rescale_finish(c, in, (size_t)comps * limbs * N, t.p(), (size_t)comps * nl * N, out,
+                    (size_t)comps * nl * N, B, comps, limbs);
+}
+
+void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input) {
+  const size_t ln = (size_t)limbs * c.N;
+  DBuf tmp(&c, (size_t)B * 2 * ln);
+  kern::automorphism(c, in, 2 * ln, tmp.p(), 2 * ln, B, 2 * limbs, g);
+  if (add_input) kern::add(c, tmp.p(), 2 * ln, in, 2 * ln, tmp.p(), 2 * ln, B, kern::chain_map(limbs));
+  key_switch(c, tmp.p() + ln, 2 * ln, B, limbs, key, tmp.p(), 2 * ln, add_input ? in + ln : nullptr,
+             2 * ln, out, 2 * ln);
+}
+
+void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out) {
+  const size_t N = c.N;
+  kern::copy_limbs(c, in, (size_t)comps * from * N, (size_t)from * N, out, 1, (size_t)comps * to * N,
+                   0, (size_t)to * N, B, comps, to);
+}
+
+// ----------------------------------------------------------------- plaintexts and encryption
+
+void upload_plain(Ctx& c, const int64_t* host, int B, int limbs, u64* out) {
+  const size_t N = c.N;
+  DBuf raw(&c, (size_t)B * N);
+  HIP_OK(hipMemcpyAsync(raw.p(), host, (size_t)B * N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  kern::reduce_int(c, (const int64_t*)raw.p(), out, (size_t)limbs * N, B, N, kern::chain_map(limbs));
+  kern::ntt(c, out, (size_t)limbs * N, out, (size_t)limbs * N, B, kern::chain_map(limbs), false);
+  HIP_OK(hipStreamSynchronize(c.stream));   // `host` may be released by the caller
+}
+
+template <class F>
+static void parallel_for(size_t n, F f) {
+  const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+  const size_t nt = std::min(hw, n);
+  if (nt <= 1) {
+    for (size_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (size_t t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (size_t i = t; i < n; i += nt) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+void encrypt_batch(Ctx& c, const bm_pk* pk, const int64_t* m, int B, int limbs, u64 seed,
+                   const u64* ct_ids, u64* out) {
+  const size_t N = c.N;
+  const size_t ln = (size_t)limbs * N;
+  std::vector<int64_t> host((size_t)3 * B * N);
+  parallel_for((size_t)3 * B, [&](size_t idx) {
+    const size_t b = idx / 3, which = idx % 3;
+    int64_t* dst = host.data() + (which * B + b) * N;
+    if (which == 0) sample_ternary(seed, DOM_ENC_V, ct_ids[b], N, dst);
+    else sample_gauss(c, seed, which == 1 ? DOM_ENC_E0 : DOM_ENC_E1, ct_ids[b], N, dst);
+  });
+  DBuf v(&c, (size_t)B * ln), e0(&c, (size_t)B * ln), e1(&c, (size_t)B * ln), mm(&c, (size_t)B * ln);
+  upload_plain(c, host.data(), B, limbs, v.p());
+  upload_plain(c, host.data() + (size_t)B * N, B, limbs, e0.p());
+  upload_plain(c, host.data() + (size_t)2 * B * N, B, limbs, e1.p());
+  upload_plain(c, m, B, limbs, mm.p());
+  const u64* pb = pk->pk.p();
+  const u64* pa = pk->pk.p() + (size_t)(c.L + 1) * N;
+  const LimbMap cm = kern::chain_map(limbs);
+  kern::mul(c, v.p(), ln, pb, 0, out, 2 * ln, B, cm);
+  kern::add(c, out, 2 * ln, e0.p(), ln, out, 2 * ln, B, cm);
+  kern::add(c, out, 2 * ln, mm.p(), ln, out, 2 * ln, B, cm);
+  kern::mul(c, v.p(), ln, pa, 0, out + ln, 2 * ln, B, cm);
+  kern::add(c, out + ln, 2 * ln, e1.p(), ln, out + ln, 2 * ln, B, cm);
+}
+
+void export_coeffs(Ctx& c, const u64* dev, int polys, int limbs, u64* host) {
+  const size_t ln = (size_t)limbs * c.N;
+  DBuf tmp(&c, (size_t)polys * ln);
+  kern::ntt(c, dev, ln, tmp.p(), ln, polys, kern::chain_map(limbs), true);
+  HIP_OK(hipMemcpyAsync(host, tmp.p(), (size_t)polys * ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+  HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+void import_coeffs(Ctx& c, const u64* host, int polys, int limbs, u64* dev) {
+  const size_t ln = (size_t)limbs * c.N;
+  HIP_OK(hipMemcpyAsync(dev, host, (size_t)polys * ln * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+  kern::ntt(c, dev, ln, dev, ln, polys, kern::chain_map(limbs), false);
+  HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+void decrypt_coeffs(Ctx& c, const bm_sk* sk, const u64* ct, int comps, int limbs, double* m) {
+  const size_t N = c.N;
+  const int use = std::min(limbs, 2);          // two limbs determine the centred message
+  const size_t ln = (size_t)limbs * N;
+  const LimbMap cm = kern::chain_map(use);
+  DBuf acc(&c, (size_t)use * N), sp(&c, (size_t)use * N), tmp(&c, (size_t)use * N);
+  HIP_OK(hipMemcpyAsync(acc.p(), ct, (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
+  HIP_OK(hipMemcpyAsync(sp.p(), sk->s_ntt.p(), (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice,
+                        c.stream));
+  for (int comp = 1; comp < comps; ++comp) {
+    kern::mul(c, ct + comp * ln, 0, sp.p(), 0, tmp.p(), 0, 1, cm);
+    kern::add(c, acc.p(), 0, tmp.p(), 0, acc.p(), 0, 1, cm);
+    if (comp + 1 < comps) kern::mul(c, sp.p(), 0, sk->s_ntt.p(), 0, sp.p(), 0, 1, cm);
+  }
+  kern::ntt(c, acc.p(), 0, acc.p(), 0, 1, cm, true);
+  std::vector<u64> r((size_t)use * N);
+  HIP_OK(hipMemcpyAsync(r.data(), acc.p(), r.size() * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+  HIP_OK(hipStreamSynchronize(c.stream));
+  const u64 q0 = c.primes[0].q;
+  if (use == 1) {
+    for (size_t i = 0; i < N; ++i) m[i] = r[i] > q0 / 2 ? -(double)(q0 - r[i]) : (double)r[i];
+    return;
+  }
+  const u64 q1 = c.primes[1].q;
+  const u64 inv = h_invmod(q0 % q1, q1);
+  const u128 Q = (u128)q0 * q1;
+  for (size_t i = 0; i < N; ++i) {
+    const u64 a0 = r[i], a1 = r[N + i];
+    const u64 d = (a1 + q1 - a0 % q1) % q1;
+    const u128 v = (u128)a0 + (u128)q0 * h_mulmod(d, inv, q1);
+    m[i] = v > Q / 2 ? -(double)(Q - v) : (double)v;
+  }
+}
+
+// ----------------------------------------------------------------- keys
+
+void keygen_secret(Ctx& c, u64 seed, bm_sk* sk) {
+  const size_t N = c.N;
+  sk->s.resize(N);
+  sample_ternary(seed, DOM_S, 0, N, sk->s.data());
+  const int np = c.nprimes();
+  sk->s_ntt = DBuf(&c, (size_t)np * N);
+  DBuf raw(&c, N);
+  HIP_OK(hipMemcpyAsync(raw.p(), sk->s.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  const LimbMap all = kern::ext_map(c, c.L + 1);
+  kern::reduce_int(c, (const int64_t*)raw.p(), sk->s_ntt.p(), 0, 1, 0, all);
+  kern::ntt(c, sk->s_ntt.p(), 0, sk->s_ntt.p(), 0, 1, all, false);
+  HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+void keygen_public(Ctx& c, u64 seed, const bm_sk* sk, bm_pk* pk) {
+  const size_t N = c.N;
+  const int nq = c.L + 1;
+  std::vector<u64> qs(nq);
+  for (int i = 0; i < nq; ++i) qs[i] = c.primes[i].q;
+  std::vector<u64> a((size_t)nq * N);
+  std::vector<int64_t> e(N);
+  sample_uniform(seed, DOM_PK_A, 0, qs.data(), nq, N, a.data());
+  sample_gauss(c, seed, DOM_PK_E, 0, N, e.data());
+  pk->pk = DBuf(&c, (size_t)2 * nq * N);
+  u64* b = pk->pk.p();
+  u64* ad = b + (size_t)nq * N;
+  HIP_OK(hipMemcpyAsync(ad, a.data(), a.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+  const LimbMap cm = kern::chain_map(nq);
+  kern::ntt(c, ad, 0, ad, 0, 1, cm, false);
+  DBuf ee(&c, (size_t)nq * N);
+  upload_plain(c, e.data(), 1, nq, ee.p());
+  kern::mul(c, ad, 0, sk->s_ntt.p(), 0, b, 0, 1, cm);
+  kern::sub(c, ee.p(), 0, b, 0, b, 0, 1, cm);
+  HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const bm_sk* sk,
+                   const u64* s_prime, DBuf& key) {
+  const size_t N = c.N;
+  const int np = c.nprimes();
+  const int nq = c.L + 1;
+  std::vector<u64> qs(np);
+  for (int i = 0; i < np; ++i) qs[i] = c.primes[i].q;
+  std::vector<u64> a((size_t)c.dnum * np * N);
+  std::vector<int64_t> e((size_t)c.dnum * N);
+  parallel_for((size_t)2 * c.dnum, [&](size_t idx) {
+    const int j = (int)(idx / 2);
+    if (idx % 2 == 0)
+      sample_uniform(seed, dom_a, index_base + j, qs.data(), np, N, a.data() + (size_t)j * np * N);
+    else
+      sample_gauss(c, seed, dom_e, index_base + j, N, e.data() + (size_t)j * N);
+  });
+  key = DBuf(&c, (size_t)c.dnum * 2 * np * N);
+  const LimbMap all = kern::ext_map(c, nq);
+  DBuf raw(&c, N), tmp(&c, (size_t)np * N);
+  // [P]_{q_i} as Shoup pairs, for the gadget term of each digit
+  std::vector<u64> pmod(2 * MAX_LIMBS, 0);
+  for (int j = 0; j < c.dnum; ++j) {
+    u64* bj = key.p() + (size_t)(2 * j) * np * N;
+    u64* aj = key.p() + (size_t)(2 * j + 1) * np * N;
+    HIP_OK(hipMemcpyAsync(aj, a.data() + (size_t)j * np * N, (size_t)np * N * sizeof(u64),
+                          hipMemcpyHostToDevice, c.stream));
+    kern::ntt(c, aj, 0, aj, 0, 1, all, false);
+    HIP_OK(hipMemcpyAsync(raw.p(), e.data() + (size_t)j * N, N * sizeof(int64_t), hipMemcpyHostToDevice,
+                          c.stream));
+    kern::reduce_int(c, (const int64_t*)raw.p(), bj, 0, 1, 0, all);
+    kern::ntt(c, bj, 0, bj, 0, 1, all, false);
+    kern::mul(c, aj, 0, sk->s_ntt.p(), 0, tmp.p(), 0, 1, all);
+    kern::sub(c, bj, 0, tmp.p(), 0, bj, 0, 1, all);
+    // + [P]_{q_i} s' on the limbs of digit j
+    LimbMap dm{};
+    const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, nq);
+    for (int i = lo; i < hi; ++i) {
+      const u64 qi = c.primes[i].q;
+      u64 P = 1;
+      for (int kk = 0; kk < c.K; ++kk) P = h_mulmod(P, c.primes[c.pid_special(kk)].q % qi, qi);
+      pmod[2 * dm.n] = P;
+      pmod[2 * dm.n + 1] = h_shoup(P, qi);
+      dm.prime[dm.n] = i;
+      dm.off[dm.n] = dm.ooff[dm.n] = i;
+      ++dm.n;
+    }
+    DBuf scal(&c, pmod.size());
+    HIP_OK(hipMemcpyAsync(scal.p(), pmod.data(), pmod.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+    kern::axpy_scalar(c, s_prime, 0, scal.p(), bj, 0, 1, dm);
+    HIP_OK(hipStreamSynchronize(c.stream));
+  }
+  kern::to_mont(c, key.p(), (size_t)np * N, 2 * c.dnum, all);
+  HIP_OK(hipStreamSynchronize(c.stream));
+}
+
+}  // namespace ev
+}  // namespace bm

@@ -1,0 +1,47 @@
+// evaluator.hpp -- batched CKKS operations on device buffers (host side).
+#pragma once
+#include "bm_internal.hpp"
+
+namespace bm {
+namespace ev {
+
+// Domains of the seeded SHAKE-256 streams.
+enum : u32 {
+  DOM_S = 1, DOM_PK_A = 2, DOM_PK_E = 3, DOM_RLK_A = 4, DOM_RLK_E = 5, DOM_GK_A = 6, DOM_GK_E = 7,
+  DOM_ENC_V = 8, DOM_ENC_E0 = 9, DOM_ENC_E1 = 10
+};
+
+u64 galois_for_rotation(const Ctx& c, long r);
+
+// Hybrid key switch of x ([B][limbs][N], stride sx, evaluation domain) with
+// `key`; out[b] = (KS_0(x_b) + add0_b, KS_1(x_b) + add1_b) as [2][limbs][N].
+void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key, const u64* add0,
+                size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so);
+// d: [B][3][limbs][N] -> out [B][2][limbs][N]
+void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
+// in: [B][comps][limbs][N] -> out [B][comps][limbs-1][N]
+void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
+// in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
+void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
+// out = first `to` limbs of each of `comps` components of in ([B][comps][from][N])
+void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out);
+
+// coefficient-domain int64 plaintexts [B][N] -> evaluation-domain residues [B][limbs][N]
+void upload_plain(Ctx& c, const int64_t* host, int B, int limbs, u64* out);
+// public-key encryption of B plaintexts (host int64 [B][N]) at `limbs` limbs
+void encrypt_batch(Ctx& c, const bm_pk* pk, const int64_t* m, int B, int limbs, u64 seed,
+                   const u64* ct_ids, u64* out);
+// evaluation-domain ciphertext [comps][limbs][N] -> coefficient words on host
+void export_coeffs(Ctx& c, const u64* dev, int polys, int limbs, u64* host);
+void import_coeffs(Ctx& c, const u64* host, int polys, int limbs, u64* dev);
+// decrypt: centred plaintext coefficients (as doubles) of ct [comps][limbs][N]
+void decrypt_coeffs(Ctx& c, const bm_sk* sk, const u64* ct, int comps, int limbs, double* m);
+
+void keygen_secret(Ctx& c, u64 seed, bm_sk* sk);
+void keygen_public(Ctx& c, u64 seed, const bm_sk* sk, bm_pk* pk);
+// switching key from s' (evaluation domain over all primes) to s
+void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const bm_sk* sk,
+                   const u64* s_prime, DBuf& key);
+
+}  // namespace ev
+}  // namespace bm

@@ -1,0 +1,600 @@
+// kernels.hip -- gfx950 kernels of the RNS-CKKS evaluator.
+//
+// All arithmetic is exact modular integer arithmetic on 64-bit words with
+// primes below 2^51, emulated on the 32-bit VALU (no MFMA, no floating
+// point): constant operands use Shoup's precomputed quotient, variable
+// products use Montgomery reduction with R = 2^64 (switching keys are kept in
+// Montgomery form so one reduction gives the plain product).
+//
+// Grids are (element chunks, limb slot, batch element): blockIdx.y picks the
+// limb (and with it the prime, uniform across the block so its constants come
+// from scalar loads) and blockIdx.z the polynomial of the batch.
+#include "bm_internal.hpp"
+
+namespace bm {
+namespace {
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+  u64 s = a + b;
+  return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + (q - b); }
+
+// a * w mod q for any 64-bit a, w < q, ws = floor(w 2^64 / q)
+__device__ __forceinline__ u64 mul_shoup(u64 a, u64 w, u64 ws, u64 q) {
+  u64 qh = __umul64hi(a, ws);
+  u64 r = a * w - qh * q;
+  return r >= q ? r - q : r;
+}
+
+// a * b * 2^-64 mod q for a < 2^64, b < q (Montgomery, qn = -q^-1 mod 2^64)
+__device__ __forceinline__ u64 mont_mul(u64 a, u64 b, u64 q, u64 qn) {
+  u64 lo = a * b;
+  u64 hi = __umul64hi(a, b);
+  u64 m = lo * qn;
+  u64 t = hi + __umul64hi(m, q) + (lo != 0);
+  return t >= q ? t - q : t;
+}
+
+// plain a * b mod q
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeC& p) {
+  return mont_mul(mont_mul(a, b, p.q, p.qn), p.r2, p.q, p.qn);
+}
+
+// any 64-bit word mod q (Shoup with w = 1)
+__device__ __forceinline__ u64 reduce64(u64 a, const PrimeC& p) { return mul_shoup(a, 1, p.pad[0], p.q); }
+
+constexpr int TPB = 256;        // threads per block of every kernel here
+constexpr int NTT_E = 4096;     // words per NTT block held in LDS
+
+// ---------------------------------------------------------------- NTT
+//
+// Forward: Cooley-Tukey with the negacyclic twist merged into the twiddles
+// (W[k] = psi^{brv(k)}); stage s pairs (j, j + N/2^{s+1}) inside block
+// i = j / (N/2^s) with twiddle W[2^s + i].  The output is in bit-reversed
+// order: position j holds a(psi^{2 brv(j) + 1}).  Inverse: Gentleman-Sande
+// with psi^{-1} in reverse stage order, then the factor N^{-1}.
+//
+// For N > 4096 the stages split into two passes over an N1 x N2 view of the
+// limb: the first log N1 stages act on N2 columns of length N1 with the same
+// twiddles for every column, the remaining log N2 stages act on N1 rows of
+// length N2 with row-dependent twiddles.  One block holds 4096 words: V views
+// of M = 2^logm elements, padded by one word per view in LDS.
+
+template <bool INV>
+__global__ void __launch_bounds__(TPB) k_ntt_pass(const u64* __restrict__ in, size_t in_stride,
+                                                  u64* __restrict__ out, size_t out_stride,
+                                                  LimbMap m, const PrimeC* __restrict__ P,
+                                                  const u64* __restrict__ tw,
+                                                  const u64* __restrict__ tws, int log_n, int logm,
+                                                  int s0, int col, int last) {
+  extern __shared__ u64 sh[];
+  const int N = 1 << log_n;
+  const int M = 1 << logm;
+  const int E = N < NTT_E ? N : NTT_E;
+  const int V = E / M;
+  const int slot = blockIdx.y;
+  const int pid = m.prime[slot];
+  const u64 q = P[pid].q;
+  const u64* W = tw + (size_t)pid * N;
+  const u64* WS = tws + (size_t)pid * N;
+  const u64* src = in + (size_t)blockIdx.z * in_stride + (size_t)m.off[slot] * N;
+  u64* dst = out + (size_t)blockIdx.z * out_stride + (size_t)m.ooff[slot] * N;
+  const int v0 = blockIdx.x * V;
+  const int cstride = N >> logm;   // distance between consecutive elements of a column
+  const int MP = M + 1;            // padded view length in LDS
+
+  for (int e = threadIdx.x; e < E; e += TPB) {
+    int a, v;
+    size_t g;
+    if (col) { a = e / V; v = e % V; g = (size_t)a * cstride + (v0 + v); }
+    else     { v = e / M; a = e % M; g = (size_t)(v0 + v) * M + a; }
+    sh[v * MP + a] = src[g];
+  }
+  __syncthreads();
+
+  const int halfM = M >> 1;
+  const int nbf = V * halfM;
+  if (!INV) {
+    for (int sp = 0; sp < logm; ++sp) {
+      const int h = M >> (sp + 1);
+      for (int bf = threadIdx.x; bf < nbf; bf += TPB) {
+        const int v = bf / halfM, kk = bf % halfM;
+        const int i = kk / h, r = kk % h;
+        const int a0 = 2 * i * h + r;
+        const int vb = col ? 0 : (v0 + v);
+        const int tix = (1 << (s0 + sp)) + (vb << sp) + i;
+        u64* x = sh + v * MP;
+        const u64 U = x[a0];
+        const u64 T = mul_shoup(x[a0 + h], W[tix], WS[tix], q);
+        x[a0] = add_mod(U, T, q);
+        x[a0 + h] = sub_mod(U, T, q);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int sp = logm - 1; sp >= 0; --sp) {
+      const int h = M >> (sp + 1);
+      for (int bf = threadIdx.x; bf < nbf; bf += TPB) {
+        const int v = bf / halfM, kk = bf % halfM;
+        const int i = kk / h, r = kk % h;
+        const int a0 = 2 * i * h + r;
+        const int vb = col ? 0 : (v0 + v);
+        const int tix = (1 << (s0 + sp)) + (vb << sp) + i;
+        u64* x = sh + v * MP;
+        const u64 U = x[a0], Vv = x[a0 + h];
+        x[a0] = add_mod(U, Vv, q);
+        x[a0 + h] = mul_shoup(U + (q - Vv), W[tix], WS[tix], q);
+      }
+      __syncthreads();
+    }
+  }
+
+  const u64 ninv = P[pid].ninv, ninv_s = P[pid].ninv_s;
+  for (int e = threadIdx.x; e < E; e += TPB) {
+    int a, v;
+    size_t g;
+    if (col) { a = e / V; v = e % V; g = (size_t)a * cstride + (v0 + v); }
+    else     { v = e / M; a = e % M; g = (size_t)(v0 + v) * M + a; }
+    u64 x = sh[v * MP + a];
+    if (last) x = mul_shoup(x, ninv, ninv_s, q);
+    dst[g] = x;
+  }
+}
+
+// ---------------------------------------------------------------- elementwise
+
+#define EW_PROLOGUE                                               \
+  const int slot = blockIdx.y;                                    \
+  const size_t loff = (size_t)m.off[slot] * N;                    \
+  const PrimeC& pr = P[m.prime[slot]];                            \
+  const u64 q = pr.q;                                             \
+  (void)q;                                                        \
+  const size_t bz = blockIdx.z;
+
+#define EW_LOOP for (int i = blockIdx.x * TPB + threadIdx.x; i < N; i += gridDim.x * TPB)
+
+__global__ void k_add(const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+                      LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const u64* A = a + bz * sa + loff;
+  const u64* B = b + bz * sb + loff;
+  u64* O = o + bz * so + loff;
+  EW_LOOP O[i] = add_mod(A[i], B[i], q);
+}
+
+__global__ void k_sub(const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+                      LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const u64* A = a + bz * sa + loff;
+  const u64* B = b + bz * sb + loff;
+  u64* O = o + bz * so + loff;
+  EW_LOOP O[i] = sub_mod(A[i], B[i], q);
+}
+
+__global__ void k_mul(const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
+                      LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const u64* A = a + bz * sa + loff;
+  const u64* B = b + bz * sb + loff;
+  u64* O = o + bz * so + loff;
+  EW_LOOP O[i] = mul_mod(A[i], B[i], pr);
+}
+
+__global__ void k_neg(const u64* a, size_t sa, u64* o, size_t so, LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const u64* A = a + bz * sa + loff;
+  u64* O = o + bz * so + loff;
+  EW_LOOP O[i] = A[i] ? q - A[i] : 0;
+}
+
+__global__ void k_to_mont(u64* a, size_t sa, LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  u64* A = a + bz * sa + loff;
+  EW_LOOP A[i] = mont_mul(A[i], pr.r2, q, pr.qn);
+}
+
+// o += s * scal[slot] (scal holds a Shoup pair per limb slot)
+__global__ void k_axpy_scalar(const u64* s, size_t ss, const u64* scal, u64* o, size_t so,
+                              LimbMap m, const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const u64* S = s + bz * ss + loff;
+  u64* O = o + bz * so + loff;
+  const u64 w = scal[2 * slot], ws = scal[2 * slot + 1];
+  EW_LOOP O[i] = add_mod(O[i], mul_shoup(S[i], w, ws, q), q);
+}
+
+__global__ void k_reduce_int(const int64_t* src, size_t ss, u64* o, size_t so, LimbMap m,
+                             const PrimeC* P, int N) {
+  EW_PROLOGUE
+  const int64_t* S = src + bz * ss;
+  u64* O = o + bz * so + loff;
+  EW_LOOP {
+    const int64_t x = S[i];
+    if (x >= 0) {
+      O[i] = reduce64((u64)x, pr);
+    } else {
+      const u64 r = reduce64((u64)(-x), pr);
+      O[i] = r ? q - r : 0;
+    }
+  }
+}
+
+// (a0, a1) x (b0, b1) -> (a0 b0, a0 b1 + a1 b0, a1 b1); limb slot = chain limb.
+// Batch element z pairs operand a[z / a_div] with operand b[z % b_mod], so one
+// launch can cross several queries with several gallery groups.
+__global__ void k_tensor(const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
+                         u64* o, size_t so, int limbs, const PrimeC* P, int N, int accumulate) {
+  const int l = blockIdx.y;
+  const PrimeC& pr = P[l];
+  const u64 q = pr.q;
+  const size_t bz = blockIdx.z;
+  const size_t ln = (size_t)limbs * N;
+  const u64* A0 = a + (bz / a_div) * sa + (size_t)l * N;
+  const u64* A1 = A0 + ln;
+  const u64* B0 = b + (bz % b_mod) * sb + (size_t)l * N;
+  const u64* B1 = B0 + ln;
+  u64* O0 = o + bz * so + (size_t)l * N;
+  u64* O1 = O0 + ln;
+  u64* O2 = O1 + ln;
+  EW_LOOP {
+    const u64 x0 = A0[i], x1 = A1[i], y0 = B0[i], y1 = B1[i];
+    u64 d0 = mul_mod(x0, y0, pr);
+    u64 d1 = add_mod(mul_mod(x0, y1, pr), mul_mod(x1, y0, pr), q);
+    u64 d2 = mul_mod(x1, y1, pr);
+    if (accumulate) {
+      d0 = add_mod(d0, O0[i], q);
+      d1 = add_mod(d1, O1[i], q);
+      d2 = add_mod(d2, O2[i], q);
+    }
+    O0[i] = d0;
+    O1[i] = d1;
+    O2[i] = d2;
+  }
+}
+
+// evaluation-domain automorphism: out[j] = in[j'] with
+// 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.  blockIdx.y = row (comp*limbs + limb)
+__global__ void k_automorphism(const u64* in, size_t si, u64* out, size_t so, u64 g, int log_n) {
+  const int N = 1 << log_n;
+  const size_t row = (size_t)blockIdx.y * N;
+  const u64* I = in + (size_t)blockIdx.z * si + row;
+  u64* O = out + (size_t)blockIdx.z * so + row;
+  const u32 mask2n = (2u << log_n) - 1;
+  EW_LOOP {
+    const u32 rj = __brev((u32)i) >> (32 - log_n);
+    const u32 e = (u32)(((u64)(2 * rj + 1) * g) & mask2n);
+    const u32 src = __brev((e - 1) >> 1) >> (32 - log_n);
+    O[i] = I[src];
+  }
+}
+
+// ModUp of digit j at `limbs` chain limbs.  blockIdx.y enumerates the target
+// slots outside the digit; output slot t of y (coefficient domain).
+__global__ void k_modup(const u64* xc, size_t sx, u64* y, size_t sy, const ModUpTable* T,
+                        int j, const PrimeC* P, int N) {
+  const ModUpTable& tb = *T;
+  const ModUpDigit& dg = tb.d[j];
+  const int lo = dg.src[0];
+  int t = blockIdx.y;
+  if (t >= lo) t += dg.nsrc;           // skip the digit's own slots
+  const PrimeC& pt = P[tb.ext_prime[t]];
+  const u64 qt = pt.q;
+  const size_t bz = blockIdx.z;
+  const u64* X = xc + bz * sx;
+  u64* Y = y + bz * sy + (size_t)t * N;
+  EW_LOOP {
+    u64 acc = 0;
+    for (int a = 0; a < dg.nsrc; ++a) {
+      const int src = dg.src[a];
+      const u64 qi = P[src].q;
+      const u64 v = mul_shoup(X[(size_t)src * N + i], dg.qhatinv[a][0], dg.qhatinv[a][1], qi);
+      acc = add_mod(acc, mul_shoup(v, dg.qhat[a][t][0], dg.qhat[a][t][1], qt), qt);
+    }
+    Y[i] = acc;
+  }
+}
+
+// key inner product over every extended slot t of the level:
+// u[t] = sum_j y_j[t] * b_j[key limb of t], w[t] likewise with a_j.  For the
+// digit's own slots y_j[t] is the input limb itself (evaluation domain).
+__global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u64* key,
+                      u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
+                      const PrimeC* P, int N) {
+  const ModUpTable& tb = *T;
+  const int t = blockIdx.y;
+  const int ext = tb.ext;
+  const int pid = tb.ext_prime[t];
+  const PrimeC& pr = P[pid];
+  const u64 q = pr.q;
+  const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
+  const size_t bz = blockIdx.z;
+  u64* U = uw + bz * suw + (size_t)t * N;
+  u64* Wp = U + (size_t)ext * N;
+  EW_LOOP {
+    u64 su = 0, sw = 0;
+    for (int j = 0; j < tb.beta; ++j) {
+      const ModUpDigit& dg = tb.d[j];
+      const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+      const u64 v = own ? x[bz * sx + (size_t)t * N + i] : y[bz * sy + ((size_t)j * ext + t) * N + i];
+      const u64* kb = key + ((size_t)(2 * j) * key_limbs + kl) * N;
+      const u64* ka = key + ((size_t)(2 * j + 1) * key_limbs + kl) * N;
+      su = add_mod(su, mont_mul(v, kb[i], q, pr.qn), q);
+      sw = add_mod(sw, mont_mul(v, ka[i], q, pr.qn), q);
+    }
+    U[i] = su;
+    Wp[i] = sw;
+  }
+}
+
+// conv[c][i] = sum_k [u_c[p_k] (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}   (coefficient domain)
+__global__ void k_moddown_conv(const u64* uw, size_t suw, u64* conv, size_t sc,
+                               const ModDownTable* D, int limbs, const PrimeC* P, int N) {
+  const ModDownTable& md = *D;
+  const int i = blockIdx.y % limbs, c = blockIdx.y / limbs;
+  const u64 qi = P[i].q;
+  const int ext = limbs + md.K;
+  const size_t bz = blockIdx.z;
+  const u64* Uc = uw + bz * suw + (size_t)c * ext * N;
+  u64* C = conv + bz * sc + ((size_t)c * limbs + i) * N;
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) {
+    u64 acc = 0;
+    for (int k = 0; k < md.K; ++k) {
+      const u64 pk = P[md.pprime[k]].q;
+      const u64 v = mul_shoup(Uc[(size_t)(limbs + k) * N + e], md.phatinv[k][0], md.phatinv[k][1], pk);
+      acc = add_mod(acc, mul_shoup(v, md.phat[k][i][0], md.phat[k][i][1], qi), qi);
+    }
+    C[e] = acc;
+  }
+}
+
+// out[c][i] = (u[c][i] - conv[c][i]) P^-1 mod q_i (+ add_c[i])
+__global__ void k_moddown_finish(const u64* uw, size_t suw, const u64* conv, size_t sc,
+                                 const u64* add0, size_t sa0, const u64* add1, size_t sa1,
+                                 u64* out, size_t so, const ModDownTable* D, int limbs,
+                                 const PrimeC* P, int N) {
+  const ModDownTable& md = *D;
+  const int i = blockIdx.y % limbs, c = blockIdx.y / limbs;
+  const u64 qi = P[i].q;
+  const int ext = limbs + md.K;
+  const size_t bz = blockIdx.z;
+  const u64* U = uw + bz * suw + ((size_t)c * ext + i) * N;
+  const u64* C = conv + bz * sc + ((size_t)c * limbs + i) * N;
+  const u64* A = c == 0 ? add0 : add1;
+  const size_t sA = c == 0 ? sa0 : sa1;
+  const u64* Ad = A ? A + bz * sA + (size_t)i * N : nullptr;
+  u64* O = out + bz * so + ((size_t)c * limbs + i) * N;
+  const u64 w = md.pinv[i][0], ws = md.pinv[i][1];
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) {
+    u64 r = mul_shoup(sub_mod(U[e], C[e], qi), w, ws, qi);
+    if (Ad) r = add_mod(r, Ad[e], qi);
+    O[e] = r;
+  }
+}
+
+// t[c][i] = last_c mod q_i for i < limbs-1 (coefficient domain)
+__global__ void k_rescale_conv(const u64* last, size_t sl, size_t lcs, u64* t, size_t st,
+                               int comps, int limbs, const PrimeC* P, int N) {
+  const int nl = limbs - 1;
+  const int i = blockIdx.y % nl, c = blockIdx.y / nl;
+  const PrimeC& pr = P[i];
+  const size_t bz = blockIdx.z;
+  const u64* Lp = last + bz * sl + (size_t)c * lcs;
+  u64* T = t + bz * st + ((size_t)c * nl + i) * N;
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) T[e] = reduce64(Lp[e], pr);
+}
+
+// out[c][i] = (in[c][i] - t[c][i]) q_last^-1 mod q_i
+__global__ void k_rescale_finish(const u64* in, size_t si, const u64* t, size_t st, u64* out,
+                                 size_t so, const u64* rs, int comps, int limbs, int nq,
+                                 const PrimeC* P, int N) {
+  const int nl = limbs - 1;
+  const int i = blockIdx.y % nl, c = blockIdx.y / nl;
+  const u64 qi = P[i].q;
+  const size_t bz = blockIdx.z;
+  const u64* I = in + bz * si + ((size_t)c * limbs + i) * N;
+  const u64* T = t + bz * st + ((size_t)c * nl + i) * N;
+  u64* O = out + bz * so + ((size_t)c * nl + i) * N;
+  const u64* pair = rs + ((size_t)(limbs - 1) * nq + i) * 2;
+  const u64 w = pair[0], ws = pair[1];
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB)
+    O[e] = mul_shoup(sub_mod(I[e], T[e], qi), w, ws, qi);
+}
+
+// batch element z goes to out + (z / div) * so_hi + (z % div) * so_lo
+__global__ void k_copy_limbs(const u64* in, size_t si, size_t ics, u64* out, int div, size_t so_hi,
+                             size_t so_lo, size_t ocs, int limbs, int N) {
+  const int l = blockIdx.y % limbs, c = blockIdx.y / limbs;
+  const size_t bz = blockIdx.z;
+  const u64* I = in + bz * si + c * ics + (size_t)l * N;
+  u64* O = out + (bz / div) * so_hi + (bz % div) * so_lo + c * ocs + (size_t)l * N;
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) O[e] = I[e];
+}
+
+inline dim3 ew_grid(size_t N, int ys, int B) {
+  size_t bx = (N + TPB * 4 - 1) / (TPB * 4);
+  if (bx == 0) bx = 1;
+  return dim3((unsigned)bx, (unsigned)ys, (unsigned)B);
+}
+
+inline void check_launch() { HIP_OK(hipGetLastError()); }
+
+}  // namespace
+
+namespace kern {
+
+LimbMap chain_map(int limbs) {
+  LimbMap m{};
+  m.n = limbs;
+  for (int i = 0; i < limbs; ++i) { m.prime[i] = i; m.off[i] = m.ooff[i] = i; }
+  return m;
+}
+
+LimbMap ext_map(const Ctx& c, int limbs) {
+  LimbMap m{};
+  m.n = limbs + c.K;
+  for (int i = 0; i < limbs; ++i) { m.prime[i] = i; m.off[i] = m.ooff[i] = i; }
+  for (int k = 0; k < c.K; ++k) {
+    m.prime[limbs + k] = c.pid_special(k);
+    m.off[limbs + k] = m.ooff[limbs + k] = limbs + k;
+  }
+  return m;
+}
+
+LimbMap single(int prime, int off) {
+  LimbMap m{};
+  m.n = 1;
+  m.prime[0] = prime;
+  m.off[0] = m.ooff[0] = off;
+  return m;
+}
+
+void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+         const LimbMap& m, bool inverse) {
+  if (B <= 0 || m.n <= 0) return;
+  const int logn = c.log_n;
+  const int N = 1 << logn;
+  const int E = N < NTT_E ? N : NTT_E;
+  const dim3 grid((unsigned)(N / E), (unsigned)m.n, (unsigned)B);
+  auto launch = [&](const u64* src, size_t ss, u64* dst, size_t ds, int logm, int s0, int col,
+                    int last) {
+    const int M = 1 << logm;
+    const size_t lds = (size_t)(E / M) * (M + 1) * sizeof(u64);
+    if (inverse)
+      hipLaunchKernelGGL(k_ntt_pass<true>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, m,
+                         c.d_primes, c.d_itw, c.d_itws, logn, logm, s0, col, last);
+    else
+      hipLaunchKernelGGL(k_ntt_pass<false>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, m,
+                         c.d_primes, c.d_tw, c.d_tws, logn, logm, s0, col, last);
+    check_launch();
+  };
+  if (logn <= 12) {
+    launch(in, in_stride, out, out_stride, logn, 0, 0, inverse ? 1 : 0);
+    return;
+  }
+  const int la = logn / 2, lb = logn - la;
+  if (!inverse) {
+    launch(in, in_stride, out, out_stride, la, 0, 1, 0);
+    launch(out, out_stride, out, out_stride, lb, la, 0, 0);
+  } else {
+    launch(in, in_stride, out, out_stride, lb, la, 0, 0);
+    launch(out, out_stride, out, out_stride, la, 0, 1, 1);
+  }
+}
+
+void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
+                size_t src_stride, const LimbMap& m) {
+  hipLaunchKernelGGL(k_reduce_int, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, src, src_stride,
+                     out, out_stride, m, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
+         const LimbMap& m) {
+  hipLaunchKernelGGL(k_add, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
+         const LimbMap& m) {
+  hipLaunchKernelGGL(k_sub, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
+         const LimbMap& m) {
+  hipLaunchKernelGGL(k_mul, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m) {
+  hipLaunchKernelGGL(k_neg, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, o, so, m,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m) {
+  hipLaunchKernelGGL(k_to_mont, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, m,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o, size_t so, int B,
+                 const LimbMap& m) {
+  hipLaunchKernelGGL(k_axpy_scalar, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, s, ss, scal, o,
+                     so, m, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
+            u64* o, size_t so, int B, int limbs, bool accumulate) {
+  hipLaunchKernelGGL(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, b, sb,
+                     b_mod, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
+  check_launch();
+}
+
+void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B, int rows,
+                  u64 g) {
+  hipLaunchKernelGGL(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out,
+                     so, g, c.log_n);
+  check_launch();
+}
+
+void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  const int targets = tb.ext - tb.d[j].nsrc;
+  hipLaunchKernelGGL(k_modup, ew_grid(c.N, targets, B), dim3(TPB), 0, c.stream, xc, sx,
+                     y + (size_t)j * tb.ext * c.N, sy, c.d_modup + limbs, j, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key,
+         u64* uw, size_t suw, int B, int limbs) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  hipLaunchKernelGGL(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
+                     key, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs) {
+  hipLaunchKernelGGL(k_moddown_conv, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
+                     conv, sc, c.d_moddown, limbs, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void moddown_finish(const Ctx& c, const u64* uw, size_t suw, const u64* conv, size_t sc,
+                    const u64* add0, size_t sadd0, const u64* add1, size_t sadd1, u64* out,
+                    size_t so, int B, int limbs) {
+  hipLaunchKernelGGL(k_moddown_finish, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
+                     conv, sc, add0, sadd0, add1, sadd1, out, so, c.d_moddown, limbs, c.d_primes,
+                     (int)c.N);
+  check_launch();
+}
+
+void rescale_conv(const Ctx& c, const u64* last, size_t sl, size_t last_comp_stride, u64* t,
+                  size_t st, int B, int comps, int limbs) {
+  hipLaunchKernelGGL(k_rescale_conv, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0, c.stream,
+                     last, sl, last_comp_stride, t, st, comps, limbs, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t st, u64* out,
+                    size_t so, int B, int comps, int limbs) {
+  hipLaunchKernelGGL(k_rescale_finish, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0,
+                     c.stream, in, si, t, st, out, so, c.d_rescale, comps, limbs, c.L + 1,
+                     c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
+                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs) {
+  hipLaunchKernelGGL(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
+                     in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
+  check_launch();
+}
+
+}  // namespace kern
+}  // namespace bm

@@ -1,0 +1,56 @@
+"""Shared set-up of the GPU parity tests: one library context per preset, and
+the oracle's key set for the same seed.  Oracle inputs are made by the oracle
+or by the seeded generators, never by the library."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import ckks, blindmatch as obm
+
+SEED = 0xB11D
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@functools.lru_cache(maxsize=None)
+def lib_ctx(preset):
+    import paper_2408_06167_amd as bm
+    return bm.bm_ctx_create(bm.bm_params_preset(preset), 0)
+
+
+@functools.lru_cache(maxsize=None)
+def lib_keys(preset, rots):
+    import paper_2408_06167_amd as bm
+    return bm.bm_keygen(lib_ctx(preset), SEED, list(rots))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_keys(preset, rots):
+    P = ckks.Params.preset(preset)
+    return P, ckks.keygen(P, SEED, list(rots))
+
+
+def all_rotations(preset, shapes):
+    P = ckks.Params.preset(preset)
+    r = set()
+    for d, k in shapes:
+        r.update(obm.rotations_needed(P, d, k))
+    return tuple(sorted(r))
+
+
+def ct_words(ct):
+    """Oracle ciphertext -> [comps][limbs][N] uint64."""
+    return np.stack(ct.c)
+
+
+def assert_words_equal(got, want, what):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape, "%s: shape %s vs %s" % (what, got.shape, want.shape)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, "%s: %d of %d words differ, first at %s" % (
+        what, bad.shape[0], got.size, tuple(bad[0]))
