@@ -100,6 +100,17 @@ int bm_ctx_set_group_chunk(bm_ctx *ctx, uint32_t groups);
 /* Device memory currently held by the context's caching pool, in bytes. */
 int bm_ctx_pool_bytes(const bm_ctx *ctx, uint64_t *bytes);
 
+/* Kernel timing for measurement.  bm_profile_enable(ctx, 1) clears the
+ * counters and brackets every subsequent kernel launch of the context (and of
+ * its server lanes) with HIP events on the launch stream; 0 stops.
+ * bm_profile_dump waits for the recorded events and writes one text line per
+ * kernel class, "name launches total_ms algorithmic_bytes algorithmic_ops",
+ * into buf (NUL-terminated, truncated to cap); *needed receives the full
+ * length.  Algorithmic bytes count each distinct input and output word once
+ * per launch; ops are modular multiplications (butterflies for the NTT). */
+int bm_profile_enable(bm_ctx *ctx, int on);
+int bm_profile_dump(bm_ctx *ctx, char *buf, size_t cap, size_t *needed);
+
 /* ------------------------------------------------------------------ keys */
 
 /* Key set of Sec. 3.1 (public key for clients, evaluation key for the

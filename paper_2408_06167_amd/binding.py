@@ -54,6 +54,8 @@ _SIGS = {
     "bm_ctx_free": (None, [_P]),
     "bm_ctx_set_group_chunk": (ctypes.c_int, [_P, _u32]),
     "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
+    "bm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "bm_profile_dump": (ctypes.c_int, [_P, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
     "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
     "bm_rotations_for": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_sk_export": (ctypes.c_int, [_P, _P, _sz]),
@@ -175,6 +177,23 @@ def bm_ctx_pool_bytes(ctx):
     v = _u64()
     _check(lib().bm_ctx_pool_bytes(ctx, ctypes.byref(v)), "bm_ctx_pool_bytes", ctx)
     return int(v.value)
+
+
+def bm_profile_enable(ctx, on=True):
+    _check(lib().bm_profile_enable(ctx, 1 if on else 0), "bm_profile_enable", ctx)
+
+
+def bm_profile_dump(ctx):
+    """{kernel: dict(launches, ms, bytes, ops)} since bm_profile_enable."""
+    need = _sz()
+    _check(lib().bm_profile_dump(ctx, None, 0, ctypes.byref(need)), "bm_profile_dump", ctx)
+    buf = ctypes.create_string_buffer(need.value + 1)
+    _check(lib().bm_profile_dump(ctx, buf, need.value + 1, ctypes.byref(need)), "bm_profile_dump", ctx)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms, b, o = line.split()
+        out[name] = dict(launches=int(n), ms=float(ms), bytes=float(b), ops=float(o))
+    return out
 
 
 def bm_rotations_for(d, k):

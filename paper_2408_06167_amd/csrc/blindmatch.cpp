@@ -57,7 +57,7 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
       const long step = ((i >> t) & 1) == 0 ? -r : r;
       const u64 g = ev::galois_for_rotation(c, step);
       ev::rotate(c, ci, 1, nl, g, galois_key(evk, g), tmp.p(), true);
-      HIP_OK(hipMemcpyAsync(ci, tmp.p(), 2 * nln * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
+      HIP_OK(dev::memcpy_async(ci, tmp.p(), 2 * nln * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
     }
   }
 }

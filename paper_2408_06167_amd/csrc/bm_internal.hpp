@@ -32,6 +32,34 @@ constexpr int MAX_LIMBS = 24;    // limbs in one polynomial of a launch
 constexpr int MAX_DIGITS = 16;
 constexpr int MAX_ALPHA = 4;
 
+// ----------------------------------------------------------------- device runtime
+//
+// Every HIP runtime call of the library goes through these wrappers.  With
+// the environment variable BM_DRY_RUN=1 they run without a GPU: device memory
+// is host memory, copies are memcpy, kernel launches are skipped and every
+// launch check still runs, so the launch geometry of whole call sequences can
+// be validated on a CPU-only machine.
+namespace dev {
+bool dry();
+hipError_t malloc_raw(void** p, size_t bytes);
+template <class T>
+inline hipError_t malloc(T** p, size_t bytes) { return malloc_raw((void**)p, bytes); }
+hipError_t free(void* p);
+hipError_t memcpy(void* d, const void* s, size_t bytes, hipMemcpyKind k);
+hipError_t memcpy_async(void* d, const void* s, size_t bytes, hipMemcpyKind k, hipStream_t st);
+hipError_t stream_sync(hipStream_t s);
+hipError_t stream_create(hipStream_t* s);
+hipError_t stream_destroy(hipStream_t s);
+hipError_t set_device(int d);
+hipError_t event_create(hipEvent_t* e, bool timing);
+hipError_t event_destroy(hipEvent_t e);
+hipError_t event_record(hipEvent_t e, hipStream_t s);
+hipError_t event_sync(hipEvent_t e);
+hipError_t event_elapsed(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t event_query(hipEvent_t e);
+hipError_t last_error();
+}  // namespace dev
+
 // ----------------------------------------------------------------- errors
 
 struct Error {
@@ -94,6 +122,22 @@ struct ModDownTable {
 
 // ----------------------------------------------------------------- device memory
 
+// Registry of live device allocations.  Every kernel launcher checks, before
+// the launch, that each range its kernel will read or write lies inside one
+// registered allocation, and raises BM_EINVAL instead of launching otherwise.
+namespace audit {
+void add(const void* p, size_t bytes);
+void remove(const void* p);
+// throws unless [p, p + bytes) is inside one registered allocation
+void check(const void* p, size_t bytes, const char* what);
+// RAII registration of a caller-owned buffer for the duration of a call
+struct Scoped {
+  const void* p;
+  Scoped(const void* p_, size_t bytes) : p(p_) { add(p_, bytes); }
+  ~Scoped() { remove(p); }
+};
+}  // namespace audit
+
 // Caching allocator: blocks are recycled by exact size.  All work of a context
 // is ordered on one stream, so a block freed by the host can be handed to the
 // next request immediately (stream order protects pending readers).
@@ -114,6 +158,35 @@ class DevicePool {
 };
 
 struct Ctx;
+
+// Optional per-kernel timing: when on, every launch is bracketed by two HIP
+// events on the launch stream and charged with its algorithmic bytes and
+// operations (counted by the launcher from the shapes it was given).
+class Profiler {
+ public:
+  struct Entry {
+    uint64_t launches = 0;
+    double ms = 0, bytes = 0, ops = 0;
+  };
+  bool on = false;
+  void begin(hipStream_t s, const char* name, double bytes, double ops);
+  void end(hipStream_t s);
+  void collect();                       // waits for pending events, accumulates
+  void reset();
+  std::map<std::string, Entry> entries;
+  ~Profiler();
+
+ private:
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes, ops;
+  };
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> spare_;
+  std::mutex mu_;
+  hipEvent_t take();
+};
 
 // RAII device buffer of u64 words from a context's pool.
 class DBuf {
@@ -171,6 +244,7 @@ struct Ctx {
   int group_chunk = 0;             // gallery groups per batched pass (0 = auto)
 
   bool owns_tables = true;         // false for a lane sharing another context's tables
+  std::shared_ptr<Profiler> prof = std::make_shared<Profiler>();
 
   int nprimes() const { return (int)primes.size(); }
   int pid_special(int k) const { return L + 1 + k; }

@@ -3,6 +3,7 @@
 // documented in include/blindmatch.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <thread>
 
@@ -50,7 +51,7 @@ std::vector<u64> primes_below(int bits, size_t N, int count, const std::vector<u
   return out;
 }
 
-void sync(Ctx& c) { HIP_OK(hipStreamSynchronize(c.stream)); }
+void sync(Ctx& c) { HIP_OK(dev::stream_sync(c.stream)); }
 
 }  // namespace
 
@@ -154,8 +155,8 @@ int bm_ctx_create(const bm_params* p, int device, bm_ctx** out) {
       c.primes.push_back(hp);
     }
     c.cdt = gaussian_cdt(c.sigma, 19);
-    HIP_OK(hipSetDevice(device));
-    HIP_OK(hipStreamCreateWithFlags(&c.own_stream, hipStreamNonBlocking));
+    HIP_OK(dev::set_device(device));
+    HIP_OK(dev::stream_create(&c.own_stream));
     c.stream = c.own_stream;
     c.pool.reset(new DevicePool(device));
     build_context_tables(c);
@@ -176,6 +177,36 @@ int bm_ctx_pool_bytes(const bm_ctx* ctx, uint64_t* bytes) {
   if (!ctx || !bytes) return BM_EINVAL;
   *bytes = ctx->c.pool->bytes_held();
   return BM_OK;
+}
+
+int bm_profile_enable(bm_ctx* ctx, int on) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    Profiler& p = *ctx->c.prof;
+    if (on) p.reset();
+    p.on = on != 0;
+  });
+}
+
+int bm_profile_dump(bm_ctx* ctx, char* buf, size_t cap, size_t* needed) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    Profiler& p = *ctx->c.prof;
+    p.collect();
+    std::string out;
+    char line[256];
+    for (auto& kv : p.entries) {
+      std::snprintf(line, sizeof(line), "%s %llu %.6f %.0f %.0f\n", kv.first.c_str(),
+                    (unsigned long long)kv.second.launches, kv.second.ms, kv.second.bytes, kv.second.ops);
+      out += line;
+    }
+    if (needed) *needed = out.size();
+    if (buf && cap) {
+      const size_t n = std::min(cap - 1, out.size());
+      std::memcpy(buf, out.data(), n);
+      buf[n] = 0;
+    }
+  });
 }
 
 // ------------------------------------------------------------------ keys
@@ -271,11 +302,11 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
     // undo the Montgomery form (multiply by 1 in Montgomery = divide by R) via a
     // plain product with R^{-1}: done on the host after the coefficient export
     DBuf tmp(&c, ln);
-    HIP_OK(hipMemcpyAsync(tmp.p(), key + (size_t)(2 * digit + comp) * ln, ln * sizeof(u64),
+    HIP_OK(dev::memcpy_async(tmp.p(), key + (size_t)(2 * digit + comp) * ln, ln * sizeof(u64),
                           hipMemcpyDeviceToDevice, c.stream));
     const LimbMap all = kern::ext_map(c, c.L + 1);
     kern::ntt(c, tmp.p(), 0, tmp.p(), 0, 1, all, true);
-    HIP_OK(hipMemcpyAsync(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+    HIP_OK(dev::memcpy_async(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
     sync(c);
     for (int l = 0; l < np; ++l) {
       const u64 q = c.primes[l].q;
@@ -504,6 +535,8 @@ int bm_ntt(bm_ctx* ctx, uint64_t* dev_words, uint32_t n_polys, uint32_t limbs,
       m.off[l] = m.ooff[l] = (int)l;
     }
     c.use_stream(stream);
+    // the caller vouches for n_polys * limbs * N words at dev_words
+    audit::Scoped reg(dev_words, (size_t)n_polys * limbs * c.N * sizeof(u64));
     kern::ntt(c, dev_words, (size_t)limbs * c.N, dev_words, (size_t)limbs * c.N, (int)n_polys, m,
               inverse != 0);
   });
@@ -523,7 +556,7 @@ int bm_op_add(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
     kern::add(c, a->buf.p(), ln, b->buf.p(), ln, o->buf.p(), ln, (int)common, kern::chain_map(a->limbs));
     if (comps > common) {
       const bm_ct* big = a->comps > b->comps ? a : b;
-      HIP_OK(hipMemcpyAsync(o->buf.p() + common * ln, big->buf.p() + common * ln,
+      HIP_OK(dev::memcpy_async(o->buf.p() + common * ln, big->buf.p() + common * ln,
                             (comps - common) * ln * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
     }
     sync(c);
@@ -674,7 +707,7 @@ int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* ma
     std::vector<std::unique_ptr<bm_ct>> res;
     for (uint32_t i = 0; i < k; ++i) {
       res.emplace_back(new_ct(ctx, 2, q->limbs - 1, scale));
-      HIP_OK(hipMemcpyAsync(res.back()->buf.p(), all.p() + (size_t)i * 2 * nln, 2 * nln * sizeof(u64),
+      HIP_OK(dev::memcpy_async(res.back()->buf.p(), all.p() + (size_t)i * 2 * nln, 2 * nln * sizeof(u64),
                             hipMemcpyDeviceToDevice, c.stream));
     }
     sync(c);

@@ -10,8 +10,43 @@ namespace bm {
 
 // ----------------------------------------------------------------- memory
 
+namespace audit {
+namespace {
+std::mutex g_mu;
+std::map<uintptr_t, size_t>& live() {
+  static std::map<uintptr_t, size_t> m;
+  return m;
+}
+}  // namespace
+
+void add(const void* p, size_t bytes) {
+  std::lock_guard<std::mutex> g(g_mu);
+  live()[(uintptr_t)p] = bytes;
+}
+
+void remove(const void* p) {
+  std::lock_guard<std::mutex> g(g_mu);
+  live().erase((uintptr_t)p);
+}
+
+void check(const void* p, size_t bytes, const char* what) {
+  if (!p) BM_THROW(BM_EINVAL, std::string("launch check: null operand of ") + what);
+  std::lock_guard<std::mutex> g(g_mu);
+  const uintptr_t a = (uintptr_t)p;
+  auto it = live().upper_bound(a);
+  if (it != live().begin()) {
+    --it;
+    if (a >= it->first && a + bytes <= it->first + it->second) return;
+  }
+  BM_THROW(BM_EINVAL, std::string("launch check: ") + what + " would access outside its buffer");
+}
+}  // namespace audit
+
 DevicePool::~DevicePool() {
-  for (auto& kv : free_) (void)hipFree(kv.second);
+  for (auto& kv : free_) {
+    audit::remove(kv.second);
+    (void)dev::free(kv.second);
+  }
 }
 
 void* DevicePool::alloc(size_t bytes) {
@@ -23,16 +58,24 @@ void* DevicePool::alloc(size_t bytes) {
     return p;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
+  struct Reg {
+    void*& p;
+    size_t b;
+    ~Reg() {
+      if (p) audit::add(p, b);
+    }
+  } reg{p, bytes};
+  if (dev::malloc(&p, bytes) != hipSuccess) {
+    (void)dev::last_error();
     // release cached blocks and retry once
     for (auto& kv : free_) {
-      (void)hipFree(kv.second);
+      audit::remove(kv.second);
+      (void)dev::free(kv.second);
       held_ -= kv.first;
     }
     free_.clear();
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
+    if (dev::malloc(&p, bytes) != hipSuccess) {
+      (void)dev::last_error();
       BM_THROW(BM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
   }
@@ -48,7 +91,8 @@ void DevicePool::release(void* p, size_t bytes) {
 void DevicePool::trim() {
   std::lock_guard<std::mutex> g(mu_);
   for (auto& kv : free_) {
-    (void)hipFree(kv.second);
+    audit::remove(kv.second);
+    (void)dev::free(kv.second);
     held_ -= kv.first;
   }
   free_.clear();
@@ -77,19 +121,22 @@ DBuf& DBuf::operator=(DBuf&& o) noexcept {
 void Ctx::use_stream(void* s) {
   hipStream_t want = s ? (hipStream_t)s : own_stream;
   if (want != stream) {
-    if (stream) HIP_OK(hipStreamSynchronize(stream));
+    if (stream) HIP_OK(dev::stream_sync(stream));
     stream = want;
   }
 }
 
 Ctx::~Ctx() {
-  if (stream) (void)hipStreamSynchronize(stream);
+  if (stream) (void)dev::stream_sync(stream);
   pool.reset();
   if (owns_tables)
     for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws,
                     (void*)d_modup, (void*)d_moddown, (void*)d_rescale})
-      if (p) (void)hipFree(p);
-  if (own_stream) (void)hipStreamDestroy(own_stream);
+      if (p) {
+        audit::remove(p);
+        (void)dev::free(p);
+      }
+  if (own_stream) (void)dev::stream_destroy(own_stream);
 }
 
 std::unique_ptr<Ctx> Ctx::make_lane() const {
@@ -119,11 +166,68 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->h_moddown = h_moddown;
   l->group_chunk = group_chunk;
   l->owns_tables = false;
-  HIP_OK(hipSetDevice(device));
-  HIP_OK(hipStreamCreateWithFlags(&l->own_stream, hipStreamNonBlocking));
+  l->prof = prof;
+  HIP_OK(dev::set_device(device));
+  HIP_OK(dev::stream_create(&l->own_stream));
   l->stream = l->own_stream;
   l->pool.reset(new DevicePool(device));
   return l;
+}
+
+// ----------------------------------------------------------------- profiler
+
+hipEvent_t Profiler::take() {
+  if (!spare_.empty()) {
+    hipEvent_t e = spare_.back();
+    spare_.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_OK(dev::event_create(&e, true));
+  return e;
+}
+
+void Profiler::begin(hipStream_t s, const char* name, double bytes, double ops) {
+  std::lock_guard<std::mutex> g(mu_);
+  Pending p{name, take(), take(), bytes, ops};
+  HIP_OK(dev::event_record(p.a, s));
+  pending_.push_back(p);
+}
+
+void Profiler::end(hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu_);
+  HIP_OK(dev::event_record(pending_.back().b, s));
+}
+
+void Profiler::collect() {
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto& p : pending_) {
+    HIP_OK(dev::event_sync(p.b));
+    float ms = 0;
+    HIP_OK(dev::event_elapsed(&ms, p.a, p.b));
+    Entry& e = entries[p.name];
+    e.launches += 1;
+    e.ms += ms;
+    e.bytes += p.bytes;
+    e.ops += p.ops;
+    spare_.push_back(p.a);
+    spare_.push_back(p.b);
+  }
+  pending_.clear();
+}
+
+void Profiler::reset() {
+  collect();
+  std::lock_guard<std::mutex> g(mu_);
+  entries.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto& p : pending_) {
+    (void)dev::event_destroy(p.a);
+    (void)dev::event_destroy(p.b);
+  }
+  for (auto e : spare_) (void)dev::event_destroy(e);
 }
 
 namespace ev {
@@ -219,10 +323,10 @@ void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out) {
 void upload_plain(Ctx& c, const int64_t* host, int B, int limbs, u64* out) {
   const size_t N = c.N;
   DBuf raw(&c, (size_t)B * N);
-  HIP_OK(hipMemcpyAsync(raw.p(), host, (size_t)B * N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  HIP_OK(dev::memcpy_async(raw.p(), host, (size_t)B * N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
   kern::reduce_int(c, (const int64_t*)raw.p(), out, (size_t)limbs * N, B, N, kern::chain_map(limbs));
   kern::ntt(c, out, (size_t)limbs * N, out, (size_t)limbs * N, B, kern::chain_map(limbs), false);
-  HIP_OK(hipStreamSynchronize(c.stream));   // `host` may be released by the caller
+  HIP_OK(dev::stream_sync(c.stream));   // `host` may be released by the caller
 }
 
 template <class F>
@@ -271,15 +375,15 @@ void export_coeffs(Ctx& c, const u64* dev, int polys, int limbs, u64* host) {
   const size_t ln = (size_t)limbs * c.N;
   DBuf tmp(&c, (size_t)polys * ln);
   kern::ntt(c, dev, ln, tmp.p(), ln, polys, kern::chain_map(limbs), true);
-  HIP_OK(hipMemcpyAsync(host, tmp.p(), (size_t)polys * ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::memcpy_async(host, tmp.p(), (size_t)polys * ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
 }
 
 void import_coeffs(Ctx& c, const u64* host, int polys, int limbs, u64* dev) {
   const size_t ln = (size_t)limbs * c.N;
-  HIP_OK(hipMemcpyAsync(dev, host, (size_t)polys * ln * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+  HIP_OK(dev::memcpy_async(dev, host, (size_t)polys * ln * sizeof(u64), hipMemcpyHostToDevice, c.stream));
   kern::ntt(c, dev, ln, dev, ln, polys, kern::chain_map(limbs), false);
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
 }
 
 void decrypt_coeffs(Ctx& c, const bm_sk* sk, const u64* ct, int comps, int limbs, double* m) {
@@ -288,8 +392,8 @@ void decrypt_coeffs(Ctx& c, const bm_sk* sk, const u64* ct, int comps, int limbs
   const size_t ln = (size_t)limbs * N;
   const LimbMap cm = kern::chain_map(use);
   DBuf acc(&c, (size_t)use * N), sp(&c, (size_t)use * N), tmp(&c, (size_t)use * N);
-  HIP_OK(hipMemcpyAsync(acc.p(), ct, (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
-  HIP_OK(hipMemcpyAsync(sp.p(), sk->s_ntt.p(), (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice,
+  HIP_OK(dev::memcpy_async(acc.p(), ct, (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
+  HIP_OK(dev::memcpy_async(sp.p(), sk->s_ntt.p(), (size_t)use * N * sizeof(u64), hipMemcpyDeviceToDevice,
                         c.stream));
   for (int comp = 1; comp < comps; ++comp) {
     kern::mul(c, ct + comp * ln, 0, sp.p(), 0, tmp.p(), 0, 1, cm);
@@ -298,8 +402,8 @@ void decrypt_coeffs(Ctx& c, const bm_sk* sk, const u64* ct, int comps, int limbs
   }
   kern::ntt(c, acc.p(), 0, acc.p(), 0, 1, cm, true);
   std::vector<u64> r((size_t)use * N);
-  HIP_OK(hipMemcpyAsync(r.data(), acc.p(), r.size() * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::memcpy_async(r.data(), acc.p(), r.size() * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
   const u64 q0 = c.primes[0].q;
   if (use == 1) {
     for (size_t i = 0; i < N; ++i) m[i] = r[i] > q0 / 2 ? -(double)(q0 - r[i]) : (double)r[i];
@@ -325,11 +429,11 @@ void keygen_secret(Ctx& c, u64 seed, bm_sk* sk) {
   const int np = c.nprimes();
   sk->s_ntt = DBuf(&c, (size_t)np * N);
   DBuf raw(&c, N);
-  HIP_OK(hipMemcpyAsync(raw.p(), sk->s.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  HIP_OK(dev::memcpy_async(raw.p(), sk->s.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
   const LimbMap all = kern::ext_map(c, c.L + 1);
   kern::reduce_int(c, (const int64_t*)raw.p(), sk->s_ntt.p(), 0, 1, 0, all);
   kern::ntt(c, sk->s_ntt.p(), 0, sk->s_ntt.p(), 0, 1, all, false);
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
 }
 
 void keygen_public(Ctx& c, u64 seed, const bm_sk* sk, bm_pk* pk) {
@@ -344,14 +448,14 @@ void keygen_public(Ctx& c, u64 seed, const bm_sk* sk, bm_pk* pk) {
   pk->pk = DBuf(&c, (size_t)2 * nq * N);
   u64* b = pk->pk.p();
   u64* ad = b + (size_t)nq * N;
-  HIP_OK(hipMemcpyAsync(ad, a.data(), a.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+  HIP_OK(dev::memcpy_async(ad, a.data(), a.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
   const LimbMap cm = kern::chain_map(nq);
   kern::ntt(c, ad, 0, ad, 0, 1, cm, false);
   DBuf ee(&c, (size_t)nq * N);
   upload_plain(c, e.data(), 1, nq, ee.p());
   kern::mul(c, ad, 0, sk->s_ntt.p(), 0, b, 0, 1, cm);
   kern::sub(c, ee.p(), 0, b, 0, b, 0, 1, cm);
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
 }
 
 void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const bm_sk* sk,
@@ -378,10 +482,10 @@ void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const
   for (int j = 0; j < c.dnum; ++j) {
     u64* bj = key.p() + (size_t)(2 * j) * np * N;
     u64* aj = key.p() + (size_t)(2 * j + 1) * np * N;
-    HIP_OK(hipMemcpyAsync(aj, a.data() + (size_t)j * np * N, (size_t)np * N * sizeof(u64),
+    HIP_OK(dev::memcpy_async(aj, a.data() + (size_t)j * np * N, (size_t)np * N * sizeof(u64),
                           hipMemcpyHostToDevice, c.stream));
     kern::ntt(c, aj, 0, aj, 0, 1, all, false);
-    HIP_OK(hipMemcpyAsync(raw.p(), e.data() + (size_t)j * N, N * sizeof(int64_t), hipMemcpyHostToDevice,
+    HIP_OK(dev::memcpy_async(raw.p(), e.data() + (size_t)j * N, N * sizeof(int64_t), hipMemcpyHostToDevice,
                           c.stream));
     kern::reduce_int(c, (const int64_t*)raw.p(), bj, 0, 1, 0, all);
     kern::ntt(c, bj, 0, bj, 0, 1, all, false);
@@ -401,12 +505,12 @@ void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const
       ++dm.n;
     }
     DBuf scal(&c, pmod.size());
-    HIP_OK(hipMemcpyAsync(scal.p(), pmod.data(), pmod.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+    HIP_OK(dev::memcpy_async(scal.p(), pmod.data(), pmod.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
     kern::axpy_scalar(c, s_prime, 0, scal.p(), bj, 0, 1, dm);
-    HIP_OK(hipStreamSynchronize(c.stream));
+    HIP_OK(dev::stream_sync(c.stream));
   }
   kern::to_mont(c, key.p(), (size_t)np * N, 2 * c.dnum, all);
-  HIP_OK(hipStreamSynchronize(c.stream));
+  HIP_OK(dev::stream_sync(c.stream));
 }
 
 }  // namespace ev

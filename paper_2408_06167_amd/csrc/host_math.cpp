@@ -151,17 +151,19 @@ void build_context_tables(Ctx& c) {
       itws[i * N + k] = h_shoup(ipw[r], q);
     }
   }
-  HIP_OK(hipMalloc(&c.d_primes, sizeof(PrimeC) * MAX_PRIMES));
-  HIP_OK(hipMemcpy(c.d_primes, pc.data(), sizeof(PrimeC) * MAX_PRIMES, hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_primes, sizeof(PrimeC) * MAX_PRIMES));
+  audit::add(c.d_primes, sizeof(PrimeC) * MAX_PRIMES);
+  HIP_OK(dev::memcpy(c.d_primes, pc.data(), sizeof(PrimeC) * MAX_PRIMES, hipMemcpyHostToDevice));
   const size_t tb = sizeof(u64) * MAX_PRIMES * N;
-  HIP_OK(hipMalloc(&c.d_tw, tb));
-  HIP_OK(hipMalloc(&c.d_tws, tb));
-  HIP_OK(hipMalloc(&c.d_itw, tb));
-  HIP_OK(hipMalloc(&c.d_itws, tb));
-  HIP_OK(hipMemcpy(c.d_tw, tw.data(), tb, hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(c.d_tws, tws.data(), tb, hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(c.d_itw, itw.data(), tb, hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(c.d_itws, itws.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_tw, tb));
+  HIP_OK(dev::malloc(&c.d_tws, tb));
+  HIP_OK(dev::malloc(&c.d_itw, tb));
+  HIP_OK(dev::malloc(&c.d_itws, tb));
+  for (void* p : {(void*)c.d_tw, (void*)c.d_tws, (void*)c.d_itw, (void*)c.d_itws}) audit::add(p, tb);
+  HIP_OK(dev::memcpy(c.d_tw, tw.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_tws, tws.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_itw, itw.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_itws, itws.data(), tb, hipMemcpyHostToDevice));
 
   // ---- ModUp tables, one per number of chain limbs l = 1..L+1
   const int nq = c.L + 1;
@@ -196,8 +198,9 @@ void build_context_tables(Ctx& c) {
       }
     }
   }
-  HIP_OK(hipMalloc(&c.d_modup, sizeof(ModUpTable) * (nq + 1)));
-  HIP_OK(hipMemcpy(c.d_modup, c.h_modup.data(), sizeof(ModUpTable) * (nq + 1),
+  HIP_OK(dev::malloc(&c.d_modup, sizeof(ModUpTable) * (nq + 1)));
+  audit::add(c.d_modup, sizeof(ModUpTable) * (nq + 1));
+  HIP_OK(dev::memcpy(c.d_modup, c.h_modup.data(), sizeof(ModUpTable) * (nq + 1),
                    hipMemcpyHostToDevice));
 
   // ---- ModDown table
@@ -225,8 +228,9 @@ void build_context_tables(Ctx& c) {
     for (int k = 0; k < c.K; ++k) P = h_mulmod(P, c.primes[c.pid_special(k)].q % qi, qi);
     put_pair(md.pinv[i], h_invmod(P, qi), qi);
   }
-  HIP_OK(hipMalloc(&c.d_moddown, sizeof(ModDownTable)));
-  HIP_OK(hipMemcpy(c.d_moddown, &md, sizeof(ModDownTable), hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_moddown, sizeof(ModDownTable)));
+  audit::add(c.d_moddown, sizeof(ModDownTable));
+  HIP_OK(dev::memcpy(c.d_moddown, &md, sizeof(ModDownTable), hipMemcpyHostToDevice));
 
   // ---- rescale table: q_l^{-1} mod q_i
   std::vector<u64> rs((size_t)nq * nq * 2, 0);
@@ -236,8 +240,9 @@ void build_context_tables(Ctx& c) {
       const u64 qi = c.primes[i].q;
       put_pair(&rs[((size_t)l * nq + i) * 2], h_invmod(c.primes[l].q % qi, qi), qi);
     }
-  HIP_OK(hipMalloc(&c.d_rescale, rs.size() * sizeof(u64)));
-  HIP_OK(hipMemcpy(c.d_rescale, rs.data(), rs.size() * sizeof(u64), hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_rescale, rs.size() * sizeof(u64)));
+  audit::add(c.d_rescale, rs.size() * sizeof(u64));
+  HIP_OK(dev::memcpy(c.d_rescale, rs.data(), rs.size() * sizeof(u64), hipMemcpyHostToDevice));
 }
 
 }  // namespace bm

@@ -9,6 +9,8 @@
 // Grids are (element chunks, limb slot, batch element): blockIdx.y picks the
 // limb (and with it the prime, uniform across the block so its constants come
 // from scalar loads) and blockIdx.z the polynomial of the batch.
+#include <algorithm>
+
 #include "bm_internal.hpp"
 
 namespace bm {
@@ -43,6 +45,12 @@ __device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeC& p) {
 
 // any 64-bit word mod q (Shoup with w = 1)
 __device__ __forceinline__ u64 reduce64(u64 a, const PrimeC& p) { return mul_shoup(a, 1, p.pad[0], p.q); }
+
+// kernel launch; skipped (checks only) in dry-run mode
+#define LAUNCH(...)                              \
+  do {                                           \
+    if (!dev::dry()) hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
 
 constexpr int TPB = 256;        // threads per block of every kernel here
 constexpr int NTT_E = 4096;     // words per NTT block held in LDS
@@ -417,7 +425,44 @@ inline dim3 ew_grid(size_t N, int ys, int B) {
   return dim3((unsigned)bx, (unsigned)ys, (unsigned)B);
 }
 
-inline void check_launch() { HIP_OK(hipGetLastError()); }
+inline void check_launch() { HIP_OK(dev::last_error()); }
+
+// ---- launch checks: the word range a launch touches in each operand
+inline int max_off(const LimbMap& m, bool out = false) {
+  int x = 0;
+  for (int i = 0; i < m.n; ++i) x = std::max(x, out ? m.ooff[i] : m.off[i]);
+  return x;
+}
+inline int min_off(const LimbMap& m, bool out = false) {
+  int x = 1 << 30;
+  for (int i = 0; i < m.n; ++i) x = std::min(x, out ? m.ooff[i] : m.off[i]);
+  return x;
+}
+// operand with B batch elements of stride `st` whose last touched word is at
+// `tail` words past the element start, first touched word `head`
+inline void chk(const void* p, int B, size_t st, size_t head, size_t tail, const char* what) {
+  if (B <= 0) return;
+  const u64* base = (const u64*)p + head;
+  audit::check(base, ((size_t)(B - 1) * st + tail - head) * sizeof(u64), what);
+}
+inline void chk_map(const Ctx& c, const void* p, int B, size_t st, const LimbMap& m, const char* what,
+                    bool out = false) {
+  for (int i = 0; i < m.n; ++i)
+    if (m.prime[i] < 0 || m.prime[i] >= c.nprimes()) BM_THROW(BM_EINVAL, "launch check: prime id");
+  chk(p, B, st, (size_t)min_off(m, out) * c.N, (size_t)(max_off(m, out) + 1) * c.N, what);
+}
+
+// Times one launch when the context's profiler is on.
+struct Prof {
+  const Ctx& c;
+  bool on;
+  Prof(const Ctx& c_, const char* name, double bytes, double ops) : c(c_), on(c_.prof && c_.prof->on) {
+    if (on) c.prof->begin(c.stream, name, bytes, ops);
+  }
+  ~Prof() {
+    if (on) c.prof->end(c.stream);
+  }
+};
 
 }  // namespace
 
@@ -456,89 +501,131 @@ void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_str
   const int N = 1 << logn;
   const int E = N < NTT_E ? N : NTT_E;
   const dim3 grid((unsigned)(N / E), (unsigned)m.n, (unsigned)B);
+  // The second pass works in place on `out`, so it must address its input with
+  // the output offsets.
+  LimbMap m_out = m;
+  for (int i = 0; i < m.n; ++i) m_out.off[i] = m.ooff[i];
   auto launch = [&](const u64* src, size_t ss, u64* dst, size_t ds, int logm, int s0, int col,
-                    int last) {
+                    int last, const LimbMap& mm) {
     const int M = 1 << logm;
     const size_t lds = (size_t)(E / M) * (M + 1) * sizeof(u64);
+    // the pass reads src at mm.off and writes dst at mm.ooff
+    chk_map(c, src, B, ss, mm, "ntt pass input");
+    chk_map(c, dst, B, ds, mm, "ntt pass output", true);
+    const double elems = (double)N * m.n * B;
+    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * logm);
     if (inverse)
-      hipLaunchKernelGGL(k_ntt_pass<true>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, m,
+      LAUNCH(k_ntt_pass<true>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, mm,
                          c.d_primes, c.d_itw, c.d_itws, logn, logm, s0, col, last);
     else
-      hipLaunchKernelGGL(k_ntt_pass<false>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, m,
+      LAUNCH(k_ntt_pass<false>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, mm,
                          c.d_primes, c.d_tw, c.d_tws, logn, logm, s0, col, last);
     check_launch();
   };
   if (logn <= 12) {
-    launch(in, in_stride, out, out_stride, logn, 0, 0, inverse ? 1 : 0);
+    launch(in, in_stride, out, out_stride, logn, 0, 0, inverse ? 1 : 0, m);
     return;
   }
   const int la = logn / 2, lb = logn - la;
   if (!inverse) {
-    launch(in, in_stride, out, out_stride, la, 0, 1, 0);
-    launch(out, out_stride, out, out_stride, lb, la, 0, 0);
+    launch(in, in_stride, out, out_stride, la, 0, 1, 0, m);
+    launch(out, out_stride, out, out_stride, lb, la, 0, 0, m_out);
   } else {
-    launch(in, in_stride, out, out_stride, lb, la, 0, 0);
-    launch(out, out_stride, out, out_stride, la, 0, 1, 1);
+    launch(in, in_stride, out, out_stride, lb, la, 0, 0, m);
+    launch(out, out_stride, out, out_stride, la, 0, 1, 1, m_out);
   }
 }
 
 void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
                 size_t src_stride, const LimbMap& m) {
-  hipLaunchKernelGGL(k_reduce_int, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, src, src_stride,
+  chk(src, B, src_stride, 0, c.N, "reduce_int input");
+  chk_map(c, out, B, out_stride, m, "reduce_int output");
+  Prof pf(c, "reduce_int", 8.0 * c.N * B * (1 + m.n), (double)c.N * B * m.n);
+  LAUNCH(k_reduce_int, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, src, src_stride,
                      out, out_stride, m, c.d_primes, (int)c.N);
   check_launch();
 }
 
 void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
          const LimbMap& m) {
-  hipLaunchKernelGGL(k_add, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+  chk_map(c, a, B, sa, m, "add a");
+  chk_map(c, b, B, sb, m, "add b");
+  chk_map(c, o, B, so, m, "add out");
+  Prof pf(c, "add", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_add, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
 }
 
 void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
          const LimbMap& m) {
-  hipLaunchKernelGGL(k_sub, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+  chk_map(c, a, B, sa, m, "sub a");
+  chk_map(c, b, B, sb, m, "sub b");
+  chk_map(c, o, B, so, m, "sub out");
+  Prof pf(c, "sub", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_sub, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
 }
 
 void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so, int B,
          const LimbMap& m) {
-  hipLaunchKernelGGL(k_mul, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
+  chk_map(c, a, B, sa, m, "mul a");
+  chk_map(c, b, B, sb, m, "mul b");
+  chk_map(c, o, B, so, m, "mul out");
+  Prof pf(c, "mul", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_mul, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
 }
 
 void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m) {
-  hipLaunchKernelGGL(k_neg, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, o, so, m,
+  chk_map(c, a, B, sa, m, "neg a");
+  chk_map(c, o, B, so, m, "neg out");
+  Prof pf(c, "neg", 16.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_neg, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
 }
 
 void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m) {
-  hipLaunchKernelGGL(k_to_mont, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, m,
+  chk_map(c, a, B, sa, m, "to_mont");
+  Prof pf(c, "to_mont", 16.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_to_mont, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, m,
                      c.d_primes, (int)c.N);
   check_launch();
 }
 
 void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o, size_t so, int B,
                  const LimbMap& m) {
-  hipLaunchKernelGGL(k_axpy_scalar, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, s, ss, scal, o,
+  chk_map(c, s, B, ss, m, "axpy s");
+  chk_map(c, o, B, so, m, "axpy out");
+  audit::check(scal, 2 * sizeof(u64) * m.n, "axpy scalars");
+  Prof pf(c, "axpy", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  LAUNCH(k_axpy_scalar, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, s, ss, scal, o,
                      so, m, c.d_primes, (int)c.N);
   check_launch();
 }
 
 void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
             u64* o, size_t so, int B, int limbs, bool accumulate) {
-  hipLaunchKernelGGL(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, b, sb,
+  if (a_div < 1 || b_mod < 1) BM_THROW(BM_EINVAL, "launch check: tensor batch divisors");
+  chk(a, (B - 1) / a_div + 1, sa, 0, (size_t)2 * limbs * c.N, "tensor a");
+  chk(b, std::min(B, b_mod), sb, 0, (size_t)2 * limbs * c.N, "tensor b");
+  chk(o, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
+  if (limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: tensor limbs");
+  Prof pf(c, "tensor", 8.0 * c.N * B * limbs * (accumulate ? 10 : 7), 4.0 * c.N * B * limbs);
+  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, b, sb,
                      b_mod, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
   check_launch();
 }
 
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B, int rows,
                   u64 g) {
-  hipLaunchKernelGGL(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out,
+  chk(in, B, si, 0, (size_t)rows * c.N, "automorphism in");
+  chk(out, B, so, 0, (size_t)rows * c.N, "automorphism out");
+  Prof pf(c, "automorphism", 16.0 * c.N * B * rows, 0.0);
+  LAUNCH(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out,
                      so, g, c.log_n);
   check_launch();
 }
@@ -546,7 +633,12 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
 void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j) {
   const ModUpTable& tb = c.h_modup[limbs];
   const int targets = tb.ext - tb.d[j].nsrc;
-  hipLaunchKernelGGL(k_modup, ew_grid(c.N, targets, B), dim3(TPB), 0, c.stream, xc, sx,
+  const int ns = tb.d[j].nsrc;
+  if (limbs < 1 || limbs > c.L + 1 || j < 0 || j >= tb.beta) BM_THROW(BM_EINVAL, "launch check: modup digit");
+  chk(xc, B, sx, 0, (size_t)limbs * c.N, "modup input");
+  chk(y + (size_t)j * tb.ext * c.N, B, sy, 0, (size_t)tb.ext * c.N, "modup output");
+  Prof pf(c, "modup", 8.0 * c.N * B * (ns + targets), (double)c.N * B * ns * (1 + targets));
+  LAUNCH(k_modup, ew_grid(c.N, targets, B), dim3(TPB), 0, c.stream, xc, sx,
                      y + (size_t)j * tb.ext * c.N, sy, c.d_modup + limbs, j, c.d_primes, (int)c.N);
   check_launch();
 }
@@ -554,13 +646,24 @@ void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int
 void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key,
          u64* uw, size_t suw, int B, int limbs) {
   const ModUpTable& tb = c.h_modup[limbs];
-  hipLaunchKernelGGL(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
+  if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
+  chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "kip digits");
+  chk(y_own, B, sown, 0, (size_t)limbs * c.N, "kip input");
+  chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
+  chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "kip output");
+  Prof pf(c, "kip", 8.0 * c.N * tb.ext * ((double)B * tb.beta + 2.0 * tb.beta + 2.0 * B),
+          2.0 * c.N * tb.ext * tb.beta * B);
+  LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
                      key, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
   check_launch();
 }
 
 void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs) {
-  hipLaunchKernelGGL(k_moddown_conv, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
+  chk(uw, B, suw, 0, (size_t)2 * (limbs + c.K) * c.N, "moddown_conv input");
+  chk(conv, B, sc, 0, (size_t)2 * limbs * c.N, "moddown_conv output");
+  Prof pf(c, "moddown_conv", 8.0 * c.N * B * (2 * c.K + 2 * limbs),
+          (double)c.N * B * (2 * c.K + 2 * c.K * limbs));
+  LAUNCH(k_moddown_conv, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
                      conv, sc, c.d_moddown, limbs, c.d_primes, (int)c.N);
   check_launch();
 }
@@ -568,7 +671,14 @@ void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc,
 void moddown_finish(const Ctx& c, const u64* uw, size_t suw, const u64* conv, size_t sc,
                     const u64* add0, size_t sadd0, const u64* add1, size_t sadd1, u64* out,
                     size_t so, int B, int limbs) {
-  hipLaunchKernelGGL(k_moddown_finish, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
+  chk(uw, B, suw, 0, (size_t)2 * (limbs + c.K) * c.N, "moddown_finish input");
+  chk(conv, B, sc, 0, (size_t)2 * limbs * c.N, "moddown_finish conv");
+  if (add0) chk(add0, B, sadd0, 0, (size_t)limbs * c.N, "moddown_finish add0");
+  if (add1) chk(add1, B, sadd1, 0, (size_t)limbs * c.N, "moddown_finish add1");
+  chk(out, B, so, 0, (size_t)2 * limbs * c.N, "moddown_finish output");
+  Prof pf(c, "moddown_finish", 8.0 * c.N * B * 2 * limbs * (3 + (add0 ? 1 : 0)),
+          2.0 * c.N * B * limbs);
+  LAUNCH(k_moddown_finish, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
                      conv, sc, add0, sadd0, add1, sadd1, out, so, c.d_moddown, limbs, c.d_primes,
                      (int)c.N);
   check_launch();
@@ -576,14 +686,23 @@ void moddown_finish(const Ctx& c, const u64* uw, size_t suw, const u64* conv, si
 
 void rescale_conv(const Ctx& c, const u64* last, size_t sl, size_t last_comp_stride, u64* t,
                   size_t st, int B, int comps, int limbs) {
-  hipLaunchKernelGGL(k_rescale_conv, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0, c.stream,
+  if (limbs < 2) BM_THROW(BM_EINVAL, "launch check: rescale limbs");
+  chk(last, B, sl, 0, (size_t)(comps - 1) * last_comp_stride + c.N, "rescale_conv input");
+  chk(t, B, st, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_conv output");
+  Prof pf(c, "rescale_conv", 8.0 * c.N * B * comps * limbs, (double)c.N * B * comps * (limbs - 1));
+  LAUNCH(k_rescale_conv, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0, c.stream,
                      last, sl, last_comp_stride, t, st, comps, limbs, c.d_primes, (int)c.N);
   check_launch();
 }
 
 void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t st, u64* out,
                     size_t so, int B, int comps, int limbs) {
-  hipLaunchKernelGGL(k_rescale_finish, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0,
+  if (limbs < 2 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: rescale limbs");
+  chk(in, B, si, 0, (size_t)comps * limbs * c.N, "rescale_finish input");
+  chk(t, B, st, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_finish t");
+  chk(out, B, so, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_finish output");
+  Prof pf(c, "rescale_finish", 24.0 * c.N * B * comps * (limbs - 1), (double)c.N * B * comps * (limbs - 1));
+  LAUNCH(k_rescale_finish, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0,
                      c.stream, in, si, t, st, out, so, c.d_rescale, comps, limbs, c.L + 1,
                      c.d_primes, (int)c.N);
   check_launch();
@@ -591,7 +710,14 @@ void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t
 
 void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
                 size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs) {
-  hipLaunchKernelGGL(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
+  if (div < 1) BM_THROW(BM_EINVAL, "launch check: copy divisor");
+  chk(in, B, si, 0, (size_t)(comps - 1) * in_comp_stride + (size_t)limbs * c.N, "copy_limbs input");
+  {
+    const size_t hi = (size_t)((B - 1) / div) * so_hi + (size_t)std::min(B - 1, div - 1) * so_lo;
+    chk(out, 1, 0, 0, hi + (size_t)(comps - 1) * out_comp_stride + (size_t)limbs * c.N, "copy_limbs output");
+  }
+  Prof pf(c, "copy_limbs", 16.0 * c.N * B * comps * limbs, 0.0);
+  LAUNCH(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
                      in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
   check_launch();
 }

@@ -106,7 +106,7 @@ struct bm_server {
       const bm_ct& q = *lane.reqs[j].q;
       if (g.k == 1) {
         if ((int)q.limbs != lg) BM_THROW(BM_ELEVEL, "query level does not match the gallery");
-        HIP_OK(hipMemcpyAsync(cu.p() + j * cu_stride, q.buf.p(), part * sizeof(u64),
+        HIP_OK(dev::memcpy_async(cu.p() + j * cu_stride, q.buf.p(), part * sizeof(u64),
                               hipMemcpyDeviceToDevice, c.stream));
         cu_scale = q.scale;
       } else {
@@ -134,7 +134,7 @@ struct bm_server {
       r->off = (size_t)j * per;
       lane.results.push_back(std::move(r));
     }
-    HIP_OK(hipEventRecord(lane.done, c.stream));
+    HIP_OK(dev::event_record(lane.done, c.stream));
   }
 
   void finish(Lane& lane, int status) {
@@ -168,7 +168,7 @@ struct bm_server {
       // completions
       for (Lane& lane : lanes) {
         if (!lane.busy) continue;
-        hipError_t e = hipEventQuery(lane.done);
+        hipError_t e = dev::event_query(lane.done);
         if (e == hipErrorNotReady) continue;
         finish(lane, e == hipSuccess ? BM_OK : BM_EDEVICE);
         progress = true;
@@ -240,7 +240,7 @@ int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, 
     s->lanes.resize(3);
     for (auto& lane : s->lanes) {
       lane.c = ctx->c.make_lane();
-      HIP_OK(hipEventCreateWithFlags(&lane.done, hipEventDisableTiming));
+      HIP_OK(dev::event_create(&lane.done, false));
     }
     bm_server* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
@@ -333,7 +333,7 @@ void bm_server_free(bm_server* s) {
   for (auto& kv : s->done)
     if (kv.second.r) bm_result_free(kv.second.r);
   for (auto& lane : s->lanes)
-    if (lane.done) (void)hipEventDestroy(lane.done);
+    if (lane.done) (void)dev::event_destroy(lane.done);
   for (auto& g : s->galleries)
     if (g.masks) bm_masks_free(g.masks);
   delete s;

@@ -1,0 +1,81 @@
+"""Drive the library's call sequences with BM_DRY_RUN=1 (no GPU): every kernel
+launch is checked against the buffers it would touch, none is executed.
+Run as a script by test_dry_run.py; exits non-zero on the first failure."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+assert os.environ.get("BM_DRY_RUN") == "1"
+import paper_2408_06167_amd as bm  # noqa: E402
+
+
+def flow(preset, shapes, n_templates):
+    p = bm.bm_params_preset(preset)
+    ctx = bm.bm_ctx_create(p, 0)
+    N, L1 = p.N, p.n_q
+    rots = set()
+    for d, k in shapes:
+        rots.update(bm.bm_rotations_for(d, k))
+    sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(rots))
+    rng = np.random.default_rng(0)
+    words = rng.integers(0, 1 << 40, size=(2, L1, N), dtype=np.uint64)
+    a = bm.bm_ct_import(ctx, words, p.scale)
+    b = bm.bm_ct_import(ctx, words, p.scale)
+    for op in (lambda: bm.bm_op_add(ctx, a, b), lambda: bm.bm_op_tensor(ctx, a, b),
+               lambda: bm.bm_op_rescale(ctx, a), lambda: bm.bm_op_drop(ctx, a, 1),
+               lambda: bm.bm_op_pmul(ctx, a, np.ones(N, dtype=np.int64), 2.0)):
+        bm.bm_ct_free(op())
+    t = bm.bm_op_tensor(ctx, a, b)
+    bm.bm_ct_free(bm.bm_op_relin(ctx, evk, t))
+    for r in sorted(rots)[:3]:
+        bm.bm_ct_free(bm.bm_op_rotate(ctx, evk, a, r))
+    for limbs in range(1, L1 + 1):
+        c = bm.bm_encrypt_coeffs(ctx, pk, np.zeros(N, dtype=np.int64), limbs, p.scale, 1, limbs)
+        bm.bm_ct_export(ctx, c, N)
+        if limbs >= 2:
+            bm.bm_ct_free(bm.bm_op_rescale(ctx, c))
+            bm.bm_ct_free(bm.bm_op_rotate(ctx, evk, c, sorted(rots)[-1]))
+        bm.bm_ct_free(c)
+    for d, k in shapes:
+        X = rng.standard_normal((n_templates, d)).astype(np.float32)
+        q = bm.bm_encrypt_query(ctx, pk, X[0], 1, 1)
+        g = bm.bm_encrypt_gallery(ctx, pk, X, k, 1, 10)
+        if k > 1:
+            m = bm.bm_masks_create(ctx, d, k)
+            for h in bm.bm_expand(ctx, evk, q, m, k):
+                bm.bm_ct_free(h)
+            bm.bm_masks_free(m)
+        for s in (1, 2):
+            for chunk in (0, 1, 3):
+                bm.bm_ctx_set_group_chunk(ctx, chunk)
+                r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
+                bm.bm_decrypt_scores(ctx, sk, r, n_templates)
+                G, limbs, _ = bm.bm_result_info(r)
+                bm.bm_result_export(ctx, r, G - 1, N)
+                bm.bm_result_free(r)
+        rs = bm.bm_match_batch(ctx, evk, [q, q], [g, g], schedule=2)
+        for r in rs:
+            bm.bm_result_free(r)
+        bm.bm_ctx_set_group_chunk(ctx, 0)
+        srv = bm.bm_server_create(ctx, evk, 64 << 30, 2)
+        gid = bm.bm_server_add_gallery(srv, g)
+        tickets = [bm.bm_server_submit(srv, gid, bm.bm_encrypt_query(ctx, pk, X[i], 1, 100 + i))
+                   for i in range(5)]
+        bm.bm_server_drain(srv)
+        for t_ in tickets:
+            bm.bm_result_free(bm.bm_server_poll(srv, t_))
+        bm.bm_server_free(srv)
+        bm.bm_ct_free(q)
+        print("preset %d d=%d k=%d ok" % (preset, d, k), flush=True)
+    for h in (a, b, t):
+        bm.bm_ct_free(h)
+    bm.bm_ctx_free(ctx)
+
+
+if __name__ == "__main__":
+    flow(1, [(16, 1), (16, 2), (16, 4), (8, 8)], 300)
+    flow(2, [(128, 1), (128, 4), (128, 16), (16, 1)], 5000)
+    print("dry run ok")
