@@ -150,6 +150,179 @@ __global__ void __launch_bounds__(TPB) k_ntt_pass(const u64* __restrict__ in, si
   }
 }
 
+// ---------------------------------------------------------------- register-radix NTT
+//
+// Same transform as k_ntt_pass, organised for gfx950: every thread keeps 16
+// words of one view in registers and applies four butterfly stages to them
+// (a radix-16 phase) before the view is exchanged through LDS; a pass of 8
+// stages is two phases, the single pass of N = 4096 is three.  Indices are
+// shifts and masks only.  Twiddles of the block are staged once in LDS (8-stage
+// passes) or read through the cache (12-stage pass).  Arithmetic is lazy
+// (Harvey): the forward butterfly lets values grow by 4q per stage and the
+// inverse keeps them below 4q; each pass ends with one exact reduction.
+//
+// Pass kinds: COL = columns of length 256 of one polynomial (first 8 stages of
+// N = 2^16, twiddles common to all columns); ROW = one row of length 256
+// taken from V polynomials that share the prime (last 8 stages, row twiddles);
+// ONE = a whole N = 4096 polynomial.
+
+// a * w mod q up to 3q: the quotient floor(a * ws / 2^64) is estimated from
+// three 32 x 32 partial products; the estimate is at most 2 below the exact
+// one, which is itself within 1 of a*w/q, so the result lies in [0, 4q).
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
+  const u32 a0 = (u32)a, a1 = (u32)(a >> 32);
+  const u32 s0 = (u32)ws, s1 = (u32)(ws >> 32);
+  const u64 qh = (u64)a1 * s1 + (u64)__umulhi(a1, s0) + (u64)__umulhi(a0, s1);
+  return a * w - qh * q;
+}
+
+enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
+
+template <int LOGM, bool INV, int KIND>
+__global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
+                                                  u64* __restrict__ out, size_t out_stride,
+                                                  LimbMap m, const PrimeC* __restrict__ P,
+                                                  const u64* __restrict__ tw,
+                                                  const u64* __restrict__ tws, int log_n, int s0,
+                                                  int last, int B) {
+  constexpr int M = 1 << LOGM;
+  constexpr int TPV = M / 16;                 // threads per view
+  constexpr int VS = M + M / 16;              // padded view length in LDS
+  constexpr int PH = LOGM / 4;                // radix-16 phases
+  extern __shared__ u64 sh[];
+  __shared__ u64 tl[2 * 256];                 // block twiddles (w, ws) for 8-stage passes
+  const int t = threadIdx.x;
+  const int V = (int)blockDim.x / TPV;        // views in this block
+  const int nthr = (int)blockDim.x;
+  const int slot = blockIdx.y;
+  const int pid = m.prime[slot];
+  const u64 q = P[pid].q;
+  const int N = 1 << log_n;
+  const u64* W = tw + (size_t)pid * N;
+  const u64* WS = tws + (size_t)pid * N;
+  const size_t ioff = (size_t)m.off[slot] * N, ooff = (size_t)m.ooff[slot] * N;
+  auto pad = [](int a) { return a + (a >> 4); };
+
+  // ---- stage the block's twiddles (8-stage passes): tl[2^s + i] for stage s, block i
+  if (LOGM == 8) {
+    const int vb = KIND == NTT_ROW ? (int)blockIdx.x : 0;
+    for (int k = t; k < 256; k += nthr) {
+      if (k == 0) continue;
+      const int s = 31 - __clz(k);
+      const int g = (1 << (s0 + s)) + (vb << s) + (k - (1 << s));
+      tl[2 * k] = W[g];
+      tl[2 * k + 1] = WS[g];
+    }
+  }
+
+  // ---- coalesced load of the tile into LDS
+  const int total = V * M;
+  for (int e = t; e < total; e += nthr) {
+    int v, a;
+    size_t g;
+    bool ok = true;
+    if (KIND == NTT_COL) {
+      a = e / V; v = e % V;                     // V = 16 consecutive columns
+      g = (size_t)blockIdx.z * in_stride + ioff + (size_t)a * (N >> LOGM) + (size_t)blockIdx.x * V + v;
+    } else if (KIND == NTT_ROW) {
+      v = e / M; a = e % M;
+      const int z = blockIdx.z * V + v;
+      ok = z < B;
+      g = (size_t)z * in_stride + ioff + (size_t)blockIdx.x * M + a;
+    } else {
+      v = 0; a = e;
+      g = (size_t)blockIdx.z * in_stride + ioff + a;
+    }
+    sh[v * VS + pad(a)] = ok ? in[g] : 0;
+  }
+  __syncthreads();
+
+  const int v = t / TPV, u = t % TPV;
+  u64 x[16];
+  auto addr = [&](int p, int j) {
+    const int sh_lo = LOGM - 4 * p - 4;
+    const int hi = u >> sh_lo, lo = u & ((1 << sh_lo) - 1);
+    return (hi << (LOGM - 4 * p)) + (j << sh_lo) + lo;
+  };
+  auto twid = [&](int kk, u64& w, u64& ws) {
+    if (LOGM == 8) { w = tl[2 * kk]; ws = tl[2 * kk + 1]; }
+    else { w = W[kk]; ws = WS[kk]; }
+  };
+  const u64 q4 = 4 * q;
+
+#pragma unroll
+  for (int ph = 0; ph < PH; ++ph) {
+    const int p = INV ? PH - 1 - ph : ph;
+    const int hi = u >> (LOGM - 4 * p - 4);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(p, j))];
+    if (!INV) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int step = 8 >> k;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j & step) continue;
+          u64 w, ws;
+          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, ws);
+          const u64 T = shoup_lazy(x[j + step], w, ws, q);
+          const u64 U = x[j];
+          x[j] = U + T;
+          x[j + step] = U + q4 - T;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 3; k >= 0; --k) {
+        const int step = 8 >> k;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j & step) continue;
+          u64 w, ws;
+          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, ws);
+          const u64 U = x[j], Vv = x[j + step];
+          const u64 S = U + Vv;
+          x[j] = S >= q4 ? S - q4 : S;
+          x[j + step] = shoup_lazy(U + q4 - Vv, w, ws, q);
+        }
+      }
+    }
+    if (ph + 1 < PH) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(p, j))] = x[j];
+      __syncthreads();
+    } else {
+      // exact reduction (times N^-1 at the end of an inverse transform)
+      const u64 w1 = last ? P[pid].ninv : 1, w1s = last ? P[pid].ninv_s : P[pid].pad[0];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(p, j))] = mul_shoup(x[j], w1, w1s, q);
+      __syncthreads();
+    }
+  }
+
+  // ---- coalesced store of the tile
+  for (int e = t; e < total; e += nthr) {
+    int vv, a;
+    size_t g;
+    bool ok = true;
+    if (KIND == NTT_COL) {
+      a = e / V; vv = e % V;
+      g = (size_t)blockIdx.z * out_stride + ooff + (size_t)a * (N >> LOGM) + (size_t)blockIdx.x * V + vv;
+    } else if (KIND == NTT_ROW) {
+      vv = e / M; a = e % M;
+      const int z = blockIdx.z * V + vv;
+      ok = z < B;
+      g = (size_t)z * out_stride + ooff + (size_t)blockIdx.x * M + a;
+    } else {
+      vv = 0; a = e;
+      g = (size_t)blockIdx.z * out_stride + ooff + a;
+    }
+    if (ok) out[g] = sh[vv * VS + pad(a)];
+  }
+}
+
 // ---------------------------------------------------------------- elementwise
 
 #define EW_PROLOGUE                                               \
@@ -494,6 +667,69 @@ LimbMap single(int prime, int off) {
   return m;
 }
 
+
+// N = 2^12: one 12-stage pass; N = 2^16: 8 column stages then 8 row stages
+// (inverse: rows first).  Row passes take up to 16 polynomials per block.
+void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+              const LimbMap& m, const LimbMap& m_out, bool inverse) {
+  const int logn = c.log_n;
+  const int N = 1 << logn;
+  const double elems = (double)N * m.n * B;
+  const u64* tw = inverse ? c.d_itw : c.d_tw;
+  const u64* tws = inverse ? c.d_itws : c.d_tws;
+  if (logn == 12) {
+    chk_map(c, in, B, in_stride, m, "ntt input");
+    chk_map(c, out, B, out_stride, m, "ntt output", true);
+    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 12);
+    const size_t lds = (size_t)(4096 + 256) * sizeof(u64);
+    const dim3 grid(1, (unsigned)m.n, (unsigned)B);
+    if (inverse)
+      LAUNCH((k_ntt_fast<12, true, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 1, B);
+    else
+      LAUNCH((k_ntt_fast<12, false, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 0, B);
+    check_launch();
+    return;
+  }
+  const int Vr = B < 16 ? B : 16;
+  const size_t lds_col = (size_t)16 * (256 + 16) * sizeof(u64);
+  const size_t lds_row = (size_t)Vr * (256 + 16) * sizeof(u64);
+  const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
+  const dim3 grow(N / 256, (unsigned)m.n, (unsigned)((B + Vr - 1) / Vr));
+  auto col = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm, int last) {
+    chk_map(c, src, B, ss, mm, "ntt column pass input");
+    chk_map(c, dst, B, ds, mm, "ntt column pass output", true);
+    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 8);
+    if (inverse)
+      LAUNCH((k_ntt_fast<8, true, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
+             c.d_primes, tw, tws, logn, 0, last, B);
+    else
+      LAUNCH((k_ntt_fast<8, false, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
+             c.d_primes, tw, tws, logn, 0, last, B);
+    check_launch();
+  };
+  auto row = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm) {
+    chk_map(c, src, B, ss, mm, "ntt row pass input");
+    chk_map(c, dst, B, ds, mm, "ntt row pass output", true);
+    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 8);
+    if (inverse)
+      LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vr), lds_row, c.stream, src, ss, dst, ds,
+             mm, c.d_primes, tw, tws, logn, 8, 0, B);
+    else
+      LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vr), lds_row, c.stream, src, ss, dst, ds,
+             mm, c.d_primes, tw, tws, logn, 8, 0, B);
+    check_launch();
+  };
+  if (!inverse) {
+    col(in, in_stride, out, out_stride, m, 0);
+    row(out, out_stride, out, out_stride, m_out);
+  } else {
+    row(in, in_stride, out, out_stride, m);
+    col(out, out_stride, out, out_stride, m_out, 1);
+  }
+}
+
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
          const LimbMap& m, bool inverse) {
   if (B <= 0 || m.n <= 0) return;
@@ -522,6 +758,10 @@ void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_str
                          c.d_primes, c.d_tw, c.d_tws, logn, logm, s0, col, last);
     check_launch();
   };
+  if (logn == 12 || logn == 16) {
+    ntt_fast(c, in, in_stride, out, out_stride, B, m, m_out, inverse);
+    return;
+  }
   if (logn <= 12) {
     launch(in, in_stride, out, out_stride, logn, 0, 0, inverse ? 1 : 0, m);
     return;
