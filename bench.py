@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--schedule", type=int, default=0, help="1 or 2; 0 sweeps both")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
     return ap.parse_args()
 
 
@@ -68,12 +69,17 @@ def main():
     gals = {k: bm.bm_encrypt_gallery(ctx, pk, X, k, seed, 1000) for k in ks}
     print("# setup %.1fs (keys for %d rotations, %d galleries)" % (time.time() - t0, len(rots), len(ks)),
           file=sys.stderr, flush=True)
-    stream = torch.cuda.current_stream()
+    # a dedicated stream: the library's launches and the timing events share it
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     sptr = stream.cuda_stream
 
     def run_once(k, s):
         r = bm.bm_match(ctx, evk, q_ct, gals[k], None, schedule=s, out_limbs=0, stream=sptr)
         return r
+
+    # matches are captured once per configuration as HIP graphs and replayed
+    bm.bm_ctx_set_graphs(ctx, not args.eager)
 
     # ---- short sweep over (k, schedule)
     sweep = {}
@@ -98,8 +104,6 @@ def main():
     for _ in range(args.warmup):
         bm.bm_result_free(run_once(bk, bs))
     torch.cuda.synchronize()
-    if not args.no_profile:
-        bm.bm_profile_enable(ctx, True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     results = []
@@ -111,12 +115,25 @@ def main():
         ends[i].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof = bm.bm_profile_dump(ctx) if not args.no_profile else {}
-    bm.bm_profile_enable(ctx, False)
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     scores = bm.bm_decrypt_scores(ctx, sk, results[-1], n_tmpl)
     for r in results:
         bm.bm_result_free(r)
+
+    # ---- per-kernel times: the same steps once more, launched eagerly with a
+    # HIP event pair around every kernel on its stream (a graph replay cannot
+    # be bracketed kernel by kernel)
+    prof, eager_ms = {}, None
+    if not args.no_profile:
+        bm.bm_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            bm.bm_result_free(run_once(bk, bs))
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+        prof = bm.bm_profile_dump(ctx)
+        bm.bm_profile_enable(ctx, False)
     cos = X.astype(np.float64) @ q.astype(np.float64)
     err = float(np.max(np.abs(scores - cos)))
     top = bm.bm_top1(scores)[0]
@@ -177,6 +194,8 @@ def main():
             "sweep_ms": {k: round(v, 3) for k, v in sweep.items()},
             "max_abs_err_vs_fp64_cosine": err, "top1_correct": bool(top == w["known"]),
             "kernel_ms_per_step": breakdown,
+            "launch": "eager" if args.eager else "hip_graph",
+            "eager_profiled_ms_per_step": round(eager_ms, 3) if eager_ms else None,
             "paper_context": "Lattigo CPU, N=8192 real slots, 3 clusters x 2 Xeon Gold 5220 cores: "
                              "6144 x 128-dim matched in 451.67 ms (13,603 templates/s)",
         },

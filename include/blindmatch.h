@@ -97,6 +97,14 @@ const char *bm_last_error(const bm_ctx *ctx);
 /* Result-invariant tuning knob: gallery groups evaluated per batched pass
  * (0 = choose automatically).  Changes speed and scratch size, never bits. */
 int bm_ctx_set_group_chunk(bm_ctx *ctx, uint32_t groups);
+/* Result-invariant knob: with on != 0, bm_match captures the launches of a
+ * match as a HIP graph the first time a (keys, gallery, masks, schedule,
+ * output level, stream) combination is seen and replays it afterwards (the
+ * query is copied into the graph's input slot, the result out of its output
+ * slot).  Each graph keeps its own scratch memory; freeing an evaluation key,
+ * gallery or masks handle drops the context's graphs.  Off by default.
+ * Kernel profiling (bm_profile_enable) runs matches eagerly. */
+int bm_ctx_set_graphs(bm_ctx *ctx, int on);
 /* Device memory currently held by the context's caching pool, in bytes. */
 int bm_ctx_pool_bytes(const bm_ctx *ctx, uint64_t *bytes);
 

@@ -53,6 +53,7 @@ _SIGS = {
     "bm_ctx_create": (ctypes.c_int, [ctypes.POINTER(bm_params), ctypes.c_int, _PP]),
     "bm_ctx_free": (None, [_P]),
     "bm_ctx_set_group_chunk": (ctypes.c_int, [_P, _u32]),
+    "bm_ctx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
     "bm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_profile_dump": (ctypes.c_int, [_P, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
@@ -111,10 +112,22 @@ _SIGS = {
 _lib = None
 
 
+def _one_hip_runtime():
+    """PyTorch ships its own HIP runtime (soname libamdhip64.so.7) and asks for
+    it by the unversioned name.  Loaded first, it also serves this library, so
+    the process holds one runtime and torch streams are valid stream handles
+    here; loaded after the system runtime, torch would start a second one."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        _one_hip_runtime()
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libblindmatch.so is not built (run paper_2408_06167_amd.build.build())")
         L = ctypes.CDLL(LIB_PATH)
@@ -171,6 +184,10 @@ def bm_ctx_free(ctx):
 
 def bm_ctx_set_group_chunk(ctx, groups):
     _check(lib().bm_ctx_set_group_chunk(ctx, int(groups)), "bm_ctx_set_group_chunk", ctx)
+
+
+def bm_ctx_set_graphs(ctx, on=True):
+    _check(lib().bm_ctx_set_graphs(ctx, 1 if on else 0), "bm_ctx_set_graphs", ctx)
 
 
 def bm_ctx_pool_bytes(ctx):

@@ -49,17 +49,18 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
     kern::mul(c, q + comp * ln, 0, masks, (size_t)(c.L + 1) * N, pm.p() + comp * ln, 2 * ln, (int)k,
            kern::chain_map(l));
   ev::rescale(c, pm.p(), (int)k, 2, l, out);
-  DBuf tmp(&c, 2 * nln);
-  for (u32 i = 0; i < k; ++i) {
-    u64* ci = out + (size_t)i * 2 * nln;
-    for (int t = 0; (1u << t) < k; ++t) {
-      const long r = (long)cc << t;
-      const long step = ((i >> t) & 1) == 0 ? -r : r;
-      const u64 g = ev::galois_for_rotation(c, step);
-      ev::rotate(c, ci, 1, nl, g, galois_key(evk, g), tmp.p(), true);
-      HIP_OK(dev::memcpy_async(ci, tmp.p(), 2 * nln * sizeof(u64), hipMemcpyDeviceToDevice, c.stream));
-    }
+  // step t: part i adds Rot(., -c 2^t) when bit t of i is 0 and Rot(., +c 2^t)
+  // otherwise; all k parts go in one batch, the sign chosen per element.
+  DBuf tmp(&c, (size_t)k * 2 * nln);
+  u64* a = out;
+  u64* b = tmp.p();
+  for (int t = 0; (1u << t) < k; ++t) {
+    const long r = (long)cc << t;
+    const u64 gm = ev::galois_for_rotation(c, -r), gp = ev::galois_for_rotation(c, r);
+    ev::rotate2(c, a, (int)k, nl, gm, galois_key(evk, gm), gp, galois_key(evk, gp), t, b, true);
+    std::swap(a, b);
   }
+  if (a != out) kern::copy_limbs(c, a, 2 * nln, nln, out, 1, 2 * nln, 0, nln, (int)k, 2, nl);
 }
 
 void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,

@@ -58,6 +58,11 @@ hipError_t event_sync(hipEvent_t e);
 hipError_t event_elapsed(float* ms, hipEvent_t a, hipEvent_t b);
 hipError_t event_query(hipEvent_t e);
 hipError_t last_error();
+hipError_t begin_capture(hipStream_t s);
+hipError_t end_capture(hipStream_t s, hipGraph_t* g);
+hipError_t graph_instantiate(hipGraphExec_t* e, hipGraph_t g);
+hipError_t graph_destroy(hipGraph_t g);
+hipError_t graph_launch(hipGraphExec_t e, hipStream_t s);
 }  // namespace dev
 
 // ----------------------------------------------------------------- errors
@@ -188,7 +193,8 @@ class Profiler {
   hipEvent_t take();
 };
 
-// RAII device buffer of u64 words from a context's pool.
+// RAII device buffer of u64 words from the context's current pool; it goes
+// back to the pool it came from (a graph's private pool during a capture).
 class DBuf {
  public:
   DBuf() = default;
@@ -202,9 +208,19 @@ class DBuf {
   size_t words() const { return words_; }
 
  private:
-  Ctx* ctx_ = nullptr;
+  DevicePool* pool_ = nullptr;
   u64* p_ = nullptr;
   size_t words_ = 0;
+};
+
+// A captured match: replayed with the query copied into q_slot and the
+// result copied out of out_slot.  Its scratch lives in its own pool.
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  std::unique_ptr<DevicePool> pool;
+  DBuf q_slot, out_slot;
+  hipGraphExec_t exec = nullptr;
+  ~GraphEntry();
 };
 
 // ----------------------------------------------------------------- context
@@ -245,6 +261,8 @@ struct Ctx {
 
   bool owns_tables = true;         // false for a lane sharing another context's tables
   std::shared_ptr<Profiler> prof = std::make_shared<Profiler>();
+  bool use_graphs = false;                          // capture and replay matches
+  std::vector<std::unique_ptr<GraphEntry>> graphs;  // most recent last
 
   int nprimes() const { return (int)primes.size(); }
   int pid_special(int k) const { return L + 1 + k; }
@@ -307,13 +325,15 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2]
 void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
             u64* o, size_t so, int B, int limbs, bool accumulate);
 // evaluation-domain automorphism X -> X^g of `comps` components of `limbs` limbs
+// batch element z uses Galois element g1 when bit `sel` of z is set, else g0
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B,
-                  int rows, u64 g);
+                  int rows, u64 g0, u64 g1, int sel);
 // ModUp of digit j: coefficient-domain x [l] -> y slots of every target (coefficient)
 void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j);
 // key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext], key Montgomery)
-void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key,
-         u64* uw, size_t suw, int B, int limbs);
+// batch element z uses key1 when bit `sel` of z is set, else key0
+void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
+         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs);
 // ModDown base conversion: special limbs of u (coefficient) -> conv [l] (coefficient)
 void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs);
 // out = (u - conv) * P^{-1} (+ addend), both components
@@ -333,10 +353,6 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
 }  // namespace bm
 
 // ----------------------------------------------------------------- opaque handles
-
-struct bm_ctx {
-  bm::Ctx c;
-};
 
 struct bm_ct {
   bm_ctx* ctx = nullptr;
@@ -371,6 +387,12 @@ struct bm_masks {
   uint32_t d = 0, k = 0;
   double scale = 0;
   bm::DBuf pt;             // [k][L+1][N] evaluation domain
+};
+
+struct bm_ctx {
+  bm::Ctx c;
+  // masks of Alg. 1 per (d, k), made on first use (declared after c: freed first)
+  std::map<uint64_t, std::unique_ptr<bm_masks>> mask_cache;
 };
 
 struct bm_gallery {

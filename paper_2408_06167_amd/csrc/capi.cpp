@@ -173,6 +173,17 @@ int bm_ctx_set_group_chunk(bm_ctx* ctx, uint32_t groups) {
   });
 }
 
+int bm_ctx_set_graphs(bm_ctx* ctx, int on) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    if (!on && !ctx->c.graphs.empty()) {
+      HIP_OK(dev::stream_sync(ctx->c.stream));
+      ctx->c.graphs.clear();
+    }
+    ctx->c.use_graphs = on != 0;
+  });
+}
+
 int bm_ctx_pool_bytes(const bm_ctx* ctx, uint64_t* bytes) {
   if (!ctx || !bytes) return BM_EINVAL;
   *bytes = ctx->c.pool->bytes_held();
@@ -257,7 +268,7 @@ int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot
         const u64 g = ev::galois_for_rotation(c, rotations[i]);
         if (e->gk.count(g)) continue;
         DBuf sg(&c, (size_t)np * c.N);
-        kern::automorphism(c, s->s_ntt.p(), 0, sg.p(), 0, 1, np, g);
+        kern::automorphism(c, s->s_ntt.p(), 0, sg.p(), 0, 1, np, g, g, 31);
         std::unique_ptr<bm_switch_key> key(new bm_switch_key);
         ev::keygen_switch(c, seed, ev::DOM_GK_A, ev::DOM_GK_E, g * (u64)c.dnum, s.get(), sg.p(), key->k);
         e->gk.emplace(g, std::move(key));
@@ -319,7 +330,16 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
 
 void bm_sk_free(bm_sk* sk) { delete sk; }
 void bm_pk_free(bm_pk* pk) { delete pk; }
-void bm_evk_free(bm_evk* evk) { delete evk; }
+static void drop_graphs(bm_ctx* ctx) {
+  if (!ctx || ctx->c.graphs.empty()) return;
+  (void)dev::stream_sync(ctx->c.stream);
+  ctx->c.graphs.clear();
+}
+
+void bm_evk_free(bm_evk* evk) {
+  if (evk) drop_graphs(evk->ctx);
+  delete evk;
+}
 
 // ------------------------------------------------------------------ encode / encrypt
 
@@ -468,7 +488,10 @@ int bm_gallery_info(const bm_gallery* g, uint64_t* groups, uint32_t* limbs, doub
   return BM_OK;
 }
 
-void bm_gallery_free(bm_gallery* g) { delete g; }
+void bm_gallery_free(bm_gallery* g) {
+  if (g) drop_graphs(g->ctx);
+  delete g;
+}
 
 // ------------------------------------------------------------------ ciphertexts
 
@@ -662,21 +685,26 @@ static bm_masks* make_masks(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* 
   return m.release();
 }
 
+// Library masks of Alg. 1 on the context's current stream.
+static bm_masks* create_masks(bm_ctx* ctx, uint32_t d, uint32_t k) {
+  Ctx& c = ctx->c;
+  bmx::check_shape(c, d, k);
+  const uint32_t cc = d / k;
+  const double scale = (double)c.primes[c.L].q;
+  std::vector<int64_t> coeffs((size_t)k * c.N);
+  std::vector<double> slots(c.n);
+  for (uint32_t i = 0; i < k; ++i) {
+    for (size_t s = 0; s < c.n; ++s) slots[s] = ((s % d) / cc == i) ? 1.0 : 0.0;
+    encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
+  }
+  return make_masks(ctx, d, k, coeffs.data(), scale);
+}
+
 int bm_masks_create(bm_ctx* ctx, uint32_t d, uint32_t k, bm_masks** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
-    Ctx& c = ctx->c;
-    bmx::check_shape(c, d, k);
-    const uint32_t cc = d / k;
-    const double scale = (double)c.primes[c.L].q;
-    std::vector<int64_t> coeffs((size_t)k * c.N);
-    std::vector<double> slots(c.n);
-    for (uint32_t i = 0; i < k; ++i) {
-      for (size_t s = 0; s < c.n; ++s) slots[s] = ((s % d) / cc == i) ? 1.0 : 0.0;
-      encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
-    }
-    c.use_stream(nullptr);
-    *out = make_masks(ctx, d, k, coeffs.data(), scale);
+    ctx->c.use_stream(nullptr);
+    *out = create_masks(ctx, d, k);
   });
 }
 
@@ -690,7 +718,10 @@ int bm_masks_import(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* coeffs, 
   });
 }
 
-void bm_masks_free(bm_masks* m) { delete m; }
+void bm_masks_free(bm_masks* m) {
+  if (m) drop_graphs(m->ctx);
+  delete m;
+}
 
 int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* masks, bm_ct** outs) {
   return guarded(ctx, [&] {
@@ -715,6 +746,72 @@ int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* ma
   });
 }
 
+// Expansion (k > 1) and Alg. 2 for one query: q [2][ql][N] -> out [G][2][ol][N]
+static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t ql, const bm_gallery* g,
+                       const bm_masks* m, uint32_t schedule, int ol, u64* out) {
+  const uint32_t k = g->k;
+  const u64* cu = q;
+  DBuf expanded;
+  if (k > 1) {
+    const size_t nln = (size_t)(ql - 1) * c.N;
+    expanded = DBuf(&c, (size_t)k * 2 * nln);
+    bmx::expand(c, evk, q, (int)ql, m->pt.p(), g->d, k, expanded.p());
+    cu = expanded.p();
+  }
+  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, schedule, ol, out, 0);
+}
+
+// Replay (capturing on first use) the match of this shape as a HIP graph.
+static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
+                        const bm_masks* m, uint32_t schedule, int ol, u64* out) {
+  const std::vector<uint64_t> key = {(uint64_t)evk, (uint64_t)evk->rlk.k.p(), (uint64_t)g->buf.p(),
+                                     g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
+                                     schedule, (uint64_t)ol, q->limbs, (uint64_t)c.stream,
+                                     (uint64_t)c.group_chunk};
+  GraphEntry* e = nullptr;
+  for (auto& ge : c.graphs)
+    if (ge->key == key) e = ge.get();
+  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)g->groups * 2 * ol * c.N;
+  if (!e) {
+    std::unique_ptr<GraphEntry> ne(new GraphEntry);
+    ne->key = key;
+    ne->pool.reset(new DevicePool(c.device));
+    std::swap(c.pool, ne->pool);          // scratch of the capture comes from the graph's pool
+    hipGraph_t graph = nullptr;
+    bool capturing = false;
+    try {
+      ne->q_slot = DBuf(&c, qw);
+      ne->out_slot = DBuf(&c, ow);
+      HIP_OK(dev::begin_capture(c.stream));
+      capturing = true;
+      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, schedule, ol, ne->out_slot.p());
+      capturing = false;
+      HIP_OK(dev::end_capture(c.stream, &graph));
+      HIP_OK(dev::graph_instantiate(&ne->exec, graph));
+      HIP_OK(dev::graph_destroy(graph));
+    } catch (...) {
+      if (capturing) {
+        hipGraph_t dead = nullptr;
+        (void)dev::end_capture(c.stream, &dead);
+        if (dead) (void)dev::graph_destroy(dead);
+      }
+      std::swap(c.pool, ne->pool);
+      throw;
+    }
+    std::swap(c.pool, ne->pool);
+    if (c.graphs.size() >= 8) {
+      HIP_OK(dev::stream_sync(c.stream));
+      c.graphs.erase(c.graphs.begin());
+    }
+    c.graphs.push_back(std::move(ne));
+    e = c.graphs.back().get();
+  }
+  kern::copy_limbs(c, q->buf.p(), qw, qw / 2, e->q_slot.p(), 1, qw, 0, qw / 2, 1, 2, (int)q->limbs);
+  HIP_OK(dev::graph_launch(e->exec, c.stream));
+  kern::copy_limbs(c, e->out_slot.p(), 2 * (size_t)ol * c.N, (size_t)ol * c.N, out, 1,
+                   2 * (size_t)ol * c.N, 0, (size_t)ol * c.N, (int)g->groups, 2, ol);
+}
+
 static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
                       const bm_masks* masks, uint32_t schedule, uint32_t out_limbs, bm_result** out) {
   Ctx& c = ctx->c;
@@ -725,6 +822,23 @@ static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_g
   int ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : ol_nat);
   ol = std::min(ol, ol_nat);
   REQUIRE(ol >= 1, BM_ELEVEL, "output level");
+  double cu_scale = q->scale;
+  const bm_masks* m = masks;
+  if (k == 1) {
+    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
+  } else {
+    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
+    if (!m) {
+      const uint64_t key = ((uint64_t)g->d << 32) | k;
+      auto it = ctx->mask_cache.find(key);
+      if (it == ctx->mask_cache.end())
+        it = ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(create_masks(ctx, g->d, k))).first;
+      m = it->second.get();
+    }
+    REQUIRE(m->d == g->d && m->k == k, BM_EDIM, "masks do not match the gallery shape");
+    cu_scale = q->scale * m->scale / (double)c.primes[q->limbs - 1].q;
+  }
+  REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
   std::unique_ptr<bm_result> r(new bm_result);
   r->ctx = ctx;
   r->d = g->d;
@@ -733,33 +847,10 @@ static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_g
   r->groups = g->groups;
   r->n_templates = g->n_templates;
   r->store = std::make_shared<DBuf>(&c, (size_t)g->groups * 2 * ol * c.N);
-  const u64* cu = nullptr;
-  DBuf expanded;
-  double cu_scale = q->scale;
-  if (k == 1) {
-    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
-    cu = q->buf.p();
-  } else {
-    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
-    std::unique_ptr<bm_masks> own;
-    const bm_masks* m = masks;
-    if (!m) {
-      bm_masks* tmp = nullptr;
-      int st = bm_masks_create(ctx, g->d, k, &tmp);
-      if (st != BM_OK) BM_THROW(st, c.last_error);
-      own.reset(tmp);
-      m = tmp;
-    }
-    REQUIRE(m->d == g->d && m->k == k, BM_EDIM, "masks do not match the gallery shape");
-    const size_t nln = (size_t)(q->limbs - 1) * c.N;
-    expanded = DBuf(&c, (size_t)k * 2 * nln);
-    bmx::expand(c, evk, q->buf.p(), (int)q->limbs, m->pt.p(), g->d, k, expanded.p());
-    cu = expanded.p();
-    cu_scale = q->scale * m->scale / (double)c.primes[q->limbs - 1].q;
-  }
-  REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
-  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, schedule, ol,
-                   r->p(), 0);
+  if (c.use_graphs && !c.prof->on)
+    match_graph(c, evk, q, g, m, schedule, ol, r->p());
+  else
+    match_body(c, evk, q->buf.p(), q->limbs, g, m, schedule, ol, r->p());
   r->scale = cu_scale * g->scale / (double)c.primes[g->limbs - 1].q;
   *out = r.release();
 }

@@ -88,5 +88,29 @@ hipError_t event_elapsed(float* ms, hipEvent_t a, hipEvent_t b) {
 hipError_t event_query(hipEvent_t e) { return dry() ? hipSuccess : hipEventQuery(e); }
 hipError_t last_error() { return dry() ? hipSuccess : hipGetLastError(); }
 
+hipError_t begin_capture(hipStream_t s) {
+  return dry() ? hipSuccess : hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+}
+
+hipError_t end_capture(hipStream_t s, hipGraph_t* g) {
+  if (dry()) {
+    *g = (hipGraph_t)0x1;
+    return hipSuccess;
+  }
+  return hipStreamEndCapture(s, g);
+}
+
+hipError_t graph_instantiate(hipGraphExec_t* e, hipGraph_t g) {
+  if (dry()) {
+    static std::atomic<uintptr_t> next{0x200000};
+    *e = (hipGraphExec_t)(next += 16);
+    return hipSuccess;
+  }
+  return hipGraphInstantiate(e, g, nullptr, nullptr, 0);
+}
+
+hipError_t graph_destroy(hipGraph_t g) { return dry() ? hipSuccess : hipGraphDestroy(g); }
+hipError_t graph_launch(hipGraphExec_t e, hipStream_t s) { return dry() ? hipSuccess : hipGraphLaunch(e, s); }
+
 }  // namespace dev
 }  // namespace bm

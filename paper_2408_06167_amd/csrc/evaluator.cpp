@@ -98,24 +98,30 @@ void DevicePool::trim() {
   free_.clear();
 }
 
-DBuf::DBuf(Ctx* c, size_t words) : ctx_(c), words_(words) {
-  p_ = words ? (u64*)c->pool->alloc(words * sizeof(u64)) : nullptr;
+DBuf::DBuf(Ctx* c, size_t words) : pool_(c->pool.get()), words_(words) {
+  p_ = words ? (u64*)pool_->alloc(words * sizeof(u64)) : nullptr;
 }
 
 DBuf::~DBuf() {
-  if (p_) ctx_->pool->release(p_, words_ * sizeof(u64));
+  if (p_) pool_->release(p_, words_ * sizeof(u64));
 }
 
 DBuf& DBuf::operator=(DBuf&& o) noexcept {
   if (this != &o) {
-    if (p_) ctx_->pool->release(p_, words_ * sizeof(u64));
-    ctx_ = o.ctx_;
+    if (p_) pool_->release(p_, words_ * sizeof(u64));
+    pool_ = o.pool_;
     p_ = o.p_;
     words_ = o.words_;
     o.p_ = nullptr;
     o.words_ = 0;
   }
   return *this;
+}
+
+GraphEntry::~GraphEntry() {
+  if (exec && !dev::dry()) (void)hipGraphExecDestroy(exec);
+  q_slot = DBuf();
+  out_slot = DBuf();
 }
 
 void Ctx::use_stream(void* s) {
@@ -128,6 +134,7 @@ void Ctx::use_stream(void* s) {
 
 Ctx::~Ctx() {
   if (stream) (void)dev::stream_sync(stream);
+  graphs.clear();
   pool.reset();
   if (owns_tables)
     for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws,
@@ -242,6 +249,11 @@ u64 galois_for_rotation(const Ctx& c, long r) {
 
 void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key, const u64* add0,
                 size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
+  key_switch2(c, x, sx, B, limbs, key, key, 31, add0, sa0, add1, sa1, out, so);
+}
+
+void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key0, const u64* key1,
+                 int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
   const size_t N = c.N;
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
@@ -266,7 +278,7 @@ void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* ke
   // 3. key inner product over Q_l u P
   const size_t suw = (size_t)2 * ext * N;
   DBuf uw(&c, (size_t)B * suw);
-  kern::kip(c, y.p(), sy, x, sx, key, uw.p(), suw, B, limbs);
+  kern::kip(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs);
   // 4. ModDown: special limbs to coefficient form, convert, back, subtract, scale by P^-1
   LimbMap mp{};
   for (int comp = 0; comp < 2; ++comp)
@@ -304,12 +316,17 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
 }
 
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input) {
+  rotate2(c, in, B, limbs, g, key, g, key, 31, out, add_input);
+}
+
+void rotate2(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1, const u64* key1,
+             int sel, u64* out, bool add_input) {
   const size_t ln = (size_t)limbs * c.N;
   DBuf tmp(&c, (size_t)B * 2 * ln);
-  kern::automorphism(c, in, 2 * ln, tmp.p(), 2 * ln, B, 2 * limbs, g);
+  kern::automorphism(c, in, 2 * ln, tmp.p(), 2 * ln, B, 2 * limbs, g0, g1, sel);
   if (add_input) kern::add(c, tmp.p(), 2 * ln, in, 2 * ln, tmp.p(), 2 * ln, B, kern::chain_map(limbs));
-  key_switch(c, tmp.p() + ln, 2 * ln, B, limbs, key, tmp.p(), 2 * ln, add_input ? in + ln : nullptr,
-             2 * ln, out, 2 * ln);
+  key_switch2(c, tmp.p() + ln, 2 * ln, B, limbs, key0, key1, sel, tmp.p(), 2 * ln,
+              add_input ? in + ln : nullptr, 2 * ln, out, 2 * ln);
 }
 
 void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out) {

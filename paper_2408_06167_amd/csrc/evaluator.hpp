@@ -17,12 +17,18 @@ u64 galois_for_rotation(const Ctx& c, long r);
 // `key`; out[b] = (KS_0(x_b) + add0_b, KS_1(x_b) + add1_b) as [2][limbs][N].
 void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key, const u64* add0,
                 size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so);
+// as above; batch element z switches with key1 when bit `sel` of z is set
+void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key0, const u64* key1,
+                 int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so);
 // d: [B][3][limbs][N] -> out [B][2][limbs][N]
 void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
 // in: [B][comps][limbs][N] -> out [B][comps][limbs-1][N]
 void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
+// batch element z rotates with (g1, key1) when bit `sel` of z is set, else (g0, key0)
+void rotate2(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1, const u64* key1,
+             int sel, u64* out, bool add_input);
 // out = first `to` limbs of each of `comps` components of in ([B][comps][from][N])
 void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out);
 

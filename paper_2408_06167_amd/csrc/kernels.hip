@@ -187,63 +187,95 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   int last, int B) {
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
-  constexpr int VS = M + M / 16;              // padded view length in LDS
+  constexpr int VS = M + M / 16 + 1;          // padded view length in LDS (odd: spreads banks)
   constexpr int PH = LOGM / 4;                // radix-16 phases
   extern __shared__ u64 sh[];
   __shared__ u64 tl[2 * 256];                 // block twiddles (w, ws) for 8-stage passes
   const int t = threadIdx.x;
   const int V = (int)blockDim.x / TPV;        // views in this block
   const int nthr = (int)blockDim.x;
-  const int slot = blockIdx.y;
-  const int pid = m.prime[slot];
+  const int pid = m.prime[blockIdx.y];
   const u64 q = P[pid].q;
   const int N = 1 << log_n;
   const u64* W = tw + (size_t)pid * N;
   const u64* WS = tws + (size_t)pid * N;
-  const size_t ioff = (size_t)m.off[slot] * N, ooff = (size_t)m.ooff[slot] * N;
   auto pad = [](int a) { return a + (a >> 4); };
+
+  // Lane layout: in a column pass consecutive lanes take consecutive columns
+  // (views); otherwise consecutive lanes take consecutive words of one view.
+  const int v = KIND == NTT_COL ? (t & 15) : t / TPV;
+  const int u = KIND == NTT_COL ? (t >> 4) : t % TPV;
+  // Global address of view word a: base + a * astride.
+  size_t base_in, base_out, astride;
+  bool valid = true;
+  if (KIND == NTT_COL) {
+    astride = (size_t)(N >> LOGM);
+    const size_t col = (size_t)blockIdx.x * 16 + v;
+    base_in = (size_t)blockIdx.z * in_stride + (size_t)m.off[blockIdx.y] * N + col;
+    base_out = (size_t)blockIdx.z * out_stride + (size_t)m.ooff[blockIdx.y] * N + col;
+  } else if (KIND == NTT_ROW) {
+    astride = 1;
+    const int z = blockIdx.z * V + v;
+    valid = z < B;
+    const size_t zz = valid ? (size_t)z : 0;
+    base_in = zz * in_stride + (size_t)m.off[blockIdx.y] * N + (size_t)blockIdx.x * M;
+    base_out = zz * out_stride + (size_t)m.ooff[blockIdx.y] * N + (size_t)blockIdx.x * M;
+  } else {
+    astride = 1;
+    base_in = (size_t)blockIdx.z * in_stride + (size_t)m.off[blockIdx.y] * N;
+    base_out = (size_t)blockIdx.z * out_stride + (size_t)m.ooff[blockIdx.y] * N;
+  }
+  const u64* src = in + base_in;
+  u64* dst = out + base_out;
 
   // ---- stage the block's twiddles (8-stage passes): tl[2^s + i] for stage s, block i
   if (LOGM == 8) {
     const int vb = KIND == NTT_ROW ? (int)blockIdx.x : 0;
     for (int k = t; k < 256; k += nthr) {
       if (k == 0) continue;
-      const int s = 31 - __clz(k);
-      const int g = (1 << (s0 + s)) + (vb << s) + (k - (1 << s));
+      const int st = 31 - __clz(k);
+      const int g = (1 << (s0 + st)) + (vb << st) + (k - (1 << st));
       tl[2 * k] = W[g];
       tl[2 * k + 1] = WS[g];
     }
   }
 
-  // ---- coalesced load of the tile into LDS
-  const int total = V * M;
-  for (int e = t; e < total; e += nthr) {
-    int v, a;
-    size_t g;
-    bool ok = true;
-    if (KIND == NTT_COL) {
-      a = e / V; v = e % V;                     // V = 16 consecutive columns
-      g = (size_t)blockIdx.z * in_stride + ioff + (size_t)a * (N >> LOGM) + (size_t)blockIdx.x * V + v;
-    } else if (KIND == NTT_ROW) {
-      v = e / M; a = e % M;
-      const int z = blockIdx.z * V + v;
-      ok = z < B;
-      g = (size_t)z * in_stride + ioff + (size_t)blockIdx.x * M + a;
-    } else {
-      v = 0; a = e;
-      g = (size_t)blockIdx.z * in_stride + ioff + a;
-    }
-    sh[v * VS + pad(a)] = ok ? in[g] : 0;
-  }
-  __syncthreads();
-
-  const int v = t / TPV, u = t % TPV;
   u64 x[16];
+  // phase p holds a = hi * 2^(LOGM-4p) + j * 2^(LOGM-4p-4) + lo,  u = hi * 2^(LOGM-4p-4) + lo
   auto addr = [&](int p, int j) {
     const int sh_lo = LOGM - 4 * p - 4;
     const int hi = u >> sh_lo, lo = u & ((1 << sh_lo) - 1);
     return (hi << (LOGM - 4 * p)) + (j << sh_lo) + lo;
   };
+  // A phase mapping is "direct" when lanes that differ in the fastest lane
+  // index touch consecutive global words: always for columns (lanes run over
+  // columns), and for the phase with lo = u (p = 0) otherwise.
+  constexpr int P_FIRST = INV ? PH - 1 : 0;
+  constexpr int P_LAST = INV ? 0 : PH - 1;
+  constexpr bool DIRECT_IN = KIND == NTT_COL || P_FIRST == 0;
+  constexpr bool DIRECT_OUT = KIND == NTT_COL || P_LAST == 0;
+
+  if (DIRECT_IN) {
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = src[(size_t)addr(P_FIRST, j) * astride];
+    }
+  } else {
+    // coalesced load in the p = 0 order, transpose through LDS
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int a = addr(0, j);
+        sh[v * VS + pad(a)] = src[a];
+      }
+    }
+  }
+  __syncthreads();                            // twiddles (and the transposed tile) ready
+  if (!DIRECT_IN) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(P_FIRST, j))];
+  }
+
   auto twid = [&](int kk, u64& w, u64& ws) {
     if (LOGM == 8) { w = tl[2 * kk]; ws = tl[2 * kk + 1]; }
     else { w = W[kk]; ws = WS[kk]; }
@@ -254,8 +286,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   for (int ph = 0; ph < PH; ++ph) {
     const int p = INV ? PH - 1 - ph : ph;
     const int hi = u >> (LOGM - 4 * p - 4);
+    if (ph > 0) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(p, j))];
+      for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(p, j))];
+    }
     if (!INV) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -292,34 +326,30 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
       for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(p, j))] = x[j];
       __syncthreads();
-    } else {
-      // exact reduction (times N^-1 at the end of an inverse transform)
-      const u64 w1 = last ? P[pid].ninv : 1, w1s = last ? P[pid].ninv_s : P[pid].pad[0];
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(p, j))] = mul_shoup(x[j], w1, w1s, q);
-      __syncthreads();
     }
   }
 
-  // ---- coalesced store of the tile
-  for (int e = t; e < total; e += nthr) {
-    int vv, a;
-    size_t g;
-    bool ok = true;
-    if (KIND == NTT_COL) {
-      a = e / V; vv = e % V;
-      g = (size_t)blockIdx.z * out_stride + ooff + (size_t)a * (N >> LOGM) + (size_t)blockIdx.x * V + vv;
-    } else if (KIND == NTT_ROW) {
-      vv = e / M; a = e % M;
-      const int z = blockIdx.z * V + vv;
-      ok = z < B;
-      g = (size_t)z * out_stride + ooff + (size_t)blockIdx.x * M + a;
-    } else {
-      vv = 0; a = e;
-      g = (size_t)blockIdx.z * out_stride + ooff + a;
+  // ---- exact reduction (times N^-1 at the end of an inverse transform) and store
+  const u64 w1 = last ? P[pid].ninv : 1, w1s = last ? P[pid].ninv_s : P[pid].pad[0];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) x[j] = mul_shoup(x[j], w1, w1s, q);
+  if (DIRECT_OUT) {
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) dst[(size_t)addr(P_LAST, j) * astride] = x[j];
     }
-    if (ok) out[g] = sh[vv * VS + pad(a)];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(P_LAST, j))] = x[j];
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int a = addr(0, j);
+        dst[a] = sh[v * VS + pad(a)];
+      }
+    }
   }
 }
 
@@ -435,12 +465,15 @@ __global__ void k_tensor(const u64* a, size_t sa, int a_div, const u64* b, size_
 }
 
 // evaluation-domain automorphism: out[j] = in[j'] with
-// 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.  blockIdx.y = row (comp*limbs + limb)
-__global__ void k_automorphism(const u64* in, size_t si, u64* out, size_t so, u64 g, int log_n) {
+// 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.  blockIdx.y = row (comp*limbs + limb).
+// Batch element z uses g1 when bit `sel` of z is set, g0 otherwise.
+__global__ void k_automorphism(const u64* in, size_t si, u64* out, size_t so, u64 g0, u64 g1, int sel,
+                               int log_n) {
   const int N = 1 << log_n;
   const size_t row = (size_t)blockIdx.y * N;
   const u64* I = in + (size_t)blockIdx.z * si + row;
   u64* O = out + (size_t)blockIdx.z * so + row;
+  const u64 g = ((blockIdx.z >> sel) & 1) ? g1 : g0;
   const u32 mask2n = (2u << log_n) - 1;
   EW_LOOP {
     const u32 rj = __brev((u32)i) >> (32 - log_n);
@@ -479,9 +512,9 @@ __global__ void k_modup(const u64* xc, size_t sx, u64* y, size_t sy, const ModUp
 // key inner product over every extended slot t of the level:
 // u[t] = sum_j y_j[t] * b_j[key limb of t], w[t] likewise with a_j.  For the
 // digit's own slots y_j[t] is the input limb itself (evaluation domain).
-__global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u64* key,
-                      u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
-                      const PrimeC* P, int N) {
+__global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u64* key0,
+                      const u64* key1, int sel, u64* uw, size_t suw, const ModUpTable* T,
+                      int key_limbs, int L1, const PrimeC* P, int N) {
   const ModUpTable& tb = *T;
   const int t = blockIdx.y;
   const int ext = tb.ext;
@@ -490,6 +523,7 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   const u64 q = pr.q;
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const size_t bz = blockIdx.z;
+  const u64* key = ((blockIdx.z >> sel) & 1) ? key1 : key0;   // per-element key choice
   u64* U = uw + bz * suw + (size_t)t * N;
   u64* Wp = U + (size_t)ext * N;
   EW_LOOP {
@@ -681,7 +715,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     chk_map(c, in, B, in_stride, m, "ntt input");
     chk_map(c, out, B, out_stride, m, "ntt output", true);
     Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 12);
-    const size_t lds = (size_t)(4096 + 256) * sizeof(u64);
+    const size_t lds = (size_t)(4096 + 256 + 1) * sizeof(u64);
     const dim3 grid(1, (unsigned)m.n, (unsigned)B);
     if (inverse)
       LAUNCH((k_ntt_fast<12, true, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
@@ -693,8 +727,8 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     return;
   }
   const int Vr = B < 16 ? B : 16;
-  const size_t lds_col = (size_t)16 * (256 + 16) * sizeof(u64);
-  const size_t lds_row = (size_t)Vr * (256 + 16) * sizeof(u64);
+  const size_t lds_col = (size_t)16 * (256 + 16 + 1) * sizeof(u64);
+  const size_t lds_row = (size_t)Vr * (256 + 16 + 1) * sizeof(u64);
   const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
   const dim3 grow(N / 256, (unsigned)m.n, (unsigned)((B + Vr - 1) / Vr));
   auto col = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm, int last) {
@@ -861,12 +895,14 @@ void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size
 }
 
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B, int rows,
-                  u64 g) {
+                  u64 g0, u64 g1, int sel) {
   chk(in, B, si, 0, (size_t)rows * c.N, "automorphism in");
   chk(out, B, so, 0, (size_t)rows * c.N, "automorphism out");
+  if ((g0 & 1) == 0 || (g1 & 1) == 0 || g0 >= 2 * c.N || g1 >= 2 * c.N)
+    BM_THROW(BM_EINVAL, "launch check: Galois element");
   Prof pf(c, "automorphism", 16.0 * c.N * B * rows, 0.0);
-  LAUNCH(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out,
-                     so, g, c.log_n);
+  LAUNCH(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out, so, g0, g1,
+         sel, c.log_n);
   check_launch();
 }
 
@@ -883,18 +919,19 @@ void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int
   check_launch();
 }
 
-void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key,
-         u64* uw, size_t suw, int B, int limbs) {
+void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
+         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs) {
   const ModUpTable& tb = c.h_modup[limbs];
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
   chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "kip digits");
   chk(y_own, B, sown, 0, (size_t)limbs * c.N, "kip input");
-  chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
+  chk(key0, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
+  chk(key1, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
   chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "kip output");
   Prof pf(c, "kip", 8.0 * c.N * tb.ext * ((double)B * tb.beta + 2.0 * tb.beta + 2.0 * B),
           2.0 * c.N * tb.ext * tb.beta * B);
-  LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
-                     key, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
+  LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown, key0, key1, sel,
+         uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
   check_launch();
 }
 

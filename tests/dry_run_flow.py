@@ -49,6 +49,7 @@ def flow(preset, shapes, n_templates):
                 bm.bm_ct_free(h)
             bm.bm_masks_free(m)
         for s in (1, 2):
+            bm.bm_ctx_set_graphs(ctx, s == 2)
             for chunk in (0, 1, 3):
                 bm.bm_ctx_set_group_chunk(ctx, chunk)
                 r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
@@ -56,6 +57,7 @@ def flow(preset, shapes, n_templates):
                 G, limbs, _ = bm.bm_result_info(r)
                 bm.bm_result_export(ctx, r, G - 1, N)
                 bm.bm_result_free(r)
+        bm.bm_ctx_set_graphs(ctx, False)
         rs = bm.bm_match_batch(ctx, evk, [q, q], [g, g], schedule=2)
         for r in rs:
             bm.bm_result_free(r)

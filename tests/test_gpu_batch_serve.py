@@ -1,0 +1,162 @@
+"""GPU: graph replay, batched matching and the serving loop return exactly the
+words of the plain per-query path (exact integer arithmetic, so the bar is
+bit-identity), and requests are the same alone and in a mix."""
+import numpy as np
+import pytest
+
+from gpu_common import SEED, lib_ctx, lib_keys, all_rotations, assert_words_equal, log
+from workloads import normalize
+
+pytestmark = pytest.mark.gpu
+
+SHAPES1 = [(16, 1), (16, 2), (16, 4), (8, 8)]
+SHAPES2 = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import paper_2408_06167_amd as bm
+    return bm
+
+
+def keys(preset):
+    return lib_keys(preset, all_rotations(preset, SHAPES1 if preset == 1 else SHAPES2))
+
+
+def words_of(bm, ctx, res, N):
+    G, _, _ = bm.bm_result_info(res)
+    return [bm.bm_result_export(ctx, res, g, N)[0] for g in range(G)]
+
+
+@pytest.mark.parametrize("preset,d,k,schedule", [(1, 16, 1, 1), (1, 16, 4, 2), (2, 128, 2, 2)])
+def test_graph_replay_equals_eager(bm, preset, d, k, schedule):
+    ctx = lib_ctx(preset)
+    sk, pk, evk = keys(preset)
+    p = bm.bm_params_preset(preset)
+    rng = np.random.default_rng(7)
+    n = 300 if preset == 1 else 3000
+    X = normalize(rng.standard_normal((n, d)))
+    gal = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 500)
+    queries = [bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(d)), SEED, 40 + i) for i in range(3)]
+    log("graph replay preset %d d=%d k=%d S%d" % (preset, d, k, schedule))
+    bm.bm_ctx_set_graphs(ctx, False)
+    eager = []
+    for q in queries:
+        r = bm.bm_match(ctx, evk, q, gal, None, schedule=schedule)
+        eager.append(words_of(bm, ctx, r, p.N))
+        bm.bm_result_free(r)
+    bm.bm_ctx_set_graphs(ctx, True)
+    try:
+        for rep in range(3):
+            for qi, q in enumerate(queries):
+                r = bm.bm_match(ctx, evk, q, gal, None, schedule=schedule)
+                got = words_of(bm, ctx, r, p.N)
+                for g, (a, b) in enumerate(zip(got, eager[qi])):
+                    assert_words_equal(a, b, "replay %d query %d group %d" % (rep, qi, g))
+                bm.bm_result_free(r)
+                # eager work and a synchronisation between replays
+                t = bm.bm_op_add(ctx, q, q)
+                bm.bm_ct_free(t)
+    finally:
+        bm.bm_ctx_set_graphs(ctx, False)
+    for q in queries:
+        bm.bm_ct_free(q)
+    bm.bm_gallery_free(gal)
+
+
+def test_match_batch_equals_individual(bm):
+    """Pairs of different d, k and size in one call: each result equals the
+    per-pair match word for word."""
+    ctx = lib_ctx(1)
+    sk, pk, evk = keys(1)
+    p = bm.bm_params_preset(1)
+    rng = np.random.default_rng(11)
+    pairs = []
+    for d, k, n in [(16, 1, 100), (16, 2, 700), (8, 8, 50), (16, 4, 1300), (16, 1, 129)]:
+        X = normalize(rng.standard_normal((n, d)))
+        g = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 1000 + n)
+        q = bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(d)), SEED, n)
+        pairs.append((q, g, X))
+    for schedule in (1, 2):
+        outs = bm.bm_match_batch(ctx, evk, [q for q, _, _ in pairs], [g for _, g, _ in pairs], schedule=schedule)
+        for (q, g, X), r in zip(pairs, outs):
+            single = bm.bm_match(ctx, evk, q, g, None, schedule=schedule)
+            for a, b in zip(words_of(bm, ctx, r, p.N), words_of(bm, ctx, single, p.N)):
+                assert_words_equal(a, b, "batched vs single")
+            bm.bm_result_free(single)
+            bm.bm_result_free(r)
+    for q, g, _ in pairs:
+        bm.bm_ct_free(q)
+        bm.bm_gallery_free(g)
+
+
+@pytest.mark.parametrize("preset", [1, 2])
+def test_server_alone_equals_mix(bm, preset):
+    """A query served alone and the same query served among others give the
+    same words, equal to the plain per-query match."""
+    ctx = lib_ctx(preset)
+    sk, pk, evk = keys(preset)
+    p = bm.bm_params_preset(preset)
+    rng = np.random.default_rng(13)
+    shapes = [(16, 1, 400), (16, 2, 900)] if preset == 1 else [(128, 1, 1000), (128, 4, 3000)]
+    srv = bm.bm_server_create(ctx, evk, 64 << 30, 2)
+    gids, gals, Xs = [], [], []
+    ref_gals = []
+    for d, k, n in shapes:
+        X = normalize(rng.standard_normal((n, d)))
+        Xs.append(X)
+        g = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 7000 + n)
+        ref_gals.append(bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 7000 + n))   # same words, kept outside
+        gids.append(bm.bm_server_add_gallery(srv, g))
+    probe_vec = normalize(rng.standard_normal(shapes[1][0]))
+    log("server preset %d: alone" % preset)
+    t = bm.bm_server_submit(srv, gids[1], bm.bm_encrypt_query(ctx, pk, probe_vec, SEED, 99))
+    bm.bm_server_drain(srv)
+    alone = bm.bm_server_poll(srv, t)
+    alone_w = words_of(bm, ctx, alone, p.N)
+    log("server preset %d: mix" % preset)
+    tickets = []
+    for i in range(7):
+        gi = i % 2
+        v = probe_vec if i == 3 else normalize(rng.standard_normal(shapes[gi][0]))
+        cq = bm.bm_encrypt_query(ctx, pk, v, SEED, 99 if i == 3 else 200 + i)
+        tickets.append((gi, bm.bm_server_submit(srv, gids[gi], cq), v))
+    bm.bm_server_drain(srv)
+    for i, (gi, tk, v) in enumerate(tickets):
+        r = bm.bm_server_poll(srv, tk)
+        assert r is not None
+        if i == 3:
+            for a, b in zip(words_of(bm, ctx, r, p.N), alone_w):
+                assert_words_equal(a, b, "mix vs alone")
+        scores = bm.bm_decrypt_scores(ctx, sk, r, Xs[gi].shape[0])
+        cos = Xs[gi].astype(np.float64) @ v.astype(np.float64)
+        assert np.max(np.abs(scores - cos)) < 1e-4
+        bm.bm_result_free(r)
+    # and the plain path gives the same words
+    q_plain = bm.bm_encrypt_query(ctx, pk, probe_vec, SEED, 99)
+    plain = bm.bm_match(ctx, evk, q_plain, ref_gals[1], None, schedule=2)
+    for a, b in zip(words_of(bm, ctx, plain, p.N), alone_w):
+        assert_words_equal(a, b, "served vs plain")
+    st = bm.bm_server_stats(srv)
+    assert st["completed"] == 8 and st["p99_ms"] >= st["p50_ms"] > 0
+    for h in (alone, plain):
+        bm.bm_result_free(h)
+    bm.bm_ct_free(q_plain)
+    for g in ref_gals:
+        bm.bm_gallery_free(g)
+    bm.bm_server_free(srv)
+
+
+def test_server_rejects_request_above_budget(bm):
+    ctx = lib_ctx(1)
+    sk, pk, evk = keys(1)
+    rng = np.random.default_rng(17)
+    srv = bm.bm_server_create(ctx, evk, 1 << 20, 2)     # 1 MiB: nothing fits
+    g = bm.bm_encrypt_gallery(ctx, pk, normalize(rng.standard_normal((100, 16))), 1, SEED, 1)
+    gid = bm.bm_server_add_gallery(srv, g)
+    q = bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(16)), SEED, 2)
+    with pytest.raises(bm.BMError) as e:
+        bm.bm_server_submit(srv, gid, q)
+    assert e.value.code == bm.BM_EBUDGET
+    bm.bm_ct_free(q)
+    bm.bm_server_free(srv)
