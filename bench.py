@@ -59,7 +59,7 @@ def main():
     params = bm.bm_params_preset(2)
     ctx = bm.bm_ctx_create(params, 0)
     ks = [args.k] if args.k else [1, 2, 4, 8, 16]
-    scheds = [args.schedule] if args.schedule else [1, 2]
+    scheds = [args.schedule] if args.schedule else [1, 2, 1 | bm.BM_LEVEL_MIN, 2 | bm.BM_LEVEL_MIN]
     rots = set()
     for k in ks:
         rots.update(bm.bm_rotations_for(d, k))
@@ -82,10 +82,13 @@ def main():
     bm.bm_ctx_set_graphs(ctx, not args.eager)
 
     # ---- short sweep over (k, schedule)
-    sweep = {}
+    def sname(s):
+        return "S%d%s" % (s & 0xff, "+levelmin" if s & bm.BM_LEVEL_MIN else "")
+
+    sweep, conf = {}, {}
     for k in ks:
         for s in scheds:
-            if k == 1 and s == 2 and 1 in scheds:
+            if k == 1 and (s & 0xff) == 2 and (s - 1) in scheds:
                 continue          # identical work for a single part
             bm.bm_result_free(run_once(k, s))
             torch.cuda.synchronize()
@@ -94,11 +97,14 @@ def main():
             for _ in range(reps):
                 bm.bm_result_free(run_once(k, s))
             torch.cuda.synchronize()
-            sweep["k%d_S%d" % (k, s)] = (time.perf_counter() - t) * 1e3 / reps
-            print("# sweep k=%d S%d: %.2f ms/match" % (k, s, sweep["k%d_S%d" % (k, s)]),
-                  file=sys.stderr, flush=True)
+            key = "k%d_%s" % (k, sname(s))
+            sweep[key] = (time.perf_counter() - t) * 1e3 / reps
+            conf[key] = (k, s)
+            print("# sweep %s: %.2f ms/match" % (key, sweep[key]), file=sys.stderr, flush=True)
     best = min(sweep, key=sweep.get)
-    bk, bs = int(best[1:best.index("_")]), int(best[-1])
+    bk, bs = conf[best]
+    canon = {key: v for key, v in sweep.items() if not conf[key][1] & bm.BM_LEVEL_MIN}
+    canon_best = min(canon, key=canon.get) if canon else None
 
     # ---- timed region
     for _ in range(args.warmup):
@@ -188,7 +194,10 @@ def main():
         "config": {
             "workload": "face-scale 1:N match: N=2^16, 8x50-bit chain + 2x51-bit special primes, "
                         "dnum=4, 6144 x 128-dim templates in 24 ciphertexts, one query",
-            "k": bk, "schedule": "S%d" % bs, "templates": n_tmpl,
+            "k": bk, "schedule": sname(bs), "templates": n_tmpl,
+            "natural_level_best": ({"config": canon_best, "ms_per_match": round(canon[canon_best], 3),
+                                    "templates_per_s": round(n_tmpl / canon[canon_best] * 1e3, 1)}
+                                   if canon_best else None),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "sweep_ms": {k: round(v, 3) for k, v in sweep.items()},
@@ -217,23 +226,28 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
     cq = ckks.encrypt(P, keys.pk, m, len(P.q), P.scale, 0xB11D, 1)
     lg = obm.gallery_limbs(P, k)
     groups = obm.pack_gallery(P, X.astype(np.float64), d, k)
-    masks, mscale = obm.mask_coeffs(P, d, k, len(P.q)) if k > 1 else (None, None)
+    lmin, sch = bool(schedule & 0x100), schedule & 0xff
+    t_l, ql = obm.level_min_shape(P, k, lg) if lmin else (lg, len(P.q))
+    masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
     t0 = time.perf_counter()
-    cu = [cq] if k == 1 else obm.expand(P, keys, cq, d, k, masks, mscale)
+    cq_used = ckks.drop_limbs(cq, ql) if lmin else cq
+    cu = [cq_used] if k == 1 else obm.expand(P, keys, cq_used, d, k, masks, mscale)
     dt = time.perf_counter() - t0          # matching time only; gallery encryption is setup
     done = 0
     for g, part_slots in enumerate(groups):
         gal = [ckks.encrypt(P, keys.pk, ckks.encode(v, P.scale, P.N), lg, P.scale, 0xB11D, 1000 + g * k + i)
                for i, v in enumerate(part_slots)]
         t1 = time.perf_counter()
-        ckks.drop_limbs(obm.hec3(P, keys, cu, gal, d, k, schedule), 2)
+        if lmin:
+            gal = [ckks.drop_limbs(x, t_l) for x in gal]
+        ckks.drop_limbs(obm.hec3(P, keys, cu, gal, d, k, sch, rot_limbs=2 if lmin else None), 2)
         dt += time.perf_counter() - t1
         done += min(T, X.shape[0] - g * T)
         if dt >= budget_s:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=round(done / dt, 1), unit="templates/s", cores=cores, kind="oracle",
-                sample="%d of %d templates (%d of %d groups, k=%d, S%d, one expansion), %.1fs of oracle time"
+                sample="%d of %d templates (%d of %d groups, k=%d, schedule %#x, one expansion), %.1fs of oracle time"
                        % (done, X.shape[0], g + 1, len(groups), k, schedule, dt))
 
 

@@ -54,6 +54,8 @@ enum {
 };
 
 enum { BM_S1 = 1, BM_S2 = 2 };   /* Alg. 2 schedules, see bm_match */
+/* OR-ed into a schedule: evaluate at the minimum level (see bm_match). */
+enum { BM_LEVEL_MIN = 0x100 };
 
 typedef struct bm_ctx bm_ctx;
 typedef struct bm_sk bm_sk;
@@ -240,7 +242,13 @@ int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *ma
  * then log2(d/k) steps acc += Rot(acc, 2^t).  The score of template g T + b is
  * at slot b c of group g.  `masks` may be NULL (the library's own masks are
  * used).  out_limbs: 0 = context default, otherwise an exact level drop of
- * each result.  Asynchronous on `stream`. */
+ * each result.  Asynchronous on `stream`.
+ * schedule | BM_LEVEL_MIN: every input is first cut by exact limb drops to
+ * the level the rest needs -- the products at 3 chain limbs (gallery read in
+ * place, query cut to 3 limbs, or 4 before Alg. 1 with masks at scale q_3),
+ * and the accumulator at the output limbs before rotate-and-sum.  Same
+ * message and accuracy, other bits, about a third of the NTTs; the query
+ * and gallery keep the levels they were encrypted at. */
 int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g,
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);

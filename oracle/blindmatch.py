@@ -20,6 +20,12 @@ N_in = k the number of parts, c = m / N_in the chunk length.  Slots are
   * gallery group g, part i, slot s holds x_{g T + floor(s/c)}[i c + s mod c],
     T = n / c templates per group, zeros past the last template; the score of
     template g T + b is read at slot b c of group g's output.
+  * minimum-level schedule (an option of this build): every ciphertext is
+    first cut, by exact limb drops, to the fewest limbs the rest of the
+    computation needs -- the products at EVAL_LIMBS = 3 chain limbs, the
+    query one limb more when Alg. 1 runs (its masks then encoded at scale
+    q_3), and the accumulator at the output limbs before rotate-and-sum.
+    The paper sizes its own modulus chain this way (starting level 3).
 """
 import math
 
@@ -118,9 +124,10 @@ def expand(params, keys, cq, d, k, masks, mask_scale):
     return out
 
 
-def hec3(params, keys, cu, cs, d, k, schedule):
+def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None):
     """Alg. 2 on one gallery group: accumulate the products of the k parts,
-    then log2(c) steps of C_out += Rot(C_out, 2^t)."""
+    then log2(c) steps of C_out += Rot(C_out, 2^t).  With rot_limbs the
+    accumulator is first cut to that many limbs (exact drop)."""
     c, _ = layout(params, d, k)
     acc = None
     if schedule == S1:
@@ -136,24 +143,44 @@ def hec3(params, keys, cu, cs, d, k, schedule):
         acc = ckks.rescale(params, ckks.relinearize(params, deg2, keys.rlk))
     else:
         raise ValueError("schedule")
+    if rot_limbs is not None and rot_limbs < acc.limbs:
+        acc = ckks.drop_limbs(acc, rot_limbs)
     for t in range(log2_exact(c)):
         acc = ckks.hadd(params, acc, ckks.rotate(params, acc, 1 << t, keys.gks))
     return acc
 
 
+EVAL_LIMBS = 3
+
+
+def level_min_shape(params, k, gallery_limbs):
+    """Limbs of the products and of the expanded query under the minimum-level
+    schedule, never above what the inputs carry."""
+    t = min(EVAL_LIMBS, gallery_limbs)
+    return t, (t + 1 if k > 1 else t)
+
+
 def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None,
-          out_limbs=None, groups=None):
+          out_limbs=None, groups=None, level_min=False):
     """Whole server side: expansion (k > 1) then HE-C^3 per gallery group.
     `gallery` is a list over groups of k ciphertexts.  Optionally only the
-    listed `groups` are evaluated (sampled parity at large sizes)."""
+    listed `groups` are evaluated (sampled parity at large sizes).  With
+    level_min every input is first cut to the minimum level (see above); the
+    masks must then be encoded at scale q_{limbs of the cut query - 1}."""
+    idx = range(len(gallery)) if groups is None else groups
+    rot_limbs = None
+    if level_min:
+        t, ql = level_min_shape(params, k, gallery[0][0].limbs)
+        cq = ckks.drop_limbs(cq, ql)
+        gallery = {g: [ckks.drop_limbs(x, t) for x in gallery[g]] for g in idx}
+        rot_limbs = min(out_limbs, t - 1) if out_limbs else t - 1
     if k == 1:
         cu = [cq]
     else:
         cu = expand(params, keys, cq, d, k, masks, mask_scale)
-    idx = range(len(gallery)) if groups is None else groups
     outs = {}
     for g in idx:
-        o = hec3(params, keys, cu, gallery[g], d, k, schedule)
+        o = hec3(params, keys, cu, gallery[g], d, k, schedule, rot_limbs)
         if out_limbs is not None and out_limbs < o.limbs:
             o = ckks.drop_limbs(o, out_limbs)
         outs[g] = o

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libblindmatch.so")
 BM_OK, BM_EINVAL, BM_EDIM, BM_ELEVEL, BM_ESCALE, BM_ENOKEY = 0, -1, -2, -3, -4, -5
 BM_ENOMEM, BM_EBUDGET, BM_EDEVICE, BM_EBUSY = -6, -7, -8, -9
 BM_S1, BM_S2 = 1, 2
+BM_LEVEL_MIN = 0x100
 
 
 class BMError(RuntimeError):

@@ -64,14 +64,16 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
 }
 
 void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
-                 const u64* gal, u64 G, int lg, u32 schedule, int out_limbs, u64* out,
-                 size_t out_qstride) {
+                 const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
+                 u64* out, size_t out_qstride) {
   const size_t N = c.N;
-  const int l = lg, nl = lg - 1;
-  if (nl < 1) BM_THROW(BM_ELEVEL, "matching needs two limbs");
-  if (out_limbs < 1 || out_limbs > nl) BM_THROW(BM_ELEVEL, "output limbs out of range");
-  const size_t ln = (size_t)l * N, nln = (size_t)nl * N;
-  const size_t part = 2 * ln;                 // one gallery ciphertext
+  const int nl = l - 1;
+  if (nl < 1 || l > lg_store) BM_THROW(BM_ELEVEL, "matching needs two limbs");
+  if (rot_limbs < 1 || rot_limbs > nl) BM_THROW(BM_ELEVEL, "rotation limbs out of range");
+  if (out_limbs < 1 || out_limbs > rot_limbs) BM_THROW(BM_ELEVEL, "output limbs out of range");
+  const size_t ln = (size_t)l * N, nln = (size_t)nl * N, rln = (size_t)rot_limbs * N;
+  const size_t gpart = 2 * (size_t)lg_store * N;   // one stored gallery ciphertext
+  const size_t upart = 2 * ln;                      // one expanded query part
   const size_t oct = (size_t)2 * out_limbs * N;
   const u32 cc = d / k;
   const int rots = ilog2(cc);
@@ -89,14 +91,15 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
   const u64 Bmax = Bg_max * nq;
   DBuf d3(&c, Bmax * 3 * ln), rl(&c, Bmax * 2 * ln);
   DBuf acc(&c, Bmax * 2 * nln), acc2(&c, Bmax * 2 * nln);
+  DBuf racc(rot_limbs < nl ? DBuf(&c, Bmax * 2 * rln) : DBuf());
   for (u64 g0 = 0; g0 < G; g0 += Bg_max) {
     const int Bg = (int)std::min<u64>(Bg_max, G - g0);
     const int B = Bg * nq;
-    const u64* gbase = gal + g0 * k * part;
+    const u64* gbase = gal + g0 * k * gpart;
     if (schedule == BM_S1) {
       for (u32 i = 0; i < k; ++i) {
-        kern::tensor(c, cu + (size_t)i * part, cu_stride, Bg, gbase + (size_t)i * part, (size_t)k * part,
-                     Bg, d3.p(), 3 * ln, B, l, false);
+        kern::tensor(c, cu + (size_t)i * upart, cu_stride, Bg, ln, gbase + (size_t)i * gpart,
+                     (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln, B, l, false);
         ev::relin(c, d3.p(), B, l, rlk, rl.p());
         u64* dst = i == 0 ? acc.p() : acc2.p();
         ev::rescale(c, rl.p(), B, 2, l, dst);
@@ -104,8 +107,8 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
       }
     } else if (schedule == BM_S2) {
       for (u32 i = 0; i < k; ++i)
-        kern::tensor(c, cu + (size_t)i * part, cu_stride, Bg, gbase + (size_t)i * part, (size_t)k * part,
-                     Bg, d3.p(), 3 * ln, B, l, i > 0);
+        kern::tensor(c, cu + (size_t)i * upart, cu_stride, Bg, ln, gbase + (size_t)i * gpart,
+                     (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln, B, l, i > 0);
       ev::relin(c, d3.p(), B, l, rlk, rl.p());
       ev::rescale(c, rl.p(), B, 2, l, acc.p());
     } else {
@@ -113,11 +116,16 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
     }
     u64* a = acc.p();
     u64* b = acc2.p();
+    if (rot_limbs < nl) {                 // exact level drop before rotate-and-sum
+      ev::drop(c, acc.p(), B, 2, nl, rot_limbs, racc.p());
+      a = racc.p();
+      b = acc.p();                        // acc is free again and large enough
+    }
     for (int t = 0; t < rots; ++t) {
-      ev::rotate(c, a, B, nl, gel[t], gks[t], b, true);
+      ev::rotate(c, a, B, rot_limbs, gel[t], gks[t], b, true);
       std::swap(a, b);
     }
-    kern::copy_limbs(c, a, 2 * nln, nln, out + g0 * oct, Bg, out_qstride, oct, (size_t)out_limbs * N,
+    kern::copy_limbs(c, a, 2 * rln, rln, out + g0 * oct, Bg, out_qstride, oct, (size_t)out_limbs * N,
                      B, 2, out_limbs);
   }
 }

@@ -14,11 +14,18 @@ int gallery_limbs(const Ctx& c, u32 k);
 void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
             u64* out);
 // Alg. 2 for nq queries x G groups.  Query j's k expanded parts start at
-// cu + j*cu_stride ([k][2][lg][N]); gal is [G][k][2][lg][N]; the result of
-// (j, g) goes to out + j*out_qstride + g*2*out_limbs*N.
+// cu + j*cu_stride ([k][2][l][N]); gal is [G][k][2][lg_store][N] and is read
+// at its first l limbs; the accumulator is cut to rot_limbs before the
+// rotate-and-sum; the result of (j, g) goes to
+// out + j*out_qstride + g*2*out_limbs*N.
 void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
-                 const u64* gal, u64 G, int lg, u32 schedule, int out_limbs, u64* out,
-                 size_t out_qstride);
+                 const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
+                 u64* out, size_t out_qstride);
 
 }  // namespace bmx
 }  // namespace bm
+
+// library masks of Alg. 1 for a query of `ql` limbs (scale q_{ql-1}), made on
+// the context's current stream (capi.cpp; internal, not exported)
+extern "C" __attribute__((visibility("hidden"))) bm_masks* bmx_create_masks(bm_ctx* ctx, uint32_t d,
+                                                                             uint32_t k, uint32_t ql);

@@ -28,7 +28,7 @@ using u32 = uint32_t;
 using u128 = unsigned __int128;
 
 constexpr int MAX_PRIMES = 24;   // chain + special primes
-constexpr int MAX_LIMBS = 24;    // limbs in one polynomial of a launch
+constexpr int MAX_LIMBS = 40;    // limb slots of one launch (all ModUp targets of a key switch)
 constexpr int MAX_DIGITS = 16;
 constexpr int MAX_ALPHA = 4;
 
@@ -114,6 +114,9 @@ struct ModUpTable {                       // one per level (number of chain limb
   int beta;                              // digits present
   int ext;                               // l + K target slots: chain limbs then specials
   int ext_prime[MAX_LIMBS];
+  int npairs;                            // (digit, target slot outside the digit) pairs
+  int8_t pair_j[MAX_LIMBS];
+  int8_t pair_t[MAX_LIMBS];
   ModUpDigit d[MAX_DIGITS];
 };
 
@@ -322,14 +325,16 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2]
                  u64* o, size_t so, int B, const LimbMap& m);
 // tensor product (a0,a1) x (b0,b1) -> (d0,d1,d2), optionally accumulated into o;
 // batch element z uses a[z / a_div] and b[z % b_mod]
-void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
-            u64* o, size_t so, int B, int limbs, bool accumulate);
+// a_cs, b_cs: component strides of the operands (>= limbs * N)
+void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
+            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate);
 // evaluation-domain automorphism X -> X^g of `comps` components of `limbs` limbs
 // batch element z uses Galois element g1 when bit `sel` of z is set, else g0
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B,
                   int rows, u64 g0, u64 g1, int sel);
-// ModUp of digit j: coefficient-domain x [l] -> y slots of every target (coefficient)
-void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j);
+// ModUp of every digit: coefficient-domain x [l] -> y[j][t] for every target slot t
+// outside digit j (coefficient domain); y is [beta][ext][N] per batch element
+void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs);
 // key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext], key Montgomery)
 // batch element z uses key1 when bit `sel` of z is set, else key0
 void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,

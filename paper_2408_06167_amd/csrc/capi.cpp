@@ -610,7 +610,8 @@ int bm_op_tensor(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
     std::unique_ptr<bm_ct> o(new_ct(ctx, 3, a->limbs, a->scale * b->scale));
-    kern::tensor(c, a->buf.p(), 0, 1, b->buf.p(), 0, 1, o->buf.p(), 0, 1, (int)a->limbs, false);
+    kern::tensor(c, a->buf.p(), 0, 1, (size_t)a->limbs * c.N, b->buf.p(), 0, 1, (size_t)b->limbs * c.N,
+                 o->buf.p(), 0, 1, (int)a->limbs, false);
     sync(c);
     *out = o.release();
   });
@@ -685,12 +686,14 @@ static bm_masks* make_masks(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* 
   return m.release();
 }
 
-// Library masks of Alg. 1 on the context's current stream.
-static bm_masks* create_masks(bm_ctx* ctx, uint32_t d, uint32_t k) {
+// Library masks of Alg. 1 on the context's current stream, encoded at the
+// scale of the last limb of a query with `ql` limbs.
+bm_masks* bmx_create_masks(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t ql) {
   Ctx& c = ctx->c;
   bmx::check_shape(c, d, k);
+  if (ql < 2 || (int)ql > c.L + 1) BM_THROW(BM_ELEVEL, "mask level out of range");
   const uint32_t cc = d / k;
-  const double scale = (double)c.primes[c.L].q;
+  const double scale = (double)c.primes[ql - 1].q;
   std::vector<int64_t> coeffs((size_t)k * c.N);
   std::vector<double> slots(c.n);
   for (uint32_t i = 0; i < k; ++i) {
@@ -704,7 +707,7 @@ int bm_masks_create(bm_ctx* ctx, uint32_t d, uint32_t k, bm_masks** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
     ctx->c.use_stream(nullptr);
-    *out = create_masks(ctx, d, k);
+    *out = bmx_create_masks(ctx, d, k, (uint32_t)ctx->c.L + 1);
   });
 }
 
@@ -746,32 +749,72 @@ int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* ma
   });
 }
 
-// Expansion (k > 1) and Alg. 2 for one query: q [2][ql][N] -> out [G][2][ol][N]
-static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t ql, const bm_gallery* g,
-                       const bm_masks* m, uint32_t schedule, int ol, u64* out) {
+// Shape of one match: limbs of the products (t), of the query as used (ql),
+// of the accumulator during rotate-and-sum and of the output.
+struct MatchShape {
+  uint32_t sched;   // BM_S1 or BM_S2
+  bool lmin;        // BM_LEVEL_MIN
+  int t, ql, rot, ol;
+};
+
+static MatchShape match_shape(const Ctx& c, const bm_ct* q, const bm_gallery* g, uint32_t schedule,
+                              uint32_t out_limbs) {
+  MatchShape s;
+  s.sched = schedule & 0xff;
+  s.lmin = (schedule & BM_LEVEL_MIN) != 0;
+  REQUIRE((schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN)) == 0, BM_EINVAL, "unknown schedule flags");
+  REQUIRE(s.sched == BM_S1 || s.sched == BM_S2, BM_EINVAL, "schedule must be BM_S1 or BM_S2");
+  REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
+  s.t = s.lmin ? std::min<int>(3, (int)g->limbs) : (int)g->limbs;
+  s.ql = g->k > 1 ? s.t + 1 : s.t;
+  if (s.lmin)
+    REQUIRE((int)q->limbs >= s.ql && (int)q->limbs == (int)g->limbs + (g->k > 1 ? 1 : 0), BM_ELEVEL,
+            "query level does not fit the gallery");
+  else if (g->k == 1)
+    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
+  else
+    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
+  const int nat = s.t - 1;
+  s.ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : nat);
+  s.ol = std::min(s.ol, nat);
+  REQUIRE(s.ol >= 1, BM_ELEVEL, "output level");
+  s.rot = s.lmin ? s.ol : nat;
+  return s;
+}
+
+// Expansion (k > 1) and Alg. 2 for one query: q [2][q_limbs][N] -> out [G][2][ol][N]
+static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t q_limbs, const bm_gallery* g,
+                       const bm_masks* m, const MatchShape& s, u64* out) {
   const uint32_t k = g->k;
-  const u64* cu = q;
+  const u64* qq = q;
+  DBuf cut;
+  if ((int)q_limbs > s.ql) {             // exact level drop of the query to ql limbs
+    cut = DBuf(&c, (size_t)2 * s.ql * c.N);
+    ev::drop(c, q, 1, 2, (int)q_limbs, s.ql, cut.p());
+    qq = cut.p();
+  }
+  const u64* cu = qq;
   DBuf expanded;
   if (k > 1) {
-    const size_t nln = (size_t)(ql - 1) * c.N;
-    expanded = DBuf(&c, (size_t)k * 2 * nln);
-    bmx::expand(c, evk, q, (int)ql, m->pt.p(), g->d, k, expanded.p());
+    expanded = DBuf(&c, (size_t)k * 2 * s.t * c.N);
+    bmx::expand(c, evk, qq, s.ql, m->pt.p(), g->d, k, expanded.p());
     cu = expanded.p();
   }
-  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, schedule, ol, out, 0);
+  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, s.t, s.sched, s.rot,
+                   s.ol, out, 0);
 }
 
 // Replay (capturing on first use) the match of this shape as a HIP graph.
 static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
-                        const bm_masks* m, uint32_t schedule, int ol, u64* out) {
+                        const bm_masks* m, const MatchShape& s, uint32_t schedule, u64* out) {
   const std::vector<uint64_t> key = {(uint64_t)evk, (uint64_t)evk->rlk.k.p(), (uint64_t)g->buf.p(),
                                      g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
-                                     schedule, (uint64_t)ol, q->limbs, (uint64_t)c.stream,
+                                     schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
                                      (uint64_t)c.group_chunk};
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
     if (ge->key == key) e = ge.get();
-  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)g->groups * 2 * ol * c.N;
+  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)g->groups * 2 * s.ol * c.N;
   if (!e) {
     std::unique_ptr<GraphEntry> ne(new GraphEntry);
     ne->key = key;
@@ -784,7 +827,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
       ne->out_slot = DBuf(&c, ow);
       HIP_OK(dev::begin_capture(c.stream));
       capturing = true;
-      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, schedule, ol, ne->out_slot.p());
+      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, s, ne->out_slot.p());
       capturing = false;
       HIP_OK(dev::end_capture(c.stream, &graph));
       HIP_OK(dev::graph_instantiate(&ne->exec, graph));
@@ -808,50 +851,46 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   }
   kern::copy_limbs(c, q->buf.p(), qw, qw / 2, e->q_slot.p(), 1, qw, 0, qw / 2, 1, 2, (int)q->limbs);
   HIP_OK(dev::graph_launch(e->exec, c.stream));
-  kern::copy_limbs(c, e->out_slot.p(), 2 * (size_t)ol * c.N, (size_t)ol * c.N, out, 1,
-                   2 * (size_t)ol * c.N, 0, (size_t)ol * c.N, (int)g->groups, 2, ol);
+  kern::copy_limbs(c, e->out_slot.p(), 2 * (size_t)s.ol * c.N, (size_t)s.ol * c.N, out, 1,
+                   2 * (size_t)s.ol * c.N, 0, (size_t)s.ol * c.N, (int)g->groups, 2, s.ol);
+}
+
+// masks for this shape: the caller's, or the context's cached library masks
+static const bm_masks* masks_for(bm_ctx* ctx, const bm_gallery* g, const bm_masks* masks, int ql) {
+  if (masks) return masks;
+  const uint64_t key = ((uint64_t)g->d << 40) | ((uint64_t)g->k << 20) | (uint64_t)ql;
+  auto it = ctx->mask_cache.find(key);
+  if (it == ctx->mask_cache.end())
+    it = ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(bmx_create_masks(ctx, g->d, g->k, ql))).first;
+  return it->second.get();
 }
 
 static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
                       const bm_masks* masks, uint32_t schedule, uint32_t out_limbs, bm_result** out) {
   Ctx& c = ctx->c;
-  REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
-  REQUIRE(schedule == BM_S1 || schedule == BM_S2, BM_EINVAL, "schedule must be BM_S1 or BM_S2");
+  const MatchShape s = match_shape(c, q, g, schedule, out_limbs);
   const uint32_t k = g->k;
-  const int ol_nat = (int)g->limbs - 1;
-  int ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : ol_nat);
-  ol = std::min(ol, ol_nat);
-  REQUIRE(ol >= 1, BM_ELEVEL, "output level");
   double cu_scale = q->scale;
-  const bm_masks* m = masks;
-  if (k == 1) {
-    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
-  } else {
-    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
-    if (!m) {
-      const uint64_t key = ((uint64_t)g->d << 32) | k;
-      auto it = ctx->mask_cache.find(key);
-      if (it == ctx->mask_cache.end())
-        it = ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(create_masks(ctx, g->d, k))).first;
-      m = it->second.get();
-    }
+  const bm_masks* m = nullptr;
+  if (k > 1) {
+    m = masks_for(ctx, g, masks, s.ql);
     REQUIRE(m->d == g->d && m->k == k, BM_EDIM, "masks do not match the gallery shape");
-    cu_scale = q->scale * m->scale / (double)c.primes[q->limbs - 1].q;
+    cu_scale = q->scale * m->scale / (double)c.primes[s.ql - 1].q;
   }
   REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
   std::unique_ptr<bm_result> r(new bm_result);
   r->ctx = ctx;
   r->d = g->d;
   r->k = k;
-  r->limbs = (uint32_t)ol;
+  r->limbs = (uint32_t)s.ol;
   r->groups = g->groups;
   r->n_templates = g->n_templates;
-  r->store = std::make_shared<DBuf>(&c, (size_t)g->groups * 2 * ol * c.N);
+  r->store = std::make_shared<DBuf>(&c, (size_t)g->groups * 2 * s.ol * c.N);
   if (c.use_graphs && !c.prof->on)
-    match_graph(c, evk, q, g, m, schedule, ol, r->p());
+    match_graph(c, evk, q, g, m, s, schedule, r->p());
   else
-    match_body(c, evk, q->buf.p(), q->limbs, g, m, schedule, ol, r->p());
-  r->scale = cu_scale * g->scale / (double)c.primes[g->limbs - 1].q;
+    match_body(c, evk, q->buf.p(), q->limbs, g, m, s, r->p());
+  r->scale = cu_scale * g->scale / (double)c.primes[s.t - 1].q;
   *out = r.release();
 }
 

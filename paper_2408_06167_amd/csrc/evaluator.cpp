@@ -263,18 +263,15 @@ void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* k
   // 2. ModUp every digit to the extended basis, then back to evaluation form
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
-  for (int j = 0; j < beta; ++j) {
-    kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs, j);
-    LimbMap m{};
-    const int lo = tb.d[j].src[0], hi = lo + tb.d[j].nsrc;
-    for (int t = 0; t < ext; ++t) {
-      if (t >= lo && t < hi) continue;
-      m.prime[m.n] = tb.ext_prime[t];
-      m.off[m.n] = m.ooff[m.n] = j * ext + t;
-      ++m.n;
-    }
-    kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
+  kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
+  LimbMap m{};
+  for (int i = 0; i < tb.npairs; ++i) {
+    const int t = tb.pair_t[i];
+    m.prime[m.n] = tb.ext_prime[t];
+    m.off[m.n] = m.ooff[m.n] = tb.pair_j[i] * ext + t;
+    ++m.n;
   }
+  kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
   // 3. key inner product over Q_l u P
   const size_t suw = (size_t)2 * ext * N;
   DBuf uw(&c, (size_t)B * suw);

@@ -4,6 +4,7 @@
 // generator g of Z_q^*, found by factoring q-1.  Twiddles are stored in
 // bit-reversed order (W[k] = psi^{brv(k)}) with Shoup companions
 // floor(W[k] 2^64 / q), so a butterfly needs one 64x64-high multiply.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -176,6 +177,17 @@ void build_context_tables(Ctx& c) {
     t.ext = l + c.K;
     if (t.ext > MAX_LIMBS || t.beta > MAX_DIGITS) BM_THROW(BM_EINVAL, "table limits exceeded");
     for (int s = 0; s < t.ext; ++s) t.ext_prime[s] = s < l ? s : c.pid_special(s - l);
+    t.npairs = 0;
+    for (int j = 0; j < t.beta; ++j) {
+      const int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, l);
+      for (int s = 0; s < t.ext; ++s) {
+        if (s >= lo && s < hi) continue;
+        if (t.npairs >= MAX_LIMBS) BM_THROW(BM_EINVAL, "too many ModUp targets for one launch");
+        t.pair_j[t.npairs] = (int8_t)j;
+        t.pair_t[t.npairs] = (int8_t)s;
+        ++t.npairs;
+      }
+    }
     for (int j = 0; j < t.beta; ++j) {
       ModUpDigit& dg = t.d[j];
       int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, l);

@@ -433,18 +433,21 @@ __global__ void k_reduce_int(const int64_t* src, size_t ss, u64* o, size_t so, L
 
 // (a0, a1) x (b0, b1) -> (a0 b0, a0 b1 + a1 b0, a1 b1); limb slot = chain limb.
 // Batch element z pairs operand a[z / a_div] with operand b[z % b_mod], so one
-// launch can cross several queries with several gallery groups.
-__global__ void k_tensor(const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
-                         u64* o, size_t so, int limbs, const PrimeC* P, int N, int accumulate) {
+// launch can cross several queries with several gallery groups.  a_cs and b_cs
+// are the component strides of the operands (they may hold more limbs than
+// the product uses: an exact level drop on the fly).
+__global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
+                         int b_mod, size_t b_cs, u64* o, size_t so, int limbs, const PrimeC* P, int N,
+                         int accumulate) {
   const int l = blockIdx.y;
   const PrimeC& pr = P[l];
   const u64 q = pr.q;
   const size_t bz = blockIdx.z;
   const size_t ln = (size_t)limbs * N;
   const u64* A0 = a + (bz / a_div) * sa + (size_t)l * N;
-  const u64* A1 = A0 + ln;
+  const u64* A1 = A0 + a_cs;
   const u64* B0 = b + (bz % b_mod) * sb + (size_t)l * N;
-  const u64* B1 = B0 + ln;
+  const u64* B1 = B0 + b_cs;
   u64* O0 = o + bz * so + (size_t)l * N;
   u64* O1 = O0 + ln;
   u64* O2 = O1 + ln;
@@ -483,20 +486,18 @@ __global__ void k_automorphism(const u64* in, size_t si, u64* out, size_t so, u6
   }
 }
 
-// ModUp of digit j at `limbs` chain limbs.  blockIdx.y enumerates the target
-// slots outside the digit; output slot t of y (coefficient domain).
+// ModUp of every digit at `limbs` chain limbs.  blockIdx.y enumerates the
+// (digit j, target slot t outside j) pairs; output y[j][t] (coefficient domain).
 __global__ void k_modup(const u64* xc, size_t sx, u64* y, size_t sy, const ModUpTable* T,
-                        int j, const PrimeC* P, int N) {
+                        const PrimeC* P, int N) {
   const ModUpTable& tb = *T;
+  const int j = tb.pair_j[blockIdx.y], t = tb.pair_t[blockIdx.y];
   const ModUpDigit& dg = tb.d[j];
-  const int lo = dg.src[0];
-  int t = blockIdx.y;
-  if (t >= lo) t += dg.nsrc;           // skip the digit's own slots
   const PrimeC& pt = P[tb.ext_prime[t]];
   const u64 qt = pt.q;
   const size_t bz = blockIdx.z;
   const u64* X = xc + bz * sx;
-  u64* Y = y + bz * sy + (size_t)t * N;
+  u64* Y = y + bz * sy + ((size_t)j * tb.ext + t) * N;
   EW_LOOP {
     u64 acc = 0;
     for (int a = 0; a < dg.nsrc; ++a) {
@@ -881,16 +882,17 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o,
   check_launch();
 }
 
-void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, const u64* b, size_t sb, int b_mod,
-            u64* o, size_t so, int B, int limbs, bool accumulate) {
+void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
+            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate) {
   if (a_div < 1 || b_mod < 1) BM_THROW(BM_EINVAL, "launch check: tensor batch divisors");
-  chk(a, (B - 1) / a_div + 1, sa, 0, (size_t)2 * limbs * c.N, "tensor a");
-  chk(b, std::min(B, b_mod), sb, 0, (size_t)2 * limbs * c.N, "tensor b");
+  if (limbs > c.L + 1 || a_cs < (size_t)limbs * c.N || b_cs < (size_t)limbs * c.N)
+    BM_THROW(BM_EINVAL, "launch check: tensor limbs");
+  chk(a, (B - 1) / a_div + 1, sa, 0, a_cs + (size_t)limbs * c.N, "tensor a");
+  chk(b, std::min(B, b_mod), sb, 0, b_cs + (size_t)limbs * c.N, "tensor b");
   chk(o, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
-  if (limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: tensor limbs");
   Prof pf(c, "tensor", 8.0 * c.N * B * limbs * (accumulate ? 10 : 7), 4.0 * c.N * B * limbs);
-  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, b, sb,
-                     b_mod, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
+  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, a_cs, b, sb, b_mod,
+         b_cs, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
   check_launch();
 }
 
@@ -906,16 +908,20 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
   check_launch();
 }
 
-void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs, int j) {
+void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs) {
+  if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: modup level");
   const ModUpTable& tb = c.h_modup[limbs];
-  const int targets = tb.ext - tb.d[j].nsrc;
-  const int ns = tb.d[j].nsrc;
-  if (limbs < 1 || limbs > c.L + 1 || j < 0 || j >= tb.beta) BM_THROW(BM_EINVAL, "launch check: modup digit");
   chk(xc, B, sx, 0, (size_t)limbs * c.N, "modup input");
-  chk(y + (size_t)j * tb.ext * c.N, B, sy, 0, (size_t)tb.ext * c.N, "modup output");
-  Prof pf(c, "modup", 8.0 * c.N * B * (ns + targets), (double)c.N * B * ns * (1 + targets));
-  LAUNCH(k_modup, ew_grid(c.N, targets, B), dim3(TPB), 0, c.stream, xc, sx,
-                     y + (size_t)j * tb.ext * c.N, sy, c.d_modup + limbs, j, c.d_primes, (int)c.N);
+  chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "modup output");
+  double ops = 0, rd = 0;
+  for (int j = 0; j < tb.beta; ++j) {
+    const int ns = tb.d[j].nsrc;
+    ops += (double)ns * (1 + tb.ext - ns);
+    rd += ns;
+  }
+  Prof pf(c, "modup", 8.0 * c.N * B * (rd + tb.npairs), ops * c.N * B);
+  LAUNCH(k_modup, ew_grid(c.N, tb.npairs, B), dim3(TPB), 0, c.stream, xc, sx, y, sy, c.d_modup + limbs,
+         c.d_primes, (int)c.N);
   check_launch();
 }
 

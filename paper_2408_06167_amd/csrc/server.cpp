@@ -75,18 +75,29 @@ struct bm_server {
   std::vector<double> latencies;
   uint64_t batches = 0, batched = 0;
 
+  // limbs of the products, the query as used, rotate-and-sum and output
+  void shape(const bm_gallery& g, int& t, int& ql, int& rot, int& ol) const {
+    const Ctx& c = ctx->c;
+    const bool lmin = (schedule & BM_LEVEL_MIN) != 0;
+    t = lmin ? std::min<int>(3, (int)g.limbs) : (int)g.limbs;
+    ql = g.k > 1 ? t + 1 : t;
+    ol = std::min<int>(c.out_limbs ? (int)c.out_limbs : t - 1, t - 1);
+    rot = lmin ? ol : t - 1;
+  }
+
   uint64_t estimate(const bm_gallery& g, int nq) const {
     const Ctx& c = ctx->c;
+    int t, ql, rot, ol;
+    shape(g, t, ql, rot, ol);
     const u64 N = c.N;
-    const u64 l = g.limbs, nl = l - 1;
+    const u64 l = (u64)t;
     const u64 beta = (l + c.alpha - 1) / c.alpha, ext = l + c.K;
     u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 8 : 64);
     const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
     const u64 pairs = std::min<u64>(per_q, g.groups) * nq;
     const u64 pair_words = (3 + 2 + 2 + 2 + 1 + 2 + 2) * l * N + (beta + 2) * ext * N;
-    const int ol = std::min<int>(c.out_limbs ? (int)c.out_limbs : (int)nl, (int)nl);
     const u64 out_words = (u64)nq * g.groups * 2 * ol * N;
-    const u64 cu_words = (u64)nq * g.k * 2 * l * N + (g.k > 1 ? g.k * 4 * (l + 1) * N : 0);
+    const u64 cu_words = (u64)nq * g.k * 2 * l * N + (g.k > 1 ? g.k * 4 * (u64)ql * N : 0);
     return 8 * (pairs * pair_words + out_words + cu_words);
   }
 
@@ -96,30 +107,34 @@ struct bm_server {
     const bm_gallery& g = *G.g;
     const int nq = (int)lane.reqs.size();
     const size_t N = c.N;
-    const int lg = (int)g.limbs, nl = lg - 1;
-    const int ol = std::min<int>(c.out_limbs ? (int)c.out_limbs : nl, nl);
-    const size_t part = 2 * (size_t)lg * N;
-    const size_t cu_stride = (size_t)g.k * part;
+    int t, ql, rot, ol;
+    shape(g, t, ql, rot, ol);
+    const size_t cu_stride = (size_t)g.k * 2 * t * N;
     DBuf cu(&c, (size_t)nq * cu_stride);
+    DBuf cut(g.k > 1 ? DBuf(&c, (size_t)2 * ql * N) : DBuf());
     double cu_scale = 0;
     for (int j = 0; j < nq; ++j) {
       const bm_ct& q = *lane.reqs[j].q;
-      if (g.k == 1) {
-        if ((int)q.limbs != lg) BM_THROW(BM_ELEVEL, "query level does not match the gallery");
-        HIP_OK(dev::memcpy_async(cu.p() + j * cu_stride, q.buf.p(), part * sizeof(u64),
-                              hipMemcpyDeviceToDevice, c.stream));
+      if ((int)q.limbs != (int)g.limbs + (g.k > 1 ? 1 : 0))
+        BM_THROW(BM_ELEVEL, "query level does not fit the gallery");
+      if (g.k == 1) {                     // exact drop straight into the batch buffer
+        ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, t, cu.p() + j * cu_stride);
         cu_scale = q.scale;
       } else {
-        if ((int)q.limbs != lg + 1) BM_THROW(BM_ELEVEL, "query must sit one level above the gallery");
-        bmx::expand(c, evk, q.buf.p(), (int)q.limbs, G.masks->pt.p(), g.d, g.k, cu.p() + j * cu_stride);
-        cu_scale = q.scale * G.masks->scale / (double)c.primes[q.limbs - 1].q;
+        const u64* qq = q.buf.p();
+        if ((int)q.limbs > ql) {
+          ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, ql, cut.p());
+          qq = cut.p();
+        }
+        bmx::expand(c, evk, qq, ql, G.masks->pt.p(), g.d, g.k, cu.p() + j * cu_stride);
+        cu_scale = q.scale * G.masks->scale / (double)c.primes[ql - 1].q;
       }
       if (cu_scale != g.scale) BM_THROW(BM_ESCALE, "query and gallery scales differ");
     }
     const size_t per = (size_t)g.groups * 2 * ol * N;
     auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
-    bmx::hec3_groups(c, evk, cu.p(), nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, lg, schedule, ol,
-                     store->p(), per);
+    bmx::hec3_groups(c, evk, cu.p(), nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, t,
+                     schedule & 0xff, rot, ol, store->p(), per);
     lane.results.clear();
     for (int j = 0; j < nq; ++j) {
       std::unique_ptr<bm_result> r(new bm_result);
@@ -129,7 +144,7 @@ struct bm_server {
       r->limbs = (uint32_t)ol;
       r->groups = g.groups;
       r->n_templates = g.n_templates;
-      r->scale = cu_scale * g.scale / (double)c.primes[lg - 1].q;
+      r->scale = cu_scale * g.scale / (double)c.primes[t - 1].q;
       r->store = store;
       r->off = (size_t)j * per;
       lane.results.push_back(std::move(r));
@@ -230,7 +245,8 @@ extern "C" {
 int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, uint32_t schedule,
                      bm_server** out) {
   if (!ctx || !evk || !out || hbm_budget_bytes == 0) return BM_EINVAL;
-  if (schedule != BM_S1 && schedule != BM_S2) return BM_EINVAL;
+  const uint32_t base = schedule & 0xff;
+  if ((base != BM_S1 && base != BM_S2) || (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN))) return BM_EINVAL;
   try {
     std::unique_ptr<bm_server> s(new bm_server);
     s->ctx = ctx;
@@ -256,8 +272,14 @@ int bm_server_add_gallery(bm_server* s, bm_gallery* g, uint32_t* gallery_id) {
   if (!s || !g || !gallery_id || g->ctx != s->ctx) return BM_EINVAL;
   bm_server::Gal entry;
   if (g->k > 1) {
-    int st = bm_masks_create(s->ctx, g->d, g->k, &entry.masks);
-    if (st != BM_OK) return st;
+    int t, ql, rot, ol;
+    s->shape(*g, t, ql, rot, ol);
+    try {
+      entry.masks = bmx_create_masks(s->ctx, g->d, g->k, (uint32_t)ql);
+    } catch (const Error& e) {
+      s->ctx->c.last_error = e.msg;
+      return e.code;
+    }
   }
   entry.g.reset(g);
   std::lock_guard<std::mutex> lk(s->mu);

@@ -48,8 +48,8 @@ def flow(preset, shapes, n_templates):
             for h in bm.bm_expand(ctx, evk, q, m, k):
                 bm.bm_ct_free(h)
             bm.bm_masks_free(m)
-        for s in (1, 2):
-            bm.bm_ctx_set_graphs(ctx, s == 2)
+        for s in (1, 2, 1 | bm.BM_LEVEL_MIN, 2 | bm.BM_LEVEL_MIN):
+            bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
             for chunk in (0, 1, 3):
                 bm.bm_ctx_set_group_chunk(ctx, chunk)
                 r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
@@ -62,7 +62,7 @@ def flow(preset, shapes, n_templates):
         for r in rs:
             bm.bm_result_free(r)
         bm.bm_ctx_set_group_chunk(ctx, 0)
-        srv = bm.bm_server_create(ctx, evk, 64 << 30, 2)
+        srv = bm.bm_server_create(ctx, evk, 64 << 30, 2 | (bm.BM_LEVEL_MIN if k > 1 else 0))
         gid = bm.bm_server_add_gallery(srv, g)
         tickets = [bm.bm_server_submit(srv, gid, bm.bm_encrypt_query(ctx, pk, X[i], 1, 100 + i))
                    for i in range(5)]

@@ -28,7 +28,8 @@ def words_of(bm, ctx, res, N):
     return [bm.bm_result_export(ctx, res, g, N)[0] for g in range(G)]
 
 
-@pytest.mark.parametrize("preset,d,k,schedule", [(1, 16, 1, 1), (1, 16, 4, 2), (2, 128, 2, 2)])
+@pytest.mark.parametrize("preset,d,k,schedule", [(1, 16, 1, 1), (1, 16, 4, 2), (2, 128, 2, 2),
+                                                 (2, 128, 4, 0x102)])
 def test_graph_replay_equals_eager(bm, preset, d, k, schedule):
     ctx = lib_ctx(preset)
     sk, pk, evk = keys(preset)
@@ -90,8 +91,8 @@ def test_match_batch_equals_individual(bm):
         bm.bm_gallery_free(g)
 
 
-@pytest.mark.parametrize("preset", [1, 2])
-def test_server_alone_equals_mix(bm, preset):
+@pytest.mark.parametrize("preset,schedule", [(1, 2), (2, 2), (2, 0x102)])
+def test_server_alone_equals_mix(bm, preset, schedule):
     """A query served alone and the same query served among others give the
     same words, equal to the plain per-query match."""
     ctx = lib_ctx(preset)
@@ -99,7 +100,7 @@ def test_server_alone_equals_mix(bm, preset):
     p = bm.bm_params_preset(preset)
     rng = np.random.default_rng(13)
     shapes = [(16, 1, 400), (16, 2, 900)] if preset == 1 else [(128, 1, 1000), (128, 4, 3000)]
-    srv = bm.bm_server_create(ctx, evk, 64 << 30, 2)
+    srv = bm.bm_server_create(ctx, evk, 64 << 30, schedule)
     gids, gals, Xs = [], [], []
     ref_gals = []
     for d, k, n in shapes:
@@ -134,7 +135,7 @@ def test_server_alone_equals_mix(bm, preset):
         bm.bm_result_free(r)
     # and the plain path gives the same words
     q_plain = bm.bm_encrypt_query(ctx, pk, probe_vec, SEED, 99)
-    plain = bm.bm_match(ctx, evk, q_plain, ref_gals[1], None, schedule=2)
+    plain = bm.bm_match(ctx, evk, q_plain, ref_gals[1], None, schedule=schedule)
     for a, b in zip(words_of(bm, ctx, plain, p.N), alone_w):
         assert_words_equal(a, b, "served vs plain")
     st = bm.bm_server_stats(srv)

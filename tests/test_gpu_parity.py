@@ -236,7 +236,7 @@ def test_expand_bit_exact(bm, d, k):
 
 
 @pytest.mark.parametrize("d,k,schedule", [(16, 1, 1), (16, 2, 1), (16, 2, 2), (16, 4, 1),
-                                          (16, 4, 2), (8, 8, 2)])
+                                          (16, 4, 2), (8, 8, 2), (16, 1, 0x101), (16, 4, 0x102)])
 def test_match_small_ring_bit_exact(bm, d, k, schedule):
     """N = 2^12: a two-group gallery with a ragged last group."""
     P, okeys, ctx, sk, pk, evk = setup(1)
@@ -252,7 +252,8 @@ def test_match_small_ring_bit_exact(bm, d, k, schedule):
     cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
     gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 1000)
     masks, mscale = obm.mask_coeffs(P, d, k, len(P.q)) if k > 1 else (None, None)
-    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule, masks, mscale)
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale,
+                     level_min=bool(schedule & 0x100))
     cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
     gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
     lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
@@ -296,7 +297,8 @@ def test_match_library_encryption_end_to_end(bm):
     assert bm.bm_top1(scores)[0] == w["known"]
 
 
-@pytest.mark.parametrize("k,schedule", [(1, 1), (4, 1), (4, 2), (16, 2)])
+@pytest.mark.parametrize("k,schedule", [(1, 1), (4, 1), (4, 2), (16, 2), (1, 0x101), (4, 0x102),
+                                        (8, 0x102)])
 def test_match_face_scale_sampled(bm, k, schedule):
     """N = 2^16, 6,144 x 128-dim gallery: the full match runs on the GPU; the
     oracle recomputes two sampled groups (first and last) word for word."""
@@ -311,15 +313,17 @@ def test_match_face_scale_sampled(bm, k, schedule):
     cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
     gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 5000)
     G = len(gal_o)
-    masks, mscale = obm.mask_coeffs(P, d, k, len(P.q)) if k > 1 else (None, None)
+    level_min = bool(schedule & 0x100)
+    ql = obm.level_min_shape(P, k, lg)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
     cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
     gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, X.shape[0])
     lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
     log("library match")
     res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
     log("oracle match on sampled groups")
-    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule, masks, mscale, out_limbs=2,
-                     groups=[0, G - 1])
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
+                     groups=[0, G - 1], level_min=level_min)
     for g, o in want.items():
         got, sc = bm.bm_result_export(ctx, res, g, P.N)
         assert sc == o.scale

@@ -124,6 +124,33 @@ def test_encrypted_match_equals_slot_sim(tiny_setup, d, k, schedule):
     assert np.max(np.abs(scores - X @ q)) < 1e-8
 
 
+@pytest.mark.parametrize("d,k,schedule", [(8, 1, bm.S1), (8, 4, bm.S2), (16, 4, bm.S1)])
+def test_minimum_level_match_equals_slot_sim(tiny_setup, d, k, schedule):
+    """Minimum-level schedule: products at 3 limbs, query cut to 4 limbs before
+    Alg. 1 (masks at scale q_3), rotate-and-sum at the 2 output limbs."""
+    P, keys = tiny_setup
+    rng = np.random.default_rng(d + 31 * k + schedule)
+    c, T = bm.layout(P, d, k)
+    R = 2 * T - 3
+    X = rng.standard_normal((R, d)) / np.sqrt(d)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    qslots = bm.pack_query(P, q, d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(qslots, P.scale, P.N), len(P.q), P.scale, 3, 1)
+    lg = bm.gallery_limbs(P, k)
+    gal_slots = bm.pack_gallery(P, X, d, k)
+    gallery = [[ckks.encrypt(P, keys.pk, ckks.encode(v, P.scale, P.N), lg, P.scale, 3, 300 + 10 * g + i)
+                for i, v in enumerate(parts)] for g, parts in enumerate(gal_slots)]
+    t, ql = bm.level_min_shape(P, k, lg)
+    assert t == 3 and ql == (4 if k > 1 else 3)
+    masks, mscale = bm.mask_coeffs(P, d, k, ql)
+    outs = bm.match(P, keys, cq, gallery, d, k, schedule, masks, mscale, out_limbs=2, level_min=True)
+    sim_u = slot_sim.expand(qslots, d, k)
+    for g, o in outs.items():
+        assert o.limbs == 2
+        got = ckks.decrypt_decode(P, keys.s, o)
+        assert np.max(np.abs(got - slot_sim.hec3(sim_u, gal_slots[g], d, k))) < 1e-8
+
+
 def test_full_vector_inner_product_special_case(tiny_setup):
     """k = 1 and d = n: one template fills the ciphertext and the rotate-and-sum
     is the textbook sum of all slots."""
