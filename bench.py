@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
+    ap.add_argument("--workload", default="face", choices=["face", "fingerprint", "batch", "serve"],
+                    help="face: 6,144 x 128-dim (default); fingerprint: 1,048,576 x 16-dim; "
+                         "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals")
+    ap.add_argument("--scale", type=float, default=1.0, help="gallery size factor for batch/serve")
+    ap.add_argument("--rates", default="5,10,20,40", help="serve: arrival rates (queries/s)")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")
     return ap.parse_args()
 
 
@@ -49,6 +55,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload != "face":
+        import bench_workloads
+        bench_workloads.run(args)
+        return
     import torch
     import paper_2408_06167_amd as bm
     from workloads import face_gallery

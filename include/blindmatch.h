@@ -253,11 +253,19 @@ int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);
 /* Many (query, gallery) pairs of possibly different d, k and size in one
- * call: pairs of equal shape share batched launches.  outs[i] receives the
- * result of pair i.  Results are bit-identical to per-pair bm_match. */
+ * call: the pairs that share a gallery (up to 16 at a time) run as one
+ * batched Alg. 2 pass in which every launch covers query x group pairs.
+ * outs[i] receives the result of pair i.  Results are bit-identical to
+ * per-pair bm_match. */
 int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
                    const bm_gallery *const *gs, size_t n_pairs, uint32_t schedule,
                    uint32_t out_limbs, void *stream, bm_result **outs);
+/* Autotuner of the result-invariant knob `group_chunk` (query x group pairs
+ * per batched pass): times bm_match of (q, g) for chunk sizes 1..64 with HIP
+ * events on the context's stream, keeps the fastest in the context and
+ * returns it with its time per match.  Bits never depend on the choice. */
+int bm_autotune(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g, uint32_t schedule,
+                uint32_t *best_chunk, double *best_ms);
 int bm_result_info(const bm_result *r, uint64_t *groups, uint32_t *limbs, double *scale);
 /* Coefficient-domain words[2][limbs][N] of group `group`. */
 int bm_result_export(const bm_result *r, uint64_t group, uint64_t *words, size_t n_words);
@@ -292,6 +300,8 @@ int bm_server_drain(bm_server *s);
 /* Per-request latency statistics in ms (completion minus submission). */
 int bm_server_stats(bm_server *s, uint64_t *completed, double *p50_ms, double *p99_ms,
                     double *mean_batch);
+/* Clear the latency and batch statistics. */
+int bm_server_reset_stats(bm_server *s);
 void bm_server_free(bm_server *s);
 
 #ifdef __cplusplus

@@ -94,6 +94,7 @@ _SIGS = {
     "bm_expand": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "bm_match": (ctypes.c_int, [_P, _P, _P, _P, _P, _u32, _u32, _P, _PP]),
     "bm_match_batch": (ctypes.c_int, [_P, _P, _P, _P, _sz, _u32, _u32, _P, _P]),
+    "bm_autotune": (ctypes.c_int, [_P, _P, _P, _P, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_dbl)]),
     "bm_result_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                       ctypes.POINTER(_dbl)]),
     "bm_result_export": (ctypes.c_int, [_P, _u64, _P, _sz]),
@@ -107,6 +108,7 @@ _SIGS = {
     "bm_server_drain": (ctypes.c_int, [_P]),
     "bm_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_dbl),
                                        ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "bm_server_reset_stats": (ctypes.c_int, [_P]),
     "bm_server_free": (None, [_P]),
 }
 
@@ -435,6 +437,14 @@ def bm_match_batch(ctx, evk, queries, galleries, schedule=BM_S1, out_limbs=0, st
     return [ctypes.c_void_p(outs[i]) for i in range(n)]
 
 
+def bm_autotune(ctx, evk, q, gallery, schedule=BM_S2):
+    """(best group_chunk, ms per match); the context keeps the best chunk."""
+    c, ms = _u32(), _dbl()
+    _check(lib().bm_autotune(ctx, evk, q, gallery, int(schedule), ctypes.byref(c), ctypes.byref(ms)),
+           "bm_autotune", ctx)
+    return int(c.value), float(ms.value)
+
+
 def bm_result_info(r):
     G, l, s = _u64(), _u32(), _dbl()
     _check(lib().bm_result_info(r, ctypes.byref(G), ctypes.byref(l), ctypes.byref(s)), "bm_result_info")
@@ -498,6 +508,10 @@ def bm_server_stats(server):
     _check(lib().bm_server_stats(server, ctypes.byref(n), ctypes.byref(p50), ctypes.byref(p99),
                                  ctypes.byref(mb)), "bm_server_stats")
     return dict(completed=int(n.value), p50_ms=p50.value, p99_ms=p99.value, mean_batch=mb.value)
+
+
+def bm_server_reset_stats(server):
+    _check(lib().bm_server_reset_stats(server), "bm_server_reset_stats")
 
 
 def bm_server_free(server):

@@ -85,7 +85,7 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
     gks[t] = galois_key(evk, gel[t]);
   }
   // batch = (query, group) pairs; `chunk` bounds the pairs per pass
-  u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 8 : 64);
+  u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 16 : 64);
   const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
   const u64 Bg_max = std::min<u64>(per_q, G);
   const u64 Bmax = Bg_max * nq;

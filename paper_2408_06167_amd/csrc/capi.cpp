@@ -903,19 +903,130 @@ int bm_match(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g
   });
 }
 
+// Several queries against one gallery in one batched Alg. 2 pass: query x
+// group pairs share every launch.  Bit-identical to per-query bm_match.
+static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, int nq,
+                        const bm_gallery* g, uint32_t schedule, uint32_t out_limbs, bm_result** outs) {
+  Ctx& c = ctx->c;
+  const MatchShape s = match_shape(c, qs[0], g, schedule, out_limbs);
+  const uint32_t k = g->k;
+  const size_t N = c.N;
+  const bm_masks* m = k > 1 ? masks_for(ctx, g, nullptr, s.ql) : nullptr;
+  const size_t cu_stride = (size_t)k * 2 * s.t * N;
+  DBuf cu(&c, (size_t)nq * cu_stride);
+  DBuf cut(k > 1 ? DBuf(&c, (size_t)2 * s.ql * N) : DBuf());
+  double cu_scale = 0;
+  for (int j = 0; j < nq; ++j) {
+    const bm_ct* q = qs[j];
+    REQUIRE(q->comps == 2 && q->limbs == qs[0]->limbs && q->scale == qs[0]->scale, BM_ELEVEL,
+            "queries of one gallery differ in level or scale");
+    if (k == 1) {
+      ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.t, cu.p() + j * cu_stride);
+      cu_scale = q->scale;
+    } else {
+      const u64* qq = q->buf.p();
+      if ((int)q->limbs > s.ql) {
+        ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.ql, cut.p());
+        qq = cut.p();
+      }
+      bmx::expand(c, evk, qq, s.ql, m->pt.p(), g->d, k, cu.p() + j * cu_stride);
+      cu_scale = q->scale * m->scale / (double)c.primes[s.ql - 1].q;
+    }
+  }
+  REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
+  const size_t per = (size_t)g->groups * 2 * s.ol * N;
+  auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
+  bmx::hec3_groups(c, evk, cu.p(), nq, cu_stride, g->d, k, g->buf.p(), g->groups, (int)g->limbs, s.t,
+                   s.sched, s.rot, s.ol, store->p(), per);
+  for (int j = 0; j < nq; ++j) {
+    std::unique_ptr<bm_result> r(new bm_result);
+    r->ctx = ctx;
+    r->d = g->d;
+    r->k = k;
+    r->limbs = (uint32_t)s.ol;
+    r->groups = g->groups;
+    r->n_templates = g->n_templates;
+    r->scale = cu_scale * g->scale / (double)c.primes[s.t - 1].q;
+    r->store = store;
+    r->off = (size_t)j * per;
+    outs[j] = r.release();
+  }
+}
+
 int bm_match_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
                    size_t n_pairs, uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** outs) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && qs && gs && outs, BM_EINVAL, "NULL argument");
     ctx->c.use_stream(stream);
+    for (size_t i = 0; i < n_pairs; ++i) REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
+    // pairs that share a gallery (and query level) go through one batched pass
     std::vector<std::unique_ptr<bm_result>> res(n_pairs);
+    std::vector<bool> done(n_pairs, false);
+    const size_t max_q = 16;
     for (size_t i = 0; i < n_pairs; ++i) {
-      REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
-      bm_result* r = nullptr;
-      match_one(ctx, evk, qs[i], gs[i], nullptr, schedule, out_limbs, &r);
-      res[i].reset(r);
+      if (done[i]) continue;
+      std::vector<size_t> idx;
+      for (size_t j = i; j < n_pairs && idx.size() < max_q; ++j)
+        if (!done[j] && gs[j] == gs[i] && qs[j]->limbs == qs[i]->limbs) idx.push_back(j);
+      std::vector<const bm_ct*> qv;
+      for (size_t j : idx) qv.push_back(qs[j]);
+      std::vector<bm_result*> rv(idx.size(), nullptr);
+      match_multi(ctx, evk, qv.data(), (int)qv.size(), gs[i], schedule, out_limbs, rv.data());
+      for (size_t a = 0; a < idx.size(); ++a) {
+        res[idx[a]].reset(rv[a]);
+        done[idx[a]] = true;
+      }
     }
     for (size_t i = 0; i < n_pairs; ++i) outs[i] = res[i].release();
+  });
+}
+
+int bm_autotune(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g, uint32_t schedule,
+                uint32_t* best_chunk, double* best_ms) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && q && g, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const bool graphs = c.use_graphs;
+    const int saved = c.group_chunk;
+    hipEvent_t a, b;
+    HIP_OK(dev::event_create(&a, true));
+    HIP_OK(dev::event_create(&b, true));
+    double best = 1e30;
+    int pick = saved;
+    try {
+      for (int chunk : {1, 2, 4, 8, 16, 32, 64}) {
+        if (chunk > 1 && (u64)(chunk / 2) >= g->groups) break;   // larger chunks change nothing
+        c.group_chunk = chunk;
+        bm_result* r = nullptr;
+        match_one(ctx, evk, q, g, nullptr, schedule, 0, &r);    // warm-up (and capture)
+        bm_result_free(r);
+        HIP_OK(dev::event_record(a, c.stream));
+        for (int rep = 0; rep < 3; ++rep) {
+          match_one(ctx, evk, q, g, nullptr, schedule, 0, &r);
+          bm_result_free(r);
+        }
+        HIP_OK(dev::event_record(b, c.stream));
+        HIP_OK(dev::event_sync(b));
+        float ms = 0;
+        HIP_OK(dev::event_elapsed(&ms, a, b));
+        if (ms / 3 < best) {
+          best = ms / 3;
+          pick = chunk;
+        }
+      }
+    } catch (...) {
+      c.group_chunk = saved;
+      (void)dev::event_destroy(a);
+      (void)dev::event_destroy(b);
+      throw;
+    }
+    (void)dev::event_destroy(a);
+    (void)dev::event_destroy(b);
+    c.group_chunk = pick;
+    c.use_graphs = graphs;
+    if (best_chunk) *best_chunk = (uint32_t)pick;
+    if (best_ms) *best_ms = best;
   });
 }
 

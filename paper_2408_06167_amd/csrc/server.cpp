@@ -92,7 +92,7 @@ struct bm_server {
     const u64 N = c.N;
     const u64 l = (u64)t;
     const u64 beta = (l + c.alpha - 1) / c.alpha, ext = l + c.K;
-    u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 8 : 64);
+    u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 16 : 64);
     const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
     const u64 pairs = std::min<u64>(per_q, g.groups) * nq;
     const u64 pair_words = (3 + 2 + 2 + 2 + 1 + 2 + 2) * l * N + (beta + 2) * ext * N;
@@ -341,6 +341,14 @@ int bm_server_stats(bm_server* s, uint64_t* completed, double* p50_ms, double* p
   if (p50_ms) *p50_ms = pct(0.50);
   if (p99_ms) *p99_ms = pct(0.99);
   if (mean_batch) *mean_batch = s->batches ? (double)s->batched / (double)s->batches : 0.0;
+  return BM_OK;
+}
+
+int bm_server_reset_stats(bm_server* s) {
+  if (!s) return BM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->latencies.clear();
+  s->batches = s->batched = 0;
   return BM_OK;
 }
 

@@ -58,7 +58,11 @@ def flow(preset, shapes, n_templates):
                 bm.bm_result_export(ctx, r, G - 1, N)
                 bm.bm_result_free(r)
         bm.bm_ctx_set_graphs(ctx, False)
-        rs = bm.bm_match_batch(ctx, evk, [q, q], [g, g], schedule=2)
+        rs = bm.bm_match_batch(ctx, evk, [q, q, q], [g, g, g], schedule=2)
+        for r in rs:
+            bm.bm_result_free(r)
+        rs = bm.bm_match_batch(ctx, evk, [q, q], [g, g], schedule=2 | bm.BM_LEVEL_MIN)
+        bm.bm_autotune(ctx, evk, q, g, 2)
         for r in rs:
             bm.bm_result_free(r)
         bm.bm_ctx_set_group_chunk(ctx, 0)

@@ -73,12 +73,17 @@ def test_match_batch_equals_individual(bm):
     p = bm.bm_params_preset(1)
     rng = np.random.default_rng(11)
     pairs = []
+    gals = []
     for d, k, n in [(16, 1, 100), (16, 2, 700), (8, 8, 50), (16, 4, 1300), (16, 1, 129)]:
         X = normalize(rng.standard_normal((n, d)))
         g = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 1000 + n)
-        q = bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(d)), SEED, n)
-        pairs.append((q, g, X))
-    for schedule in (1, 2):
+        gals.append(g)
+        for rep in range(3 if k in (1, 4) else 1):     # several queries share a gallery
+            q = bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(d)), SEED, 10 * n + rep)
+            pairs.append((q, g, X))
+    order = list(rng.permutation(len(pairs)))
+    pairs = [pairs[i] for i in order]
+    for schedule in (1, 2, 0x102):
         outs = bm.bm_match_batch(ctx, evk, [q for q, _, _ in pairs], [g for _, g, _ in pairs], schedule=schedule)
         for (q, g, X), r in zip(pairs, outs):
             single = bm.bm_match(ctx, evk, q, g, None, schedule=schedule)
@@ -86,8 +91,9 @@ def test_match_batch_equals_individual(bm):
                 assert_words_equal(a, b, "batched vs single")
             bm.bm_result_free(single)
             bm.bm_result_free(r)
-    for q, g, _ in pairs:
+    for q, _, _ in pairs:
         bm.bm_ct_free(q)
+    for g in gals:
         bm.bm_gallery_free(g)
 
 
