@@ -7,6 +7,9 @@ batch:       64 queries of dimension 16, 64, 128, 512 (16 each) against two
              galleries of uneven size per dimension (128 pairs), matched
              (a) pair by pair with the plain path and (b) with bm_match_batch,
              which batches all queries of a gallery into each launch.
+copy:        a plain device-to-device copy of 1 GiB, timed: the HBM bandwidth a
+             copy reaches, and the known-size dispatch that scales the
+             FETCH_SIZE / WRITE_SIZE counters of the other kernels to bytes.
 serve:       the continuous-batching server over 16 resident galleries (twelve
              128-dim, four 16-dim), Poisson arrivals at several rates, a 3:1
              mix of 128-dim to 16-dim queries; p50/p99 latency and admitted
@@ -34,7 +37,7 @@ def _setup(bm, shapes, seed=0xB11D):
 
 def run(args):
     import paper_2408_06167_amd as bm
-    {"fingerprint": fingerprint, "batch": batch, "serve": serve}[args.workload](bm, args)
+    {"fingerprint": fingerprint, "batch": batch, "serve": serve, "copy": copy}[args.workload](bm, args)
 
 
 def fingerprint(bm, args):
@@ -215,3 +218,27 @@ def serve(bm, args):
                                  "Poisson arrivals, 3:1 mix" % args.scale, "templates": sum(sizes.values()),
                                  "schedule": "S2+levelmin", "by_rate": out,
                                  "plain_ms_per_query": plain}}), flush=True)
+
+
+def copy(bm, args):
+    """1 GiB device copy: read 1 GiB, write 1 GiB per dispatch."""
+    import torch
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(max(args.warmup, 1)):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        dst.copy_(src)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    assert bool((dst[:: 1 << 20] == 1).all())
+    print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": round(2 * nbytes / ms / 1e6, 1),
+                      "unit": "GB/s", "bytes_read_per_dispatch": nbytes, "bytes_written_per_dispatch": nbytes,
+                      "ms_median": round(ms, 4), "dispatches": args.steps}))

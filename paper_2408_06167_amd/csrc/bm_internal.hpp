@@ -167,9 +167,10 @@ class DevicePool {
 
 struct Ctx;
 
-// Optional per-kernel timing: when on, every launch is bracketed by two HIP
-// events on the launch stream and charged with its algorithmic bytes and
-// operations (counted by the launcher from the shapes it was given).
+// Optional per-kernel timing: when on, every kernel is launched with a pair of
+// HIP events that the runtime stamps with the kernel's own start and end, and
+// is charged with its algorithmic bytes and operations (counted by the
+// launcher from the shapes it was given).
 class Profiler {
  public:
   struct Entry {
@@ -177,8 +178,8 @@ class Profiler {
     double ms = 0, bytes = 0, ops = 0;
   };
   bool on = false;
-  void begin(hipStream_t s, const char* name, double bytes, double ops);
-  void end(hipStream_t s);
+  // events for the next launch, charged to `name`
+  std::pair<hipEvent_t, hipEvent_t> begin(const char* name, double bytes, double ops);
   void collect();                       // waits for pending events, accumulates
   void reset();
   std::map<std::string, Entry> entries;

@@ -194,16 +194,11 @@ hipEvent_t Profiler::take() {
   return e;
 }
 
-void Profiler::begin(hipStream_t s, const char* name, double bytes, double ops) {
+std::pair<hipEvent_t, hipEvent_t> Profiler::begin(const char* name, double bytes, double ops) {
   std::lock_guard<std::mutex> g(mu_);
   Pending p{name, take(), take(), bytes, ops};
-  HIP_OK(dev::event_record(p.a, s));
   pending_.push_back(p);
-}
-
-void Profiler::end(hipStream_t s) {
-  std::lock_guard<std::mutex> g(mu_);
-  HIP_OK(dev::event_record(pending_.back().b, s));
+  return {p.a, p.b};
 }
 
 void Profiler::collect() {

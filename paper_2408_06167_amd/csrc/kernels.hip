@@ -11,6 +11,8 @@
 // from scalar loads) and blockIdx.z the polynomial of the batch.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "bm_internal.hpp"
 
 namespace bm {
@@ -47,9 +49,16 @@ __device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const PrimeC& p) {
 __device__ __forceinline__ u64 reduce64(u64 a, const PrimeC& p) { return mul_shoup(a, 1, p.pad[0], p.q); }
 
 // kernel launch; skipped (checks only) in dry-run mode
-#define LAUNCH(...)                              \
-  do {                                           \
-    if (!dev::dry()) hipLaunchKernelGGL(__VA_ARGS__); \
+// Every launch sits in the scope of a Prof named pf.  With profiling on, the
+// kernel is launched with its own start/stop events, which the runtime stamps
+// with the kernel's execution interval (dispatch latency excluded).
+#define LAUNCH(F, G, BL, L, S, ...)                                                   \
+  do {                                                                                \
+    if (dev::dry()) break;                                                            \
+    if (pf.on)                                                                        \
+      hipExtLaunchKernelGGL(F, G, BL, L, S, pf.ev.first, pf.ev.second, 0, __VA_ARGS__); \
+    else                                                                              \
+      hipLaunchKernelGGL(F, G, BL, L, S, __VA_ARGS__);                                \
   } while (0)
 
 constexpr int TPB = 256;        // threads per block of every kernel here
@@ -662,13 +671,10 @@ inline void chk_map(const Ctx& c, const void* p, int B, size_t st, const LimbMap
 
 // Times one launch when the context's profiler is on.
 struct Prof {
-  const Ctx& c;
   bool on;
-  Prof(const Ctx& c_, const char* name, double bytes, double ops) : c(c_), on(c_.prof && c_.prof->on) {
-    if (on) c.prof->begin(c.stream, name, bytes, ops);
-  }
-  ~Prof() {
-    if (on) c.prof->end(c.stream);
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  Prof(const Ctx& c, const char* name, double bytes, double ops) : on(c.prof && c.prof->on) {
+    if (on) ev = c.prof->begin(name, bytes, ops);
   }
 };
 
@@ -715,7 +721,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   if (logn == 12) {
     chk_map(c, in, B, in_stride, m, "ntt input");
     chk_map(c, out, B, out_stride, m, "ntt output", true);
-    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 12);
+    Prof pf(c, inverse ? "ntt_inv_one" : "ntt_fwd_one", 16.0 * elems, 0.5 * elems * 12);
     const size_t lds = (size_t)(4096 + 256 + 1) * sizeof(u64);
     const dim3 grid(1, (unsigned)m.n, (unsigned)B);
     if (inverse)
@@ -735,7 +741,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   auto col = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm, int last) {
     chk_map(c, src, B, ss, mm, "ntt column pass input");
     chk_map(c, dst, B, ds, mm, "ntt column pass output", true);
-    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, inverse ? "ntt_inv_col" : "ntt_fwd_col", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
              c.d_primes, tw, tws, logn, 0, last, B);
@@ -747,7 +753,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   auto row = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm) {
     chk_map(c, src, B, ss, mm, "ntt row pass input");
     chk_map(c, dst, B, ds, mm, "ntt row pass output", true);
-    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, inverse ? "ntt_inv_row" : "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vr), lds_row, c.stream, src, ss, dst, ds,
              mm, c.d_primes, tw, tws, logn, 8, 0, B);
