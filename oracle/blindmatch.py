@@ -20,6 +20,14 @@ N_in = k the number of parts, c = m / N_in the chunk length.  Slots are
   * gallery group g, part i, slot s holds x_{g T + floor(s/c)}[i c + s mod c],
     T = n / c templates per group, zeros past the last template; the score of
     template g T + b is read at slot b c of group g's output.
+  * compression method (Sec. 3.4, Prop. 3): every group output is multiplied
+    by a mask with ones at the score slots b c (encoded at scale q_top of the
+    output, so the rescale returns the scale to Delta) and rescaled; then the
+    groups of each block of c consecutive groups are merged by halving,
+    x_j += Rot(x_{j+H}, -H) for H = P/2, ..., 1 (P the power of two >= the
+    block size), so group g lands at slot b c + (g mod c) of compressed
+    ciphertext floor(g / c).  One Mul(P), one Rot and one Add per group as
+    Prop. 3 counts them; the merge order is this build's reading.
   * minimum-level schedule (an option of this build): every ciphertext is
     first cut, by exact limb drops, to the fewest limbs the rest of the
     computation needs -- the products at EVAL_LIMBS = 3 chain limbs, the
@@ -153,27 +161,71 @@ def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None):
 EVAL_LIMBS = 3
 
 
-def level_min_shape(params, k, gallery_limbs):
+def level_min_shape(params, k, gallery_limbs, compress=False):
     """Limbs of the products and of the expanded query under the minimum-level
-    schedule, never above what the inputs carry."""
-    t = min(EVAL_LIMBS, gallery_limbs)
+    schedule, never above what the inputs carry; compression needs one level
+    more."""
+    t = min(EVAL_LIMBS + (1 if compress else 0), gallery_limbs)
     return t, (t + 1 if k > 1 else t)
 
 
+def compress_mask_coeffs(params, d, k, limbs):
+    """Integer plaintext of the score mask (ones at slots b c) at scale
+    q_{limbs-1}, the top prime of the ciphertexts it multiplies."""
+    c, _ = layout(params, d, k)
+    s = np.arange(params.n)
+    qtop = params.q[limbs - 1]
+    return ckks.encode((s % c == 0).astype(np.float64), float(qtop), params.N), float(qtop)
+
+
+def compress(params, keys, outs, d, k, mask, mask_scale):
+    """Compression method: list over groups of HE-C^3 outputs -> list over
+    blocks of c groups of one ciphertext each (layout in the module notes)."""
+    c, _ = layout(params, d, k)
+    y = [ckks.rescale(params, ckks.pmul(params, o, mask, mask_scale)) for o in outs]
+    res = []
+    for o in range(0, len(y), c):
+        blk = y[o:o + c]
+        r = len(blk)
+        half = 1
+        while 2 * half < r:
+            half *= 2
+        while half >= 1 and r > 1:
+            for j in range(half):
+                if j + half < r:
+                    blk[j] = ckks.hadd(params, blk[j], ckks.rotate(params, blk[j + half], -half, keys.gks))
+            half //= 2
+        res.append(blk[0])
+    return res
+
+
+def compress_rotations(params, d, k):
+    """Rotation amounts the compression merges use: -2^t for t < log2(c)."""
+    c, _ = layout(params, d, k)
+    return [-(1 << t) for t in range(log2_exact(c))]
+
+
 def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None,
-          out_limbs=None, groups=None, level_min=False):
+          out_limbs=None, groups=None, level_min=False, compress_mask=None):
     """Whole server side: expansion (k > 1) then HE-C^3 per gallery group.
     `gallery` is a list over groups of k ciphertexts.  Optionally only the
     listed `groups` are evaluated (sampled parity at large sizes).  With
     level_min every input is first cut to the minimum level (see above); the
-    masks must then be encoded at scale q_{limbs of the cut query - 1}."""
+    masks must then be encoded at scale q_{limbs of the cut query - 1}.
+    With compress_mask = (plaintext, scale) the group outputs are compressed
+    (all groups; the mask encoded at scale q_{rot limbs - 1}) and a list of
+    compressed ciphertexts is returned instead of the dict over groups."""
+    comp = compress_mask is not None
+    if comp and groups is not None:
+        raise ValueError("compression needs every group")
     idx = range(len(gallery)) if groups is None else groups
     rot_limbs = None
     if level_min:
-        t, ql = level_min_shape(params, k, gallery[0][0].limbs)
+        t, ql = level_min_shape(params, k, gallery[0][0].limbs, comp)
         cq = ckks.drop_limbs(cq, ql)
         gallery = {g: [ckks.drop_limbs(x, t) for x in gallery[g]] for g in idx}
-        rot_limbs = min(out_limbs, t - 1) if out_limbs else t - 1
+        extra = 1 if comp else 0
+        rot_limbs = min(out_limbs + extra, t - 1) if out_limbs else t - 1
     if k == 1:
         cu = [cq]
     else:
@@ -181,10 +233,23 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
     outs = {}
     for g in idx:
         o = hec3(params, keys, cu, gallery[g], d, k, schedule, rot_limbs)
-        if out_limbs is not None and out_limbs < o.limbs:
+        if not comp and out_limbs is not None and out_limbs < o.limbs:
             o = ckks.drop_limbs(o, out_limbs)
         outs[g] = o
-    return outs
+    if not comp:
+        return outs
+    res = compress(params, keys, [outs[g] for g in idx], d, k, *compress_mask)
+    if out_limbs is not None:
+        res = [ckks.drop_limbs(x, out_limbs) if out_limbs < x.limbs else x for x in res]
+    return res
+
+
+def compressed_rot_limbs(params, k, gallery_limbs, out_limbs=None, level_min=False):
+    """Limbs of the HE-C^3 outputs that the compression mask multiplies."""
+    if level_min:
+        t, _ = level_min_shape(params, k, gallery_limbs, True)
+        return min(out_limbs + 1, t - 1) if out_limbs else t - 1
+    return gallery_limbs - 1
 
 
 def scores_from_slots(params, slots_by_group, d, k, R):
@@ -196,6 +261,21 @@ def scores_from_slots(params, slots_by_group, d, k, R):
         tid = g * T + b
         ok = tid < R
         out[tid[ok]] = np.real(z[b[ok] * c])
+    return out
+
+
+def scores_from_compressed(params, slots_by_ct, d, k, R):
+    """Template g T + b is scored at slot b c + (g mod c) of compressed
+    ciphertext floor(g / c)."""
+    c, T = layout(params, d, k)
+    out = np.full(R, np.nan)
+    for o, z in enumerate(slots_by_ct):
+        for r in range(c):
+            g = o * c + r
+            b = np.arange(T)
+            tid = g * T + b
+            ok = tid < R
+            out[tid[ok]] = np.real(z[b[ok] * c + r])
     return out
 
 

@@ -196,3 +196,68 @@ def test_c1_end_to_end_scores_and_top1():
         assert np.max(np.abs(scores - cos)) < 1e-4
         assert bm.top1(scores)[0] == int(np.argmax(cos))
     assert bm.top1(scores)[0] == w["known"]
+
+
+# ---------------------------------------------------------------- compression method
+
+def _compressed_want(P, X, q, d, k, n_ct):
+    """Closed form of the compressed layout: slot b c + r of ciphertext o holds
+    <q, x_t> for t = (o c + r) T + b when that template exists, 0 elsewhere."""
+    c, T = bm.layout(P, d, k)
+    R = X.shape[0]
+    want = np.zeros((n_ct, P.n))
+    for o in range(n_ct):
+        for r in range(c):
+            for b in range(T):
+                t = (o * c + r) * T + b
+                if t < R:
+                    want[o, b * c + r] = X[t] @ q
+    return want
+
+
+@pytest.mark.parametrize("d,k,schedule,level_min,groups", [(8, 1, bm.S1, False, 11), (8, 2, bm.S2, False, 5),
+                                                            (8, 1, bm.S2, True, 8), (4, 2, bm.S1, True, 3),
+                                                            (8, 1, bm.S1, False, 1)])
+def test_compressed_scores_follow_closed_form_layout(tiny_setup, d, k, schedule, level_min, groups):
+    """Compression (Sec. 3.4, Prop. 3): group g's scores land at slot b c + (g mod c)
+    of ciphertext floor(g / c) and every other slot is zero."""
+    P, keys0 = tiny_setup
+    c, T = bm.layout(P, d, k)
+    rots = set(bm.rotations_needed(P, d, k)) | set(bm.compress_rotations(P, d, k))
+    keys = ckks.keygen(P, 0xB11D, rotations=sorted(rots))
+    rng = np.random.default_rng(17 * d + k + groups)
+    R = groups * T - (T // 2 if groups > 1 else 0)        # ragged last group
+    X = rng.standard_normal((R, d)) / np.sqrt(d)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(bm.pack_query(P, q, d), P.scale, P.N), len(P.q), P.scale, 5, 1)
+    lg = bm.gallery_limbs(P, k)
+    gallery = [[ckks.encrypt(P, keys.pk, ckks.encode(v, P.scale, P.N), lg, P.scale, 5, 50 + 10 * g + i)
+                for i, v in enumerate(parts)] for g, parts in enumerate(bm.pack_gallery(P, X, d, k))]
+    assert len(gallery) == groups
+    ql = bm.level_min_shape(P, k, lg, True)[1] if level_min else len(P.q)
+    masks, mscale = bm.mask_coeffs(P, d, k, ql)
+    rl = bm.compressed_rot_limbs(P, k, lg, out_limbs=2, level_min=level_min)
+    cmask = bm.compress_mask_coeffs(P, d, k, rl)
+    res = bm.match(P, keys, cq, gallery, d, k, schedule, masks, mscale, out_limbs=2,
+                   level_min=level_min, compress_mask=cmask)
+    n_ct = -(-groups // c)
+    assert len(res) == n_ct
+    want = _compressed_want(P, X, q, d, k, n_ct)
+    t = bm.level_min_shape(P, k, lg, True)[0] if level_min else lg
+    slots = []
+    for o, ct in enumerate(res):
+        # the mask at scale q_top and its rescale leave the HE-C^3 output scale
+        assert ct.limbs == 2 and ct.scale == P.scale * P.scale / P.q[t - 1]
+        z = ckks.decrypt_decode(P, keys.s, ct)
+        assert np.max(np.abs(z - want[o])) < 1e-7
+        slots.append(z)
+    scores = bm.scores_from_compressed(P, slots, d, k, R)
+    assert np.max(np.abs(scores - X @ q)) < 1e-7
+
+
+def test_compression_level_rules(tiny_setup):
+    P, _ = tiny_setup
+    assert bm.level_min_shape(P, 2, 7, compress=True) == (4, 5)
+    assert bm.compressed_rot_limbs(P, 2, 7, out_limbs=2, level_min=True) == 3
+    assert bm.compressed_rot_limbs(P, 1, 8) == 7
+    assert bm.compress_rotations(P, 16, 2) == [-1, -2, -4]
