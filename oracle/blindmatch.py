@@ -199,6 +199,48 @@ def compress(params, keys, outs, d, k, mask, mask_scale):
     return res
 
 
+def enroll_mask_coeffs(params, d, k, limbs):
+    """Enrollment masks (Sec. 3.2): mask_i has ones at slots [i c, (i+1) c)
+    and zeros elsewhere, as integer plaintexts at scale q_{limbs-1}."""
+    c, _ = layout(params, d, k)
+    s = np.arange(params.n)
+    qtop = params.q[limbs - 1]
+    return [ckks.encode(((s >= i * c) & (s < (i + 1) * c)).astype(np.float64), float(qtop), params.N)
+            for i in range(k)], float(qtop)
+
+
+def enroll_rotations(params, d, k):
+    """Rotation amounts enrollment uses: c 2^t for t < log2(T)."""
+    c, T = layout(params, d, k)
+    return [c << t for t in range(log2_exact(T))]
+
+
+def enroll(params, keys, users, indices, d, k, masks, mask_scale, gallery=None):
+    """Server-side enrollment (Sec. 3.2, Fig. 3).  users[u] encrypts template u's
+    feature vector in slots [0, d) (zeros elsewhere); its identifier
+    Index = indices[u] (0-indexed) is position b = Index mod T of group
+    g = Index div T.  For every part i: C = Res(Mul(P)(C_u, mask_i)) is rotated
+    right by (b - i) c slots -- taken as left rotations by c 2^t for the set
+    bits t of (i - b) mod T, ascending -- and added into part i of group g.
+    `gallery` maps group -> list of k ciphertexts; missing groups start as the
+    trivial zero ciphertext.  Returns the updated mapping."""
+    c, T = layout(params, d, k)
+    gallery = {} if gallery is None else gallery
+    for cu, index in zip(users, indices):
+        g, b = divmod(int(index), T)
+        for i in range(k):
+            x = ckks.rescale(params, ckks.pmul(params, cu, masks[i], mask_scale))
+            m = (i - b) % T
+            t = 0
+            while m >> t:
+                if (m >> t) & 1:
+                    x = ckks.rotate(params, x, c << t, keys.gks)
+                t += 1
+            parts = gallery.setdefault(g, [None] * k)
+            parts[i] = x if parts[i] is None else ckks.hadd(params, parts[i], x)
+    return gallery
+
+
 def compress_rotations(params, d, k):
     """Rotation amounts the compression merges use: -2^t for t < log2(c)."""
     c, _ = layout(params, d, k)
@@ -220,6 +262,9 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
         raise ValueError("compression needs every group")
     idx = range(len(gallery)) if groups is None else groups
     rot_limbs = None
+    g_limbs = gallery[idx[0]][0].limbs
+    if not level_min and cq.limbs > g_limbs + (1 if k > 1 else 0):
+        cq = ckks.drop_limbs(cq, g_limbs + (1 if k > 1 else 0))   # products at the gallery's level
     if level_min:
         t, ql = level_min_shape(params, k, gallery[0][0].limbs, comp)
         cq = ckks.drop_limbs(cq, ql)

@@ -261,3 +261,72 @@ def test_compression_level_rules(tiny_setup):
     assert bm.compressed_rot_limbs(P, 2, 7, out_limbs=2, level_min=True) == 3
     assert bm.compressed_rot_limbs(P, 1, 8) == 7
     assert bm.compress_rotations(P, 16, 2) == [-1, -2, -4]
+
+
+# ---------------------------------------------------------------- server-side enrollment
+
+def _enrolled_want(P, X, indices, d, k, G):
+    """Closed form of the stored layout: template Index = g T + b occupies
+    slots [b c, (b+1) c) of part i of group g with its chunk i."""
+    c, T = bm.layout(P, d, k)
+    want = np.zeros((G, k, P.n))
+    for x, index in zip(X, indices):
+        g, b = divmod(int(index), T)
+        for i in range(k):
+            want[g, i, b * c:(b + 1) * c] = x[i * c:(i + 1) * c]
+    return want
+
+
+@pytest.mark.parametrize("d,k", [(8, 1), (8, 2), (8, 4), (4, 4), (16, 2)])
+def test_enrolled_gallery_follows_closed_form_and_matches(tiny_setup, d, k):
+    """Sec. 3.2 / Fig. 3: masked parts rotated right by (Index - i) c and added
+    give the packed layout of the gallery (slot by slot), one level below the
+    user ciphertexts, and matching it gives the inner products."""
+    P, _ = tiny_setup
+    c, T = bm.layout(P, d, k)
+    rots = set(bm.rotations_needed(P, d, k)) | set(bm.enroll_rotations(P, d, k))
+    keys = ckks.keygen(P, 0xB11D, rotations=sorted(rots))
+    rng = np.random.default_rng(d * 5 + k)
+    G = 2
+    indices = rng.permutation(G * T)[: G * T - 1]      # random order, one position left empty
+    X = rng.standard_normal((len(indices), d)) / np.sqrt(d)
+    top = len(P.q)
+    users = []
+    for u, x in enumerate(X):
+        z = np.zeros(P.n)
+        z[:d] = x
+        users.append(ckks.encrypt(P, keys.pk, ckks.encode(z, P.scale, P.N), top, P.scale, 7, 500 + u))
+    emasks, escale = bm.enroll_mask_coeffs(P, d, k, top)
+    gal = bm.enroll(P, keys, users, indices, d, k, emasks, escale)
+    assert sorted(gal) == list(range(G))
+    want = _enrolled_want(P, X, indices, d, k, G)
+    for g in range(G):
+        for i in range(k):
+            ct = gal[g][i]
+            assert ct.limbs == top - 1 and ct.scale == P.scale
+            assert np.max(np.abs(ckks.decrypt_decode(P, keys.s, ct) - want[g, i])) < 1e-7
+    # match the enrolled gallery: template Index is scored like a packed one
+    q = rng.standard_normal(d) / np.sqrt(d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(bm.pack_query(P, q, d), P.scale, P.N), top, P.scale, 7, 1)
+    masks, mscale = bm.mask_coeffs(P, d, k, top) if k > 1 else (None, None)
+    outs = bm.match(P, keys, cq, [gal[g] for g in range(G)], d, k, bm.S2, masks, mscale, out_limbs=2)
+    scores = bm.scores_from_slots(P, {g: ckks.decrypt_decode(P, keys.s, o) for g, o in outs.items()},
+                                  d, k, G * T)
+    assert np.max(np.abs(scores[indices] - X @ q)) < 1e-7
+    empty = sorted(set(range(G * T)) - set(int(v) for v in indices))
+    assert np.max(np.abs(scores[empty])) < 1e-7
+
+
+def test_enrollment_without_rotation_is_the_masked_part(tiny_setup):
+    """Index = i gives no rotation: part i is exactly Res(Mul(P)(C_u, mask_i))."""
+    P, keys = tiny_setup
+    d, k = 8, 4
+    rng = np.random.default_rng(3)
+    z = np.zeros(P.n)
+    z[:d] = rng.standard_normal(d)
+    cu = ckks.encrypt(P, keys.pk, ckks.encode(z, P.scale, P.N), len(P.q), P.scale, 7, 9)
+    emasks, escale = bm.enroll_mask_coeffs(P, d, k, len(P.q))
+    keys2 = ckks.keygen(P, 0xB11D, rotations=bm.enroll_rotations(P, d, k))
+    gal = bm.enroll(P, keys2, [cu], [2], d, k, emasks, escale)
+    direct = ckks.rescale(P, ckks.pmul(P, cu, emasks[2], escale))
+    assert all(np.array_equal(a, b) for a, b in zip(gal[0][2].c, direct.c))
