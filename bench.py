@@ -107,6 +107,7 @@ def main():
     rots = set()
     for k in ks:
         rots.update(bm.bm_rotations_for(d, k))
+        rots.update(bm.bm_rotations_compress(d, k))
     t0 = time.time()
     sk, pk, evk = bm.bm_keygen(ctx, seed, sorted(rots))
     q_ct = bm.bm_encrypt_query(ctx, pk, q, seed, 1)
@@ -127,7 +128,8 @@ def main():
 
     # ---- short sweep over (k, schedule)
     def sname(s):
-        return "S%d%s" % (s & 0xff, "+levelmin" if s & bm.BM_LEVEL_MIN else "")
+        return "S%d%s%s" % (s & 0xff, "+levelmin" if s & bm.BM_LEVEL_MIN else "",
+                            "+compress" if s & bm.BM_COMPRESS else "")
 
     sweep, conf = {}, {}
     for k in ks:
@@ -149,6 +151,35 @@ def main():
     bk, bs = conf[best]
     canon = {key: v for key, v in sweep.items() if not conf[key][1] & bm.BM_LEVEL_MIN}
     canon_best = min(canon, key=canon.get) if canon else None
+
+    # ---- the same match with the compression method: one result ciphertext
+    # per c groups instead of one per group (what the client downloads)
+    compressed = None
+    if not bs & bm.BM_COMPRESS:
+        cs = bs | bm.BM_COMPRESS
+        bm.bm_result_free(run_once(bk, cs))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = [run_once(bk, cs) for _ in range(3)]
+        torch.cuda.synchronize()
+        cms = (time.perf_counter() - t) * 1e3 / 3
+        r = rs.pop()
+        for x in rs:
+            bm.bm_result_free(x)
+        n_ct, climbs, _ = bm.bm_result_info(r)
+        csc = bm.bm_decrypt_scores(ctx, sk, r, n_tmpl)
+        bm.bm_result_free(r)
+        r = run_once(bk, bs)
+        n_plain, plimbs, _ = bm.bm_result_info(r)
+        bm.bm_result_free(r)
+        cos0 = X.astype(np.float64) @ q.astype(np.float64)
+        compressed = {"config": "k%d_%s" % (bk, sname(cs)), "ms_per_match": round(cms, 3),
+                      "result_ciphertexts": n_ct, "result_bytes": n_ct * 2 * climbs * params.N * 8,
+                      "uncompressed_ciphertexts": n_plain,
+                      "uncompressed_bytes": n_plain * 2 * plimbs * params.N * 8,
+                      "max_abs_err_vs_fp64_cosine": float(np.max(np.abs(csc - cos0)))}
+        print("# compressed %s: %.2f ms/match, %d -> %d result ciphertexts" %
+              (compressed["config"], cms, n_plain, n_ct), file=sys.stderr, flush=True)
 
     # ---- timed region
     for _ in range(args.warmup):
@@ -240,7 +271,7 @@ def main():
         "config": {
             "workload": "face-scale 1:N match: N=2^16, 8x50-bit chain + 2x51-bit special primes, "
                         "dnum=4, 6144 x 128-dim templates in 24 ciphertexts, one query",
-            "k": bk, "schedule": sname(bs), "templates": n_tmpl,
+            "k": bk, "schedule": sname(bs), "templates": n_tmpl, "compressed": compressed,
             "natural_level_best": ({"config": canon_best, "ms_per_match": round(canon[canon_best], 3),
                                     "templates_per_s": round(n_tmpl / canon[canon_best] * 1e3, 1)}
                                    if canon_best else None),

@@ -54,8 +54,9 @@ enum {
 };
 
 enum { BM_S1 = 1, BM_S2 = 2 };   /* Alg. 2 schedules, see bm_match */
-/* OR-ed into a schedule: evaluate at the minimum level (see bm_match). */
-enum { BM_LEVEL_MIN = 0x100 };
+/* OR-ed into a schedule: evaluate at the minimum level, and compress the
+ * group outputs into few ciphertexts (see bm_match). */
+enum { BM_LEVEL_MIN = 0x100, BM_COMPRESS = 0x200 };
 
 typedef struct bm_ctx bm_ctx;
 typedef struct bm_sk bm_sk;
@@ -137,6 +138,12 @@ int bm_keygen(bm_ctx *ctx, uint64_t seed, const int32_t *rotations, size_t n_rot
  * parts: 2^t for t < log2(d/k), and -+(d/k) 2^t for t < log2 k.  Writes at
  * most `cap` values and the count to *n. */
 int bm_rotations_for(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
+/* Rotation amounts the compression method (BM_COMPRESS) adds: -2^t for
+ * t < log2(d/k). */
+int bm_rotations_compress(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
+/* Rotation amounts server-side enrollment (bm_enroll) uses: c 2^t for
+ * t < log2(T), c = d/k, T = (N/2)/c templates per group. */
+int bm_rotations_enroll(const bm_ctx *ctx, uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
 /* Coefficient-domain export for checking: secret key (N signed values);
  * public key component comp (0 = b, 1 = a) as [L+1][N]; switching key digit
  * j component comp as [L+1+K][N] for the relinearisation key (galois = 0) or
@@ -176,6 +183,29 @@ int bm_encrypt_gallery(bm_ctx *ctx, const bm_pk *pk, const float *x, uint64_t n,
 int bm_gallery_import(bm_ctx *ctx, const uint64_t *words, uint64_t groups, uint32_t d,
                       uint32_t k, uint32_t limbs, double scale, uint64_t n_templates,
                       bm_gallery **out);
+/* ---- server-side enrollment (Sec. 3.2, Fig. 3) */
+/* Client side of enrollment: x[0..d-1] in slots [0, d), zeros elsewhere,
+ * encoded at the context scale, encrypted at L+1 limbs. */
+int bm_encrypt_template(bm_ctx *ctx, const bm_pk *pk, const float *x, uint32_t d, uint64_t seed,
+                        uint64_t ct_id, bm_ct **out);
+/* Empty gallery (every part the trivial zero ciphertext) for n_templates
+ * identifiers of dimension d split into k parts, stored at `limbs` limbs
+ * (L for galleries filled by bm_enroll from L+1-limb users). */
+int bm_gallery_create(bm_ctx *ctx, uint32_t d, uint32_t k, uint64_t n_templates, uint32_t limbs,
+                      bm_gallery **out);
+/* Server-side enrollment of n users: users[u] is a bm_encrypt_template
+ * ciphertext one level above the gallery, indices[u] < n_templates its
+ * identifier Index (0-indexed), stored at position b = Index mod T of group
+ * Index / T.  For every part i the server multiplies C_u by mask_i (ones at
+ * slots [i c, (i+1) c), at scale q_top of C_u), rescales, rotates right by
+ * (b - i) c slots -- left rotations by c 2^t for the set bits t of
+ * (i - b) mod T, ascending (keys of bm_rotations_enroll) -- and adds the
+ * result into part i of the group.  The stored layout is that of
+ * bm_encrypt_gallery, one level lower.  Enrolling an identifier twice adds
+ * the two vectors.  Asynchronous on `stream`; errors: BM_ELEVEL (user
+ * level), BM_ESCALE, BM_EINVAL (identifier out of range), BM_ENOKEY. */
+int bm_enroll(bm_ctx *ctx, const bm_evk *evk, bm_gallery *g, const bm_ct *const *users,
+              const uint64_t *indices, size_t n, void *stream);
 int bm_gallery_export(const bm_gallery *g, uint64_t *words, size_t n_words);
 int bm_gallery_info(const bm_gallery *g, uint64_t *groups, uint32_t *limbs, double *scale);
 void bm_gallery_free(bm_gallery *g);
@@ -240,15 +270,26 @@ int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *ma
  *   schedule BM_S2: acc = Res(Relin(sum_i Tensor(C_u,i, C_s,i))) -- one key
  *                   switch and one rescale per group; same message, other bits.
  * then log2(d/k) steps acc += Rot(acc, 2^t).  The score of template g T + b is
- * at slot b c of group g.  `masks` may be NULL (the library's own masks are
- * used).  out_limbs: 0 = context default, otherwise an exact level drop of
+ * at slot b c of group g.  The query needs at least the gallery's limbs
+ * (k = 1) or one more (k > 1); a higher query is cut exactly.  `masks` may
+ * be NULL (the library's own masks are used).  out_limbs: 0 = context default, otherwise an exact level drop of
  * each result.  Asynchronous on `stream`.
  * schedule | BM_LEVEL_MIN: every input is first cut by exact limb drops to
  * the level the rest needs -- the products at 3 chain limbs (gallery read in
  * place, query cut to 3 limbs, or 4 before Alg. 1 with masks at scale q_3),
  * and the accumulator at the output limbs before rotate-and-sum.  Same
  * message and accuracy, other bits, about a third of the NTTs; the query
- * and gallery keep the levels they were encrypted at. */
+ * and gallery keep the levels they were encrypted at.
+ * schedule | BM_COMPRESS: the compression method of Sec. 3.4 (cost in
+ * Prop. 3).  Each group output is multiplied by the score mask (ones at
+ * slots b c, encoded at scale q_top of the output) and rescaled; then the
+ * groups of every block of c = d/k consecutive groups are merged by halving,
+ * x_j += Rot(x_{j+h}, -h) for h = P/2, ..., 1 (P the power of two >= the
+ * block size).  The result holds ceil(G / c) ciphertexts; template g T + b
+ * is at slot b c + (g mod c) of ciphertext floor(g / c).  Needs the keys of
+ * bm_rotations_compress and one level more than the plain match (with
+ * BM_LEVEL_MIN the products are taken at 4 limbs); BM_ELEVEL if the
+ * gallery has no level to spare. */
 int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g,
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);
@@ -266,13 +307,17 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * returns it with its time per match.  Bits never depend on the choice. */
 int bm_autotune(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g, uint32_t schedule,
                 uint32_t *best_chunk, double *best_ms);
+/* *groups = result ciphertexts (gallery groups, or ceil(groups / c) when
+ * compressed). */
 int bm_result_info(const bm_result *r, uint64_t *groups, uint32_t *limbs, double *scale);
-/* Coefficient-domain words[2][limbs][N] of group `group`. */
+/* Coefficient-domain words[2][limbs][N] of result ciphertext `group`. */
 int bm_result_export(const bm_result *r, uint64_t group, uint64_t *words, size_t n_words);
 void bm_result_free(bm_result *r);
 
-/* Client side (Sec. 3.4): decrypt every group, decode, read template
- * g T + b at slot b c.  scores must hold n = n_templates values. */
+/* Client side (Sec. 3.4): decrypt every result ciphertext, decode, read
+ * template g T + b at slot b c of group g (compressed: at slot
+ * b c + (g mod c) of ciphertext floor(g / c)).  scores must hold
+ * n = n_templates values. */
 int bm_decrypt_scores(bm_ctx *ctx, const bm_sk *sk, const bm_result *r, double *scores,
                       uint64_t n);
 /* Arg-max of scores[0..n-1] (lowest index on ties); *idx = -1 when the best

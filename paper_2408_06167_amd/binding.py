@@ -18,6 +18,7 @@ BM_OK, BM_EINVAL, BM_EDIM, BM_ELEVEL, BM_ESCALE, BM_ENOKEY = 0, -1, -2, -3, -4, 
 BM_ENOMEM, BM_EBUDGET, BM_EDEVICE, BM_EBUSY = -6, -7, -8, -9
 BM_S1, BM_S2 = 1, 2
 BM_LEVEL_MIN = 0x100
+BM_COMPRESS = 0x200
 
 
 class BMError(RuntimeError):
@@ -60,6 +61,7 @@ _SIGS = {
     "bm_profile_dump": (ctypes.c_int, [_P, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
     "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
     "bm_rotations_for": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
+    "bm_rotations_compress": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_sk_export": (ctypes.c_int, [_P, _P, _sz]),
     "bm_pk_export": (ctypes.c_int, [_P, _u32, _P, _sz]),
     "bm_evk_export": (ctypes.c_int, [_P, _u64, _u32, _u32, _P, _sz]),
@@ -72,6 +74,10 @@ _SIGS = {
     "bm_encrypt_gallery": (ctypes.c_int, [_P, _P, _P, _u64, _u32, _u32, _u64, _u64, _PP]),
     "bm_gallery_import": (ctypes.c_int, [_P, _P, _u64, _u32, _u32, _u32, _dbl, _u64, _PP]),
     "bm_gallery_export": (ctypes.c_int, [_P, _P, _sz]),
+    "bm_encrypt_template": (ctypes.c_int, [_P, _P, _P, _u32, _u64, _u64, _PP]),
+    "bm_gallery_create": (ctypes.c_int, [_P, _u32, _u32, _u64, _u32, _PP]),
+    "bm_enroll": (ctypes.c_int, [_P, _P, _P, _P, _P, _sz, _P]),
+    "bm_rotations_enroll": (ctypes.c_int, [_P, _u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_gallery_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                        ctypes.POINTER(_dbl)]),
     "bm_gallery_free": (None, [_P]),
@@ -224,6 +230,15 @@ def bm_rotations_for(d, k):
     return [int(x) for x in out]
 
 
+def bm_rotations_compress(d, k):
+    n = _sz(0)
+    _check(lib().bm_rotations_compress(int(d), int(k), None, 0, ctypes.byref(n)), "bm_rotations_compress")
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(lib().bm_rotations_compress(int(d), int(k), _ptr(out), out.size, ctypes.byref(n)),
+           "bm_rotations_compress")
+    return [int(v) for v in out]
+
+
 def bm_keygen(ctx, seed, rotations=()):
     rots = np.ascontiguousarray(sorted(set(int(r) for r in rotations)), dtype=np.int32)
     sk, pk, evk = _out(), _out(), _out()
@@ -303,6 +318,39 @@ def bm_gallery_import(ctx, words, d, k, limbs, scale, n_templates):
     _check(lib().bm_gallery_import(ctx, _ptr(w), groups, int(d), int(k), int(limbs), float(scale),
                                    int(n_templates), ctypes.byref(h)), "bm_gallery_import", ctx)
     return h
+
+
+def bm_encrypt_template(ctx, pk, x, seed, ct_id):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    h = _out()
+    _check(lib().bm_encrypt_template(ctx, pk, _ptr(x), x.size, int(seed), int(ct_id), ctypes.byref(h)),
+           "bm_encrypt_template", ctx)
+    return h
+
+
+def bm_gallery_create(ctx, d, k, n_templates, limbs):
+    h = _out()
+    _check(lib().bm_gallery_create(ctx, int(d), int(k), int(n_templates), int(limbs), ctypes.byref(h)),
+           "bm_gallery_create", ctx)
+    return h
+
+
+def bm_enroll(ctx, evk, gallery, users, indices, stream=None):
+    n = len(users)
+    ua = (ctypes.c_void_p * max(n, 1))(*[u.value for u in users])
+    idx = np.ascontiguousarray(indices, dtype=np.uint64)
+    assert idx.size == n
+    _check(lib().bm_enroll(ctx, evk, gallery, ctypes.cast(ua, _P), _ptr(idx), n,
+                           ctypes.c_void_p(stream) if stream else None), "bm_enroll", ctx)
+
+
+def bm_rotations_enroll(ctx, d, k):
+    n = _sz(0)
+    _check(lib().bm_rotations_enroll(ctx, int(d), int(k), None, 0, ctypes.byref(n)), "bm_rotations_enroll")
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(lib().bm_rotations_enroll(ctx, int(d), int(k), _ptr(out), out.size, ctypes.byref(n)),
+           "bm_rotations_enroll")
+    return [int(v) for v in out]
 
 
 def bm_gallery_info(g):

@@ -36,6 +36,55 @@ const u64* galois_key(const bm_evk* evk, u64 g) {
 
 int gallery_limbs(const Ctx& c, u32 k) { return k == 1 ? c.L + 1 : c.L; }
 
+Plan plan(const Ctx& c, uint32_t schedule, uint32_t k, int g_limbs, uint32_t out_limbs) {
+  Plan s;
+  s.sched = schedule & 0xff;
+  s.lmin = (schedule & BM_LEVEL_MIN) != 0;
+  s.comp = (schedule & BM_COMPRESS) != 0;
+  if (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS)) BM_THROW(BM_EINVAL, "unknown schedule flags");
+  if (s.sched != BM_S1 && s.sched != BM_S2) BM_THROW(BM_EINVAL, "schedule must be BM_S1 or BM_S2");
+  s.t = s.lmin ? std::min<int>(EVAL_LIMBS + (s.comp ? 1 : 0), g_limbs) : g_limbs;
+  s.ql = k > 1 ? s.t + 1 : s.t;
+  const int nat = s.t - 1;                   // HE-C^3 output level
+  const int top = s.comp ? nat - 1 : nat;    // highest possible output
+  s.ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : top);
+  s.ol = std::min(s.ol, top);
+  if (s.ol < 1) BM_THROW(BM_ELEVEL, s.comp ? "compression needs one level more" : "output level");
+  s.rot = s.lmin ? s.ol + (s.comp ? 1 : 0) : nat;
+  return s;
+}
+
+u64 out_cts(const Plan& p, u64 G, u32 d, u32 k) {
+  const u64 cc = d / k;
+  return p.comp ? (G + cc - 1) / cc : G;
+}
+
+double result_scale(const Ctx& c, const Plan& p, double cu_scale, double g_scale) {
+  double s = cu_scale * g_scale / (double)c.primes[p.t - 1].q;
+  if (p.comp) {                              // Mul(P) by the mask at scale q_{rot-1}, then Res
+    const double qm = (double)c.primes[p.rot - 1].q;
+    s = s * qm / qm;
+  }
+  return s;
+}
+
+void match_groups(Ctx& c, const bm_evk* evk, const Plan& p, const u64* cu, int nq, size_t cu_stride,
+                  const bm_gallery& g, const u64* cmask, u64* out, size_t out_qstride) {
+  if (!p.comp) {
+    hec3_groups(c, evk, cu, nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, p.t, p.sched, p.rot,
+                p.ol, out, out_qstride);
+    return;
+  }
+  if (!cmask) BM_THROW(BM_EINVAL, "compression mask missing");
+  const size_t per = (size_t)g.groups * 2 * p.rot * c.N;
+  DBuf tmp(&c, (size_t)nq * per);
+  hec3_groups(c, evk, cu, nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, p.t, p.sched, p.rot,
+              p.rot, tmp.p(), per);
+  for (int j = 0; j < nq; ++j)
+    compress(c, evk, tmp.p() + j * per, (size_t)2 * p.rot * c.N, g.groups, g.d, g.k, cmask, p.rot, p.ol,
+             out + j * out_qstride);
+}
+
 void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
             u64* out) {
   const size_t N = c.N;
@@ -127,6 +176,112 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
     }
     kern::copy_limbs(c, a, 2 * rln, rln, out + g0 * oct, Bg, out_qstride, oct, (size_t)out_limbs * N,
                      B, 2, out_limbs);
+  }
+}
+
+// Compression method (Sec. 3.4, Prop. 3).  Every group output is multiplied
+// by the score mask (ones at slots b c, at scale q_{rl-1}) and rescaled; the
+// groups of each block of c consecutive groups are then merged by halving,
+// x_j += Rot(x_{j+h}, -h) for h = P/2, ..., 1, so group g ends at slot
+// b c + (g mod c) of compressed ciphertext floor(g / c).  Every merge step is
+// one batched rotate-and-add over the pairs of the block.
+void compress(Ctx& c, const bm_evk* evk, const u64* in, size_t in_stride, u64 G, u32 d, u32 k,
+              const u64* mask, int rl, int ol, u64* out) {
+  const size_t N = c.N;
+  const int nl = rl - 1;
+  if (nl < 1) BM_THROW(BM_ELEVEL, "compression needs two limbs");
+  if (ol < 1 || ol > nl) BM_THROW(BM_ELEVEL, "output limbs out of range");
+  const u64 cc = d / k;
+  const size_t rln = (size_t)rl * N, ct = (size_t)2 * nl * N, oct = (size_t)2 * ol * N;
+  DBuf pm(&c, G * 2 * rln), y(&c, G * ct);
+  for (int comp = 0; comp < 2; ++comp)
+    kern::mul(c, in + comp * rln, in_stride, mask, 0, pm.p() + comp * rln, 2 * rln, (int)G,
+              kern::chain_map(rl));
+  ev::rescale(c, pm.p(), (int)G, 2, rl, y.p());
+  for (u64 o = 0; o * cc < G; ++o) {
+    u64* base = y.p() + o * cc * ct;
+    const u64 r = std::min<u64>(cc, G - o * cc);
+    u64 h = 1;
+    while (2 * h < r) h *= 2;
+    for (; r > 1 && h >= 1; h /= 2) {
+      const u64 cnt = std::min<u64>(h, r - h);
+      const u64 g = ev::galois_for_rotation(c, -(long)h);
+      ev::rotate_add(c, base + h * ct, (int)cnt, nl, g, galois_key(evk, g), base, base);
+    }
+    kern::copy_limbs(c, base, ct, (size_t)nl * N, out + o * oct, 1, oct, 0, (size_t)ol * N, 1, 2, ol);
+  }
+}
+
+// Server-side enrollment (Sec. 3.2, Fig. 3).  User u's ciphertext holds its
+// feature vector in slots [0, d); its identifier Index = indices[u] is
+// position b = Index mod T of group Index div T.  Part i of the user is
+// Res(Mul(P)(C_u, mask_i)) (mask_i: ones at [i c, (i+1) c)), rotated right by
+// (b - i) c slots as left rotations by c 2^t for the set bits t of
+// (i - b) mod T, ascending, and added into part i of the group.  The parts
+// of a chunk of users go through every step as one batch; the elements that
+// rotate at bit t are gathered, rotated together and scattered back.
+void enroll(Ctx& c, const bm_evk* evk, bm_gallery& g, const u64* const* users, int user_limbs,
+            const uint64_t* indices, int nu, const u64* masks) {
+  const size_t N = c.N;
+  const u32 d = g.d, k = g.k, cc = d / k;
+  const u64 T = c.n / cc;
+  const int ul = user_limbs, lg = (int)g.limbs;
+  if (lg != ul - 1) BM_THROW(BM_ELEVEL, "users must sit one level above the gallery");
+  const size_t uct = (size_t)2 * ul * N, ct = (size_t)2 * lg * N;
+  const int logT = ilog2(T);
+  std::vector<u64> gel(logT);
+  std::vector<const u64*> key(logT);
+  for (int t = 0; t < logT; ++t) {
+    gel[t] = ev::galois_for_rotation(c, (long)cc << t);
+    key[t] = galois_key(evk, gel[t]);
+  }
+  const int per_chunk = std::max(1, 64 / (int)k);          // users per pass
+  const int rb = 64;                                          // elements per rotation batch
+  for (int u0 = 0; u0 < nu; u0 += per_chunk) {
+    const int U = std::min(per_chunk, nu - u0);
+    const int E = U * (int)k;
+    DBuf pm(&c, (size_t)E * uct), x(&c, (size_t)E * ct);
+    for (int u = 0; u < U; ++u)
+      for (int comp = 0; comp < 2; ++comp)
+        kern::mul(c, users[u0 + u] + comp * (size_t)ul * N, 0, masks, (size_t)(c.L + 1) * N,
+                  pm.p() + (size_t)u * k * uct + comp * (size_t)ul * N, uct, (int)k, kern::chain_map(ul));
+    ev::rescale(c, pm.p(), E, 2, ul, x.p());
+    std::vector<u64> amount(E);
+    for (int u = 0; u < U; ++u) {
+      const u64 b = indices[u0 + u] % T;
+      for (u32 i = 0; i < k; ++i) amount[(size_t)u * k + i] = (i + T - b) % T;
+    }
+    // element lists of every bit, uploaded once per chunk
+    std::vector<uint32_t> sel;
+    std::vector<size_t> first(logT + 1, 0);
+    for (int t = 0; t < logT; ++t) {
+      first[t] = sel.size();
+      for (int e = 0; e < E; ++e)
+        if ((amount[e] >> t) & 1) sel.push_back((uint32_t)e);
+    }
+    first[logT] = sel.size();
+    DBuf idx(&c, sel.size() / 2 + 2);
+    if (!sel.empty()) {
+      HIP_OK(dev::memcpy_async(idx.p(), sel.data(), sel.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               c.stream));
+      HIP_OK(dev::stream_sync(c.stream));   // the host list may be released
+    }
+    DBuf a(&c, (size_t)std::min(rb, E) * ct), r(&c, (size_t)std::min(rb, E) * ct);
+    for (int t = 0; t < logT; ++t)
+      for (size_t s0 = first[t]; s0 < first[t + 1]; s0 += rb) {
+        const int B = (int)std::min<size_t>(rb, first[t + 1] - s0);
+        const uint32_t* id = (const uint32_t*)idx.p() + s0;
+        const uint32_t mx = *std::max_element(sel.begin() + s0, sel.begin() + s0 + B);
+        kern::move_idx(c, x.p(), ct, a.p(), ct, id, mx, false, B, ct);
+        ev::rotate(c, a.p(), B, lg, gel[t], key[t], r.p(), false);
+        kern::move_idx(c, r.p(), ct, x.p(), ct, id, mx, true, B, ct);
+      }
+    for (int u = 0; u < U; ++u) {
+      const u64 grp = indices[u0 + u] / T;
+      u64* dst = g.buf.p() + (size_t)grp * k * ct;
+      kern::add(c, dst, (size_t)lg * N, x.p() + (size_t)u * k * ct, (size_t)lg * N, dst, (size_t)lg * N,
+                2 * (int)k, kern::chain_map(lg));
+    }
   }
 }
 

@@ -354,6 +354,12 @@ void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t
 // batch element z is written to out + (z / div) so_hi + (z % div) so_lo
 void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
                 size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs);
+// out[0 .. words) = 0
+void zero(const Ctx& c, u64* out, size_t words);
+// B elements of `words` words: gather out[z] = in[idx[z]] or scatter
+// out[idx[z]] = in[z]; idx_dev is a device array of B indices <= max_idx
+void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const uint32_t* idx_dev,
+              uint32_t max_idx, bool scatter, int B, size_t words);
 }  // namespace kern
 
 }  // namespace bm
@@ -412,7 +418,8 @@ struct bm_gallery {
 struct bm_result {
   bm_ctx* ctx = nullptr;
   uint32_t d = 0, k = 0, limbs = 0;
-  uint64_t n_templates = 0, groups = 0;
+  uint64_t n_templates = 0, groups = 0;   // groups = result ciphertexts
+  uint32_t packed = 0;                      // groups per ciphertext when compressed, else 0
   double scale = 0;
   std::shared_ptr<bm::DBuf> store;   // may be shared by the results of one batch
   size_t off = 0;                     // words; this result is [G][2][limbs][N] at store + off

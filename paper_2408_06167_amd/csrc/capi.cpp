@@ -239,6 +239,31 @@ int bm_rotations_for(uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n
   });
 }
 
+int bm_rotations_compress(uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {
+  return guarded(nullptr, [&] {
+    REQUIRE(n, BM_EINVAL, "n is NULL");
+    REQUIRE(bmx::is_pow2(d) && bmx::is_pow2(k) && k <= d, BM_EDIM, "power-of-two k | d");
+    std::vector<int32_t> r;
+    for (uint32_t t = 0; (1u << t) < d / k; ++t) r.push_back(-(int32_t)(1u << t));
+    *n = r.size();
+    if (out)
+      for (size_t i = 0; i < std::min(cap, r.size()); ++i) out[i] = r[i];
+  });
+}
+
+int bm_rotations_enroll(const bm_ctx* ctx, uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {
+  return guarded(nullptr, [&] {
+    REQUIRE(ctx && n, BM_EINVAL, "NULL argument");
+    bmx::check_shape(ctx->c, d, k);
+    std::vector<int32_t> r;
+    const uint64_t cc = d / k, T = ctx->c.n / cc;
+    for (uint32_t t = 0; (1ULL << t) < T; ++t) r.push_back((int32_t)(cc << t));
+    *n = r.size();
+    if (out)
+      for (size_t i = 0; i < std::min(cap, r.size()); ++i) out[i] = r[i];
+  });
+}
+
 int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot, bm_sk** sk,
               bm_pk** pk, bm_evk** evk) {
   return guarded(ctx, [&] {
@@ -383,6 +408,24 @@ int bm_encrypt_query(bm_ctx* ctx, const bm_pk* pk, const float* q, uint32_t d, u
     REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= N/2");
     std::vector<double> slots(c.n);
     for (size_t s = 0; s < c.n; ++s) slots[s] = (double)q[s % d];
+    std::vector<int64_t> m(c.N);
+    encode_slots(c.N, slots.data(), nullptr, c.scale, m.data());
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, c.L + 1, c.scale));
+    ev::encrypt_batch(c, pk, m.data(), 1, c.L + 1, seed, &ct_id, ct->buf.p());
+    sync(c);
+    *out = ct.release();
+  });
+}
+
+int bm_encrypt_template(bm_ctx* ctx, const bm_pk* pk, const float* x, uint32_t d, uint64_t seed,
+                        uint64_t ct_id, bm_ct** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && pk && x && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= N/2");
+    std::vector<double> slots(c.n, 0.0);
+    for (size_t s = 0; s < d; ++s) slots[s] = (double)x[s];
     std::vector<int64_t> m(c.N);
     encode_slots(c.N, slots.data(), nullptr, c.scale, m.data());
     c.use_stream(nullptr);
@@ -703,6 +746,88 @@ bm_masks* bmx_create_masks(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t ql) {
   return make_masks(ctx, d, k, coeffs.data(), scale);
 }
 
+// The enrollment masks of Sec. 3.2: mask_i has ones at slots [i c, (i+1) c),
+// encoded at scale q_{limbs-1}; k plaintexts, cached in the context.
+const bm_masks* bmx_enroll_masks(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t limbs) {
+  Ctx& c = ctx->c;
+  bmx::check_shape(c, d, k);
+  if (limbs < 2 || (int)limbs > c.L + 1) BM_THROW(BM_ELEVEL, "mask level out of range");
+  const uint64_t key = (2ULL << 62) | ((uint64_t)d << 40) | ((uint64_t)k << 20) | (uint64_t)limbs;
+  auto it = ctx->mask_cache.find(key);
+  if (it != ctx->mask_cache.end()) return it->second.get();
+  const uint32_t cc = d / k;
+  const double scale = (double)c.primes[limbs - 1].q;
+  std::vector<int64_t> coeffs((size_t)k * c.N);
+  std::vector<double> slots(c.n);
+  for (uint32_t i = 0; i < k; ++i) {
+    for (size_t s = 0; s < c.n; ++s) slots[s] = (s >= (size_t)i * cc && s < (size_t)(i + 1) * cc) ? 1.0 : 0.0;
+    encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
+  }
+  bm_masks* m = make_masks(ctx, d, k, coeffs.data(), scale);
+  return ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(m)).first->second.get();
+}
+
+int bm_gallery_create(bm_ctx* ctx, uint32_t d, uint32_t k, uint64_t n_templates, uint32_t limbs,
+                      bm_gallery** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    bmx::check_shape(c, d, k);
+    REQUIRE(n_templates > 0, BM_EINVAL, "empty gallery");
+    REQUIRE(limbs >= 1 && (int)limbs <= c.L + 1, BM_ELEVEL, "limbs out of range");
+    const uint64_t T = c.n / (d / k);
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_gallery> g(new_gallery(ctx, d, k, limbs, (n_templates + T - 1) / T, n_templates,
+                                              c.scale));
+    kern::zero(c, g->buf.p(), g->buf.words());
+    sync(c);
+    *out = g.release();
+  });
+}
+
+int bm_enroll(bm_ctx* ctx, const bm_evk* evk, bm_gallery* g, const bm_ct* const* users,
+              const uint64_t* indices, size_t n, void* stream) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && g && (n == 0 || (users && indices)), BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    c.use_stream(stream);
+    if (n == 0) return;
+    const uint32_t ul = users[0]->limbs;
+    REQUIRE(ul == g->limbs + 1, BM_ELEVEL, "users must sit one level above the gallery");
+    const bm_masks* m = bmx_enroll_masks(ctx, g->d, g->k, ul);
+    std::vector<const u64*> ptrs(n);
+    for (size_t u = 0; u < n; ++u) {
+      REQUIRE(users[u] && users[u]->comps == 2 && users[u]->limbs == ul, BM_ELEVEL,
+              "users must be fresh two-component ciphertexts of one level");
+      REQUIRE(users[u]->scale * m->scale / (double)c.primes[ul - 1].q == g->scale, BM_ESCALE,
+              "user and gallery scales differ");
+      REQUIRE(indices[u] < g->n_templates, BM_EINVAL, "identifier beyond the gallery size");
+      ptrs[u] = users[u]->buf.p();
+    }
+    bmx::enroll(c, evk, *g, ptrs.data(), (int)ul, indices, (int)n, m->pt.p());
+  });
+}
+
+// The compression method's score mask: ones at slots b c (c = d/k), encoded
+// at scale q_{limbs-1}; one plaintext, cached in the context.
+const bm_masks* bmx_compress_mask(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t limbs) {
+  Ctx& c = ctx->c;
+  bmx::check_shape(c, d, k);
+  if (limbs < 2 || (int)limbs > c.L + 1) BM_THROW(BM_ELEVEL, "mask level out of range");
+  const uint64_t key = (1ULL << 62) | ((uint64_t)d << 40) | ((uint64_t)k << 20) | (uint64_t)limbs;
+  auto it = ctx->mask_cache.find(key);
+  if (it != ctx->mask_cache.end()) return it->second.get();
+  const uint32_t cc = d / k;
+  const double scale = (double)c.primes[limbs - 1].q;
+  std::vector<int64_t> coeffs(c.N);
+  std::vector<double> slots(c.n);
+  for (size_t s = 0; s < c.n; ++s) slots[s] = s % cc == 0 ? 1.0 : 0.0;
+  encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data());
+  bm_masks* m = make_masks(ctx, d, 1, coeffs.data(), scale);
+  m->k = k;
+  return ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(m)).first->second.get();
+}
+
 int bm_masks_create(bm_ctx* ctx, uint32_t d, uint32_t k, bm_masks** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
@@ -749,42 +874,23 @@ int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* ma
   });
 }
 
-// Shape of one match: limbs of the products (t), of the query as used (ql),
-// of the accumulator during rotate-and-sum and of the output.
-struct MatchShape {
-  uint32_t sched;   // BM_S1 or BM_S2
-  bool lmin;        // BM_LEVEL_MIN
-  int t, ql, rot, ol;
-};
+using bmx::Plan;
 
-static MatchShape match_shape(const Ctx& c, const bm_ct* q, const bm_gallery* g, uint32_t schedule,
-                              uint32_t out_limbs) {
-  MatchShape s;
-  s.sched = schedule & 0xff;
-  s.lmin = (schedule & BM_LEVEL_MIN) != 0;
-  REQUIRE((schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN)) == 0, BM_EINVAL, "unknown schedule flags");
-  REQUIRE(s.sched == BM_S1 || s.sched == BM_S2, BM_EINVAL, "schedule must be BM_S1 or BM_S2");
+// The plan of one match, checked against the query's level.
+static Plan match_shape(const Ctx& c, const bm_ct* q, const bm_gallery* g, uint32_t schedule,
+                        uint32_t out_limbs) {
   REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
-  s.t = s.lmin ? std::min<int>(3, (int)g->limbs) : (int)g->limbs;
-  s.ql = g->k > 1 ? s.t + 1 : s.t;
-  if (s.lmin)
-    REQUIRE((int)q->limbs >= s.ql && (int)q->limbs == (int)g->limbs + (g->k > 1 ? 1 : 0), BM_ELEVEL,
-            "query level does not fit the gallery");
-  else if (g->k == 1)
-    REQUIRE(q->limbs == g->limbs, BM_ELEVEL, "query and gallery levels differ");
-  else
-    REQUIRE(q->limbs == g->limbs + 1, BM_ELEVEL, "query must sit one level above the gallery");
-  const int nat = s.t - 1;
-  s.ol = out_limbs ? (int)out_limbs : (c.out_limbs ? (int)c.out_limbs : nat);
-  s.ol = std::min(s.ol, nat);
-  REQUIRE(s.ol >= 1, BM_ELEVEL, "output level");
-  s.rot = s.lmin ? s.ol : nat;
+  const Plan s = bmx::plan(c, schedule, g->k, (int)g->limbs, out_limbs);
+  // the query is cut exactly to ql limbs: the gallery's level (k = 1) or one
+  // above it (k > 1), lower under the minimum-level schedule
+  REQUIRE((int)q->limbs >= s.ql, BM_ELEVEL,
+          g->k == 1 ? "query below the gallery level" : "query must sit at least one level above the gallery");
   return s;
 }
 
 // Expansion (k > 1) and Alg. 2 for one query: q [2][q_limbs][N] -> out [G][2][ol][N]
 static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t q_limbs, const bm_gallery* g,
-                       const bm_masks* m, const MatchShape& s, u64* out) {
+                       const bm_masks* m, const u64* cmask, const Plan& s, u64* out) {
   const uint32_t k = g->k;
   const u64* qq = q;
   DBuf cut;
@@ -800,21 +906,21 @@ static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t q_limbs
     bmx::expand(c, evk, qq, s.ql, m->pt.p(), g->d, k, expanded.p());
     cu = expanded.p();
   }
-  bmx::hec3_groups(c, evk, cu, 1, 0, g->d, k, g->buf.p(), g->groups, (int)g->limbs, s.t, s.sched, s.rot,
-                   s.ol, out, 0);
+  bmx::match_groups(c, evk, s, cu, 1, 0, *g, cmask, out, 0);
 }
 
 // Replay (capturing on first use) the match of this shape as a HIP graph.
 static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
-                        const bm_masks* m, const MatchShape& s, uint32_t schedule, u64* out) {
+                        const bm_masks* m, const u64* cmask, const Plan& s, uint32_t schedule, u64* out) {
   const std::vector<uint64_t> key = {(uint64_t)evk, (uint64_t)evk->rlk.k.p(), (uint64_t)g->buf.p(),
                                      g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
-                                     schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
+                                     (uint64_t)cmask, schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
                                      (uint64_t)c.group_chunk};
+  const u64 n_out = bmx::out_cts(s, g->groups, g->d, g->k);
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
     if (ge->key == key) e = ge.get();
-  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)g->groups * 2 * s.ol * c.N;
+  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)n_out * 2 * s.ol * c.N;
   if (!e) {
     std::unique_ptr<GraphEntry> ne(new GraphEntry);
     ne->key = key;
@@ -827,7 +933,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
       ne->out_slot = DBuf(&c, ow);
       HIP_OK(dev::begin_capture(c.stream));
       capturing = true;
-      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, s, ne->out_slot.p());
+      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, cmask, s, ne->out_slot.p());
       capturing = false;
       HIP_OK(dev::end_capture(c.stream, &graph));
       HIP_OK(dev::graph_instantiate(&ne->exec, graph));
@@ -852,7 +958,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   kern::copy_limbs(c, q->buf.p(), qw, qw / 2, e->q_slot.p(), 1, qw, 0, qw / 2, 1, 2, (int)q->limbs);
   HIP_OK(dev::graph_launch(e->exec, c.stream));
   kern::copy_limbs(c, e->out_slot.p(), 2 * (size_t)s.ol * c.N, (size_t)s.ol * c.N, out, 1,
-                   2 * (size_t)s.ol * c.N, 0, (size_t)s.ol * c.N, (int)g->groups, 2, s.ol);
+                   2 * (size_t)s.ol * c.N, 0, (size_t)s.ol * c.N, (int)n_out, 2, s.ol);
 }
 
 // masks for this shape: the caller's, or the context's cached library masks
@@ -865,10 +971,29 @@ static const bm_masks* masks_for(bm_ctx* ctx, const bm_gallery* g, const bm_mask
   return it->second.get();
 }
 
+// the compression mask of this shape (cached in the context), or NULL
+static const u64* cmask_for(bm_ctx* ctx, const bm_gallery* g, const Plan& s) {
+  if (!s.comp) return nullptr;
+  return bmx_compress_mask(ctx, g->d, g->k, (uint32_t)s.rot)->pt.p();
+}
+
+static bm_result* new_result(bm_ctx* ctx, const bm_gallery* g, const Plan& s, double scale) {
+  std::unique_ptr<bm_result> r(new bm_result);
+  r->ctx = ctx;
+  r->d = g->d;
+  r->k = g->k;
+  r->limbs = (uint32_t)s.ol;
+  r->groups = bmx::out_cts(s, g->groups, g->d, g->k);
+  r->packed = s.comp ? g->d / g->k : 0;
+  r->n_templates = g->n_templates;
+  r->scale = scale;
+  return r.release();
+}
+
 static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g,
                       const bm_masks* masks, uint32_t schedule, uint32_t out_limbs, bm_result** out) {
   Ctx& c = ctx->c;
-  const MatchShape s = match_shape(c, q, g, schedule, out_limbs);
+  const Plan s = match_shape(c, q, g, schedule, out_limbs);
   const uint32_t k = g->k;
   double cu_scale = q->scale;
   const bm_masks* m = nullptr;
@@ -878,19 +1003,13 @@ static void match_one(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_g
     cu_scale = q->scale * m->scale / (double)c.primes[s.ql - 1].q;
   }
   REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
-  std::unique_ptr<bm_result> r(new bm_result);
-  r->ctx = ctx;
-  r->d = g->d;
-  r->k = k;
-  r->limbs = (uint32_t)s.ol;
-  r->groups = g->groups;
-  r->n_templates = g->n_templates;
-  r->store = std::make_shared<DBuf>(&c, (size_t)g->groups * 2 * s.ol * c.N);
+  const u64* cm = cmask_for(ctx, g, s);
+  std::unique_ptr<bm_result> r(new_result(ctx, g, s, bmx::result_scale(c, s, cu_scale, g->scale)));
+  r->store = std::make_shared<DBuf>(&c, (size_t)r->groups * 2 * s.ol * c.N);
   if (c.use_graphs && !c.prof->on)
-    match_graph(c, evk, q, g, m, s, schedule, r->p());
+    match_graph(c, evk, q, g, m, cm, s, schedule, r->p());
   else
-    match_body(c, evk, q->buf.p(), q->limbs, g, m, s, r->p());
-  r->scale = cu_scale * g->scale / (double)c.primes[s.t - 1].q;
+    match_body(c, evk, q->buf.p(), q->limbs, g, m, cm, s, r->p());
   *out = r.release();
 }
 
@@ -908,7 +1027,7 @@ int bm_match(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g
 static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, int nq,
                         const bm_gallery* g, uint32_t schedule, uint32_t out_limbs, bm_result** outs) {
   Ctx& c = ctx->c;
-  const MatchShape s = match_shape(c, qs[0], g, schedule, out_limbs);
+  const Plan s = match_shape(c, qs[0], g, schedule, out_limbs);
   const uint32_t k = g->k;
   const size_t N = c.N;
   const bm_masks* m = k > 1 ? masks_for(ctx, g, nullptr, s.ql) : nullptr;
@@ -934,19 +1053,11 @@ static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, 
     }
   }
   REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
-  const size_t per = (size_t)g->groups * 2 * s.ol * N;
+  const size_t per = (size_t)bmx::out_cts(s, g->groups, g->d, k) * 2 * s.ol * N;
   auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
-  bmx::hec3_groups(c, evk, cu.p(), nq, cu_stride, g->d, k, g->buf.p(), g->groups, (int)g->limbs, s.t,
-                   s.sched, s.rot, s.ol, store->p(), per);
+  bmx::match_groups(c, evk, s, cu.p(), nq, cu_stride, *g, cmask_for(ctx, g, s), store->p(), per);
   for (int j = 0; j < nq; ++j) {
-    std::unique_ptr<bm_result> r(new bm_result);
-    r->ctx = ctx;
-    r->d = g->d;
-    r->k = k;
-    r->limbs = (uint32_t)s.ol;
-    r->groups = g->groups;
-    r->n_templates = g->n_templates;
-    r->scale = cu_scale * g->scale / (double)c.primes[s.t - 1].q;
+    std::unique_ptr<bm_result> r(new_result(ctx, g, s, bmx::result_scale(c, s, cu_scale, g->scale)));
     r->store = store;
     r->off = (size_t)j * per;
     outs[j] = r.release();
@@ -1060,13 +1171,17 @@ int bm_decrypt_scores(bm_ctx* ctx, const bm_sk* sk, const bm_result* r, double* 
     c.use_stream(nullptr);
     const uint32_t cc = r->d / r->k;
     const uint64_t T = c.n / cc;
+    const uint64_t per = r->packed ? r->packed : 1;   // groups per result ciphertext
     std::vector<double> m(c.N), re(c.n);
-    for (uint64_t g = 0; g < r->groups; ++g) {
-      ev::decrypt_coeffs(c, sk, r->p() + g * 2 * (size_t)r->limbs * c.N, 2, (int)r->limbs, m.data());
+    for (uint64_t o = 0; o < r->groups; ++o) {
+      ev::decrypt_coeffs(c, sk, r->p() + o * 2 * (size_t)r->limbs * c.N, 2, (int)r->limbs, m.data());
       decode_coeffs(c.N, m.data(), r->scale, re.data(), nullptr);
-      for (uint64_t b = 0; b < T; ++b) {
-        const uint64_t tid = g * T + b;
-        if (tid < n) scores[tid] = re[b * cc];
+      for (uint64_t j = 0; j < per; ++j) {
+        const uint64_t g = o * per + j;
+        for (uint64_t b = 0; b < T; ++b) {
+          const uint64_t tid = g * T + b;
+          if (tid < n) scores[tid] = re[b * cc + (r->packed ? j : 0)];
+        }
       }
     }
   });

@@ -311,14 +311,25 @@ void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64*
   rotate2(c, in, B, limbs, g, key, g, key, 31, out, add_input);
 }
 
-void rotate2(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1, const u64* key1,
-             int sel, u64* out, bool add_input) {
+// out = Rot(in) (+ addend): phi(c0) (+ addend0) plus the switched phi(c1)
+static void rotate_impl(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1,
+                        const u64* key1, int sel, const u64* addend, u64* out) {
   const size_t ln = (size_t)limbs * c.N;
   DBuf tmp(&c, (size_t)B * 2 * ln);
   kern::automorphism(c, in, 2 * ln, tmp.p(), 2 * ln, B, 2 * limbs, g0, g1, sel);
-  if (add_input) kern::add(c, tmp.p(), 2 * ln, in, 2 * ln, tmp.p(), 2 * ln, B, kern::chain_map(limbs));
+  if (addend) kern::add(c, tmp.p(), 2 * ln, addend, 2 * ln, tmp.p(), 2 * ln, B, kern::chain_map(limbs));
   key_switch2(c, tmp.p() + ln, 2 * ln, B, limbs, key0, key1, sel, tmp.p(), 2 * ln,
-              add_input ? in + ln : nullptr, 2 * ln, out, 2 * ln);
+              addend ? addend + ln : nullptr, 2 * ln, out, 2 * ln);
+}
+
+void rotate2(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1, const u64* key1,
+             int sel, u64* out, bool add_input) {
+  rotate_impl(c, in, B, limbs, g0, key0, g1, key1, sel, add_input ? in : nullptr, out);
+}
+
+void rotate_add(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, const u64* addend,
+                u64* out) {
+  rotate_impl(c, in, B, limbs, g, key, g, key, 31, addend, out);
 }
 
 void drop(Ctx& c, const u64* in, int B, int comps, int from, int to, u64* out) {

@@ -27,6 +27,9 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
 // batch element z rotates with (g1, key1) when bit `sel` of z is set, else (g0, key0)
+// out = addend + Rot(in) (out may alias addend, not in)
+void rotate_add(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, const u64* addend,
+                u64* out);
 void rotate2(Ctx& c, const u64* in, int B, int limbs, u64 g0, const u64* key0, u64 g1, const u64* key1,
              int sel, u64* out, bool add_input);
 // out = first `to` limbs of each of `comps` components of in ([B][comps][from][N])

@@ -636,6 +636,19 @@ __global__ void k_copy_limbs(const u64* in, size_t si, size_t ics, u64* out, int
   for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) O[e] = I[e];
 }
 
+__global__ void k_zero(u64* out, size_t words) {
+  for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < words; e += (size_t)gridDim.x * TPB) out[e] = 0;
+}
+
+// element z of `words` words: gather out[z] = in[idx[z]], or scatter out[idx[z]] = in[z]
+__global__ void k_move_idx(const u64* in, size_t si, u64* out, size_t so, const uint32_t* idx, int scatter,
+                           size_t words) {
+  const size_t z = blockIdx.z;
+  const u64* I = in + (scatter ? z : (size_t)idx[z]) * si;
+  u64* O = out + (scatter ? (size_t)idx[z] : z) * so;
+  for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < words; e += (size_t)gridDim.x * TPB) O[e] = I[e];
+}
+
 inline dim3 ew_grid(size_t N, int ys, int B) {
   size_t bx = (N + TPB * 4 - 1) / (TPB * 4);
   if (bx == 0) bx = 1;
@@ -1008,6 +1021,28 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
   Prof pf(c, "copy_limbs", 16.0 * c.N * B * comps * limbs, 0.0);
   LAUNCH(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
                      in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
+  check_launch();
+}
+
+void zero(const Ctx& c, u64* out, size_t words) {
+  if (words == 0) return;
+  chk(out, 1, 0, 0, words, "zero output");
+  Prof pf(c, "zero", 8.0 * words, 0.0);
+  const size_t blocks = std::min<size_t>((words + TPB * 4 - 1) / (TPB * 4), 65535);
+  LAUNCH(k_zero, dim3((unsigned)blocks), dim3(TPB), 0, c.stream, out, words);
+  check_launch();
+}
+
+void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const uint32_t* idx_dev,
+              uint32_t max_idx, bool scatter, int B, size_t words) {
+  if (B <= 0 || words == 0) return;
+  chk(in, scatter ? B : (int)max_idx + 1, si, 0, words, "move_idx input");
+  chk(out, scatter ? (int)max_idx + 1 : B, so, 0, words, "move_idx output");
+  chk(idx_dev, 1, 0, 0, ((size_t)B + 1) / 2, "move_idx index list");
+  Prof pf(c, "move_idx", 16.0 * words * B, 0.0);
+  const size_t blocks = std::min<size_t>((words + TPB * 4 - 1) / (TPB * 4), 65535);
+  LAUNCH(k_move_idx, dim3((unsigned)blocks, 1, (unsigned)B), dim3(TPB), 0, c.stream, in, si, out, so, idx_dev,
+         scatter ? 1 : 0, words);
   check_launch();
 }
 

@@ -39,7 +39,8 @@ struct bm_server {
 
   struct Gal {
     std::unique_ptr<bm_gallery> g;
-    bm_masks* masks = nullptr;   // owned, k > 1 only
+    bm_masks* masks = nullptr;       // owned, k > 1 only
+    const u64* cmask = nullptr;      // compression mask (context cache), BM_COMPRESS only
   };
   std::vector<Gal> galleries;
 
@@ -75,20 +76,12 @@ struct bm_server {
   std::vector<double> latencies;
   uint64_t batches = 0, batched = 0;
 
-  // limbs of the products, the query as used, rotate-and-sum and output
-  void shape(const bm_gallery& g, int& t, int& ql, int& rot, int& ol) const {
-    const Ctx& c = ctx->c;
-    const bool lmin = (schedule & BM_LEVEL_MIN) != 0;
-    t = lmin ? std::min<int>(3, (int)g.limbs) : (int)g.limbs;
-    ql = g.k > 1 ? t + 1 : t;
-    ol = std::min<int>(c.out_limbs ? (int)c.out_limbs : t - 1, t - 1);
-    rot = lmin ? ol : t - 1;
-  }
+  bmx::Plan shape(const bm_gallery& g) const { return bmx::plan(ctx->c, schedule, g.k, (int)g.limbs, 0); }
 
   uint64_t estimate(const bm_gallery& g, int nq) const {
     const Ctx& c = ctx->c;
-    int t, ql, rot, ol;
-    shape(g, t, ql, rot, ol);
+    const bmx::Plan p = shape(g);
+    const int t = p.t, ql = p.ql, ol = p.ol;
     const u64 N = c.N;
     const u64 l = (u64)t;
     const u64 beta = (l + c.alpha - 1) / c.alpha, ext = l + c.K;
@@ -96,9 +89,13 @@ struct bm_server {
     const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
     const u64 pairs = std::min<u64>(per_q, g.groups) * nq;
     const u64 pair_words = (3 + 2 + 2 + 2 + 1 + 2 + 2) * l * N + (beta + 2) * ext * N;
-    const u64 out_words = (u64)nq * g.groups * 2 * ol * N;
+    const u64 out_words = (u64)nq * bmx::out_cts(p, g.groups, g.d, g.k) * 2 * ol * N;
     const u64 cu_words = (u64)nq * g.k * 2 * l * N + (g.k > 1 ? g.k * 4 * (u64)ql * N : 0);
-    return 8 * (pairs * pair_words + out_words + cu_words);
+    // compression: the uncompressed outputs, the masked and rescaled copies and one rotation's scratch
+    const u64 comp_words = p.comp ? (u64)nq * g.groups * 2 * (2 * p.rot + p.rot - 1) * N +
+                                        pair_words
+                                  : 0;
+    return 8 * (pairs * pair_words + out_words + cu_words + comp_words);
   }
 
   void launch(Lane& lane) {
@@ -107,16 +104,15 @@ struct bm_server {
     const bm_gallery& g = *G.g;
     const int nq = (int)lane.reqs.size();
     const size_t N = c.N;
-    int t, ql, rot, ol;
-    shape(g, t, ql, rot, ol);
+    const bmx::Plan p = shape(g);
+    const int t = p.t, ql = p.ql, ol = p.ol;
     const size_t cu_stride = (size_t)g.k * 2 * t * N;
     DBuf cu(&c, (size_t)nq * cu_stride);
     DBuf cut(g.k > 1 ? DBuf(&c, (size_t)2 * ql * N) : DBuf());
     double cu_scale = 0;
     for (int j = 0; j < nq; ++j) {
       const bm_ct& q = *lane.reqs[j].q;
-      if ((int)q.limbs != (int)g.limbs + (g.k > 1 ? 1 : 0))
-        BM_THROW(BM_ELEVEL, "query level does not fit the gallery");
+      if ((int)q.limbs < ql) BM_THROW(BM_ELEVEL, "query level does not fit the gallery");
       if (g.k == 1) {                     // exact drop straight into the batch buffer
         ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, t, cu.p() + j * cu_stride);
         cu_scale = q.scale;
@@ -131,10 +127,10 @@ struct bm_server {
       }
       if (cu_scale != g.scale) BM_THROW(BM_ESCALE, "query and gallery scales differ");
     }
-    const size_t per = (size_t)g.groups * 2 * ol * N;
+    const u64 n_out = bmx::out_cts(p, g.groups, g.d, g.k);
+    const size_t per = (size_t)n_out * 2 * ol * N;
     auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
-    bmx::hec3_groups(c, evk, cu.p(), nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, t,
-                     schedule & 0xff, rot, ol, store->p(), per);
+    bmx::match_groups(c, evk, p, cu.p(), nq, cu_stride, g, G.cmask, store->p(), per);
     lane.results.clear();
     for (int j = 0; j < nq; ++j) {
       std::unique_ptr<bm_result> r(new bm_result);
@@ -142,9 +138,10 @@ struct bm_server {
       r->d = g.d;
       r->k = g.k;
       r->limbs = (uint32_t)ol;
-      r->groups = g.groups;
+      r->groups = n_out;
+      r->packed = p.comp ? g.d / g.k : 0;
       r->n_templates = g.n_templates;
-      r->scale = cu_scale * g.scale / (double)c.primes[t - 1].q;
+      r->scale = bmx::result_scale(c, p, cu_scale, g.scale);
       r->store = store;
       r->off = (size_t)j * per;
       lane.results.push_back(std::move(r));
@@ -246,7 +243,8 @@ int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, 
                      bm_server** out) {
   if (!ctx || !evk || !out || hbm_budget_bytes == 0) return BM_EINVAL;
   const uint32_t base = schedule & 0xff;
-  if ((base != BM_S1 && base != BM_S2) || (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN))) return BM_EINVAL;
+  if ((base != BM_S1 && base != BM_S2) || (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS)))
+    return BM_EINVAL;
   try {
     std::unique_ptr<bm_server> s(new bm_server);
     s->ctx = ctx;
@@ -271,15 +269,13 @@ int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, 
 int bm_server_add_gallery(bm_server* s, bm_gallery* g, uint32_t* gallery_id) {
   if (!s || !g || !gallery_id || g->ctx != s->ctx) return BM_EINVAL;
   bm_server::Gal entry;
-  if (g->k > 1) {
-    int t, ql, rot, ol;
-    s->shape(*g, t, ql, rot, ol);
-    try {
-      entry.masks = bmx_create_masks(s->ctx, g->d, g->k, (uint32_t)ql);
-    } catch (const Error& e) {
-      s->ctx->c.last_error = e.msg;
-      return e.code;
-    }
+  try {
+    const bmx::Plan p = s->shape(*g);
+    if (g->k > 1) entry.masks = bmx_create_masks(s->ctx, g->d, g->k, (uint32_t)p.ql);
+    if (p.comp) entry.cmask = bmx_compress_mask(s->ctx, g->d, g->k, (uint32_t)p.rot)->pt.p();
+  } catch (const Error& e) {
+    s->ctx->c.last_error = e.msg;
+    return e.code;
   }
   entry.g.reset(g);
   std::lock_guard<std::mutex> lk(s->mu);
@@ -294,8 +290,7 @@ int bm_server_submit(bm_server* s, uint32_t gallery_id, bm_ct* q, uint64_t* tick
   if (gallery_id >= s->galleries.size()) return BM_EINVAL;
   const bm_gallery& g = *s->galleries[gallery_id].g;
   if (s->estimate(g, 1) > s->budget) return BM_EBUDGET;
-  const uint32_t want = g.k == 1 ? g.limbs : g.limbs + 1;
-  if (q->limbs != want || q->comps != 2) return BM_ELEVEL;
+  if ((int)q->limbs < s->shape(g).ql || q->comps != 2) return BM_ELEVEL;
   bm_server::Req r;
   r.ticket = s->next_ticket++;
   r.gid = gallery_id;

@@ -19,6 +19,8 @@ def flow(preset, shapes, n_templates):
     rots = set()
     for d, k in shapes:
         rots.update(bm.bm_rotations_for(d, k))
+        rots.update(bm.bm_rotations_compress(d, k))
+        rots.update(bm.bm_rotations_enroll(ctx, d, k))
     sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(rots))
     rng = np.random.default_rng(0)
     words = rng.integers(0, 1 << 40, size=(2, L1, N), dtype=np.uint64)
@@ -57,7 +59,24 @@ def flow(preset, shapes, n_templates):
                 G, limbs, _ = bm.bm_result_info(r)
                 bm.bm_result_export(ctx, r, G - 1, N)
                 bm.bm_result_free(r)
+        # compression: needs one level more than the plain match
+        can_compress = preset == 2 or k == 1
+        for s in (2 | bm.BM_COMPRESS, 1 | bm.BM_LEVEL_MIN | bm.BM_COMPRESS):
+            bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
+            try:
+                r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
+            except bm.BMError as e:
+                assert not can_compress and e.code == bm.BM_ELEVEL, e
+                continue
+            assert can_compress
+            bm.bm_decrypt_scores(ctx, sk, r, n_templates)
+            G, limbs, _ = bm.bm_result_info(r)
+            bm.bm_result_export(ctx, r, G - 1, N)
+            bm.bm_result_free(r)
         bm.bm_ctx_set_graphs(ctx, False)
+        if can_compress:
+            for r in bm.bm_match_batch(ctx, evk, [q, q, q], [g, g, g], schedule=2 | bm.BM_COMPRESS):
+                bm.bm_result_free(r)
         rs = bm.bm_match_batch(ctx, evk, [q, q, q], [g, g, g], schedule=2)
         for r in rs:
             bm.bm_result_free(r)
@@ -66,7 +85,19 @@ def flow(preset, shapes, n_templates):
         for r in rs:
             bm.bm_result_free(r)
         bm.bm_ctx_set_group_chunk(ctx, 0)
-        srv = bm.bm_server_create(ctx, evk, 64 << 30, 2 | (bm.BM_LEVEL_MIN if k > 1 else 0))
+        # server-side enrollment into an empty gallery, then a match against it
+        c_, T_ = d // k, (N // 2) // (d // k)
+        eg = bm.bm_gallery_create(ctx, d, k, 2 * T_, L1 - 1)
+        users = [bm.bm_encrypt_template(ctx, pk, X[i], 1, 700 + i) for i in range(3)]
+        bm.bm_enroll(ctx, evk, eg, users, [0, T_ + 1, 2 * T_ - 1])
+        for u in users:
+            bm.bm_ct_free(u)
+        r = bm.bm_match(ctx, evk, q, eg, None, schedule=2, out_limbs=0)
+        bm.bm_decrypt_scores(ctx, sk, r, 2 * T_)
+        bm.bm_result_free(r)
+        bm.bm_gallery_free(eg)
+        srv = bm.bm_server_create(ctx, evk, 64 << 30, 2 | (bm.BM_LEVEL_MIN if k > 1 else 0) |
+                                  (bm.BM_COMPRESS if can_compress and k != 4 else 0))
         gid = bm.bm_server_add_gallery(srv, g)
         tickets = [bm.bm_server_submit(srv, gid, bm.bm_encrypt_query(ctx, pk, X[i], 1, 100 + i))
                    for i in range(5)]

@@ -39,6 +39,8 @@ def all_rotations(preset, shapes):
     r = set()
     for d, k in shapes:
         r.update(obm.rotations_needed(P, d, k))
+        r.update(obm.compress_rotations(P, d, k))
+        r.update(obm.enroll_rotations(P, d, k))
     return tuple(sorted(r))
 
 

@@ -16,7 +16,7 @@ from workloads import tiny_gallery, face_gallery
 
 pytestmark = pytest.mark.gpu
 
-C1_SHAPES = [(16, 1), (16, 2), (16, 4), (8, 8)]
+C1_SHAPES = [(16, 1), (16, 2), (16, 4), (8, 8), (4, 1)]
 C2_SHAPES = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
 
 
@@ -337,3 +337,95 @@ def test_match_face_scale_sampled(bm, k, schedule):
     bm.bm_result_free(res)
     if lm:
         bm.bm_masks_free(lm)
+
+
+# ------------------------------------------------------------------ compression method (Sec. 3.4)
+
+@pytest.mark.parametrize("d,R,schedule", [(16, 300, 0x201), (16, 300, 0x302), (4, 2300, 0x202),
+                                          (16, 100, 0x201)])
+def test_match_compressed_small_ring_bit_exact(bm, d, R, schedule):
+    """N = 2^12, k = 1: every compressed ciphertext word equals the oracle's,
+    including a ragged last block (d = 4: c = 4, five groups -> 4 + 1) and a
+    single group (mask and rescale only)."""
+    P, okeys, ctx, sk, pk, evk = setup(1)
+    k = 1
+    rng = np.random.default_rng(R + d)
+    X = rng.standard_normal((R, d))
+    X = (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+    qv = X[R // 3] + 0.05 * rng.standard_normal(d).astype(np.float32)
+    qv = qv / np.linalg.norm(qv)
+    log("compressed match N=2^12 d=%d R=%d schedule %#x" % (d, R, schedule))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 19)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 3000)
+    level_min = bool(schedule & 0x100)
+    rl = obm.compressed_rot_limbs(P, k, lg, level_min=level_min)
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, level_min=level_min,
+                     compress_mask=obm.compress_mask_coeffs(P, d, k, rl))
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
+    res = bm.bm_match(ctx, evk, cq, gal, None, schedule=schedule, out_limbs=0)
+    n_ct, limbs, scale = bm.bm_result_info(res)
+    assert n_ct == len(want) == -(-len(gal_o) // (d // k))
+    for o in range(n_ct):
+        got, sc = bm.bm_result_export(ctx, res, o, P.N)
+        assert sc == want[o].scale and limbs == want[o].limbs
+        assert_words_equal(got, ct_words(want[o]), "compressed ciphertext %d" % o)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, R)
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == int(np.argmax(cos))
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+
+
+def test_compression_without_a_spare_level_is_rejected(bm):
+    P, okeys, ctx, sk, pk, evk = setup(1)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((50, 16)).astype(np.float32)
+    q = bm.bm_encrypt_query(ctx, pk, X[0], SEED, 1)
+    g = bm.bm_encrypt_gallery(ctx, pk, X, 2, SEED, 10)      # k = 2: gallery at 2 limbs
+    with pytest.raises(bm.BMError) as e:
+        bm.bm_match(ctx, evk, q, g, None, schedule=2 | bm.BM_COMPRESS)
+    assert e.value.code == bm.BM_ELEVEL
+    bm.bm_ct_free(q)
+    bm.bm_gallery_free(g)
+
+
+@pytest.mark.parametrize("k,schedule", [(4, 0x302), (8, 0x301)])
+def test_match_face_scale_compressed_bit_exact(bm, k, schedule):
+    """N = 2^16, 6,144 x 128-dim, compressed at the minimum level: the G
+    group outputs fold into one ciphertext; the oracle recomputes all of it."""
+    P, okeys, ctx, sk, pk, evk = setup(2)
+    d = 128
+    w = face_gallery(seed=2)
+    X, qv = w["gallery"], w["query_known"]
+    log("compressed match N=2^16 k=%d schedule %#x: oracle gallery encryption" % (k, schedule))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 5000)
+    ql = obm.level_min_shape(P, k, lg, True)[1]
+    masks, mscale = obm.mask_coeffs(P, d, k, ql)
+    rl = obm.compressed_rot_limbs(P, k, lg, out_limbs=2, level_min=True)
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, X.shape[0])
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
+    log("library match")
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
+    log("oracle match, all %d groups" % len(gal_o))
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
+                     level_min=True, compress_mask=obm.compress_mask_coeffs(P, d, k, rl))
+    n_ct, limbs, _ = bm.bm_result_info(res)
+    assert n_ct == len(want) == 1 and limbs == 2
+    got, sc = bm.bm_result_export(ctx, res, 0, P.N)
+    assert sc == want[0].scale
+    assert_words_equal(got, ct_words(want[0]), "compressed ciphertext")
+    scores = bm.bm_decrypt_scores(ctx, sk, res, X.shape[0])
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == w["known"]
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    bm.bm_masks_free(lm)
