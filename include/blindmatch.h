@@ -202,10 +202,12 @@ int bm_gallery_create(bm_ctx *ctx, uint32_t d, uint32_t k, uint64_t n_templates,
  * (i - b) mod T, ascending (keys of bm_rotations_enroll) -- and adds the
  * result into part i of the group.  The stored layout is that of
  * bm_encrypt_gallery, one level lower.  Enrolling an identifier twice adds
- * the two vectors.  Asynchronous on `stream`; errors: BM_ELEVEL (user
+ * the two vectors.  `masks` may be NULL (the library's own enrollment
+ * masks), else k plaintexts made elsewhere (bm_masks_import) at scale
+ * q_top of the users.  Asynchronous on `stream`; errors: BM_ELEVEL (user
  * level), BM_ESCALE, BM_EINVAL (identifier out of range), BM_ENOKEY. */
 int bm_enroll(bm_ctx *ctx, const bm_evk *evk, bm_gallery *g, const bm_ct *const *users,
-              const uint64_t *indices, size_t n, void *stream);
+              const uint64_t *indices, size_t n, const bm_masks *masks, void *stream);
 int bm_gallery_export(const bm_gallery *g, uint64_t *words, size_t n_words);
 int bm_gallery_info(const bm_gallery *g, uint64_t *groups, uint32_t *limbs, double *scale);
 void bm_gallery_free(bm_gallery *g);

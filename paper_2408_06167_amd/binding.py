@@ -76,7 +76,7 @@ _SIGS = {
     "bm_gallery_export": (ctypes.c_int, [_P, _P, _sz]),
     "bm_encrypt_template": (ctypes.c_int, [_P, _P, _P, _u32, _u64, _u64, _PP]),
     "bm_gallery_create": (ctypes.c_int, [_P, _u32, _u32, _u64, _u32, _PP]),
-    "bm_enroll": (ctypes.c_int, [_P, _P, _P, _P, _P, _sz, _P]),
+    "bm_enroll": (ctypes.c_int, [_P, _P, _P, _P, _P, _sz, _P, _P]),
     "bm_rotations_enroll": (ctypes.c_int, [_P, _u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_gallery_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                        ctypes.POINTER(_dbl)]),
@@ -335,12 +335,12 @@ def bm_gallery_create(ctx, d, k, n_templates, limbs):
     return h
 
 
-def bm_enroll(ctx, evk, gallery, users, indices, stream=None):
+def bm_enroll(ctx, evk, gallery, users, indices, masks=None, stream=None):
     n = len(users)
     ua = (ctypes.c_void_p * max(n, 1))(*[u.value for u in users])
     idx = np.ascontiguousarray(indices, dtype=np.uint64)
     assert idx.size == n
-    _check(lib().bm_enroll(ctx, evk, gallery, ctypes.cast(ua, _P), _ptr(idx), n,
+    _check(lib().bm_enroll(ctx, evk, gallery, ctypes.cast(ua, _P), _ptr(idx), n, masks,
                            ctypes.c_void_p(stream) if stream else None), "bm_enroll", ctx)
 
 

@@ -786,7 +786,7 @@ int bm_gallery_create(bm_ctx* ctx, uint32_t d, uint32_t k, uint64_t n_templates,
 }
 
 int bm_enroll(bm_ctx* ctx, const bm_evk* evk, bm_gallery* g, const bm_ct* const* users,
-              const uint64_t* indices, size_t n, void* stream) {
+              const uint64_t* indices, size_t n, const bm_masks* masks, void* stream) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && g && (n == 0 || (users && indices)), BM_EINVAL, "NULL argument");
     Ctx& c = ctx->c;
@@ -794,7 +794,8 @@ int bm_enroll(bm_ctx* ctx, const bm_evk* evk, bm_gallery* g, const bm_ct* const*
     if (n == 0) return;
     const uint32_t ul = users[0]->limbs;
     REQUIRE(ul == g->limbs + 1, BM_ELEVEL, "users must sit one level above the gallery");
-    const bm_masks* m = bmx_enroll_masks(ctx, g->d, g->k, ul);
+    const bm_masks* m = masks ? masks : bmx_enroll_masks(ctx, g->d, g->k, ul);
+    REQUIRE(m->d == g->d && m->k == g->k, BM_EDIM, "masks do not match the gallery shape");
     std::vector<const u64*> ptrs(n);
     for (size_t u = 0; u < n; ++u) {
       REQUIRE(users[u] && users[u]->comps == 2 && users[u]->limbs == ul, BM_ELEVEL,

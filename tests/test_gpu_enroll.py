@@ -46,7 +46,11 @@ def test_enroll_small_ring_bit_exact(bm, d, k):
     c, T = obm.layout(P, d, k)
     G = 3
     rng = np.random.default_rng(d + 10 * k)
-    ids = rng.permutation(2 * T)[: T + T // 2]            # groups 0 and 1 only; group 2 stays empty
+    n_users = min(T + T // 2, 96)                          # the oracle enrolls every user on the CPU
+    ids = np.concatenate([[0, T - 1, T, 2 * T - 1],          # both ends of groups 0 and 1
+                          rng.choice(np.arange(1, T - 1), n_users // 2 - 2, replace=False),
+                          rng.choice(np.arange(T + 1, 2 * T - 1), n_users - n_users // 2 - 2, replace=False)])
+    ids = rng.permutation(ids)                              # random order; group 2 stays empty
     X = normalize(rng.standard_normal((ids.size, d))).astype(np.float64)
     log("enroll N=2^12 d=%d k=%d users=%d" % (d, k, ids.size))
     users_o = oracle_users(P, okeys, X, 7000)
@@ -54,9 +58,11 @@ def test_enroll_small_ring_bit_exact(bm, d, k):
     want = obm.enroll(P, okeys, users_o, ids, d, k, emasks, escale)
     users = [bm.bm_ct_import(ctx, ct_words(u), P.scale) for u in users_o]
     gal = bm.bm_gallery_create(ctx, d, k, G * T, len(P.q) - 1)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(emasks), escale)   # integer plaintexts shared
     half = len(users) // 2                                 # two calls: the second adds into the first
-    bm.bm_enroll(ctx, evk, gal, users[:half], ids[:half])
-    bm.bm_enroll(ctx, evk, gal, users[half:], ids[half:])
+    bm.bm_enroll(ctx, evk, gal, users[:half], ids[:half], lm)
+    bm.bm_enroll(ctx, evk, gal, users[half:], ids[half:], lm)
+    bm.bm_masks_free(lm)
     Gl, limbs, scale = bm.bm_gallery_info(gal)
     assert (Gl, limbs) == (G, len(P.q) - 1) and scale == P.scale
     words = bm.bm_gallery_export(ctx, gal, k, P.N)
@@ -68,7 +74,7 @@ def test_enroll_small_ring_bit_exact(bm, d, k):
             else:
                 assert not words[g, i].any(), "untouched group %d is not zero" % g
     # match the enrolled gallery
-    qv = normalize(X[3] + 0.05 * rng.standard_normal(d))
+    qv = normalize(X[3] + 0.01 * rng.standard_normal(d))
     cq = bm.bm_encrypt_query(ctx, pk, qv, SEED, 1)
     res = bm.bm_match(ctx, evk, cq, gal, None, schedule=2, out_limbs=0)
     scores = bm.bm_decrypt_scores(ctx, sk, res, G * T)
@@ -132,7 +138,9 @@ def test_enroll_face_scale(bm):
     emasks, escale = obm.enroll_mask_coeffs(P, d, k, len(P.q))
     want = obm.enroll(P, okeys, users_o, picks, d, k, emasks, escale)
     lone = bm.bm_gallery_create(ctx, d, k, n, len(P.q) - 1)
-    bm.bm_enroll(ctx, evk, lone, [users[u] for u in picks], picks)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(emasks), escale)   # integer plaintexts shared
+    bm.bm_enroll(ctx, evk, lone, [users[u] for u in picks], picks, lm)
+    bm.bm_masks_free(lm)
     lw = bm.bm_gallery_export(ctx, lone, k, P.N)
     for g, parts in want.items():
         for i in range(k):
