@@ -132,6 +132,39 @@ def expand(params, keys, cq, d, k, masks, mask_scale):
     return out
 
 
+def expansion_amounts(params, d, k, i):
+    """Rotation amounts of part i once Alg. 1's log2 k steps are unrolled: one
+    per non-empty subset S of the steps, sum over t in S of -c 2^t (bit t of i
+    is 0) or +c 2^t (bit t of i is 1), in increasing order of the subset mask."""
+    c, _ = layout(params, d, k)
+    out = []
+    for S in range(1, k):
+        r = 0
+        for t in range(log2_exact(k)):
+            if (S >> t) & 1:
+                r += (c << t) if (i >> t) & 1 else -(c << t)
+        out.append(r)
+    return out
+
+
+def expansion_rotations_hoisted(params, d, k):
+    """Rotation amounts the hoisted expansion needs (all parts)."""
+    return sorted({r for i in range(k) for r in expansion_amounts(params, d, k, i)})
+
+
+def expand_hoisted(params, keys, cq, d, k, masks, mask_scale):
+    """Alg. 1 with the rotations hoisted (an option of this build): the log2 k
+    rotate-and-add steps of part i unroll to C_i + sum over the non-empty
+    subsets S of Rot(C_i, r_S), evaluated with one ModUp and one ModDown per
+    part (ckks.rotation_sum_hoisted).  Same message as expand(), other bits."""
+    out = []
+    for i in range(k):
+        ci = ckks.rescale(params, ckks.pmul(params, cq, masks[i], mask_scale))
+        out.append(ckks.rotation_sum_hoisted(params, ci, expansion_amounts(params, d, k, i), keys.gks)
+                   if k > 1 else ci)
+    return out
+
+
 def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None):
     """Alg. 2 on one gallery group: accumulate the products of the k parts,
     then log2(c) steps of C_out += Rot(C_out, 2^t).  With rot_limbs the
@@ -248,7 +281,7 @@ def compress_rotations(params, d, k):
 
 
 def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None,
-          out_limbs=None, groups=None, level_min=False, compress_mask=None):
+          out_limbs=None, groups=None, level_min=False, compress_mask=None, hoist=False):
     """Whole server side: expansion (k > 1) then HE-C^3 per gallery group.
     `gallery` is a list over groups of k ciphertexts.  Optionally only the
     listed `groups` are evaluated (sampled parity at large sizes).  With
@@ -256,7 +289,8 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
     masks must then be encoded at scale q_{limbs of the cut query - 1}.
     With compress_mask = (plaintext, scale) the group outputs are compressed
     (all groups; the mask encoded at scale q_{rot limbs - 1}) and a list of
-    compressed ciphertexts is returned instead of the dict over groups."""
+    compressed ciphertexts is returned instead of the dict over groups.
+    With hoist the expansion is expand_hoisted()."""
     comp = compress_mask is not None
     if comp and groups is not None:
         raise ValueError("compression needs every group")
@@ -273,6 +307,8 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
         rot_limbs = min(out_limbs + extra, t - 1) if out_limbs else t - 1
     if k == 1:
         cu = [cq]
+    elif hoist:
+        cu = expand_hoisted(params, keys, cq, d, k, masks, mask_scale)
     else:
         cu = expand(params, keys, cq, d, k, masks, mask_scale)
     outs = {}

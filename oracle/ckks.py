@@ -503,6 +503,44 @@ def rotate(params, x, r, gks):
     return Ciphertext([add(c0, u, primes), w], x.limbs, x.scale)
 
 
+def rotation_sum_hoisted(params, x, amounts, gks):
+    """x + sum_r Rot(x, r) with the rotations hoisted twice: digit ModUp of x_1
+    once; for every r the automorphism applied to the extended digits and the
+    key inner product with the key for s(X^g) accumulated over Q_l u P; one
+    ModDown of the sums at the end; the automorphisms of x_0 added in Q_l.
+    Same message as the sum of plain rotations; other rounding, so other bits
+    (the automorphism of a ModUp is not the ModUp of the automorphism)."""
+    l = x.limbs
+    qs = params.q[:l]
+    ext = qs + params.p
+    key_limb = list(range(l)) + [len(params.q) + k for k in range(params.K)]
+    beta = -(-l // params.alpha)
+    ys = [mod_up_digit(params, x.c[1], l, j) for j in range(beta)]
+    jobs = []
+    for r in amounts:
+        g = galois_element(params, r)
+        if g not in gks:
+            raise KeyError("no Galois key for rotation %d" % r)
+        for j in range(beta):
+            yg = automorphism(ys[j], g, ext)
+            for t, mod in enumerate(ext):
+                jobs.append((yg[t], gks[g].b[j][key_limb[t]], mod))
+                jobs.append((yg[t], gks[g].a[j][key_limb[t]], mod))
+    prods = iter(prims.polymul_batch(jobs))
+    u = np.zeros((len(ext), params.N), dtype=np.uint64)
+    w = np.zeros((len(ext), params.N), dtype=np.uint64)
+    for _ in amounts:
+        for j in range(beta):
+            for t, mod in enumerate(ext):
+                u[t] = (u[t] + next(prods)) % np.uint64(mod)
+                w[t] = (w[t] + next(prods)) % np.uint64(mod)
+    c0 = x.c[0].copy()
+    for r in amounts:
+        c0 = add(c0, automorphism(x.c[0], galois_element(params, r), qs), qs)
+    return Ciphertext([add(c0, mod_down(params, u, l), qs), add(x.c[1], mod_down(params, w, l), qs)],
+                      l, x.scale)
+
+
 def drop_limbs(x, limbs):
     """Exact level drop: keep the first `limbs` residues."""
     if limbs > x.limbs:

@@ -330,3 +330,51 @@ def test_enrollment_without_rotation_is_the_masked_part(tiny_setup):
     gal = bm.enroll(P, keys2, [cu], [2], d, k, emasks, escale)
     direct = ckks.rescale(P, ckks.pmul(P, cu, emasks[2], escale))
     assert all(np.array_equal(a, b) for a, b in zip(gal[0][2].c, direct.c))
+
+
+# ---------------------------------------------------------------- hoisted expansion
+
+def test_expansion_amounts_unroll_alg1():
+    """The subsets of Alg. 1's steps give every block shift once: part i of
+    k = 4 collects the shifts that move each other chunk position onto it."""
+    P = tiny(log_n=7)
+    c = 4
+    assert bm.expansion_amounts(P, 16, 4, 0) == [-c, -2 * c, -3 * c]
+    assert bm.expansion_amounts(P, 16, 4, 3) == [c, 2 * c, 3 * c]
+    assert bm.expansion_amounts(P, 16, 4, 1) == [c, -2 * c, -c]
+    for k in (2, 4, 8):
+        for i in range(k):
+            shifts = sorted(r // (16 // k) for r in bm.expansion_amounts(P, 16, k, i))
+            assert len(set(shifts)) == k - 1 and 0 not in shifts
+
+
+@pytest.mark.parametrize("d,k", [(8, 2), (8, 4), (16, 4), (8, 8)])
+def test_hoisted_expansion_equals_slot_sim(tiny_setup, d, k):
+    P, _ = tiny_setup
+    rots = set(bm.expansion_rotations_hoisted(P, d, k))
+    keys = ckks.keygen(P, 0xB11D, rotations=sorted(rots))
+    rng = np.random.default_rng(d * 3 + k)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    qslots = bm.pack_query(P, q, d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(qslots, P.scale, P.N), len(P.q), P.scale, 4, 1)
+    masks, mscale = bm.mask_coeffs(P, d, k, len(P.q))
+    got = bm.expand_hoisted(P, keys, cq, d, k, masks, mscale)
+    want = slot_sim.expand(qslots, d, k)
+    for i in range(k):
+        assert got[i].limbs == len(P.q) - 1
+        assert np.max(np.abs(ckks.decrypt_decode(P, keys.s, got[i]) - want[i])) < 1e-9
+
+
+def test_hoisted_rotation_sum_single_amount_is_a_rotation(tiny_setup):
+    """One amount: x + Rot(x, r) in the slots, and the key-switch error of a
+    plain rotation (the two differ only in rounding)."""
+    P, keys = tiny_setup
+    rng = np.random.default_rng(8)
+    z = rng.standard_normal(P.n)
+    x = ckks.encrypt(P, keys.pk, ckks.encode(z, P.scale, P.N), 5, P.scale, 4, 2)
+    r = max(bm.rotations_needed(P, 8, 2))
+    h = ckks.rotation_sum_hoisted(P, x, [r], keys.gks)
+    plain = ckks.hadd(P, x, ckks.rotate(P, x, r, keys.gks))
+    zh, zp = ckks.decrypt_decode(P, keys.s, h), ckks.decrypt_decode(P, keys.s, plain)
+    assert np.max(np.abs(zh - (z + np.roll(z, -r)))) < 1e-9
+    assert np.max(np.abs(zh - zp)) < 1e-9
