@@ -23,15 +23,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Butterflies (one 64-bit modular multiply with its modular add and subtract)
-# per second the VALU can issue at most.  Unit counts and clock: 256 CUs x 4
-# SIMDs x 16 lanes x 2.4 GHz = 39.32 T lane-issue-cycles/s.  A butterfly on
-# 32-bit lanes needs at least 9 32x32 multiplies (3 for the Shoup quotient
-# estimate, 3 for the low word of a*w, 3 for the low word of q^*q), issued at
-# half rate (2 cycles each), and 14 full-rate adds/subtracts with carry (the
-# partial-product sums, a*w - q^*q, and the two 64-bit butterfly outputs):
-# 32 issue cycles, so 39.32e12 / 32 = 1.229 T butterflies/s.
-ALU_PEAK_GMODMUL = 39.3216e3 / 32.0
+# Butterflies per second the VALU can issue at most.  The NTT carries exact
+# integer residues (q < 2^51) in FP64, which CDNA4 issues at one operation per
+# lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T FP64
+# operations/s (the 78.6 TFLOP/s vector figure counts an FMA as two).  One
+# butterfly needs at least 8 of them: the exact product a*w - round(a*w/q)*q
+# (multiply, FMA for the low half, multiply by w/q, round, FMA, add) and the
+# sum and difference.  Peak: 39.32e12 / 8 = 4.915 T butterflies/s.
+ALU_PEAK_GMODMUL = 39.3216e3 / 8.0
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by
 # a 1 GiB device copy: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE), kept with
 # the sha256 of the kernel source they were taken on and the workload; the

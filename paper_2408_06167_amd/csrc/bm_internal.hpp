@@ -88,7 +88,7 @@ struct PrimeC {
   u64 r2;       // 2^128 mod q
   u64 ninv;     // N^{-1} mod q
   u64 ninv_s;   // Shoup companion of ninv
-  u64 pad[3];
+  u64 pad[3];   // [0] floor(2^64 / q); [1] bits of the double 1/q; [2] bits of the double ninv/q
 };
 
 // Limb selection for one launch: limb slot y of every polynomial in the
@@ -254,6 +254,10 @@ struct Ctx {
   u64* d_tws = nullptr;
   u64* d_itw = nullptr;            // psi^{-brv(k)}
   u64* d_itws = nullptr;
+  double* d_twf = nullptr;         // the same twiddles as doubles, and w / q rounded (FP64 NTT)
+  double* d_twq = nullptr;
+  double* d_itwf = nullptr;
+  double* d_itwq = nullptr;
   ModUpTable* d_modup = nullptr;   // [L+2] indexed by number of chain limbs
   ModDownTable* d_moddown = nullptr;
   u64* d_rescale = nullptr;        // [L+1][L+1][2]: q_l^{-1} mod q_i, Shoup pair

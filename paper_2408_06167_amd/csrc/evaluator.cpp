@@ -137,8 +137,9 @@ Ctx::~Ctx() {
   graphs.clear();
   pool.reset();
   if (owns_tables)
-    for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws,
-                    (void*)d_modup, (void*)d_moddown, (void*)d_rescale})
+    for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws, (void*)d_twf,
+                    (void*)d_twq, (void*)d_itwf, (void*)d_itwq, (void*)d_modup, (void*)d_moddown,
+                    (void*)d_rescale})
       if (p) {
         audit::remove(p);
         (void)dev::free(p);
@@ -166,6 +167,10 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->d_tws = d_tws;
   l->d_itw = d_itw;
   l->d_itws = d_itws;
+  l->d_twf = d_twf;
+  l->d_twq = d_twq;
+  l->d_itwf = d_itwf;
+  l->d_itwq = d_itwq;
   l->d_modup = d_modup;
   l->d_moddown = d_moddown;
   l->d_rescale = d_rescale;

@@ -125,6 +125,7 @@ void build_context_tables(Ctx& c) {
   std::vector<PrimeC> pc(MAX_PRIMES);
   std::vector<u64> tw(MAX_PRIMES * N), tws(MAX_PRIMES * N), itw(MAX_PRIMES * N),
       itws(MAX_PRIMES * N);
+  std::vector<double> twf(MAX_PRIMES * N), twq(MAX_PRIMES * N), itwf(MAX_PRIMES * N), itwq(MAX_PRIMES * N);
   std::vector<u64> pw(N), ipw(N);
   for (int i = 0; i < np; ++i) {
     const u64 q = c.primes[i].q;
@@ -137,6 +138,10 @@ void build_context_tables(Ctx& c) {
     p.ninv = h_invmod(N % q, q);
     p.ninv_s = h_shoup(p.ninv, q);
     p.pad[0] = h_shoup(1, q);   // floor(2^64 / q): reduction of any 64-bit word
+    if (q >= (1ULL << 51)) BM_THROW(BM_EINVAL, "primes must lie below 2^51");
+    const double qd = (double)q, qinv = 1.0 / qd, niq = (double)p.ninv / qd;
+    std::memcpy(&p.pad[1], &qinv, sizeof(double));
+    std::memcpy(&p.pad[2], &niq, sizeof(double));
     const u64 psi = c.primes[i].psi;
     const u64 ipsi = h_invmod(psi, q);
     pw[0] = ipw[0] = 1;
@@ -150,6 +155,10 @@ void build_context_tables(Ctx& c) {
       tws[i * N + k] = h_shoup(pw[r], q);
       itw[i * N + k] = ipw[r];
       itws[i * N + k] = h_shoup(ipw[r], q);
+      twf[i * N + k] = (double)pw[r];
+      twq[i * N + k] = (double)pw[r] / (double)q;
+      itwf[i * N + k] = (double)ipw[r];
+      itwq[i * N + k] = (double)ipw[r] / (double)q;
     }
   }
   HIP_OK(dev::malloc(&c.d_primes, sizeof(PrimeC) * MAX_PRIMES));
@@ -165,6 +174,15 @@ void build_context_tables(Ctx& c) {
   HIP_OK(dev::memcpy(c.d_tws, tws.data(), tb, hipMemcpyHostToDevice));
   HIP_OK(dev::memcpy(c.d_itw, itw.data(), tb, hipMemcpyHostToDevice));
   HIP_OK(dev::memcpy(c.d_itws, itws.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_twf, tb));
+  HIP_OK(dev::malloc(&c.d_twq, tb));
+  HIP_OK(dev::malloc(&c.d_itwf, tb));
+  HIP_OK(dev::malloc(&c.d_itwq, tb));
+  for (void* p : {(void*)c.d_twf, (void*)c.d_twq, (void*)c.d_itwf, (void*)c.d_itwq}) audit::add(p, tb);
+  HIP_OK(dev::memcpy(c.d_twf, twf.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_twq, twq.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_itwf, itwf.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::memcpy(c.d_itwq, itwq.data(), tb, hipMemcpyHostToDevice));
 
   // ---- ModUp tables, one per number of chain limbs l = 1..L+1
   const int nq = c.L + 1;

@@ -166,23 +166,54 @@ __global__ void __launch_bounds__(TPB) k_ntt_pass(const u64* __restrict__ in, si
 // (a radix-16 phase) before the view is exchanged through LDS; a pass of 8
 // stages is two phases, the single pass of N = 4096 is three.  Indices are
 // shifts and masks only.  Twiddles of the block are staged once in LDS (8-stage
-// passes) or read through the cache (12-stage pass).  Arithmetic is lazy
-// (Harvey): the forward butterfly lets values grow by 4q per stage and the
-// inverse keeps them below 4q; each pass ends with one exact reduction.
+// passes) or read through the cache (12-stage pass).
+//
+// Arithmetic is exact integer arithmetic carried in FP64, which the CDNA4
+// VALU issues at the full rate where 32-bit integer multiplies run at about
+// half of it.  Residues (q < 2^51) are integers held in doubles; every
+// intermediate stays an integer of magnitude below 2^53, so every operation
+// below is exact:
+//   fmul_mod(a, w) = a w - rint(a (w/q)) q, computed as hi = fl(a w),
+//     lo = a w - hi (one FMA, exact), r = (hi - qt q) + lo (one FMA whose
+//     exact result is an integer below 2^53, then an exact add).  The
+//     quotient estimate is within 0.5 + |a| 2^-52 of a w / q, so
+//     |r| <= q (0.5 + |a| 2^-52 (1 + 2^-52)).
+//   fred(a) = a - rint(a / q) q lies in [-q/2 - 1, q/2 + 1].
+// Values are brought back to |x| <= q/2 + 1 before the third stage of every
+// phase and before the first stage of every phase but the first, which
+// starts from residues in [0, q).  Forward (CT): from 0.5q two stages give
+// 1.25q and then 2.375q (the multiplied inputs stay below 1.25q, so every
+// product is below 1.13q); from [0, q) they give 2q and then 3.5q.  Inverse
+// (GS): from 0.5q two stages give 1q and then 2q; from [0, q), 2q and then
+// 4q (the difference fed to the product stays below 4q, so it is below
+// 2.5q).  With q < 2^51 all of these stay below 2^53.  Each pass ends with
+// fred and a conditional +q, so passes exchange exact residues in [0, q) as
+// 64-bit words.
 //
 // Pass kinds: COL = columns of length 256 of one polynomial (first 8 stages of
 // N = 2^16, twiddles common to all columns); ROW = one row of length 256
 // taken from V polynomials that share the prime (last 8 stages, row twiddles);
 // ONE = a whole N = 4096 polynomial.
 
-// a * w mod q up to 3q: the quotient floor(a * ws / 2^64) is estimated from
-// three 32 x 32 partial products; the estimate is at most 2 below the exact
-// one, which is itself within 1 of a*w/q, so the result lies in [0, 4q).
-__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
-  const u32 a0 = (u32)a, a1 = (u32)(a >> 32);
-  const u32 s0 = (u32)ws, s1 = (u32)(ws >> 32);
-  const u64 qh = (u64)a1 * s1 + (u64)__umulhi(a1, s0) + (u64)__umulhi(a0, s1);
-  return a * w - qh * q;
+__device__ __forceinline__ double fmul_mod(double a, double w, double wq, double q) {
+  const double hi = __dmul_rn(a, w);
+  const double lo = __fma_rn(a, w, -hi);
+  const double qt = rint(__dmul_rn(a, wq));
+  return __dadd_rn(__fma_rn(-qt, q, hi), lo);
+}
+
+__device__ __forceinline__ double fred(double a, double qi, double q) {
+  return __fma_rn(-rint(__dmul_rn(a, qi)), q, a);
+}
+
+// exact conversions for 0 <= v < 2^52
+__device__ __forceinline__ double u64_to_f(u64 v) {
+  return __fma_rn((double)(u32)(v >> 32), 4294967296.0, (double)(u32)v);
+}
+__device__ __forceinline__ u64 f_to_u64(double x) {
+  const u32 h = (u32)__dmul_rn(x, 1.0 / 4294967296.0);          // truncation: floor for x >= 0
+  const u32 l = (u32)__fma_rn(-(double)h, 4294967296.0, x);
+  return ((u64)h << 32) | l;
 }
 
 enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
@@ -191,23 +222,26 @@ template <int LOGM, bool INV, int KIND>
 __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
                                                   LimbMap m, const PrimeC* __restrict__ P,
-                                                  const u64* __restrict__ tw,
-                                                  const u64* __restrict__ tws, int log_n, int s0,
+                                                  const double* __restrict__ twf,
+                                                  const double* __restrict__ twq, int log_n, int s0,
                                                   int last, int B) {
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
   constexpr int VS = M + M / 16 + 1;          // padded view length in LDS (odd: spreads banks)
   constexpr int PH = LOGM / 4;                // radix-16 phases
-  extern __shared__ u64 sh[];
-  __shared__ u64 tl[2 * 256];                 // block twiddles (w, ws) for 8-stage passes
+  extern __shared__ u64 sh_raw[];
+  double* sh = reinterpret_cast<double*>(sh_raw);
+  __shared__ double tl[2 * 256];              // block twiddles (w, w/q) for 8-stage passes
   const int t = threadIdx.x;
   const int V = (int)blockDim.x / TPV;        // views in this block
   const int nthr = (int)blockDim.x;
   const int pid = m.prime[blockIdx.y];
-  const u64 q = P[pid].q;
+  const PrimeC& pr = P[pid];
+  const double q = (double)pr.q;
+  const double qi = __longlong_as_double((long long)pr.pad[1]);   // 1/q
   const int N = 1 << log_n;
-  const u64* W = tw + (size_t)pid * N;
-  const u64* WS = tws + (size_t)pid * N;
+  const double* W = twf + (size_t)pid * N;
+  const double* WQ = twq + (size_t)pid * N;
   auto pad = [](int a) { return a + (a >> 4); };
 
   // Lane layout: in a column pass consecutive lanes take consecutive columns
@@ -237,19 +271,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   const u64* src = in + base_in;
   u64* dst = out + base_out;
 
-  // ---- stage the block's twiddles (8-stage passes): tl[2^s + i] for stage s, block i
-  if (LOGM == 8) {
-    const int vb = KIND == NTT_ROW ? (int)blockIdx.x : 0;
-    for (int k = t; k < 256; k += nthr) {
-      if (k == 0) continue;
-      const int st = 31 - __clz(k);
-      const int g = (1 << (s0 + st)) + (vb << st) + (k - (1 << st));
-      tl[2 * k] = W[g];
-      tl[2 * k + 1] = WS[g];
-    }
-  }
-
-  u64 x[16];
+  double x[16];
   // phase p holds a = hi * 2^(LOGM-4p) + j * 2^(LOGM-4p-4) + lo,  u = hi * 2^(LOGM-4p-4) + lo
   auto addr = [&](int p, int j) {
     const int sh_lo = LOGM - 4 * p - 4;
@@ -264,19 +286,31 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   constexpr bool DIRECT_IN = KIND == NTT_COL || P_FIRST == 0;
   constexpr bool DIRECT_OUT = KIND == NTT_COL || P_LAST == 0;
 
-  if (DIRECT_IN) {
-    if (valid) {
+  // data loads first, so that their latency overlaps the twiddle staging
+  u64 raw[16] = {};
+  if (valid) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) x[j] = src[(size_t)addr(P_FIRST, j) * astride];
+    for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
+  }
+  // ---- stage the block's twiddles (8-stage passes): tl[2^s + i] for stage s, block i
+  if (LOGM == 8) {
+    const int vb = KIND == NTT_ROW ? (int)blockIdx.x : 0;
+    for (int k = t; k < 256; k += nthr) {
+      if (k == 0) continue;
+      const int st = 31 - __clz(k);
+      const int g = (1 << (s0 + st)) + (vb << st) + (k - (1 << st));
+      tl[2 * k] = W[g];
+      tl[2 * k + 1] = WQ[g];
     }
+  }
+  if (DIRECT_IN) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = u64_to_f(raw[j]);
   } else {
     // coalesced load in the p = 0 order, transpose through LDS
     if (valid) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int a = addr(0, j);
-        sh[v * VS + pad(a)] = src[a];
-      }
+      for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(0, j))] = u64_to_f(raw[j]);
     }
   }
   __syncthreads();                            // twiddles (and the transposed tile) ready
@@ -285,11 +319,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(P_FIRST, j))];
   }
 
-  auto twid = [&](int kk, u64& w, u64& ws) {
-    if (LOGM == 8) { w = tl[2 * kk]; ws = tl[2 * kk + 1]; }
-    else { w = W[kk]; ws = WS[kk]; }
+  auto twid = [&](int kk, double& w, double& wq) {
+    if (LOGM == 8) { w = tl[2 * kk]; wq = tl[2 * kk + 1]; }
+    else { w = W[kk]; wq = WQ[kk]; }
   };
-  const u64 q4 = 4 * q;
 
 #pragma unroll
   for (int ph = 0; ph < PH; ++ph) {
@@ -302,31 +335,38 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     if (!INV) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
+        if ((k == 0 && ph > 0) || k == 2) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+        }
         const int step = 8 >> k;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           if (j & step) continue;
-          u64 w, ws;
-          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, ws);
-          const u64 T = shoup_lazy(x[j + step], w, ws, q);
-          const u64 U = x[j];
-          x[j] = U + T;
-          x[j + step] = U + q4 - T;
+          double w, wq;
+          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, wq);
+          const double T = fmul_mod(x[j + step], w, wq, q);
+          const double U = x[j];
+          x[j] = __dadd_rn(U, T);
+          x[j + step] = __dsub_rn(U, T);
         }
       }
     } else {
 #pragma unroll
       for (int k = 3; k >= 0; --k) {
+        if ((k == 3 && ph > 0) || k == 1) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+        }
         const int step = 8 >> k;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           if (j & step) continue;
-          u64 w, ws;
-          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, ws);
-          const u64 U = x[j], Vv = x[j + step];
-          const u64 S = U + Vv;
-          x[j] = S >= q4 ? S - q4 : S;
-          x[j + step] = shoup_lazy(U + q4 - Vv, w, ws, q);
+          double w, wq;
+          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, wq);
+          const double U = x[j], Vv = x[j + step];
+          x[j] = __dadd_rn(U, Vv);
+          x[j + step] = fmul_mod(__dsub_rn(U, Vv), w, wq, q);
         }
       }
     }
@@ -338,25 +378,34 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     }
   }
 
-  // ---- exact reduction (times N^-1 at the end of an inverse transform) and store
-  const u64 w1 = last ? P[pid].ninv : 1, w1s = last ? P[pid].ninv_s : P[pid].pad[0];
+  // ---- exact residues in [0, q) (times N^-1 at the end of an inverse transform) and store
+  if (last) {
+    const double ni = (double)pr.ninv, niq = __longlong_as_double((long long)pr.pad[2]);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) x[j] = mul_shoup(x[j], w1, w1s, q);
+    for (int j = 0; j < 16; ++j) x[j] = fmul_mod(x[j], ni, niq, q);
+  }
+  u64 y[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double r = fred(x[j], qi, q);
+    r = r < 0.0 ? __dadd_rn(r, q) : r;
+    y[j] = f_to_u64(r);
+  }
   if (DIRECT_OUT) {
     if (valid) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) dst[(size_t)addr(P_LAST, j) * astride] = x[j];
+      for (int j = 0; j < 16; ++j) dst[(size_t)addr(P_LAST, j) * astride] = y[j];
     }
   } else {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(P_LAST, j))] = x[j];
+    for (int j = 0; j < 16; ++j) sh_raw[v * VS + pad(addr(P_LAST, j))] = y[j];
     __syncthreads();
     if (valid) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int a = addr(0, j);
-        dst[a] = sh[v * VS + pad(a)];
+        dst[a] = sh_raw[v * VS + pad(a)];
       }
     }
   }
@@ -729,8 +778,8 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   const int logn = c.log_n;
   const int N = 1 << logn;
   const double elems = (double)N * m.n * B;
-  const u64* tw = inverse ? c.d_itw : c.d_tw;
-  const u64* tws = inverse ? c.d_itws : c.d_tws;
+  const double* tw = inverse ? c.d_itwf : c.d_twf;
+  const double* tws = inverse ? c.d_itwq : c.d_twq;
   if (logn == 12) {
     chk_map(c, in, B, in_stride, m, "ntt input");
     chk_map(c, out, B, out_stride, m, "ntt output", true);
