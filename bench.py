@@ -102,11 +102,14 @@ def main():
     params = bm.bm_params_preset(2)
     ctx = bm.bm_ctx_create(params, 0)
     ks = [args.k] if args.k else [1, 2, 4, 8, 16]
-    scheds = [args.schedule] if args.schedule else [1, 2, 1 | bm.BM_LEVEL_MIN, 2 | bm.BM_LEVEL_MIN]
+    lm, ho = bm.BM_LEVEL_MIN, bm.BM_HOIST
+    scheds = [args.schedule] if args.schedule else [1, 2, 1 | lm, 2 | lm, 2 | ho, 2 | lm | ho]
     rots = set()
     for k in ks:
         rots.update(bm.bm_rotations_for(d, k))
         rots.update(bm.bm_rotations_compress(d, k))
+        if any(s & ho for s in scheds):
+            rots.update(bm.bm_rotations_hoisted(d, k))
     t0 = time.time()
     sk, pk, evk = bm.bm_keygen(ctx, seed, sorted(rots))
     q_ct = bm.bm_encrypt_query(ctx, pk, q, seed, 1)
@@ -127,8 +130,8 @@ def main():
 
     # ---- short sweep over (k, schedule)
     def sname(s):
-        return "S%d%s%s" % (s & 0xff, "+levelmin" if s & bm.BM_LEVEL_MIN else "",
-                            "+compress" if s & bm.BM_COMPRESS else "")
+        return "S%d%s%s%s" % (s & 0xff, "+levelmin" if s & bm.BM_LEVEL_MIN else "",
+                              "+hoist" if s & bm.BM_HOIST else "", "+compress" if s & bm.BM_COMPRESS else "")
 
     sweep, conf = {}, {}
     for k in ks:
@@ -148,7 +151,7 @@ def main():
             print("# sweep %s: %.2f ms/match" % (key, sweep[key]), file=sys.stderr, flush=True)
     best = min(sweep, key=sweep.get)
     bk, bs = conf[best]
-    canon = {key: v for key, v in sweep.items() if not conf[key][1] & bm.BM_LEVEL_MIN}
+    canon = {key: v for key, v in sweep.items() if not conf[key][1] & (bm.BM_LEVEL_MIN | bm.BM_HOIST)}
     canon_best = min(canon, key=canon.get) if canon else None
 
     # ---- the same match with the compression method: one result ciphertext
@@ -291,23 +294,29 @@ def main():
 
 
 def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
-    """The oracle as it stands on the same workload, group after group until
-    about `budget_s` of CPU time is spent (expansion counted once, as in one
-    query), scaled to templates/s."""
+    """The oracle as it stands on the same workload and schedule, group after
+    group until about `budget_s` of CPU time is spent (expansion counted once,
+    as in one query), scaled to templates/s."""
     from oracle import ckks, blindmatch as obm
     P = ckks.Params.preset(2)
     c, T = obm.layout(P, d, k)
-    keys = ckks.keygen(P, 0xB11D, obm.rotations_needed(P, d, k))
+    lmin, hoist, sch = bool(schedule & 0x100), bool(schedule & 0x400), schedule & 0xff
+    rots = set(obm.rotations_needed(P, d, k))
+    if hoist:
+        rots.update(obm.hoisted_rotations(P, d, k))
+    keys = ckks.keygen(P, 0xB11D, sorted(rots))
     m = ckks.encode(obm.pack_query(P, q.astype(np.float64), d), P.scale, P.N)
     cq = ckks.encrypt(P, keys.pk, m, len(P.q), P.scale, 0xB11D, 1)
     lg = obm.gallery_limbs(P, k)
     groups = obm.pack_gallery(P, X.astype(np.float64), d, k)
-    lmin, sch = bool(schedule & 0x100), schedule & 0xff
     t_l, ql = obm.level_min_shape(P, k, lg) if lmin else (lg, len(P.q))
     masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
     t0 = time.perf_counter()
     cq_used = ckks.drop_limbs(cq, ql) if lmin else cq
-    cu = [cq_used] if k == 1 else obm.expand(P, keys, cq_used, d, k, masks, mscale)
+    if k == 1:
+        cu = [cq_used]
+    else:
+        cu = (obm.expand_hoisted if hoist else obm.expand)(P, keys, cq_used, d, k, masks, mscale)
     dt = time.perf_counter() - t0          # matching time only; gallery encryption is setup
     done = 0
     for g, part_slots in enumerate(groups):
@@ -316,7 +325,8 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
         t1 = time.perf_counter()
         if lmin:
             gal = [ckks.drop_limbs(x, t_l) for x in gal]
-        ckks.drop_limbs(obm.hec3(P, keys, cu, gal, d, k, sch, rot_limbs=2 if lmin else None), 2)
+        out = obm.hec3(P, keys, cu, gal, d, k, sch, rot_limbs=2 if lmin else None, hoist=hoist)
+        ckks.drop_limbs(out, 2)
         dt += time.perf_counter() - t1
         done += min(T, X.shape[0] - g * T)
         if dt >= budget_s:

@@ -56,7 +56,7 @@ enum {
 enum { BM_S1 = 1, BM_S2 = 2 };   /* Alg. 2 schedules, see bm_match */
 /* OR-ed into a schedule: evaluate at the minimum level, and compress the
  * group outputs into few ciphertexts (see bm_match). */
-enum { BM_LEVEL_MIN = 0x100, BM_COMPRESS = 0x200 };
+enum { BM_LEVEL_MIN = 0x100, BM_COMPRESS = 0x200, BM_HOIST = 0x400 };
 
 typedef struct bm_ctx bm_ctx;
 typedef struct bm_sk bm_sk;
@@ -138,6 +138,10 @@ int bm_keygen(bm_ctx *ctx, uint64_t seed, const int32_t *rotations, size_t n_rot
  * parts: 2^t for t < log2(d/k), and -+(d/k) 2^t for t < log2 k.  Writes at
  * most `cap` values and the count to *n. */
 int bm_rotations_for(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
+/* Rotation amounts the hoisted schedule (BM_HOIST) uses: 1 .. c-1 for the
+ * rotate-and-sum and, when k > 1, every sum of Alg. 1's shifts over a
+ * non-empty subset of its steps (at most +-(k-1) c), c = d/k. */
+int bm_rotations_hoisted(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
 /* Rotation amounts the compression method (BM_COMPRESS) adds: -2^t for
  * t < log2(d/k). */
 int bm_rotations_compress(uint32_t d, uint32_t k, int32_t *out, size_t cap, size_t *n);
@@ -291,7 +295,14 @@ int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *ma
  * is at slot b c + (g mod c) of ciphertext floor(g / c).  Needs the keys of
  * bm_rotations_compress and one level more than the plain match (with
  * BM_LEVEL_MIN the products are taken at 4 limbs); BM_ELEVEL if the
- * gallery has no level to spare. */
+ * gallery has no level to spare.
+ * schedule | BM_HOIST: the rotations hoisted twice (one ModUp of c1, the
+ * automorphisms applied to the extended digits inside fused key inner
+ * products accumulated over Q_l u P, one ModDown).  Alg. 2's log2 c
+ * rotate-and-add steps become the sum of the c - 1 rotations 1 .. c-1 of
+ * the accumulator, and Alg. 1's log2 k steps of part i the sum over the
+ * non-empty subsets S of its steps of Rot(C_i, sum_{t in S} -+c 2^t).
+ * Same message, other bits; keys of bm_rotations_hoisted. */
 int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g,
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);

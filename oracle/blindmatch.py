@@ -165,10 +165,12 @@ def expand_hoisted(params, keys, cq, d, k, masks, mask_scale):
     return out
 
 
-def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None):
+def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None, hoist=False):
     """Alg. 2 on one gallery group: accumulate the products of the k parts,
     then log2(c) steps of C_out += Rot(C_out, 2^t).  With rot_limbs the
-    accumulator is first cut to that many limbs (exact drop)."""
+    accumulator is first cut to that many limbs (exact drop).  With hoist
+    (an option of this build) the log2(c) steps are evaluated as the one
+    hoisted sum C_out + sum_{r=1}^{c-1} Rot(C_out, r), the same message."""
     c, _ = layout(params, d, k)
     acc = None
     if schedule == S1:
@@ -186,9 +188,21 @@ def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None):
         raise ValueError("schedule")
     if rot_limbs is not None and rot_limbs < acc.limbs:
         acc = ckks.drop_limbs(acc, rot_limbs)
+    if hoist:
+        return ckks.rotation_sum_hoisted(params, acc, list(range(1, c)), keys.gks) if c > 1 else acc
     for t in range(log2_exact(c)):
         acc = ckks.hadd(params, acc, ckks.rotate(params, acc, 1 << t, keys.gks))
     return acc
+
+
+def hoisted_rotations(params, d, k):
+    """Rotation amounts of the hoisted schedule: 1 .. c-1 and, for k > 1,
+    the unrolled Alg. 1 amounts."""
+    c, _ = layout(params, d, k)
+    r = set(range(1, c))
+    if k > 1:
+        r.update(expansion_rotations_hoisted(params, d, k))
+    return sorted(r)
 
 
 EVAL_LIMBS = 3
@@ -290,7 +304,8 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
     With compress_mask = (plaintext, scale) the group outputs are compressed
     (all groups; the mask encoded at scale q_{rot limbs - 1}) and a list of
     compressed ciphertexts is returned instead of the dict over groups.
-    With hoist the expansion is expand_hoisted()."""
+    With hoist the expansion is expand_hoisted() and the rotate-and-sum the
+    hoisted sum of hec3()."""
     comp = compress_mask is not None
     if comp and groups is not None:
         raise ValueError("compression needs every group")
@@ -313,7 +328,7 @@ def match(params, keys, cq, gallery, d, k, schedule, masks=None, mask_scale=None
         cu = expand(params, keys, cq, d, k, masks, mask_scale)
     outs = {}
     for g in idx:
-        o = hec3(params, keys, cu, gallery[g], d, k, schedule, rot_limbs)
+        o = hec3(params, keys, cu, gallery[g], d, k, schedule, rot_limbs, hoist)
         if not comp and out_limbs is not None and out_limbs < o.limbs:
             o = ckks.drop_limbs(o, out_limbs)
         outs[g] = o

@@ -19,6 +19,7 @@ BM_ENOMEM, BM_EBUDGET, BM_EDEVICE, BM_EBUSY = -6, -7, -8, -9
 BM_S1, BM_S2 = 1, 2
 BM_LEVEL_MIN = 0x100
 BM_COMPRESS = 0x200
+BM_HOIST = 0x400
 
 
 class BMError(RuntimeError):
@@ -62,6 +63,7 @@ _SIGS = {
     "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
     "bm_rotations_for": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_rotations_compress": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
+    "bm_rotations_hoisted": (ctypes.c_int, [_u32, _u32, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_sk_export": (ctypes.c_int, [_P, _P, _sz]),
     "bm_pk_export": (ctypes.c_int, [_P, _u32, _P, _sz]),
     "bm_evk_export": (ctypes.c_int, [_P, _u64, _u32, _u32, _P, _sz]),
@@ -228,6 +230,15 @@ def bm_rotations_for(d, k):
     out = np.zeros(n.value, dtype=np.int32)
     _check(lib().bm_rotations_for(int(d), int(k), _ptr(out), out.size, ctypes.byref(n)), "bm_rotations_for")
     return [int(x) for x in out]
+
+
+def bm_rotations_hoisted(d, k):
+    n = _sz(0)
+    _check(lib().bm_rotations_hoisted(int(d), int(k), None, 0, ctypes.byref(n)), "bm_rotations_hoisted")
+    out = np.zeros(n.value, dtype=np.int32)
+    _check(lib().bm_rotations_hoisted(int(d), int(k), _ptr(out), out.size, ctypes.byref(n)),
+           "bm_rotations_hoisted")
+    return [int(v) for v in out]
 
 
 def bm_rotations_compress(d, k):

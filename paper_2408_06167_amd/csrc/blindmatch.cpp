@@ -41,7 +41,9 @@ Plan plan(const Ctx& c, uint32_t schedule, uint32_t k, int g_limbs, uint32_t out
   s.sched = schedule & 0xff;
   s.lmin = (schedule & BM_LEVEL_MIN) != 0;
   s.comp = (schedule & BM_COMPRESS) != 0;
-  if (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS)) BM_THROW(BM_EINVAL, "unknown schedule flags");
+  s.hoist = (schedule & BM_HOIST) != 0;
+  if (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS | BM_HOIST))
+    BM_THROW(BM_EINVAL, "unknown schedule flags");
   if (s.sched != BM_S1 && s.sched != BM_S2) BM_THROW(BM_EINVAL, "schedule must be BM_S1 or BM_S2");
   s.t = s.lmin ? std::min<int>(EVAL_LIMBS + (s.comp ? 1 : 0), g_limbs) : g_limbs;
   s.ql = k > 1 ? s.t + 1 : s.t;
@@ -72,17 +74,75 @@ void match_groups(Ctx& c, const bm_evk* evk, const Plan& p, const u64* cu, int n
                   const bm_gallery& g, const u64* cmask, u64* out, size_t out_qstride) {
   if (!p.comp) {
     hec3_groups(c, evk, cu, nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, p.t, p.sched, p.rot,
-                p.ol, out, out_qstride);
+                p.ol, out, out_qstride, p.hoist);
     return;
   }
   if (!cmask) BM_THROW(BM_EINVAL, "compression mask missing");
   const size_t per = (size_t)g.groups * 2 * p.rot * c.N;
   DBuf tmp(&c, (size_t)nq * per);
   hec3_groups(c, evk, cu, nq, cu_stride, g.d, g.k, g.buf.p(), g.groups, (int)g.limbs, p.t, p.sched, p.rot,
-              p.rot, tmp.p(), per);
+              p.rot, tmp.p(), per, p.hoist);
   for (int j = 0; j < nq; ++j)
     compress(c, evk, tmp.p() + j * per, (size_t)2 * p.rot * c.N, g.groups, g.d, g.k, cmask, p.rot, p.ol,
              out + j * out_qstride);
+}
+
+// Galois elements of a hoisted rotation sum, split into launches of at most
+// HOIST_MAX elements; amounts[z][a] (per_elem) or amounts[0][a] for every element.
+static std::vector<HoistArgs> hoist_args(const Ctx& c, const bm_evk* evk,
+                                         const std::vector<std::vector<long>>& amounts, bool per_elem,
+                                         std::vector<const u64*>& keys) {
+  std::vector<HoistArgs> hs;
+  const int A = (int)amounts[0].size();
+  const int Z = per_elem ? (int)amounts.size() : 1;
+  if (per_elem && A * Z > HOIST_MAX) BM_THROW(BM_EINVAL, "too many hoisted rotations per launch");
+  const int per = per_elem ? A : HOIST_MAX;
+  for (int a0 = 0; a0 < A; a0 += per) {
+    HoistArgs h{};
+    h.A = std::min(per, A - a0);
+    h.per_elem = per_elem ? 1 : 0;
+    for (int z = 0; z < Z; ++z)
+      for (int a = 0; a < h.A; ++a) {
+        const u64 g = ev::galois_for_rotation(c, amounts[z][a0 + a]);
+        keys.push_back(galois_key(evk, g));                 // BM_ENOKEY when missing
+        h.g[per_elem ? z * h.A + a : a] = (uint32_t)g;
+      }
+    hs.push_back(h);
+  }
+  return hs;
+}
+
+// Rotation amounts of part i once Alg. 1's steps are unrolled: one per
+// non-empty subset S of the log2 k steps, sum over t in S of -c 2^t (bit t
+// of i is 0) or +c 2^t (bit t of i is 1), in increasing order of S.
+static std::vector<long> expansion_amounts(u32 d, u32 k, u32 i) {
+  const long cc = d / k;
+  std::vector<long> out;
+  for (u32 S = 1; S < k; ++S) {
+    long r = 0;
+    for (int t = 0; (1u << t) < k; ++t)
+      if ((S >> t) & 1) r += ((i >> t) & 1) ? (cc << t) : -(cc << t);
+    out.push_back(r);
+  }
+  return out;
+}
+
+void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
+                    u64* out) {
+  const size_t N = c.N;
+  const int l = qlimbs, nl = qlimbs - 1;
+  if (nl < 1) BM_THROW(BM_ELEVEL, "expansion needs two limbs");
+  const size_t ln = (size_t)l * N;
+  DBuf pm(&c, (size_t)k * 2 * ln);
+  for (int comp = 0; comp < 2; ++comp)
+    kern::mul(c, q + comp * ln, 0, masks, (size_t)(c.L + 1) * N, pm.p() + comp * ln, 2 * ln, (int)k,
+              kern::chain_map(l));
+  ev::rescale(c, pm.p(), (int)k, 2, l, out);
+  std::vector<std::vector<long>> amounts;
+  for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
+  std::vector<const u64*> keys;
+  const std::vector<HoistArgs> hs = hoist_args(c, evk, amounts, true, keys);
+  ev::rotation_sum_hoisted(c, evk, out, (int)k, nl, hs, keys, out);
 }
 
 void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
@@ -114,7 +174,7 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
 
 void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
                  const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
-                 u64* out, size_t out_qstride) {
+                 u64* out, size_t out_qstride, bool hoist) {
   const size_t N = c.N;
   const int nl = l - 1;
   if (nl < 1 || l > lg_store) BM_THROW(BM_ELEVEL, "matching needs two limbs");
@@ -127,11 +187,21 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
   const u32 cc = d / k;
   const int rots = ilog2(cc);
   const u64* rlk = evk->rlk.k.p();
-  std::vector<const u64*> gks(rots);
-  std::vector<u64> gel(rots);
-  for (int t = 0; t < rots; ++t) {
-    gel[t] = ev::galois_for_rotation(c, 1L << t);
-    gks[t] = galois_key(evk, gel[t]);
+  std::vector<const u64*> gks(hoist ? 0 : rots);
+  std::vector<u64> gel(hoist ? 0 : rots);
+  std::vector<const u64*> hkeys;
+  std::vector<HoistArgs> hs;
+  if (hoist) {            // rotate-and-sum as one hoisted sum of the rotations 1 .. c-1
+    if (cc > 1) {
+      std::vector<std::vector<long>> amounts(1);
+      for (u32 r = 1; r < cc; ++r) amounts[0].push_back((long)r);
+      hs = hoist_args(c, evk, amounts, false, hkeys);
+    }
+  } else {
+    for (int t = 0; t < rots; ++t) {
+      gel[t] = ev::galois_for_rotation(c, 1L << t);
+      gks[t] = galois_key(evk, gel[t]);
+    }
   }
   // batch = (query, group) pairs; `chunk` bounds the pairs per pass
   u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 16 : 64);
@@ -170,9 +240,16 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
       a = racc.p();
       b = acc.p();                        // acc is free again and large enough
     }
-    for (int t = 0; t < rots; ++t) {
-      ev::rotate(c, a, B, rot_limbs, gel[t], gks[t], b, true);
-      std::swap(a, b);
+    if (hoist) {
+      if (!hs.empty()) {
+        ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, b);
+        std::swap(a, b);
+      }
+    } else {
+      for (int t = 0; t < rots; ++t) {
+        ev::rotate(c, a, B, rot_limbs, gel[t], gks[t], b, true);
+        std::swap(a, b);
+      }
     }
     kern::copy_limbs(c, a, 2 * rln, rln, out + g0 * oct, Bg, out_qstride, oct, (size_t)out_limbs * N,
                      B, 2, out_limbs);

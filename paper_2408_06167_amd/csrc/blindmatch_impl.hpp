@@ -12,6 +12,7 @@ struct Plan {
   uint32_t sched = 0;   // BM_S1 or BM_S2
   bool lmin = false;    // BM_LEVEL_MIN
   bool comp = false;    // BM_COMPRESS
+  bool hoist = false;   // BM_HOIST
   int t = 0, ql = 0, rot = 0, ol = 0;
 };
 // products of the minimum-level schedule (one limb more with compression)
@@ -41,9 +42,13 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
 // at its first l limbs; the accumulator is cut to rot_limbs before the
 // rotate-and-sum; the result of (j, g) goes to
 // out + j*out_qstride + g*2*out_limbs*N.
+// With hoist the rotate-and-sum is one hoisted sum of the rotations 1 .. c-1.
 void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
                  const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
-                 u64* out, size_t out_qstride);
+                 u64* out, size_t out_qstride, bool hoist);
+// Alg. 1 with its log2 k steps unrolled into one hoisted rotation sum per part
+void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
+                    u64* out);
 
 // Compression method: in holds G HE-C^3 outputs [2][rl][N] at stride
 // in_stride; mask [rl..][N] is the score mask at scale q_{rl-1};

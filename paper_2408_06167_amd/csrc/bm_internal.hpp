@@ -120,6 +120,15 @@ struct ModUpTable {                       // one per level (number of chain limb
   ModUpDigit d[MAX_DIGITS];
 };
 
+// Galois elements of a hoisted rotation sum, passed by value to the kernels:
+// g[a] for amount a of every element, or g[z * A + a] per element z.
+constexpr int HOIST_MAX = 256;
+struct HoistArgs {
+  uint32_t g[HOIST_MAX];
+  int A;
+  int per_elem;
+};
+
 struct ModDownTable {
   int K;
   int pprime[4];                          // prime ids of the special primes
@@ -364,6 +373,14 @@ void zero(const Ctx& c, u64* out, size_t words);
 // out[idx[z]] = in[z]; idx_dev is a device array of B indices <= max_idx
 void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const uint32_t* idx_dev,
               uint32_t max_idx, bool scatter, int B, size_t words);
+// (u, w)[z] = sum_a KIP(phi_{g(z,a)}(y[z]), key_{g(z,a)}); gtab[g/2] holds the
+// key of element g; `keys` lists the keys used (launch check)
+void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
+               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, int B,
+               int limbs, bool accumulate);
+// out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) over `limbs` limbs of one component
+void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const HoistArgs& h, int B,
+               int limbs, bool accumulate);
 }  // namespace kern
 
 }  // namespace bm
@@ -396,6 +413,7 @@ struct bm_evk {
   bm_ctx* ctx = nullptr;
   bm_switch_key rlk;
   std::map<uint64_t, std::unique_ptr<bm_switch_key>> gk;   // by Galois element
+  bm::DBuf gtab;           // [N] device addresses of the Galois keys, at g / 2 (0 if absent)
 };
 
 struct bm_masks {

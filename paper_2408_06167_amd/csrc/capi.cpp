@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <set>
 #include <thread>
 
 #include "blindmatch_impl.hpp"
@@ -251,6 +252,27 @@ int bm_rotations_compress(uint32_t d, uint32_t k, int32_t* out, size_t cap, size
   });
 }
 
+int bm_rotations_hoisted(uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {
+  return guarded(nullptr, [&] {
+    REQUIRE(n, BM_EINVAL, "n is NULL");
+    REQUIRE(bmx::is_pow2(d) && bmx::is_pow2(k) && k <= d, BM_EDIM, "power-of-two k | d");
+    const int32_t c = (int32_t)(d / k);
+    std::set<int32_t> r;
+    for (int32_t j = 1; j < c; ++j) r.insert(j);
+    for (uint32_t i = 0; i < k; ++i)
+      for (uint32_t S = 1; S < k; ++S) {
+        int32_t a = 0;
+        for (int t = 0; (1u << t) < k; ++t)
+          if ((S >> t) & 1) a += ((i >> t) & 1) ? (c << t) : -(c << t);
+        r.insert(a);
+      }
+    std::vector<int32_t> v(r.begin(), r.end());
+    *n = v.size();
+    if (out)
+      for (size_t i = 0; i < std::min(cap, v.size()); ++i) out[i] = v[i];
+  });
+}
+
 int bm_rotations_enroll(const bm_ctx* ctx, uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {
   return guarded(nullptr, [&] {
     REQUIRE(ctx && n, BM_EINVAL, "NULL argument");
@@ -298,6 +320,12 @@ int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot
         ev::keygen_switch(c, seed, ev::DOM_GK_A, ev::DOM_GK_E, g * (u64)c.dnum, s.get(), sg.p(), key->k);
         e->gk.emplace(g, std::move(key));
       }
+      // device table of the Galois keys by g / 2, for the hoisted rotation sums
+      std::vector<u64> tab(c.N, 0);
+      for (auto& kv : e->gk) tab[kv.first >> 1] = (u64)(uintptr_t)kv.second->k.p();
+      e->gtab = DBuf(&c, c.N);
+      HIP_OK(dev::memcpy_async(e->gtab.p(), tab.data(), c.N * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+      sync(c);
     }
     sync(c);
     if (sk) *sk = s.release();
@@ -904,7 +932,7 @@ static void match_body(Ctx& c, const bm_evk* evk, const u64* q, uint32_t q_limbs
   DBuf expanded;
   if (k > 1) {
     expanded = DBuf(&c, (size_t)k * 2 * s.t * c.N);
-    bmx::expand(c, evk, qq, s.ql, m->pt.p(), g->d, k, expanded.p());
+    (s.hoist ? bmx::expand_hoisted : bmx::expand)(c, evk, qq, s.ql, m->pt.p(), g->d, k, expanded.p());
     cu = expanded.p();
   }
   bmx::match_groups(c, evk, s, cu, 1, 0, *g, cmask, out, 0);
@@ -1049,7 +1077,8 @@ static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, 
         ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.ql, cut.p());
         qq = cut.p();
       }
-      bmx::expand(c, evk, qq, s.ql, m->pt.p(), g->d, k, cu.p() + j * cu_stride);
+      (s.hoist ? bmx::expand_hoisted : bmx::expand)(c, evk, qq, s.ql, m->pt.p(), g->d, k,
+                                                    cu.p() + j * cu_stride);
       cu_scale = q->scale * m->scale / (double)c.primes[s.ql - 1].q;
     }
   }

@@ -252,15 +252,14 @@ void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* ke
   key_switch2(c, x, sx, B, limbs, key, key, 31, add0, sa0, add1, sa1, out, so);
 }
 
-void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key0, const u64* key1,
-                 int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
+// ModUp of every digit of x (evaluation domain) to the extended basis, back
+// in evaluation form: y [B][beta][ext][N] (the digit's own slots unused).
+static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const size_t N = c.N;
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
-  // 1. coefficient form of the input
   DBuf xc(&c, (size_t)B * limbs * N);
   kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true);
-  // 2. ModUp every digit to the extended basis, then back to evaluation form
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
   kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
@@ -272,11 +271,16 @@ void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* k
     ++m.n;
   }
   kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
-  // 3. key inner product over Q_l u P
+  return y;
+}
+
+// ModDown of (u, w) [B][2][ext][N] over Q_l u P plus the addends:
+// out = (add0 + ModDown(u), add1 + ModDown(w))
+static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
+                        size_t sa1, u64* out, size_t so) {
+  const size_t N = c.N;
+  const int ext = c.h_modup[limbs].ext;
   const size_t suw = (size_t)2 * ext * N;
-  DBuf uw(&c, (size_t)B * suw);
-  kern::kip(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs);
-  // 4. ModDown: special limbs to coefficient form, convert, back, subtract, scale by P^-1
   LimbMap mp{};
   for (int comp = 0; comp < 2; ++comp)
     for (int kk = 0; kk < c.K; ++kk) {
@@ -284,12 +288,38 @@ void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* k
       mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
       ++mp.n;
     }
-  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true);
+  kern::ntt(c, uw, suw, uw, suw, B, mp, true);
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
-  kern::moddown_conv(c, uw.p(), suw, conv.p(), sc, B, limbs);
+  kern::moddown_conv(c, uw, suw, conv.p(), sc, B, limbs);
   kern::ntt(c, conv.p(), (size_t)limbs * N, conv.p(), (size_t)limbs * N, 2 * B, kern::chain_map(limbs), false);
-  kern::moddown_finish(c, uw.p(), suw, conv.p(), sc, add0, sa0, add1, sa1, out, so, B, limbs);
+  kern::moddown_finish(c, uw, suw, conv.p(), sc, add0, sa0, add1, sa1, out, so, B, limbs);
+}
+
+void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* key0, const u64* key1,
+                 int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  const size_t sy = (size_t)tb.beta * tb.ext * c.N, suw = (size_t)2 * tb.ext * c.N;
+  DBuf y = modup_eval(c, x, sx, B, limbs);
+  DBuf uw(&c, (size_t)B * suw);
+  kern::kip(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs);
+  moddown_add(c, uw.p(), B, limbs, add0, sa0, add1, sa1, out, so);
+}
+
+void rotation_sum_hoisted(Ctx& c, const bm_evk* evk, const u64* in, int B, int limbs,
+                          const std::vector<HoistArgs>& hs, const std::vector<const u64*>& keys, u64* out) {
+  const size_t N = c.N, ln = (size_t)limbs * N;
+  const ModUpTable& tb = c.h_modup[limbs];
+  const size_t sy = (size_t)tb.beta * tb.ext * N, suw = (size_t)2 * tb.ext * N;
+  if (hs.empty()) BM_THROW(BM_EINVAL, "no rotation amounts");
+  DBuf y = modup_eval(c, in + ln, 2 * ln, B, limbs);
+  DBuf uw(&c, (size_t)B * suw), c0(&c, (size_t)B * ln);
+  for (size_t part = 0; part < hs.size(); ++part) {   // amount lists longer than one launch carries
+    kern::kip_hoist(c, y.p(), sy, in + ln, 2 * ln, (const u64* const*)evk->gtab.p(), hs[part], keys, uw.p(),
+                    suw, B, limbs, part > 0);
+    kern::autom_sum(c, in, 2 * ln, c0.p(), ln, hs[part], B, limbs, part > 0);
+  }
+  moddown_add(c, uw.p(), B, limbs, c0.p(), ln, in + ln, 2 * ln, out, 2 * ln);
 }
 
 void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {

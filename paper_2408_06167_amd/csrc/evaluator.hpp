@@ -27,6 +27,13 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
 // batch element z rotates with (g1, key1) when bit `sel` of z is set, else (g0, key0)
+// out[z] = in[z] + sum_a Rot(in[z], r(z, a)) with the rotations hoisted twice:
+// one ModUp of c1, the automorphisms applied to the extended digits inside
+// fused key inner products that accumulate over Q_l u P, one ModDown.  The
+// amounts come in one or more HoistArgs (each at most HOIST_MAX Galois
+// elements); `keys` lists the keys used (for the launch check).
+void rotation_sum_hoisted(Ctx& c, const bm_evk* evk, const u64* in, int B, int limbs,
+                          const std::vector<HoistArgs>& hs, const std::vector<const u64*>& keys, u64* out);
 // out = addend + Rot(in) (out may alias addend, not in)
 void rotate_add(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, const u64* addend,
                 u64* out);

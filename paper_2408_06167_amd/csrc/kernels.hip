@@ -601,6 +601,85 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   }
 }
 
+// Position of the source word of an automorphism X -> X^g in the bit-reversed
+// evaluation domain: out[i] = in[src].
+__device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n) {
+  const u32 rj = __brev(i) >> (32 - log_n);
+  const u32 e = (u32)(((u64)(2 * rj + 1) * g) & ((2u << log_n) - 1));
+  return __brev((e - 1) >> 1) >> (32 - log_n);
+}
+
+// Hoisted key inner products: for element z,
+//   (u, w)[z] = sum_a sum_j phi_{g(z,a)}(y_j[z]) * key_{g(z,a), j}     over Q_l u P,
+// the automorphism read as a gather (an aligned block of consecutive words
+// maps onto an aligned block).  Keys come from the key table (indexed by
+// g / 2).  Each thread keeps HZ elements, so that a key word is read once
+// for all of them when the elements share their Galois elements.
+constexpr int HZ = 4;
+__global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
+                            HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
+                            const PrimeC* P, int log_n, int B, int accumulate) {
+  const ModUpTable& tb = *T;
+  const int N = 1 << log_n;
+  const int t = blockIdx.y;
+  const int ext = tb.ext;
+  const PrimeC& pr = P[tb.ext_prime[t]];
+  const u64 q = pr.q;
+  const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
+  const int z0 = blockIdx.z * HZ;
+  const int nz = min(HZ, B - z0);
+  EW_LOOP {
+    u64 su[HZ] = {}, sw[HZ] = {};
+    for (int a = 0; a < h.A; ++a) {
+#pragma unroll
+      for (int zz = 0; zz < HZ; ++zz) {
+        if (zz >= nz) break;
+        const int z = z0 + zz;
+        const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+        const u32 src = autom_src((u32)i, g, log_n);
+        const u64* key = gtab[g >> 1];
+        for (int j = 0; j < tb.beta; ++j) {
+          const ModUpDigit& dg = tb.d[j];
+          const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+          const u64 v = own ? x[(size_t)z * sx + (size_t)t * N + src]
+                            : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src];
+          const u64* kb = key + ((size_t)(2 * j) * key_limbs + kl) * N;
+          const u64* ka = key + ((size_t)(2 * j + 1) * key_limbs + kl) * N;
+          su[zz] = add_mod(su[zz], mont_mul(v, kb[i], q, pr.qn), q);
+          sw[zz] = add_mod(sw[zz], mont_mul(v, ka[i], q, pr.qn), q);
+        }
+      }
+    }
+#pragma unroll
+    for (int zz = 0; zz < HZ; ++zz) {
+      if (zz >= nz) break;
+      u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
+      U[i] = accumulate ? add_mod(U[i], su[zz], q) : su[zz];
+      U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], sw[zz], q) : sw[zz];
+    }
+  }
+}
+
+// out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
+// (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in)
+__global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, HoistArgs h, const PrimeC* P,
+                            int log_n, int accumulate) {
+  const int N = 1 << log_n;
+  const int l = blockIdx.y;
+  const int z = blockIdx.z;
+  const u64 q = P[l].q;
+  const u64* I = in + (size_t)z * si + (size_t)l * N;
+  u64* O = out + (size_t)z * so + (size_t)l * N;
+  EW_LOOP {
+    u64 acc = accumulate ? O[i] : I[i];
+    for (int a = 0; a < h.A; ++a) {
+      const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+      acc = add_mod(acc, I[autom_src((u32)i, g, log_n)], q);
+    }
+    O[i] = acc;
+  }
+}
+
 // conv[c][i] = sum_k [u_c[p_k] (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}   (coefficient domain)
 __global__ void k_moddown_conv(const u64* uw, size_t suw, u64* conv, size_t sc,
                                const ModDownTable* D, int limbs, const PrimeC* P, int N) {
@@ -1006,6 +1085,37 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
           2.0 * c.N * tb.ext * tb.beta * B);
   LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown, key0, key1, sel,
          uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
+               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, int B,
+               int limbs, bool accumulate) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
+  if (h.A < 1 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
+  chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "hoisted kip digits");
+  chk(y_own, B, sown, 0, (size_t)limbs * c.N, "hoisted kip input");
+  chk(gtab, 1, 0, 0, c.N, "key table");
+  for (const u64* key : keys) chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "hoisted kip key");
+  chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "hoisted kip output");
+  const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
+  Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
+          2.0 * c.N * tb.ext * tb.beta * B * h.A);
+  LAUNCH(k_kip_hoist, ew_grid(c.N, tb.ext, (B + HZ - 1) / HZ), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
+         gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B,
+         accumulate ? 1 : 0);
+  check_launch();
+}
+
+void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const HoistArgs& h, int B,
+               int limbs, bool accumulate) {
+  if (h.A < 0 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
+  chk(in, B, si, 0, (size_t)limbs * c.N, "autom_sum input");
+  chk(out, B, so, 0, (size_t)limbs * c.N, "autom_sum output");
+  Prof pf(c, "autom_sum", 8.0 * c.N * B * limbs * (h.A + 2), (double)c.N * B * limbs * h.A);
+  LAUNCH(k_autom_sum, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes,
+         c.log_n, accumulate ? 1 : 0);
   check_launch();
 }
 

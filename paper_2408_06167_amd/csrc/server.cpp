@@ -122,7 +122,8 @@ struct bm_server {
           ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, ql, cut.p());
           qq = cut.p();
         }
-        bmx::expand(c, evk, qq, ql, G.masks->pt.p(), g.d, g.k, cu.p() + j * cu_stride);
+        (p.hoist ? bmx::expand_hoisted : bmx::expand)(c, evk, qq, ql, G.masks->pt.p(), g.d, g.k,
+                                                      cu.p() + j * cu_stride);
         cu_scale = q.scale * G.masks->scale / (double)c.primes[ql - 1].q;
       }
       if (cu_scale != g.scale) BM_THROW(BM_ESCALE, "query and gallery scales differ");
@@ -243,7 +244,8 @@ int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, 
                      bm_server** out) {
   if (!ctx || !evk || !out || hbm_budget_bytes == 0) return BM_EINVAL;
   const uint32_t base = schedule & 0xff;
-  if ((base != BM_S1 && base != BM_S2) || (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS)))
+  if ((base != BM_S1 && base != BM_S2) ||
+      (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS | BM_HOIST)))
     return BM_EINVAL;
   try {
     std::unique_ptr<bm_server> s(new bm_server);

@@ -21,6 +21,8 @@ def flow(preset, shapes, n_templates):
         rots.update(bm.bm_rotations_for(d, k))
         rots.update(bm.bm_rotations_compress(d, k))
         rots.update(bm.bm_rotations_enroll(ctx, d, k))
+        if d // k <= 32:
+            rots.update(bm.bm_rotations_hoisted(d, k))
     sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(rots))
     rng = np.random.default_rng(0)
     words = rng.integers(0, 1 << 40, size=(2, L1, N), dtype=np.uint64)
@@ -61,6 +63,12 @@ def flow(preset, shapes, n_templates):
                 bm.bm_result_free(r)
         # compression: needs one level more than the plain match
         can_compress = preset == 2 or k == 1
+        if d // k <= 32:
+            for s in (1 | bm.BM_HOIST, 2 | bm.BM_HOIST | bm.BM_LEVEL_MIN):
+                bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
+                r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
+                bm.bm_decrypt_scores(ctx, sk, r, n_templates)
+                bm.bm_result_free(r)
         for s in (2 | bm.BM_COMPRESS, 1 | bm.BM_LEVEL_MIN | bm.BM_COMPRESS):
             bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
             try:

@@ -34,6 +34,11 @@ def oracle_keys(preset, rots):
     return P, ckks.keygen(P, SEED, list(rots))
 
 
+# shapes whose hoisted-schedule keys are generated too (c - 1 + unrolled Alg. 1
+# keys each; the k = 1, 2 shapes at N = 2^16 would need 63 to 127 more)
+HOIST_SHAPES = {1: None, 2: [(128, 4)]}
+
+
 def all_rotations(preset, shapes):
     P = ckks.Params.preset(preset)
     r = set()
@@ -41,6 +46,8 @@ def all_rotations(preset, shapes):
         r.update(obm.rotations_needed(P, d, k))
         r.update(obm.compress_rotations(P, d, k))
         r.update(obm.enroll_rotations(P, d, k))
+        if HOIST_SHAPES[preset] is None or (d, k) in HOIST_SHAPES[preset]:
+            r.update(obm.hoisted_rotations(P, d, k))
     return tuple(sorted(r))
 
 

@@ -29,7 +29,8 @@ def words_of(bm, ctx, res, N):
 
 
 @pytest.mark.parametrize("preset,d,k,schedule", [(1, 16, 1, 1), (1, 16, 4, 2), (2, 128, 2, 2),
-                                                 (2, 128, 4, 0x102), (2, 128, 4, 0x302)])
+                                                 (2, 128, 4, 0x102), (2, 128, 4, 0x302), (2, 128, 4, 0x502),
+                                                 (1, 16, 4, 0x402)])
 def test_graph_replay_equals_eager(bm, preset, d, k, schedule):
     ctx = lib_ctx(preset)
     sk, pk, evk = keys(preset)
@@ -83,7 +84,7 @@ def test_match_batch_equals_individual(bm):
             pairs.append((q, g, X, k))
     order = list(rng.permutation(len(pairs)))
     pairs = [pairs[i] for i in order]
-    for schedule in (1, 2, 0x102, 0x202):
+    for schedule in (1, 2, 0x102, 0x202, 0x402):
         # at N = 2^12 only the k = 1 galleries have a level to spare for compression
         sel = [pr for pr in pairs if pr[3] == 1] if schedule & bm.BM_COMPRESS else pairs
         outs = bm.bm_match_batch(ctx, evk, [pr[0] for pr in sel], [pr[1] for pr in sel], schedule=schedule)

@@ -190,7 +190,7 @@ def test_op_errors(bm):
         bm.bm_op_add(ctx, a, c)
     assert e.value.code == bm.BM_ESCALE
     with pytest.raises(bm.BMError) as e:
-        bm.bm_op_rotate(ctx, evk, a, 3)
+        bm.bm_op_rotate(ctx, evk, a, 1001)          # no key for this amount
     assert e.value.code == bm.BM_ENOKEY
     one = bm.bm_op_drop(ctx, a, 1)
     with pytest.raises(bm.BMError) as e:
@@ -421,6 +421,94 @@ def test_match_face_scale_compressed_bit_exact(bm, k, schedule):
     got, sc = bm.bm_result_export(ctx, res, 0, P.N)
     assert sc == want[0].scale
     assert_words_equal(got, ct_words(want[0]), "compressed ciphertext")
+    scores = bm.bm_decrypt_scores(ctx, sk, res, X.shape[0])
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == w["known"]
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    bm.bm_masks_free(lm)
+
+
+# ------------------------------------------------------------------ hoisted schedule
+
+@pytest.mark.parametrize("d,k,schedule", [(16, 1, 0x401), (16, 2, 0x402), (16, 4, 0x401), (8, 8, 0x402),
+                                          (16, 4, 0x502), (16, 1, 0x701)])
+def test_match_hoisted_small_ring_bit_exact(bm, d, k, schedule):
+    """N = 2^12, BM_HOIST (with the minimum level and compression too): every
+    word equals the oracle's hoisted schedule."""
+    P, okeys, ctx, sk, pk, evk = setup(1)
+    rng = np.random.default_rng(d * 13 + k + schedule)
+    c, T = obm.layout(P, d, k)
+    R = T + T // 2
+    X = normalize_rows(rng.standard_normal((R, d)))
+    qv = X[R // 2] + 0.02 * rng.standard_normal(d)
+    qv = qv / np.linalg.norm(qv)
+    log("hoisted match N=2^12 d=%d k=%d schedule %#x" % (d, k, schedule))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 29)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 4000)
+    level_min, comp = bool(schedule & 0x100), bool(schedule & 0x200)
+    ql = obm.level_min_shape(P, k, lg, comp)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
+    cmask = obm.compress_mask_coeffs(P, d, k, obm.compressed_rot_limbs(P, k, lg, level_min=level_min)) \
+        if comp else None
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, level_min=level_min,
+                     compress_mask=cmask, hoist=True)
+    want = want if comp else [want[g] for g in sorted(want)]
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=0)
+    n_out, limbs, _ = bm.bm_result_info(res)
+    assert n_out == len(want)
+    for o in range(n_out):
+        got, sc = bm.bm_result_export(ctx, res, o, P.N)
+        assert sc == want[o].scale
+        assert_words_equal(got, ct_words(want[o]), "result %d" % o)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, R)
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    if lm:
+        bm.bm_masks_free(lm)
+
+
+def normalize_rows(X):
+    return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("schedule", [0x502, 0x402])
+def test_match_face_scale_hoisted_sampled(bm, schedule):
+    """N = 2^16, 6,144 x 128-dim, k = 4, hoisted: two sampled groups word for
+    word against the oracle, scores against the cosine."""
+    P, okeys, ctx, sk, pk, evk = setup(2)
+    d, k = 128, 4
+    w = face_gallery(seed=2)
+    X, qv = w["gallery"], w["query_known"]
+    log("hoisted match N=2^16 k=4 schedule %#x: oracle gallery encryption" % schedule)
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 5000)
+    G = len(gal_o)
+    level_min = bool(schedule & 0x100)
+    ql = obm.level_min_shape(P, k, lg)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql)
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, X.shape[0])
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
+    log("library match")
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
+    log("oracle match on sampled groups")
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
+                     groups=[0, G - 1], level_min=level_min, hoist=True)
+    for g, o in want.items():
+        got, sc = bm.bm_result_export(ctx, res, g, P.N)
+        assert sc == o.scale
+        assert_words_equal(got, ct_words(o), "group %d" % g)
     scores = bm.bm_decrypt_scores(ctx, sk, res, X.shape[0])
     cos = X.astype(np.float64) @ qv.astype(np.float64)
     assert np.max(np.abs(scores - cos)) < 1e-4

@@ -378,3 +378,28 @@ def test_hoisted_rotation_sum_single_amount_is_a_rotation(tiny_setup):
     zh, zp = ckks.decrypt_decode(P, keys.s, h), ckks.decrypt_decode(P, keys.s, plain)
     assert np.max(np.abs(zh - (z + np.roll(z, -r)))) < 1e-9
     assert np.max(np.abs(zh - zp)) < 1e-9
+
+
+@pytest.mark.parametrize("d,k,schedule", [(8, 1, bm.S1), (8, 2, bm.S2), (16, 4, bm.S2), (32, 1, bm.S2)])
+def test_hoisted_match_equals_slot_sim(tiny_setup, d, k, schedule):
+    """Hoisted schedule: the rotate-and-sum as one hoisted sum of the c - 1
+    rotations, the expansion hoisted; every slot equals the simulator."""
+    P, _ = tiny_setup
+    keys = ckks.keygen(P, 0xB11D, rotations=bm.hoisted_rotations(P, d, k))
+    rng = np.random.default_rng(d * 11 + k)
+    c, T = bm.layout(P, d, k)
+    R = 2 * T - 1
+    X = rng.standard_normal((R, d)) / np.sqrt(d)
+    q = rng.standard_normal(d) / np.sqrt(d)
+    qslots = bm.pack_query(P, q, d)
+    cq = ckks.encrypt(P, keys.pk, ckks.encode(qslots, P.scale, P.N), len(P.q), P.scale, 6, 1)
+    lg = bm.gallery_limbs(P, k)
+    gal_slots = bm.pack_gallery(P, X, d, k)
+    gallery = [[ckks.encrypt(P, keys.pk, ckks.encode(v, P.scale, P.N), lg, P.scale, 6, 100 + 10 * g + i)
+                for i, v in enumerate(parts)] for g, parts in enumerate(gal_slots)]
+    masks, mscale = bm.mask_coeffs(P, d, k, len(P.q))
+    outs = bm.match(P, keys, cq, gallery, d, k, schedule, masks, mscale, out_limbs=2, hoist=True)
+    sim_u = slot_sim.expand(qslots, d, k)
+    for g, o in outs.items():
+        got = ckks.decrypt_decode(P, keys.s, o)
+        assert np.max(np.abs(got - slot_sim.hec3(sim_u, gal_slots[g], d, k))) < 1e-8
