@@ -5,7 +5,7 @@
 //                        bit-reversed order unless stated otherwise
 //   ciphertext          [comps][limbs][N]   (comps = 2, or 3 after a tensor)
 //   ciphertext batch    [B][comps][limbs][N] with a per-batch element stride
-//   switching key       [dnum][2][L+1+K][N] evaluation domain, Montgomery form
+//   switching key       [dnum][2][L+1+K][N] evaluation domain
 //   gallery             [G][k][2][limbs][N]
 // Limb l < L+1 is chain prime q_l; limb L+1+k is special prime p_k.
 #pragma once
@@ -332,7 +332,7 @@ void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
 void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
          int B, const LimbMap& m);
 void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m);
-// o = a * R mod q (Montgomery form for switching keys)
+// o = a * R mod q (Montgomery form)
 void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m);
 // o_limb += s_limb * scalar[limb] (scalar per limb slot, Shoup pair list)
 void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2] device*/,
@@ -349,7 +349,7 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
 // ModUp of every digit: coefficient-domain x [l] -> y[j][t] for every target slot t
 // outside digit j (coefficient domain); y is [beta][ext][N] per batch element
 void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs);
-// key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext], key Montgomery)
+// key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext])
 // batch element z uses key1 when bit `sel` of z is set, else key0
 void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
          const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs);
@@ -406,7 +406,7 @@ struct bm_pk {
 };
 
 struct bm_switch_key {
-  bm::DBuf k;              // [dnum][2][L+1+K][N] evaluation domain, Montgomery form
+  bm::DBuf k;              // [dnum][2][L+1+K][N] evaluation domain
 };
 
 struct bm_evk {

@@ -363,8 +363,6 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
     REQUIRE(words && comp < 2 && (int)digit < c.dnum && n_words == ln, BM_EINVAL, "evk export size");
     const u64* key = galois == 0 ? evk->rlk.k.p() : bmx::galois_key(evk, galois);
     c.use_stream(nullptr);
-    // undo the Montgomery form (multiply by 1 in Montgomery = divide by R) via a
-    // plain product with R^{-1}: done on the host after the coefficient export
     DBuf tmp(&c, ln);
     HIP_OK(dev::memcpy_async(tmp.p(), key + (size_t)(2 * digit + comp) * ln, ln * sizeof(u64),
                           hipMemcpyDeviceToDevice, c.stream));
@@ -372,12 +370,6 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
     kern::ntt(c, tmp.p(), 0, tmp.p(), 0, 1, all, true);
     HIP_OK(dev::memcpy_async(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
     sync(c);
-    for (int l = 0; l < np; ++l) {
-      const u64 q = c.primes[l].q;
-      const u64 r1 = (u64)(((u128)1 << 64) % q);
-      const u64 rinv = h_invmod(r1, q);
-      for (size_t i = 0; i < c.N; ++i) words[(size_t)l * c.N + i] = h_mulmod(words[(size_t)l * c.N + i], rinv, q);
-    }
   });
 }
 

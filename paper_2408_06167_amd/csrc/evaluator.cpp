@@ -564,7 +564,6 @@ void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const
     kern::axpy_scalar(c, s_prime, 0, scal.p(), bj, 0, 1, dm);
     HIP_OK(dev::stream_sync(c.stream));
   }
-  kern::to_mont(c, key.p(), (size_t)np * N, 2 * c.dnum, all);
   HIP_OK(dev::stream_sync(c.stream));
 }
 

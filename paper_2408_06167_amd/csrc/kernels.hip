@@ -1,10 +1,11 @@
 // kernels.hip -- gfx950 kernels of the RNS-CKKS evaluator.
 //
 // All arithmetic is exact modular integer arithmetic on 64-bit words with
-// primes below 2^51, emulated on the 32-bit VALU (no MFMA, no floating
-// point): constant operands use Shoup's precomputed quotient, variable
-// products use Montgomery reduction with R = 2^64 (switching keys are kept in
-// Montgomery form so one reduction gives the plain product).
+// primes below 2^51 (no MFMA: nothing here is a dense contraction).  The NTT
+// and the key inner products carry residues as exact integers in FP64, which
+// the VALU issues at full rate; the element-wise kernels use 32-bit integer
+// arithmetic: Shoup's precomputed quotient for constant operands, Montgomery
+// reduction with R = 2^64 for variable products.
 //
 // Grids are (element chunks, limb slot, batch element): blockIdx.y picks the
 // limb (and with it the prime, uniform across the block so its constants come
@@ -215,6 +216,25 @@ __device__ __forceinline__ u64 f_to_u64(double x) {
   const u32 l = (u32)__fma_rn(-(double)h, 4294967296.0, x);
   return ((u64)h << 32) | l;
 }
+
+// Sum of exact products v * w mod q (v, w residues in [0, q)) carried in FP64:
+// each product lies within 1.25 q of 0 (w/q rounded twice), the running sum
+// is folded back to |s| <= q/2 + 1 after every second term, so it stays
+// below 3q < 2^53; residue() returns the exact sum in [0, q).
+struct FAcc {
+  double s = 0.0;
+  int n = 0;
+  __device__ __forceinline__ void add(double v, u64 w_word, double qi, double q) {
+    const double w = u64_to_f(w_word);
+    s = __dadd_rn(s, fmul_mod(v, w, __dmul_rn(w, qi), q));
+    if (++n == 2) { s = fred(s, qi, q); n = 0; }
+  }
+  __device__ __forceinline__ u64 residue(double qi, double q) const {
+    double r = fred(s, qi, q);
+    r = r < 0.0 ? __dadd_rn(r, q) : r;
+    return f_to_u64(r);
+  }
+};
 
 enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 
@@ -585,19 +605,18 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   const u64* key = ((blockIdx.z >> sel) & 1) ? key1 : key0;   // per-element key choice
   u64* U = uw + bz * suw + (size_t)t * N;
   u64* Wp = U + (size_t)ext * N;
+  const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
   EW_LOOP {
-    u64 su = 0, sw = 0;
+    FAcc su, sw;
     for (int j = 0; j < tb.beta; ++j) {
       const ModUpDigit& dg = tb.d[j];
       const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-      const u64 v = own ? x[bz * sx + (size_t)t * N + i] : y[bz * sy + ((size_t)j * ext + t) * N + i];
-      const u64* kb = key + ((size_t)(2 * j) * key_limbs + kl) * N;
-      const u64* ka = key + ((size_t)(2 * j + 1) * key_limbs + kl) * N;
-      su = add_mod(su, mont_mul(v, kb[i], q, pr.qn), q);
-      sw = add_mod(sw, mont_mul(v, ka[i], q, pr.qn), q);
+      const double v = u64_to_f(own ? x[bz * sx + (size_t)t * N + i] : y[bz * sy + ((size_t)j * ext + t) * N + i]);
+      su.add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
+      sw.add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
     }
-    U[i] = su;
-    Wp[i] = sw;
+    U[i] = su.residue(qi, qd);
+    Wp[i] = sw.residue(qi, qd);
   }
 }
 
@@ -615,7 +634,7 @@ __device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n) {
 // maps onto an aligned block).  Keys come from the key table (indexed by
 // g / 2).  Each thread keeps HZ elements, so that a key word is read once
 // for all of them when the elements share their Galois elements.
-constexpr int HZ = 4;
+constexpr int HZ = 8;
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
                             const PrimeC* P, int log_n, int B, int accumulate) {
@@ -628,35 +647,35 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const int z0 = blockIdx.z * HZ;
   const int nz = min(HZ, B - z0);
-  EW_LOOP {
-    u64 su[HZ] = {}, sw[HZ] = {};
-    for (int a = 0; a < h.A; ++a) {
-#pragma unroll
-      for (int zz = 0; zz < HZ; ++zz) {
-        if (zz >= nz) break;
-        const int z = z0 + zz;
-        const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-        const u32 src = autom_src((u32)i, g, log_n);
-        const u64* key = gtab[g >> 1];
-        for (int j = 0; j < tb.beta; ++j) {
-          const ModUpDigit& dg = tb.d[j];
-          const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-          const u64 v = own ? x[(size_t)z * sx + (size_t)t * N + src]
-                            : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src];
-          const u64* kb = key + ((size_t)(2 * j) * key_limbs + kl) * N;
-          const u64* ka = key + ((size_t)(2 * j + 1) * key_limbs + kl) * N;
-          su[zz] = add_mod(su[zz], mont_mul(v, kb[i], q, pr.qn), q);
-          sw[zz] = add_mod(sw[zz], mont_mul(v, ka[i], q, pr.qn), q);
-        }
-      }
-    }
+  const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
+  const int i = blockIdx.x * TPB + threadIdx.x;      // one position per thread
+  if (i >= N) return;
+  FAcc su[HZ], sw[HZ];
+  for (int a = 0; a < h.A; ++a) {
 #pragma unroll
     for (int zz = 0; zz < HZ; ++zz) {
       if (zz >= nz) break;
-      u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
-      U[i] = accumulate ? add_mod(U[i], su[zz], q) : su[zz];
-      U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], sw[zz], q) : sw[zz];
+      const int z = z0 + zz;
+      const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+      const u32 src = autom_src((u32)i, g, log_n);
+      const u64* key = gtab[g >> 1];
+      for (int j = 0; j < tb.beta; ++j) {
+        const ModUpDigit& dg = tb.d[j];
+        const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+        const double v = u64_to_f(own ? x[(size_t)z * sx + (size_t)t * N + src]
+                                      : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src]);
+        su[zz].add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
+        sw[zz].add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
+      }
     }
+  }
+#pragma unroll
+  for (int zz = 0; zz < HZ; ++zz) {
+    if (zz >= nz) break;
+    u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
+    const u64 ru = su[zz].residue(qi, qd), rw = sw[zz].residue(qi, qd);
+    U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
+    U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
   }
 }
 
@@ -1102,7 +1121,8 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
   Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
-  LAUNCH(k_kip_hoist, ew_grid(c.N, tb.ext, (B + HZ - 1) / HZ), dim3(TPB), 0, c.stream, y, sy, y_own, sown,
+  LAUNCH(k_kip_hoist, dim3((unsigned)((c.N + TPB - 1) / TPB), (unsigned)tb.ext, (unsigned)((B + HZ - 1) / HZ)),
+         dim3(TPB), 0, c.stream, y, sy, y_own, sown,
          gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B,
          accumulate ? 1 : 0);
   check_launch();
