@@ -224,10 +224,9 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
         ev::rescale(c, rl.p(), B, 2, l, dst);
         if (i > 0) kern::add(c, acc.p(), nln, acc2.p(), nln, acc.p(), nln, 2 * B, kern::chain_map(nl));
       }
-    } else if (schedule == BM_S2) {
-      for (u32 i = 0; i < k; ++i)
-        kern::tensor(c, cu + (size_t)i * upart, cu_stride, Bg, ln, gbase + (size_t)i * gpart,
-                     (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln, B, l, i > 0);
+    } else if (schedule == BM_S2) {          // the k tensors summed in one pass
+      kern::tensor(c, cu, cu_stride, Bg, ln, gbase, (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln,
+                   B, l, false, (int)k, upart, gpart);
       ev::relin(c, d3.p(), B, l, rlk, rl.p());
       ev::rescale(c, rl.p(), B, 2, l, acc.p());
     } else {

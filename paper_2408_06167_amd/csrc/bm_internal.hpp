@@ -339,9 +339,11 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2]
                  u64* o, size_t so, int B, const LimbMap& m);
 // tensor product (a0,a1) x (b0,b1) -> (d0,d1,d2), optionally accumulated into o;
 // batch element z uses a[z / a_div] and b[z % b_mod]
-// a_cs, b_cs: component strides of the operands (>= limbs * N)
+// a_cs, b_cs: component strides of the operands (>= limbs * N); with parts > 1
+// the tensors of parts pairs (a + p a_ps, b + p b_ps) are summed
 void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
-            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate);
+            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate, int parts = 1, size_t a_ps = 0,
+            size_t b_ps = 0);
 // evaluation-domain automorphism X -> X^g of `comps` components of `limbs` limbs
 // batch element z uses Galois element g1 when bit `sel` of z is set, else g0
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B,

@@ -229,6 +229,11 @@ struct FAcc {
     s = __dadd_rn(s, fmul_mod(v, w, __dmul_rn(w, qi), q));
     if (++n == 2) { s = fred(s, qi, q); n = 0; }
   }
+  // add one product already reduced by fmul_mod
+  __device__ __forceinline__ void add_f(double p, double qi, double q) {
+    s = __dadd_rn(s, p);
+    if (++n == 2) { s = fred(s, qi, q); n = 0; }
+  }
   __device__ __forceinline__ u64 residue(double qi, double q) const {
     double r = fred(s, qi, q);
     r = r < 0.0 ? __dadd_rn(r, q) : r;
@@ -244,16 +249,20 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   LimbMap m, const PrimeC* __restrict__ P,
                                                   const double* __restrict__ twf,
                                                   const double* __restrict__ twq, int log_n, int s0,
-                                                  int last, int B) {
+                                                  int last, int B, int vz) {
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
   constexpr int VS = M + M / 16 + 1;          // padded view length in LDS (odd: spreads banks)
   constexpr int PH = LOGM / 4;                // radix-16 phases
   extern __shared__ u64 sh_raw[];
   double* sh = reinterpret_cast<double*>(sh_raw);
-  __shared__ double tl[2 * 256];              // block twiddles (w, w/q) for 8-stage passes
   const int t = threadIdx.x;
   const int V = (int)blockDim.x / TPV;        // views in this block
+  // Row passes take vz polynomials x R consecutive rows per block (R = V / vz),
+  // so that small batches still fill whole waves; every row stages its own
+  // twiddles (w, w/q) after the views in LDS.  Other passes: R = 1.
+  const int R = KIND == NTT_ROW ? V / vz : 1;
+  double* tl = sh + V * VS;                   // [R][2 * 256] block twiddles (8-stage passes)
   const int nthr = (int)blockDim.x;
   const int pid = m.prime[blockIdx.y];
   const PrimeC& pr = P[pid];
@@ -278,11 +287,12 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     base_out = (size_t)blockIdx.z * out_stride + (size_t)m.ooff[blockIdx.y] * N + col;
   } else if (KIND == NTT_ROW) {
     astride = 1;
-    const int z = blockIdx.z * V + v;
+    const int z = blockIdx.z * vz + v % vz;
+    const size_t row = (size_t)blockIdx.x * R + v / vz;
     valid = z < B;
     const size_t zz = valid ? (size_t)z : 0;
-    base_in = zz * in_stride + (size_t)m.off[blockIdx.y] * N + (size_t)blockIdx.x * M;
-    base_out = zz * out_stride + (size_t)m.ooff[blockIdx.y] * N + (size_t)blockIdx.x * M;
+    base_in = zz * in_stride + (size_t)m.off[blockIdx.y] * N + row * M;
+    base_out = zz * out_stride + (size_t)m.ooff[blockIdx.y] * N + row * M;
   } else {
     astride = 1;
     base_in = (size_t)blockIdx.z * in_stride + (size_t)m.off[blockIdx.y] * N;
@@ -312,15 +322,16 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
   }
-  // ---- stage the block's twiddles (8-stage passes): tl[2^s + i] for stage s, block i
+  // ---- stage the block's twiddles (8-stage passes): tl[r][2^s + i] for stage s, block i of row r
   if (LOGM == 8) {
-    const int vb = KIND == NTT_ROW ? (int)blockIdx.x : 0;
-    for (int k = t; k < 256; k += nthr) {
-      if (k == 0) continue;
-      const int st = 31 - __clz(k);
-      const int g = (1 << (s0 + st)) + (vb << st) + (k - (1 << st));
-      tl[2 * k] = W[g];
-      tl[2 * k + 1] = WQ[g];
+    for (int k = t; k < 256 * R; k += nthr) {
+      const int kk = k & 255, rr = k >> 8;
+      if (kk == 0) continue;
+      const int vb = KIND == NTT_ROW ? (int)blockIdx.x * R + rr : 0;
+      const int st = 31 - __clz(kk);
+      const int g = (1 << (s0 + st)) + (vb << st) + (kk - (1 << st));
+      tl[rr * 512 + 2 * kk] = W[g];
+      tl[rr * 512 + 2 * kk + 1] = WQ[g];
     }
   }
   if (DIRECT_IN) {
@@ -339,8 +350,9 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(P_FIRST, j))];
   }
 
+  const double* tlv = tl + (KIND == NTT_ROW ? (v / vz) * 512 : 0);   // this view's row twiddles
   auto twid = [&](int kk, double& w, double& wq) {
-    if (LOGM == 8) { w = tl[2 * kk]; wq = tl[2 * kk + 1]; }
+    if (LOGM == 8) { w = tlv[2 * kk]; wq = tlv[2 * kk + 1]; }
     else { w = W[kk]; wq = WQ[kk]; }
   };
 
@@ -514,9 +526,9 @@ __global__ void k_reduce_int(const int64_t* src, size_t ss, u64* o, size_t so, L
 // launch can cross several queries with several gallery groups.  a_cs and b_cs
 // are the component strides of the operands (they may hold more limbs than
 // the product uses: an exact level drop on the fly).
-__global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
-                         int b_mod, size_t b_cs, u64* o, size_t so, int limbs, const PrimeC* P, int N,
-                         int accumulate) {
+__global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, size_t a_ps, const u64* b,
+                         size_t sb, int b_mod, size_t b_cs, size_t b_ps, int parts, u64* o, size_t so,
+                         int limbs, const PrimeC* P, int N, int accumulate) {
   const int l = blockIdx.y;
   const PrimeC& pr = P[l];
   const u64 q = pr.q;
@@ -530,10 +542,14 @@ __global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, const 
   u64* O1 = O0 + ln;
   u64* O2 = O1 + ln;
   EW_LOOP {
-    const u64 x0 = A0[i], x1 = A1[i], y0 = B0[i], y1 = B1[i];
-    u64 d0 = mul_mod(x0, y0, pr);
-    u64 d1 = add_mod(mul_mod(x0, y1, pr), mul_mod(x1, y0, pr), q);
-    u64 d2 = mul_mod(x1, y1, pr);
+    u64 d0 = 0, d1 = 0, d2 = 0;
+    for (int p = 0; p < parts; ++p) {     // sum of the tensors of `parts` pairs of parts
+      const size_t ao = (size_t)p * a_ps + i, bo = (size_t)p * b_ps + i;
+      const u64 x0 = A0[ao], x1 = A1[ao], y0 = B0[bo], y1 = B1[bo];
+      d0 = add_mod(d0, mul_mod(x0, y0, pr), q);
+      d1 = add_mod(d1, add_mod(mul_mod(x0, y1, pr), mul_mod(x1, y0, pr), q), q);
+      d2 = add_mod(d2, mul_mod(x1, y1, pr), q);
+    }
     if (accumulate) {
       d0 = add_mod(d0, O0[i], q);
       d1 = add_mod(d1, O1[i], q);
@@ -635,6 +651,8 @@ __device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n) {
 // g / 2).  Each thread keeps HZ elements, so that a key word is read once
 // for all of them when the elements share their Galois elements.
 constexpr int HZ = 8;
+constexpr int HOIST_BETA = 4;   // digits a thread keeps key words for (dnum <= 4 at every level)
+template <bool PER_ELEM>
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
                             const PrimeC* P, int log_n, int B, int accumulate) {
@@ -652,20 +670,47 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   if (i >= N) return;
   FAcc su[HZ], sw[HZ];
   for (int a = 0; a < h.A; ++a) {
+    // key words of this amount, converted once for every element (shared Galois element)
+    double kb[HOIST_BETA], kbq[HOIST_BETA], ka[HOIST_BETA], kaq[HOIST_BETA];
+    u32 g = h.g[a];
+    u32 src = autom_src((u32)i, g, log_n);
+    if (!PER_ELEM) {
+      const u64* key = gtab[g >> 1];
+      #pragma unroll
+        for (int j = 0; j < HOIST_BETA; ++j) {
+          if (j >= tb.beta) break;
+        kb[j] = u64_to_f(key[((size_t)(2 * j) * key_limbs + kl) * N + i]);
+        ka[j] = u64_to_f(key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i]);
+        kbq[j] = __dmul_rn(kb[j], qi);
+        kaq[j] = __dmul_rn(ka[j], qi);
+      }
+    }
 #pragma unroll
     for (int zz = 0; zz < HZ; ++zz) {
       if (zz >= nz) break;
       const int z = z0 + zz;
-      const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-      const u32 src = autom_src((u32)i, g, log_n);
-      const u64* key = gtab[g >> 1];
-      for (int j = 0; j < tb.beta; ++j) {
+      if (PER_ELEM) {
+        g = h.g[z * h.A + a];
+        src = autom_src((u32)i, g, log_n);
+        const u64* key = gtab[g >> 1];
+        #pragma unroll
+        for (int j = 0; j < HOIST_BETA; ++j) {
+          if (j >= tb.beta) break;
+          kb[j] = u64_to_f(key[((size_t)(2 * j) * key_limbs + kl) * N + i]);
+          ka[j] = u64_to_f(key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i]);
+          kbq[j] = __dmul_rn(kb[j], qi);
+          kaq[j] = __dmul_rn(ka[j], qi);
+        }
+      }
+      #pragma unroll
+        for (int j = 0; j < HOIST_BETA; ++j) {
+          if (j >= tb.beta) break;
         const ModUpDigit& dg = tb.d[j];
         const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
         const double v = u64_to_f(own ? x[(size_t)z * sx + (size_t)t * N + src]
                                       : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src]);
-        su[zz].add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
-        sw[zz].add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
+        su[zz].add_f(fmul_mod(v, kb[j], kbq[j], qd), qi, qd);
+        sw[zz].add_f(fmul_mod(v, ka[j], kaq[j], qd), qi, qd);
       }
     }
   }
@@ -886,28 +931,35 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     const dim3 grid(1, (unsigned)m.n, (unsigned)B);
     if (inverse)
       LAUNCH((k_ntt_fast<12, true, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
-             out_stride, m, c.d_primes, tw, tws, logn, 0, 1, B);
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 1, B, 1);
     else
       LAUNCH((k_ntt_fast<12, false, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
-             out_stride, m, c.d_primes, tw, tws, logn, 0, 0, B);
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 0, B, 1);
     check_launch();
     return;
   }
-  const int Vr = B < 16 ? B : 16;
-  const size_t lds_col = (size_t)16 * (256 + 16 + 1) * sizeof(u64);
-  const size_t lds_row = (size_t)Vr * (256 + 16 + 1) * sizeof(u64);
+  // row passes: vz polynomials x R rows per block, R the largest power of two
+  // with vz R <= 16 (whole waves for small batches) and at most 64 KiB of LDS
+  const int vz = B < 16 ? B : 16;
+  const size_t view_words = 256 + 16 + 1;
+  auto row_lds = [&](int r) { return ((size_t)vz * r * view_words + (size_t)512 * r) * sizeof(u64); };
+  int R = 1;
+  while (vz * R * 2 <= 16 && row_lds(2 * R) <= 65536) R *= 2;
+  const int Vrow = vz * R;
+  const size_t lds_col = ((size_t)16 * view_words + 512) * sizeof(u64);
+  const size_t lds_row = row_lds(R);
   const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
-  const dim3 grow(N / 256, (unsigned)m.n, (unsigned)((B + Vr - 1) / Vr));
+  const dim3 grow((unsigned)(N / 256 / R), (unsigned)m.n, (unsigned)((B + vz - 1) / vz));
   auto col = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm, int last) {
     chk_map(c, src, B, ss, mm, "ntt column pass input");
     chk_map(c, dst, B, ds, mm, "ntt column pass output", true);
     Prof pf(c, inverse ? "ntt_inv_col" : "ntt_fwd_col", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
-             c.d_primes, tw, tws, logn, 0, last, B);
+             c.d_primes, tw, tws, logn, 0, last, B, 1);
     else
       LAUNCH((k_ntt_fast<8, false, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
-             c.d_primes, tw, tws, logn, 0, last, B);
+             c.d_primes, tw, tws, logn, 0, last, B, 1);
     check_launch();
   };
   auto row = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm) {
@@ -915,11 +967,11 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     chk_map(c, dst, B, ds, mm, "ntt row pass output", true);
     Prof pf(c, inverse ? "ntt_inv_row" : "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
-      LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vr), lds_row, c.stream, src, ss, dst, ds,
-             mm, c.d_primes, tw, tws, logn, 8, 0, B);
+      LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vrow), lds_row, c.stream, src, ss, dst, ds,
+             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz);
     else
-      LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vr), lds_row, c.stream, src, ss, dst, ds,
-             mm, c.d_primes, tw, tws, logn, 8, 0, B);
+      LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vrow), lds_row, c.stream, src, ss, dst, ds,
+             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz);
     check_launch();
   };
   if (!inverse) {
@@ -1049,16 +1101,18 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o,
 }
 
 void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
-            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate) {
-  if (a_div < 1 || b_mod < 1) BM_THROW(BM_EINVAL, "launch check: tensor batch divisors");
+            int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate, int parts, size_t a_ps,
+            size_t b_ps) {
+  if (a_div < 1 || b_mod < 1 || parts < 1) BM_THROW(BM_EINVAL, "launch check: tensor batch divisors");
   if (limbs > c.L + 1 || a_cs < (size_t)limbs * c.N || b_cs < (size_t)limbs * c.N)
     BM_THROW(BM_EINVAL, "launch check: tensor limbs");
-  chk(a, (B - 1) / a_div + 1, sa, 0, a_cs + (size_t)limbs * c.N, "tensor a");
-  chk(b, std::min(B, b_mod), sb, 0, b_cs + (size_t)limbs * c.N, "tensor b");
+  const size_t pa = (size_t)(parts - 1) * a_ps, pb = (size_t)(parts - 1) * b_ps;
+  chk(a, (B - 1) / a_div + 1, sa, 0, pa + a_cs + (size_t)limbs * c.N, "tensor a");
+  chk(b, std::min(B, b_mod), sb, 0, pb + b_cs + (size_t)limbs * c.N, "tensor b");
   chk(o, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
-  Prof pf(c, "tensor", 8.0 * c.N * B * limbs * (accumulate ? 10 : 7), 4.0 * c.N * B * limbs);
-  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, a_cs, b, sb, b_mod,
-         b_cs, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
+  Prof pf(c, "tensor", 8.0 * c.N * B * limbs * (4.0 * parts + (accumulate ? 6 : 3)), 4.0 * c.N * B * limbs * parts);
+  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, a_cs, a_ps, b, sb, b_mod,
+         b_cs, b_ps, parts, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
   check_launch();
 }
 
@@ -1121,10 +1175,14 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
   Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
-  LAUNCH(k_kip_hoist, dim3((unsigned)((c.N + TPB - 1) / TPB), (unsigned)tb.ext, (unsigned)((B + HZ - 1) / HZ)),
-         dim3(TPB), 0, c.stream, y, sy, y_own, sown,
-         gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B,
-         accumulate ? 1 : 0);
+  if (tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: too many digits for the hoisted kip");
+  const dim3 grid((unsigned)((c.N + TPB - 1) / TPB), (unsigned)tb.ext, (unsigned)((B + HZ - 1) / HZ));
+  if (h.per_elem)
+    LAUNCH(k_kip_hoist<true>, grid, dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
+           c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
+  else
+    LAUNCH(k_kip_hoist<false>, grid, dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
+           c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
   check_launch();
 }
 
