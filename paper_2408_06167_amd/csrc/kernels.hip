@@ -648,100 +648,79 @@ __device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n) {
 //   (u, w)[z] = sum_a sum_j phi_{g(z,a)}(y_j[z]) * key_{g(z,a), j}     over Q_l u P,
 // the automorphism read as a gather (an aligned block of consecutive words
 // maps onto an aligned block).  Keys come from the key table (indexed by
-// g / 2).  Each thread keeps HZ elements, so that a key word is read once
-// for all of them when the elements share their Galois elements.
-constexpr int HZ = 8;
-constexpr int HOIST_BETA = 4;   // digits a thread keeps key words for (dnum <= 4 at every level)
-template <bool PER_ELEM>
+// g / 2).  One thread per (element, limb, position); the elements of one
+// (limb, position block) are consecutive blocks, so that on one XCD they
+// share the key words through L2.
+constexpr int HOIST_BETA = 4;   // digits a thread handles (dnum <= 4 at every level)
+
+// XCD-aware block order: the hardware deals workgroups to the 8 XCDs in
+// turn, so workgroup w runs on XCD w mod 8.  Logical block
+// (w mod 8) * (W / 8) + w / 8 gives every XCD one contiguous range of logical
+// blocks (W a multiple of 8), whose gathered words and shared key words then
+// stay in that XCD's L2.
+__device__ __forceinline__ int xcd_block(int w, int W) { return (w & 7) * (W >> 3) + (w >> 3); }
+
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
                             const PrimeC* P, int log_n, int B, int accumulate) {
   const ModUpTable& tb = *T;
   const int N = 1 << log_n;
-  const int t = blockIdx.y;
   const int ext = tb.ext;
+  // 1-D grid of (limb, position block, element), element fastest
+  const int gx = (N + TPB - 1) / TPB;
+  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int z = lb % B;
+  const int pb = (lb / B) % gx;
+  const int t = lb / (B * gx);
+  const int i = pb * TPB + threadIdx.x;
+  if (i >= N || t >= ext) return;
   const PrimeC& pr = P[tb.ext_prime[t]];
   const u64 q = pr.q;
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
-  const int z0 = blockIdx.z * HZ;
-  const int nz = min(HZ, B - z0);
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
-  const int i = blockIdx.x * TPB + threadIdx.x;      // one position per thread
-  if (i >= N) return;
-  FAcc su[HZ], sw[HZ];
+  FAcc su, sw;
   for (int a = 0; a < h.A; ++a) {
-    // key words of this amount, converted once for every element (shared Galois element)
-    double kb[HOIST_BETA], kbq[HOIST_BETA], ka[HOIST_BETA], kaq[HOIST_BETA];
-    u32 g = h.g[a];
-    u32 src = autom_src((u32)i, g, log_n);
-    if (!PER_ELEM) {
-      const u64* key = gtab[g >> 1];
-      #pragma unroll
-        for (int j = 0; j < HOIST_BETA; ++j) {
-          if (j >= tb.beta) break;
-        kb[j] = u64_to_f(key[((size_t)(2 * j) * key_limbs + kl) * N + i]);
-        ka[j] = u64_to_f(key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i]);
-        kbq[j] = __dmul_rn(kb[j], qi);
-        kaq[j] = __dmul_rn(ka[j], qi);
-      }
-    }
+    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    const u32 src = autom_src((u32)i, g, log_n);
+    const u64* key = gtab[g >> 1];
 #pragma unroll
-    for (int zz = 0; zz < HZ; ++zz) {
-      if (zz >= nz) break;
-      const int z = z0 + zz;
-      if (PER_ELEM) {
-        g = h.g[z * h.A + a];
-        src = autom_src((u32)i, g, log_n);
-        const u64* key = gtab[g >> 1];
-        #pragma unroll
-        for (int j = 0; j < HOIST_BETA; ++j) {
-          if (j >= tb.beta) break;
-          kb[j] = u64_to_f(key[((size_t)(2 * j) * key_limbs + kl) * N + i]);
-          ka[j] = u64_to_f(key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i]);
-          kbq[j] = __dmul_rn(kb[j], qi);
-          kaq[j] = __dmul_rn(ka[j], qi);
-        }
-      }
-      #pragma unroll
-        for (int j = 0; j < HOIST_BETA; ++j) {
-          if (j >= tb.beta) break;
-        const ModUpDigit& dg = tb.d[j];
-        const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-        const double v = u64_to_f(own ? x[(size_t)z * sx + (size_t)t * N + src]
-                                      : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src]);
-        su[zz].add_f(fmul_mod(v, kb[j], kbq[j], qd), qi, qd);
-        sw[zz].add_f(fmul_mod(v, ka[j], kaq[j], qd), qi, qd);
-      }
+    for (int j = 0; j < HOIST_BETA; ++j) {
+      if (j >= tb.beta) break;
+      const ModUpDigit& dg = tb.d[j];
+      const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+      const double v = u64_to_f(own ? x[(size_t)z * sx + (size_t)t * N + src]
+                                    : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src]);
+      su.add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
+      sw.add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
     }
   }
-#pragma unroll
-  for (int zz = 0; zz < HZ; ++zz) {
-    if (zz >= nz) break;
-    u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
-    const u64 ru = su[zz].residue(qi, qd), rw = sw[zz].residue(qi, qd);
-    U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
-    U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
-  }
+  u64* U = uw + (size_t)z * suw + (size_t)t * N;
+  const u64 ru = su.residue(qi, qd), rw = sw.residue(qi, qd);
+  U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
+  U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
 }
 
 // out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
 // (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in)
 __global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, HoistArgs h, const PrimeC* P,
-                            int log_n, int accumulate) {
+                            int log_n, int limbs, int accumulate) {
   const int N = 1 << log_n;
-  const int l = blockIdx.y;
-  const int z = blockIdx.z;
+  // 1-D XCD-aware grid of (element, limb, position block), position block fastest
+  const int gx = (N + TPB - 1) / TPB;
+  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int l = (lb / gx) % limbs;
+  const int z = lb / (gx * limbs);
+  const int i = (lb % gx) * TPB + threadIdx.x;
+  if (i >= N) return;
   const u64 q = P[l].q;
   const u64* I = in + (size_t)z * si + (size_t)l * N;
   u64* O = out + (size_t)z * so + (size_t)l * N;
-  EW_LOOP {
-    u64 acc = accumulate ? O[i] : I[i];
-    for (int a = 0; a < h.A; ++a) {
-      const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-      acc = add_mod(acc, I[autom_src((u32)i, g, log_n)], q);
-    }
-    O[i] = acc;
+  u64 acc = accumulate ? O[i] : I[i];
+  for (int a = 0; a < h.A; ++a) {
+    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    acc = add_mod(acc, I[autom_src((u32)i, g, log_n)], q);
   }
+  O[i] = acc;
 }
 
 // conv[c][i] = sum_k [u_c[p_k] (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}   (coefficient domain)
@@ -1176,13 +1155,11 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
   if (tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: too many digits for the hoisted kip");
-  const dim3 grid((unsigned)((c.N + TPB - 1) / TPB), (unsigned)tb.ext, (unsigned)((B + HZ - 1) / HZ));
-  if (h.per_elem)
-    LAUNCH(k_kip_hoist<true>, grid, dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
-           c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
-  else
-    LAUNCH(k_kip_hoist<false>, grid, dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
-           c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
+  const size_t gx = (c.N + TPB - 1) / TPB;
+  const size_t W = gx * tb.ext * B;
+  if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+  LAUNCH(k_kip_hoist, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
+         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
   check_launch();
 }
 
@@ -1192,8 +1169,10 @@ void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, cons
   chk(in, B, si, 0, (size_t)limbs * c.N, "autom_sum input");
   chk(out, B, so, 0, (size_t)limbs * c.N, "autom_sum output");
   Prof pf(c, "autom_sum", 8.0 * c.N * B * limbs * (h.A + 2), (double)c.N * B * limbs * h.A);
-  LAUNCH(k_autom_sum, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes,
-         c.log_n, accumulate ? 1 : 0);
+  const size_t W = (size_t)((c.N + TPB - 1) / TPB) * limbs * B;
+  if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
+  LAUNCH(k_autom_sum, dim3((unsigned)W), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes, c.log_n, limbs,
+         accumulate ? 1 : 0);
   check_launch();
 }
 
