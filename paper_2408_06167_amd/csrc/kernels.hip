@@ -541,15 +541,20 @@ __global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, size_t
   u64* O0 = o + bz * so + (size_t)l * N;
   u64* O1 = O0 + ln;
   u64* O2 = O1 + ln;
+  const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
   EW_LOOP {
-    u64 d0 = 0, d1 = 0, d2 = 0;
+    FAcc f0, f1, f2;                      // exact FP64 sums of the products (see FAcc)
     for (int p = 0; p < parts; ++p) {     // sum of the tensors of `parts` pairs of parts
       const size_t ao = (size_t)p * a_ps + i, bo = (size_t)p * b_ps + i;
-      const u64 x0 = A0[ao], x1 = A1[ao], y0 = B0[bo], y1 = B1[bo];
-      d0 = add_mod(d0, mul_mod(x0, y0, pr), q);
-      d1 = add_mod(d1, add_mod(mul_mod(x0, y1, pr), mul_mod(x1, y0, pr), q), q);
-      d2 = add_mod(d2, mul_mod(x1, y1, pr), q);
+      const double x0 = u64_to_f(A0[ao]), x1 = u64_to_f(A1[ao]);
+      const double y0 = u64_to_f(B0[bo]), y1 = u64_to_f(B1[bo]);
+      const double y0q = __dmul_rn(y0, qi), y1q = __dmul_rn(y1, qi);
+      f0.add_f(fmul_mod(x0, y0, y0q, qd), qi, qd);
+      f1.add_f(fmul_mod(x0, y1, y1q, qd), qi, qd);
+      f1.add_f(fmul_mod(x1, y0, y0q, qd), qi, qd);
+      f2.add_f(fmul_mod(x1, y1, y1q, qd), qi, qd);
     }
+    u64 d0 = f0.residue(qi, qd), d1 = f1.residue(qi, qd), d2 = f2.residue(qi, qd);
     if (accumulate) {
       d0 = add_mod(d0, O0[i], q);
       d1 = add_mod(d1, O1[i], q);
@@ -682,7 +687,9 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   for (int a = 0; a < h.A; ++a) {
     const u32 g = h.g[h.per_elem ? z * h.A + a : a];
     const u32 src = autom_src((u32)i, g, log_n);
-    const u64* key = gtab[g >> 1];
+    // the key pointer comes from memory: tell the compiler it is a global one
+    const __attribute__((address_space(1))) u64* key =
+        (const __attribute__((address_space(1))) u64*)gtab[g >> 1];
 #pragma unroll
     for (int j = 0; j < HOIST_BETA; ++j) {
       if (j >= tb.beta) break;
