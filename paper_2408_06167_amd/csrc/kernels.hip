@@ -678,18 +678,24 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   const int pb = (lb / B) % gx;
   const int t = lb / (B * gx);
   const int i = pb * TPB + threadIdx.x;
+  // key addresses of this block's amounts, staged once in LDS (they are
+  // uniform across the block), so that no global load sits in front of the
+  // key words inside the loop
+  __shared__ const u64* kp[HOIST_MAX];
+  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[h.per_elem ? z * h.A + a : a] >> 1];
+  __syncthreads();
   if (i >= N || t >= ext) return;
   const PrimeC& pr = P[tb.ext_prime[t]];
   const u64 q = pr.q;
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
   FAcc su, sw;
+#pragma unroll 4
   for (int a = 0; a < h.A; ++a) {
     const u32 g = h.g[h.per_elem ? z * h.A + a : a];
     const u32 src = autom_src((u32)i, g, log_n);
     // the key pointer comes from memory: tell the compiler it is a global one
-    const __attribute__((address_space(1))) u64* key =
-        (const __attribute__((address_space(1))) u64*)gtab[g >> 1];
+    const __attribute__((address_space(1))) u64* key = (const __attribute__((address_space(1))) u64*)kp[a];
 #pragma unroll
     for (int j = 0; j < HOIST_BETA; ++j) {
       if (j >= tb.beta) break;
