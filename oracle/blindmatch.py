@@ -106,7 +106,7 @@ def mask_slots(params, d, k, i):
 def mask_coeffs(params, d, k, limbs_query):
     """Integer plaintexts of mask_0..mask_{k-1} at scale q_top of the query."""
     qtop = params.q[limbs_query - 1]
-    return [ckks.encode(mask_slots(params, d, k, i), float(qtop), params.N) for i in range(k)], \
+    return [ckks.encode(mask_slots(params, d, k, i), float(qtop), params.N, params.ring) for i in range(k)], \
         float(qtop)
 
 
@@ -222,7 +222,7 @@ def compress_mask_coeffs(params, d, k, limbs):
     c, _ = layout(params, d, k)
     s = np.arange(params.n)
     qtop = params.q[limbs - 1]
-    return ckks.encode((s % c == 0).astype(np.float64), float(qtop), params.N), float(qtop)
+    return ckks.encode((s % c == 0).astype(np.float64), float(qtop), params.N, params.ring), float(qtop)
 
 
 def compress(params, keys, outs, d, k, mask, mask_scale):
@@ -252,7 +252,7 @@ def enroll_mask_coeffs(params, d, k, limbs):
     c, _ = layout(params, d, k)
     s = np.arange(params.n)
     qtop = params.q[limbs - 1]
-    return [ckks.encode(((s >= i * c) & (s < (i + 1) * c)).astype(np.float64), float(qtop), params.N)
+    return [ckks.encode(((s >= i * c) & (s < (i + 1) * c)).astype(np.float64), float(qtop), params.N, params.ring)
             for i in range(k)], float(qtop)
 
 

@@ -25,6 +25,18 @@ not fix the concrete scheme variant; the readings taken here are:
   * randomness from SHAKE-256 streams keyed by (seed, domain, index):
     ternary secret, discrete Gaussian (sigma = 3.2, |e| <= 19, by cumulative
     table) errors, uniform masks.
+
+Conjugate-invariant ring (the paper's setting, Sec. 2; presets 3 and 4):
+R' = Z[X + X^-1] inside Z[X]/(X^2N + 1), rank N, with N real slots.  An
+element is kept as its first N coefficients c_0..c_{N-1} in Z[X]/(X^2N+1);
+the others follow from the invariance a(X^-1) = a(X): c_N = 0 and
+c_{2N-k} = -c_k.  Products and automorphisms are taken on that extension
+in Z[X]/(X^2N+1) and cut back to N coefficients; encoding is the canonical
+embedding of Z[X]/(X^2N+1) with real slot values (slot j at zeta^(5^j),
+zeta = exp(i pi / 2N)), whose coefficients have exactly that symmetry;
+rotations use Galois elements 5^r mod 4N; all other steps are
+coefficient-wise and unchanged.  Secrets, errors and masks are sampled as
+the N coefficients c_0..c_{N-1}.
 """
 from decimal import Decimal, getcontext
 from fractions import Fraction
@@ -52,14 +64,27 @@ PRESET_PRIMES = {
             q=[0x3ffffffd20001, 0x3ffffffb80001, 0x3fffffed60001, 0x3fffffec80001,
                0x3fffffebe0001, 0x3fffffea60001, 0x3fffffea40001, 0x3fffffe9e0001],
             p=[0x7fffffffe0001, 0x7ffffffd20001], alpha=2, log_scale=50),
+    # conjugate-invariant ring, N = 2^12 (4096 real slots): primes = 1 mod 4N
+    3: dict(log_n=12,
+            q=[0x3ffffffffc001, 0xfffffdc001, 0xfffff4c001],
+            p=[0x7fffffffe0001], alpha=1, log_scale=40, ring="ci"),
+    # conjugate-invariant ring, N = 2^16 (65536 real slots): primes = 1 mod 4N
+    4: dict(log_n=16,
+            q=[0x3ffffffb80001, 0x3fffffec80001, 0x3fffffea40001, 0x3fffffe940001,
+               0x3fffffdd40001, 0x3fffffd900001, 0x3fffffd540001, 0x3fffffd500001],
+            p=[0x7ffffff9c0001, 0x7ffffff900001], alpha=2, log_scale=50, ring="ci"),
 }
 
 
 class Params:
-    def __init__(self, log_n, q, p, alpha, log_scale, sigma=3.2):
+    def __init__(self, log_n, q, p, alpha, log_scale, sigma=3.2, ring="std"):
         self.log_n = int(log_n)
         self.N = 1 << self.log_n
-        self.n = self.N // 2
+        if ring not in ("std", "ci"):
+            raise ValueError("ring")
+        self.ring = ring
+        self.n = self.N if ring == "ci" else self.N // 2     # slots
+        self.M = 4 * self.N if ring == "ci" else 2 * self.N  # order of the Galois group's roots
         self.q = [int(x) for x in q]
         self.p = [int(x) for x in p]
         self.L = len(self.q) - 1          # top level; a fresh ciphertext has L+1 limbs
@@ -140,9 +165,29 @@ def neg(a, primes):
     return np.stack([(np.uint64(q) - a[i]) % np.uint64(q) for i, q in enumerate(primes)])
 
 
-def mul(a, b, primes):
+def ci_extend(a, q):
+    """N coefficients of a conjugate-invariant element -> its 2N coefficients
+    in Z_q[X]/(X^2N+1): c_N = 0, c_{2N-k} = -c_k."""
+    N = a.shape[0]
+    out = np.zeros(2 * N, dtype=np.uint64)
+    out[:N] = a
+    out[N + 1:] = ((np.uint64(q) - a[1:]) % np.uint64(q))[::-1]
+    return out
+
+
+def polymul_jobs(jobs, ring="std"):
+    """Products of (a, b, q) jobs in the ring: negacyclic of length N, or for
+    the conjugate-invariant ring on the length-2N extensions, cut to N."""
+    if ring == "std":
+        return prims.polymul_batch(jobs)
+    N = jobs[0][0].shape[0]
+    prods = prims.polymul_batch([(ci_extend(a, q), ci_extend(b, q), q) for a, b, q in jobs])
+    return [p[:N].copy() for p in prods]
+
+
+def mul(a, b, primes, ring="std"):
     """Ring product, limb by limb."""
-    return np.stack(prims.polymul_batch([(a[i], b[i], q) for i, q in enumerate(primes)]))
+    return np.stack(polymul_jobs([(a[i], b[i], q) for i, q in enumerate(primes)], ring))
 
 
 def mul_scalar(a, c, primes):
@@ -150,9 +195,13 @@ def mul_scalar(a, c, primes):
     return np.stack([prims.mulmod_scalar(a[i], int(c) % q, q) for i, q in enumerate(primes)])
 
 
-def automorphism(a, g, primes):
+def automorphism(a, g, primes, ring="std"):
     """a(X) -> a(X^g) in Z_q[X]/(X^N+1), g odd: coefficient i moves to i*g mod 2N
-    and changes sign when that index is >= N (X^N = -1)."""
+    and changes sign when that index is >= N (X^N = -1).  Conjugate-invariant
+    ring: the same on the 2N extension, cut back to N coefficients."""
+    if ring == "ci":
+        ext = np.stack([ci_extend(a[i], q) for i, q in enumerate(primes)])
+        return automorphism(ext, g, primes)[:, :a.shape[1]].copy()
     N = a.shape[1]
     dst = (np.arange(N, dtype=np.int64) * int(g)) % (2 * N)
     flip = dst >= N
@@ -165,8 +214,10 @@ def automorphism(a, g, primes):
 
 
 def galois_element(params, r):
-    """Galois element of a left rotation by r slots: 5^(r mod n) mod 2N."""
-    return pow(5, r % params.n, 2 * params.N)
+    """Galois element of a left rotation by r slots: 5^(r mod n) mod 2N
+    (mod 4N in the conjugate-invariant ring, whose N slots sit at the roots
+    zeta^(5^j) of order 4N)."""
+    return pow(5, r % params.n, params.M)
 
 
 # --------------------------------------------------------------------------
@@ -180,12 +231,17 @@ def _slot_roots(N):
     return (e - 1) // 2, (2 * N - e - 1) // 2
 
 
-def encode(z, scale, N):
+def encode(z, scale, N, ring="std"):
     """Integer coefficients m_k = round_half_away((2/N) * Re sum_j scale*z_j * zeta^(-k 5^j)).
+
+    Conjugate-invariant ring of rank N: the encoding of the N real values in
+    Z[X]/(X^2N+1), cut to its first N coefficients.
 
     Evaluated by one length-N FFT over all odd-power roots: the vector holding
     scale*z_j at the root of slot j and its conjugate at the conjugate root,
     transformed and untwisted by zeta^(-k)."""
+    if ring == "ci":
+        return encode(np.real(np.asarray(z, dtype=np.complex128)), scale, 2 * N)[:N].copy()
     z = np.asarray(z, dtype=np.complex128)
     n = N // 2
     assert z.shape == (n,)
@@ -212,11 +268,18 @@ def encode_direct(z, scale, N):
     return out
 
 
-def decode(m, scale, N):
+def decode(m, scale, N, ring="std"):
     """Slots z_j = (1/scale) * sum_k m_k zeta^(k 5^j) for an integer (or float)
-    coefficient vector m.  Evaluated with one inverse FFT."""
+    coefficient vector m.  Evaluated with one inverse FFT.  Conjugate-invariant
+    ring: the N coefficients are extended to 2N (c_N = 0, c_{2N-k} = -c_k) and
+    decoded in Z[X]/(X^2N+1); the N slots are real."""
     m = np.asarray([float(v) for v in m], dtype=np.float64) if not isinstance(m, np.ndarray) \
         else m.astype(np.float64)
+    if ring == "ci":
+        ext = np.zeros(2 * N)
+        ext[:N] = m
+        ext[N + 1:] = -m[1:][::-1]
+        return decode(ext, scale, 2 * N)
     k = np.arange(N)
     w = np.fft.ifft(m * np.exp(1j * np.pi * k / N)) * N
     t_slot, _ = _slot_roots(N)
@@ -282,7 +345,7 @@ def switch_key(params, s, s_prime, seed, dom_a, dom_e, index_base):
     for j in range(params.dnum):
         a = sample_uniform(params, seed, dom_a, index_base + j, primes)
         e = reduce_int(sample_gaussian(params, seed, dom_e, index_base + j), primes)
-        b = sub(e, mul(a, s_res, primes), primes)
+        b = sub(e, mul(a, s_res, primes, params.ring), primes)
         for i in _digit(params, j, len(params.q)):
             gadget = prims.mulmod_scalar(sp_res[i], params.P % primes[i], primes[i])
             b[i] = (b[i] + gadget) % np.uint64(primes[i])
@@ -299,17 +362,17 @@ def keygen(params, seed, rotations=()):
     a = sample_uniform(params, seed, DOM_PK_A, 0, q_primes)
     e = reduce_int(sample_gaussian(params, seed, DOM_PK_E, 0), q_primes)
     s_q = reduce_int(s, q_primes)
-    b = sub(e, mul(a, s_q, q_primes), q_primes)
+    b = sub(e, mul(a, s_q, q_primes, params.ring), q_primes)
     kp = params.key_primes()
     s_kp = reduce_int(s, kp)
-    s2 = mul(s_kp, s_kp, kp)
+    s2 = mul(s_kp, s_kp, kp, params.ring)
     rlk = switch_key(params, s, s2, seed, DOM_RLK_A, DOM_RLK_E, 0)
     gks = {}
     for r in rotations:
         g = galois_element(params, r)
         if g in gks:
             continue
-        s_g = automorphism(s_kp, g, kp)
+        s_g = automorphism(s_kp, g, kp, params.ring)
         gks[g] = switch_key(params, s, s_g, seed, DOM_GK_A, DOM_GK_E, g * params.dnum)
     assert N == s.size
     return KeySet(params, s, (b, a), rlk, gks)
@@ -324,8 +387,8 @@ def encrypt(params, pk, m, limbs, scale, seed, ct_id):
     e1 = reduce_int(sample_gaussian(params, seed, DOM_ENC_E1, ct_id), primes)
     mm = reduce_int(m, primes)
     b, a = pk[0][:limbs], pk[1][:limbs]
-    c0 = add(add(mul(v, b, primes), e0, primes), mm, primes)
-    c1 = add(mul(v, a, primes), e1, primes)
+    c0 = add(add(mul(v, b, primes, params.ring), e0, primes), mm, primes)
+    c1 = add(mul(v, a, primes, params.ring), e1, primes)
     return Ciphertext([c0, c1], limbs, scale)
 
 
@@ -336,8 +399,8 @@ def decrypt_residues(params, s, ct):
     acc = ct.c[0].copy()
     spow = s_res
     for comp in ct.c[1:]:
-        acc = add(acc, mul(comp, spow, primes), primes)
-        spow = mul(spow, s_res, primes)
+        acc = add(acc, mul(comp, spow, primes, params.ring), primes)
+        spow = mul(spow, s_res, primes, params.ring)
     return acc
 
 
@@ -359,7 +422,7 @@ def crt_centered(params, res):
 
 
 def decrypt_decode(params, s, ct):
-    return decode(crt_centered(params, decrypt_residues(params, s, ct)), ct.scale, params.N)
+    return decode(crt_centered(params, decrypt_residues(params, s, ct)), ct.scale, params.N, params.ring)
 
 
 # --------------------------------------------------------------------------
@@ -391,7 +454,7 @@ def pmul(params, x, pt, pt_scale):
     """Mul(P): multiply both components by the integer plaintext pt."""
     primes = params.q[:x.limbs]
     p = reduce_int(pt, primes)
-    return Ciphertext([mul(c, p, primes) for c in x.c], x.limbs, x.scale * pt_scale)
+    return Ciphertext([mul(c, p, primes, params.ring) for c in x.c], x.limbs, x.scale * pt_scale)
 
 
 def tensor(params, x, y):
@@ -402,9 +465,9 @@ def tensor(params, x, y):
     primes = params.q[:x.limbs]
     a0, a1 = x.c
     b0, b1 = y.c
-    d0 = mul(a0, b0, primes)
-    d1 = add(mul(a0, b1, primes), mul(a1, b0, primes), primes)
-    d2 = mul(a1, b1, primes)
+    d0 = mul(a0, b0, primes, params.ring)
+    d1 = add(mul(a0, b1, primes, params.ring), mul(a1, b0, primes, params.ring), primes)
+    d2 = mul(a1, b1, primes, params.ring)
     return Ciphertext([d0, d1, d2], x.limbs, x.scale * y.scale)
 
 
@@ -437,7 +500,7 @@ def key_switch(params, x, limbs, key):
         for t, mod in enumerate(ext):
             jobs.append((y[t], key.b[j][key_limb[t]], mod))
             jobs.append((y[t], key.a[j][key_limb[t]], mod))
-    prods = prims.polymul_batch(jobs)
+    prods = polymul_jobs(jobs, params.ring)
     u = np.zeros((len(ext), params.N), dtype=np.uint64)
     w = np.zeros((len(ext), params.N), dtype=np.uint64)
     it = iter(prods)
@@ -497,8 +560,8 @@ def rotate(params, x, r, gks):
     if g not in gks:
         raise KeyError("no Galois key for rotation %d" % r)
     primes = params.q[:x.limbs]
-    c0 = automorphism(x.c[0], g, primes)
-    c1 = automorphism(x.c[1], g, primes)
+    c0 = automorphism(x.c[0], g, primes, params.ring)
+    c1 = automorphism(x.c[1], g, primes, params.ring)
     u, w = key_switch(params, c1, x.limbs, gks[g])
     return Ciphertext([add(c0, u, primes), w], x.limbs, x.scale)
 
@@ -522,11 +585,11 @@ def rotation_sum_hoisted(params, x, amounts, gks):
         if g not in gks:
             raise KeyError("no Galois key for rotation %d" % r)
         for j in range(beta):
-            yg = automorphism(ys[j], g, ext)
+            yg = automorphism(ys[j], g, ext, params.ring)
             for t, mod in enumerate(ext):
                 jobs.append((yg[t], gks[g].b[j][key_limb[t]], mod))
                 jobs.append((yg[t], gks[g].a[j][key_limb[t]], mod))
-    prods = iter(prims.polymul_batch(jobs))
+    prods = iter(polymul_jobs(jobs, params.ring))
     u = np.zeros((len(ext), params.N), dtype=np.uint64)
     w = np.zeros((len(ext), params.N), dtype=np.uint64)
     for _ in amounts:
@@ -536,7 +599,7 @@ def rotation_sum_hoisted(params, x, amounts, gks):
                 w[t] = (w[t] + next(prods)) % np.uint64(mod)
     c0 = x.c[0].copy()
     for r in amounts:
-        c0 = add(c0, automorphism(x.c[0], galois_element(params, r), qs), qs)
+        c0 = add(c0, automorphism(x.c[0], galois_element(params, r), qs, params.ring), qs)
     return Ciphertext([add(c0, mod_down(params, u, l), qs), add(x.c[1], mod_down(params, w, l), qs)],
                       l, x.scale)
 

@@ -35,10 +35,10 @@ def is_prime(n):
 
 # ---------------------------------------------------------------- primes
 
-@pytest.mark.parametrize("preset", [1, 2])
+@pytest.mark.parametrize("preset", [1, 2, 3, 4])
 def test_preset_primes_are_ntt_friendly_primes(preset):
     P = ckks.Params.preset(preset)
-    two_n = 2 * P.N
+    two_n = P.M          # 2N, or 4N in the conjugate-invariant ring
     for q in P.q + P.p:
         assert is_prime(q)
         assert q % two_n == 1
@@ -69,6 +69,30 @@ def test_preset_primes_are_largest_in_their_size_class():
     while not is_prime(cand):
         cand -= 2 * c1.N
     assert cand == c1.q[0]
+
+
+@pytest.mark.parametrize("preset", [3, 4])
+def test_ci_preset_primes_are_largest_below_their_bounds(preset):
+    """Conjugate-invariant presets: each size class holds the largest primes
+    below 2^b congruent to 1 mod 4N, in descending order."""
+    P = ckks.Params.preset(preset)
+    step = P.M
+    assert step == 4 * P.N
+
+    def largest(bits, count, skip=()):
+        out = []
+        cand = ((1 << bits) - 1) // step * step + 1
+        while len(out) < count:
+            if cand not in skip and is_prime(cand):
+                out.append(cand)
+            cand -= step
+        return out
+    bits = [q.bit_length() for q in P.q]
+    got = []
+    for b in sorted(set(bits), reverse=True):
+        got += largest(b, bits.count(b))
+    assert got == P.q
+    assert largest(51, len(P.p)) == P.p
 
 
 # ---------------------------------------------------------------- SHAKE-256
