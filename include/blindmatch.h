@@ -68,12 +68,24 @@ typedef struct bm_gallery bm_gallery;
 typedef struct bm_result bm_result;
 typedef struct bm_server bm_server;
 
+/* Rings (Sec. 2): the power-of-two cyclotomic ring Z[X]/(X^N + 1) with N/2
+ * complex slots, or the conjugate-invariant ring Z[X + X^-1] of rank N with N
+ * real slots.  A conjugate-invariant element is stored as its first N
+ * coefficients in Z[X]/(X^2N + 1) (coefficient N is 0 and coefficient 2N - k
+ * is minus coefficient k); its slots are the values at zeta^(5^j), zeta a
+ * primitive 4N-th root of unity, and rotation by r is X -> X^(5^r mod 4N). */
+enum { BM_RING_STD = 0, BM_RING_CI = 1 };
+
 /* Scheme parameters.  q[0..n_q-1] are the chain primes q_0..q_L (n_q = L+1),
  * p[0..n_p-1] the special primes of hybrid key switching, `alpha` chain limbs
  * per key-switching digit (dnum = ceil(n_q / alpha)).  Every prime must be
- * below 2^51 and congruent to 1 mod 2N.  `scale` is the encoding scale Delta,
- * `sigma` the error standard deviation.  `out_limbs` is the default number of
- * limbs a match result is dropped to (0 keeps the natural level). */
+ * below 2^51 and congruent to 1 mod 2N (mod 4N in the conjugate-invariant
+ * ring).  `scale` is the encoding scale Delta, `sigma` the error standard
+ * deviation.  `out_limbs` is the default number of limbs a match result is
+ * dropped to (0 keeps the natural level).  `ring` is BM_RING_STD or
+ * BM_RING_CI.  Below, "slots" means n = N/2 (standard) or N (conjugate-
+ * invariant) and "2N" in a Galois element means the ring's root order M = 2N
+ * or 4N. */
 typedef struct {
   uint32_t log_n;
   uint32_t n_q, n_p, alpha;
@@ -82,13 +94,16 @@ typedef struct {
   uint64_t p[4];
   double scale;
   double sigma;
+  uint32_t ring;
 } bm_params;
 
 /* Preset 1: N = 2^12, q = {50, 40, 40}-bit, one 51-bit special prime,
  * alpha = 1, scale 2^40 (a small parity/test ring, below 128-bit security).
  * Preset 2: N = 2^16, eight 50-bit chain primes, two 51-bit special primes,
  * alpha = 2 (dnum = 4), scale 2^50, out_limbs = 2.  Each prime is the largest
- * below its bit bound that is 1 mod 2N.  Returns BM_EINVAL for other values. */
+ * below its bit bound that is 1 mod 2N.  Presets 3 and 4 are presets 1 and 2
+ * over the conjugate-invariant ring of the same rank N (primes 1 mod 4N).
+ * Returns BM_EINVAL for other values. */
 int bm_params_preset(int preset, bm_params *out);
 
 /* Create a context on HIP device `device`: validates the primes, builds the
@@ -108,6 +123,8 @@ int bm_ctx_set_group_chunk(bm_ctx *ctx, uint32_t groups);
  * gallery or masks handle drops the context's graphs.  Off by default.
  * Kernel profiling (bm_profile_enable) runs matches eagerly. */
 int bm_ctx_set_graphs(bm_ctx *ctx, int on);
+/* The parameters the context was created with. */
+int bm_ctx_params(const bm_ctx *ctx, bm_params *out);
 /* Device memory currently held by the context's caching pool, in bytes. */
 int bm_ctx_pool_bytes(const bm_ctx *ctx, uint64_t *bytes);
 
@@ -164,8 +181,10 @@ void bm_evk_free(bm_evk *evk);
 
 /* Canonical-embedding encoding of n real slots at `scale`:
  * coeffs[k] = round_half_away((2/N) Re sum_j scale*slots[j] zeta^(-k 5^j)),
- * zeta = exp(i pi / N).  `n_slots` must equal N/2.  Double-precision FFT:
- * results may differ by 1 from another implementation on rare coefficients. */
+ * zeta = exp(i pi / N).  `n_slots` must equal N/2.  In the conjugate-invariant
+ * ring the same formula at dimension 2N (zeta = exp(i pi / 2N), n_slots = N)
+ * gives the coefficients 0..N-1.  Double-precision FFT: results may differ by
+ * 1 from another implementation on rare coefficients. */
 int bm_encode(bm_ctx *ctx, const double *slots, size_t n_slots, double scale, int64_t *coeffs);
 /* Public-key encryption of the integer plaintext coeffs[N] at `limbs` chain
  * limbs: (v b + e0 + m, v a + e1), v ternary, e0/e1 Gaussian, drawn from

@@ -20,6 +20,7 @@ BM_S1, BM_S2 = 1, 2
 BM_LEVEL_MIN = 0x100
 BM_COMPRESS = 0x200
 BM_HOIST = 0x400
+BM_RING_STD, BM_RING_CI = 0, 1
 
 
 class BMError(RuntimeError):
@@ -32,11 +33,15 @@ class bm_params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
                 ("alpha", ctypes.c_uint32), ("out_limbs", ctypes.c_uint32),
                 ("q", ctypes.c_uint64 * 16), ("p", ctypes.c_uint64 * 4),
-                ("scale", ctypes.c_double), ("sigma", ctypes.c_double)]
+                ("scale", ctypes.c_double), ("sigma", ctypes.c_double), ("ring", ctypes.c_uint32)]
 
     @property
     def N(self):
         return 1 << self.log_n
+
+    @property
+    def slots(self):
+        return self.N if self.ring == BM_RING_CI else self.N // 2
 
     def chain(self):
         return [int(self.q[i]) for i in range(self.n_q)]
@@ -55,6 +60,7 @@ _SIGS = {
     "bm_params_preset": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(bm_params)]),
     "bm_ctx_create": (ctypes.c_int, [ctypes.POINTER(bm_params), ctypes.c_int, _PP]),
     "bm_ctx_free": (None, [_P]),
+    "bm_ctx_params": (ctypes.c_int, [_P, ctypes.POINTER(bm_params)]),
     "bm_ctx_set_group_chunk": (ctypes.c_int, [_P, _u32]),
     "bm_ctx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
@@ -193,6 +199,12 @@ def bm_ctx_free(ctx):
     lib().bm_ctx_free(ctx)
 
 
+def bm_ctx_params(ctx):
+    p = bm_params()
+    _check(lib().bm_ctx_params(ctx, ctypes.byref(p)), "bm_ctx_params", ctx)
+    return p
+
+
 def bm_ctx_set_group_chunk(ctx, groups):
     _check(lib().bm_ctx_set_group_chunk(ctx, int(groups)), "bm_ctx_set_group_chunk", ctx)
 
@@ -293,7 +305,7 @@ def bm_evk_free(h):
 
 def bm_encode(ctx, slots, scale):
     slots = np.ascontiguousarray(slots, dtype=np.float64)
-    out = np.zeros(2 * slots.size, dtype=np.int64)
+    out = np.zeros(bm_ctx_params(ctx).N, dtype=np.int64)
     _check(lib().bm_encode(ctx, _ptr(slots), slots.size, float(scale), _ptr(out)), "bm_encode", ctx)
     return out
 

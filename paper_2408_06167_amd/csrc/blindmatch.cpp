@@ -25,7 +25,7 @@ int ilog2(u64 v) {
 bool is_pow2(u64 v) { return v && !(v & (v - 1)); }
 
 void check_shape(const Ctx& c, u32 d, u32 k) {
-  if (!is_pow2(d) || !is_pow2(k) || k > d || d > c.n) BM_THROW(BM_EDIM, "need power-of-two k | d <= N/2");
+  if (!is_pow2(d) || !is_pow2(k) || k > d || d > c.n) BM_THROW(BM_EDIM, "need power-of-two k | d <= slot count");
 }
 
 const u64* galois_key(const bm_evk* evk, u64 g) {

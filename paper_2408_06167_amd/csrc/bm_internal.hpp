@@ -241,13 +241,15 @@ struct GraphEntry {
 struct HostPrime {
   u64 q;
   int bits;
-  u64 psi;                 // primitive 2N-th root used by the device NTT
+  u64 psi;                 // primitive M-th root used by the device NTT (2N, or 4N: conjugate-invariant)
 };
 
 struct Ctx {
   int device = 0;
   int log_n = 0;
-  size_t N = 0, n = 0;
+  size_t N = 0, n = 0;     // ring dimension and slots (N/2, or N in the conjugate-invariant ring)
+  bool ci = false;         // conjugate-invariant ring R' = Z[X + X^-1] of rank N
+  u64 M = 0;               // order of the roots behind the slots: 2N, or 4N in the conjugate-invariant ring
   int L = 0;               // top level; fresh ciphertexts have L+1 limbs
   int K = 0, alpha = 1, dnum = 1;
   double scale = 0, sigma = 3.2;
@@ -267,6 +269,8 @@ struct Ctx {
   double* d_twq = nullptr;
   double* d_itwf = nullptr;
   double* d_itwq = nullptr;
+  u64* d_ci = nullptr;             // conjugate-invariant ring: [MAX_PRIMES][4] iota = zeta^N, its Shoup
+                                   // companion, 1/2 and its companion (the fold to Z_q[X]/(X^N - iota))
   ModUpTable* d_modup = nullptr;   // [L+2] indexed by number of chain limbs
   ModDownTable* d_moddown = nullptr;
   u64* d_rescale = nullptr;        // [L+1][L+1][2]: q_l^{-1} mod q_i, Shoup pair
@@ -310,6 +314,10 @@ void sample_uniform(u64 seed, u32 domain, u64 index, const u64* qs, size_t nq, s
 // canonical-embedding encoder (encoder.cpp)
 void encode_slots(size_t N, const double* re, const double* im, double scale, int64_t* out);
 void decode_coeffs(size_t N, const double* m, double scale, double* re, double* im);
+// the context's ring: n real slot values -> N integer coefficients, and back
+// (conjugate-invariant ring: through Z[X]/(X^2N+1), see encoder.cpp)
+void ring_encode(const Ctx& c, const double* slots, double scale, int64_t* out);
+void ring_decode(const Ctx& c, const double* m, double scale, double* slots);
 
 // ----------------------------------------------------------------- device kernels (kernels.hip)
 
@@ -426,6 +434,7 @@ struct bm_masks {
 };
 
 struct bm_ctx {
+  bm_params params;        // as created
   bm::Ctx c;
   // masks of Alg. 1 per (d, k), made on first use (declared after c: freed first)
   std::map<uint64_t, std::unique_ptr<bm_masks>> mask_cache;

@@ -40,9 +40,9 @@ int guarded(bm_ctx* ctx, F&& f) {
   } while (0)
 
 // Largest `count` primes below 2^bits that are 1 mod 2N, in descending order.
-std::vector<u64> primes_below(int bits, size_t N, int count, const std::vector<u64>& avoid) {
+// the `count` largest primes below 2^bits that are 1 mod `step` (2N, or 4N)
+std::vector<u64> primes_below(int bits, u64 step, int count, const std::vector<u64>& avoid) {
   std::vector<u64> out;
-  const u64 step = 2 * N;
   u64 cand = (((1ULL << bits) - 1) / step) * step + 1;
   while ((int)out.size() < count && cand > step) {
     if (h_is_prime(cand) && std::find(avoid.begin(), avoid.end(), cand) == avoid.end())
@@ -83,12 +83,14 @@ int bm_params_preset(int preset, bm_params* out) {
     REQUIRE(out, BM_EINVAL, "out is NULL");
     std::memset(out, 0, sizeof(*out));
     out->sigma = 3.2;
-    if (preset == 1) {
+    if (preset == 1 || preset == 3) {
       const size_t N = 1u << 12;
+      const u64 M = preset == 3 ? 4 * N : 2 * N;
       out->log_n = 12;
-      auto q0 = primes_below(50, N, 1, {});
-      auto q12 = primes_below(40, N, 2, {});
-      auto p = primes_below(51, N, 1, {});
+      out->ring = preset == 3 ? BM_RING_CI : BM_RING_STD;
+      auto q0 = primes_below(50, M, 1, {});
+      auto q12 = primes_below(40, M, 2, {});
+      auto p = primes_below(51, M, 1, {});
       out->n_q = 3;
       out->q[0] = q0[0];
       out->q[1] = q12[0];
@@ -98,11 +100,13 @@ int bm_params_preset(int preset, bm_params* out) {
       out->alpha = 1;
       out->scale = std::ldexp(1.0, 40);
       out->out_limbs = 0;
-    } else if (preset == 2) {
+    } else if (preset == 2 || preset == 4) {
       const size_t N = 1u << 16;
+      const u64 M = preset == 4 ? 4 * N : 2 * N;
       out->log_n = 16;
-      auto q = primes_below(50, N, 8, {});
-      auto p = primes_below(51, N, 2, {});
+      out->ring = preset == 4 ? BM_RING_CI : BM_RING_STD;
+      auto q = primes_below(50, M, 8, {});
+      auto p = primes_below(51, M, 2, {});
       out->n_q = 8;
       for (int i = 0; i < 8; ++i) out->q[i] = q[i];
       out->n_p = 2;
@@ -126,11 +130,15 @@ int bm_ctx_create(const bm_params* p, int device, bm_ctx** out) {
     REQUIRE(p->alpha >= 1 && p->alpha <= (uint32_t)MAX_ALPHA, BM_EINVAL, "alpha in [1, 4]");
     REQUIRE(p->n_q + p->n_p <= (uint32_t)MAX_PRIMES, BM_EINVAL, "too many primes");
     std::unique_ptr<bm_ctx> h(new bm_ctx);
+    h->params = *p;
     Ctx& c = h->c;
     c.device = device;
     c.log_n = (int)p->log_n;
     c.N = (size_t)1 << p->log_n;
-    c.n = c.N / 2;
+    REQUIRE(p->ring == BM_RING_STD || p->ring == BM_RING_CI, BM_EINVAL, "unknown ring");
+    c.ci = p->ring == BM_RING_CI;
+    c.n = c.ci ? c.N : c.N / 2;
+    c.M = c.ci ? 4 * (u64)c.N : 2 * (u64)c.N;
     c.L = (int)p->n_q - 1;
     c.K = (int)p->n_p;
     c.alpha = (int)p->alpha;
@@ -146,13 +154,13 @@ int bm_ctx_create(const bm_params* p, int device, bm_ctx** out) {
     for (size_t i = 0; i < all.size(); ++i) {
       const u64 q = all[i];
       REQUIRE(q > 2 && q < (1ULL << 51), BM_EINVAL, "primes must lie below 2^51");
-      REQUIRE(q % (2 * c.N) == 1, BM_EINVAL, "primes must be 1 mod 2N");
+      REQUIRE(q % c.M == 1, BM_EINVAL, c.ci ? "primes must be 1 mod 4N" : "primes must be 1 mod 2N");
       REQUIRE(h_is_prime(q), BM_EINVAL, "modulus is not prime");
       for (size_t j = 0; j < i; ++j) REQUIRE(all[j] != q, BM_EINVAL, "repeated prime");
       HostPrime hp;
       hp.q = q;
       hp.bits = 64 - __builtin_clzll(q);
-      hp.psi = h_primitive_2n_root(q, c.N);
+      hp.psi = h_primitive_2n_root(q, c.M / 2);   // primitive M-th root
       c.primes.push_back(hp);
     }
     c.cdt = gaussian_cdt(c.sigma, 19);
@@ -321,10 +329,11 @@ int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot
         e->gk.emplace(g, std::move(key));
       }
       // device table of the Galois keys by g / 2, for the hoisted rotation sums
-      std::vector<u64> tab(c.N, 0);
+      std::vector<u64> tab(c.M / 2, 0);
       for (auto& kv : e->gk) tab[kv.first >> 1] = (u64)(uintptr_t)kv.second->k.p();
-      e->gtab = DBuf(&c, c.N);
-      HIP_OK(dev::memcpy_async(e->gtab.p(), tab.data(), c.N * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+      e->gtab = DBuf(&c, c.M / 2);
+      HIP_OK(dev::memcpy_async(e->gtab.p(), tab.data(), tab.size() * sizeof(u64), hipMemcpyHostToDevice,
+                               c.stream));
       sync(c);
     }
     sync(c);
@@ -388,11 +397,18 @@ void bm_evk_free(bm_evk* evk) {
 
 // ------------------------------------------------------------------ encode / encrypt
 
+int bm_ctx_params(const bm_ctx* ctx, bm_params* out) {
+  return guarded(nullptr, [&] {
+    REQUIRE(ctx && out, BM_EINVAL, "NULL argument");
+    *out = ctx->params;
+  });
+}
+
 int bm_encode(bm_ctx* ctx, const double* slots, size_t n_slots, double scale, int64_t* coeffs) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && slots && coeffs, BM_EINVAL, "NULL argument");
-    REQUIRE(n_slots == ctx->c.n, BM_EINVAL, "n_slots must be N/2");
-    encode_slots(ctx->c.N, slots, nullptr, scale, coeffs);
+    REQUIRE(n_slots == ctx->c.n, BM_EINVAL, "n_slots must equal the slot count");
+    ring_encode(ctx->c, slots, scale, coeffs);
   });
 }
 
@@ -425,11 +441,11 @@ int bm_encrypt_query(bm_ctx* ctx, const bm_pk* pk, const float* q, uint32_t d, u
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && q && out, BM_EINVAL, "NULL argument");
     Ctx& c = ctx->c;
-    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= N/2");
+    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= slot count");
     std::vector<double> slots(c.n);
     for (size_t s = 0; s < c.n; ++s) slots[s] = (double)q[s % d];
     std::vector<int64_t> m(c.N);
-    encode_slots(c.N, slots.data(), nullptr, c.scale, m.data());
+    ring_encode(c, slots.data(), c.scale, m.data());
     c.use_stream(nullptr);
     std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, c.L + 1, c.scale));
     ev::encrypt_batch(c, pk, m.data(), 1, c.L + 1, seed, &ct_id, ct->buf.p());
@@ -443,11 +459,11 @@ int bm_encrypt_template(bm_ctx* ctx, const bm_pk* pk, const float* x, uint32_t d
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && x && out, BM_EINVAL, "NULL argument");
     Ctx& c = ctx->c;
-    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= N/2");
+    REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= slot count");
     std::vector<double> slots(c.n, 0.0);
     for (size_t s = 0; s < d; ++s) slots[s] = (double)x[s];
     std::vector<int64_t> m(c.N);
-    encode_slots(c.N, slots.data(), nullptr, c.scale, m.data());
+    ring_encode(c, slots.data(), c.scale, m.data());
     c.use_stream(nullptr);
     std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, c.L + 1, c.scale));
     ev::encrypt_batch(c, pk, m.data(), 1, c.L + 1, seed, &ct_id, ct->buf.p());
@@ -502,7 +518,7 @@ int bm_encrypt_gallery(bm_ctx* ctx, const bm_pk* pk, const float* x, uint64_t n,
               const uint64_t tid = g * T + s / cc;
               slots[s] = tid < n ? (double)x[tid * d + i * cc + s % cc] : 0.0;
             }
-            encode_slots(N, slots.data(), nullptr, c.scale, m.data() + b * N);
+            ring_encode(c, slots.data(), c.scale, m.data() + b * N);
           }
         });
       for (auto& th1 : th) th1.join();
@@ -597,11 +613,11 @@ int bm_decrypt_slots(bm_ctx* ctx, const bm_sk* sk, const bm_ct* ct, double* slot
   return guarded(ctx, [&] {
     REQUIRE(ctx && sk && ct && slots, BM_EINVAL, "NULL argument");
     Ctx& c = ctx->c;
-    REQUIRE(n == c.n, BM_EINVAL, "n must be N/2");
+    REQUIRE(n == c.n, BM_EINVAL, "n must equal the slot count");
     c.use_stream(nullptr);
     std::vector<double> m(c.N);
     ev::decrypt_coeffs(c, sk, ct->buf.p(), (int)ct->comps, (int)ct->limbs, m.data());
-    decode_coeffs(c.N, m.data(), ct->scale, slots, nullptr);
+    ring_decode(c, m.data(), ct->scale, slots);
   });
 }
 
@@ -761,7 +777,7 @@ bm_masks* bmx_create_masks(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t ql) {
   std::vector<double> slots(c.n);
   for (uint32_t i = 0; i < k; ++i) {
     for (size_t s = 0; s < c.n; ++s) slots[s] = ((s % d) / cc == i) ? 1.0 : 0.0;
-    encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
+    ring_encode(c, slots.data(), scale, coeffs.data() + (size_t)i * c.N);
   }
   return make_masks(ctx, d, k, coeffs.data(), scale);
 }
@@ -781,7 +797,7 @@ const bm_masks* bmx_enroll_masks(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t l
   std::vector<double> slots(c.n);
   for (uint32_t i = 0; i < k; ++i) {
     for (size_t s = 0; s < c.n; ++s) slots[s] = (s >= (size_t)i * cc && s < (size_t)(i + 1) * cc) ? 1.0 : 0.0;
-    encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data() + (size_t)i * c.N);
+    ring_encode(c, slots.data(), scale, coeffs.data() + (size_t)i * c.N);
   }
   bm_masks* m = make_masks(ctx, d, k, coeffs.data(), scale);
   return ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(m)).first->second.get();
@@ -843,7 +859,7 @@ const bm_masks* bmx_compress_mask(bm_ctx* ctx, uint32_t d, uint32_t k, uint32_t 
   std::vector<int64_t> coeffs(c.N);
   std::vector<double> slots(c.n);
   for (size_t s = 0; s < c.n; ++s) slots[s] = s % cc == 0 ? 1.0 : 0.0;
-  encode_slots(c.N, slots.data(), nullptr, scale, coeffs.data());
+  ring_encode(c, slots.data(), scale, coeffs.data());
   bm_masks* m = make_masks(ctx, d, 1, coeffs.data(), scale);
   m->k = k;
   return ctx->mask_cache.emplace(key, std::unique_ptr<bm_masks>(m)).first->second.get();
@@ -1197,7 +1213,7 @@ int bm_decrypt_scores(bm_ctx* ctx, const bm_sk* sk, const bm_result* r, double* 
     std::vector<double> m(c.N), re(c.n);
     for (uint64_t o = 0; o < r->groups; ++o) {
       ev::decrypt_coeffs(c, sk, r->p() + o * 2 * (size_t)r->limbs * c.N, 2, (int)r->limbs, m.data());
-      decode_coeffs(c.N, m.data(), r->scale, re.data(), nullptr);
+      ring_decode(c, m.data(), r->scale, re.data());
       for (uint64_t j = 0; j < per; ++j) {
         const uint64_t g = o * per + j;
         for (uint64_t b = 0; b < T; ++b) {

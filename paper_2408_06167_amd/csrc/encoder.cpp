@@ -85,4 +85,32 @@ void decode_coeffs(size_t N, const double* m, double scale, double* re, double* 
   }
 }
 
+// Conjugate-invariant ring R' = Z[X + X^-1] of rank N: an element is kept as
+// its first N coefficients in Z[X]/(X^2N+1), the rest following from
+// a(X^-1) = a(X) (c_N = 0, c_{2N-k} = -c_k).  The canonical embedding of
+// Z[X]/(X^2N+1) with real slot values (slot j at zeta^(5^j), zeta of order
+// 4N) produces exactly such coefficients, so encoding runs at dimension 2N
+// and keeps the first N; decoding extends and takes the real parts.
+void ring_encode(const Ctx& c, const double* slots, double scale, int64_t* out) {
+  if (!c.ci) {
+    encode_slots(c.N, slots, nullptr, scale, out);
+    return;
+  }
+  std::vector<int64_t> full(2 * c.N);
+  encode_slots(2 * c.N, slots, nullptr, scale, full.data());
+  std::copy(full.begin(), full.begin() + c.N, out);
+}
+
+void ring_decode(const Ctx& c, const double* m, double scale, double* slots) {
+  if (!c.ci) {
+    decode_coeffs(c.N, m, scale, slots, nullptr);
+    return;
+  }
+  const size_t N = c.N;
+  std::vector<double> full(2 * N, 0.0);
+  for (size_t k = 0; k < N; ++k) full[k] = m[k];
+  for (size_t k = 1; k < N; ++k) full[2 * N - k] = -m[k];
+  decode_coeffs(2 * N, full.data(), scale, slots, nullptr);
+}
+
 }  // namespace bm

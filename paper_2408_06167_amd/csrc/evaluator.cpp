@@ -138,7 +138,7 @@ Ctx::~Ctx() {
   pool.reset();
   if (owns_tables)
     for (void* p : {(void*)d_primes, (void*)d_tw, (void*)d_tws, (void*)d_itw, (void*)d_itws, (void*)d_twf,
-                    (void*)d_twq, (void*)d_itwf, (void*)d_itwq, (void*)d_modup, (void*)d_moddown,
+                    (void*)d_twq, (void*)d_itwf, (void*)d_itwq, (void*)d_ci, (void*)d_modup, (void*)d_moddown,
                     (void*)d_rescale})
       if (p) {
         audit::remove(p);
@@ -153,6 +153,8 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->log_n = log_n;
   l->N = N;
   l->n = n;
+  l->ci = ci;
+  l->M = M;
   l->L = L;
   l->K = K;
   l->alpha = alpha;
@@ -171,6 +173,7 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->d_twq = d_twq;
   l->d_itwf = d_itwf;
   l->d_itwq = d_itwq;
+  l->d_ci = d_ci;
   l->d_modup = d_modup;
   l->d_moddown = d_moddown;
   l->d_rescale = d_rescale;
@@ -242,7 +245,7 @@ namespace ev {
 u64 galois_for_rotation(const Ctx& c, long r) {
   const long n = (long)c.n;
   long e = ((r % n) + n) % n;
-  return h_powmod(5, (u64)e, 2 * c.N);
+  return h_powmod(5, (u64)e, c.M);
 }
 
 // ----------------------------------------------------------------- key switching

@@ -4,6 +4,10 @@
 // generator g of Z_q^*, found by factoring q-1.  Twiddles are stored in
 // bit-reversed order (W[k] = psi^{brv(k)}) with Shoup companions
 // floor(W[k] 2^64 / q), so a butterfly needs one 64x64-high multiply.
+// Conjugate-invariant ring: the transform evaluates a polynomial reduced
+// modulo X^N - zeta^N (zeta a primitive 4N-th root) at its roots
+// zeta^(1 + 4 brv(i)); the same butterflies do so with twiddles
+// W[2^S + B] = zeta^(2 brv(2^S + B) - N / 2^(S+1)), S = floor(log2 k).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -126,7 +130,7 @@ void build_context_tables(Ctx& c) {
   std::vector<u64> tw(MAX_PRIMES * N), tws(MAX_PRIMES * N), itw(MAX_PRIMES * N),
       itws(MAX_PRIMES * N);
   std::vector<double> twf(MAX_PRIMES * N), twq(MAX_PRIMES * N), itwf(MAX_PRIMES * N), itwq(MAX_PRIMES * N);
-  std::vector<u64> pw(N), ipw(N);
+  std::vector<u64> pw(N), ipw(N), ci(4 * MAX_PRIMES, 0);
   for (int i = 0; i < np; ++i) {
     const u64 q = c.primes[i].q;
     PrimeC& p = pc[i];
@@ -142,15 +146,29 @@ void build_context_tables(Ctx& c) {
     const double qd = (double)q, qinv = 1.0 / qd, niq = (double)p.ninv / qd;
     std::memcpy(&p.pad[1], &qinv, sizeof(double));
     std::memcpy(&p.pad[2], &niq, sizeof(double));
-    const u64 psi = c.primes[i].psi;
+    const u64 psi = c.primes[i].psi;   // primitive M-th root
     const u64 ipsi = h_invmod(psi, q);
+    const size_t E = c.ci ? 2 * N : N;  // exponents the twiddles use
+    pw.resize(E);
+    ipw.resize(E);
     pw[0] = ipw[0] = 1;
-    for (size_t k = 1; k < N; ++k) {
+    for (size_t k = 1; k < E; ++k) {
       pw[k] = h_mulmod(pw[k - 1], psi, q);
       ipw[k] = h_mulmod(ipw[k - 1], ipsi, q);
     }
+    if (c.ci) {
+      const u64 io = h_powmod(psi, N, q), h = (q + 1) / 2;
+      ci[4 * i] = io;
+      ci[4 * i + 1] = h_shoup(io, q);
+      ci[4 * i + 2] = h;
+      ci[4 * i + 3] = h_shoup(h, q);
+    }
     for (size_t k = 0; k < N; ++k) {
       u32 r = brv((u32)k, c.log_n);
+      if (c.ci && k > 0) {
+        int S = 31 - __builtin_clz((u32)k);
+        r = 2 * r - (u32)(N >> (S + 1));
+      }
       tw[i * N + k] = pw[r];
       tws[i * N + k] = h_shoup(pw[r], q);
       itw[i * N + k] = ipw[r];
@@ -183,6 +201,9 @@ void build_context_tables(Ctx& c) {
   HIP_OK(dev::memcpy(c.d_twq, twq.data(), tb, hipMemcpyHostToDevice));
   HIP_OK(dev::memcpy(c.d_itwf, itwf.data(), tb, hipMemcpyHostToDevice));
   HIP_OK(dev::memcpy(c.d_itwq, itwq.data(), tb, hipMemcpyHostToDevice));
+  HIP_OK(dev::malloc(&c.d_ci, ci.size() * sizeof(u64)));
+  audit::add(c.d_ci, ci.size() * sizeof(u64));
+  HIP_OK(dev::memcpy(c.d_ci, ci.data(), ci.size() * sizeof(u64), hipMemcpyHostToDevice));
 
   // ---- ModUp tables, one per number of chain limbs l = 1..L+1
   const int nq = c.L + 1;

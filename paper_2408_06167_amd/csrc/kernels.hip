@@ -566,22 +566,61 @@ __global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, size_t
   }
 }
 
-// evaluation-domain automorphism: out[j] = in[j'] with
-// 2 brv(j') + 1 = g (2 brv(j) + 1) mod 2N.  blockIdx.y = row (comp*limbs + limb).
-// Batch element z uses g1 when bit `sel` of z is set, g0 otherwise.
+// Position of the source word of an automorphism X -> X^g in the bit-reversed
+// evaluation domain: out[i] = in[src].  Word i holds the value at w^(1 + M/N
+// brv(i)) for w a primitive M-th root of unity, M = N << ms (ms = 1: the roots
+// of X^N + 1; ms = 2: the conjugate-invariant ring's evaluation points, the
+// roots of X^N - w^N), and X -> X^g maps that point onto the one of
+// exponent g (1 + (M/N) brv(i)) mod M, again 1 mod M/N as g is.
+__device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n, int ms) {
+  const u32 rj = __brev(i) >> (32 - log_n);
+  const u32 e = (u32)(((u64)((rj << ms) + 1) * g) & ((1u << (log_n + ms)) - 1));
+  return __brev((e - 1) >> ms) >> (32 - log_n);
+}
+
+// evaluation-domain automorphism: out[j] = in[autom_src(j)].  blockIdx.y = row
+// (comp*limbs + limb).  Batch element z uses g1 when bit `sel` of z is set,
+// g0 otherwise.
 __global__ void k_automorphism(const u64* in, size_t si, u64* out, size_t so, u64 g0, u64 g1, int sel,
-                               int log_n) {
+                               int log_n, int ms) {
   const int N = 1 << log_n;
   const size_t row = (size_t)blockIdx.y * N;
   const u64* I = in + (size_t)blockIdx.z * si + row;
   u64* O = out + (size_t)blockIdx.z * so + row;
   const u64 g = ((blockIdx.z >> sel) & 1) ? g1 : g0;
-  const u32 mask2n = (2u << log_n) - 1;
-  EW_LOOP {
-    const u32 rj = __brev((u32)i) >> (32 - log_n);
-    const u32 e = (u32)(((u64)(2 * rj + 1) * g) & mask2n);
-    const u32 src = __brev((e - 1) >> 1) >> (32 - log_n);
-    O[i] = I[src];
+  EW_LOOP O[i] = I[autom_src((u32)i, (u32)g, log_n, ms)];
+}
+
+// Conjugate-invariant ring: an element c (coefficients 0..N-1 of a polynomial
+// of Z_q[X]/(X^2N+1) with c_N = 0 and c_{2N-k} = -c_k) is reduced modulo
+// X^N - iota, iota = w^N for w a primitive 4N-th root, whose N roots are the
+// evaluation points: b_k = c_k - iota c_{N-k} (b_0 = c_0).  The reduction is
+// a ring homomorphism, invertible on such elements:
+// c_k = (b_k + iota b_{N-k}) / 2 (c_0 = b_0).  One thread handles the pair
+// (k, N-k), so in == out is allowed.  ci[prime] = {iota, its Shoup
+// companion, 1/2, its companion}.
+__global__ void k_ci_fold(const u64* in, size_t si, u64* out, size_t so, LimbMap m, const PrimeC* P,
+                          const u64* ci, int N, int inverse) {
+  const int slot = blockIdx.y;
+  const int pid = m.prime[slot];
+  const u64 q = P[pid].q;
+  const u64 io = ci[4 * pid], ios = ci[4 * pid + 1], h = ci[4 * pid + 2], hs = ci[4 * pid + 3];
+  const u64* I = in + (size_t)blockIdx.z * si + (size_t)m.off[slot] * N;
+  u64* O = out + (size_t)blockIdx.z * so + (size_t)m.ooff[slot] * N;
+  for (int k = blockIdx.x * TPB + threadIdx.x; k <= N / 2; k += gridDim.x * TPB) {
+    if (k == 0) {
+      O[0] = I[0];
+      continue;
+    }
+    const u64 a = I[k], b = I[N - k];
+    const u64 ib = mul_shoup(b, io, ios, q), ia = mul_shoup(a, io, ios, q);
+    if (inverse) {
+      O[k] = mul_shoup(add_mod(a, ib, q), h, hs, q);
+      O[N - k] = mul_shoup(add_mod(b, ia, q), h, hs, q);
+    } else {
+      O[k] = sub_mod(a, ib, q);
+      O[N - k] = sub_mod(b, ia, q);
+    }
   }
 }
 
@@ -641,14 +680,6 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   }
 }
 
-// Position of the source word of an automorphism X -> X^g in the bit-reversed
-// evaluation domain: out[i] = in[src].
-__device__ __forceinline__ u32 autom_src(u32 i, u32 g, int log_n) {
-  const u32 rj = __brev(i) >> (32 - log_n);
-  const u32 e = (u32)(((u64)(2 * rj + 1) * g) & ((2u << log_n) - 1));
-  return __brev((e - 1) >> 1) >> (32 - log_n);
-}
-
 // Hoisted key inner products: for element z,
 //   (u, w)[z] = sum_a sum_j phi_{g(z,a)}(y_j[z]) * key_{g(z,a), j}     over Q_l u P,
 // the automorphism read as a gather (an aligned block of consecutive words
@@ -667,7 +698,7 @@ __device__ __forceinline__ int xcd_block(int w, int W) { return (w & 7) * (W >> 
 
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
-                            const PrimeC* P, int log_n, int B, int accumulate) {
+                            const PrimeC* P, int log_n, int ms, int B, int accumulate) {
   const ModUpTable& tb = *T;
   const int N = 1 << log_n;
   const int ext = tb.ext;
@@ -693,7 +724,7 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 #pragma unroll 4
   for (int a = 0; a < h.A; ++a) {
     const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-    const u32 src = autom_src((u32)i, g, log_n);
+    const u32 src = autom_src((u32)i, g, log_n, ms);
     // the key pointer comes from memory: tell the compiler it is a global one
     const __attribute__((address_space(1))) u64* key = (const __attribute__((address_space(1))) u64*)kp[a];
 #pragma unroll
@@ -716,7 +747,7 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 // out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
 // (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in)
 __global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, HoistArgs h, const PrimeC* P,
-                            int log_n, int limbs, int accumulate) {
+                            int log_n, int ms, int limbs, int accumulate) {
   const int N = 1 << log_n;
   // 1-D XCD-aware grid of (element, limb, position block), position block fastest
   const int gx = (N + TPB - 1) / TPB;
@@ -731,7 +762,7 @@ __global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, Hoist
   u64 acc = accumulate ? O[i] : I[i];
   for (int a = 0; a < h.A; ++a) {
     const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-    acc = add_mod(acc, I[autom_src((u32)i, g, log_n)], q);
+    acc = add_mod(acc, I[autom_src((u32)i, g, log_n, ms)], q);
   }
   O[i] = acc;
 }
@@ -975,9 +1006,43 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   }
 }
 
+// Conjugate-invariant ring: reduction modulo X^N - iota before the forward
+// transform, and its inverse after the inverse transform (k_ci_fold).
+void ci_fold(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B, const LimbMap& m,
+             bool inverse) {
+  chk_map(c, in, B, si, m, "ci fold input");
+  chk_map(c, out, B, so, m, "ci fold output", true);
+  Prof pf(c, inverse ? "ci_unfold" : "ci_fold", 16.0 * c.N * m.n * B, 2.0 * c.N * m.n * B);
+  size_t bx = (c.N / 2 + 1 + TPB * 2 - 1) / (TPB * 2);
+  LAUNCH(k_ci_fold, dim3((unsigned)bx, (unsigned)m.n, (unsigned)B), dim3(TPB), 0, c.stream, in, si, out, so, m,
+         c.d_primes, c.d_ci, (int)c.N, inverse ? 1 : 0);
+  check_launch();
+}
+
+void ntt_core(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+              const LimbMap& m, bool inverse);
+
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
          const LimbMap& m, bool inverse) {
   if (B <= 0 || m.n <= 0) return;
+  if (!c.ci) {
+    ntt_core(c, in, in_stride, out, out_stride, B, m, inverse);
+    return;
+  }
+  // the second step works in place on `out`, addressed with the output offsets
+  LimbMap m_out = m;
+  for (int i = 0; i < m.n; ++i) m_out.off[i] = m.ooff[i];
+  if (!inverse) {
+    ci_fold(c, in, in_stride, out, out_stride, B, m, false);
+    ntt_core(c, out, out_stride, out, out_stride, B, m_out, false);
+  } else {
+    ntt_core(c, in, in_stride, out, out_stride, B, m, true);
+    ci_fold(c, out, out_stride, out, out_stride, B, m_out, true);
+  }
+}
+
+void ntt_core(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+              const LimbMap& m, bool inverse) {
   const int logn = c.log_n;
   const int N = 1 << logn;
   const int E = N < NTT_E ? N : NTT_E;
@@ -1112,11 +1177,12 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
                   u64 g0, u64 g1, int sel) {
   chk(in, B, si, 0, (size_t)rows * c.N, "automorphism in");
   chk(out, B, so, 0, (size_t)rows * c.N, "automorphism out");
-  if ((g0 & 1) == 0 || (g1 & 1) == 0 || g0 >= 2 * c.N || g1 >= 2 * c.N)
+  const u64 gm = c.ci ? 3 : 1;   // Galois elements are 1 mod M/N
+  if ((g0 & gm) != 1 || (g1 & gm) != 1 || g0 >= c.M || g1 >= c.M)
     BM_THROW(BM_EINVAL, "launch check: Galois element");
   Prof pf(c, "automorphism", 16.0 * c.N * B * rows, 0.0);
   LAUNCH(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out, so, g0, g1,
-         sel, c.log_n);
+         sel, c.log_n, c.ci ? 2 : 1);
   check_launch();
 }
 
@@ -1161,7 +1227,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   if (h.A < 1 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
   chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "hoisted kip digits");
   chk(y_own, B, sown, 0, (size_t)limbs * c.N, "hoisted kip input");
-  chk(gtab, 1, 0, 0, c.N, "key table");
+  chk(gtab, 1, 0, 0, c.M / 2, "key table");
   for (const u64* key : keys) chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "hoisted kip key");
   chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "hoisted kip output");
   const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
@@ -1172,7 +1238,8 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const size_t W = gx * tb.ext * B;
   if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
   LAUNCH(k_kip_hoist, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
-         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, B, accumulate ? 1 : 0);
+         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,
+         accumulate ? 1 : 0);
   check_launch();
 }
 
@@ -1184,8 +1251,8 @@ void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, cons
   Prof pf(c, "autom_sum", 8.0 * c.N * B * limbs * (h.A + 2), (double)c.N * B * limbs * h.A);
   const size_t W = (size_t)((c.N + TPB - 1) / TPB) * limbs * B;
   if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
-  LAUNCH(k_autom_sum, dim3((unsigned)W), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes, c.log_n, limbs,
-         accumulate ? 1 : 0);
+  LAUNCH(k_autom_sum, dim3((unsigned)W), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes, c.log_n,
+         c.ci ? 2 : 1, limbs, accumulate ? 1 : 0);
   check_launch();
 }
 

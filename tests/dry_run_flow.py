@@ -62,7 +62,7 @@ def flow(preset, shapes, n_templates):
                 bm.bm_result_export(ctx, r, G - 1, N)
                 bm.bm_result_free(r)
         # compression: needs one level more than the plain match
-        can_compress = preset == 2 or k == 1
+        can_compress = preset in (2, 4) or k == 1
         if d // k <= 32:
             for s in (1 | bm.BM_HOIST, 2 | bm.BM_HOIST | bm.BM_LEVEL_MIN):
                 bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
@@ -94,7 +94,7 @@ def flow(preset, shapes, n_templates):
             bm.bm_result_free(r)
         bm.bm_ctx_set_group_chunk(ctx, 0)
         # server-side enrollment into an empty gallery, then a match against it
-        c_, T_ = d // k, (N // 2) // (d // k)
+        c_, T_ = d // k, p.slots // (d // k)
         eg = bm.bm_gallery_create(ctx, d, k, 2 * T_, L1 - 1)
         users = [bm.bm_encrypt_template(ctx, pk, X[i], 1, 700 + i) for i in range(3)]
         bm.bm_enroll(ctx, evk, eg, users, [0, T_ + 1, 2 * T_ - 1])
@@ -123,4 +123,7 @@ def flow(preset, shapes, n_templates):
 if __name__ == "__main__":
     flow(1, [(16, 1), (16, 2), (16, 4), (8, 8)], 300)
     flow(2, [(128, 1), (128, 4), (128, 16), (16, 1)], 5000)
+    # conjugate-invariant ring (N real slots)
+    flow(3, [(16, 1), (16, 4), (8, 8)], 600)
+    flow(4, [(128, 4), (128, 16)], 9000)
     print("dry run ok")

@@ -36,7 +36,7 @@ def oracle_keys(preset, rots):
 
 # shapes whose hoisted-schedule keys are generated too (c - 1 + unrolled Alg. 1
 # keys each; the k = 1, 2 shapes at N = 2^16 would need 63 to 127 more)
-HOIST_SHAPES = {1: None, 2: [(128, 4)]}
+HOIST_SHAPES = {1: None, 2: [(128, 4)], 3: None, 4: [(128, 4)]}
 
 
 def all_rotations(preset, shapes):

@@ -1,0 +1,280 @@
+"""GPU parity in the conjugate-invariant ring (Sec. 2; presets 3 and 4: N real
+slots at rank N).  As for the standard ring, inputs come from the oracle or the
+seeded generators, and every word the library produces is compared with the
+oracle's; scores are compared with the FP64 cosine (1e-4)."""
+import numpy as np
+import pytest
+
+from gpu_common import (SEED, lib_ctx, lib_keys, oracle_keys, all_rotations, ct_words,
+                        assert_words_equal, log)
+from oracle import ckks, blindmatch as obm
+from workloads import face_gallery
+
+pytestmark = pytest.mark.gpu
+
+CI_SHAPES = {3: [(16, 1), (16, 4), (8, 8)], 4: [(128, 4)]}
+
+
+@pytest.fixture(scope="module")
+def bm():
+    import paper_2408_06167_amd as bm
+    return bm
+
+
+def setup(preset):
+    rots = all_rotations(preset, CI_SHAPES[preset])
+    P, okeys = oracle_keys(preset, rots)
+    ctx = lib_ctx(preset)
+    sk, pk, evk = lib_keys(preset, rots)
+    return P, okeys, ctx, sk, pk, evk
+
+
+def random_ct(P, rng, limbs, comps=2):
+    return np.stack([np.stack([rng.integers(0, q, P.N, dtype=np.uint64) for q in P.q[:limbs]])
+                     for _ in range(comps)])
+
+
+def root_of_order(q, M):
+    """g^((q-1)/M) for g the least generator of Z_q^* (a primitive M-th root)."""
+    m, fac, f = q - 1, [], 2
+    while f * f <= m:
+        if m % f == 0:
+            fac.append(f)
+            while m % f == 0:
+                m //= f
+        f += 1 if f == 2 else 2
+    if m > 1:
+        fac.append(m)
+    g = 2
+    while any(pow(g, (q - 1) // p, q) == 1 for p in fac):
+        g += 1
+    return pow(g, (q - 1) // M, q)
+
+
+def brv(x, bits):
+    return int(format(x, "0%db" % bits)[::-1], 2)
+
+
+@pytest.mark.parametrize("preset", [3, 4])
+def test_ntt_evaluates_the_invariant_polynomial(bm, preset):
+    """Forward transform position j holds the value of the ring element (its
+    length-2N extension: c_N = 0, c_{2N-k} = -c_k) at zeta^(1 + 4 brv(j)), zeta
+    a primitive 4N-th root (sampled positions, Python integers); the inverse
+    restores every word."""
+    import torch
+    P = ckks.Params.preset(preset)
+    ctx = lib_ctx(preset)
+    primes = P.q + P.p
+    N, logn = P.N, P.log_n
+    rng = np.random.default_rng(preset)
+    host = np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in primes])
+    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+    log("ci ntt preset %d: %d limbs of N=%d" % (preset, len(primes), N))
+    bm.bm_ntt(ctx, dev.data_ptr(), 1, list(range(len(primes))), inverse=False)
+    torch.cuda.synchronize()
+    fwd = dev.cpu().numpy().view(np.uint64)
+    for li, q in enumerate(primes):
+        zeta = root_of_order(q, 4 * N)
+        c = [int(v) for v in host[li]]
+        ext = c + [0] + [(q - c[N - t]) % q for t in range(1, N)]   # coefficient N + t = -c_{N-t}
+        for j in [0, N - 1] + [int(x) for x in rng.integers(0, N, 2)]:
+            w = pow(zeta, 1 + 4 * brv(j, logn), q)
+            acc, pw = 0, 1
+            for coef in ext:
+                acc += coef * pw
+                pw = pw * w % q
+            assert int(fwd[li, j]) == acc % q, "prime %d position %d" % (li, j)
+    bm.bm_ntt(ctx, dev.data_ptr(), 1, list(range(len(primes))), inverse=True)
+    torch.cuda.synchronize()
+    assert_words_equal(dev.cpu().numpy().view(np.uint64), host, "inverse(forward(a))")
+
+
+@pytest.mark.parametrize("preset", [3, 4])
+def test_ci_keys_bit_exact(bm, preset):
+    P, okeys, ctx, sk, pk, evk = setup(preset)
+    log("ci keys preset %d" % preset)
+    assert np.array_equal(bm.bm_sk_export(sk, P.N), okeys.s)
+    for comp in (0, 1):
+        assert_words_equal(bm.bm_pk_export(ctx, pk, comp, P.L + 1, P.N), okeys.pk[comp], "pk[%d]" % comp)
+    nprimes = len(P.q) + len(P.p)
+    for j in range(P.dnum):
+        assert_words_equal(bm.bm_evk_export(ctx, evk, 0, j, 0, nprimes, P.N), okeys.rlk.b[j], "rlk.b[%d]" % j)
+        assert_words_equal(bm.bm_evk_export(ctx, evk, 0, j, 1, nprimes, P.N), okeys.rlk.a[j], "rlk.a[%d]" % j)
+    gs = sorted(okeys.gks)
+    for g in (gs[0], gs[-1]):
+        for j in range(P.dnum):
+            assert_words_equal(bm.bm_evk_export(ctx, evk, g, j, 0, nprimes, P.N), okeys.gks[g].b[j], "gk.b")
+            assert_words_equal(bm.bm_evk_export(ctx, evk, g, j, 1, nprimes, P.N), okeys.gks[g].a[j], "gk.a")
+
+
+@pytest.mark.parametrize("preset,limbs", [(3, 3), (3, 2), (4, 8), (4, 3)])
+def test_ci_encrypt_decrypt(bm, preset, limbs):
+    P, okeys, ctx, sk, pk, evk = setup(preset)
+    rng = np.random.default_rng(limbs + 40)
+    z = rng.uniform(-1, 1, P.n)
+    m = ckks.encode(z, P.scale, P.N, P.ring)
+    assert np.max(np.abs(bm.bm_encode(ctx, z, P.scale) - m)) <= 1
+    want = ckks.encrypt(P, okeys.pk, m, limbs, P.scale, SEED, 177 + limbs)
+    ct = bm.bm_encrypt_coeffs(ctx, pk, m, limbs, P.scale, SEED, 177 + limbs)
+    got, scale = bm.bm_ct_export(ctx, ct, P.N)
+    assert scale == want.scale
+    assert_words_equal(got, ct_words(want), "encrypt")
+    dec = bm.bm_decrypt_slots(ctx, sk, ct, P.n)
+    assert dec.shape == (P.N,)
+    assert np.max(np.abs(dec - z)) < 1e-6
+    bm.bm_ct_free(ct)
+
+
+@pytest.mark.parametrize("preset,limbs", [(3, 3), (3, 2), (4, 8), (4, 4)])
+def test_ci_ops_bit_exact(bm, preset, limbs):
+    P, okeys, ctx, sk, pk, evk = setup(preset)
+    rng = np.random.default_rng(200 + limbs)
+    log("ci ops preset %d limbs %d" % (preset, limbs))
+    a_w, b_w = random_ct(P, rng, limbs), random_ct(P, rng, limbs)
+    oa, ob = ckks.Ciphertext(list(a_w), limbs, P.scale), ckks.Ciphertext(list(b_w), limbs, P.scale)
+    la, lb = bm.bm_ct_import(ctx, a_w, P.scale), bm.bm_ct_import(ctx, b_w, P.scale)
+    handles = [la, lb]
+
+    def check(h, want, what):
+        got, scale = bm.bm_ct_export(ctx, h, P.N)
+        assert scale == want.scale, what
+        assert_words_equal(got, ct_words(want), what)
+        handles.append(h)
+
+    t_o = ckks.tensor(P, oa, ob)
+    t_l = bm.bm_op_tensor(ctx, la, lb)
+    check(t_l, t_o, "tensor")
+    check(bm.bm_op_relin(ctx, evk, t_l), ckks.relinearize(P, t_o, okeys.rlk), "relin")
+    check(bm.bm_op_rescale(ctx, la), ckks.rescale(P, oa), "rescale")
+    for r in (1, 4, -8 if preset == 3 else -64):
+        check(bm.bm_op_rotate(ctx, evk, la, r), ckks.rotate(P, oa, r, okeys.gks), "rotate %d" % r)
+    pt = ckks.encode(rng.uniform(-1, 1, P.n), 2.0 ** 20, P.N, P.ring)
+    check(bm.bm_op_pmul(ctx, la, pt, 2.0 ** 20), ckks.pmul(P, oa, pt, 2.0 ** 20), "pmul")
+    for h in handles:
+        bm.bm_ct_free(h)
+
+
+def normalize_rows(X):
+    return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+
+
+def oracle_gallery_words(P, okeys, X, d, k, seed_base):
+    lg = obm.gallery_limbs(P, k)
+    groups = obm.pack_gallery(P, X, d, k)
+    cts = [[ckks.encrypt(P, okeys.pk, ckks.encode(v, P.scale, P.N, P.ring), lg, P.scale, SEED,
+                         seed_base + g * k + i) for i, v in enumerate(parts)]
+           for g, parts in enumerate(groups)]
+    words = np.stack([np.stack([ct_words(c) for c in parts]) for parts in cts])
+    return cts, words, lg
+
+
+@pytest.mark.parametrize("d,k,schedule", [(16, 1, 1), (16, 4, 2), (8, 8, 0x102), (16, 4, 0x402),
+                                          (16, 1, 0x701), (16, 1, 0x201)])
+def test_ci_match_small_ring_bit_exact(bm, d, k, schedule):
+    """N = 2^12 (4,096 real slots): a two-group gallery with a ragged last
+    group; every output word equals the oracle's."""
+    P, okeys, ctx, sk, pk, evk = setup(3)
+    rng = np.random.default_rng(d * 7 + k + schedule)
+    c, T = obm.layout(P, d, k)
+    assert T == P.N // c
+    R = T + T // 2
+    X = normalize_rows(rng.standard_normal((R, d)))
+    qv = X[R // 3] + 0.03 * rng.standard_normal(d)
+    qv = qv / np.linalg.norm(qv)
+    log("ci match N=2^12 d=%d k=%d schedule %#x R=%d" % (d, k, schedule, R))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N, P.ring)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 39)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 6000)
+    level_min, comp, hoist = bool(schedule & 0x100), bool(schedule & 0x200), bool(schedule & 0x400)
+    ql = obm.level_min_shape(P, k, lg, comp)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
+    cmask = obm.compress_mask_coeffs(P, d, k, obm.compressed_rot_limbs(P, k, lg, level_min=level_min)) \
+        if comp else None
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, level_min=level_min,
+                     compress_mask=cmask, hoist=hoist)
+    want = want if comp else [want[g] for g in sorted(want)]
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=0)
+    n_out, limbs, _ = bm.bm_result_info(res)
+    assert n_out == len(want)
+    for o in range(n_out):
+        got, sc = bm.bm_result_export(ctx, res, o, P.N)
+        assert sc == want[o].scale
+        assert_words_equal(got, ct_words(want[o]), "result %d" % o)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, R)
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == int(np.argmax(cos))
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    if lm:
+        bm.bm_masks_free(lm)
+
+
+def test_ci_match_library_encryption_end_to_end(bm):
+    """The library's own encoding and encryption in the conjugate-invariant
+    ring at N = 2^12: scores within 1e-4 of the cosine, the top-1 found."""
+    P, okeys, ctx, sk, pk, evk = setup(3)
+    rng = np.random.default_rng(11)
+    d, k = 16, 4
+    X = normalize_rows(rng.standard_normal((3000, d)))
+    qv = X[1234] + 0.01 * rng.standard_normal(d).astype(np.float32)
+    qv = (qv / np.linalg.norm(qv)).astype(np.float32)     # the scores are inner products
+    cq = bm.bm_encrypt_query(ctx, pk, qv, SEED, 1)
+    gal = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 1000)
+    assert bm.bm_gallery_info(gal)[0] == -(-3000 // (P.N // (d // k)))
+    masks = bm.bm_masks_create(ctx, d, k)
+    res = bm.bm_match(ctx, evk, cq, gal, masks, schedule=2)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, X.shape[0])
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == 1234
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    bm.bm_masks_free(masks)
+
+
+@pytest.mark.parametrize("schedule", [0x102, 0x502])
+def test_ci_match_face_scale_sampled(bm, schedule):
+    """N = 2^16 conjugate-invariant ring, 6,144 x 128-dim, k = 4: 2,048
+    templates per group (twice the standard ring's), so three groups; the
+    oracle recomputes the first and last word for word."""
+    P, okeys, ctx, sk, pk, evk = setup(4)
+    d, k = 128, 4
+    w = face_gallery(seed=2)
+    X, qv = w["gallery"], w["query_known"]
+    c, T = obm.layout(P, d, k)
+    assert T == 2048
+    log("ci match N=2^16 k=4 schedule %#x: oracle gallery encryption" % schedule)
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N, P.ring)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 5000)
+    G = len(gal_o)
+    assert G == 3
+    level_min = bool(schedule & 0x100)
+    ql = obm.level_min_shape(P, k, lg)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql)
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, X.shape[0])
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
+    log("library match")
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
+    log("oracle match on sampled groups")
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
+                     groups=[0, G - 1], level_min=level_min, hoist=bool(schedule & 0x400))
+    for g, o in want.items():
+        got, sc = bm.bm_result_export(ctx, res, g, P.N)
+        assert sc == o.scale
+        assert_words_equal(got, ct_words(o), "group %d" % g)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, X.shape[0])
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == w["known"]
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    bm.bm_masks_free(lm)

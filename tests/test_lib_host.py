@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(bm):
 
 def test_presets_follow_the_prime_rule_and_match_the_oracle(bm):
     from oracle import ckks
-    for preset in (1, 2):
+    for preset in (1, 2, 3, 4):
         p = bm.bm_params_preset(preset)
         o = ckks.Params.preset(preset)
         assert p.log_n == o.log_n
@@ -51,8 +51,10 @@ def test_presets_follow_the_prime_rule_and_match_the_oracle(bm):
         assert p.special() == o.p
         assert p.alpha == o.alpha
         assert p.scale == o.scale
+        assert p.ring == (bm.BM_RING_CI if o.ring == "ci" else bm.BM_RING_STD)
+        assert p.slots == o.n
     with pytest.raises(bm.BMError):
-        bm.bm_params_preset(3)
+        bm.bm_params_preset(5)
 
 
 @pytest.mark.parametrize("d,k", [(128, 1), (128, 4), (16, 16), (512, 8)])
