@@ -252,7 +252,12 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   int last, int B, int vz) {
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
-  constexpr int VS = M + M / 16 + 1;          // padded view length in LDS (odd: spreads banks)
+  // padded view length in LDS.  Column passes put 16 views side by side in a
+  // wave (odd stride: the views land on distinct banks); row passes put 4
+  // views of 16 lanes each, whose padded offsets 17 u (mod 32 doubles) fill
+  // half of the banks, so a stride of 16 (mod 32) gives the next view the
+  // other half.
+  constexpr int VS = KIND == NTT_ROW ? M + M / 16 : M + M / 16 + 1;
   constexpr int PH = LOGM / 4;                // radix-16 phases
   extern __shared__ u64 sh_raw[];
   double* sh = reinterpret_cast<double*>(sh_raw);
@@ -262,7 +267,9 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   // so that small batches still fill whole waves; every row stages its own
   // twiddles (w, w/q) after the views in LDS.  Other passes: R = 1.
   const int R = KIND == NTT_ROW ? V / vz : 1;
-  double* tl = sh + V * VS;                   // [R][2 * 256] block twiddles (8-stage passes)
+  // [R][2][256] block twiddles (8-stage passes): w, then w/q, each in the
+  // order tw_slot() gives, in which the lanes of a view read consecutive words
+  double* tl = sh + V * VS;
   const int nthr = (int)blockDim.x;
   const int pid = m.prime[blockIdx.y];
   const PrimeC& pr = P[pid];
@@ -322,16 +329,22 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
   }
-  // ---- stage the block's twiddles (8-stage passes): tl[r][2^s + i] for stage s, block i of row r
+  // ---- stage the block's twiddles (8-stage passes).  Stage st (0..7) of the
+  // pass uses 2^st twiddles b; in stages 4..7 lane hi of a view reads
+  // b = (hi << k) + jj (k = st - 4, jj < 2^k), so they are kept at
+  // 2^st + jj * 16 + hi: consecutive lanes, consecutive words.
   if (LOGM == 8) {
+    // consecutive threads fill consecutive slots (conflict-free LDS writes)
     for (int k = t; k < 256 * R; k += nthr) {
-      const int kk = k & 255, rr = k >> 8;
-      if (kk == 0) continue;
+      const int slot = k & 255, rr = k >> 8;
+      if (slot == 0) continue;
       const int vb = KIND == NTT_ROW ? (int)blockIdx.x * R + rr : 0;
-      const int st = 31 - __clz(kk);
-      const int g = (1 << (s0 + st)) + (vb << st) + (kk - (1 << st));
-      tl[rr * 512 + 2 * kk] = W[g];
-      tl[rr * 512 + 2 * kk + 1] = WQ[g];
+      const int st = 31 - __clz(slot);
+      const int o = slot - (1 << st);
+      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+      const int g = (1 << (s0 + st)) + (vb << st) + b;
+      tl[rr * 512 + slot] = W[g];
+      tl[rr * 512 + 256 + slot] = WQ[g];
     }
   }
   if (DIRECT_IN) {
@@ -351,9 +364,17 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   }
 
   const double* tlv = tl + (KIND == NTT_ROW ? (v / vz) * 512 : 0);   // this view's row twiddles
-  auto twid = [&](int kk, double& w, double& wq) {
-    if (LOGM == 8) { w = tlv[2 * kk]; wq = tlv[2 * kk + 1]; }
-    else { w = W[kk]; wq = WQ[kk]; }
+  // twiddle of phase p, stage k of the phase, butterfly group hi, word j
+  auto twid = [&](int p, int k, int hi, int j, double& w, double& wq) {
+    if (LOGM == 8) {
+      const int slot = p == 0 ? (1 << k) + (j >> (4 - k)) : (1 << (4 + k)) + ((j >> (4 - k)) << 4) + hi;
+      w = tlv[slot];
+      wq = tlv[256 + slot];
+    } else {
+      const int kk = (1 << (4 * p + k)) + (hi << k) + (j >> (4 - k));
+      w = W[kk];
+      wq = WQ[kk];
+    }
   };
 
 #pragma unroll
@@ -376,7 +397,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         for (int j = 0; j < 16; ++j) {
           if (j & step) continue;
           double w, wq;
-          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, wq);
+          twid(p, k, hi, j, w, wq);
           const double T = fmul_mod(x[j + step], w, wq, q);
           const double U = x[j];
           x[j] = __dadd_rn(U, T);
@@ -395,7 +416,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         for (int j = 0; j < 16; ++j) {
           if (j & step) continue;
           double w, wq;
-          twid((1 << (4 * p + k)) + (hi << k) + (j >> (4 - k)), w, wq);
+          twid(p, k, hi, j, w, wq);
           const double U = x[j], Vv = x[j + step];
           x[j] = __dadd_rn(U, Vv);
           x[j + step] = fmul_mod(__dsub_rn(U, Vv), w, wq, q);
@@ -964,8 +985,8 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   // row passes: vz polynomials x R rows per block, R the largest power of two
   // with vz R <= 16 (whole waves for small batches) and at most 64 KiB of LDS
   const int vz = B < 16 ? B : 16;
-  const size_t view_words = 256 + 16 + 1;
-  auto row_lds = [&](int r) { return ((size_t)vz * r * view_words + (size_t)512 * r) * sizeof(u64); };
+  const size_t view_words = 256 + 16 + 1;   // column views; row views are one word shorter
+  auto row_lds = [&](int r) { return ((size_t)vz * r * (view_words - 1) + (size_t)512 * r) * sizeof(u64); };
   int R = 1;
   while (vz * R * 2 <= 16 && row_lds(2 * R) <= 65536) R *= 2;
   const int Vrow = vz * R;
