@@ -137,6 +137,34 @@ struct ModDownTable {
   u64 pinv[MAX_PRIMES][2];                // P^{-1} mod q_i
 };
 
+// Work folded into the two passes of a forward transform at N = 2^16 (see
+// kern::ntt_fused).  The column pass computes its input words on the fly from
+// coefficient-domain sources (prologue), the row pass finishes each output
+// word against a second operand before storing it (epilogue).
+// Batch element z of a source / minuend / output sits at
+//   base + (z / div) * hi + (z % div) * lo + limb * N.
+struct FuseArgs {
+  int pro = 0;   // 1: ModUp digit conversion (pair slots of the ModUpTable),
+                 // 2: ModDown conversion of the special limbs, 3: reduction of one limb
+  int epi = 0;   // 1: out = (minuend - x) w (+ addend) with w = wtab[2 slot]
+  const ModUpTable* mu = nullptr;
+  const ModDownTable* md = nullptr;
+  const u64* src = nullptr;
+  size_t s_hi = 0, s_lo = 0;
+  int s_div = 1;
+  int s_off0 = 0;                // ModDown: limb offset of the first special limb
+  const u64* mnd = nullptr;
+  size_t m_hi = 0, m_lo = 0;
+  const u64* add0 = nullptr;     // addend of elements with z % div == 0
+  size_t a0_hi = 0;
+  const u64* add1 = nullptr;     // and of the others
+  size_t a1_hi = 0;
+  u64* out = nullptr;
+  size_t o_hi = 0, o_lo = 0;
+  int e_div = 1;
+  const u64* wtab = nullptr;
+};
+
 // ----------------------------------------------------------------- device memory
 
 // Registry of live device allocations.  Every kernel launcher checks, before
@@ -329,6 +357,12 @@ LimbMap single(int prime, int off);
 // forward / inverse negacyclic NTT; in and out may alias
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
          const LimbMap& m, bool inverse);
+// whether ntt_fused serves this context (N = 2^16, standard ring)
+bool fused_ok(const Ctx& c);
+// forward NTT of the words f's prologue computes, into tmp at the slots m.ooff
+// (slot s of element z at tmp + z * ts + m.ooff[s] * N); with an epilogue the
+// finished words go to f.out instead and tmp only carries the first pass
+void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m);
 // signed integer polynomial [N] -> residues in limbs of m (coefficient domain)
 void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
                 size_t src_stride, const LimbMap& m);

@@ -265,7 +265,6 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true);
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
-  kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
   LimbMap m{};
   for (int i = 0; i < tb.npairs; ++i) {
     const int t = tb.pair_t[i];
@@ -273,7 +272,18 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
     m.off[m.n] = m.ooff[m.n] = tb.pair_j[i] * ext + t;
     ++m.n;
   }
-  kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
+  if (kern::fused_ok(c)) {           // conversion computed inside the forward transform
+    FuseArgs f;
+    f.pro = 1;
+    f.mu = c.d_modup + limbs;
+    f.src = xc.p();
+    f.s_hi = (size_t)limbs * N;
+    audit::check(xc.p(), (size_t)B * limbs * N * sizeof(u64), "fused modup source");
+    kern::ntt_fused(c, f, y.p(), sy, B, m);
+  } else {
+    kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
+    kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
+  }
   return y;
 }
 
@@ -294,6 +304,32 @@ static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size
   kern::ntt(c, uw, suw, uw, suw, B, mp, true);
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
+  if (kern::fused_ok(c)) {           // conversion and finish inside the forward transform
+    FuseArgs f;
+    f.pro = 2;
+    f.md = c.d_moddown;
+    f.src = uw;
+    f.s_div = f.e_div = 2;           // element 2 z + comp
+    f.s_hi = f.m_hi = suw;
+    f.s_lo = f.m_lo = (size_t)ext * N;
+    f.s_off0 = limbs;
+    f.epi = 1;
+    f.mnd = uw;
+    f.add0 = add0;
+    f.a0_hi = sa0;
+    f.add1 = add1;
+    f.a1_hi = sa1;
+    f.out = out;
+    f.o_hi = so;
+    f.o_lo = (size_t)limbs * N;
+    f.wtab = &c.d_moddown->pinv[0][0];
+    audit::check(uw, (size_t)B * suw * sizeof(u64), "fused moddown source");
+    if (add0) audit::check(add0, ((size_t)(B - 1) * sa0 + (size_t)limbs * N) * sizeof(u64), "moddown addend 0");
+    if (add1) audit::check(add1, ((size_t)(B - 1) * sa1 + (size_t)limbs * N) * sizeof(u64), "moddown addend 1");
+    audit::check(out, ((size_t)(B - 1) * so + 2 * (size_t)limbs * N) * sizeof(u64), "moddown output");
+    kern::ntt_fused(c, f, conv.p(), (size_t)limbs * N, 2 * B, kern::chain_map(limbs));
+    return;
+  }
   kern::moddown_conv(c, uw, suw, conv.p(), sc, B, limbs);
   kern::ntt(c, conv.p(), (size_t)limbs * N, conv.p(), (size_t)limbs * N, 2 * B, kern::chain_map(limbs), false);
   kern::moddown_finish(c, uw, suw, conv.p(), sc, add0, sa0, add1, sa1, out, so, B, limbs);
@@ -339,6 +375,23 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
   m.ooff[0] = 0;
   kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true);
   DBuf t(&c, (size_t)B * comps * nl * N);
+  if (kern::fused_ok(c)) {           // reduction and finish inside the forward transform
+    if (in == out) BM_THROW(BM_EINVAL, "rescale cannot work in place");
+    FuseArgs f;
+    f.pro = 3;
+    f.src = last.p();
+    f.s_hi = N;
+    f.epi = 1;
+    f.mnd = in;
+    f.m_hi = (size_t)limbs * N;
+    f.out = out;
+    f.o_hi = (size_t)nl * N;
+    f.wtab = c.d_rescale + (size_t)(limbs - 1) * (c.L + 1) * 2;
+    audit::check(in, (size_t)B * comps * limbs * N * sizeof(u64), "rescale input");
+    audit::check(out, (size_t)B * comps * nl * N * sizeof(u64), "rescale output");
+    kern::ntt_fused(c, f, t.p(), (size_t)nl * N, B * comps, kern::chain_map(nl));
+    return;
+  }
   kern::rescale_conv(c, last.p(), (size_t)comps * N, N, t.p(), (size_t)comps * nl * N, B, comps, limbs);
   kern::ntt(c, t.p(), (size_t)nl * N, t.p(), (size_t)nl * N, B * comps, kern::chain_map(nl), false);
   kern::rescale_finish(c, in, (size_t)comps * limbs * N, t.p(), (size_t)comps * nl * N, out,

@@ -243,13 +243,17 @@ struct FAcc {
 
 enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 
-template <int LOGM, bool INV, int KIND>
+// FUSE = 1: forward column pass whose input words come from f's prologue;
+// FUSE = 2: forward row pass that stores through f's epilogue.
+template <int LOGM, bool INV, int KIND, int FUSE = 0>
 __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
                                                   LimbMap m, const PrimeC* __restrict__ P,
                                                   const double* __restrict__ twf,
                                                   const double* __restrict__ twq, int log_n, int s0,
-                                                  int last, int B, int vz) {
+                                                  int last, int B, int vz, FuseArgs f) {
+  static_assert(FUSE == 0 || (!INV && ((FUSE == 1 && KIND == NTT_COL) || (FUSE == 2 && KIND == NTT_ROW))),
+                "fused prologues serve forward column passes, epilogues forward row passes");
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
   // padded view length in LDS.  Column passes put 16 views side by side in a
@@ -325,9 +329,58 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 
   // data loads first, so that their latency overlaps the twiddle staging
   u64 raw[16] = {};
-  if (valid) {
+  if (FUSE != 1 && valid) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
+  }
+  if constexpr (FUSE == 1) {
+    // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
+    // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
+    // the bracket the exact residue in [0, m_a)); one limb: X mod q.
+    const int slot = blockIdx.y;
+    const size_t zz = blockIdx.z;
+    const u64* S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo + (size_t)blockIdx.x * 16 + v;
+    if (f.pro == 3) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(S[(size_t)addr(0, j) * astride]), qi, q);
+    } else {
+      const int jd = f.pro == 1 ? f.mu->pair_j[slot] : 0, tt = f.pro == 1 ? f.mu->pair_t[slot] : 0;
+      const int ns = f.pro == 1 ? f.mu->d[jd].nsrc : f.md->K;
+      for (int a = 0; a < ns; ++a) {
+        int soff, spid;
+        u64 c1, c2;
+        if (f.pro == 1) {
+          const ModUpDigit& dg = f.mu->d[jd];
+          soff = spid = dg.src[a];
+          c1 = dg.qhatinv[a][0];
+          c2 = dg.qhat[a][tt][0];
+        } else {
+          soff = f.s_off0 + a;
+          spid = f.md->pprime[a];
+          c1 = f.md->phatinv[a][0];
+          c2 = f.md->phat[a][slot][0];
+        }
+        const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
+        const u64* Sa = S + (size_t)soff * N;
+        u64 r[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) r[j] = Sa[(size_t)addr(0, j) * astride];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
+          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+          const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
+          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+        }
+        if (a & 1) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+    }
   }
   // ---- stage the block's twiddles (8-stage passes).  Stage st (0..7) of the
   // pass uses 2^st twiddles b; in stages 4..7 lane hi of a view reads
@@ -347,7 +400,8 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       tl[rr * 512 + 256 + slot] = WQ[g];
     }
   }
-  if (DIRECT_IN) {
+  if (FUSE == 1) {
+  } else if (DIRECT_IN) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) x[j] = u64_to_f(raw[j]);
   } else {
@@ -455,10 +509,33 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     for (int j = 0; j < 16; ++j) sh_raw[v * VS + pad(addr(P_LAST, j))] = y[j];
     __syncthreads();
     if (valid) {
+      if constexpr (FUSE == 2) {
+        // out = (minuend - x) w (+ addend), all words exact residues
+        const int slot = blockIdx.y;
+        const size_t zz = blockIdx.z * vz + v % vz;
+        const size_t hi = zz / f.e_div, lo = zz % f.e_div;
+        const size_t pos = ((size_t)blockIdx.x * R + v / vz) * M + (size_t)slot * N;
+        const u64* Mn = f.mnd + hi * f.m_hi + lo * f.m_lo + pos;
+        const u64* Ad = lo == 0 ? (f.add0 ? f.add0 + hi * f.a0_hi + pos : nullptr)
+                                : (f.add1 ? f.add1 + hi * f.a1_hi + pos : nullptr);
+        u64* O = f.out + hi * f.o_hi + lo * f.o_lo + pos;
+        const double wd = (double)f.wtab[2 * slot], wq = wd / q;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int a = addr(0, j);
-        dst[a] = sh_raw[v * VS + pad(a)];
+        for (int j = 0; j < 16; ++j) {
+          const int a = addr(0, j);
+          const double d = __dsub_rn(u64_to_f(Mn[a]), u64_to_f(sh_raw[v * VS + pad(a)]));   // |d| < q
+          double r = fmul_mod(d, wd, wq, q);                                                 // |r| <= q
+          if (Ad) r = __dadd_rn(r, u64_to_f(Ad[a]));
+          r = fred(r, qi, q);
+          r = r < 0.0 ? __dadd_rn(r, q) : r;
+          O[a] = f_to_u64(r);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int a = addr(0, j);
+          dst[a] = sh_raw[v * VS + pad(a)];
+        }
       }
     }
   }
@@ -975,10 +1052,10 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     const dim3 grid(1, (unsigned)m.n, (unsigned)B);
     if (inverse)
       LAUNCH((k_ntt_fast<12, true, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
-             out_stride, m, c.d_primes, tw, tws, logn, 0, 1, B, 1);
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 1, B, 1, FuseArgs{});
     else
       LAUNCH((k_ntt_fast<12, false, NTT_ONE>), grid, dim3(256), lds, c.stream, in, in_stride, out,
-             out_stride, m, c.d_primes, tw, tws, logn, 0, 0, B, 1);
+             out_stride, m, c.d_primes, tw, tws, logn, 0, 0, B, 1, FuseArgs{});
     check_launch();
     return;
   }
@@ -1000,10 +1077,10 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     Prof pf(c, inverse ? "ntt_inv_col" : "ntt_fwd_col", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
-             c.d_primes, tw, tws, logn, 0, last, B, 1);
+             c.d_primes, tw, tws, logn, 0, last, B, 1, FuseArgs{});
     else
       LAUNCH((k_ntt_fast<8, false, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
-             c.d_primes, tw, tws, logn, 0, last, B, 1);
+             c.d_primes, tw, tws, logn, 0, last, B, 1, FuseArgs{});
     check_launch();
   };
   auto row = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm) {
@@ -1012,10 +1089,10 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     Prof pf(c, inverse ? "ntt_inv_row" : "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vrow), lds_row, c.stream, src, ss, dst, ds,
-             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz);
+             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz, FuseArgs{});
     else
       LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vrow), lds_row, c.stream, src, ss, dst, ds,
-             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz);
+             mm, c.d_primes, tw, tws, logn, 8, 0, B, vz, FuseArgs{});
     check_launch();
   };
   if (!inverse) {
@@ -1025,6 +1102,48 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     row(in, in_stride, out, out_stride, m);
     col(out, out_stride, out, out_stride, m_out, 1);
   }
+}
+
+bool fused_ok(const Ctx& c) { return c.log_n == 16 && !c.ci; }
+
+void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m) {
+  if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
+  if (B <= 0 || m.n <= 0) return;
+  if (f.pro < 1 || f.pro > 3 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
+      (f.pro == 2 && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)))
+    BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
+  const int logn = 16, N = 1 << logn;
+  LimbMap mo = m;
+  for (int i = 0; i < m.n; ++i) mo.off[i] = mo.ooff[i];
+  chk_map(c, tmp, B, ts, mo, "fused ntt scratch", true);
+  const double elems = (double)N * m.n * B;
+  // launch geometry of ntt_fast's forward passes
+  const int vz = B < 16 ? B : 16;
+  const size_t view_words = 256 + 16 + 1;
+  auto row_lds = [&](int r) { return ((size_t)vz * r * (view_words - 1) + (size_t)512 * r) * sizeof(u64); };
+  int R = 1;
+  while (vz * R * 2 <= 16 && row_lds(2 * R) <= 65536) R *= 2;
+  const int Vrow = vz * R;
+  const size_t lds_col = ((size_t)16 * view_words + 512) * sizeof(u64);
+  const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
+  const dim3 grow((unsigned)(N / 256 / R), (unsigned)m.n, (unsigned)((B + vz - 1) / vz));
+  {
+    const double srcs = f.pro == 1 ? 2.0 : f.pro == 2 ? (double)c.K : 1.0;
+    Prof pf(c, "ntt_fwd_col_fused", 8.0 * elems * (1.0 + srcs), 0.5 * elems * 8 + 2.0 * srcs * elems);
+    LAUNCH((k_ntt_fast<8, false, NTT_COL, 1>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
+           (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
+    check_launch();
+  }
+  if (f.epi) {
+    Prof pf(c, "ntt_fwd_row_fused", 8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
+    LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
+           (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
+  } else {
+    Prof pf(c, "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
+    LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts, tmp,
+           ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, FuseArgs{});
+  }
+  check_launch();
 }
 
 // Conjugate-invariant ring: reduction modulo X^N - iota before the forward
