@@ -357,6 +357,9 @@ LimbMap single(int prime, int off);
 // forward / inverse negacyclic NTT; in and out may alias
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
          const LimbMap& m, bool inverse);
+// in place: residue words (< 2^52) <-> the bit patterns of the same values as
+// FP64 numbers (the form switching keys are kept in)
+void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);
 // whether ntt_fused serves this context (N = 2^16, standard ring)
 bool fused_ok(const Ctx& c);
 // forward NTT of the words f's prologue computes, into tmp at the slots m.ooff

@@ -375,6 +375,7 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
     DBuf tmp(&c, ln);
     HIP_OK(dev::memcpy_async(tmp.p(), key + (size_t)(2 * digit + comp) * ln, ln * sizeof(u64),
                           hipMemcpyDeviceToDevice, c.stream));
+    kern::words_f64(c, tmp.p(), ln, false);   // keys are held as FP64 values
     const LimbMap all = kern::ext_map(c, c.L + 1);
     kern::ntt(c, tmp.p(), 0, tmp.p(), 0, 1, all, true);
     HIP_OK(dev::memcpy_async(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));

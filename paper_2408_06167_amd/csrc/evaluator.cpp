@@ -620,6 +620,8 @@ void keygen_switch(Ctx& c, u64 seed, u32 dom_a, u32 dom_e, u64 index_base, const
     kern::axpy_scalar(c, s_prime, 0, scal.p(), bj, 0, 1, dm);
     HIP_OK(dev::stream_sync(c.stream));
   }
+  // the key inner products read key words as FP64 values
+  kern::words_f64(c, key.p(), (size_t)c.dnum * 2 * np * N, true);
   HIP_OK(dev::stream_sync(c.stream));
 }
 

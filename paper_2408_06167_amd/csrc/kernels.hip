@@ -224,8 +224,7 @@ __device__ __forceinline__ u64 f_to_u64(double x) {
 struct FAcc {
   double s = 0.0;
   int n = 0;
-  __device__ __forceinline__ void add(double v, u64 w_word, double qi, double q) {
-    const double w = u64_to_f(w_word);
+  __device__ __forceinline__ void add(double v, double w, double qi, double q) {
     s = __dadd_rn(s, fmul_mod(v, w, __dmul_rn(w, qi), q));
     if (++n == 2) { s = fred(s, qi, q); n = 0; }
   }
@@ -760,7 +759,8 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   const u64 q = pr.q;
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const size_t bz = blockIdx.z;
-  const u64* key = ((blockIdx.z >> sel) & 1) ? key1 : key0;   // per-element key choice
+  // per-element key choice; key words are FP64 values
+  const double* key = (const double*)(((blockIdx.z >> sel) & 1) ? key1 : key0);
   u64* U = uw + bz * suw + (size_t)t * N;
   u64* Wp = U + (size_t)ext * N;
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
@@ -794,6 +794,7 @@ constexpr int HOIST_BETA = 4;   // digits a thread handles (dnum <= 4 at every l
 // stay in that XCD's L2.
 __device__ __forceinline__ int xcd_block(int w, int W) { return (w & 7) * (W >> 3) + (w >> 3); }
 
+template <int BETA>
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
                             const PrimeC* P, int log_n, int ms, int B, int accumulate) {
@@ -818,26 +819,64 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   const u64 q = pr.q;
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
-  FAcc su, sw;
-#pragma unroll 4
-  for (int a = 0; a < h.A; ++a) {
-    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-    const u32 src = autom_src((u32)i, g, log_n, ms);
-    // the key pointer comes from memory: tell the compiler it is a global one
-    const __attribute__((address_space(1))) u64* key = (const __attribute__((address_space(1))) u64*)kp[a];
+  // row of digit j at slot t: the input limb itself for the digit's own slots
+  const u64* src[BETA];
 #pragma unroll
-    for (int j = 0; j < HOIST_BETA; ++j) {
-      if (j >= tb.beta) break;
-      const ModUpDigit& dg = tb.d[j];
-      const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-      const double v = u64_to_f(own ? x[(size_t)z * sx + (size_t)t * N + src]
-                                    : y[(size_t)z * sy + ((size_t)j * ext + t) * N + src]);
-      su.add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
-      sw.add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
+  for (int j = 0; j < BETA; ++j) {
+    const ModUpDigit& dg = tb.d[j];
+    const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+    src[j] = own ? x + (size_t)z * sx + (size_t)t * N : y + (size_t)z * sy + ((size_t)j * ext + t) * N;
+  }
+  const size_t ko = (size_t)kl * N + i, kst = (size_t)key_limbs * N;
+  typedef const __attribute__((address_space(1))) double* gdp;   // the key pointers are global ones
+  // words of one amount: digits (gathered), key b and key a words of every digit
+  struct Words {
+    u64 v[BETA];
+    double kb[BETA], ka[BETA];
+  };
+  auto load = [&](int a, Words& w) {
+    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    const u32 s = autom_src((u32)i, g, log_n, ms);
+    const gdp key = (gdp)kp[a];
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) {
+      w.v[j] = src[j][s];
+      w.kb[j] = key[ko + (size_t)(2 * j) * kst];
+      w.ka[j] = key[ko + (size_t)(2 * j + 1) * kst];
     }
+  };
+  // exact sums in FP64: every product lies within 1.25 q of 0, and the sums are
+  // folded back to |s| <= q/2 + 1 after every second product (so |s| < 3q + 1)
+  double su = 0.0, sw = 0.0;
+  auto mac = [&](const Words& w) {
+#pragma unroll
+    for (int j = 0; j < BETA; ++j) {
+      const double v = u64_to_f(w.v[j]);
+      su = __dadd_rn(su, fmul_mod(v, w.kb[j], __dmul_rn(w.kb[j], qi), qd));
+      sw = __dadd_rn(sw, fmul_mod(v, w.ka[j], __dmul_rn(w.ka[j], qi), qd));
+      if ((j & 1) || j == BETA - 1) {
+        su = fred(su, qi, qd);
+        sw = fred(sw, qi, qd);
+      }
+    }
+  };
+  // two buffers: the words of amount a + 1 are in flight while a is multiplied
+  Words w0, w1;
+  load(0, w0);
+  for (int a = 0; a < h.A; a += 2) {
+    if (a + 1 < h.A) load(a + 1, w1);
+    mac(w0);
+    if (a + 1 >= h.A) break;
+    if (a + 2 < h.A) load(a + 2, w0);
+    mac(w1);
   }
   u64* U = uw + (size_t)z * suw + (size_t)t * N;
-  const u64 ru = su.residue(qi, qd), rw = sw.residue(qi, qd);
+  auto res = [&](double s_) {
+    double r = fred(s_, qi, qd);
+    r = r < 0.0 ? __dadd_rn(r, qd) : r;
+    return f_to_u64(r);
+  };
+  const u64 ru = res(su), rw = res(sw);
   U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
   U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
 }
@@ -947,6 +986,14 @@ __global__ void k_copy_limbs(const u64* in, size_t si, size_t ics, u64* out, int
   const u64* I = in + bz * si + c * ics + (size_t)l * N;
   u64* O = out + (bz / div) * so_hi + (bz % div) * so_lo + c * ocs + (size_t)l * N;
   for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) O[e] = I[e];
+}
+
+// in place: residue word <-> bit pattern of its FP64 value (exact below 2^53)
+__global__ void k_words_f64(u64* p, size_t n, int to_f64) {
+  for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
+    const u64 w = p[e];
+    p[e] = to_f64 ? (u64)__double_as_longlong(u64_to_f(w)) : f_to_u64(__longlong_as_double((long long)w));
+  }
 }
 
 __global__ void k_zero(u64* out, size_t words) {
@@ -1105,6 +1152,15 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
 }
 
 bool fused_ok(const Ctx& c) { return c.log_n == 16 && !c.ci; }
+
+void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
+  if (n == 0) return;
+  chk(p, 1, 0, 0, n, "words_f64");
+  Prof pf(c, "words_f64", 16.0 * n, 0.0);
+  const size_t bx = std::min<size_t>((n + TPB - 1) / TPB, 65536);
+  LAUNCH(k_words_f64, dim3((unsigned)bx), dim3(TPB), 0, c.stream, p, n, to_f64 ? 1 : 0);
+  check_launch();
+}
 
 void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m) {
   if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
@@ -1373,13 +1429,20 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
   Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
-  if (tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: too many digits for the hoisted kip");
+  if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the hoisted kip");
   const size_t gx = (c.N + TPB - 1) / TPB;
   const size_t W = gx * tb.ext * B;
   if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
-  LAUNCH(k_kip_hoist, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw,
-         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,
-         accumulate ? 1 : 0);
+#define KIP_HOIST(BETA)                                                                                      \
+  LAUNCH(k_kip_hoist<BETA>, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw, \
+         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B, accumulate ? 1 : 0)
+  switch (tb.beta) {
+    case 1: KIP_HOIST(1); break;
+    case 2: KIP_HOIST(2); break;
+    case 3: KIP_HOIST(3); break;
+    default: KIP_HOIST(4); break;
+  }
+#undef KIP_HOIST
   check_launch();
 }
 
