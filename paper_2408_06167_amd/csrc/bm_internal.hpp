@@ -363,9 +363,11 @@ void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);
 // whether ntt_fused serves this context (N = 2^16, standard ring)
 bool fused_ok(const Ctx& c);
 // forward NTT of the words f's prologue computes, into tmp at the slots m.ooff
-// (slot s of element z at tmp + z * ts + m.ooff[s] * N); with an epilogue the
-// finished words go to f.out instead and tmp only carries the first pass
-void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m);
+// (slot s of element z at tmp + z * ts + m.ooff[s] * N), as FP64 values when
+// f64_out; with an epilogue the finished words go to f.out instead and tmp
+// only carries the first pass
+void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m,
+               bool f64_out = false);
 // signed integer polynomial [N] -> residues in limbs of m (coefficient domain)
 void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
                 size_t src_stride, const LimbMap& m);

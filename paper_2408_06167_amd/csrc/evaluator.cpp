@@ -256,7 +256,8 @@ void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* ke
 }
 
 // ModUp of every digit of x (evaluation domain) to the extended basis, back
-// in evaluation form: y [B][beta][ext][N] (the digit's own slots unused).
+// in evaluation form: y [B][beta][ext][N] (the digit's own slots unused), the
+// residues held as FP64 values for the key inner products.
 static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const size_t N = c.N;
   const ModUpTable& tb = c.h_modup[limbs];
@@ -279,10 +280,11 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
     f.src = xc.p();
     f.s_hi = (size_t)limbs * N;
     audit::check(xc.p(), (size_t)B * limbs * N * sizeof(u64), "fused modup source");
-    kern::ntt_fused(c, f, y.p(), sy, B, m);
+    kern::ntt_fused(c, f, y.p(), sy, B, m, true);
   } else {
     kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
     kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
+    kern::words_f64(c, y.p(), (size_t)B * sy, true);
   }
   return y;
 }

@@ -203,6 +203,16 @@ __device__ __forceinline__ double fmul_mod(double a, double w, double wq, double
   return __dadd_rn(__fma_rn(-qt, q, hi), lo);
 }
 
+// a w mod q for |a|, w < q < 2^51, quotient from fl(fl(a w) fl(1/q)): it is
+// within 0.5 + 3 (a w / q) 2^-53 < 1.25 of a w / q, so |r| <= 1.25 q, and both
+// the FMA (an integer below 2^53) and the final add are exact.
+__device__ __forceinline__ double fmul_mod_q(double a, double w, double qi, double q) {
+  const double hi = __dmul_rn(a, w);
+  const double lo = __fma_rn(a, w, -hi);
+  const double qt = rint(__dmul_rn(hi, qi));
+  return __dadd_rn(__fma_rn(-qt, q, hi), lo);
+}
+
 __device__ __forceinline__ double fred(double a, double qi, double q) {
   return __fma_rn(-rint(__dmul_rn(a, qi)), q, a);
 }
@@ -218,14 +228,14 @@ __device__ __forceinline__ u64 f_to_u64(double x) {
 }
 
 // Sum of exact products v * w mod q (v, w residues in [0, q)) carried in FP64:
-// each product lies within 1.25 q of 0 (w/q rounded twice), the running sum
-// is folded back to |s| <= q/2 + 1 after every second term, so it stays
-// below 3q < 2^53; residue() returns the exact sum in [0, q).
+// each product lies within 1.25 q of 0 (fmul_mod_q), the running sum is
+// folded back to |s| <= q/2 + 1 after every second term, so it stays below
+// 3q < 2^53; residue() returns the exact sum in [0, q).
 struct FAcc {
   double s = 0.0;
   int n = 0;
   __device__ __forceinline__ void add(double v, double w, double qi, double q) {
-    s = __dadd_rn(s, fmul_mod(v, w, __dmul_rn(w, qi), q));
+    s = __dadd_rn(s, fmul_mod_q(v, w, qi, q));
     if (++n == 2) { s = fred(s, qi, q); n = 0; }
   }
   // add one product already reduced by fmul_mod
@@ -243,7 +253,8 @@ struct FAcc {
 enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 
 // FUSE = 1: forward column pass whose input words come from f's prologue;
-// FUSE = 2: forward row pass that stores through f's epilogue.
+// FUSE = 2: forward row pass that stores through f's epilogue;
+// FUSE = 3: forward row pass that stores the residues as FP64 values.
 template <int LOGM, bool INV, int KIND, int FUSE = 0>
 __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
@@ -251,7 +262,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   const double* __restrict__ twf,
                                                   const double* __restrict__ twq, int log_n, int s0,
                                                   int last, int B, int vz, FuseArgs f) {
-  static_assert(FUSE == 0 || (!INV && ((FUSE == 1 && KIND == NTT_COL) || (FUSE == 2 && KIND == NTT_ROW))),
+  static_assert(FUSE == 0 || (!INV && ((FUSE == 1 && KIND == NTT_COL) || (FUSE >= 2 && KIND == NTT_ROW))),
                 "fused prologues serve forward column passes, epilogues forward row passes");
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
@@ -495,7 +506,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   for (int j = 0; j < 16; ++j) {
     double r = fred(x[j], qi, q);
     r = r < 0.0 ? __dadd_rn(r, q) : r;
-    y[j] = f_to_u64(r);
+    y[j] = FUSE == 3 ? (u64)__double_as_longlong(r) : f_to_u64(r);
   }
   if (DIRECT_OUT) {
     if (valid) {
@@ -769,7 +780,9 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
     for (int j = 0; j < tb.beta; ++j) {
       const ModUpDigit& dg = tb.d[j];
       const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-      const double v = u64_to_f(own ? x[bz * sx + (size_t)t * N + i] : y[bz * sy + ((size_t)j * ext + t) * N + i]);
+      // ModUp digits are FP64 values, the input limbs residue words
+      const double v = own ? u64_to_f(x[bz * sx + (size_t)t * N + i])
+                           : __longlong_as_double((long long)y[bz * sy + ((size_t)j * ext + t) * N + i]);
       su.add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
       sw.add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
     }
@@ -820,12 +833,14 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
   // row of digit j at slot t: the input limb itself for the digit's own slots
+  // (ModUp digits are FP64 values, the input limbs residue words)
   const u64* src[BETA];
+  bool own[BETA];
 #pragma unroll
   for (int j = 0; j < BETA; ++j) {
     const ModUpDigit& dg = tb.d[j];
-    const bool own = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
-    src[j] = own ? x + (size_t)z * sx + (size_t)t * N : y + (size_t)z * sy + ((size_t)j * ext + t) * N;
+    own[j] = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+    src[j] = own[j] ? x + (size_t)z * sx + (size_t)t * N : y + (size_t)z * sy + ((size_t)j * ext + t) * N;
   }
   const size_t ko = (size_t)kl * N + i, kst = (size_t)key_limbs * N;
   typedef const __attribute__((address_space(1))) double* gdp;   // the key pointers are global ones
@@ -845,30 +860,37 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
       w.ka[j] = key[ko + (size_t)(2 * j + 1) * kst];
     }
   };
-  // exact sums in FP64: every product lies within 1.25 q of 0, and the sums are
-  // folded back to |s| <= q/2 + 1 after every second product (so |s| < 3q + 1)
+  // exact sums in FP64: every product lies within 1.25 q of 0 (fmul_mod_q), and
+  // the sums are folded back to |s| <= q/2 + 1 after every second product of
+  // the two-amount window (so |s| < 3q + 1)
   double su = 0.0, sw = 0.0;
-  auto mac = [&](const Words& w) {
+  auto mac = [&](const Words& w, int d) {
 #pragma unroll
     for (int j = 0; j < BETA; ++j) {
-      const double v = u64_to_f(w.v[j]);
-      su = __dadd_rn(su, fmul_mod(v, w.kb[j], __dmul_rn(w.kb[j], qi), qd));
-      sw = __dadd_rn(sw, fmul_mod(v, w.ka[j], __dmul_rn(w.ka[j], qi), qd));
-      if ((j & 1) || j == BETA - 1) {
+      const double v = own[j] ? u64_to_f(w.v[j]) : __longlong_as_double((long long)w.v[j]);
+      su = __dadd_rn(su, fmul_mod_q(v, w.kb[j], qi, qd));
+      sw = __dadd_rn(sw, fmul_mod_q(v, w.ka[j], qi, qd));
+      if ((d * BETA + j) & 1) {
         su = fred(su, qi, qd);
         sw = fred(sw, qi, qd);
       }
     }
   };
-  // two buffers: the words of amount a + 1 are in flight while a is multiplied
-  Words w0, w1;
-  load(0, w0);
-  for (int a = 0; a < h.A; a += 2) {
-    if (a + 1 < h.A) load(a + 1, w1);
-    mac(w0);
-    if (a + 1 >= h.A) break;
-    if (a + 2 < h.A) load(a + 2, w0);
-    mac(w1);
+  // D buffers: the words of the next D - 1 amounts are in flight while one is
+  // multiplied
+  constexpr int D = 2;
+  Words w[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (d < h.A) load(d, w[d]);
+  for (int a = 0; a < h.A; a += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (a + d < h.A) {
+        mac(w[d], d);
+        if (a + d + D < h.A) load(a + d + D, w[d]);
+      }
+    }
   }
   u64* U = uw + (size_t)z * suw + (size_t)t * N;
   auto res = [&](double s_) {
@@ -1162,7 +1184,7 @@ void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
   check_launch();
 }
 
-void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m) {
+void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m, bool f64_out) {
   if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
   if (B <= 0 || m.n <= 0) return;
   if (f.pro < 1 || f.pro > 3 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
@@ -1194,6 +1216,10 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
     Prof pf(c, "ntt_fwd_row_fused", 8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
            (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
+  } else if (f64_out) {
+    Prof pf(c, "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
+    LAUNCH((k_ntt_fast<8, false, NTT_ROW, 3>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
+           tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, FuseArgs{});
   } else {
     Prof pf(c, "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts, tmp,
