@@ -903,6 +903,109 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
 }
 
+// The same sums when every element uses the same amounts: one thread serves up
+// to ZB elements of one (limb, position), so each key word is loaded once and
+// used ZB times from registers, and takes the amounts CH at a time, all their
+// words requested before the first is used (memory latency, not arithmetic,
+// sets the pace of this kernel).
+template <int BETA, int ZB, int CH>
+__global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
+                               HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
+                               const PrimeC* P, int log_n, int ms, int B, int accumulate) {
+  const ModUpTable& tb = *T;
+  const int N = 1 << log_n;
+  const int ext = tb.ext;
+  // 1-D grid of (limb, position block, element group), element group fastest
+  const int gx = (N + TPB - 1) / TPB;
+  const int ZG = (B + ZB - 1) / ZB;
+  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int zg = lb % ZG;
+  const int pb = (lb / ZG) % gx;
+  const int t = lb / (ZG * gx);
+  const int i = pb * TPB + threadIdx.x;
+  __shared__ const u64* kp[HOIST_MAX];
+  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
+  __syncthreads();
+  if (i >= N || t >= ext) return;
+  const int z0 = zg * ZB, nz = min(ZB, B - z0);
+  const PrimeC& pr = P[tb.ext_prime[t]];
+  const u64 q = pr.q;
+  const int kl = t < tb.limbs ? t : L1 + (t - tb.limbs);
+  const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
+  // ModUp digits are FP64 values, the input limbs residue words
+  const u64* src[BETA];
+  size_t zst[BETA];
+  bool own[BETA];
+#pragma unroll
+  for (int j = 0; j < BETA; ++j) {
+    const ModUpDigit& dg = tb.d[j];
+    own[j] = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+    src[j] = own[j] ? x + (size_t)z0 * sx + (size_t)t * N : y + (size_t)z0 * sy + ((size_t)j * ext + t) * N;
+    zst[j] = own[j] ? sx : sy;
+  }
+  const size_t ko = (size_t)kl * N + i, kst = (size_t)key_limbs * N;
+  typedef const __attribute__((address_space(1))) double* gdp;
+  double su[ZB], sw[ZB];
+#pragma unroll
+  for (int zz = 0; zz < ZB; ++zz) su[zz] = sw[zz] = 0.0;
+  for (int a0 = 0; a0 < h.A; a0 += CH) {
+    double kb[CH][BETA], ka[CH][BETA];
+    u64 v[CH][BETA][ZB];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int a = a0 + c < h.A ? a0 + c : h.A - 1;   // a ragged chunk repeats the last amount, unused
+      const u32 s = autom_src((u32)i, h.g[a], log_n, ms);
+      const gdp key = (gdp)kp[a];
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+        kb[c][j] = key[ko + (size_t)(2 * j) * kst];
+        ka[c][j] = key[ko + (size_t)(2 * j + 1) * kst];
+#pragma unroll
+        for (int zz = 0; zz < ZB; ++zz) v[c][j][zz] = zz < nz ? src[j][zz * zst[j] + s] : 0;
+      }
+    }
+    // products; the sums are folded back to |s| <= q/2 + 1 after every second
+    // product of the chunk (every product lies within 1.25 q of 0)
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (a0 + c >= h.A) break;
+#pragma unroll
+      for (int j = 0; j < BETA; ++j) {
+#pragma unroll
+        for (int zz = 0; zz < ZB; ++zz) {
+          const double vv = own[j] ? u64_to_f(v[c][j][zz]) : __longlong_as_double((long long)v[c][j][zz]);
+          su[zz] = __dadd_rn(su[zz], fmul_mod_q(vv, kb[c][j], qi, qd));
+          sw[zz] = __dadd_rn(sw[zz], fmul_mod_q(vv, ka[c][j], qi, qd));
+          if ((c * BETA + j) & 1) {
+            su[zz] = fred(su[zz], qi, qd);
+            sw[zz] = fred(sw[zz], qi, qd);
+          }
+        }
+      }
+    }
+    if ((CH * BETA) & 1) {   // an odd chunk ends with one product pending
+#pragma unroll
+      for (int zz = 0; zz < ZB; ++zz) {
+        su[zz] = fred(su[zz], qi, qd);
+        sw[zz] = fred(sw[zz], qi, qd);
+      }
+    }
+  }
+  auto res = [&](double s_) {
+    double r = fred(s_, qi, qd);
+    r = r < 0.0 ? __dadd_rn(r, qd) : r;
+    return f_to_u64(r);
+  };
+#pragma unroll
+  for (int zz = 0; zz < ZB; ++zz) {
+    if (zz >= nz) break;
+    u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
+    const u64 ru = res(su[zz]), rw = res(sw[zz]);
+    U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
+    U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
+  }
+}
+
 // out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
 // (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in)
 __global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, HoistArgs h, const PrimeC* P,
@@ -1459,6 +1562,26 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const size_t gx = (c.N + TPB - 1) / TPB;
   const size_t W = gx * tb.ext * B;
   if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+  if (!h.per_elem && B > 1) {
+    // shared amounts: elements grouped per thread and amounts per chunk sized to
+    // about 100 registers
+    const int ZB = tb.beta <= 2 ? 4 : 2;
+    const size_t Wz = gx * tb.ext * (size_t)((B + ZB - 1) / ZB);
+    if (Wz % 8 != 0 || Wz > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+#define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                        \
+  LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)Wz), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, \
+         h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,          \
+         accumulate ? 1 : 0)
+    switch (tb.beta) {
+      case 1: KIP_HOIST_ZB(1, 4, 4); break;
+      case 2: KIP_HOIST_ZB(2, 4, 2); break;
+      case 3: KIP_HOIST_ZB(3, 2, 2); break;
+      default: KIP_HOIST_ZB(4, 2, 2); break;
+    }
+#undef KIP_HOIST_ZB
+    check_launch();
+    return;
+  }
 #define KIP_HOIST(BETA)                                                                                      \
   LAUNCH(k_kip_hoist<BETA>, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw, \
          c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B, accumulate ? 1 : 0)
