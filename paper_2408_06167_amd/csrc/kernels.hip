@@ -903,11 +903,12 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
 }
 
-// The same sums when every element uses the same amounts: one thread serves up
-// to ZB elements of one (limb, position), so each key word is loaded once and
-// used ZB times from registers, and takes the amounts CH at a time, all their
-// words requested before the first is used (memory latency, not arithmetic,
-// sets the pace of this kernel).
+// The same sums when every element uses the same amounts: one thread serves
+// two neighbouring positions (16-byte loads: the automorphism maps an aligned
+// pair of positions onto an aligned pair) of up to ZB elements of one limb, so
+// each key word is loaded once and used ZB times from registers, and takes
+// the amounts CH at a time, all their words requested before the first is
+// used (memory latency, not arithmetic, sets the pace of this kernel).
 template <int BETA, int ZB, int CH>
 __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                                HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
@@ -916,17 +917,17 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   const int N = 1 << log_n;
   const int ext = tb.ext;
   // 1-D grid of (limb, position block, element group), element group fastest
-  const int gx = (N + TPB - 1) / TPB;
+  const int gx = N / (2 * TPB);
   const int ZG = (B + ZB - 1) / ZB;
   const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
   const int zg = lb % ZG;
   const int pb = (lb / ZG) % gx;
   const int t = lb / (ZG * gx);
-  const int i = pb * TPB + threadIdx.x;
+  const int i = 2 * (pb * TPB + (int)threadIdx.x);   // positions i, i + 1
   __shared__ const u64* kp[HOIST_MAX];
   for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
   __syncthreads();
-  if (i >= N || t >= ext) return;
+  if (t >= ext) return;
   const int z0 = zg * ZB, nz = min(ZB, B - z0);
   const PrimeC& pr = P[tb.ext_prime[t]];
   const u64 q = pr.q;
@@ -944,24 +945,26 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
     zst[j] = own[j] ? sx : sy;
   }
   const size_t ko = (size_t)kl * N + i, kst = (size_t)key_limbs * N;
-  typedef const __attribute__((address_space(1))) double* gdp;
-  double su[ZB], sw[ZB];
+  double su[ZB][2], sw[ZB][2];
 #pragma unroll
-  for (int zz = 0; zz < ZB; ++zz) su[zz] = sw[zz] = 0.0;
+  for (int zz = 0; zz < ZB; ++zz) su[zz][0] = su[zz][1] = sw[zz][0] = sw[zz][1] = 0.0;
   for (int a0 = 0; a0 < h.A; a0 += CH) {
-    double kb[CH][BETA], ka[CH][BETA];
-    u64 v[CH][BETA][ZB];
+    double2 kb[CH][BETA], ka[CH][BETA];
+    ulonglong2 v[CH][BETA][ZB];
+    bool swp[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int a = a0 + c < h.A ? a0 + c : h.A - 1;   // a ragged chunk repeats the last amount, unused
       const u32 s = autom_src((u32)i, h.g[a], log_n, ms);
-      const gdp key = (gdp)kp[a];
+      swp[c] = s & 1;                                    // position i reads the odd word of the pair
+      const double* key = (const double*)kp[a];
 #pragma unroll
       for (int j = 0; j < BETA; ++j) {
-        kb[c][j] = key[ko + (size_t)(2 * j) * kst];
-        ka[c][j] = key[ko + (size_t)(2 * j + 1) * kst];
+        kb[c][j] = *(const double2*)(key + ko + (size_t)(2 * j) * kst);
+        ka[c][j] = *(const double2*)(key + ko + (size_t)(2 * j + 1) * kst);
 #pragma unroll
-        for (int zz = 0; zz < ZB; ++zz) v[c][j][zz] = zz < nz ? src[j][zz * zst[j] + s] : 0;
+        for (int zz = 0; zz < ZB; ++zz)
+          v[c][j][zz] = zz < nz ? *(const ulonglong2*)(src[j] + zz * zst[j] + (s & ~1u)) : make_ulonglong2(0, 0);
       }
     }
     // products; the sums are folded back to |s| <= q/2 + 1 after every second
@@ -973,22 +976,31 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
       for (int j = 0; j < BETA; ++j) {
 #pragma unroll
         for (int zz = 0; zz < ZB; ++zz) {
-          const double vv = own[j] ? u64_to_f(v[c][j][zz]) : __longlong_as_double((long long)v[c][j][zz]);
-          su[zz] = __dadd_rn(su[zz], fmul_mod_q(vv, kb[c][j], qi, qd));
-          sw[zz] = __dadd_rn(sw[zz], fmul_mod_q(vv, ka[c][j], qi, qd));
+          const u64 w0 = swp[c] ? v[c][j][zz].y : v[c][j][zz].x, w1 = swp[c] ? v[c][j][zz].x : v[c][j][zz].y;
+          const double v0 = own[j] ? u64_to_f(w0) : __longlong_as_double((long long)w0);
+          const double v1 = own[j] ? u64_to_f(w1) : __longlong_as_double((long long)w1);
+          su[zz][0] = __dadd_rn(su[zz][0], fmul_mod_q(v0, kb[c][j].x, qi, qd));
+          su[zz][1] = __dadd_rn(su[zz][1], fmul_mod_q(v1, kb[c][j].y, qi, qd));
+          sw[zz][0] = __dadd_rn(sw[zz][0], fmul_mod_q(v0, ka[c][j].x, qi, qd));
+          sw[zz][1] = __dadd_rn(sw[zz][1], fmul_mod_q(v1, ka[c][j].y, qi, qd));
           if ((c * BETA + j) & 1) {
-            su[zz] = fred(su[zz], qi, qd);
-            sw[zz] = fred(sw[zz], qi, qd);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+              su[zz][e] = fred(su[zz][e], qi, qd);
+              sw[zz][e] = fred(sw[zz][e], qi, qd);
+            }
           }
         }
       }
     }
     if ((CH * BETA) & 1) {   // an odd chunk ends with one product pending
 #pragma unroll
-      for (int zz = 0; zz < ZB; ++zz) {
-        su[zz] = fred(su[zz], qi, qd);
-        sw[zz] = fred(sw[zz], qi, qd);
-      }
+      for (int zz = 0; zz < ZB; ++zz)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          su[zz][e] = fred(su[zz][e], qi, qd);
+          sw[zz][e] = fred(sw[zz][e], qi, qd);
+        }
     }
   }
   auto res = [&](double s_) {
@@ -999,10 +1011,17 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
 #pragma unroll
   for (int zz = 0; zz < ZB; ++zz) {
     if (zz >= nz) break;
-    u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N;
-    const u64 ru = res(su[zz]), rw = res(sw[zz]);
-    U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
-    U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
+    u64* U = uw + (size_t)(z0 + zz) * suw + (size_t)t * N + i;
+    u64* W = U + (size_t)ext * N;
+    ulonglong2 ru = make_ulonglong2(res(su[zz][0]), res(su[zz][1]));
+    ulonglong2 rw = make_ulonglong2(res(sw[zz][0]), res(sw[zz][1]));
+    if (accumulate) {
+      const ulonglong2 ou = *(ulonglong2*)U, ow = *(ulonglong2*)W;
+      ru = make_ulonglong2(add_mod(ou.x, ru.x, q), add_mod(ou.y, ru.y, q));
+      rw = make_ulonglong2(add_mod(ow.x, rw.x, q), add_mod(ow.y, rw.y, q));
+    }
+    *(ulonglong2*)U = ru;
+    *(ulonglong2*)W = rw;
   }
 }
 
@@ -1562,21 +1581,21 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   const size_t gx = (c.N + TPB - 1) / TPB;
   const size_t W = gx * tb.ext * B;
   if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
-  if (!h.per_elem && B > 1) {
+  if (!h.per_elem && B > 1 && c.N % (2 * TPB) == 0) {
     // shared amounts: elements grouped per thread and amounts per chunk sized to
     // about 100 registers
-    const int ZB = tb.beta <= 2 ? 4 : 2;
-    const size_t Wz = gx * tb.ext * (size_t)((B + ZB - 1) / ZB);
+    const int ZB = tb.beta == 1 ? 4 : 2;
+    const size_t Wz = (c.N / (2 * TPB)) * tb.ext * (size_t)((B + ZB - 1) / ZB);
     if (Wz % 8 != 0 || Wz > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
 #define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                        \
   LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)Wz), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, \
          h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,          \
          accumulate ? 1 : 0)
     switch (tb.beta) {
-      case 1: KIP_HOIST_ZB(1, 4, 4); break;
-      case 2: KIP_HOIST_ZB(2, 4, 2); break;
-      case 3: KIP_HOIST_ZB(3, 2, 2); break;
-      default: KIP_HOIST_ZB(4, 2, 2); break;
+      case 1: KIP_HOIST_ZB(1, 4, 2); break;
+      case 2: KIP_HOIST_ZB(2, 2, 2); break;
+      case 3: KIP_HOIST_ZB(3, 2, 1); break;
+      default: KIP_HOIST_ZB(4, 2, 1); break;
     }
 #undef KIP_HOIST_ZB
     check_launch();
