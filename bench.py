@@ -23,25 +23,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Butterflies per second the VALU can issue at most.  The NTT carries exact
-# integer residues (q < 2^51) in FP64, which CDNA4 issues at one operation per
-# lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32 T FP64
-# operations/s (the 78.6 TFLOP/s vector figure counts an FMA as two).  One
-# butterfly needs at least 8 of them: the exact product a*w - round(a*w/q)*q
-# (multiply, FMA for the low half, multiply by w/q, round, FMA, add) and the
-# sum and difference.  Peak: 39.32e12 / 8 = 4.915 T butterflies/s.
+# Modular products per second the VALU can issue at most, reported beside the
+# HBM figure.  Residues (q < 2^51) are carried in FP64, which CDNA4 issues at
+# one operation per lane per clock: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.32 T FP64 operations/s (the 78.6 TFLOP/s vector figure counts an FMA as
+# two).  A butterfly (or a multiply-accumulate of the key products) needs at
+# least 8 of them: the exact product a*w - round(a*w/q)*q (multiply, FMA for
+# the low half, multiply for the quotient, round, FMA, add) and two adds.
+# Peak: 39.32e12 / 8 = 4.915 T/s.  Every kernel of the match moves at least
+# one 8-byte word per such operation, below the 5 operations per byte at which
+# the FP64 VALU would bind before HBM, so the roofline is the HBM one.
 ALU_PEAK_GMODMUL = 39.3216e3 / 8.0
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs (scaled by
 # a 1 GiB device copy: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE), kept with
 # the sha256 of the kernel source they were taken on and the workload; the
 # figure is reported only while both still match.
-TRAFFIC = {
-    ("ntt_fwd_row", "k4_S2+levelmin"): dict(
-        bytes_per_launch=27433245, algorithmic_bytes_per_launch=23884231,
-        kernels_sha256="b74e35cacf3c564ce0513983c74a3ecd7bac02ef7ff5c793c1f48d7a92ba6c78"),
-}
-ALU_BOUND_KERNELS = ("ntt_fwd_col", "ntt_fwd_row", "ntt_inv_col", "ntt_inv_row", "ntt_fwd_one",
-                     "ntt_inv_one")
+TRAFFIC = {}
 
 
 def kernels_sha256():
@@ -234,18 +231,10 @@ def main():
         ops_per = e["ops"] / e["launches"]
         gbs = bytes_per / avg_s / 1e9
         gmm = ops_per / avg_s / 1e9
-        # the NTT passes are VALU-bound (VALU busy ~90% of their cycles in the
-        # counter runs); the element-wise kernels stream HBM
         f_hbm, f_alu = gbs / HBM_PEAK_GBS, gmm / ALU_PEAK_GMODMUL
-        if name in ALU_BOUND_KERNELS:
-            roof = dict(bound="alu", kernel=name, achieved=round(gmm, 2), peak=round(ALU_PEAK_GMODMUL, 1),
-                        unit="Gbutterfly/s", frac=round(f_alu, 4), hbm_gbs=round(gbs, 1),
-                        hbm_frac=round(f_hbm, 4), avg_us=round(avg_s * 1e6, 2), launches=e["launches"],
-                        traffic=None)
-        else:
-            roof = dict(bound="hbm", kernel=name, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(f_hbm, 4), alu_gmodmul=round(gmm, 2), alu_frac=round(f_alu, 4),
-                        avg_us=round(avg_s * 1e6, 2), launches=e["launches"], traffic=None)
+        roof = dict(bound="hbm", kernel=name, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(f_hbm, 4), alu_gmodmul=round(gmm, 2), alu_frac=round(f_alu, 4),
+                    avg_us=round(avg_s * 1e6, 2), launches=e["launches"], traffic=None)
         roof["traffic"] = traffic_for(name, "k%d_%s" % (bk, sname(bs)), bytes_per)
         step_ms_dev = sum(v["ms"] for v in prof.values()) / args.steps
         roof["kernel_share"] = round(e["ms"] / args.steps / max(step_ms_dev, 1e-9), 3)

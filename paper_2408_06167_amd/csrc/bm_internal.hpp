@@ -423,13 +423,13 @@ void zero(const Ctx& c, u64* out, size_t words);
 void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const uint32_t* idx_dev,
               uint32_t max_idx, bool scatter, int B, size_t words);
 // (u, w)[z] = sum_a KIP(phi_{g(z,a)}(y[z]), key_{g(z,a)}); gtab[g/2] holds the
-// key of element g; `keys` lists the keys used (launch check)
+// key of element g; `keys` lists the keys used (launch check).  The same
+// launch computes c0_out[z] = c0_in[z] + sum_a phi_{g(z,a)}(c0_in[z]) over
+// `limbs` limbs (accumulate: both outputs are added to; c0_out must not alias
+// c0_in).
 void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
-               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, int B,
-               int limbs, bool accumulate);
-// out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) over `limbs` limbs of one component
-void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const HoistArgs& h, int B,
-               int limbs, bool accumulate);
+               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
+               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate);
 }  // namespace kern
 
 }  // namespace bm

@@ -357,8 +357,7 @@ void rotation_sum_hoisted(Ctx& c, const bm_evk* evk, const u64* in, int B, int l
   DBuf uw(&c, (size_t)B * suw), c0(&c, (size_t)B * ln);
   for (size_t part = 0; part < hs.size(); ++part) {   // amount lists longer than one launch carries
     kern::kip_hoist(c, y.p(), sy, in + ln, 2 * ln, (const u64* const*)evk->gtab.p(), hs[part], keys, uw.p(),
-                    suw, B, limbs, part > 0);
-    kern::autom_sum(c, in, 2 * ln, c0.p(), ln, hs[part], B, limbs, part > 0);
+                    suw, in, 2 * ln, c0.p(), ln, B, limbs, part > 0);
   }
   moddown_add(c, uw.p(), B, limbs, c0.p(), ln, in + ln, 2 * ln, out, 2 * ln);
 }

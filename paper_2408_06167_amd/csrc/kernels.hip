@@ -807,16 +807,55 @@ constexpr int HOIST_BETA = 4;   // digits a thread handles (dnum <= 4 at every l
 // stay in that XCD's L2.
 __device__ __forceinline__ int xcd_block(int w, int W) { return (w & 7) * (W >> 3) + (w >> 3); }
 
+// out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
+// (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in).
+// Runs as the first am.W blocks of a hoisted key inner product launch (the c0
+// half of the hoisted rotation sum), over a 1-D XCD-aware grid of (element,
+// limb, position block), position block fastest.
+struct AutomArgs {
+  const u64* in;
+  size_t si;
+  u64* out;
+  size_t so;
+  int limbs;
+  int W;   // blocks of the launch that do this part
+};
+
+__device__ __forceinline__ void autom_sum_part(const AutomArgs& am, const HoistArgs& h, const PrimeC* P,
+                                               int log_n, int ms, int accumulate, int w) {
+  const int N = 1 << log_n;
+  const int gx = (N + TPB - 1) / TPB;
+  const int lb = xcd_block(w, am.W);
+  const int l = (lb / gx) % am.limbs;
+  const int z = lb / (gx * am.limbs);
+  const int i = (lb % gx) * TPB + threadIdx.x;
+  if (i >= N) return;
+  const u64 q = P[l].q;
+  const u64* I = am.in + (size_t)z * am.si + (size_t)l * N;
+  u64* O = am.out + (size_t)z * am.so + (size_t)l * N;
+  u64 acc = accumulate ? O[i] : I[i];
+#pragma unroll 4
+  for (int a = 0; a < h.A; ++a) {
+    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    acc = add_mod(acc, I[autom_src((u32)i, g, log_n, ms)], q);
+  }
+  O[i] = acc;
+}
+
 template <int BETA>
 __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                             HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
-                            const PrimeC* P, int log_n, int ms, int B, int accumulate) {
+                            const PrimeC* P, int log_n, int ms, int B, int accumulate, AutomArgs am) {
+  if ((int)blockIdx.x < am.W) {
+    autom_sum_part(am, h, P, log_n, ms, accumulate, (int)blockIdx.x);
+    return;
+  }
   const ModUpTable& tb = *T;
   const int N = 1 << log_n;
   const int ext = tb.ext;
   // 1-D grid of (limb, position block, element), element fastest
   const int gx = (N + TPB - 1) / TPB;
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
   const int z = lb % B;
   const int pb = (lb / B) % gx;
   const int t = lb / (B * gx);
@@ -912,14 +951,18 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 template <int BETA, int ZB, int CH>
 __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                                HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
-                               const PrimeC* P, int log_n, int ms, int B, int accumulate) {
+                               const PrimeC* P, int log_n, int ms, int B, int accumulate, AutomArgs am) {
+  if ((int)blockIdx.x < am.W) {
+    autom_sum_part(am, h, P, log_n, ms, accumulate, (int)blockIdx.x);
+    return;
+  }
   const ModUpTable& tb = *T;
   const int N = 1 << log_n;
   const int ext = tb.ext;
   // 1-D grid of (limb, position block, element group), element group fastest
   const int gx = N / (2 * TPB);
   const int ZG = (B + ZB - 1) / ZB;
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+  const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
   const int zg = lb % ZG;
   const int pb = (lb / ZG) % gx;
   const int t = lb / (ZG * gx);
@@ -1023,29 +1066,6 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
     *(ulonglong2*)U = ru;
     *(ulonglong2*)W = rw;
   }
-}
-
-// out[z] = in[z] + sum_a phi_{g(z,a)}(in[z]) on `limbs` limbs of one component
-// (accumulate: out[z] += sum_a phi_{g(z,a)}(in[z]); out must not alias in)
-__global__ void k_autom_sum(const u64* in, size_t si, u64* out, size_t so, HoistArgs h, const PrimeC* P,
-                            int log_n, int ms, int limbs, int accumulate) {
-  const int N = 1 << log_n;
-  // 1-D XCD-aware grid of (element, limb, position block), position block fastest
-  const int gx = (N + TPB - 1) / TPB;
-  const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-  const int l = (lb / gx) % limbs;
-  const int z = lb / (gx * limbs);
-  const int i = (lb % gx) * TPB + threadIdx.x;
-  if (i >= N) return;
-  const u64 q = P[l].q;
-  const u64* I = in + (size_t)z * si + (size_t)l * N;
-  u64* O = out + (size_t)z * so + (size_t)l * N;
-  u64 acc = accumulate ? O[i] : I[i];
-  for (int a = 0; a < h.A; ++a) {
-    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
-    acc = add_mod(acc, I[autom_src((u32)i, g, log_n, ms)], q);
-  }
-  O[i] = acc;
 }
 
 // conv[c][i] = sum_k [u_c[p_k] (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}   (coefficient domain)
@@ -1564,8 +1584,8 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
 }
 
 void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
-               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, int B,
-               int limbs, bool accumulate) {
+               const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
+               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate) {
   const ModUpTable& tb = c.h_modup[limbs];
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
   if (h.A < 1 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
@@ -1574,23 +1594,26 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   chk(gtab, 1, 0, 0, c.M / 2, "key table");
   for (const u64* key : keys) chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "hoisted kip key");
   chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "hoisted kip output");
-  const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
-  Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2)),
-          2.0 * c.N * tb.ext * tb.beta * B * h.A);
+  chk(c0_in, B, c0_si, 0, (size_t)limbs * c.N, "autom_sum input");
+  chk(c0_out, B, c0_so, 0, (size_t)limbs * c.N, "autom_sum output");
   if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the hoisted kip");
+  const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
+  // the c0 half (gathered sum of the rotations) rides in the same launch
+  Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2) + 2.0 * c.N * limbs * B),
+          2.0 * c.N * tb.ext * tb.beta * B * h.A);
   const size_t gx = (c.N + TPB - 1) / TPB;
-  const size_t W = gx * tb.ext * B;
-  if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+  AutomArgs am{c0_in, c0_si, c0_out, c0_so, limbs, (int)(gx * limbs * B)};
+  if (am.W % 8 != 0) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
   if (!h.per_elem && B > 1 && c.N % (2 * TPB) == 0) {
     // shared amounts: elements grouped per thread and amounts per chunk sized to
     // about 100 registers
     const int ZB = tb.beta == 1 ? 4 : 2;
     const size_t Wz = (c.N / (2 * TPB)) * tb.ext * (size_t)((B + ZB - 1) / ZB);
-    if (Wz % 8 != 0 || Wz > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
-#define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                        \
-  LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)Wz), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, \
-         h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,          \
-         accumulate ? 1 : 0)
+    if (Wz % 8 != 0 || Wz + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+#define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                          \
+  LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)(Wz + am.W)), dim3(TPB), 0, c.stream, y, sy, y_own, sown, \
+         gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,      \
+         accumulate ? 1 : 0, am)
     switch (tb.beta) {
       case 1: KIP_HOIST_ZB(1, 4, 2); break;
       case 2: KIP_HOIST_ZB(2, 2, 2); break;
@@ -1601,9 +1624,11 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
     check_launch();
     return;
   }
-#define KIP_HOIST(BETA)                                                                                      \
-  LAUNCH(k_kip_hoist<BETA>, dim3((unsigned)W), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, suw, \
-         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B, accumulate ? 1 : 0)
+  const size_t W = gx * tb.ext * B;
+  if (W % 8 != 0 || W + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
+#define KIP_HOIST(BETA)                                                                                        \
+  LAUNCH(k_kip_hoist<BETA>, dim3((unsigned)(W + am.W)), dim3(TPB), 0, c.stream, y, sy, y_own, sown, gtab, h, uw, \
+         suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B, accumulate ? 1 : 0, am)
   switch (tb.beta) {
     case 1: KIP_HOIST(1); break;
     case 2: KIP_HOIST(2); break;
@@ -1611,19 +1636,6 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
     default: KIP_HOIST(4); break;
   }
 #undef KIP_HOIST
-  check_launch();
-}
-
-void autom_sum(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const HoistArgs& h, int B,
-               int limbs, bool accumulate) {
-  if (h.A < 0 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
-  chk(in, B, si, 0, (size_t)limbs * c.N, "autom_sum input");
-  chk(out, B, so, 0, (size_t)limbs * c.N, "autom_sum output");
-  Prof pf(c, "autom_sum", 8.0 * c.N * B * limbs * (h.A + 2), (double)c.N * B * limbs * h.A);
-  const size_t W = (size_t)((c.N + TPB - 1) / TPB) * limbs * B;
-  if (W % 8 != 0 || W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
-  LAUNCH(k_autom_sum, dim3((unsigned)W), dim3(TPB), 0, c.stream, in, si, out, so, h, c.d_primes, c.log_n,
-         c.ci ? 2 : 1, limbs, accumulate ? 1 : 0);
   check_launch();
 }
 
