@@ -343,53 +343,66 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
   }
-  if constexpr (FUSE == 1) {
-    // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
-    // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
-    // the bracket the exact residue in [0, m_a)); one limb: X mod q.
-    const int slot = blockIdx.y;
-    const size_t zz = blockIdx.z;
-    const u64* S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo + (size_t)blockIdx.x * 16 + v;
-    if (f.pro == 3) {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(S[(size_t)addr(0, j) * astride]), qi, q);
+  // FUSE = 1: the words of the first two sources are requested here, before
+  // the twiddles are staged, and combined after (see below)
+  const u64* S = nullptr;
+  int ns = 0, jd = 0, tt = 0;
+  u64 r0[FUSE == 1 ? 16 : 1], r1[FUSE == 1 ? 16 : 1];
+  // source a of slot blockIdx.y: limb offset, prime, and the two constants
+  auto src_info = [&](int a, int& soff, int& spid, u64& c1, u64& c2) {
+    if (f.pro == 1) {
+      const ModUpDigit& dg = f.mu->d[jd];
+      soff = spid = dg.src[a];
+      c1 = dg.qhatinv[a][0];
+      c2 = dg.qhat[a][tt][0];
     } else {
-      const int jd = f.pro == 1 ? f.mu->pair_j[slot] : 0, tt = f.pro == 1 ? f.mu->pair_t[slot] : 0;
-      const int ns = f.pro == 1 ? f.mu->d[jd].nsrc : f.md->K;
-      for (int a = 0; a < ns; ++a) {
-        int soff, spid;
-        u64 c1, c2;
-        if (f.pro == 1) {
-          const ModUpDigit& dg = f.mu->d[jd];
-          soff = spid = dg.src[a];
-          c1 = dg.qhatinv[a][0];
-          c2 = dg.qhat[a][tt][0];
-        } else {
-          soff = f.s_off0 + a;
-          spid = f.md->pprime[a];
-          c1 = f.md->phatinv[a][0];
-          c2 = f.md->phat[a][slot][0];
-        }
-        const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
-        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
-        const u64* Sa = S + (size_t)soff * N;
-        u64 r[16];
+      soff = f.s_off0 + a;
+      spid = f.md->pprime[a];
+      c1 = f.md->phatinv[a][0];
+      c2 = f.md->phat[a][blockIdx.y][0];
+    }
+  };
+  if constexpr (FUSE == 1) {
+    const size_t zz = blockIdx.z;
+    S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo + (size_t)blockIdx.x * 16 + v;
+    if (f.pro == 3) {
+      ns = 1;
+    } else {
+      jd = f.pro == 1 ? f.mu->pair_j[blockIdx.y] : 0;
+      tt = f.pro == 1 ? f.mu->pair_t[blockIdx.y] : 0;
+      ns = f.pro == 1 ? f.mu->d[jd].nsrc : f.md->K;
+    }
+    int soff = 0, spid;
+    u64 c1, c2;
+    if (f.pro != 3) src_info(0, soff, spid, c1, c2);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) r[j] = Sa[(size_t)addr(0, j) * astride];
+    for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
+    if (ns > 1) {
+      src_info(1, soff, spid, c1, c2);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
-          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
-          const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
-          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
-        }
-        if (a & 1) {
+      for (int j = 0; j < 16; ++j) r1[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
+    }
+  }
+  // FUSE = 2: the epilogue's operands are requested here as well
+  u64 mr[FUSE == 2 ? 16 : 1], ar[FUSE == 2 ? 16 : 1];
+  const u64* Ad = nullptr;
+  u64* Oe = nullptr;
+  if constexpr (FUSE == 2) {
+    if (valid) {
+      const int slot = blockIdx.y;
+      const size_t zz = blockIdx.z * vz + v % vz;
+      const size_t hi = zz / f.e_div, lo = zz % f.e_div;
+      const size_t pos = ((size_t)blockIdx.x * R + v / vz) * M + (size_t)slot * N;
+      const u64* Mn = f.mnd + hi * f.m_hi + lo * f.m_lo + pos;
+      Ad = lo == 0 ? (f.add0 ? f.add0 + hi * f.a0_hi + pos : nullptr)
+                   : (f.add1 ? f.add1 + hi * f.a1_hi + pos : nullptr);
+      Oe = f.out + hi * f.o_hi + lo * f.o_lo + pos;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
-        }
+      for (int j = 0; j < 16; ++j) mr[j] = Mn[addr(0, j)];
+      if (Ad) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) ar[j] = Ad[addr(0, j)];
       }
-#pragma unroll
-      for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
     }
   }
   // ---- stage the block's twiddles (8-stage passes).  Stage st (0..7) of the
@@ -410,7 +423,41 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       tl[rr * 512 + 256 + slot] = WQ[g];
     }
   }
-  if (FUSE == 1) {
+  if constexpr (FUSE == 1) {
+    // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
+    // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
+    // the bracket the exact residue in [0, m_a)); one limb: X mod q.
+    if (f.pro == 3) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
+    } else {
+      for (int a = 0; a < ns; ++a) {
+        int soff, spid;
+        u64 c1, c2;
+        src_info(a, soff, spid, c1, c2);
+        const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
+        u64 r[16];
+        if (a >= 2) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) r[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const u64 w = a == 0 ? r0[j] : a == 1 ? r1[j] : r[j];
+          double t1 = fred(fmul_mod(u64_to_f(w), c1d, c1q, ms), msi, ms);
+          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+          const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
+          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+        }
+        if (a & 1) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+    }
   } else if (DIRECT_IN) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) x[j] = u64_to_f(raw[j]);
@@ -521,24 +568,16 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     if (valid) {
       if constexpr (FUSE == 2) {
         // out = (minuend - x) w (+ addend), all words exact residues
-        const int slot = blockIdx.y;
-        const size_t zz = blockIdx.z * vz + v % vz;
-        const size_t hi = zz / f.e_div, lo = zz % f.e_div;
-        const size_t pos = ((size_t)blockIdx.x * R + v / vz) * M + (size_t)slot * N;
-        const u64* Mn = f.mnd + hi * f.m_hi + lo * f.m_lo + pos;
-        const u64* Ad = lo == 0 ? (f.add0 ? f.add0 + hi * f.a0_hi + pos : nullptr)
-                                : (f.add1 ? f.add1 + hi * f.a1_hi + pos : nullptr);
-        u64* O = f.out + hi * f.o_hi + lo * f.o_lo + pos;
-        const double wd = (double)f.wtab[2 * slot], wq = wd / q;
+        const double wd = (double)f.wtab[2 * blockIdx.y], wq = wd / q;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int a = addr(0, j);
-          const double d = __dsub_rn(u64_to_f(Mn[a]), u64_to_f(sh_raw[v * VS + pad(a)]));   // |d| < q
+          const double d = __dsub_rn(u64_to_f(mr[j]), u64_to_f(sh_raw[v * VS + pad(a)]));   // |d| < q
           double r = fmul_mod(d, wd, wq, q);                                                 // |r| <= q
-          if (Ad) r = __dadd_rn(r, u64_to_f(Ad[a]));
+          if (Ad) r = __dadd_rn(r, u64_to_f(ar[j]));
           r = fred(r, qi, q);
           r = r < 0.0 ? __dadd_rn(r, q) : r;
-          O[a] = f_to_u64(r);
+          Oe[a] = f_to_u64(r);
         }
       } else {
 #pragma unroll
