@@ -343,11 +343,11 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
   }
-  // FUSE = 1: the words of the first two sources are requested here, before
-  // the twiddles are staged, and combined after (see below)
+  // FUSE = 1: the words of the first source are requested here, before the
+  // twiddles are staged, and combined after (see below)
   const u64* S = nullptr;
   int ns = 0, jd = 0, tt = 0;
-  u64 r0[FUSE == 1 ? 16 : 1], r1[FUSE == 1 ? 16 : 1];
+  u64 r0[FUSE == 1 ? 16 : 1];
   // source a of slot blockIdx.y: limb offset, prime, and the two constants
   auto src_info = [&](int a, int& soff, int& spid, u64& c1, u64& c2) {
     if (f.pro == 1) {
@@ -377,11 +377,6 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     if (f.pro != 3) src_info(0, soff, spid, c1, c2);
 #pragma unroll
     for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
-    if (ns > 1) {
-      src_info(1, soff, spid, c1, c2);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) r1[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
-    }
   }
   // FUSE = 2: the epilogue's operands are requested here as well
   u64 mr[FUSE == 2 ? 16 : 1], ar[FUSE == 2 ? 16 : 1];
@@ -438,13 +433,13 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
         const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
         u64 r[16];
-        if (a >= 2) {
+        if (a >= 1) {
 #pragma unroll
           for (int j = 0; j < 16; ++j) r[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const u64 w = a == 0 ? r0[j] : a == 1 ? r1[j] : r[j];
+          const u64 w = a == 0 ? r0[j] : r[j];
           double t1 = fred(fmul_mod(u64_to_f(w), c1d, c1q, ms), msi, ms);
           t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
           const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
