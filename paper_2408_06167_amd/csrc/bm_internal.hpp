@@ -163,6 +163,8 @@ struct FuseArgs {
   size_t o_hi = 0, o_lo = 0;
   int e_div = 1;
   const u64* wtab = nullptr;
+  const u64* ci = nullptr;       // conjugate-invariant ring: the per-prime fold constants
+  int src_pid = -1;              // one-limb reduction: prime of the source limb
 };
 
 // ----------------------------------------------------------------- device memory
@@ -354,13 +356,15 @@ LimbMap chain_map(int limbs);                        // q_0..q_{limbs-1} at offs
 LimbMap ext_map(const Ctx& c, int limbs);           // q_0..q_{l-1}, p_0..p_{K-1}
 LimbMap single(int prime, int off);
 
-// forward / inverse negacyclic NTT; in and out may alias
+// forward / inverse negacyclic NTT; in and out may alias.  In the
+// conjugate-invariant ring `raw` leaves out the fold (forward) or unfold
+// (inverse) around the transform.
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-         const LimbMap& m, bool inverse);
+         const LimbMap& m, bool inverse, bool raw = false);
 // in place: residue words (< 2^52) <-> the bit patterns of the same values as
 // FP64 numbers (the form switching keys are kept in)
 void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);
-// whether ntt_fused serves this context (N = 2^16, standard ring)
+// whether ntt_fused serves this context (N = 2^16)
 bool fused_ok(const Ctx& c);
 // forward NTT of the words f's prologue computes, into tmp at the slots m.ooff
 // (slot s of element z at tmp + z * ts + m.ooff[s] * N), as FP64 values when

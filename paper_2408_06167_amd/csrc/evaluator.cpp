@@ -263,7 +263,8 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
   DBuf xc(&c, (size_t)B * limbs * N);
-  kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true);
+  // the fused transform unfolds (conjugate-invariant ring) on the fly
+  kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true, kern::fused_ok(c));
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
   LimbMap m{};
@@ -276,6 +277,7 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   if (kern::fused_ok(c)) {           // conversion computed inside the forward transform
     FuseArgs f;
     f.pro = 1;
+    f.ci = c.ci ? c.d_ci : nullptr;
     f.mu = c.d_modup + limbs;
     f.src = xc.p();
     f.s_hi = (size_t)limbs * N;
@@ -303,12 +305,13 @@ static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size
       mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
       ++mp.n;
     }
-  kern::ntt(c, uw, suw, uw, suw, B, mp, true);
+  kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
   if (kern::fused_ok(c)) {           // conversion and finish inside the forward transform
     FuseArgs f;
     f.pro = 2;
+    f.ci = c.ci ? c.d_ci : nullptr;
     f.md = c.d_moddown;
     f.src = uw;
     f.s_div = f.e_div = 2;           // element 2 z + comp
@@ -374,12 +377,14 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
   DBuf last(&c, (size_t)B * comps * N);
   LimbMap m = kern::single(nl, nl);
   m.ooff[0] = 0;
-  kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true);
+  kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true, kern::fused_ok(c));
   DBuf t(&c, (size_t)B * comps * nl * N);
   if (kern::fused_ok(c)) {           // reduction and finish inside the forward transform
     if (in == out) BM_THROW(BM_EINVAL, "rescale cannot work in place");
     FuseArgs f;
     f.pro = 3;
+    f.ci = c.ci ? c.d_ci : nullptr;
+    f.src_pid = nl;
     f.src = last.p();
     f.s_hi = N;
     f.epi = 1;

@@ -254,7 +254,8 @@ enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 
 // FUSE = 1: forward column pass whose input words come from f's prologue;
 // FUSE = 2: forward row pass that stores through f's epilogue;
-// FUSE = 3: forward row pass that stores the residues as FP64 values.
+// FUSE = 3: forward row pass that stores the residues as FP64 values;
+// FUSE = 4: as 1, in the conjugate-invariant ring (sources not yet unfolded).
 template <int LOGM, bool INV, int KIND, int FUSE = 0>
 __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
@@ -262,8 +263,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   const double* __restrict__ twf,
                                                   const double* __restrict__ twq, int log_n, int s0,
                                                   int last, int B, int vz, FuseArgs f) {
-  static_assert(FUSE == 0 || (!INV && ((FUSE == 1 && KIND == NTT_COL) || (FUSE >= 2 && KIND == NTT_ROW))),
+  static_assert(FUSE == 0 || (!INV && (((FUSE == 1 || FUSE == 4) && KIND == NTT_COL) ||
+                                       ((FUSE == 2 || FUSE == 3) && KIND == NTT_ROW))),
                 "fused prologues serve forward column passes, epilogues forward row passes");
+  constexpr bool PRO = FUSE == 1 || FUSE == 4;
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
   // padded view length in LDS.  Column passes put 16 views side by side in a
@@ -339,7 +342,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 
   // data loads first, so that their latency overlaps the twiddle staging
   u64 raw[16] = {};
-  if (FUSE != 1 && valid) {
+  if (!PRO && valid) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) raw[j] = src[(size_t)(DIRECT_IN ? addr(P_FIRST, j) : addr(0, j)) * astride];
   }
@@ -348,6 +351,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   const u64* S = nullptr;
   int ns = 0, jd = 0, tt = 0;
   u64 r0[FUSE == 1 ? 16 : 1];
+  (void)r0;
   // source a of slot blockIdx.y: limb offset, prime, and the two constants
   auto src_info = [&](int a, int& soff, int& spid, u64& c1, u64& c2) {
     if (f.pro == 1) {
@@ -362,7 +366,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       c2 = f.md->phat[a][blockIdx.y][0];
     }
   };
-  if constexpr (FUSE == 1) {
+  if constexpr (PRO) {
     const size_t zz = blockIdx.z;
     S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo + (size_t)blockIdx.x * 16 + v;
     if (f.pro == 3) {
@@ -375,8 +379,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     int soff = 0, spid;
     u64 c1, c2;
     if (f.pro != 3) src_info(0, soff, spid, c1, c2);
+    if constexpr (FUSE == 1) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
+      for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
+    }
   }
   // FUSE = 2: the epilogue's operands are requested here as well
   u64 mr[FUSE == 2 ? 16 : 1], ar[FUSE == 2 ? 16 : 1];
@@ -418,11 +424,63 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       tl[rr * 512 + 256 + slot] = WQ[g];
     }
   }
-  if constexpr (FUSE == 1) {
+  if constexpr (PRO) {
     // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
     // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
     // the bracket the exact residue in [0, m_a)); one limb: X mod q.
-    if (f.pro == 3) {
+    if constexpr (FUSE == 4) {
+      // Conjugate-invariant ring: the sources hold the inverse transform before
+      // its unfolding, b (coefficients modulo X^N - iota).  Word k and its
+      // mirror N - k are unfolded, c_k = (b_k + iota b_{N-k}) / 2 (c_0 = b_0),
+      // converted, and folded for the target prime, c'_k - iota' c'_{N-k}.
+      const u64* ct = f.ci + 4 * (size_t)m.prime[blockIdx.y];
+      const double it = (double)ct[0], itq = it / q;
+      double xm[16];
+      for (int a = 0; a < ns; ++a) {
+        int soff = 0, spid = f.src_pid;
+        u64 c1 = 1, c2 = 1;
+        if (f.pro != 3) src_info(a, soff, spid, c1, c2);
+        const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+        const u64* cs = f.ci + 4 * (size_t)spid;
+        const double is = (double)cs[0], isq = is / ms, h = (double)cs[2], hq = h / ms;
+        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
+        const u64* Sa = S - (size_t)blockIdx.x * 16 - v + (size_t)soff * N;   // start of the limb
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const size_t pk = (size_t)addr(0, j) * astride + (size_t)blockIdx.x * 16 + v;
+          const size_t pm = (N - pk) & (N - 1);
+          const double bk = u64_to_f(Sa[pk]), bm = u64_to_f(Sa[pm]);
+          auto unfold = [&](double u, double w) {   // (u + iota w) / 2, exact residue in [0, m)
+            double r = fmul_mod(__dadd_rn(u, fmul_mod(w, is, isq, ms)), h, hq, ms);
+            r = fred(r, msi, ms);
+            return r < 0.0 ? __dadd_rn(r, ms) : r;
+          };
+          const double ck = pk == 0 ? bk : unfold(bk, bm), cm = pk == 0 ? bk : unfold(bm, bk);
+          auto conv = [&](double cc) {                // [c q1]_m q2 mod q, |result| <= q
+            if (f.pro == 3) return fred(cc, qi, q);
+            double t1 = fred(fmul_mod(cc, c1d, c1q, ms), msi, ms);
+            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+            return fmul_mod(t1, c2d, c2q, q);
+          };
+          const double pk2 = conv(ck), pm2 = conv(cm);
+          x[j] = a == 0 ? pk2 : __dadd_rn(x[j], pk2);
+          xm[j] = a == 0 ? pm2 : __dadd_rn(xm[j], pm2);
+        }
+        if (a & 1) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            x[j] = fred(x[j], qi, q);
+            xm[j] = fred(xm[j], qi, q);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const size_t pk = (size_t)addr(0, j) * astride + (size_t)blockIdx.x * 16 + v;
+        const double xk = fred(x[j], qi, q), xmj = fred(xm[j], qi, q);
+        x[j] = pk == 0 ? xk : fred(__dsub_rn(xk, fmul_mod(xmj, it, itq, q)), qi, q);
+      }
+    } else if (f.pro == 3) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
     } else {
@@ -1349,7 +1407,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   }
 }
 
-bool fused_ok(const Ctx& c) { return c.log_n == 16 && !c.ci; }
+bool fused_ok(const Ctx& c) { return c.log_n == 16; }
 
 void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
   if (n == 0) return;
@@ -1364,7 +1422,8 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
   if (B <= 0 || m.n <= 0) return;
   if (f.pro < 1 || f.pro > 3 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
-      (f.pro == 2 && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)))
+      (f.pro == 2 && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) || (c.ci != (f.ci != nullptr)) ||
+      (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
     BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
   const int logn = 16, N = 1 << logn;
   LimbMap mo = m;
@@ -1384,8 +1443,12 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   {
     const double srcs = f.pro == 1 ? 2.0 : f.pro == 2 ? (double)c.K : 1.0;
     Prof pf(c, "ntt_fwd_col_fused", 8.0 * elems * (1.0 + srcs), 0.5 * elems * 8 + 2.0 * srcs * elems);
-    LAUNCH((k_ntt_fast<8, false, NTT_COL, 1>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
-           (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
+    if (f.ci)
+      LAUNCH((k_ntt_fast<8, false, NTT_COL, 4>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
+             (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
+    else
+      LAUNCH((k_ntt_fast<8, false, NTT_COL, 1>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
+             (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
     check_launch();
   }
   if (f.epi) {
@@ -1421,9 +1484,9 @@ void ntt_core(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
               const LimbMap& m, bool inverse);
 
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-         const LimbMap& m, bool inverse) {
+         const LimbMap& m, bool inverse, bool raw) {
   if (B <= 0 || m.n <= 0) return;
-  if (!c.ci) {
+  if (!c.ci || raw) {
     ntt_core(c, in, in_stride, out, out_stride, B, m, inverse);
     return;
   }
