@@ -38,7 +38,11 @@ ALU_PEAK_GMODMUL = 39.3216e3 / 8.0
 # a 1 GiB device copy: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE), kept with
 # the sha256 of the kernel source they were taken on and the workload; the
 # figure is reported only while both still match.
-TRAFFIC = {}
+TRAFFIC = {
+    ("kip_hoist", "k4_S2+levelmin+hoist"): dict(
+        bytes_per_launch=150694378, algorithmic_bytes_per_launch=180354359,
+        kernels_sha256="e297a5c026f48e18eb63b82bf9ef7eb573836f4ba761f10bf9113cb87b78ba26"),
+}
 
 
 def kernels_sha256():
@@ -70,6 +74,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel events")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
     ap.add_argument("--no-ci", action="store_true", help="skip the conjugate-invariant ring figure")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the compressed and conjugate-invariant figures (profiling runs)")
     ap.add_argument("--workload", default="face", choices=["face", "fingerprint", "batch", "serve", "copy"],
                     help="face: 6,144 x 128-dim (default); fingerprint: 1,048,576 x 16-dim; "
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
@@ -155,7 +161,7 @@ def main():
     # ---- the same match with the compression method: one result ciphertext
     # per c groups instead of one per group (what the client downloads)
     compressed = None
-    if not bs & bm.BM_COMPRESS:
+    if not bs & bm.BM_COMPRESS and not args.no_extras:
         cs = bs | bm.BM_COMPRESS
         bm.bm_result_free(run_once(bk, cs))
         torch.cuda.synchronize()
@@ -234,7 +240,8 @@ def main():
         f_hbm, f_alu = gbs / HBM_PEAK_GBS, gmm / ALU_PEAK_GMODMUL
         roof = dict(bound="hbm", kernel=name, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(f_hbm, 4), alu_gmodmul=round(gmm, 2), alu_frac=round(f_alu, 4),
-                    avg_us=round(avg_s * 1e6, 2), launches=e["launches"], traffic=None)
+                    avg_us=round(avg_s * 1e6, 2), launches=e["launches"],
+                    algorithmic_bytes_per_launch=int(bytes_per), traffic=None)
         roof["traffic"] = traffic_for(name, "k%d_%s" % (bk, sname(bs)), bytes_per)
         step_ms_dev = sum(v["ms"] for v in prof.values()) / args.steps
         roof["kernel_share"] = round(e["ms"] / args.steps / max(step_ms_dev, 1e-9), 3)
@@ -245,7 +252,7 @@ def main():
     # ---- the same workload in the conjugate-invariant ring (the paper's
     # setting: N real slots, so half the gallery ciphertexts)
     ci = None
-    if not args.no_ci:
+    if not args.no_ci and not args.no_extras:
         ci_scheds = sorted({s for s in scheds if s & bm.BM_LEVEL_MIN} or {bs})
         ci = ci_variant(bm, torch, X, q, d, ks, ci_scheds, w["known"], sptr, not args.eager, sname)
 
