@@ -278,3 +278,43 @@ def test_ci_match_face_scale_sampled(bm, schedule):
     bm.bm_gallery_free(gal)
     bm.bm_result_free(res)
     bm.bm_masks_free(lm)
+
+
+@pytest.mark.parametrize("d,k", [(16, 1), (16, 4)])
+def test_ci_enroll_small_ring_bit_exact(bm, d, k):
+    """Server-side enrollment (Sec. 3.2) in the conjugate-invariant ring at
+    N = 2^12 (T = N / c users per ciphertext): every stored word equals the
+    oracle's enrollment, and matching the enrolled gallery scores the users."""
+    from test_gpu_enroll import oracle_users
+    from workloads import normalize
+    P, okeys, ctx, sk, pk, evk = setup(3)
+    c, T = obm.layout(P, d, k)
+    G = 2
+    rng = np.random.default_rng(d + 7 * k)
+    ids = rng.permutation(np.concatenate([[0, T - 1, T, 2 * T - 1],
+                                          rng.choice(np.arange(1, 2 * T - 1), 40, replace=False)]))
+    ids = np.unique(ids)[rng.permutation(np.unique(ids).size)]
+    X = normalize(rng.standard_normal((ids.size, d))).astype(np.float64)
+    log("ci enroll N=2^12 d=%d k=%d users=%d" % (d, k, ids.size))
+    users_o = oracle_users(P, okeys, X, 9000)
+    emasks, escale = obm.enroll_mask_coeffs(P, d, k, len(P.q))
+    want = obm.enroll(P, okeys, users_o, ids, d, k, emasks, escale)
+    users = [bm.bm_ct_import(ctx, ct_words(u), P.scale) for u in users_o]
+    gal = bm.bm_gallery_create(ctx, d, k, G * T, len(P.q) - 1)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(emasks), escale)
+    bm.bm_enroll(ctx, evk, gal, users, ids, lm)
+    bm.bm_masks_free(lm)
+    words = bm.bm_gallery_export(ctx, gal, k, P.N)
+    for g in range(G):
+        for i in range(k):
+            assert_words_equal(words[g, i], ct_words(want[g][i]), "group %d part %d" % (g, i))
+    qv = normalize(X[2] + 0.01 * rng.standard_normal(d))
+    cq = bm.bm_encrypt_query(ctx, pk, qv, SEED, 3)
+    res = bm.bm_match(ctx, evk, cq, gal, None, schedule=2, out_limbs=0)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, G * T)
+    assert np.max(np.abs(scores[ids] - X @ qv.astype(np.float64))) < 1e-4
+    assert bm.bm_top1(scores)[0] == ids[2]
+    for h in users + [cq]:
+        bm.bm_ct_free(h)
+    bm.bm_result_free(res)
+    bm.bm_gallery_free(gal)

@@ -32,7 +32,7 @@ def oracle_users(P, okeys, X, id_base):
     for u, x in enumerate(X):
         z = np.zeros(P.n)
         z[:x.size] = x
-        out.append(ckks.encrypt(P, okeys.pk, ckks.encode(z, P.scale, P.N), len(P.q), P.scale, SEED,
+        out.append(ckks.encrypt(P, okeys.pk, ckks.encode(z, P.scale, P.N, P.ring), len(P.q), P.scale, SEED,
                                 id_base + u))
     return out
 
