@@ -304,9 +304,16 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   // Global address of view word a: base + a * astride.
   size_t base_in, base_out, astride;
   bool valid = true;
+  // FUSE = 4: block b takes columns 8b .. 8b+7 and their mirrors 256 - c, so
+  // that word k and word N - k of the polynomial sit in one block (columns 0
+  // and 128 are their own mirrors; block 0 takes 128 in place of 256 - 0)
+  auto ci_col = [&](int vv) {
+    const int b = blockIdx.x;
+    return vv < 8 ? 8 * b + vv : (vv == 8 && b == 0 ? 128 : 256 - (8 * b + vv - 8));
+  };
   if (KIND == NTT_COL) {
     astride = (size_t)(N >> LOGM);
-    const size_t col = (size_t)blockIdx.x * 16 + v;
+    const size_t col = FUSE == 4 ? (size_t)ci_col(v) : (size_t)blockIdx.x * 16 + v;
     base_in = (size_t)blockIdx.z * in_stride + (size_t)m.off[blockIdx.y] * N + col;
     base_out = (size_t)blockIdx.z * out_stride + (size_t)m.ooff[blockIdx.y] * N + col;
   } else if (KIND == NTT_ROW) {
@@ -368,7 +375,8 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   };
   if constexpr (PRO) {
     const size_t zz = blockIdx.z;
-    S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo + (size_t)blockIdx.x * 16 + v;
+    S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo +
+        (FUSE == 4 ? (size_t)ci_col(v) : (size_t)blockIdx.x * 16 + v);
     if (f.pro == 3) {
       ns = 1;
     } else {
@@ -430,12 +438,24 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     // the bracket the exact residue in [0, m_a)); one limb: X mod q.
     if constexpr (FUSE == 4) {
       // Conjugate-invariant ring: the sources hold the inverse transform before
-      // its unfolding, b (coefficients modulo X^N - iota).  Word k and its
-      // mirror N - k are unfolded, c_k = (b_k + iota b_{N-k}) / 2 (c_0 = b_0),
-      // converted, and folded for the target prime, c'_k - iota' c'_{N-k}.
+      // its unfolding, b (coefficients modulo X^N - iota).  Every word is
+      // unfolded with its mirror N - k, c_k = (b_k + iota b_{N-k}) / 2
+      // (c_0 = b_0), converted, and folded for the target prime,
+      // c'_k - iota' c'_{N-k}.  Mirrors sit in this block (see ci_col) and are
+      // read through LDS.
+      const int colv = ci_col(v);
+      const int vm = (colv == 0 || colv == 128) ? v : (v < 8 ? v + 8 : v - 8);   // mirror's view
+      auto mrow = [&](int a) { return colv == 0 ? (256 - a) & 255 : 255 - a; };  // mirror's row
+      auto mirror = [&](double* val, double* mv) {      // mv[j] = value at the mirror of word j
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(0, j))] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) mv[j] = sh[vm * VS + pad(mrow(addr(0, j)))];
+      };
       const u64* ct = f.ci + 4 * (size_t)m.prime[blockIdx.y];
       const double it = (double)ct[0], itq = it / q;
-      double xm[16];
       for (int a = 0; a < ns; ++a) {
         int soff = 0, spid = f.src_pid;
         u64 c1 = 1, c2 = 1;
@@ -444,41 +464,42 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         const u64* cs = f.ci + 4 * (size_t)spid;
         const double is = (double)cs[0], isq = is / ms, h = (double)cs[2], hq = h / ms;
         const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
-        const u64* Sa = S - (size_t)blockIdx.x * 16 - v + (size_t)soff * N;   // start of the limb
+        double b[16], bm[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) b[j] = u64_to_f(S[(size_t)soff * N + (size_t)addr(0, j) * astride]);
+        mirror(b, bm);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const size_t pk = (size_t)addr(0, j) * astride + (size_t)blockIdx.x * 16 + v;
-          const size_t pm = (N - pk) & (N - 1);
-          const double bk = u64_to_f(Sa[pk]), bm = u64_to_f(Sa[pm]);
-          auto unfold = [&](double u, double w) {   // (u + iota w) / 2, exact residue in [0, m)
-            double r = fmul_mod(__dadd_rn(u, fmul_mod(w, is, isq, ms)), h, hq, ms);
-            r = fred(r, msi, ms);
-            return r < 0.0 ? __dadd_rn(r, ms) : r;
-          };
-          const double ck = pk == 0 ? bk : unfold(bk, bm), cm = pk == 0 ? bk : unfold(bm, bk);
-          auto conv = [&](double cc) {                // [c q1]_m q2 mod q, |result| <= q
-            if (f.pro == 3) return fred(cc, qi, q);
+          const bool zero = colv == 0 && addr(0, j) == 0;
+          double cc = b[j];
+          if (!zero) {   // (b + iota b') / 2, exact residue in [0, m)
+            cc = fmul_mod(__dadd_rn(b[j], fmul_mod(bm[j], is, isq, ms)), h, hq, ms);
+            cc = fred(cc, msi, ms);
+            cc = cc < 0.0 ? __dadd_rn(cc, ms) : cc;
+          }
+          double p2;
+          if (f.pro == 3) {
+            p2 = fred(cc, qi, q);
+          } else {
             double t1 = fred(fmul_mod(cc, c1d, c1q, ms), msi, ms);
             t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
-            return fmul_mod(t1, c2d, c2q, q);
-          };
-          const double pk2 = conv(ck), pm2 = conv(cm);
-          x[j] = a == 0 ? pk2 : __dadd_rn(x[j], pk2);
-          xm[j] = a == 0 ? pm2 : __dadd_rn(xm[j], pm2);
+            p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
+          }
+          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
         }
         if (a & 1) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            x[j] = fred(x[j], qi, q);
-            xm[j] = fred(xm[j], qi, q);
-          }
+          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
         }
       }
 #pragma unroll
+      for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+      double xm[16];
+      mirror(x, xm);
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const size_t pk = (size_t)addr(0, j) * astride + (size_t)blockIdx.x * 16 + v;
-        const double xk = fred(x[j], qi, q), xmj = fred(xm[j], qi, q);
-        x[j] = pk == 0 ? xk : fred(__dsub_rn(xk, fmul_mod(xmj, it, itq, q)), qi, q);
+        const bool zero = colv == 0 && addr(0, j) == 0;
+        if (!zero) x[j] = fred(__dsub_rn(x[j], fmul_mod(xm[j], it, itq, q)), qi, q);
       }
     } else if (f.pro == 3) {
 #pragma unroll
