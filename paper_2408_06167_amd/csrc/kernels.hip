@@ -1286,8 +1286,10 @@ __global__ void k_move_idx(const u64* in, size_t si, u64* out, size_t so, const 
   for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < words; e += (size_t)gridDim.x * TPB) O[e] = I[e];
 }
 
+// one element per thread (the element-wise kernels loop with a grid stride,
+// so any grid is correct; small launches need every thread they can get)
 inline dim3 ew_grid(size_t N, int ys, int B) {
-  size_t bx = (N + TPB * 4 - 1) / (TPB * 4);
+  size_t bx = (N + TPB - 1) / TPB;
   if (bx == 0) bx = 1;
   return dim3((unsigned)bx, (unsigned)ys, (unsigned)B);
 }
