@@ -134,9 +134,7 @@ void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u
   if (nl < 1) BM_THROW(BM_ELEVEL, "expansion needs two limbs");
   const size_t ln = (size_t)l * N;
   DBuf pm(&c, (size_t)k * 2 * ln);
-  for (int comp = 0; comp < 2; ++comp)
-    kern::mul(c, q + comp * ln, 0, masks, (size_t)(c.L + 1) * N, pm.p() + comp * ln, 2 * ln, (int)k,
-              kern::chain_map(l));
+  kern::mul_ct_pt(c, q, 0, ln, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, (int)k, l);
   ev::rescale(c, pm.p(), (int)k, 2, l, out);
   std::vector<std::vector<long>> amounts;
   for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
@@ -154,9 +152,7 @@ void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* mask
   const u32 cc = d / k;
   // Mul(P) of the query by every mask, batched over the k masks
   DBuf pm(&c, (size_t)k * 2 * ln);
-  for (int comp = 0; comp < 2; ++comp)
-    kern::mul(c, q + comp * ln, 0, masks, (size_t)(c.L + 1) * N, pm.p() + comp * ln, 2 * ln, (int)k,
-           kern::chain_map(l));
+  kern::mul_ct_pt(c, q, 0, ln, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, (int)k, l);
   ev::rescale(c, pm.p(), (int)k, 2, l, out);
   // step t: part i adds Rot(., -c 2^t) when bit t of i is 0 and Rot(., +c 2^t)
   // otherwise; all k parts go in one batch, the sign chosen per element.

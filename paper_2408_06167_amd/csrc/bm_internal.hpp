@@ -375,6 +375,10 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
 // signed integer polynomial [N] -> residues in limbs of m (coefficient domain)
 void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
                 size_t src_stride, const LimbMap& m);
+// out[z][comp][l] = ct[z][comp][l] * pt[z][l], both components, chain limbs l < limbs
+// (ccs / ocs: component strides; sct = 0 broadcasts one ciphertext)
+void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out, size_t so,
+               size_t ocs, int B, int limbs);
 // out = a + b, a - b, a * b (general), per limb of m; strides per operand (0 = broadcast)
 void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
          int B, const LimbMap& m);

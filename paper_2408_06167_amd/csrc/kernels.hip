@@ -703,6 +703,19 @@ __global__ void k_mul(const u64* a, size_t sa, const u64* b, size_t sb, u64* o, 
   EW_LOOP O[i] = mul_mod(A[i], B[i], pr);
 }
 
+// out[z][comp][l] = ct[z][comp][l] * pt[z][l] over the chain limbs l < limbs,
+// both components in one launch (blockIdx.y = comp * limbs + l)
+__global__ void k_mul_ct_pt(const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out,
+                            size_t so, size_t ocs, int limbs, const PrimeC* P, int N) {
+  const int l = blockIdx.y % limbs, comp = blockIdx.y / limbs;
+  const PrimeC& pr = P[l];
+  const size_t bz = blockIdx.z;
+  const u64* A = ct + bz * sct + comp * ccs + (size_t)l * N;
+  const u64* Bp = pt + bz * spt + (size_t)l * N;
+  u64* O = out + bz * so + comp * ocs + (size_t)l * N;
+  EW_LOOP O[i] = mul_mod(A[i], Bp[i], pr);
+}
+
 __global__ void k_neg(const u64* a, size_t sa, u64* o, size_t so, LimbMap m, const PrimeC* P, int N) {
   EW_PROLOGUE
   const u64* A = a + bz * sa + loff;
@@ -1610,6 +1623,18 @@ void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
   Prof pf(c, "mul", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
   LAUNCH(k_mul, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out, size_t so,
+               size_t ocs, int B, int limbs) {
+  if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: mul_ct_pt limbs");
+  chk(ct, B, sct, 0, ccs + (size_t)limbs * c.N, "mul_ct_pt ciphertext");
+  chk(pt, B, spt, 0, (size_t)limbs * c.N, "mul_ct_pt plaintext");
+  chk(out, B, so, 0, ocs + (size_t)limbs * c.N, "mul_ct_pt output");
+  Prof pf(c, "mul", 8.0 * c.N * limbs * (4.0 * B + (sct ? 2.0 * B : 2.0)), 2.0 * c.N * B * limbs);
+  LAUNCH(k_mul_ct_pt, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, ct, sct, ccs, pt, spt, out, so, ocs, limbs,
+         c.d_primes, (int)c.N);
   check_launch();
 }
 
