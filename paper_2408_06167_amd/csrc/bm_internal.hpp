@@ -386,9 +386,6 @@ void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
          int B, const LimbMap& m);
 void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
          int B, const LimbMap& m);
-void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m);
-// o = a * R mod q (Montgomery form)
-void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m);
 // o_limb += s_limb * scalar[limb] (scalar per limb slot, Shoup pair list)
 void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2] device*/,
                  u64* o, size_t so, int B, const LimbMap& m);

@@ -716,19 +716,6 @@ __global__ void k_mul_ct_pt(const u64* ct, size_t sct, size_t ccs, const u64* pt
   EW_LOOP O[i] = mul_mod(A[i], Bp[i], pr);
 }
 
-__global__ void k_neg(const u64* a, size_t sa, u64* o, size_t so, LimbMap m, const PrimeC* P, int N) {
-  EW_PROLOGUE
-  const u64* A = a + bz * sa + loff;
-  u64* O = o + bz * so + loff;
-  EW_LOOP O[i] = A[i] ? q - A[i] : 0;
-}
-
-__global__ void k_to_mont(u64* a, size_t sa, LimbMap m, const PrimeC* P, int N) {
-  EW_PROLOGUE
-  u64* A = a + bz * sa + loff;
-  EW_LOOP A[i] = mont_mul(A[i], pr.r2, q, pr.qn);
-}
-
 // o += s * scal[slot] (scal holds a Shoup pair per limb slot)
 __global__ void k_axpy_scalar(const u64* s, size_t ss, const u64* scal, u64* o, size_t so,
                               LimbMap m, const PrimeC* P, int N) {
@@ -1635,23 +1622,6 @@ void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* p
   Prof pf(c, "mul", 8.0 * c.N * limbs * (4.0 * B + (sct ? 2.0 * B : 2.0)), 2.0 * c.N * B * limbs);
   LAUNCH(k_mul_ct_pt, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, ct, sct, ccs, pt, spt, out, so, ocs, limbs,
          c.d_primes, (int)c.N);
-  check_launch();
-}
-
-void neg(const Ctx& c, const u64* a, size_t sa, u64* o, size_t so, int B, const LimbMap& m) {
-  chk_map(c, a, B, sa, m, "neg a");
-  chk_map(c, o, B, so, m, "neg out");
-  Prof pf(c, "neg", 16.0 * c.N * B * m.n, (double)c.N * B * m.n);
-  LAUNCH(k_neg, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, o, so, m,
-                     c.d_primes, (int)c.N);
-  check_launch();
-}
-
-void to_mont(const Ctx& c, u64* a, size_t sa, int B, const LimbMap& m) {
-  chk_map(c, a, B, sa, m, "to_mont");
-  Prof pf(c, "to_mont", 16.0 * c.N * B * m.n, (double)c.N * B * m.n);
-  LAUNCH(k_to_mont, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, m,
-                     c.d_primes, (int)c.N);
   check_launch();
 }
 
