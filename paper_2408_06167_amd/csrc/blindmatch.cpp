@@ -237,6 +237,11 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
     }
     if (hoist) {
       if (!hs.empty()) {
+        // one query at the output level: the sum lands in the result directly
+        if (nq == 1 && rot_limbs == out_limbs) {
+          ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, out + g0 * oct);
+          continue;
+        }
         ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, b);
         std::swap(a, b);
       }
