@@ -204,7 +204,7 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
   const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
   const u64 Bg_max = std::min<u64>(per_q, G);
   const u64 Bmax = Bg_max * nq;
-  DBuf d3(&c, Bmax * 3 * ln), rl(&c, Bmax * 2 * ln);
+  DBuf d3(&c, Bmax * 3 * ln);
   DBuf acc(&c, Bmax * 2 * nln), acc2(&c, Bmax * 2 * nln);
   DBuf racc(rot_limbs < nl ? DBuf(&c, Bmax * 2 * rln) : DBuf());
   for (u64 g0 = 0; g0 < G; g0 += Bg_max) {
@@ -215,16 +215,14 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
       for (u32 i = 0; i < k; ++i) {
         kern::tensor(c, cu + (size_t)i * upart, cu_stride, Bg, ln, gbase + (size_t)i * gpart,
                      (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln, B, l, false);
-        ev::relin(c, d3.p(), B, l, rlk, rl.p());
         u64* dst = i == 0 ? acc.p() : acc2.p();
-        ev::rescale(c, rl.p(), B, 2, l, dst);
+        ev::relin_rescale(c, d3.p(), B, l, rlk, dst);
         if (i > 0) kern::add(c, acc.p(), nln, acc2.p(), nln, acc.p(), nln, 2 * B, kern::chain_map(nl));
       }
     } else if (schedule == BM_S2) {          // the k tensors summed in one pass
       kern::tensor(c, cu, cu_stride, Bg, ln, gbase, (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln,
                    B, l, false, (int)k, upart, gpart);
-      ev::relin(c, d3.p(), B, l, rlk, rl.p());
-      ev::rescale(c, rl.p(), B, 2, l, acc.p());
+      ev::relin_rescale(c, d3.p(), B, l, rlk, acc.p());
     } else {
       BM_THROW(BM_EINVAL, "unknown schedule");
     }

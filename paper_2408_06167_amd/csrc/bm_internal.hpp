@@ -145,8 +145,11 @@ struct ModDownTable {
 //   base + (z / div) * hi + (z % div) * lo + limb * N.
 struct FuseArgs {
   int pro = 0;   // 1: ModUp digit conversion (pair slots of the ModUpTable),
-                 // 2: ModDown conversion of the special limbs, 3: reduction of one limb
-  int epi = 0;   // 1: out = (minuend - x) w (+ addend) with w = wtab[2 slot]
+                 // 2: ModDown conversion of the special limbs, 3: reduction of one limb,
+                 // 4: relinearisation and rescale in one (ModDown conversion of the
+                 //    special limbs, the last chain limb reduced alongside)
+  int epi = 0;   // 1: out = (minuend - x) w (+ addend) with w = wtab[2 slot];
+                 // 2: out = (minuend wm + addend - x) w with wm = wmtab[2 slot]
   const ModUpTable* mu = nullptr;
   const ModDownTable* md = nullptr;
   const u64* src = nullptr;
@@ -165,6 +168,9 @@ struct FuseArgs {
   const u64* wtab = nullptr;
   const u64* ci = nullptr;       // conjugate-invariant ring: the per-prime fold constants
   int src_pid = -1;              // one-limb reduction: prime of the source limb
+  int last_off = -1;             // pro 4: limb offset (in a source component) of the last chain limb
+  int last_pid = -1;             // pro 4: its prime
+  const u64* wmtab = nullptr;    // epi 2: minuend multipliers
 };
 
 // ----------------------------------------------------------------- device memory
@@ -405,8 +411,10 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
 void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int limbs);
 // key inner product: u/w[t] = sum_j y[j][t] * key_j[t]   (y: [beta][ext])
 // batch element z uses key1 when bit `sel` of z is set, else key0
+// (dadd: P d added to the last chain limb of the outputs, see k_kip)
 void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
-         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs);
+         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs, const u64* dadd = nullptr,
+         size_t sd = 0, size_t dcs = 0);
 // ModDown base conversion: special limbs of u (coefficient) -> conv [l] (coefficient)
 void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs);
 // out = (u - conv) * P^{-1} (+ addend), both components

@@ -370,6 +370,70 @@ void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {
   key_switch(c, d + 2 * ln, 3 * ln, B, limbs, rlk, d, 3 * ln, d + ln, 3 * ln, out, 2 * ln);
 }
 
+// Relinearisation followed by the rescale, d [B][3][limbs][N] -> out
+// [B][2][limbs-1][N], with the same words as relin then rescale: the
+// relinearised component is (u - NTT(conv))P^-1 + d over Q_l, and the rescale
+// needs its last limb in the coefficient domain, which is
+// (y - conv_last)P^-1 for y = INTT(u + P d) at that limb.  So the key inner
+// product adds P d to the last limb, one inverse transform takes the special
+// limbs and that limb, and one fused forward transform computes
+// NTT(conv_i P^-1 + last) and finishes ((u P^-1 + d) - that) q_last^-1.
+void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {
+  if (!kern::fused_ok(c) || c.ci || limbs < 2) {
+    const size_t ln = (size_t)limbs * c.N;
+    DBuf rl(&c, (size_t)B * 2 * ln);
+    relin(c, d, B, limbs, rlk, rl.p());
+    rescale(c, rl.p(), B, 2, limbs, out);
+    return;
+  }
+  const size_t N = c.N, ln = (size_t)limbs * N;
+  const int nl = limbs - 1;
+  const ModUpTable& tb = c.h_modup[limbs];
+  const int ext = tb.ext;
+  const size_t sy = (size_t)tb.beta * ext * N, suw = (size_t)2 * ext * N;
+  DBuf y = modup_eval(c, d + 2 * ln, 3 * ln, B, limbs);
+  DBuf uw(&c, (size_t)B * suw);
+  kern::kip(c, y.p(), sy, d + 2 * ln, 3 * ln, rlk, rlk, 31, uw.p(), suw, B, limbs, d, 3 * ln, ln);
+  LimbMap mp{};
+  for (int comp = 0; comp < 2; ++comp) {
+    mp.prime[mp.n] = nl;
+    mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + nl;
+    ++mp.n;
+    for (int kk = 0; kk < c.K; ++kk) {
+      mp.prime[mp.n] = c.pid_special(kk);
+      mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
+      ++mp.n;
+    }
+  }
+  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true);
+  DBuf t(&c, (size_t)B * 2 * nl * N);
+  FuseArgs f;
+  f.pro = 4;
+  f.md = c.d_moddown;
+  f.src = uw.p();
+  f.s_div = f.e_div = 2;             // element 2 z + comp
+  f.s_hi = f.m_hi = suw;
+  f.s_lo = f.m_lo = (size_t)ext * N;
+  f.s_off0 = limbs;
+  f.last_off = nl;
+  f.last_pid = nl;
+  f.epi = 2;
+  f.mnd = uw.p();
+  f.wmtab = &c.d_moddown->pinv[0][0];
+  f.add0 = d;
+  f.a0_hi = 3 * ln;
+  f.add1 = d + ln;
+  f.a1_hi = 3 * ln;
+  f.out = out;
+  f.o_hi = (size_t)2 * nl * N;
+  f.o_lo = (size_t)nl * N;
+  f.wtab = c.d_rescale + (size_t)(limbs - 1) * (c.L + 1) * 2;
+  audit::check(uw.p(), (size_t)B * suw * sizeof(u64), "relin_rescale source");
+  audit::check(d, ((size_t)(B - 1) * 3 * ln + 2 * ln) * sizeof(u64), "relin_rescale addends");
+  audit::check(out, (size_t)B * 2 * nl * N * sizeof(u64), "relin_rescale output");
+  kern::ntt_fused(c, f, t.p(), (size_t)nl * N, 2 * B, kern::chain_map(nl));
+}
+
 void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
   if (limbs < 2) BM_THROW(BM_ELEVEL, "rescale needs at least two limbs");
   const size_t N = c.N;

@@ -22,6 +22,8 @@ void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* k
                  int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so);
 // d: [B][3][limbs][N] -> out [B][2][limbs][N]
 void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
+// relin followed by rescale (same words), in fewer launches at N = 2^16
+void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
 // in: [B][comps][limbs][N] -> out [B][comps][limbs-1][N]
 void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)

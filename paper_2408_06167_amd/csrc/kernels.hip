@@ -504,6 +504,51 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     } else if (f.pro == 3) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
+    } else if (f.pro == 4) {
+      // relinearisation and rescale in one (see relin_rescale): the special
+      // limbs of u and its last chain limb y = u + P d (coefficient domain)
+      // give last = (y - conv_last(u_P)) P^-1 mod q_last (exact residue), and
+      // the input word is conv_i(u_P) P^-1 + last mod q_i.
+      const ModDownTable& md = *f.md;
+      const int li = f.last_pid, ti = m.prime[blockIdx.y];
+      const double ql = (double)P[li].q, qli = __longlong_as_double((long long)P[li].pad[1]);
+      const double pl = (double)md.pinv[li][0], plq = pl / ql, pt = (double)md.pinv[ti][0], ptq = pt / q;
+      double cl[16], ci[16];
+      for (int a = 0; a < md.K; ++a) {
+        const int pid = md.pprime[a];
+        const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+        const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
+        const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
+        const u64* Sa = S + (size_t)(f.s_off0 + a) * N;
+        u64 r[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) r[j] = a == 0 ? r0[j] : Sa[(size_t)addr(0, j) * astride];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
+          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+          const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);   // each within q
+          cl[j] = a == 0 ? pL : __dadd_rn(cl[j], pL);
+          ci[j] = a == 0 ? pT : __dadd_rn(ci[j], pT);
+        }
+        if (a & 1) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            cl[j] = fred(cl[j], qli, ql);
+            ci[j] = fred(ci[j], qi, q);
+          }
+        }
+      }
+      const u64* Sl = S + (size_t)f.last_off * N;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double yl = u64_to_f(Sl[(size_t)addr(0, j) * astride]);
+        double last = fmul_mod(__dsub_rn(yl, fred(cl[j], qli, ql)), pl, plq, ql);
+        last = fred(last, qli, ql);
+        last = last < 0.0 ? __dadd_rn(last, ql) : last;                 // exact residue mod q_last
+        const double z = __dadd_rn(fmul_mod(fred(ci[j], qi, q), pt, ptq, q), fred(last, qi, q));
+        x[j] = fred(z, qi, q);
+      }
     } else {
       for (int a = 0; a < ns; ++a) {
         int soff, spid;
@@ -643,15 +688,30 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       if constexpr (FUSE == 2) {
         // out = (minuend - x) w (+ addend), all words exact residues
         const double wd = (double)f.wtab[2 * blockIdx.y], wq = wd / q;
+        if (f.epi == 2) {
+          // out = (minuend wm + addend - x) w
+          const double wm = (double)f.wmtab[2 * blockIdx.y], wmq = wm / q;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const int a = addr(0, j);
-          const double d = __dsub_rn(u64_to_f(mr[j]), u64_to_f(sh_raw[v * VS + pad(a)]));   // |d| < q
-          double r = fmul_mod(d, wd, wq, q);                                                 // |r| <= q
-          if (Ad) r = __dadd_rn(r, u64_to_f(ar[j]));
-          r = fred(r, qi, q);
-          r = r < 0.0 ? __dadd_rn(r, q) : r;
-          Oe[a] = f_to_u64(r);
+          for (int j = 0; j < 16; ++j) {
+            const int a = addr(0, j);
+            double r = fmul_mod(u64_to_f(mr[j]), wm, wmq, q);                            // |r| <= q
+            if (Ad) r = __dadd_rn(r, u64_to_f(ar[j]));
+            r = fred(__dsub_rn(r, u64_to_f(sh_raw[v * VS + pad(a)])), qi, q);
+            r = fred(fmul_mod(r, wd, wq, q), qi, q);
+            r = r < 0.0 ? __dadd_rn(r, q) : r;
+            Oe[a] = f_to_u64(r);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int a = addr(0, j);
+            const double d = __dsub_rn(u64_to_f(mr[j]), u64_to_f(sh_raw[v * VS + pad(a)]));   // |d| < q
+            double r = fmul_mod(d, wd, wq, q);                                                 // |r| <= q
+            if (Ad) r = __dadd_rn(r, u64_to_f(ar[j]));
+            r = fred(r, qi, q);
+            r = r < 0.0 ? __dadd_rn(r, q) : r;
+            Oe[a] = f_to_u64(r);
+          }
         }
       } else {
 #pragma unroll
@@ -872,9 +932,13 @@ __global__ void k_modup(const u64* xc, size_t sx, u64* y, size_t sy, const ModUp
 // key inner product over every extended slot t of the level:
 // u[t] = sum_j y_j[t] * b_j[key limb of t], w[t] likewise with a_j.  For the
 // digit's own slots y_j[t] is the input limb itself (evaluation domain).
+// With dadd, the last chain limb of each output gets P d added (P = the
+// special modulus, d the component's addend: dadd + z sd + comp dcs), the
+// form in which a relinearisation hands its last limb to the rescale.
 __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u64* key0,
                       const u64* key1, int sel, u64* uw, size_t suw, const ModUpTable* T,
-                      int key_limbs, int L1, const PrimeC* P, int N) {
+                      int key_limbs, int L1, const PrimeC* P, int N, const u64* dadd, size_t sd, size_t dcs,
+                      u64 pm, u64 pms) {
   const ModUpTable& tb = *T;
   const int t = blockIdx.y;
   const int ext = tb.ext;
@@ -899,8 +963,14 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
       su.add(v, key[((size_t)(2 * j) * key_limbs + kl) * N + i], qi, qd);
       sw.add(v, key[((size_t)(2 * j + 1) * key_limbs + kl) * N + i], qi, qd);
     }
-    U[i] = su.residue(qi, qd);
-    Wp[i] = sw.residue(qi, qd);
+    u64 ru = su.residue(qi, qd), rw = sw.residue(qi, qd);
+    if (dadd && t == tb.limbs - 1) {
+      const u64* D = dadd + bz * sd + (size_t)t * N;
+      ru = add_mod(ru, mul_shoup(D[i], pm, pms, q), q);
+      rw = add_mod(rw, mul_shoup(D[dcs + i], pm, pms, q), q);
+    }
+    U[i] = ru;
+    Wp[i] = rw;
   }
 }
 
@@ -1444,8 +1514,10 @@ void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
 void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m, bool f64_out) {
   if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
   if (B <= 0 || m.n <= 0) return;
-  if (f.pro < 1 || f.pro > 3 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
-      (f.pro == 2 && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) || (c.ci != (f.ci != nullptr)) ||
+  if (f.pro < 1 || f.pro > 4 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
+      ((f.pro == 2 || f.pro == 4) && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) ||
+      (f.epi == 2 && !f.wmtab) || (f.pro == 4 && (f.ci || f.last_pid < 0 || f.last_pid >= c.nprimes())) ||
+      (c.ci != (f.ci != nullptr)) ||
       (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
     BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
   const int logn = 16, N = 1 << logn;
@@ -1683,7 +1755,7 @@ void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int
 }
 
 void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
-         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs) {
+         const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs, const u64* dadd, size_t sd, size_t dcs) {
   const ModUpTable& tb = c.h_modup[limbs];
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
   chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "kip digits");
@@ -1693,8 +1765,16 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
   chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "kip output");
   Prof pf(c, "kip", 8.0 * c.N * tb.ext * ((double)B * tb.beta + 2.0 * tb.beta + 2.0 * B),
           2.0 * c.N * tb.ext * tb.beta * B);
+  u64 pm = 0, pms = 0;
+  if (dadd) {   // P mod q_{limbs-1}
+    chk(dadd, B, sd, 0, dcs + (size_t)limbs * c.N, "kip addend");
+    const u64 ql = c.primes[limbs - 1].q;
+    pm = 1;
+    for (int k = 0; k < c.K; ++k) pm = h_mulmod(pm, c.primes[c.pid_special(k)].q % ql, ql);
+    pms = h_shoup(pm, ql);
+  }
   LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown, key0, key1, sel,
-         uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N);
+         uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N, dadd, sd, dcs, pm, pms);
   check_launch();
 }
 
