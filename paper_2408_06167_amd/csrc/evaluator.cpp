@@ -379,7 +379,7 @@ void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {
 // limbs and that limb, and one fused forward transform computes
 // NTT(conv_i P^-1 + last) and finishes ((u P^-1 + d) - that) q_last^-1.
 void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {
-  if (!kern::fused_ok(c) || c.ci || limbs < 2) {
+  if (!kern::fused_ok(c) || limbs < 2) {
     const size_t ln = (size_t)limbs * c.N;
     DBuf rl(&c, (size_t)B * 2 * ln);
     relin(c, d, B, limbs, rlk, rl.p());
@@ -405,10 +405,11 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
       ++mp.n;
     }
   }
-  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true);
+  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
   DBuf t(&c, (size_t)B * 2 * nl * N);
   FuseArgs f;
   f.pro = 4;
+  f.ci = c.ci ? c.d_ci : nullptr;
   f.md = c.d_moddown;
   f.src = uw.p();
   f.s_div = f.e_div = 2;             // element 2 z + comp

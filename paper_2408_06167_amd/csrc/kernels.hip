@@ -456,40 +456,86 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       };
       const u64* ct = f.ci + 4 * (size_t)m.prime[blockIdx.y];
       const double it = (double)ct[0], itq = it / q;
-      for (int a = 0; a < ns; ++a) {
-        int soff = 0, spid = f.src_pid;
-        u64 c1 = 1, c2 = 1;
-        if (f.pro != 3) src_info(a, soff, spid, c1, c2);
+      // source limb at offset soff, prime spid: c_k = (b_k + iota b_{N-k}) / 2 (c_0 = b_0),
+      // exact residues in [0, m)
+      auto unfold = [&](int soff, int spid, double* cc) {
         const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
         const u64* cs = f.ci + 4 * (size_t)spid;
         const double is = (double)cs[0], isq = is / ms, h = (double)cs[2], hq = h / ms;
-        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
-        double b[16], bm[16];
+        double bm[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) b[j] = u64_to_f(S[(size_t)soff * N + (size_t)addr(0, j) * astride]);
-        mirror(b, bm);
+        for (int j = 0; j < 16; ++j) cc[j] = u64_to_f(S[(size_t)soff * N + (size_t)addr(0, j) * astride]);
+        mirror(cc, bm);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          const bool zero = colv == 0 && addr(0, j) == 0;
-          double cc = b[j];
-          if (!zero) {   // (b + iota b') / 2, exact residue in [0, m)
-            cc = fmul_mod(__dadd_rn(b[j], fmul_mod(bm[j], is, isq, ms)), h, hq, ms);
-            cc = fred(cc, msi, ms);
-            cc = cc < 0.0 ? __dadd_rn(cc, ms) : cc;
-          }
-          double p2;
-          if (f.pro == 3) {
-            p2 = fred(cc, qi, q);
-          } else {
-            double t1 = fred(fmul_mod(cc, c1d, c1q, ms), msi, ms);
-            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
-            p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
-          }
-          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+          if (colv == 0 && addr(0, j) == 0) continue;
+          double r = fmul_mod(__dadd_rn(cc[j], fmul_mod(bm[j], is, isq, ms)), h, hq, ms);
+          r = fred(r, msi, ms);
+          cc[j] = r < 0.0 ? __dadd_rn(r, ms) : r;
         }
-        if (a & 1) {
+      };
+      if (f.pro == 4) {
+        // relinearisation and rescale in one (as in the standard ring, below)
+        const ModDownTable& md = *f.md;
+        const int li = f.last_pid, ti = m.prime[blockIdx.y];
+        const double ql = (double)P[li].q, qli = __longlong_as_double((long long)P[li].pad[1]);
+        const double pl = (double)md.pinv[li][0], plq = pl / ql, pt = (double)md.pinv[ti][0], ptq = pt / q;
+        double cl[16], cc[16];
+        for (int a = 0; a < md.K; ++a) {
+          const int pid = md.pprime[a];
+          const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+          const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
+          const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
+          unfold(f.s_off0 + a, pid, cc);
 #pragma unroll
-          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+          for (int j = 0; j < 16; ++j) {
+            double t1 = fred(fmul_mod(cc[j], c1d, c1q, ms), msi, ms);
+            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+            const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);
+            cl[j] = a == 0 ? pL : __dadd_rn(cl[j], pL);
+            x[j] = a == 0 ? pT : __dadd_rn(x[j], pT);
+          }
+          if (a & 1) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              cl[j] = fred(cl[j], qli, ql);
+              x[j] = fred(x[j], qi, q);
+            }
+          }
+        }
+        unfold(f.last_off, li, cc);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double last = fmul_mod(__dsub_rn(cc[j], fred(cl[j], qli, ql)), pl, plq, ql);
+          last = fred(last, qli, ql);
+          last = last < 0.0 ? __dadd_rn(last, ql) : last;
+          x[j] = __dadd_rn(fmul_mod(fred(x[j], qi, q), pt, ptq, q), fred(last, qi, q));
+        }
+      } else {
+        for (int a = 0; a < ns; ++a) {
+          int soff = 0, spid = f.src_pid;
+          u64 c1 = 1, c2 = 1;
+          if (f.pro != 3) src_info(a, soff, spid, c1, c2);
+          const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+          const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
+          double cc[16];
+          unfold(soff, spid, cc);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            double p2;
+            if (f.pro == 3) {
+              p2 = fred(cc[j], qi, q);
+            } else {
+              double t1 = fred(fmul_mod(cc[j], c1d, c1q, ms), msi, ms);
+              t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+              p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
+            }
+            x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+          }
+          if (a & 1) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+          }
         }
       }
 #pragma unroll
@@ -1516,7 +1562,7 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   if (B <= 0 || m.n <= 0) return;
   if (f.pro < 1 || f.pro > 4 || !f.src || f.s_div < 1 || f.e_div < 1 || (f.pro == 1 && !f.mu) ||
       ((f.pro == 2 || f.pro == 4) && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) ||
-      (f.epi == 2 && !f.wmtab) || (f.pro == 4 && (f.ci || f.last_pid < 0 || f.last_pid >= c.nprimes())) ||
+      (f.epi == 2 && !f.wmtab) || (f.pro == 4 && (f.last_pid < 0 || f.last_pid >= c.nprimes() || f.last_off < 0)) ||
       (c.ci != (f.ci != nullptr)) ||
       (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
     BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
