@@ -1846,9 +1846,10 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   AutomArgs am{c0_in, c0_si, c0_out, c0_so, limbs, (int)(gx * limbs * B)};
   if (am.W % 8 != 0) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
   if (!h.per_elem && B > 1 && c.N % (2 * TPB) == 0) {
-    // shared amounts: elements grouped per thread and amounts per chunk sized to
-    // about 100 registers
-    const int ZB = tb.beta == 1 ? 4 : 2;
+    // shared amounts: elements grouped per thread and amounts per chunk (two
+    // elements a thread measured best at the face configuration; the group's
+    // second thread finds the key words in L2)
+    const int ZB = 2;
     const size_t Wz = (c.N / (2 * TPB)) * tb.ext * (size_t)((B + ZB - 1) / ZB);
     if (Wz % 8 != 0 || Wz + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
 #define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                          \
@@ -1856,7 +1857,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
          gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,      \
          accumulate ? 1 : 0, am)
     switch (tb.beta) {
-      case 1: KIP_HOIST_ZB(1, 4, 2); break;
+      case 1: KIP_HOIST_ZB(1, 2, 4); break;
       case 2: KIP_HOIST_ZB(2, 2, 2); break;
       case 3: KIP_HOIST_ZB(3, 2, 1); break;
       default: KIP_HOIST_ZB(4, 2, 1); break;
