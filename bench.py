@@ -40,8 +40,8 @@ ALU_PEAK_GMODMUL = 39.3216e3 / 8.0
 # figure is reported only while both still match.
 TRAFFIC = {
     ("kip_hoist", "k4_S2+levelmin+hoist"): dict(
-        bytes_per_launch=150528673, algorithmic_bytes_per_launch=180355072,
-        kernels_sha256="d8a72448485a0d57676a61860b469dd74f138e05b32210fa2ab426cfd4a0713d"),
+        bytes_per_launch=153587172, algorithmic_bytes_per_launch=180355072,
+        kernels_sha256="252d78937a8750ff363d5127cc2e26adebe75ca49be9aeffed5a5aeb774aac9d"),
 }
 
 
