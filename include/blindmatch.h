@@ -127,6 +127,33 @@ int bm_ctx_set_graphs(bm_ctx *ctx, int on);
 int bm_ctx_params(const bm_ctx *ctx, bm_params *out);
 /* Device memory currently held by the context's caching pool, in bytes. */
 int bm_ctx_pool_bytes(const bm_ctx *ctx, uint64_t *bytes);
+/* Route the context's device memory through a caller's allocator (for
+ * instance a framework's caching allocator), so that one allocator owns the
+ * card.  Every later block of the context's pool -- keys, ciphertexts,
+ * galleries, masks, results and match scratch -- comes from
+ * alloc_fn(bytes, user), which returns a device pointer on the context's
+ * device, aligned to at least 256 bytes, or NULL when it cannot (the pool then
+ * returns its cached blocks and asks once more; a second NULL makes the call
+ * that needed the memory fail with BM_ENOMEM).  A block goes back through
+ * free_fn(ptr, user) when the pool releases it: at bm_ctx_free, on a retry
+ * after a failed allocation, or when the allocator is changed; the device has
+ * finished all queued work by then, so the allocator may hand the block to
+ * other work at once.  The pool caches blocks by size between calls, so
+ * free_fn is not called when a handle is freed.
+ *
+ * The call waits for the context's stream, returns the pool's cached blocks
+ * to their allocators and applies to every block allocated afterwards; blocks
+ * in use keep the allocator they came from.  HIP graphs captured later and
+ * servers created later (whose lanes call the callbacks from their worker
+ * threads, which must then be safe to call from any thread) use it too.
+ * Both NULL restores hipMalloc; exactly one NULL is BM_EINVAL.  The context's
+ * constant tables (twiddles, base-conversion constants) are allocated by
+ * bm_ctx_create with hipMalloc and are not affected.  The callbacks and
+ * `user` must stay valid until the context and every handle made from it
+ * are freed.  Allocation can happen inside a HIP graph capture (relaxed
+ * mode) on the context's stream, so alloc_fn must not synchronise the device. */
+int bm_ctx_set_allocator(bm_ctx *ctx, void *(*alloc_fn)(size_t bytes, void *user),
+                         void (*free_fn)(void *ptr, void *user), void *user);
 
 /* Kernel timing for measurement.  bm_profile_enable(ctx, 1) clears the
  * counters and brackets every subsequent kernel launch of the context (and of

@@ -64,6 +64,7 @@ _SIGS = {
     "bm_ctx_set_group_chunk": (ctypes.c_int, [_P, _u32]),
     "bm_ctx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
+    "bm_ctx_set_allocator": (ctypes.c_int, [_P, _P, _P, _P]),
     "bm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_profile_dump": (ctypes.c_int, [_P, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
     "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
@@ -197,6 +198,7 @@ def bm_ctx_create(params, device=0):
 
 def bm_ctx_free(ctx):
     lib().bm_ctx_free(ctx)
+    _alloc_hooks.pop(ctx.value, None)
 
 
 def bm_ctx_params(ctx):
@@ -211,6 +213,46 @@ def bm_ctx_set_group_chunk(ctx, groups):
 
 def bm_ctx_set_graphs(ctx, on=True):
     _check(lib().bm_ctx_set_graphs(ctx, 1 if on else 0), "bm_ctx_set_graphs", ctx)
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+# context address -> every callback pair it was given; blocks keep the
+# allocator they came from, so all pairs stay alive until bm_ctx_free
+_alloc_hooks = {}
+
+
+def bm_ctx_set_allocator(ctx, alloc=None, free=None):
+    """Device memory of the context from alloc(nbytes) -> device address (0 when
+    it cannot), returned through free(address); both None restores hipMalloc.
+    An exception in a callback is printed and counts as a failed allocation."""
+    if alloc is None and free is None:
+        a = f = None
+    else:
+        def _a(n, _user, _fn=alloc):
+            return int(_fn(int(n)) or 0) if _fn else 0
+
+        def _f(ptr, _user, _fn=free):
+            if _fn:
+                _fn(int(ptr))
+        cbs = (_ALLOC_FN(_a), _FREE_FN(_f))
+        _alloc_hooks.setdefault(ctx.value, []).append(cbs)
+        a = ctypes.cast(cbs[0], ctypes.c_void_p) if alloc else None
+        f = ctypes.cast(cbs[1], ctypes.c_void_p) if free else None
+    _check(lib().bm_ctx_set_allocator(ctx, a, f, None), "bm_ctx_set_allocator", ctx)
+
+
+def torch_allocator(device=0):
+    """(alloc, free) over torch's caching allocator on `device` (current stream),
+    for bm_ctx_set_allocator."""
+    import torch
+
+    def alloc(n):
+        return torch.cuda.caching_allocator_alloc(n, device)
+
+    def free(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
 
 
 def bm_ctx_pool_bytes(ctx):

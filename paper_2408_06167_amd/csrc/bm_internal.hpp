@@ -48,6 +48,7 @@ hipError_t free(void* p);
 hipError_t memcpy(void* d, const void* s, size_t bytes, hipMemcpyKind k);
 hipError_t memcpy_async(void* d, const void* s, size_t bytes, hipMemcpyKind k, hipStream_t st);
 hipError_t stream_sync(hipStream_t s);
+hipError_t device_sync();
 hipError_t stream_create(hipStream_t* s);
 hipError_t stream_destroy(hipStream_t s);
 hipError_t set_device(int d);
@@ -191,20 +192,37 @@ struct Scoped {
 };
 }  // namespace audit
 
+// A caller's device allocator (bm_ctx_set_allocator).
+struct AllocHook {
+  void* (*alloc)(size_t bytes, void* user) = nullptr;
+  void (*free)(void* p, void* user) = nullptr;
+  void* user = nullptr;
+};
+
 // Caching allocator: blocks are recycled by exact size.  All work of a context
 // is ordered on one stream, so a block freed by the host can be handed to the
-// next request immediately (stream order protects pending readers).
+// next request immediately (stream order protects pending readers).  New
+// blocks come from the hook when one is set, else from hipMalloc; each block
+// goes back to the allocator it came from, after a device synchronisation
+// when that is the hook (hipFree synchronises by itself).
 class DevicePool {
  public:
-  explicit DevicePool(int device) : device_(device) {}
+  explicit DevicePool(int device, std::shared_ptr<const AllocHook> hook = nullptr)
+      : device_(device), hook_(std::move(hook)) {}
   ~DevicePool();
   void* alloc(size_t bytes);
   void release(void* p, size_t bytes);
   size_t bytes_held() const { return held_; }
   void trim();
+  // later blocks come from `hook` (null: hipMalloc); cached blocks are freed
+  void set_hook(std::shared_ptr<const AllocHook> hook);
 
  private:
+  void* new_block(size_t bytes);
+  void free_cached();   // caller holds mu_
   int device_;
+  std::shared_ptr<const AllocHook> hook_;
+  std::map<void*, std::shared_ptr<const AllocHook>> hooked_;   // block -> the hook that made it
   std::multimap<size_t, void*> free_;
   size_t held_ = 0;
   std::mutex mu_;
@@ -295,6 +313,7 @@ struct Ctx {
   hipStream_t stream = nullptr;    // current stream of this context
   hipStream_t own_stream = nullptr;
   std::unique_ptr<DevicePool> pool;
+  std::shared_ptr<const AllocHook> hook;   // caller's allocator for pools made from now on
   // device tables
   PrimeC* d_primes = nullptr;
   u64* d_tw = nullptr;             // [MAX_PRIMES][N] psi^{brv(k)} and Shoup companions

@@ -193,6 +193,27 @@ int bm_ctx_set_graphs(bm_ctx* ctx, int on) {
   });
 }
 
+int bm_ctx_set_allocator(bm_ctx* ctx, void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*),
+                         void* user) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx, BM_EINVAL, "NULL context");
+    REQUIRE((alloc_fn == nullptr) == (free_fn == nullptr), BM_EINVAL,
+            "give both allocator callbacks, or neither");
+    Ctx& c = ctx->c;
+    std::shared_ptr<const AllocHook> h;
+    if (alloc_fn) {
+      AllocHook a;
+      a.alloc = alloc_fn;
+      a.free = free_fn;
+      a.user = user;
+      h = std::make_shared<const AllocHook>(a);
+    }
+    HIP_OK(dev::stream_sync(c.stream));
+    c.hook = h;
+    c.pool->set_hook(h);
+  });
+}
+
 int bm_ctx_pool_bytes(const bm_ctx* ctx, uint64_t* bytes) {
   if (!ctx || !bytes) return BM_EINVAL;
   *bytes = ctx->c.pool->bytes_held();
@@ -962,7 +983,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   if (!e) {
     std::unique_ptr<GraphEntry> ne(new GraphEntry);
     ne->key = key;
-    ne->pool.reset(new DevicePool(c.device));
+    ne->pool.reset(new DevicePool(c.device, c.hook));
     std::swap(c.pool, ne->pool);          // scratch of the capture comes from the graph's pool
     hipGraph_t graph = nullptr;
     bool capturing = false;

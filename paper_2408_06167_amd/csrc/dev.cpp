@@ -50,6 +50,7 @@ hipError_t memcpy_async(void* d, const void* s, size_t bytes, hipMemcpyKind k, h
 }
 
 hipError_t stream_sync(hipStream_t s) { return dry() ? hipSuccess : hipStreamSynchronize(s); }
+hipError_t device_sync() { return dry() ? hipSuccess : hipDeviceSynchronize(); }
 
 hipError_t stream_create(hipStream_t* s) {
   if (dry()) {

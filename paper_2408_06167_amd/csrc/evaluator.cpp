@@ -43,10 +43,47 @@ void check(const void* p, size_t bytes, const char* what) {
 }  // namespace audit
 
 DevicePool::~DevicePool() {
+  std::lock_guard<std::mutex> g(mu_);
+  free_cached();
+}
+
+// Frees the cached blocks, each to the allocator it came from; a caller's
+// allocator may hand a block to other work at once, so the device finishes
+// what is queued first.
+void DevicePool::free_cached() {
+  bool synced = false;
   for (auto& kv : free_) {
-    audit::remove(kv.second);
-    (void)dev::free(kv.second);
+    void* p = kv.second;
+    audit::remove(p);
+    held_ -= kv.first;
+    auto h = hooked_.find(p);
+    if (h == hooked_.end()) {
+      (void)dev::free(p);
+      continue;
+    }
+    if (!synced) {
+      (void)dev::set_device(device_);
+      (void)dev::device_sync();
+      synced = true;
+    }
+    h->second->free(p, h->second->user);
+    hooked_.erase(h);
   }
+  free_.clear();
+}
+
+void* DevicePool::new_block(size_t bytes) {
+  if (hook_) {
+    void* p = hook_->alloc(bytes, hook_->user);
+    if (p) hooked_[p] = hook_;
+    return p;
+  }
+  void* p = nullptr;
+  if (dev::malloc(&p, bytes) != hipSuccess) {
+    (void)dev::last_error();
+    return nullptr;
+  }
+  return p;
 }
 
 void* DevicePool::alloc(size_t bytes) {
@@ -57,28 +94,13 @@ void* DevicePool::alloc(size_t bytes) {
     free_.erase(it);
     return p;
   }
-  void* p = nullptr;
-  struct Reg {
-    void*& p;
-    size_t b;
-    ~Reg() {
-      if (p) audit::add(p, b);
-    }
-  } reg{p, bytes};
-  if (dev::malloc(&p, bytes) != hipSuccess) {
-    (void)dev::last_error();
-    // release cached blocks and retry once
-    for (auto& kv : free_) {
-      audit::remove(kv.second);
-      (void)dev::free(kv.second);
-      held_ -= kv.first;
-    }
-    free_.clear();
-    if (dev::malloc(&p, bytes) != hipSuccess) {
-      (void)dev::last_error();
-      BM_THROW(BM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
+  void* p = new_block(bytes);
+  if (!p) {
+    free_cached();   // release cached blocks and retry once
+    p = new_block(bytes);
+    if (!p) BM_THROW(BM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
+  audit::add(p, bytes);
   held_ += bytes;
   return p;
 }
@@ -90,12 +112,13 @@ void DevicePool::release(void* p, size_t bytes) {
 
 void DevicePool::trim() {
   std::lock_guard<std::mutex> g(mu_);
-  for (auto& kv : free_) {
-    audit::remove(kv.second);
-    (void)dev::free(kv.second);
-    held_ -= kv.first;
-  }
-  free_.clear();
+  free_cached();
+}
+
+void DevicePool::set_hook(std::shared_ptr<const AllocHook> hook) {
+  std::lock_guard<std::mutex> g(mu_);
+  free_cached();
+  hook_ = std::move(hook);
 }
 
 DBuf::DBuf(Ctx* c, size_t words) : pool_(c->pool.get()), words_(words) {
@@ -185,7 +208,8 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   HIP_OK(dev::set_device(device));
   HIP_OK(dev::stream_create(&l->own_stream));
   l->stream = l->own_stream;
-  l->pool.reset(new DevicePool(device));
+  l->hook = hook;
+  l->pool.reset(new DevicePool(device, hook));
   return l;
 }
 

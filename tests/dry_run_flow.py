@@ -1,6 +1,7 @@
 """Drive the library's call sequences with BM_DRY_RUN=1 (no GPU): every kernel
 launch is checked against the buffers it would touch, none is executed.
 Run as a script by test_dry_run.py; exits non-zero on the first failure."""
+import ctypes
 import os
 import sys
 
@@ -12,9 +13,11 @@ assert os.environ.get("BM_DRY_RUN") == "1"
 import paper_2408_06167_amd as bm  # noqa: E402
 
 
-def flow(preset, shapes, n_templates):
+def flow(preset, shapes, n_templates, hook=None):
     p = bm.bm_params_preset(preset)
     ctx = bm.bm_ctx_create(p, 0)
+    if hook:
+        bm.bm_ctx_set_allocator(ctx, *hook)
     N, L1 = p.N, p.n_q
     rots = set()
     for d, k in shapes:
@@ -117,10 +120,72 @@ def flow(preset, shapes, n_templates):
         print("preset %d d=%d k=%d ok" % (preset, d, k), flush=True)
     for h in (a, b, t):
         bm.bm_ct_free(h)
+    bm.bm_sk_free(sk)
+    bm.bm_pk_free(pk)
+    bm.bm_evk_free(evk)
     bm.bm_ctx_free(ctx)
 
 
+class HostAllocator:
+    """Caller allocator over libc malloc (device memory is host memory in a dry
+    run) that records every block it hands out."""
+
+    def __init__(self):
+        self.libc = ctypes.CDLL(None)
+        self.libc.malloc.restype = ctypes.c_void_p
+        self.libc.malloc.argtypes = [ctypes.c_size_t]
+        self.libc.free.argtypes = [ctypes.c_void_p]
+        self.live, self.allocs, self.frees = {}, 0, 0
+
+    def alloc(self, n):
+        ptr = self.libc.malloc(n)
+        assert ptr not in self.live
+        self.live[ptr] = n
+        self.allocs += 1
+        return ptr
+
+    def free(self, ptr):
+        assert ptr in self.live, "block freed that this allocator did not hand out"
+        del self.live[ptr]
+        self.frees += 1
+        self.libc.free(ptr)
+
+
+def allocator_hook_flow():
+    # a whole flow (graphs, batches, enrollment, server lanes) on a caller's allocator
+    h = HostAllocator()
+    flow(1, [(16, 1), (16, 4)], 300, hook=(h.alloc, h.free))
+    assert h.allocs > 0 and h.frees == h.allocs and not h.live, (h.allocs, h.frees, len(h.live))
+    # switching allocators: blocks in use go back to the one they came from
+    h1, h2 = HostAllocator(), HostAllocator()
+    p = bm.bm_params_preset(1)
+    ctx = bm.bm_ctx_create(p, 0)
+    bm.bm_ctx_set_allocator(ctx, h1.alloc, h1.free)
+    sk, pk, evk = bm.bm_keygen(ctx, 1, bm.bm_rotations_for(16, 1))
+    held = bm.bm_ctx_pool_bytes(ctx)
+    assert h1.allocs > 0 and sum(h1.live.values()) == held, (sum(h1.live.values()), held)
+    bm.bm_ctx_set_allocator(ctx, h2.alloc, h2.free)
+    q = bm.bm_encrypt_query(ctx, pk, np.ones(16, dtype=np.float32), 1, 1)
+    assert h2.allocs > 0
+    bm.bm_ctx_set_allocator(ctx)           # back to the library's own allocation
+    g = bm.bm_encrypt_gallery(ctx, pk, np.ones((20, 16), dtype=np.float32), 1, 1, 10)
+    bm.bm_result_free(bm.bm_match(ctx, evk, q, g, None, schedule=1))
+    for f, x in ((bm.bm_gallery_free, g), (bm.bm_ct_free, q), (bm.bm_sk_free, sk), (bm.bm_pk_free, pk),
+                 (bm.bm_evk_free, evk)):
+        f(x)
+    try:
+        bm.bm_ctx_set_allocator(ctx, h1.alloc, None)
+        raise AssertionError("one missing callback accepted")
+    except bm.BMError as e:
+        assert e.code == bm.BM_EINVAL
+    bm.bm_ctx_free(ctx)
+    for h in (h1, h2):
+        assert h.frees == h.allocs and not h.live, (h.allocs, h.frees)
+    print("allocator hook ok", flush=True)
+
+
 if __name__ == "__main__":
+    allocator_hook_flow()
     flow(1, [(16, 1), (16, 2), (16, 4), (8, 8)], 300)
     flow(2, [(128, 1), (128, 4), (128, 16), (16, 1)], 5000)
     # conjugate-invariant ring (N real slots)
