@@ -207,6 +207,50 @@ def main():
     for r in results:
         bm.bm_result_free(r)
 
+    # ---- the same match with host buffers on both sides (never `value`): the
+    # query handed over from pinned host memory in the coefficient domain (the
+    # import runs its forward NTT), every result ciphertext copied back (the
+    # export runs the inverse NTT), each call synchronous
+    pcie = None
+    if not args.no_extras:
+        qwords, qscale = bm.bm_ct_export(ctx, q_ct, params.N)
+        hq = torch.from_numpy(qwords.view(np.int64)).pin_memory()
+        hq_np = hq.numpy().view(np.uint64)
+        r0 = run_once(bk, bs)
+        G, olimbs, _ = bm.bm_result_info(r0)
+        bm.bm_result_free(r0)
+        per = 2 * olimbs * params.N
+        hout = torch.empty((G, per), dtype=torch.int64).pin_memory()
+        L = bm.lib()
+
+        def pcie_once():
+            qc = bm.bm_ct_import(ctx, hq_np, qscale)
+            r = bm.bm_match(ctx, evk, qc, gals[bk], None, schedule=bs, out_limbs=0, stream=sptr)
+            for g in range(G):
+                st = L.bm_result_export(r, g, hout[g].data_ptr(), per)
+                if st != bm.BM_OK:
+                    raise bm.BMError(st, "bm_result_export", "")
+            bm.bm_result_free(r)
+            bm.bm_ct_free(qc)
+        for _ in range(2):
+            pcie_once()
+        torch.cuda.synchronize()
+        reps = 10
+        t = time.perf_counter()
+        for _ in range(reps):
+            pcie_once()
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t) * 1e3 / reps
+        got = hout.numpy().view(np.uint64)
+        r = run_once(bk, bs)
+        same = all(np.array_equal(got[g].reshape(2, olimbs, params.N), bm.bm_result_export(ctx, r, g, params.N)[0])
+                   for g in range(G))
+        bm.bm_result_free(r)
+        pcie = {"ms_per_match": round(pms, 3), "templates_per_s": round(n_tmpl / pms * 1e3, 1),
+                "h2d_bytes": int(qwords.nbytes), "d2h_bytes": int(hout.numel() * 8),
+                "host_memory": "pinned", "results_equal_resident_path": bool(same)}
+        print("# host buffers (PCIe-inclusive): %.3f ms/match" % pms, file=sys.stderr, flush=True)
+
     # ---- per-kernel times: the same steps once more, launched eagerly with a
     # HIP event pair around every kernel on its stream (a graph replay cannot
     # be bracketed kernel by kernel)
@@ -257,9 +301,14 @@ def main():
         ci = ci_variant(bm, torch, X, q, d, ks, ci_scheds, w["known"], sptr, not args.eager, sname)
 
     # ---- CPU oracle on a bounded sample (one gallery group, same k and schedule)
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline(bk, bs, X, q, d)
+        print("# cpu oracle (all threads): %s templates/s" % cpu["value"], file=sys.stderr, flush=True)
+        if not args.no_extras:
+            cpu1 = cpu_single_thread(bk, bs, d)
+            print("# cpu oracle (one thread): %s templates/s" % (cpu1 or {}).get("value"),
+                  file=sys.stderr, flush=True)
 
     out = {
         "metric": "encrypted templates scored/s (N=2^16, 128-dim); p50/p99 query latency",
@@ -289,6 +338,8 @@ def main():
             "launch": "eager" if args.eager else "hip_graph",
             "eager_profiled_ms_per_step": round(eager_ms, 3) if eager_ms else None,
             "conjugate_invariant_ring": ci,
+            "host_buffers_pcie_inclusive": pcie,
+            "cpu_oracle_single_thread": cpu1,
             "paper_context": "Lattigo CPU, N=8192 real slots, 3 clusters x 2 Xeon Gold 5220 cores: "
                              "6144 x 128-dim matched in 451.67 ms (13,603 templates/s)",
         },
@@ -400,6 +451,25 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
     return dict(value=round(done / dt, 1), unit="templates/s", cores=cores, kind="oracle",
                 sample="%d of %d templates (%d of %d groups, k=%d, schedule %#x, one expansion), %.1fs of oracle time"
                        % (done, X.shape[0], g + 1, len(groups), k, schedule, dt))
+
+
+def cpu_single_thread(k, schedule, d):
+    """The oracle sample on one host thread: a child process, because OpenMP
+    takes its thread count when the oracle's library is loaded."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; from workloads import face_gallery; "
+            "w = face_gallery(seed=2, d=%d, n=6144); "
+            "print(json.dumps(bench.cpu_baseline(%d, %d, w['gallery'], w['query_known'], %d, budget_s=1.0)))"
+            % (ROOT, d, k, schedule, d))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=900)
+    except subprocess.TimeoutExpired:
+        return None
+    if r.returncode != 0:
+        print("# single-thread oracle failed: " + r.stderr[-500:], file=sys.stderr, flush=True)
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 if __name__ == "__main__":
