@@ -287,6 +287,10 @@ def main():
                     avg_us=round(avg_s * 1e6, 2), launches=e["launches"],
                     algorithmic_bytes_per_launch=int(bytes_per), traffic=None)
         roof["traffic"] = traffic_for(name, "k%d_%s" % (bk, sname(bs)), bytes_per)
+        # the same kind of arithmetic at its measured register-resident rate
+        mrate = measured_butterfly_rate(bm, ctx, params)
+        roof["alu_measured_peak_gmodmul"] = round(mrate, 1)
+        roof["alu_frac_measured"] = round(gmm / mrate, 4)
         step_ms_dev = sum(v["ms"] for v in prof.values()) / args.steps
         roof["kernel_share"] = round(e["ms"] / args.steps / max(step_ms_dev, 1e-9), 3)
         breakdown = {n: round(v["ms"] / args.steps, 3) for n, v in sorted(prof.items(), key=lambda x: -x[1]["ms"])}
@@ -451,6 +455,18 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
     return dict(value=round(done / dt, 1), unit="templates/s", cores=cores, kind="oracle",
                 sample="%d of %d templates (%d of %d groups, k=%d, schedule %#x, one expansion), %.1fs of oracle time"
                        % (done, X.shape[0], g + 1, len(groups), k, schedule, dt))
+
+
+def measured_butterfly_rate(bm, ctx, params, blocks=2048, iters=4096):
+    """G butterflies/s of the library's register-resident probe (8 independent
+    FP64 butterfly chains per thread, folded every second round as in the NTT)
+    on the first chain prime: the ALU ceiling actually reachable with this
+    arithmetic, beside the one derived from unit counts."""
+    q = params.chain()[0]
+    seed = np.random.default_rng(0x5EED).integers(0, q, size=24, dtype=np.uint64)
+    bm.bm_bench_modmul(ctx, 0, blocks, 64, seed)          # warm-up
+    ms = min(bm.bm_bench_modmul(ctx, 0, blocks, iters, seed)[0] for _ in range(3))
+    return blocks * 256 * 8 * iters / (ms * 1e-3) / 1e9
 
 
 def cpu_single_thread(k, schedule, d):

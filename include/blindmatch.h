@@ -166,6 +166,24 @@ int bm_ctx_set_allocator(bm_ctx *ctx, void *(*alloc_fn)(size_t bytes, void *user
 int bm_profile_enable(bm_ctx *ctx, int on);
 int bm_profile_dump(bm_ctx *ctx, char *buf, size_t cap, size_t *needed);
 
+/* Issue-rate probe of the arithmetic every transform and key product is made
+ * of, for the ALU side of the roofline.  Launches `blocks` x 256 threads on
+ * the context's own stream; each thread runs 8 independent chains of `iters`
+ * forward butterflies mod prime `prime` (chain primes first, then special
+ * primes), (u, v) <- (u + v w, u - v w), in the FP64 form the NTT uses (the
+ * product a w - rint(a w/q) q with its exact low half, values folded back
+ * after every second round), all in registers.  Thread x starts chain j from
+ * u = (seed[j] + x) mod q and v = (seed[8 + j] + 3 x) mod q, with twiddle
+ * w = seed[16 + j]; seed holds 24 residues of that prime.  *ms receives the
+ * kernel time from HIP events around the launch (the call waits for it), so
+ * the rate is blocks * 256 * 8 * iters modular products per *ms.  The first
+ * n_words of the output (thread x's 8 (u, v) pairs as residues in [0, q) at
+ * words[16 x ...]) are copied to `words` for checking the arithmetic; n_words
+ * may be 0.  BM_EINVAL: prime out of range, blocks outside 1..65536, iters odd
+ * or outside 2..2^24, a seed word >= q, n_words above blocks * 256 * 16. */
+int bm_bench_modmul(bm_ctx *ctx, uint32_t prime, uint32_t blocks, uint32_t iters, const uint64_t *seed,
+                    uint64_t *words, size_t n_words, double *ms);
+
 /* ------------------------------------------------------------------ keys */
 
 /* Key set of Sec. 3.1 (public key for clients, evaluation key for the

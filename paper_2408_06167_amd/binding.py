@@ -65,6 +65,7 @@ _SIGS = {
     "bm_ctx_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_ctx_pool_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_u64)]),
     "bm_ctx_set_allocator": (ctypes.c_int, [_P, _P, _P, _P]),
+    "bm_bench_modmul": (ctypes.c_int, [_P, _u32, _u32, _u32, _P, _P, _sz, ctypes.POINTER(_dbl)]),
     "bm_profile_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "bm_profile_dump": (ctypes.c_int, [_P, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)]),
     "bm_keygen": (ctypes.c_int, [_P, _u64, _P, _sz, _PP, _PP, _PP]),
@@ -263,6 +264,18 @@ def bm_ctx_pool_bytes(ctx):
 
 def bm_profile_enable(ctx, on=True):
     _check(lib().bm_profile_enable(ctx, 1 if on else 0), "bm_profile_enable", ctx)
+
+
+def bm_bench_modmul(ctx, prime, blocks, iters, seed, n_words=0):
+    """(kernel ms, first n_words output words) of the butterfly issue-rate probe."""
+    sd = np.ascontiguousarray(seed, dtype=np.uint64)
+    if sd.shape != (24,):
+        raise ValueError("seed must hold 24 residues")
+    w = np.zeros(max(int(n_words), 1), dtype=np.uint64)
+    ms = _dbl()
+    _check(lib().bm_bench_modmul(ctx, int(prime), int(blocks), int(iters), _ptr(sd), _ptr(w), int(n_words),
+                                 ctypes.byref(ms)), "bm_bench_modmul", ctx)
+    return float(ms.value), w[:int(n_words)]
 
 
 def bm_profile_dump(ctx):

@@ -389,6 +389,8 @@ void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_str
 // in place: residue words (< 2^52) <-> the bit patterns of the same values as
 // FP64 numbers (the form switching keys are kept in)
 void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);
+// register-resident issue-rate probe of the FP64 butterfly (k_modmul_rate)
+void modmul_rate(const Ctx& c, int pid, int blocks, int iters, const u64* seed, u64* out);
 // whether ntt_fused serves this context (N = 2^16)
 bool fused_ok(const Ctx& c);
 // forward NTT of the words f's prologue computes, into tmp at the slots m.ooff

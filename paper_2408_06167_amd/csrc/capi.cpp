@@ -250,6 +250,39 @@ int bm_profile_dump(bm_ctx* ctx, char* buf, size_t cap, size_t* needed) {
   });
 }
 
+int bm_bench_modmul(bm_ctx* ctx, uint32_t prime, uint32_t blocks, uint32_t iters, const uint64_t* seed,
+                    uint64_t* words, size_t n_words, double* ms) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && seed && ms, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    REQUIRE((int)prime < c.nprimes(), BM_EINVAL, "prime index out of range");
+    REQUIRE(blocks >= 1 && blocks <= 65536, BM_EINVAL, "blocks must lie in 1..65536");
+    REQUIRE(iters >= 2 && iters % 2 == 0 && iters <= (1u << 24), BM_EINVAL, "iters must be even, 2..2^24");
+    const size_t nw = (size_t)blocks * 256 * 16;
+    REQUIRE(n_words <= nw && (words || !n_words), BM_EINVAL, "n_words above the probe's output");
+    for (int j = 0; j < 24; ++j) REQUIRE(seed[j] < c.primes[prime].q, BM_EINVAL, "seed words must be residues");
+    c.use_stream(nullptr);
+    DBuf sd(&c, 24), out(&c, nw);
+    HIP_OK(dev::memcpy(sd.p(), seed, 24 * sizeof(u64), hipMemcpyHostToDevice));
+    struct Ev {
+      hipEvent_t e = nullptr;
+      ~Ev() {
+        if (e) (void)dev::event_destroy(e);
+      }
+    } e0, e1;
+    HIP_OK(dev::event_create(&e0.e, true));
+    HIP_OK(dev::event_create(&e1.e, true));
+    HIP_OK(dev::event_record(e0.e, c.stream));
+    kern::modmul_rate(c, (int)prime, (int)blocks, (int)iters, sd.p(), out.p());
+    HIP_OK(dev::event_record(e1.e, c.stream));
+    HIP_OK(dev::event_sync(e1.e));
+    float t = 0.f;
+    HIP_OK(dev::event_elapsed(&t, e0.e, e1.e));
+    *ms = t;
+    if (n_words) HIP_OK(dev::memcpy(words, out.p(), n_words * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
 // ------------------------------------------------------------------ keys
 
 int bm_rotations_for(uint32_t d, uint32_t k, int32_t* out, size_t cap, size_t* n) {

@@ -250,6 +250,52 @@ struct FAcc {
   }
 };
 
+// Issue-rate probe of the butterfly arithmetic above, register-resident: each
+// thread runs 8 independent chains of forward butterflies (u, v) <- (u + t,
+// u - t), t = fmul_mod(v, w), and folds both values back with fred after
+// every second round, as the NTT passes do.  Values stay below 2.2 q < 2^53.
+// Thread x starts chain j from u = (seed[j] + x) mod q, v = (seed[8 + j] + 3x)
+// mod q with twiddle w = seed[16 + j] < q, and stores its 8 final (u, v) pairs
+// as residues in [0, q) at out[16 x ...].
+__global__ void __launch_bounds__(256) k_modmul_rate(const PrimeC* __restrict__ P, int pid, int iters,
+                                                     const u64* __restrict__ seed, u64* __restrict__ out) {
+  const PrimeC& pr = P[pid];
+  const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
+  const u64 x = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  double u[8], v[8], w[8], wq[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    u[j] = u64_to_f((seed[j] + x) % pr.q);
+    v[j] = u64_to_f((seed[8 + j] + 3 * x) % pr.q);
+    w[j] = u64_to_f(seed[16 + j]);
+    wq[j] = w[j] / q;
+  }
+  for (int it = 0; it < iters; it += 2) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double t = fmul_mod(v[j], w[j], wq[j], q);
+        const double a = __dadd_rn(u[j], t);
+        v[j] = __dsub_rn(u[j], t);
+        u[j] = a;
+      }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      u[j] = fred(u[j], qi, q);
+      v[j] = fred(v[j], qi, q);
+    }
+  }
+  u64* o = out + 16 * x;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double a = u[j] < 0.0 ? __dadd_rn(u[j], q) : u[j];
+    const double b = v[j] < 0.0 ? __dadd_rn(v[j], q) : v[j];
+    o[2 * j] = f_to_u64(a);
+    o[2 * j + 1] = f_to_u64(b);
+  }
+}
+
 enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 
 // FUSE = 1: forward column pass whose input words come from f's prologue;
@@ -1544,6 +1590,16 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     row(in, in_stride, out, out_stride, m);
     col(out, out_stride, out, out_stride, m_out, 1);
   }
+}
+
+void modmul_rate(const Ctx& c, int pid, int blocks, int iters, const u64* seed, u64* out) {
+  if (pid < 0 || pid >= c.nprimes() || blocks < 1 || iters < 2 || (iters & 1))
+    BM_THROW(BM_EINVAL, "launch check: modmul probe arguments");
+  chk(seed, 1, 0, 0, 24, "modmul probe seed");
+  chk(out, 1, 0, 0, (size_t)blocks * 256 * 16, "modmul probe output");
+  Prof pf(c, "modmul_probe", 0.0, 8.0 * 256 * blocks * iters);
+  LAUNCH(k_modmul_rate, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.d_primes, pid, iters, seed, out);
+  check_launch();
 }
 
 bool fused_ok(const Ctx& c) { return c.log_n == 16; }

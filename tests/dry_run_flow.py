@@ -18,6 +18,8 @@ def flow(preset, shapes, n_templates, hook=None):
     ctx = bm.bm_ctx_create(p, 0)
     if hook:
         bm.bm_ctx_set_allocator(ctx, *hook)
+    # the butterfly issue-rate probe, all of its output copied back
+    bm.bm_bench_modmul(ctx, p.n_q, 2, 4, np.arange(24, dtype=np.uint64), 2 * 256 * 16)
     N, L1 = p.N, p.n_q
     rots = set()
     for d, k in shapes:
