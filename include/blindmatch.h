@@ -43,7 +43,7 @@ extern "C" {
 enum {
   BM_OK = 0,
   BM_EINVAL = -1,   /* NULL handle or pointer, size mismatch, bad argument */
-  BM_EDIM = -2,     /* d or k not a power of two, k does not divide d, d > n */
+  BM_EDIM = -2,     /* d or k not a power of two, k does not divide d, d > n, query d != gallery d */
   BM_ELEVEL = -3,   /* too few limbs for the operation, or a level mismatch */
   BM_ESCALE = -4,   /* Add of ciphertexts whose scales differ */
   BM_ENOKEY = -5,   /* a needed Galois key is missing from the evaluation key */
@@ -342,8 +342,10 @@ int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *ma
  * then log2(d/k) steps acc += Rot(acc, 2^t).  The score of template g T + b is
  * at slot b c of group g.  The query needs at least the gallery's limbs
  * (k = 1) or one more (k > 1); a higher query is cut exactly.  `masks` may
- * be NULL (the library's own masks are used).  out_limbs: 0 = context default, otherwise an exact level drop of
- * each result.  Asynchronous on `stream`.
+ * be NULL (the library's own masks are used).  out_limbs: 0 = context
+ * default, otherwise an exact level drop of each result to that many limbs (a
+ * value at or above the result's natural level keeps the natural level).
+ * Asynchronous on `stream`.
  * schedule | BM_LEVEL_MIN: every input is first cut by exact limb drops to
  * the level the rest needs -- the products at 3 chain limbs (gallery read in
  * place, query cut to 3 limbs, or 4 before Alg. 1 with masks at scale q_3),
@@ -366,7 +368,9 @@ int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *ma
  * rotate-and-add steps become the sum of the c - 1 rotations 1 .. c-1 of
  * the accumulator, and Alg. 1's log2 k steps of part i the sum over the
  * non-empty subsets S of its steps of Rot(C_i, sum_{t in S} -+c 2^t).
- * Same message, other bits; keys of bm_rotations_hoisted. */
+ * Same message, other bits; keys of bm_rotations_hoisted.
+ * BM_EDIM: the query came from bm_encrypt_query with another d than the
+ * gallery's (an imported query carries no d and is not checked). */
 int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g,
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);
@@ -411,8 +415,10 @@ int bm_server_create(bm_ctx *ctx, const bm_evk *evk, uint64_t hbm_budget_bytes,
                      uint32_t schedule, bm_server **out);
 /* Ownership of the gallery moves to the server. */
 int bm_server_add_gallery(bm_server *s, bm_gallery *g, uint32_t *gallery_id);
-/* Ownership of the query moves to the server.  BM_EBUDGET if the request can
- * never fit the budget. */
+/* Ownership of the query moves to the server when the call returns BM_OK
+ * (on an error the caller keeps it).  BM_EBUDGET if the request can never fit
+ * the budget, BM_EDIM for a query encrypted for another d than the gallery,
+ * BM_ELEVEL for a query below the level the match needs. */
 int bm_server_submit(bm_server *s, uint32_t gallery_id, bm_ct *q, uint64_t *ticket);
 /* *out = NULL while the request is pending; then the result (caller frees).
  * Status of a failed request is returned once. */

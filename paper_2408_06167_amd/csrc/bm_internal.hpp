@@ -475,6 +475,7 @@ struct bm_ct {
   bm::DBuf buf;            // [comps][limbs][N], evaluation domain
   uint32_t comps = 2, limbs = 0;
   double scale = 1.0;
+  uint32_t query_d = 0;    // d of a bm_encrypt_query packing; 0 when not known
 };
 
 struct bm_sk {

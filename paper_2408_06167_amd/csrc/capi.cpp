@@ -505,6 +505,7 @@ int bm_encrypt_query(bm_ctx* ctx, const bm_pk* pk, const float* q, uint32_t d, u
     std::unique_ptr<bm_ct> ct(new_ct(ctx, 2, c.L + 1, c.scale));
     ev::encrypt_batch(c, pk, m.data(), 1, c.L + 1, seed, &ct_id, ct->buf.p());
     sync(c);
+    ct->query_d = d;
     *out = ct.release();
   });
 }
@@ -972,6 +973,7 @@ using bmx::Plan;
 static Plan match_shape(const Ctx& c, const bm_ct* q, const bm_gallery* g, uint32_t schedule,
                         uint32_t out_limbs) {
   REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
+  REQUIRE(!q->query_d || q->query_d == g->d, BM_EDIM, "query packed for another dimension than the gallery");
   const Plan s = bmx::plan(c, schedule, g->k, (int)g->limbs, out_limbs);
   // the query is cut exactly to ql limbs: the gallery's level (k = 1) or one
   // above it (k > 1), lower under the minimum-level schedule
@@ -1131,6 +1133,7 @@ static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, 
     const bm_ct* q = qs[j];
     REQUIRE(q->comps == 2 && q->limbs == qs[0]->limbs && q->scale == qs[0]->scale, BM_ELEVEL,
             "queries of one gallery differ in level or scale");
+    REQUIRE(!q->query_d || q->query_d == g->d, BM_EDIM, "query packed for another dimension than the gallery");
     if (k == 1) {
       ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.t, cu.p() + j * cu_stride);
       cu_scale = q->scale;

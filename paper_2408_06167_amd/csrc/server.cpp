@@ -292,6 +292,7 @@ int bm_server_submit(bm_server* s, uint32_t gallery_id, bm_ct* q, uint64_t* tick
   if (gallery_id >= s->galleries.size()) return BM_EINVAL;
   const bm_gallery& g = *s->galleries[gallery_id].g;
   if (s->estimate(g, 1) > s->budget) return BM_EBUDGET;
+  if (q->query_d && q->query_d != g.d) return BM_EDIM;
   if ((int)q->limbs < s->shape(g).ql || q->comps != 2) return BM_ELEVEL;
   bm_server::Req r;
   r.ticket = s->next_ticket++;

@@ -186,7 +186,71 @@ def allocator_hook_flow():
     print("allocator hook ok", flush=True)
 
 
+def input_checks():
+    """Host-side rejection of inputs the method cannot take, each with the
+    status the header states."""
+    p = bm.bm_params_preset(1)
+    ctx = bm.bm_ctx_create(p, 0)
+    sk, pk, evk = bm.bm_keygen(ctx, 1, bm.bm_rotations_for(16, 1))
+
+    def status(f):
+        try:
+            f()
+        except bm.BMError as e:
+            return e.code
+        return bm.BM_OK
+    X = np.ones((10, 16), dtype=np.float32)
+    one = lambda d: np.ones(d, dtype=np.float32)   # noqa: E731
+    q16 = bm.bm_encrypt_query(ctx, pk, one(16), 1, 1)
+    q8 = bm.bm_encrypt_query(ctx, pk, one(8), 1, 2)
+    g = bm.bm_encrypt_gallery(ctx, pk, X, 1, 1, 10)
+    w = np.zeros((2, p.n_q, p.N), dtype=np.uint64)
+    a = bm.bm_ct_import(ctx, w, p.scale)
+    b = bm.bm_ct_import(ctx, w, 2 * p.scale)
+    c2 = bm.bm_ct_import(ctx, w[:, :2], p.scale)
+    c1 = bm.bm_ct_import(ctx, w[:, :1], p.scale)
+    r = bm.bm_match(ctx, evk, q16, g, None, schedule=1)
+    cases = [
+        ("empty gallery", lambda: bm.bm_encrypt_gallery(ctx, pk, np.ones((0, 16), dtype=np.float32), 1, 1, 10),
+         bm.BM_EINVAL),
+        ("d = 0", lambda: bm.bm_encrypt_query(ctx, pk, one(0), 1, 1), bm.BM_EDIM),
+        ("d not a power of two", lambda: bm.bm_encrypt_query(ctx, pk, one(24), 1, 1), bm.BM_EDIM),
+        ("d above the slots", lambda: bm.bm_encrypt_query(ctx, pk, one(2 * p.slots), 1, 1), bm.BM_EDIM),
+        ("k not a power of two", lambda: bm.bm_encrypt_gallery(ctx, pk, X, 3, 1, 10), bm.BM_EDIM),
+        ("k above d", lambda: bm.bm_encrypt_gallery(ctx, pk, X, 32, 1, 10), bm.BM_EDIM),
+        ("query d != gallery d", lambda: bm.bm_match(ctx, evk, q8, g, None, schedule=1), bm.BM_EDIM),
+        ("query d != gallery d, batched", lambda: bm.bm_match_batch(ctx, evk, [q16, q8], [g, g], schedule=1),
+         bm.BM_EDIM),
+        ("schedule without S1 or S2", lambda: bm.bm_match(ctx, evk, q16, g, None, schedule=0), bm.BM_EINVAL),
+        ("S1 and S2 together", lambda: bm.bm_match(ctx, evk, q16, g, None, schedule=3), bm.BM_EINVAL),
+        ("query below the gallery level", lambda: bm.bm_match(ctx, evk, c1, g, None, schedule=1), bm.BM_ELEVEL),
+        ("decrypt with another template count", lambda: bm.bm_decrypt_scores(ctx, sk, r, 11), bm.BM_EINVAL),
+        ("export of a missing group", lambda: bm.bm_result_export(ctx, r, 5, p.N), bm.BM_EINVAL),
+        ("add at different scales", lambda: bm.bm_op_add(ctx, a, b), bm.BM_ESCALE),
+        ("add at different levels", lambda: bm.bm_op_add(ctx, a, c2), bm.BM_ELEVEL),
+        ("rotation without its key", lambda: bm.bm_op_rotate(ctx, evk, a, 3), bm.BM_ENOKEY),
+        ("rescale of one limb", lambda: bm.bm_op_rescale(ctx, c1), bm.BM_ELEVEL),
+        ("top-1 of no scores", lambda: bm.bm_top1(np.zeros(0)), bm.BM_EINVAL),
+    ]
+    for name, f, want in cases:
+        got = status(f)
+        assert got == want, "%s: status %d, expected %d" % (name, got, want)
+    # the server keeps a rejected query with the caller
+    srv = bm.bm_server_create(ctx, evk, 64 << 30, 1)
+    gid = bm.bm_server_add_gallery(srv, g)
+    assert status(lambda: bm.bm_server_submit(srv, gid, q8)) == bm.BM_EDIM
+    bm.bm_server_free(srv)
+    for h in (q16, q8, a, b, c2, c1):
+        bm.bm_ct_free(h)
+    bm.bm_result_free(r)
+    for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+        f(h)
+    bm.bm_ctx_free(ctx)
+    print("input checks ok", flush=True)
+
+
 if __name__ == "__main__":
+    input_checks()
     allocator_hook_flow()
     flow(1, [(16, 1), (16, 2), (16, 4), (8, 8)], 300)
     flow(2, [(128, 1), (128, 4), (128, 16), (16, 1)], 5000)

@@ -276,6 +276,54 @@ def test_match_small_ring_bit_exact(bm, d, k, schedule):
         bm.bm_masks_free(lm)
 
 
+# degenerate shapes: d = n (one template fills the ciphertext, the rotate-and-sum
+# spans every slot: the textbook sum of all slots), a gallery of one template,
+# and k = d (c = 1: no rotate-and-sum, every slot of a part is one coordinate)
+DEGENERATE = [(2048, 1, 1, 1), (2048, 1, 1, 0x101), (16, 1, 1, 2), (16, 16, 5, 2), (16, 16, 5, 0x101)]
+
+
+@pytest.mark.parametrize("d,k,R,schedule", DEGENERATE)
+def test_match_degenerate_shapes_bit_exact(bm, d, k, R, schedule):
+    P = ckks.Params.preset(1)
+    rots = set()
+    for d_, k_, _, _ in DEGENERATE:
+        rots.update(obm.rotations_needed(P, d_, k_))
+    rots = tuple(sorted(rots))
+    P, okeys = oracle_keys(1, rots)
+    ctx = lib_ctx(1)
+    sk, pk, evk = lib_keys(1, rots)
+    rng = np.random.default_rng(d + 7 * k + R)
+    X = rng.standard_normal((R, d))
+    X = X / np.linalg.norm(X, axis=1, keepdims=True)
+    qv = X[R // 2] + 0.05 * rng.standard_normal(d)
+    qv = qv / np.linalg.norm(qv)
+    log("match degenerate d=%d k=%d R=%d S%#x" % (d, k, R, schedule))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 19)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 3000)
+    masks, mscale = obm.mask_coeffs(P, d, k, len(P.q)) if k > 1 else (None, None)
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale,
+                     level_min=bool(schedule & 0x100))
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=0)
+    G, limbs, scale = bm.bm_result_info(res)
+    assert G == len(gal_o) == 1
+    got, sc = bm.bm_result_export(ctx, res, 0, P.N)
+    assert sc == want[0].scale
+    assert_words_equal(got, ct_words(want[0]), "group 0")
+    scores = bm.bm_decrypt_scores(ctx, sk, res, R)
+    cos = X @ qv
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == int(np.argmax(cos))
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    if lm:
+        bm.bm_masks_free(lm)
+
+
 def test_match_library_encryption_end_to_end(bm):
     """The library's own encode/encrypt of the N = 2^12 workload: scores within
     1e-4 of the FP64 cosine and the known answer found."""
