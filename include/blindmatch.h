@@ -330,7 +330,8 @@ void bm_masks_free(bm_masks *m);
 
 /* Alg. 1, Input Ciphertext Expansion: outs[i] = Res(Mul(P)(q, mask_i)),
  * then for t < log2 k add Rot(., -c 2^t) when bit t of i is 0, else
- * Rot(., +c 2^t).  outs must hold k handle slots. */
+ * Rot(., +c 2^t).  outs must hold k handle slots.  BM_EDIM for a query from
+ * bm_encrypt_query with another d than the masks'. */
 int bm_expand(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_masks *masks,
               bm_ct **outs);
 

@@ -950,6 +950,7 @@ int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* ma
     REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
     Ctx& c = ctx->c;
     REQUIRE(q->limbs >= 2, BM_ELEVEL, "query needs two limbs");
+    REQUIRE(!q->query_d || q->query_d == masks->d, BM_EDIM, "query packed for another dimension than the masks");
     c.use_stream(nullptr);
     const uint32_t k = masks->k;
     const size_t nln = (size_t)(q->limbs - 1) * c.N;

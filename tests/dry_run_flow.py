@@ -221,6 +221,8 @@ def input_checks():
         ("query d != gallery d", lambda: bm.bm_match(ctx, evk, q8, g, None, schedule=1), bm.BM_EDIM),
         ("query d != gallery d, batched", lambda: bm.bm_match_batch(ctx, evk, [q16, q8], [g, g], schedule=1),
          bm.BM_EDIM),
+        ("expansion with masks of another d", lambda: bm.bm_expand(ctx, evk, q8, bm.bm_masks_create(ctx, 16, 2), 2),
+         bm.BM_EDIM),
         ("schedule without S1 or S2", lambda: bm.bm_match(ctx, evk, q16, g, None, schedule=0), bm.BM_EINVAL),
         ("S1 and S2 together", lambda: bm.bm_match(ctx, evk, q16, g, None, schedule=3), bm.BM_EINVAL),
         ("query below the gallery level", lambda: bm.bm_match(ctx, evk, c1, g, None, schedule=1), bm.BM_ELEVEL),
