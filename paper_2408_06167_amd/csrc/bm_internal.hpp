@@ -172,12 +172,6 @@ struct FuseArgs {
   int last_off = -1;             // pro 4: limb offset (in a source component) of the last chain limb
   int last_pid = -1;             // pro 4: its prime
   const u64* wmtab = nullptr;    // epi 2: minuend multipliers
-  // icol = 1: the sources have been through the inverse transform's row pass
-  // only (ntt_inv_rows); the column pass finishes their inverse transform
-  // with the inverse twiddles itw / itwq (set by ntt_fused)
-  int icol = 0;
-  const double* itw = nullptr;
-  const double* itwq = nullptr;
 };
 
 // ----------------------------------------------------------------- device memory
@@ -392,13 +386,6 @@ LimbMap single(int prime, int off);
 // (inverse) around the transform.
 void ntt(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
          const LimbMap& m, bool inverse, bool raw = false);
-// N = 2^16, standard ring: the first (row) pass of the inverse transform only,
-// whose output a fused forward transform with icol = 1 finishes
-void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-                  const LimbMap& m);
-// whether a fused transform can finish the inverse transforms of `nsrc`
-// sources itself (icol = 1)
-bool icol_ok(const Ctx& c, int nsrc);
 // in place: residue words (< 2^52) <-> the bit patterns of the same values as
 // FP64 numbers (the form switching keys are kept in)
 void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);

@@ -287,13 +287,8 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
   DBuf xc(&c, (size_t)B * limbs * N);
-  // the fused transform unfolds (conjugate-invariant ring) on the fly, or
-  // finishes the inverse transform after its row pass (icol)
-  const bool icol = kern::fused_ok(c) && kern::icol_ok(c, c.alpha);
-  if (icol)
-    kern::ntt_inv_rows(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs));
-  else
-    kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true, kern::fused_ok(c));
+  // the fused transform unfolds (conjugate-invariant ring) on the fly
+  kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true, kern::fused_ok(c));
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
   LimbMap m{};
@@ -307,7 +302,6 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
     FuseArgs f;
     f.pro = 1;
     f.ci = c.ci ? c.d_ci : nullptr;
-    f.icol = icol ? 1 : 0;
     f.mu = c.d_modup + limbs;
     f.src = xc.p();
     f.s_hi = (size_t)limbs * N;
@@ -335,18 +329,13 @@ static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size
       mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
       ++mp.n;
     }
-  const bool icol = kern::fused_ok(c) && kern::icol_ok(c, c.K);
-  if (icol)
-    kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
-  else
-    kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
+  kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
   if (kern::fused_ok(c)) {           // conversion and finish inside the forward transform
     FuseArgs f;
     f.pro = 2;
     f.ci = c.ci ? c.d_ci : nullptr;
-    f.icol = icol ? 1 : 0;
     f.md = c.d_moddown;
     f.src = uw;
     f.s_div = f.e_div = 2;           // element 2 z + comp
@@ -440,16 +429,11 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
       ++mp.n;
     }
   }
-  const bool icol = kern::icol_ok(c, c.K + 1);
-  if (icol)
-    kern::ntt_inv_rows(c, uw.p(), suw, uw.p(), suw, B, mp);
-  else
-    kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
+  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
   DBuf t(&c, (size_t)B * 2 * nl * N);
   FuseArgs f;
   f.pro = 4;
   f.ci = c.ci ? c.d_ci : nullptr;
-  f.icol = icol ? 1 : 0;
   f.md = c.d_moddown;
   f.src = uw.p();
   f.s_div = f.e_div = 2;             // element 2 z + comp
@@ -482,18 +466,13 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
   DBuf last(&c, (size_t)B * comps * N);
   LimbMap m = kern::single(nl, nl);
   m.ooff[0] = 0;
-  const bool icol = kern::fused_ok(c) && kern::icol_ok(c, 1);
-  if (icol)
-    kern::ntt_inv_rows(c, in, (size_t)limbs * N, last.p(), N, B * comps, m);
-  else
-    kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true, kern::fused_ok(c));
+  kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true, kern::fused_ok(c));
   DBuf t(&c, (size_t)B * comps * nl * N);
   if (kern::fused_ok(c)) {           // reduction and finish inside the forward transform
     if (in == out) BM_THROW(BM_EINVAL, "rescale cannot work in place");
     FuseArgs f;
     f.pro = 3;
     f.ci = c.ci ? c.d_ci : nullptr;
-    f.icol = icol ? 1 : 0;
     f.src_pid = nl;
     f.src = last.p();
     f.s_hi = N;

@@ -301,10 +301,7 @@ enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 // FUSE = 1: forward column pass whose input words come from f's prologue;
 // FUSE = 2: forward row pass that stores through f's epilogue;
 // FUSE = 3: forward row pass that stores the residues as FP64 values;
-// FUSE = 4: as 1, in the conjugate-invariant ring (sources not yet unfolded);
-// FUSE = 6: as 1, with sources that have been through the inverse transform's
-//           row pass only: the block finishes their inverse transform (column
-//           stages and N^-1) before converting them.
+// FUSE = 4: as 1, in the conjugate-invariant ring (sources not yet unfolded).
 template <int LOGM, bool INV, int KIND, int FUSE = 0>
 __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
@@ -312,11 +309,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
                                                   const double* __restrict__ twf,
                                                   const double* __restrict__ twq, int log_n, int s0,
                                                   int last, int B, int vz, FuseArgs f) {
-  static_assert(FUSE == 0 || (!INV && (((FUSE == 1 || FUSE == 4 || FUSE == 6) && KIND == NTT_COL) ||
+  static_assert(FUSE == 0 || (!INV && (((FUSE == 1 || FUSE == 4) && KIND == NTT_COL) ||
                                        ((FUSE == 2 || FUSE == 3) && KIND == NTT_ROW))),
                 "fused prologues serve forward column passes, epilogues forward row passes");
-  constexpr bool PRO = FUSE == 1 || FUSE == 4 || FUSE == 6;
-  constexpr bool ICOL = FUSE == 6;            // sources still need the inverse column stages
+  constexpr bool PRO = FUSE == 1 || FUSE == 4;
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
   // padded view length in LDS.  Column passes put 16 views side by side in a
@@ -482,91 +478,6 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       tl[rr * 512 + 256 + slot] = WQ[g];
     }
   }
-  // ---- FUSE = 6: finishing the sources' inverse transforms in the block.
-  // Source a (the order of the conversion below; with prologue 4 the K
-  // special limbs, then the last chain limb) has prime src_prime(a); its
-  // inverse column twiddles sit after the forward ones, 512 doubles each, in
-  // the same slot order.
-  auto src_prime = [&](int a) -> int {
-    if (f.pro == 3) return f.src_pid;
-    if (f.pro == 4) return a < f.md->K ? f.md->pprime[a] : f.last_pid;
-    if (f.pro == 1) return f.mu->d[jd].src[a];
-    return f.md->pprime[a];
-  };
-  double* tli = tl + 512;
-  if constexpr (ICOL) {
-    const int nsl = f.pro == 4 ? f.md->K + 1 : ns;
-    for (int k = t; k < 256 * nsl; k += nthr) {
-      const int slot = k & 255, a = k >> 8;
-      if (slot == 0) continue;
-      const int st = 31 - __clz(slot);
-      const int o = slot - (1 << st);
-      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
-      const size_t g = (size_t)src_prime(a) * N + (1 << st) + b;
-      tli[a * 512 + slot] = f.itw[g];
-      tli[a * 512 + 256 + slot] = f.itwq[g];
-    }
-    __syncthreads();
-  }
-  // the inverse column stages of one source column (mod qs, twiddles tw):
-  // rows addr(1, j) in, rows addr(0, j) out, through one LDS transpose
-  auto inv_cols = [&](double* xs, const double* tw, double qs, double qsi) {
-#pragma unroll
-    for (int ph = 0; ph < 2; ++ph) {
-      const int p = 1 - ph;
-      const int hi = u >> (LOGM - 4 * p - 4);
-      if (ph > 0) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) xs[j] = sh[v * VS + pad(addr(p, j))];
-      }
-#pragma unroll
-      for (int k = 3; k >= 0; --k) {
-        if ((k == 3 && ph > 0) || k == 1) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) xs[j] = fred(xs[j], qsi, qs);
-        }
-        const int step = 8 >> k;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j & step) continue;
-          const int slot = p == 0 ? (1 << k) + (j >> (4 - k)) : (1 << (4 + k)) + ((j >> (4 - k)) << 4) + hi;
-          const double U = xs[j], Vv = xs[j + step];
-          xs[j] = __dadd_rn(U, Vv);
-          xs[j + step] = fmul_mod(__dsub_rn(U, Vv), tw[slot], tw[256 + slot], qs);
-        }
-      }
-      if (ph == 0) {
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(p, j))] = xs[j];
-        __syncthreads();
-      }
-    }
-  };
-  // words of source a at rows addr(0, j) as exact residues (doubles): read
-  // (FUSE = 1), or finished here from the row pass's output (FUSE = 6)
-  auto fetch = [&](int a, size_t soff, bool pre, double* o) {
-    if constexpr (ICOL) {
-      const PrimeC& ps = P[src_prime(a)];
-      const double qs = (double)ps.q, qsi = __longlong_as_double((long long)ps.pad[1]);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) o[j] = u64_to_f(S[soff * N + (size_t)addr(1, j) * astride]);
-      inv_cols(o, tli + a * 512, qs, qsi);
-      const double ni = (double)ps.ninv, niq = __longlong_as_double((long long)ps.pad[2]);
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const double r = fred(fmul_mod(o[j], ni, niq, qs), qsi, qs);
-        o[j] = r < 0.0 ? __dadd_rn(r, qs) : r;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) o[j] = u64_to_f(pre ? r0[j] : S[soff * N + (size_t)addr(0, j) * astride]);
-    }
-  };
-  (void)src_prime;
-  (void)tli;
-  (void)inv_cols;
-  (void)fetch;
   if constexpr (PRO) {
     // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
     // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
@@ -683,15 +594,8 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         if (!zero) x[j] = fred(__dsub_rn(x[j], fmul_mod(xm[j], it, itq, q)), qi, q);
       }
     } else if (f.pro == 3) {
-      if constexpr (ICOL) {
-        double w3[16];
-        fetch(0, 0, true, w3);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = fred(w3[j], qi, q);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
-      }
+      for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
     } else if (f.pro == 4) {
       // relinearisation and rescale in one (see relin_rescale): the special
       // limbs of u and its last chain limb y = u + P d (coefficient domain)
@@ -707,17 +611,13 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
         const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
         const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
-        double rd[16];
-        if constexpr (ICOL) {
-          fetch(a, (size_t)(f.s_off0 + a), a == 0, rd);
-        } else {
-          const u64* Sa = S + (size_t)(f.s_off0 + a) * N;
+        const u64* Sa = S + (size_t)(f.s_off0 + a) * N;
+        u64 r[16];
 #pragma unroll
-          for (int j = 0; j < 16; ++j) rd[j] = u64_to_f(a == 0 ? r0[j] : Sa[(size_t)addr(0, j) * astride]);
-        }
+        for (int j = 0; j < 16; ++j) r[j] = a == 0 ? r0[j] : Sa[(size_t)addr(0, j) * astride];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          double t1 = fred(fmul_mod(rd[j], c1d, c1q, ms), msi, ms);
+          double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
           t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
           const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);   // each within q
           cl[j] = a == 0 ? pL : __dadd_rn(cl[j], pL);
@@ -731,17 +631,11 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
           }
         }
       }
-      double yl[16];
-      if constexpr (ICOL) {
-        fetch(md.K, (size_t)f.last_off, false, yl);
-      } else {
-        const u64* Sl = S + (size_t)f.last_off * N;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) yl[j] = u64_to_f(Sl[(size_t)addr(0, j) * astride]);
-      }
+      const u64* Sl = S + (size_t)f.last_off * N;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        double last = fmul_mod(__dsub_rn(yl[j], fred(cl[j], qli, ql)), pl, plq, ql);
+        const double yl = u64_to_f(Sl[(size_t)addr(0, j) * astride]);
+        double last = fmul_mod(__dsub_rn(yl, fred(cl[j], qli, ql)), pl, plq, ql);
         last = fred(last, qli, ql);
         last = last < 0.0 ? __dadd_rn(last, ql) : last;                 // exact residue mod q_last
         const double z = __dadd_rn(fmul_mod(fred(ci[j], qi, q), pt, ptq, q), fred(last, qi, q));
@@ -754,21 +648,15 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         src_info(a, soff, spid, c1, c2);
         const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
         const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
-        double rd[16];
-        if constexpr (ICOL) {
-          fetch(a, (size_t)soff, a == 0, rd);
-        } else {
-          u64 r[16];
-          if (a >= 1) {
+        u64 r[16];
+        if (a >= 1) {
 #pragma unroll
-            for (int j = 0; j < 16; ++j) r[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
-          }
-#pragma unroll
-          for (int j = 0; j < 16; ++j) rd[j] = u64_to_f(a == 0 ? r0[j] : r[j]);
+          for (int j = 0; j < 16; ++j) r[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          double t1 = fred(fmul_mod(rd[j], c1d, c1q, ms), msi, ms);
+          const u64 w = a == 0 ? r0[j] : r[j];
+          double t1 = fred(fmul_mod(u64_to_f(w), c1d, c1q, ms), msi, ms);
           t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
           const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
           x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
@@ -1638,7 +1526,7 @@ LimbMap single(int prime, int off) {
 // N = 2^12: one 12-stage pass; N = 2^16: 8 column stages then 8 row stages
 // (inverse: rows first).  Row passes take up to 16 polynomials per block.
 void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-              const LimbMap& m, const LimbMap& m_out, bool inverse, bool rows_only = false) {
+              const LimbMap& m, const LimbMap& m_out, bool inverse) {
   const int logn = c.log_n;
   const int N = 1 << logn;
   const double elems = (double)N * m.n * B;
@@ -1700,21 +1588,8 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     row(out, out_stride, out, out_stride, m_out);
   } else {
     row(in, in_stride, out, out_stride, m);
-    if (!rows_only) col(out, out_stride, out, out_stride, m_out, 1);
+    col(out, out_stride, out, out_stride, m_out, 1);
   }
-}
-
-constexpr int ICOL_MAX = 3;   // sources whose inverse twiddles a FUSE = 6 block stages
-
-bool icol_ok(const Ctx& c, int nsrc) { return c.log_n == 16 && !c.ci && nsrc >= 1 && nsrc <= ICOL_MAX; }
-
-void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-                  const LimbMap& m) {
-  if (c.log_n != 16 || c.ci) BM_THROW(BM_EINVAL, "launch check: row-pass-only inverse needs N = 2^16, standard ring");
-  if (B <= 0 || m.n <= 0) return;
-  LimbMap m_out = m;
-  for (int i = 0; i < m.n; ++i) m_out.off[i] = m.ooff[i];
-  ntt_fast(c, in, in_stride, out, out_stride, B, m, m_out, true, true);
 }
 
 void modmul_rate(const Ctx& c, int pid, int blocks, int iters, const u64* seed, u64* out) {
@@ -1745,11 +1620,8 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
       ((f.pro == 2 || f.pro == 4) && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) ||
       (f.epi == 2 && !f.wmtab) || (f.pro == 4 && (f.last_pid < 0 || f.last_pid >= c.nprimes() || f.last_off < 0)) ||
       (c.ci != (f.ci != nullptr)) ||
-      ((f.ci || f.icol) && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
+      (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
     BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
-  const int nsrc = f.pro == 4 ? c.K + 1 : f.pro == 3 ? 1 : f.pro == 2 ? c.K : c.alpha;
-  if (f.icol && (f.ci || !icol_ok(c, nsrc)))
-    BM_THROW(BM_EINVAL, "launch check: in-block inverse transform of the sources not available here");
   const int logn = 16, N = 1 << logn;
   LimbMap mo = m;
   for (int i = 0; i < m.n; ++i) mo.off[i] = mo.ooff[i];
@@ -1768,17 +1640,10 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   {
     const double srcs = f.pro == 1 ? 2.0 : f.pro == 2 ? (double)c.K : 1.0;
     Prof pf(c, "ntt_fwd_col_fused", 8.0 * elems * (1.0 + srcs), 0.5 * elems * 8 + 2.0 * srcs * elems);
-    if (f.ci) {
+    if (f.ci)
       LAUNCH((k_ntt_fast<8, false, NTT_COL, 4>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
              (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
-    } else if (f.icol) {
-      FuseArgs g = f;
-      g.itw = c.d_itwf;
-      g.itwq = c.d_itwq;
-      const size_t lds_icol = lds_col + (size_t)512 * ICOL_MAX * sizeof(u64);
-      LAUNCH((k_ntt_fast<8, false, NTT_COL, 6>), gcol, dim3(256), lds_icol, c.stream, (const u64*)nullptr,
-             (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, g);
-    } else
+    else
       LAUNCH((k_ntt_fast<8, false, NTT_COL, 1>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
              (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
     check_launch();
