@@ -251,7 +251,54 @@ def input_checks():
     print("input checks ok", flush=True)
 
 
+def server_from_threads():
+    """bm_server_submit and bm_server_poll from several threads at once (the
+    thread-safe pair): every ticket completes exactly once."""
+    import threading
+    p = bm.bm_params_preset(1)
+    ctx = bm.bm_ctx_create(p, 0)
+    sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(set(bm.bm_rotations_for(16, 1)) | set(bm.bm_rotations_for(16, 4))))
+    rng = np.random.default_rng(4)
+    srv = bm.bm_server_create(ctx, evk, 64 << 30, 2 | bm.BM_LEVEL_MIN)
+    gids = [bm.bm_server_add_gallery(srv, bm.bm_encrypt_gallery(ctx, pk, rng.standard_normal((n, 16)).astype(np.float32),
+                                                                 k, 1, 10 * n))
+            for n, k in ((300, 1), (700, 4))]
+    n_threads, per = 4, 6
+    queries = [[bm.bm_encrypt_query(ctx, pk, rng.standard_normal(16).astype(np.float32), 1, 100 * t + i)
+                for i in range(per)] for t in range(n_threads)]   # the context itself is single-threaded
+    done, errors = [0] * n_threads, []
+
+    def client(t):
+        try:
+            tickets = [bm.bm_server_submit(srv, gids[(t + i) % 2], queries[t][i]) for i in range(per)]
+            assert len(set(tickets)) == per
+            pending = set(tickets)
+            while pending:
+                for tk in list(pending):
+                    r = bm.bm_server_poll(srv, tk)
+                    if r is not None:
+                        bm.bm_result_free(r)
+                        pending.discard(tk)
+                        done[t] += 1
+        except Exception as e:   # reported by the main thread
+            errors.append(e)
+    threads = [threading.Thread(target=client, args=(t,)) for t in range(n_threads)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=300)
+    assert not errors, errors
+    assert done == [per] * n_threads, done
+    assert bm.bm_server_stats(srv)["completed"] == n_threads * per
+    bm.bm_server_free(srv)
+    for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+        f(h)
+    bm.bm_ctx_free(ctx)
+    print("server from threads ok", flush=True)
+
+
 if __name__ == "__main__":
+    server_from_threads()
     input_checks()
     allocator_hook_flow()
     flow(1, [(16, 1), (16, 2), (16, 4), (8, 8)], 300)
