@@ -50,7 +50,7 @@ enum {
   BM_ENOMEM = -6,   /* device or host allocation failed */
   BM_EBUDGET = -7,  /* serving: request exceeds the HBM budget */
   BM_EDEVICE = -8,  /* HIP runtime error */
-  BM_EBUSY = -9     /* serving: queue full / ticket still pending */
+  BM_EBUSY = -9     /* reserved (no call returns it: a pending ticket polls as BM_OK with NULL) */
 };
 
 enum { BM_S1 = 1, BM_S2 = 2 };   /* Alg. 2 schedules, see bm_match */
