@@ -16,7 +16,8 @@
  *     text of its last error (bm_last_error).
  *   - Handles (bm_ctx, bm_sk, ...) are created by the library and released by
  *     the matching bm_*_free.  Freeing NULL is a no-op.  Every handle created
- *     from a context must be freed before that context.
+ *     from a context must be freed before that context, and is used only
+ *     with that context (a handle of another context is BM_EINVAL).
  *   - Host buffers passed in are read (or written) only during the call.
  *   - Ciphertexts, keys, galleries and results live in device memory (HBM)
  *     owned by their handle.  Interchange with the host is in the COEFFICIENT
@@ -24,9 +25,10 @@
  *   - `stream` arguments are a hipStream_t (passed as void*) or NULL for the
  *     context's own stream.  Calls that take a stream are asynchronous on it;
  *     all other calls return with their device work finished.  One context is
- *     single-threaded; changing the stream of a context first waits for the
- *     previous stream.
- *   - Ring degree N = 2^log_n, n = N/2 complex slots carrying real data; limb
+ *     single-threaded (bm_server_submit and bm_server_poll excepted);
+ *     changing the stream of a context first waits for the previous stream.
+ *   - Ring degree N = 2^log_n, n = N/2 complex slots carrying real data (N
+ *     real slots in the conjugate-invariant ring, bm_params.ring); limb
  *     l < L+1 is chain prime q_l, the K special primes follow.  A fresh
  *     ciphertext has L+1 limbs; each rescale drops the last limb.
  */

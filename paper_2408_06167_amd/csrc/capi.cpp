@@ -39,8 +39,16 @@ int guarded(bm_ctx* ctx, F&& f) {
     if (!(cond)) BM_THROW((code), (msg)); \
   } while (0)
 
-// Largest `count` primes below 2^bits that are 1 mod 2N, in descending order.
-// the `count` largest primes below 2^bits that are 1 mod `step` (2N, or 4N)
+// Every handle a call takes must come from the call's context (its buffers
+// are sized for that context's ring and limbs); NULL handles pass here.
+template <class... H>
+void same_ctx(const bm_ctx* ctx, const H*... h) {
+  const bool ok = ((h == nullptr || h->ctx == ctx) && ...);
+  REQUIRE(ok, BM_EINVAL, "handle made by another context");
+}
+
+// the `count` largest primes below 2^bits that are 1 mod `step` (2N, or 4N),
+// in descending order
 std::vector<u64> primes_below(int bits, u64 step, int count, const std::vector<u64>& avoid) {
   std::vector<u64> out;
   u64 cand = (((1ULL << bits) - 1) / step) * step + 1;
@@ -481,6 +489,7 @@ int bm_encrypt_coeffs(bm_ctx* ctx, const bm_pk* pk, const int64_t* coeffs, uint3
                       double scale, uint64_t seed, uint64_t ct_id, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && coeffs && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, pk);
     Ctx& c = ctx->c;
     REQUIRE(limbs >= 1 && (int)limbs <= c.L + 1, BM_ELEVEL, "limbs out of range");
     c.use_stream(nullptr);
@@ -495,6 +504,7 @@ int bm_encrypt_query(bm_ctx* ctx, const bm_pk* pk, const float* q, uint32_t d, u
                      uint64_t ct_id, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && q && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, pk);
     Ctx& c = ctx->c;
     REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= slot count");
     std::vector<double> slots(c.n);
@@ -514,6 +524,7 @@ int bm_encrypt_template(bm_ctx* ctx, const bm_pk* pk, const float* x, uint32_t d
                         uint64_t ct_id, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && x && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, pk);
     Ctx& c = ctx->c;
     REQUIRE(bmx::is_pow2(d) && d <= c.n, BM_EDIM, "d must be a power of two <= slot count");
     std::vector<double> slots(c.n, 0.0);
@@ -546,6 +557,7 @@ int bm_encrypt_gallery(bm_ctx* ctx, const bm_pk* pk, const float* x, uint64_t n,
                        uint32_t k, uint64_t seed, uint64_t ct_id_base, bm_gallery** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && pk && x && out && n > 0, BM_EINVAL, "NULL argument or empty gallery");
+    same_ctx(ctx, pk);
     Ctx& c = ctx->c;
     bmx::check_shape(c, d, k);
     const uint32_t cc = d / k;
@@ -668,6 +680,7 @@ void bm_ct_free(bm_ct* ct) { delete ct; }
 int bm_decrypt_slots(bm_ctx* ctx, const bm_sk* sk, const bm_ct* ct, double* slots, size_t n) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && sk && ct && slots, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, sk, ct);
     Ctx& c = ctx->c;
     REQUIRE(n == c.n, BM_EINVAL, "n must equal the slot count");
     c.use_stream(nullptr);
@@ -703,6 +716,7 @@ int bm_ntt(bm_ctx* ctx, uint64_t* dev_words, uint32_t n_polys, uint32_t limbs,
 int bm_op_add(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && a && b && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, a, b);
     REQUIRE(a->limbs == b->limbs, BM_ELEVEL, "level mismatch");
     REQUIRE(a->scale == b->scale, BM_ESCALE, "scale mismatch");
     Ctx& c = ctx->c;
@@ -725,6 +739,7 @@ int bm_op_add(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
 int bm_op_pmul(bm_ctx* ctx, const bm_ct* a, const int64_t* pt, double pt_scale, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && a && pt && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, a);
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
     const size_t ln = (size_t)a->limbs * c.N;
@@ -740,6 +755,7 @@ int bm_op_pmul(bm_ctx* ctx, const bm_ct* a, const int64_t* pt, double pt_scale, 
 int bm_op_tensor(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && a && b && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, a, b);
     REQUIRE(a->comps == 2 && b->comps == 2, BM_EINVAL, "tensor needs 2-component inputs");
     REQUIRE(a->limbs == b->limbs, BM_ELEVEL, "level mismatch");
     Ctx& c = ctx->c;
@@ -755,6 +771,7 @@ int bm_op_tensor(bm_ctx* ctx, const bm_ct* a, const bm_ct* b, bm_ct** out) {
 int bm_op_relin(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && a && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, a);
     REQUIRE(a->comps == 3, BM_EINVAL, "relinearisation needs 3 components");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
@@ -768,6 +785,7 @@ int bm_op_relin(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, bm_ct** out) {
 int bm_op_rescale(bm_ctx* ctx, const bm_ct* a, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && a && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, a);
     REQUIRE(a->limbs >= 2, BM_ELEVEL, "no level left");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
@@ -782,6 +800,7 @@ int bm_op_rescale(bm_ctx* ctx, const bm_ct* a, bm_ct** out) {
 int bm_op_rotate(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, int32_t r, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && a && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, a);
     REQUIRE(a->comps == 2, BM_EINVAL, "rotation needs 2 components");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
@@ -797,6 +816,7 @@ int bm_op_rotate(bm_ctx* ctx, const bm_evk* evk, const bm_ct* a, int32_t r, bm_c
 int bm_op_drop(bm_ctx* ctx, const bm_ct* a, uint32_t limbs, bm_ct** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && a && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, a);
     REQUIRE(limbs >= 1 && limbs <= a->limbs, BM_ELEVEL, "cannot raise the level");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
@@ -881,9 +901,14 @@ int bm_enroll(bm_ctx* ctx, const bm_evk* evk, bm_gallery* g, const bm_ct* const*
               const uint64_t* indices, size_t n, const bm_masks* masks, void* stream) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && g && (n == 0 || (users && indices)), BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, g, masks);
     Ctx& c = ctx->c;
     c.use_stream(stream);
     if (n == 0) return;
+    for (size_t i = 0; i < n; ++i) {
+      REQUIRE(users[i], BM_EINVAL, "NULL user");
+      same_ctx(ctx, users[i]);
+    }
     const uint32_t ul = users[0]->limbs;
     REQUIRE(ul == g->limbs + 1, BM_ELEVEL, "users must sit one level above the gallery");
     const bm_masks* m = masks ? masks : bmx_enroll_masks(ctx, g->d, g->k, ul);
@@ -947,6 +972,7 @@ void bm_masks_free(bm_masks* m) {
 int bm_expand(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_masks* masks, bm_ct** outs) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && q && masks && outs, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, q, masks);
     REQUIRE(q->comps == 2, BM_EINVAL, "query must have 2 components");
     Ctx& c = ctx->c;
     REQUIRE(q->limbs >= 2, BM_ELEVEL, "query needs two limbs");
@@ -1112,6 +1138,7 @@ int bm_match(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g
              uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** out) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && q && g && out, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, q, g, masks);
     ctx->c.use_stream(stream);
     match_one(ctx, evk, q, g, masks, schedule, out_limbs, out);
   });
@@ -1165,8 +1192,12 @@ int bm_match_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const
                    size_t n_pairs, uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** outs) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && qs && gs && outs, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk);
     ctx->c.use_stream(stream);
-    for (size_t i = 0; i < n_pairs; ++i) REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
+    for (size_t i = 0; i < n_pairs; ++i) {
+      REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
+      same_ctx(ctx, qs[i], gs[i]);
+    }
     // pairs that share a gallery (and query level) go through one batched pass
     std::vector<std::unique_ptr<bm_result>> res(n_pairs);
     std::vector<bool> done(n_pairs, false);
@@ -1193,6 +1224,7 @@ int bm_autotune(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery
                 uint32_t* best_chunk, double* best_ms) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && evk && q && g, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, q, g);
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
     const bool graphs = c.use_graphs;
@@ -1263,6 +1295,7 @@ void bm_result_free(bm_result* r) { delete r; }
 int bm_decrypt_scores(bm_ctx* ctx, const bm_sk* sk, const bm_result* r, double* scores, uint64_t n) {
   return guarded(ctx, [&] {
     REQUIRE(ctx && sk && r && scores, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, sk, r);
     REQUIRE(n == r->n_templates, BM_EINVAL, "n must equal the gallery size");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);

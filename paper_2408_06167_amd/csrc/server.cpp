@@ -242,7 +242,7 @@ extern "C" {
 
 int bm_server_create(bm_ctx* ctx, const bm_evk* evk, uint64_t hbm_budget_bytes, uint32_t schedule,
                      bm_server** out) {
-  if (!ctx || !evk || !out || hbm_budget_bytes == 0) return BM_EINVAL;
+  if (!ctx || !evk || !out || hbm_budget_bytes == 0 || evk->ctx != ctx) return BM_EINVAL;
   const uint32_t base = schedule & 0xff;
   if ((base != BM_S1 && base != BM_S2) ||
       (schedule & ~(uint32_t)(0xff | BM_LEVEL_MIN | BM_COMPRESS | BM_HOIST)))
@@ -287,7 +287,7 @@ int bm_server_add_gallery(bm_server* s, bm_gallery* g, uint32_t* gallery_id) {
 }
 
 int bm_server_submit(bm_server* s, uint32_t gallery_id, bm_ct* q, uint64_t* ticket) {
-  if (!s || !q || !ticket) return BM_EINVAL;
+  if (!s || !q || !ticket || q->ctx != s->ctx) return BM_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
   if (gallery_id >= s->galleries.size()) return BM_EINVAL;
   const bm_gallery& g = *s->galleries[gallery_id].g;

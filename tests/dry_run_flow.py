@@ -234,6 +234,19 @@ def input_checks():
         ("rescale of one limb", lambda: bm.bm_op_rescale(ctx, c1), bm.BM_ELEVEL),
         ("top-1 of no scores", lambda: bm.bm_top1(np.zeros(0)), bm.BM_EINVAL),
     ]
+    # handles of another context (its buffers are sized for its own ring)
+    ctx2 = bm.bm_ctx_create(bm.bm_params_preset(3), 0)
+    sk2, pk2, evk2 = bm.bm_keygen(ctx2, 1, bm.bm_rotations_for(16, 1))
+    q2 = bm.bm_encrypt_query(ctx2, pk2, one(16), 1, 1)
+    cases += [
+        ("query of another context", lambda: bm.bm_match(ctx, evk, q2, g, None, schedule=1), bm.BM_EINVAL),
+        ("keys of another context", lambda: bm.bm_match(ctx, evk2, q16, g, None, schedule=1), bm.BM_EINVAL),
+        ("public key of another context", lambda: bm.bm_encrypt_query(ctx, pk2, one(16), 1, 1), bm.BM_EINVAL),
+        ("add across contexts", lambda: bm.bm_op_add(ctx, q16, q2), bm.BM_EINVAL),
+        ("decrypt with another context's key", lambda: bm.bm_decrypt_scores(ctx, sk2, r, 10), bm.BM_EINVAL),
+        ("batch with a query of another context",
+         lambda: bm.bm_match_batch(ctx, evk, [q16, q2], [g, g], schedule=1), bm.BM_EINVAL),
+    ]
     for name, f, want in cases:
         got = status(f)
         assert got == want, "%s: status %d, expected %d" % (name, got, want)
@@ -241,7 +254,13 @@ def input_checks():
     srv = bm.bm_server_create(ctx, evk, 64 << 30, 1)
     gid = bm.bm_server_add_gallery(srv, g)
     assert status(lambda: bm.bm_server_submit(srv, gid, q8)) == bm.BM_EDIM
+    assert status(lambda: bm.bm_server_submit(srv, gid, q2)) == bm.BM_EINVAL
+    assert status(lambda: bm.bm_server_create(ctx, evk2, 64 << 30, 1)) == bm.BM_EINVAL
     bm.bm_server_free(srv)
+    bm.bm_ct_free(q2)
+    for f, h in ((bm.bm_sk_free, sk2), (bm.bm_pk_free, pk2), (bm.bm_evk_free, evk2)):
+        f(h)
+    bm.bm_ctx_free(ctx2)
     for h in (q16, q8, a, b, c2, c1):
         bm.bm_ct_free(h)
     bm.bm_result_free(r)
