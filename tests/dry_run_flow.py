@@ -309,6 +309,13 @@ def server_from_threads():
     assert not errors, errors
     assert done == [per] * n_threads, done
     assert bm.bm_server_stats(srv)["completed"] == n_threads * per
+    # a served result belongs to the caller's context: it decrypts there
+    tk = bm.bm_server_submit(srv, gids[0], bm.bm_encrypt_query(ctx, pk, rng.standard_normal(16).astype(np.float32),
+                                                                 1, 999))
+    bm.bm_server_drain(srv)
+    r = bm.bm_server_poll(srv, tk)
+    bm.bm_decrypt_scores(ctx, sk, r, 300)
+    bm.bm_result_free(r)
     bm.bm_server_free(srv)
     for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
         f(h)
