@@ -453,8 +453,8 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=round(done / dt, 1), unit="templates/s", cores=cores, kind="oracle",
-                sample="%d of %d templates (%d of %d groups, k=%d, schedule %#x, one expansion), %.1fs of oracle time"
-                       % (done, X.shape[0], g + 1, len(groups), k, schedule, dt))
+                sample="%d of %d templates (%d of %d groups, k=%d, schedule %#x%s), %.1fs of oracle time"
+                       % (done, X.shape[0], g + 1, len(groups), k, schedule, ", one expansion" if k > 1 else "", dt))
 
 
 def measured_butterfly_rate(bm, ctx, params, blocks=2048, iters=4096):

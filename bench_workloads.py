@@ -76,11 +76,17 @@ def fingerprint(bm, args):
                          top1_identity_ok=bool(int(bm.bm_top1(scores)[0]) % w["identities"] == w["query_identity"]))
         print("# %s: %.2f ms/query (chunk %d), err %.1e" % (name, ms, chunk, err), file=sys.stderr, flush=True)
     best = min(out, key=lambda n: out[n]["ms_per_query"])
+    cpu = None
+    if not args.no_cpu:            # the oracle on a bounded sample of the same gallery and schedule
+        import bench
+        cpu = bench.cpu_baseline(k, 1 | (bm.BM_LEVEL_MIN if "levelmin" in best else 0), X, q, d, budget_s=10.0)
+        print("# cpu oracle: %s templates/s (%s)" % (cpu["value"], cpu["sample"]), file=sys.stderr, flush=True)
     print(json.dumps({"metric": "encrypted templates scored/s (N=2^16, 16-dim, 1,048,576 templates)",
                       "value": out[best]["templates_per_s"], "unit": "templates/s", "n_gpus": 1,
                       "higher_is_better": True, "data": "synthetic", "dtype": "u64",
                       "config": {"workload": "fingerprint-scale: 1,048,576 x 16-dim, k=1, %d ciphertexts" % G,
-                                 "schedule": best, "variants": out}}), flush=True)
+                                 "schedule": best, "variants": out},
+                      "cpu_baseline": cpu}), flush=True)
 
 
 def batch(bm, args):
