@@ -76,10 +76,10 @@ def parse():
     ap.add_argument("--no-ci", action="store_true", help="skip the conjugate-invariant ring figure")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the compressed and conjugate-invariant figures (profiling runs)")
-    ap.add_argument("--workload", default="face", choices=["face", "fingerprint", "batch", "serve", "copy"],
+    ap.add_argument("--workload", default="face", choices=["face", "fingerprint", "batch", "serve", "copy", "ntt"],
                     help="face: 6,144 x 128-dim (default); fingerprint: 1,048,576 x 16-dim; "
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
-                         "copy: 1 GiB device copy (counter calibration)")
+                         "copy: 1 GiB device copy (counter calibration); ntt: batched NTT throughput")
     ap.add_argument("--scale", type=float, default=1.0, help="gallery size factor for batch/serve")
     ap.add_argument("--rates", default="5,10,20,40", help="serve: arrival rates (queries/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")

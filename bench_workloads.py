@@ -37,7 +37,7 @@ def _setup(bm, shapes, seed=0xB11D):
 
 def run(args):
     import paper_2408_06167_amd as bm
-    {"fingerprint": fingerprint, "batch": batch, "serve": serve, "copy": copy}[args.workload](bm, args)
+    {"fingerprint": fingerprint, "batch": batch, "serve": serve, "copy": copy, "ntt": ntt}[args.workload](bm, args)
 
 
 def fingerprint(bm, args):
@@ -224,6 +224,59 @@ def serve(bm, args):
                                  "Poisson arrivals, 3:1 mix" % args.scale, "templates": sum(sizes.values()),
                                  "schedule": "S2+levelmin", "by_rate": out,
                                  "plain_ms_per_query": plain}}), flush=True)
+
+
+def ntt(bm, args):
+    """Batched negacyclic NTT at N = 2^16 through bm_ntt, in place on device
+    words[polys][8][N] (the 8 chain primes), forward and inverse, small and
+    large batches, both rings.  Each transform is two passes that each read
+    and write every word once: 32 bytes per word of algorithmic traffic."""
+    import torch
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    rows = []
+    for preset in (2, 4):
+        p = bm.bm_params_preset(preset)
+        ctx = bm.bm_ctx_create(p, 0)
+        N, L1 = p.N, p.n_q
+        ids = list(range(L1))
+        for polys in (1, 4, 32):
+            rng = np.random.default_rng(polys)
+            host = np.stack([np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in p.chain()])
+                             for _ in range(polys)])
+            dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+            for inv in (False, True):
+                bm.bm_ntt(ctx, dev.data_ptr(), polys, ids, inv, stream.cuda_stream)
+            torch.cuda.synchronize()
+            for inv in (False, True):
+                reps = max(args.steps, 5)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    bm.bm_ntt(ctx, dev.data_ptr(), polys, ids, inv, stream.cuda_stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                words = polys * L1 * N
+                bfly = words // 2 * 16
+                rows.append(dict(ring="conjugate-invariant" if preset == 4 else "standard", limb_polys=polys * L1,
+                                 direction="inverse" if inv else "forward", us=round(ms * 1e3, 2),
+                                 gb_s=round(32.0 * words / ms / 1e6, 1), gbfly_s=round(bfly / ms / 1e6, 1)))
+                print("# %s %s, %d limb-polynomials: %.1f us, %.0f GB/s" % (
+                    rows[-1]["ring"], rows[-1]["direction"], polys * L1, ms * 1e3, rows[-1]["gb_s"]),
+                    file=sys.stderr, flush=True)
+            # the round trip gives back the input words (in the conjugate-invariant
+            # ring only for invariant inputs, which random words are not)
+            if preset == 2:
+                assert np.array_equal(dev.cpu().numpy().view(np.uint64), host)
+            del dev
+        bm.bm_ctx_free(ctx)
+    big = [r for r in rows if r["limb_polys"] == 256 and r["ring"] == "standard"]
+    print(json.dumps({"metric": "batched negacyclic NTT throughput (N=2^16, in place, 2 passes)",
+                      "value": round(min(r["gb_s"] for r in big), 1), "unit": "GB/s", "n_gpus": 1,
+                      "higher_is_better": True, "data": "synthetic", "dtype": "u64",
+                      "config": {"workload": "bm_ntt on words[polys][8][65536], standard and conjugate-invariant rings",
+                                 "rows": rows}}), flush=True)
 
 
 def copy(bm, args):
