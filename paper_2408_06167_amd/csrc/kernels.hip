@@ -1,11 +1,11 @@
 // kernels.hip -- gfx950 kernels of the RNS-CKKS evaluator.
 //
 // All arithmetic is exact modular integer arithmetic on 64-bit words with
-// primes below 2^51 (no MFMA: nothing here is a dense contraction).  The NTT
-// and the key inner products carry residues as exact integers in FP64, which
-// the VALU issues at full rate; the element-wise kernels use 32-bit integer
-// arithmetic: Shoup's precomputed quotient for constant operands, Montgomery
-// reduction with R = 2^64 for variable products.
+// primes below 2^51 (no MFMA: nothing here is a dense contraction).  The NTT,
+// the key inner products and the tensor carry residues as exact integers in
+// FP64, which the VALU issues at full rate; the other element-wise kernels use
+// 32-bit integer arithmetic: Shoup's precomputed quotient for constant
+// operands, Montgomery reduction with R = 2^64 for variable products.
 //
 // Grids are (element chunks, limb slot, batch element): blockIdx.y picks the
 // limb (and with it the prime, uniform across the block so its constants come
