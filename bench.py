@@ -210,7 +210,8 @@ def main():
     # ---- the same match with host buffers on both sides (never `value`): the
     # query handed over from pinned host memory in the coefficient domain (the
     # import runs its forward NTT), every result ciphertext copied back (the
-    # export runs the inverse NTT), each call synchronous
+    # export runs the inverse NTT, one launch and one copy for all of them),
+    # each call synchronous
     pcie = None
     if not args.no_extras:
         qwords, qscale = bm.bm_ct_export(ctx, q_ct, params.N)
@@ -226,10 +227,9 @@ def main():
         def pcie_once():
             qc = bm.bm_ct_import(ctx, hq_np, qscale)
             r = bm.bm_match(ctx, evk, qc, gals[bk], None, schedule=bs, out_limbs=0, stream=sptr)
-            for g in range(G):
-                st = L.bm_result_export(r, g, hout[g].data_ptr(), per)
-                if st != bm.BM_OK:
-                    raise bm.BMError(st, "bm_result_export", "")
+            st = L.bm_result_export_all(r, hout.data_ptr(), G * per)    # every result in one transfer
+            if st != bm.BM_OK:
+                raise bm.BMError(st, "bm_result_export_all", "")
             bm.bm_result_free(r)
             bm.bm_ct_free(qc)
         for _ in range(2):

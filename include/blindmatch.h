@@ -396,6 +396,10 @@ int bm_autotune(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery
 int bm_result_info(const bm_result *r, uint64_t *groups, uint32_t *limbs, double *scale);
 /* Coefficient-domain words[2][limbs][N] of result ciphertext `group`. */
 int bm_result_export(const bm_result *r, uint64_t group, uint64_t *words, size_t n_words);
+/* Coefficient-domain words[groups][2][limbs][N] of every result ciphertext,
+ * in one inverse-transform launch and one device-to-host copy (what a server
+ * sends back to the client); n_words must be groups * 2 * limbs * N. */
+int bm_result_export_all(const bm_result *r, uint64_t *words, size_t n_words);
 void bm_result_free(bm_result *r);
 
 /* Client side (Sec. 3.4): decrypt every result ciphertext, decode, read

@@ -114,6 +114,7 @@ _SIGS = {
     "bm_result_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                       ctypes.POINTER(_dbl)]),
     "bm_result_export": (ctypes.c_int, [_P, _u64, _P, _sz]),
+    "bm_result_export_all": (ctypes.c_int, [_P, _P, _sz]),
     "bm_result_free": (None, [_P]),
     "bm_decrypt_scores": (ctypes.c_int, [_P, _P, _P, _P, _u64]),
     "bm_top1": (ctypes.c_int, [_P, _u64, _dbl, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_dbl)]),
@@ -581,6 +582,14 @@ def bm_result_export(ctx, r, group, N):
     _, limbs, scale = bm_result_info(r)
     w = np.zeros((2, limbs, N), dtype=np.uint64)
     _check(lib().bm_result_export(r, int(group), _ptr(w), w.size), "bm_result_export", ctx)
+    return w, scale
+
+
+def bm_result_export_all(ctx, r, N):
+    """words[groups][2][limbs][N] of every result ciphertext, and the scale."""
+    groups, limbs, scale = bm_result_info(r)
+    w = np.zeros((groups, 2, limbs, N), dtype=np.uint64)
+    _check(lib().bm_result_export_all(r, _ptr(w), w.size), "bm_result_export_all", ctx)
     return w, scale
 
 

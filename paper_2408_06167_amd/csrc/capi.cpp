@@ -1290,6 +1290,17 @@ int bm_result_export(const bm_result* r, uint64_t group, uint64_t* words, size_t
   });
 }
 
+int bm_result_export_all(const bm_result* r, uint64_t* words, size_t n_words) {
+  if (!r) return BM_EINVAL;
+  bm_ctx* ctx = r->ctx;
+  return guarded(ctx, [&] {
+    Ctx& c = ctx->c;
+    REQUIRE(words && n_words == (size_t)r->groups * 2 * r->limbs * c.N, BM_EINVAL, "size");
+    c.use_stream(nullptr);
+    ev::export_coeffs(c, r->p(), (int)(2 * r->groups), (int)r->limbs, words);
+  });
+}
+
 void bm_result_free(bm_result* r) { delete r; }
 
 int bm_decrypt_scores(bm_ctx* ctx, const bm_sk* sk, const bm_result* r, double* scores, uint64_t n) {

@@ -65,6 +65,7 @@ def flow(preset, shapes, n_templates, hook=None):
                 bm.bm_decrypt_scores(ctx, sk, r, n_templates)
                 G, limbs, _ = bm.bm_result_info(r)
                 bm.bm_result_export(ctx, r, G - 1, N)
+                bm.bm_result_export_all(ctx, r, N)
                 bm.bm_result_free(r)
         # compression: needs one level more than the plain match
         can_compress = preset in (2, 4) or k == 1

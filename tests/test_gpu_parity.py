@@ -262,6 +262,8 @@ def test_match_small_ring_bit_exact(bm, d, k, schedule):
         got, sc = bm.bm_result_export(ctx, res, g, P.N)
         assert sc == want[g].scale
         assert_words_equal(got, ct_words(want[g]), "group %d" % g)
+    allw, sc = bm.bm_result_export_all(ctx, res, P.N)      # every group in one transfer
+    assert_words_equal(allw, np.stack([ct_words(want[g]) for g in range(G)]), "all groups")
     scores = bm.bm_decrypt_scores(ctx, sk, res, R)
     cos = X.astype(np.float64) @ qv.astype(np.float64)
     assert np.max(np.abs(scores - cos)) < 1e-4
