@@ -195,7 +195,11 @@ int bm_bench_modmul(bm_ctx *ctx, uint32_t prime, uint32_t blocks, uint32_t iters
  * digit j, 6/7 Galois key digit j of element g at index g*dnum + j.  The
  * evaluation key holds the relinearisation key (for s^2) and one Galois key
  * (for s(X^g), g = 5^r mod 2N) per rotation r in rotations[0..n_rot-1].
- * Any handle pointer may be NULL if that key is not wanted. */
+ * The key set is given by rotation amounts rather than by (d, k) shapes: the
+ * amounts a shape needs come from bm_rotations_for (Alg. 1 and 2),
+ * bm_rotations_hoisted (BM_HOIST), bm_rotations_compress (BM_COMPRESS) and
+ * bm_rotations_enroll (bm_enroll); the union over the shapes served is the
+ * list to pass.  Any handle pointer may be NULL if that key is not wanted. */
 int bm_keygen(bm_ctx *ctx, uint64_t seed, const int32_t *rotations, size_t n_rot,
               bm_sk **sk, bm_pk **pk, bm_evk **evk);
 /* Rotation amounts Alg. 1 and Alg. 2 use for feature length d split into k
@@ -220,6 +224,21 @@ int bm_sk_export(const bm_sk *sk, int64_t *s, size_t n);
 int bm_pk_export(const bm_pk *pk, uint32_t comp, uint64_t *words, size_t n_words);
 int bm_evk_export(const bm_evk *evk, uint64_t galois, uint32_t digit, uint32_t comp,
                   uint64_t *words, size_t n_words);
+/* Key checkpoint and hand-over (Sec. 3.1: the client sends the public and
+ * evaluation keys to the server).  bm_pk_import takes the coefficient-domain
+ * words[2][L+1][N] of a public key (b then a, as bm_pk_export writes them).
+ * bm_evk_import takes words[1 + n_galois][dnum][2][L+1+K][N]: the
+ * relinearisation key, then the Galois key of element galois[i] for each i,
+ * each digit j as component 0 then 1 (as bm_evk_export writes them).  Keys
+ * made by bm_keygen and the same words imported give bit-identical results.
+ * BM_EINVAL: a size other than stated, a word not below its limb's prime, a
+ * Galois element that is even, not in (1, 2N) or repeated.  bm_evk_galois
+ * lists the Galois elements of an evaluation key in increasing order (at most
+ * cap of them; *n receives the count). */
+int bm_pk_import(bm_ctx *ctx, const uint64_t *words, size_t n_words, bm_pk **out);
+int bm_evk_import(bm_ctx *ctx, const uint64_t *galois, size_t n_galois, const uint64_t *words,
+                  size_t n_words, bm_evk **out);
+int bm_evk_galois(const bm_evk *evk, uint64_t *galois, size_t cap, size_t *n);
 void bm_sk_free(bm_sk *sk);
 void bm_pk_free(bm_pk *pk);
 void bm_evk_free(bm_evk *evk);

@@ -75,6 +75,9 @@ _SIGS = {
     "bm_sk_export": (ctypes.c_int, [_P, _P, _sz]),
     "bm_pk_export": (ctypes.c_int, [_P, _u32, _P, _sz]),
     "bm_evk_export": (ctypes.c_int, [_P, _u64, _u32, _u32, _P, _sz]),
+    "bm_pk_import": (ctypes.c_int, [_P, _P, _sz, _PP]),
+    "bm_evk_import": (ctypes.c_int, [_P, _P, _sz, _P, _sz, _PP]),
+    "bm_evk_galois": (ctypes.c_int, [_P, _P, _sz, ctypes.POINTER(_sz)]),
     "bm_sk_free": (None, [_P]),
     "bm_pk_free": (None, [_P]),
     "bm_evk_free": (None, [_P]),
@@ -343,6 +346,33 @@ def bm_evk_export(ctx, evk, galois, digit, comp, nprimes, N):
     _check(lib().bm_evk_export(evk, int(galois), int(digit), int(comp), _ptr(w), w.size),
            "bm_evk_export", ctx)
     return w
+
+
+def bm_pk_import(ctx, words):
+    """words: [2][L+1][N] uint64 coefficient-domain public key (b, a)."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    h = _out()
+    _check(lib().bm_pk_import(ctx, _ptr(w), w.size, ctypes.byref(h)), "bm_pk_import", ctx)
+    return h
+
+
+def bm_evk_import(ctx, galois, words):
+    """words: [1 + len(galois)][dnum][2][L+1+K][N] uint64: the relinearisation
+    key, then the Galois key of each element in `galois`."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    g = np.ascontiguousarray(galois, dtype=np.uint64)
+    h = _out()
+    _check(lib().bm_evk_import(ctx, _ptr(g) if g.size else None, g.size, _ptr(w), w.size, ctypes.byref(h)),
+           "bm_evk_import", ctx)
+    return h
+
+
+def bm_evk_galois(evk):
+    n = _sz(0)
+    _check(lib().bm_evk_galois(evk, None, 0, ctypes.byref(n)), "bm_evk_galois")
+    g = np.zeros(n.value, dtype=np.uint64)
+    _check(lib().bm_evk_galois(evk, _ptr(g) if g.size else None, g.size, ctypes.byref(n)), "bm_evk_galois")
+    return [int(x) for x in g]
 
 
 def bm_sk_free(h):

@@ -261,7 +261,9 @@ class Profiler {
 };
 
 // RAII device buffer of u64 words from the context's current pool; it goes
-// back to the pool it came from (a graph's private pool during a capture).
+// back to the pool it came from (a graph's private pool during a capture) and
+// keeps that pool alive, so a buffer may outlive the context or server lane
+// that made it.
 class DBuf {
  public:
   DBuf() = default;
@@ -275,7 +277,7 @@ class DBuf {
   size_t words() const { return words_; }
 
  private:
-  DevicePool* pool_ = nullptr;
+  std::shared_ptr<DevicePool> pool_;
   u64* p_ = nullptr;
   size_t words_ = 0;
 };
@@ -284,7 +286,7 @@ class DBuf {
 // result copied out of out_slot.  Its scratch lives in its own pool.
 struct GraphEntry {
   std::vector<uint64_t> key;
-  std::unique_ptr<DevicePool> pool;
+  std::shared_ptr<DevicePool> pool;
   DBuf q_slot, out_slot;
   hipGraphExec_t exec = nullptr;
   ~GraphEntry();
@@ -312,7 +314,7 @@ struct Ctx {
   std::vector<u64> cdt;            // Gaussian cumulative table (38 entries)
   hipStream_t stream = nullptr;    // current stream of this context
   hipStream_t own_stream = nullptr;
-  std::unique_ptr<DevicePool> pool;
+  std::shared_ptr<DevicePool> pool;
   std::shared_ptr<const AllocHook> hook;   // caller's allocator for pools made from now on
   // device tables
   PrimeC* d_primes = nullptr;

@@ -356,6 +356,39 @@ int bm_rotations_enroll(const bm_ctx* ctx, uint32_t d, uint32_t k, int32_t* out,
   });
 }
 
+// device table of an evaluation key's Galois keys by g / 2 (0 where absent),
+// read by the hoisted rotation sums
+static void build_gtab(Ctx& c, bm_evk* e) {
+  std::vector<u64> tab(c.M / 2, 0);
+  for (auto& kv : e->gk) tab[kv.first >> 1] = (u64)(uintptr_t)kv.second->k.p();
+  e->gtab = DBuf(&c, c.M / 2);
+  HIP_OK(dev::memcpy_async(e->gtab.p(), tab.data(), tab.size() * sizeof(u64), hipMemcpyHostToDevice, c.stream));
+  sync(c);
+}
+
+// words[polys][limbs][N] (coefficient domain) must hold residues of their limbs' primes
+static void check_residues(const Ctx& c, const uint64_t* words, size_t polys, int limbs) {
+  for (size_t pz = 0; pz < polys; ++pz)
+    for (int l = 0; l < limbs; ++l) {
+      const u64 q = c.primes[l].q;
+      const uint64_t* w = words + (pz * limbs + l) * c.N;
+      for (size_t i = 0; i < c.N; ++i)
+        if (w[i] >= q) BM_THROW(BM_EINVAL, "a word is not a residue of its limb's prime");
+    }
+}
+
+// switching key from coefficient-domain words[dnum][2][L+1+K][N] into the
+// device form (evaluation domain, FP64 values)
+static void load_switch_key(Ctx& c, const uint64_t* words, DBuf& key) {
+  const int np = c.nprimes();
+  const size_t polys = (size_t)c.dnum * 2;
+  check_residues(c, words, polys, np);
+  key = DBuf(&c, polys * np * c.N);
+  ev::import_coeffs(c, words, (int)polys, np, key.p());
+  kern::words_f64(c, key.p(), polys * np * c.N, true);
+  sync(c);
+}
+
 int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot, bm_sk** sk,
               bm_pk** pk, bm_evk** evk) {
   return guarded(ctx, [&] {
@@ -390,13 +423,7 @@ int bm_keygen(bm_ctx* ctx, uint64_t seed, const int32_t* rotations, size_t n_rot
         ev::keygen_switch(c, seed, ev::DOM_GK_A, ev::DOM_GK_E, g * (u64)c.dnum, s.get(), sg.p(), key->k);
         e->gk.emplace(g, std::move(key));
       }
-      // device table of the Galois keys by g / 2, for the hoisted rotation sums
-      std::vector<u64> tab(c.M / 2, 0);
-      for (auto& kv : e->gk) tab[kv.first >> 1] = (u64)(uintptr_t)kv.second->k.p();
-      e->gtab = DBuf(&c, c.M / 2);
-      HIP_OK(dev::memcpy_async(e->gtab.p(), tab.data(), tab.size() * sizeof(u64), hipMemcpyHostToDevice,
-                               c.stream));
-      sync(c);
+      build_gtab(c, e.get());
     }
     sync(c);
     if (sk) *sk = s.release();
@@ -443,6 +470,61 @@ int bm_evk_export(const bm_evk* evk, uint64_t galois, uint32_t digit, uint32_t c
     HIP_OK(dev::memcpy_async(words, tmp.p(), ln * sizeof(u64), hipMemcpyDeviceToHost, c.stream));
     sync(c);
   });
+}
+
+int bm_pk_import(bm_ctx* ctx, const uint64_t* words, size_t n_words, bm_pk** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && words && out, BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    const size_t ln = (size_t)(c.L + 1) * c.N;
+    REQUIRE(n_words == 2 * ln, BM_EINVAL, "public key import needs 2 (L+1) N words");
+    check_residues(c, words, 2, c.L + 1);
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_pk> p(new bm_pk);
+    p->ctx = ctx;
+    p->pk = DBuf(&c, 2 * ln);
+    ev::import_coeffs(c, words, 2, c.L + 1, p->pk.p());
+    *out = p.release();
+  });
+}
+
+int bm_evk_import(bm_ctx* ctx, const uint64_t* galois, size_t n_galois, const uint64_t* words, size_t n_words,
+                  bm_evk** out) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && words && out && (n_galois == 0 || galois), BM_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    const size_t per = (size_t)c.dnum * 2 * c.nprimes() * c.N;
+    REQUIRE(n_words == (1 + n_galois) * per, BM_EINVAL, "evaluation key import needs (1 + n_galois) keys");
+    std::set<u64> seen;
+    for (size_t i = 0; i < n_galois; ++i) {
+      const u64 g = galois[i];
+      REQUIRE((g & 1) && g > 1 && g < c.M && !seen.count(g), BM_EINVAL,
+              "Galois elements must be distinct odd values in (1, 2N)");
+      seen.insert(g);
+    }
+    c.use_stream(nullptr);
+    std::unique_ptr<bm_evk> e(new bm_evk);
+    e->ctx = ctx;
+    load_switch_key(c, words, e->rlk.k);
+    for (size_t i = 0; i < n_galois; ++i) {
+      std::unique_ptr<bm_switch_key> key(new bm_switch_key);
+      load_switch_key(c, words + (1 + i) * per, key->k);
+      e->gk.emplace(galois[i], std::move(key));
+    }
+    build_gtab(c, e.get());
+    *out = e.release();
+  });
+}
+
+int bm_evk_galois(const bm_evk* evk, uint64_t* galois, size_t cap, size_t* n) {
+  if (!evk || !n || (cap && !galois)) return BM_EINVAL;
+  *n = evk->gk.size();
+  size_t i = 0;
+  for (auto& kv : evk->gk) {
+    if (i >= cap) break;
+    galois[i++] = kv.first;
+  }
+  return BM_OK;
 }
 
 void bm_sk_free(bm_sk* sk) { delete sk; }

@@ -121,7 +121,7 @@ void DevicePool::set_hook(std::shared_ptr<const AllocHook> hook) {
   hook_ = std::move(hook);
 }
 
-DBuf::DBuf(Ctx* c, size_t words) : pool_(c->pool.get()), words_(words) {
+DBuf::DBuf(Ctx* c, size_t words) : pool_(c->pool), words_(words) {
   p_ = words ? (u64*)pool_->alloc(words * sizeof(u64)) : nullptr;
 }
 
@@ -132,7 +132,7 @@ DBuf::~DBuf() {
 DBuf& DBuf::operator=(DBuf&& o) noexcept {
   if (this != &o) {
     if (p_) pool_->release(p_, words_ * sizeof(u64));
-    pool_ = o.pool_;
+    pool_ = std::move(o.pool_);
     p_ = o.p_;
     words_ = o.words_;
     o.p_ = nullptr;

@@ -15,6 +15,7 @@
 #include <hip/hip_ext.h>
 
 #include "bm_internal.hpp"
+#include "fp64_modarith.hpp"
 
 namespace bm {
 namespace {
@@ -196,59 +197,16 @@ __global__ void __launch_bounds__(TPB) k_ntt_pass(const u64* __restrict__ in, si
 // taken from V polynomials that share the prime (last 8 stages, row twiddles);
 // ONE = a whole N = 4096 polynomial.
 
-__device__ __forceinline__ double fmul_mod(double a, double w, double wq, double q) {
-  const double hi = __dmul_rn(a, w);
-  const double lo = __fma_rn(a, w, -hi);
-  const double qt = rint(__dmul_rn(a, wq));
-  return __dadd_rn(__fma_rn(-qt, q, hi), lo);
-}
-
-// a w mod q for |a|, w < q < 2^51, quotient from fl(fl(a w) fl(1/q)): it is
-// within 0.5 + 3 (a w / q) 2^-53 < 1.25 of a w / q, so |r| <= 1.25 q, and both
-// the FMA (an integer below 2^53) and the final add are exact.
-__device__ __forceinline__ double fmul_mod_q(double a, double w, double qi, double q) {
-  const double hi = __dmul_rn(a, w);
-  const double lo = __fma_rn(a, w, -hi);
-  const double qt = rint(__dmul_rn(hi, qi));
-  return __dadd_rn(__fma_rn(-qt, q, hi), lo);
-}
-
-__device__ __forceinline__ double fred(double a, double qi, double q) {
-  return __fma_rn(-rint(__dmul_rn(a, qi)), q, a);
-}
-
-// exact conversions for 0 <= v < 2^52
-__device__ __forceinline__ double u64_to_f(u64 v) {
-  return __fma_rn((double)(u32)(v >> 32), 4294967296.0, (double)(u32)v);
-}
-__device__ __forceinline__ u64 f_to_u64(double x) {
-  const u32 h = (u32)__dmul_rn(x, 1.0 / 4294967296.0);          // truncation: floor for x >= 0
-  const u32 l = (u32)__fma_rn(-(double)h, 4294967296.0, x);
-  return ((u64)h << 32) | l;
-}
-
-// Sum of exact products v * w mod q (v, w residues in [0, q)) carried in FP64:
-// each product lies within 1.25 q of 0 (fmul_mod_q), the running sum is
-// folded back to |s| <= q/2 + 1 after every second term, so it stays below
-// 3q < 2^53; residue() returns the exact sum in [0, q).
-struct FAcc {
-  double s = 0.0;
-  int n = 0;
-  __device__ __forceinline__ void add(double v, double w, double qi, double q) {
-    s = __dadd_rn(s, fmul_mod_q(v, w, qi, q));
-    if (++n == 2) { s = fred(s, qi, q); n = 0; }
-  }
-  // add one product already reduced by fmul_mod
-  __device__ __forceinline__ void add_f(double p, double qi, double q) {
-    s = __dadd_rn(s, p);
-    if (++n == 2) { s = fred(s, qi, q); n = 0; }
-  }
-  __device__ __forceinline__ u64 residue(double qi, double q) const {
-    double r = fred(s, qi, q);
-    r = r < 0.0 ? __dadd_rn(r, q) : r;
-    return f_to_u64(r);
-  }
-};
+// The arithmetic itself (fmul_mod, fmul_mod_q, fred, the exact conversions,
+// FAcc and the radix-16 phases) lives in fp64_modarith.hpp, shared with a
+// host build that checks it against exact integers at the extremes of these
+// bounds.
+using fpm::fmul_mod;
+using fpm::fmul_mod_q;
+using fpm::fred;
+using fpm::u64_to_f;
+using fpm::f_to_u64;
+using fpm::FAcc;
 
 // Issue-rate probe of the butterfly arithmetic above, register-resident: each
 // thread runs 8 independent chains of forward butterflies (u, v) <- (u + t,
@@ -707,44 +665,11 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
       for (int j = 0; j < 16; ++j) x[j] = sh[v * VS + pad(addr(p, j))];
     }
-    if (!INV) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if ((k == 0 && ph > 0) || k == 2) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
-        }
-        const int step = 8 >> k;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j & step) continue;
-          double w, wq;
-          twid(p, k, hi, j, w, wq);
-          const double T = fmul_mod(x[j + step], w, wq, q);
-          const double U = x[j];
-          x[j] = __dadd_rn(U, T);
-          x[j + step] = __dsub_rn(U, T);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 3; k >= 0; --k) {
-        if ((k == 3 && ph > 0) || k == 1) {
-#pragma unroll
-          for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
-        }
-        const int step = 8 >> k;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j & step) continue;
-          double w, wq;
-          twid(p, k, hi, j, w, wq);
-          const double U = x[j], Vv = x[j + step];
-          x[j] = __dadd_rn(U, Vv);
-          x[j + step] = fmul_mod(__dsub_rn(U, Vv), w, wq, q);
-        }
-      }
-    }
+    auto tw_p = [&](int k, int j, double& w, double& wq) { twid(p, k, hi, j, w, wq); };
+    if (!INV)
+      fpm::ct_phase16(x, ph > 0, qi, q, tw_p);
+    else
+      fpm::gs_phase16(x, ph > 0, qi, q, tw_p);
     if (ph + 1 < PH) {
       __syncthreads();
 #pragma unroll

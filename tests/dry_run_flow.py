@@ -324,7 +324,134 @@ def server_from_threads():
     print("server from threads ok", flush=True)
 
 
+def _is_prime(n):
+    if n < 2 or n % 2 == 0:
+        return n == 2
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        r += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        x = pow(a, d, n)
+        if x in (1, n - 1) or a % n == 0:
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def _primes_below(bits, M, count):
+    out, c = [], ((1 << bits) - 1) // M * M + 1
+    while len(out) < count:
+        if c < (1 << bits) and _is_prime(c):
+            out.append(c)
+        c -= M
+    return out
+
+
+def generic_rings():
+    """Ring degrees other than the presets' (the generic integer transform):
+    transforms, a match at every schedule, expansion and rotations."""
+    for log_n in (10, 13):
+        N = 1 << log_n
+        p = bm.bm_params_preset(1)
+        p.log_n = log_n
+        for i, v in enumerate(_primes_below(50, 2 * N, 1) + _primes_below(40, 2 * N, 2)):
+            p.q[i] = v
+        p.p[0] = _primes_below(51, 2 * N, 1)[0]
+        ctx = bm.bm_ctx_create(p, 0)
+        rots = sorted(set(bm.bm_rotations_for(16, 1)) | set(bm.bm_rotations_for(16, 2)))
+        sk, pk, evk = bm.bm_keygen(ctx, 1, rots)
+        rng = np.random.default_rng(log_n)
+        for k in (1, 2):
+            X = rng.standard_normal((N // 16 + 7, 16)).astype(np.float32)
+            q = bm.bm_encrypt_query(ctx, pk, X[0], 1, 1)
+            g = bm.bm_encrypt_gallery(ctx, pk, X, k, 1, 10)
+            for s in (1, 2, 1 | bm.BM_LEVEL_MIN):
+                r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
+                bm.bm_decrypt_scores(ctx, sk, r, X.shape[0])
+                bm.bm_result_free(r)
+            bm.bm_ct_free(q)
+            bm.bm_gallery_free(g)
+        for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+            f(h)
+        bm.bm_ctx_free(ctx)
+        print("ring N=2^%d ok" % log_n, flush=True)
+
+
+def key_import():
+    """Keys exported in the coefficient domain and imported again; the host
+    rejects malformed key words."""
+    p = bm.bm_params_preset(1)
+    ctx = bm.bm_ctx_create(p, 0)
+    rots = bm.bm_rotations_for(16, 1)
+    sk, pk, evk = bm.bm_keygen(ctx, 1, rots)
+    gal = bm.bm_evk_galois(evk)
+    assert len(gal) == len(set(rots)) and gal == sorted(gal)
+    N, L1, npr = p.N, p.n_q, p.n_q + p.n_p
+    dnum = -(-p.n_q // p.alpha)
+    pkw = np.stack([bm.bm_pk_export(ctx, pk, c, L1, N) for c in (0, 1)])
+    evw = np.stack([np.stack([np.stack([bm.bm_evk_export(ctx, evk, g, j, c, npr, N) for c in (0, 1)])
+                              for j in range(dnum)]) for g in [0] + gal])
+    pk2 = bm.bm_pk_import(ctx, np.zeros_like(pkw))
+    evk2 = bm.bm_evk_import(ctx, gal, np.zeros_like(evw))
+    assert bm.bm_evk_galois(evk2) == gal
+
+    def status(f):
+        try:
+            f()
+        except bm.BMError as e:
+            return e.code
+        return bm.BM_OK
+    big = np.zeros_like(pkw)
+    big[1, 2, 5] = p.q[2]                      # not a residue of its limb's prime
+    cases = [
+        ("public key of the wrong size", lambda: bm.bm_pk_import(ctx, pkw[:, :2]), bm.BM_EINVAL),
+        ("public key word not reduced", lambda: bm.bm_pk_import(ctx, big), bm.BM_EINVAL),
+        ("evaluation key of the wrong size", lambda: bm.bm_evk_import(ctx, gal, evw[:-1]), bm.BM_EINVAL),
+        ("even Galois element", lambda: bm.bm_evk_import(ctx, [2] + gal[1:], evw), bm.BM_EINVAL),
+        ("repeated Galois element", lambda: bm.bm_evk_import(ctx, [gal[0]] * len(gal), evw), bm.BM_EINVAL),
+        ("Galois element out of range", lambda: bm.bm_evk_import(ctx, [2 * N + 1] + gal[1:], evw), bm.BM_EINVAL),
+    ]
+    for name, f, want in cases:
+        got = status(f)
+        assert got == want, "%s: status %d, expected %d" % (name, got, want)
+    for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk), (bm.bm_pk_free, pk2),
+                 (bm.bm_evk_free, evk2)):
+        f(h)
+    bm.bm_ctx_free(ctx)
+    print("key import ok", flush=True)
+
+
+def result_outlives_server():
+    """A served result freed after its server: its memory came from a server
+    lane, which the result keeps alive."""
+    p = bm.bm_params_preset(1)
+    ctx = bm.bm_ctx_create(p, 0)
+    sk, pk, evk = bm.bm_keygen(ctx, 1, bm.bm_rotations_for(16, 1))
+    X = np.ones((40, 16), dtype=np.float32)
+    srv = bm.bm_server_create(ctx, evk, 64 << 30, 2)
+    gid = bm.bm_server_add_gallery(srv, bm.bm_encrypt_gallery(ctx, pk, X, 1, 1, 10))
+    tk = bm.bm_server_submit(srv, gid, bm.bm_encrypt_query(ctx, pk, X[0], 1, 1))
+    bm.bm_server_drain(srv)
+    r = bm.bm_server_poll(srv, tk)
+    bm.bm_server_free(srv)
+    bm.bm_decrypt_scores(ctx, sk, r, 40)
+    bm.bm_result_free(r)
+    for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+        f(h)
+    bm.bm_ctx_free(ctx)
+    print("result outlives server ok", flush=True)
+
+
 if __name__ == "__main__":
+    result_outlives_server()
+    key_import()
+    generic_rings()
     server_from_threads()
     input_checks()
     allocator_hook_flow()

@@ -39,6 +39,24 @@ def oracle_keys(preset, rots):
 HOIST_SHAPES = {1: None, 2: [(128, 4)], 3: None, 4: [(128, 4)]}
 
 
+# N = 2^16 shapes of the face workload's k sweep, and the other dimensions the
+# fingerprint (16) and batched (64, 512) workloads run at
+C2_SHAPES = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
+C2_EXTRA_SHAPES = [(16, 1), (64, 2), (512, 16)]
+
+
+def face_rotations(preset=2):
+    """One rotation set for every N = 2^16 parity test, so that one key set
+    (oracle and library) serves them all: every key of the k sweep's shapes,
+    and the plain and hoisted keys of the other dimensions."""
+    P = ckks.Params.preset(preset)
+    r = set(all_rotations(preset, C2_SHAPES))
+    for d, k in C2_EXTRA_SHAPES:
+        r.update(obm.rotations_needed(P, d, k))
+        r.update(obm.hoisted_rotations(P, d, k))
+    return tuple(sorted(r))
+
+
 def all_rotations(preset, shapes):
     P = ckks.Params.preset(preset)
     r = set()

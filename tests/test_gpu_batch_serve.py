@@ -4,13 +4,12 @@ bit-identity), and requests are the same alone and in a mix."""
 import numpy as np
 import pytest
 
-from gpu_common import SEED, lib_ctx, lib_keys, all_rotations, assert_words_equal, log
+from gpu_common import SEED, lib_ctx, lib_keys, all_rotations, face_rotations, assert_words_equal, log
 from workloads import normalize
 
 pytestmark = pytest.mark.gpu
 
 SHAPES1 = [(16, 1), (16, 2), (16, 4), (8, 8)]
-SHAPES2 = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -20,7 +19,7 @@ def bm():
 
 
 def keys(preset):
-    return lib_keys(preset, all_rotations(preset, SHAPES1 if preset == 1 else SHAPES2))
+    return lib_keys(preset, all_rotations(preset, SHAPES1) if preset == 1 else face_rotations(preset))
 
 
 def words_of(bm, ctx, res, N):

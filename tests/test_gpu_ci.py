@@ -239,10 +239,10 @@ def test_ci_match_library_encryption_end_to_end(bm):
 
 
 @pytest.mark.parametrize("schedule", [0x102, 0x502])
-def test_ci_match_face_scale_sampled(bm, schedule):
+def test_ci_match_face_scale_bit_exact(bm, schedule):
     """N = 2^16 conjugate-invariant ring, 6,144 x 128-dim, k = 4: 2,048
     templates per group (twice the standard ring's), so three groups; the
-    oracle recomputes the first and last word for word."""
+    oracle recomputes all three word for word."""
     P, okeys, ctx, sk, pk, evk = setup(4)
     d, k = 128, 4
     w = face_gallery(seed=2)
@@ -263,9 +263,10 @@ def test_ci_match_face_scale_sampled(bm, schedule):
     lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
     log("library match")
     res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
-    log("oracle match on sampled groups")
+    log("oracle match, all %d groups" % G)
     want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
-                     groups=[0, G - 1], level_min=level_min, hoist=bool(schedule & 0x400))
+                     level_min=level_min, hoist=bool(schedule & 0x400))
+    assert sorted(want) == list(range(G))
     for g, o in want.items():
         got, sc = bm.bm_result_export(ctx, res, g, P.N)
         assert sc == o.scale

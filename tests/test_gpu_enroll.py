@@ -4,14 +4,14 @@ oracle's enrollment, and matching the enrolled gallery scores the users."""
 import numpy as np
 import pytest
 
-from gpu_common import SEED, lib_ctx, lib_keys, oracle_keys, all_rotations, ct_words, assert_words_equal, log
+from gpu_common import (SEED, lib_ctx, lib_keys, oracle_keys, all_rotations, face_rotations, ct_words,
+                        assert_words_equal, log)
 from oracle import ckks, blindmatch as obm
 from workloads import face_gallery, normalize
 
 pytestmark = pytest.mark.gpu
 
 C1_SHAPES = [(16, 1), (16, 2), (16, 4), (8, 8), (4, 1)]
-C2_SHAPES = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +21,7 @@ def bm():
 
 
 def setup(preset):
-    rots = all_rotations(preset, C1_SHAPES if preset == 1 else C2_SHAPES)
+    rots = all_rotations(preset, C1_SHAPES) if preset == 1 else face_rotations(preset)
     P, okeys = oracle_keys(preset, rots)
     return P, okeys, lib_ctx(preset), lib_keys(preset, rots)
 

@@ -9,15 +9,14 @@ compared with the FP64 cosine (1e-4).
 import numpy as np
 import pytest
 
-from gpu_common import (SEED, lib_ctx, lib_keys, oracle_keys, all_rotations, ct_words,
-                        assert_words_equal, log)
+from gpu_common import (SEED, lib_ctx, lib_keys, oracle_keys, all_rotations, face_rotations, ct_words,
+                        assert_words_equal, log, C2_SHAPES)
 from oracle import ckks, blindmatch as obm
 from workloads import tiny_gallery, face_gallery
 
 pytestmark = pytest.mark.gpu
 
 C1_SHAPES = [(16, 1), (16, 2), (16, 4), (8, 8), (4, 1)]
-C2_SHAPES = [(128, 1), (128, 2), (128, 4), (128, 8), (128, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -27,17 +26,25 @@ def bm():
 
 
 def setup(preset):
-    shapes = C1_SHAPES if preset == 1 else C2_SHAPES
-    rots = all_rotations(preset, shapes)
+    rots = all_rotations(1, C1_SHAPES) if preset == 1 else face_rotations(preset)
     P, okeys = oracle_keys(preset, rots)
     ctx = lib_ctx(preset)
     sk, pk, evk = lib_keys(preset, rots)
     return P, okeys, ctx, sk, pk, evk
 
 
-def random_ct(P, rng, limbs, comps=2):
-    return np.stack([np.stack([rng.integers(0, q, P.N, dtype=np.uint64) for q in P.q[:limbs]])
-                     for _ in range(comps)])
+def fill_words(rng, q, n, fill="random"):
+    """Residues mod q: uniform, all q - 1 (the largest operands the FP64
+    arithmetic meets), or a random mix of 0 and q - 1."""
+    if fill == "max":
+        return np.full(n, q - 1, dtype=np.uint64)
+    if fill == "mixed":
+        return np.where(rng.random(n) < 0.5, 0, q - 1).astype(np.uint64)
+    return rng.integers(0, q, n, dtype=np.uint64)
+
+
+def random_ct(P, rng, limbs, comps=2, fill="random"):
+    return np.stack([np.stack([fill_words(rng, q, P.N, fill) for q in P.q[:limbs]]) for _ in range(comps)])
 
 
 # ------------------------------------------------------------------ NTT (row a1)
@@ -97,6 +104,37 @@ def test_ntt_is_negacyclic_evaluation(bm, preset):
     assert_words_equal(dev.cpu().numpy().view(np.uint64), host, "inverse(forward(a))")
 
 
+@pytest.mark.parametrize("fill", ["max", "mixed"])
+def test_ntt_extreme_words(bm, fill):
+    """N = 2^16, every chain and special prime: polynomials of all q - 1 (and a
+    mix of 0 and q - 1) through the forward transform (sampled positions
+    against Python-integer evaluation) and back (every word)."""
+    import torch
+    P = ckks.Params.preset(2)
+    ctx = lib_ctx(2)
+    primes = P.q + P.p
+    rng = np.random.default_rng(17)
+    host = np.stack([fill_words(rng, q, P.N, fill) for q in primes])
+    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+    log("ntt extreme words (%s)" % fill)
+    bm.bm_ntt(ctx, dev.data_ptr(), 1, list(range(len(primes))), inverse=False)
+    torch.cuda.synchronize()
+    fwd = dev.cpu().numpy().view(np.uint64)
+    for li, q in enumerate(primes):
+        psi = library_psi(q, P.N)
+        a = [int(v) for v in host[li]]
+        for j in (0, P.N - 1, int(rng.integers(P.N))):
+            w = pow(psi, 2 * brv(j, P.log_n) + 1, q)
+            acc, pw = 0, 1
+            for coef in a:
+                acc += coef * pw
+                pw = pw * w % q
+            assert int(fwd[li, j]) == acc % q, "prime %d position %d" % (li, j)
+    bm.bm_ntt(ctx, dev.data_ptr(), 1, list(range(len(primes))), inverse=True)
+    torch.cuda.synchronize()
+    assert_words_equal(dev.cpu().numpy().view(np.uint64), host, "inverse(forward(a))")
+
+
 # ------------------------------------------------------------------ keys and encryption
 
 @pytest.mark.parametrize("preset", [1, 2])
@@ -145,12 +183,17 @@ def test_encode_within_one(bm, preset):
 
 # ------------------------------------------------------------------ primitive operations (a2-a4, a6)
 
-@pytest.mark.parametrize("preset,limbs", [(1, 3), (1, 2), (2, 8), (2, 7), (2, 3)])
-def test_ops_bit_exact(bm, preset, limbs):
+@pytest.mark.parametrize("preset,limbs,fill", [(1, 3, "random"), (1, 2, "random"), (2, 8, "random"),
+                                               (2, 7, "random"), (2, 3, "random"), (2, 8, "max"), (2, 3, "max"),
+                                               (2, 4, "mixed"), (1, 3, "max")])
+def test_ops_bit_exact(bm, preset, limbs, fill):
+    """Every primitive op word for word against the oracle; `max` fills every
+    word with q - 1 and `mixed` with 0 or q - 1, the extremes the FP64
+    arithmetic of the transforms and key inner products is bounded for."""
     P, okeys, ctx, sk, pk, evk = setup(preset)
     rng = np.random.default_rng(100 + limbs)
-    log("ops preset %d limbs %d" % (preset, limbs))
-    a_w, b_w = random_ct(P, rng, limbs), random_ct(P, rng, limbs)
+    log("ops preset %d limbs %d fill %s" % (preset, limbs, fill))
+    a_w, b_w = random_ct(P, rng, limbs, fill=fill), random_ct(P, rng, limbs, fill=fill)
     sa = sb = P.scale
     oa, ob = ckks.Ciphertext(list(a_w), limbs, sa), ckks.Ciphertext(list(b_w), limbs, sb)
     la, lb = bm.bm_ct_import(ctx, a_w, sa), bm.bm_ct_import(ctx, b_w, sb)
@@ -345,18 +388,25 @@ def test_match_library_encryption_end_to_end(bm):
     assert bm.bm_top1(scores)[0] == w["known"]
 
 
+def face_groups(G, level_min):
+    """Groups the oracle recomputes at N = 2^16: every group of a minimum-level
+    schedule (a few seconds each), else the first, a middle and the last."""
+    return None if level_min and G <= 8 else sorted({0, G // 2, G - 1})
+
+
 @pytest.mark.parametrize("k,schedule", [(1, 1), (4, 1), (4, 2), (16, 2), (1, 0x101), (4, 0x102),
                                         (8, 0x102)])
-def test_match_face_scale_sampled(bm, k, schedule):
+def test_match_face_scale_bit_exact(bm, k, schedule):
     """N = 2^16, 6,144 x 128-dim gallery: the full match runs on the GPU; the
-    oracle recomputes two sampled groups (first and last) word for word."""
+    oracle recomputes every group of the minimum-level schedules and three
+    groups (first, middle, last) of the natural-level ones, word for word."""
     P, okeys, ctx, sk, pk, evk = setup(2)
     d = 128
     w = face_gallery(seed=2)
     X = w["gallery"]
     qv = w["query_known"]
     c, T = obm.layout(P, d, k)
-    log("match N=2^16 d=128 k=%d S%d: oracle gallery encryption" % (k, schedule))
+    log("match N=2^16 d=128 k=%d S%#x: oracle gallery encryption" % (k, schedule))
     m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
     cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 9)
     gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 5000)
@@ -369,9 +419,11 @@ def test_match_face_scale_sampled(bm, k, schedule):
     lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
     log("library match")
     res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
-    log("oracle match on sampled groups")
+    groups = face_groups(G, level_min)
+    log("oracle match on groups %s" % ("all %d" % G if groups is None else groups))
     want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
-                     groups=[0, G - 1], level_min=level_min)
+                     groups=groups, level_min=level_min)
+    assert len(want) == (G if groups is None else len(groups))
     for g, o in want.items():
         got, sc = bm.bm_result_export(ctx, res, g, P.N)
         assert sc == o.scale
@@ -380,6 +432,60 @@ def test_match_face_scale_sampled(bm, k, schedule):
     cos = X.astype(np.float64) @ qv.astype(np.float64)
     assert np.max(np.abs(scores - cos)) < 1e-4
     assert bm.bm_top1(scores)[0] == w["known"]
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    if lm:
+        bm.bm_masks_free(lm)
+
+
+# Other feature lengths at N = 2^16: the fingerprint workload's 16-dim
+# templates (a prefix of its gallery, 2,048 templates per ciphertext, the last
+# group ragged) and the batched workload's 64- and 512-dim shapes.
+DIMS = [(16, 1, 3 * 2048 + 500, 0x101), (16, 1, 3 * 2048 + 500, 0x501), (16, 1, 2048 + 100, 0x001),
+        (64, 2, 2500, 0x102), (64, 2, 2500, 0x502), (512, 16, 1500, 0x102), (512, 16, 1500, 0x502)]
+
+
+@pytest.mark.parametrize("d,k,R,schedule", DIMS)
+def test_match_face_scale_dims_bit_exact(bm, d, k, R, schedule):
+    """N = 2^16 at d = 16 (k = 1), 64 (k = 2) and 512 (k = 16): every result
+    word of every group equals the oracle's; scores within 1e-4 of the cosine."""
+    from workloads import fingerprint_gallery, normalize
+    P, okeys, ctx, sk, pk, evk = setup(2)
+    if d == 16:
+        w = fingerprint_gallery(seed=3, rows=R)
+        X, qv = w["gallery"], w["query"]
+    else:
+        rng = np.random.default_rng(d + R)
+        X = normalize(rng.standard_normal((R, d)))
+        qv = normalize(X[R // 3] + 0.05 * rng.standard_normal(d))
+    c, T = obm.layout(P, d, k)
+    log("match N=2^16 d=%d k=%d R=%d schedule %#x: oracle gallery encryption" % (d, k, R, schedule))
+    m = ckks.encode(obm.pack_query(P, qv, d), P.scale, P.N)
+    cq_o = ckks.encrypt(P, okeys.pk, m, len(P.q), P.scale, SEED, 13)
+    gal_o, words, lg = oracle_gallery_words(P, okeys, X, d, k, 7000)
+    G = len(gal_o)
+    assert G == -(-R // T)
+    level_min, hoist = bool(schedule & 0x100), bool(schedule & 0x400)
+    ql = obm.level_min_shape(P, k, lg)[1] if level_min else len(P.q)
+    masks, mscale = obm.mask_coeffs(P, d, k, ql) if k > 1 else (None, None)
+    cq = bm.bm_ct_import(ctx, ct_words(cq_o), P.scale)
+    gal = bm.bm_gallery_import(ctx, words, d, k, lg, P.scale, R)
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale) if k > 1 else None
+    log("library match")
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
+    log("oracle match, all %d groups" % G)
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
+                     level_min=level_min, hoist=hoist)
+    assert sorted(want) == list(range(G))
+    for g, o in want.items():
+        got, sc = bm.bm_result_export(ctx, res, g, P.N)
+        assert sc == o.scale
+        assert_words_equal(got, ct_words(o), "group %d" % g)
+    scores = bm.bm_decrypt_scores(ctx, sk, res, R)
+    cos = X.astype(np.float64) @ qv.astype(np.float64)
+    assert np.max(np.abs(scores - cos)) < 1e-4
+    assert bm.bm_top1(scores)[0] == int(np.argmax(cos))
     bm.bm_ct_free(cq)
     bm.bm_gallery_free(gal)
     bm.bm_result_free(res)
@@ -482,7 +588,8 @@ def test_match_face_scale_compressed_bit_exact(bm, k, schedule):
 # ------------------------------------------------------------------ hoisted schedule
 
 @pytest.mark.parametrize("d,k,schedule", [(16, 1, 0x401), (16, 2, 0x402), (16, 4, 0x401), (8, 8, 0x402),
-                                          (16, 4, 0x502), (16, 1, 0x701)])
+                                          (16, 4, 0x502), (16, 4, 0x501), (16, 1, 0x701), (16, 1, 0x702),
+                                          (16, 1, 0x601), (16, 1, 0x602)])
 def test_match_hoisted_small_ring_bit_exact(bm, d, k, schedule):
     """N = 2^12, BM_HOIST (with the minimum level and compression too): every
     word equals the oracle's hoisted schedule."""
@@ -530,9 +637,11 @@ def normalize_rows(X):
 
 
 @pytest.mark.parametrize("schedule", [0x502, 0x402])
-def test_match_face_scale_hoisted_sampled(bm, schedule):
-    """N = 2^16, 6,144 x 128-dim, k = 4, hoisted: two sampled groups word for
-    word against the oracle, scores against the cosine."""
+def test_match_face_scale_hoisted_bit_exact(bm, schedule):
+    """N = 2^16, 6,144 x 128-dim, k = 4, hoisted (0x502 is the benchmarked
+    configuration): every group word for word against the oracle (the six
+    groups span all three element groups of the grouped key inner product),
+    scores against the cosine."""
     P, okeys, ctx, sk, pk, evk = setup(2)
     d, k = 128, 4
     w = face_gallery(seed=2)
@@ -550,9 +659,10 @@ def test_match_face_scale_hoisted_sampled(bm, schedule):
     lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
     log("library match")
     res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=schedule, out_limbs=2)
-    log("oracle match on sampled groups")
+    log("oracle match, all %d groups" % G)
     want = obm.match(P, okeys, cq_o, gal_o, d, k, schedule & 0xff, masks, mscale, out_limbs=2,
-                     groups=[0, G - 1], level_min=level_min, hoist=True)
+                     level_min=level_min, hoist=True)
+    assert sorted(want) == list(range(G)) and G == 6
     for g, o in want.items():
         got, sc = bm.bm_result_export(ctx, res, g, P.N)
         assert sc == o.scale
@@ -561,6 +671,41 @@ def test_match_face_scale_hoisted_sampled(bm, schedule):
     cos = X.astype(np.float64) @ qv.astype(np.float64)
     assert np.max(np.abs(scores - cos)) < 1e-4
     assert bm.bm_top1(scores)[0] == w["known"]
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    bm.bm_result_free(res)
+    bm.bm_masks_free(lm)
+
+
+@pytest.mark.parametrize("fill", ["max", "mixed"])
+def test_match_extreme_words_face_scale(bm, fill):
+    """N = 2^16, k = 4, the benchmarked schedule (0x502): a query and a
+    two-group gallery whose every word is q - 1 (or a mix of 0 and q - 1)
+    through the expansion, tensor, fused relinearisation and rescale, the
+    hoisted key inner products and the fused ModDown: every word equals the
+    oracle's (the words decrypt to nothing meaningful; only the arithmetic is
+    under test)."""
+    P, okeys, ctx, sk, pk, evk = setup(2)
+    d, k = 128, 4
+    rng = np.random.default_rng(23)
+    lg = obm.gallery_limbs(P, k)
+    G = 2
+    qw = random_ct(P, rng, len(P.q), fill=fill)
+    gw = np.stack([np.stack([random_ct(P, rng, lg, fill=fill) for _ in range(k)]) for _ in range(G)])
+    cq_o = ckks.Ciphertext(list(qw), len(P.q), P.scale)
+    gal_o = [[ckks.Ciphertext(list(gw[g, i]), lg, P.scale) for i in range(k)] for g in range(G)]
+    ql = obm.level_min_shape(P, k, lg)[1]
+    masks, mscale = obm.mask_coeffs(P, d, k, ql)
+    log("extreme-word match (%s)" % fill)
+    cq = bm.bm_ct_import(ctx, qw, P.scale)
+    gal = bm.bm_gallery_import(ctx, gw, d, k, lg, P.scale, G * obm.layout(P, d, k)[1])
+    lm = bm.bm_masks_import(ctx, d, k, np.stack(masks), mscale)
+    res = bm.bm_match(ctx, evk, cq, gal, lm, schedule=0x502, out_limbs=2)
+    want = obm.match(P, okeys, cq_o, gal_o, d, k, 2, masks, mscale, out_limbs=2, level_min=True, hoist=True)
+    for g, o in want.items():
+        got, sc = bm.bm_result_export(ctx, res, g, P.N)
+        assert sc == o.scale
+        assert_words_equal(got, ct_words(o), "group %d" % g)
     bm.bm_ct_free(cq)
     bm.bm_gallery_free(gal)
     bm.bm_result_free(res)

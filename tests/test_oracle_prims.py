@@ -148,6 +148,9 @@ def test_uniform_sampler_rule():
 def test_gaussian_table_and_sampler():
     cdt = ckks.gaussian_cdt(3.2)
     assert len(cdt) == 38
+    # absolute value of the first entry, floor(2^64 F(-19)), computed
+    # independently of this code when the sampler was specified
+    assert cdt[0] == 50861754284
     assert all(a < b for a, b in zip(cdt, cdt[1:]))
     # symmetry of the centred distribution: F(v) + F(-v-1) = 1
     for i in range(38):
