@@ -38,11 +38,7 @@ ALU_PEAK_GMODMUL = 39.3216e3 / 8.0
 # a 1 GiB device copy: x2.0 for FETCH_SIZE, x1.0 for WRITE_SIZE), kept with
 # the sha256 of the kernel source they were taken on and the workload; the
 # figure is reported only while both still match.
-TRAFFIC = {
-    ("kip_hoist", "k4_S2+levelmin+hoist"): dict(
-        bytes_per_launch=153954937, algorithmic_bytes_per_launch=180355072,
-        kernels_sha256="f1890b07ec5c1be1ecb70da3f5c2742d68a12c47782455c08f82519f97c3755f"),
-}
+TRAFFIC = {}
 
 
 def kernels_sha256():
@@ -271,28 +267,41 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = n_tmpl * args.steps / elapsed
 
-    # ---- roofline of the kernel with the most device time
+    # ---- roofline: every kernel on its own (HIP events stamped with each
+    # launch's execution interval), the one with the most device time as the
+    # headline entry, and the whole match against its compulsory traffic
     roof = None
     if prof:
-        name = max(prof, key=lambda n: prof[n]["ms"])
-        e = prof[name]
+        kernels = []
+        for n, e in sorted(prof.items(), key=lambda x: -x[1]["ms"]):
+            avg_s = e["ms"] / e["launches"] / 1e3
+            bpl = e["bytes"] / e["launches"]
+            kernels.append(dict(kernel=n, launches_per_step=round(e["launches"] / args.steps, 2),
+                                avg_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=int(bpl),
+                                achieved_gbs=round(bpl / avg_s / 1e9, 1),
+                                frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                                ms_per_step=round(e["ms"] / args.steps, 4)))
+        top = kernels[0]
+        e = prof[top["kernel"]]
         avg_s = e["ms"] / e["launches"] / 1e3
-        bytes_per = e["bytes"] / e["launches"]
-        ops_per = e["ops"] / e["launches"]
-        gbs = bytes_per / avg_s / 1e9
-        gmm = ops_per / avg_s / 1e9
-        f_hbm, f_alu = gbs / HBM_PEAK_GBS, gmm / ALU_PEAK_GMODMUL
-        roof = dict(bound="hbm", kernel=name, achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(f_hbm, 4), alu_gmodmul=round(gmm, 2), alu_frac=round(f_alu, 4),
-                    avg_us=round(avg_s * 1e6, 2), launches=e["launches"],
-                    algorithmic_bytes_per_launch=int(bytes_per), traffic=None)
-        roof["traffic"] = traffic_for(name, "k%d_%s" % (bk, sname(bs)), bytes_per)
+        gmm = e["ops"] / e["launches"] / avg_s / 1e9
+        roof = dict(bound="hbm", kernel=top["kernel"], achieved=top["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=top["frac"], avg_us=top["avg_us"], launches_per_step=top["launches_per_step"],
+                    algorithmic_bytes_per_launch=top["algorithmic_bytes_per_launch"],
+                    alu_gmodmul=round(gmm, 2), alu_frac=round(gmm / ALU_PEAK_GMODMUL, 4), traffic=None)
+        roof["traffic"] = traffic_for(top["kernel"], "k%d_%s" % (bk, sname(bs)), top["algorithmic_bytes_per_launch"])
         # the same kind of arithmetic at its measured register-resident rate
         mrate = measured_butterfly_rate(bm, ctx, params)
         roof["alu_measured_peak_gmodmul"] = round(mrate, 1)
         roof["alu_frac_measured"] = round(gmm / mrate, 4)
         step_ms_dev = sum(v["ms"] for v in prof.values()) / args.steps
         roof["kernel_share"] = round(e["ms"] / args.steps / max(step_ms_dev, 1e-9), 3)
+        roof["kernels"] = kernels
+        mb = match_compulsory_bytes(params, d, bk, bm.bm_gallery_info(gals[bk])[0], bs, params.out_limbs, bm)
+        roof["match"] = dict(compulsory_bytes=int(mb["total"]), parts=mb["parts"], ms_per_step=round(ms_step, 4),
+                             achieved_gbs=round(mb["total"] / (ms_step * 1e-3) / 1e9, 1),
+                             frac=round(mb["total"] / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             device_ms_per_step_eager=round(step_ms_dev, 4))
         breakdown = {n: round(v["ms"] / args.steps, 3) for n, v in sorted(prof.items(), key=lambda x: -x[1]["ms"])}
     else:
         breakdown = {}
@@ -334,8 +343,13 @@ def main():
             "natural_level_best": ({"config": canon_best, "ms_per_match": round(canon[canon_best], 3),
                                     "templates_per_s": round(n_tmpl / canon[canon_best] * 1e3, 1)}
                                    if canon_best else None),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "step_latency": {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "what": "back-to-back graph replays of one match on one stream (HIP events per "
+                                     "step); no arrivals or queueing: served query latency is config.serving"},
+            "arithmetic": "exact integer residues mod primes below 2^51, held in HBM as 64-bit words; the "
+                          "transforms, key inner products and tensor carry them as exact integers in FP64 "
+                          "registers (the ALU figures are FP64 issue rates)",
             "sweep_ms": {k: round(v, 3) for k, v in sweep.items()},
             "max_abs_err_vs_fp64_cosine": err, "top1_correct": bool(top == w["known"]),
             "kernel_ms_per_step": breakdown,
@@ -351,6 +365,54 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def match_compulsory_bytes(p, d, k, G, schedule, ctx_out_limbs, bm):
+    """Bytes one match must move at least: every gallery word at the limbs the
+    products use, every key word the key switches read (each key once, over
+    the target slots of its level), the query and the masks once, the result
+    ciphertexts once.  Mirrors the library's plan of the match (levels of
+    the products, of the rotate-and-sum and of the output).  No compression."""
+    N, L1, K, alpha = p.N, p.n_q, p.n_p, p.alpha
+    lmin, hoist = bool(schedule & bm.BM_LEVEL_MIN), bool(schedule & bm.BM_HOIST)
+    g_limbs = L1 if k == 1 else L1 - 1
+    t = min(3, g_limbs) if lmin else g_limbs
+    ql = t + 1 if k > 1 else t
+    nat = t - 1
+    ol = min(ctx_out_limbs or nat, nat)
+    rot = ol if lmin else nat
+    c = d // k
+
+    def key_words(limbs):        # one switching key read over the target slots of `limbs`
+        beta = -(-limbs // alpha)
+        return 2 * beta * (limbs + K) * N
+
+    if k > 1:
+        if hoist:
+            amounts = set()
+            for i in range(k):
+                for S in range(1, k):
+                    r = 0
+                    for tt in range(k.bit_length() - 1):
+                        if (S >> tt) & 1:
+                            r += (c << tt) if (i >> tt) & 1 else -(c << tt)
+                    amounts.add(r)
+            n_exp = len(amounts)
+        else:
+            n_exp = 2 * (k.bit_length() - 1)
+    else:
+        n_exp = 0
+    n_rot = (c - 1) if hoist else (c.bit_length() - 1)
+    parts = {
+        "gallery": 8 * G * k * 2 * t * N,
+        "query": 8 * 2 * ql * N,
+        "masks": 8 * k * ql * N if k > 1 else 0,
+        "expansion_keys": 8 * n_exp * key_words(ql - 1),
+        "relinearisation_key": 8 * key_words(t),
+        "rotation_keys": 8 * n_rot * key_words(rot),
+        "results": 8 * G * 2 * ol * N,
+    }
+    return {"total": sum(parts.values()), "parts": parts}
 
 
 def ci_variant(bm, torch, X, q, d, ks, scheds, known, sptr, graphs, sname, reps=10):

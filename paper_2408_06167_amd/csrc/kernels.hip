@@ -1415,6 +1415,7 @@ struct Prof {
   Prof(const Ctx& c, const char* name, double bytes, double ops) : on(c.prof && c.prof->on) {
     if (on) ev = c.prof->begin(name, bytes, ops);
   }
+  Prof(const Ctx& c, const std::string& name, double bytes, double ops) : Prof(c, name.c_str(), bytes, ops) {}
 };
 
 }  // namespace
@@ -1460,7 +1461,8 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   if (logn == 12) {
     chk_map(c, in, B, in_stride, m, "ntt input");
     chk_map(c, out, B, out_stride, m, "ntt output", true);
-    Prof pf(c, inverse ? "ntt_inv_one" : "ntt_fwd_one", 16.0 * elems, 0.5 * elems * 12);
+    Prof pf(c, inverse ? "k_ntt_fast<12, true, 2, 0>" : "k_ntt_fast<12, false, 2, 0>", 16.0 * elems,
+            0.5 * elems * 12);
     const size_t lds = (size_t)(4096 + 256 + 1) * sizeof(u64);
     const dim3 grid(1, (unsigned)m.n, (unsigned)B);
     if (inverse)
@@ -1487,7 +1489,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   auto col = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm, int last) {
     chk_map(c, src, B, ss, mm, "ntt column pass input");
     chk_map(c, dst, B, ds, mm, "ntt column pass output", true);
-    Prof pf(c, inverse ? "ntt_inv_col" : "ntt_fwd_col", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, inverse ? "k_ntt_fast<8, true, 0, 0>" : "k_ntt_fast<8, false, 0, 0>", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_COL>), gcol, dim3(256), lds_col, c.stream, src, ss, dst, ds, mm,
              c.d_primes, tw, tws, logn, 0, last, B, 1, FuseArgs{});
@@ -1499,7 +1501,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   auto row = [&](const u64* src, size_t ss, u64* dst, size_t ds, const LimbMap& mm) {
     chk_map(c, src, B, ss, mm, "ntt row pass input");
     chk_map(c, dst, B, ds, mm, "ntt row pass output", true);
-    Prof pf(c, inverse ? "ntt_inv_row" : "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, inverse ? "k_ntt_fast<8, true, 1, 0>" : "k_ntt_fast<8, false, 1, 0>", 16.0 * elems, 0.5 * elems * 8);
     if (inverse)
       LAUNCH((k_ntt_fast<8, true, NTT_ROW>), grow, dim3(16 * Vrow), lds_row, c.stream, src, ss, dst, ds,
              mm, c.d_primes, tw, tws, logn, 8, 0, B, vz, FuseArgs{});
@@ -1522,7 +1524,7 @@ void modmul_rate(const Ctx& c, int pid, int blocks, int iters, const u64* seed, 
     BM_THROW(BM_EINVAL, "launch check: modmul probe arguments");
   chk(seed, 1, 0, 0, 24, "modmul probe seed");
   chk(out, 1, 0, 0, (size_t)blocks * 256 * 16, "modmul probe output");
-  Prof pf(c, "modmul_probe", 0.0, 8.0 * 256 * blocks * iters);
+  Prof pf(c, "k_modmul_rate", 0.0, 8.0 * 256 * blocks * iters);
   LAUNCH(k_modmul_rate, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.d_primes, pid, iters, seed, out);
   check_launch();
 }
@@ -1532,7 +1534,7 @@ bool fused_ok(const Ctx& c) { return c.log_n == 16; }
 void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
   if (n == 0) return;
   chk(p, 1, 0, 0, n, "words_f64");
-  Prof pf(c, "words_f64", 16.0 * n, 0.0);
+  Prof pf(c, "k_words_f64", 16.0 * n, 0.0);
   const size_t bx = std::min<size_t>((n + TPB - 1) / TPB, 65536);
   LAUNCH(k_words_f64, dim3((unsigned)bx), dim3(TPB), 0, c.stream, p, n, to_f64 ? 1 : 0);
   check_launch();
@@ -1563,8 +1565,22 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
   const dim3 grow((unsigned)(N / 256 / R), (unsigned)m.n, (unsigned)((B + vz - 1) / vz));
   {
+    // distinct words: every output word once, every source word once (a
+    // digit's source limbs are read by each of its target slots, from L2)
     const double srcs = f.pro == 1 ? 2.0 : f.pro == 2 ? (double)c.K : 1.0;
-    Prof pf(c, "ntt_fwd_col_fused", 8.0 * elems * (1.0 + srcs), 0.5 * elems * 8 + 2.0 * srcs * elems);
+    double src_words;
+    if (f.pro == 1) {
+      const int limbs = (int)(f.mu - c.d_modup);
+      src_words = (double)N * B * limbs;
+    } else if (f.pro == 2) {
+      src_words = (double)N * B * c.K;
+    } else if (f.pro == 4) {
+      src_words = (double)N * B * (c.K + 1);
+    } else {
+      src_words = (double)N * B;
+    }
+    Prof pf(c, f.ci ? "k_ntt_fast<8, false, 0, 4>" : "k_ntt_fast<8, false, 0, 1>", 8.0 * (elems + src_words),
+            0.5 * elems * 8 + 2.0 * srcs * elems);
     if (f.ci)
       LAUNCH((k_ntt_fast<8, false, NTT_COL, 4>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
              (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
@@ -1574,15 +1590,15 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
     check_launch();
   }
   if (f.epi) {
-    Prof pf(c, "ntt_fwd_row_fused", 8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
+    Prof pf(c, "k_ntt_fast<8, false, 1, 2>", 8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
            (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
   } else if (f64_out) {
-    Prof pf(c, "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, "k_ntt_fast<8, false, 1, 3>", 16.0 * elems, 0.5 * elems * 8);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW, 3>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
            tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, FuseArgs{});
   } else {
-    Prof pf(c, "ntt_fwd_row", 16.0 * elems, 0.5 * elems * 8);
+    Prof pf(c, "k_ntt_fast<8, false, 1, 0>", 16.0 * elems, 0.5 * elems * 8);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts, tmp,
            ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, FuseArgs{});
   }
@@ -1595,7 +1611,7 @@ void ci_fold(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B,
              bool inverse) {
   chk_map(c, in, B, si, m, "ci fold input");
   chk_map(c, out, B, so, m, "ci fold output", true);
-  Prof pf(c, inverse ? "ci_unfold" : "ci_fold", 16.0 * c.N * m.n * B, 2.0 * c.N * m.n * B);
+  Prof pf(c, "k_ci_fold", 16.0 * c.N * m.n * B, 2.0 * c.N * m.n * B);
   size_t bx = (c.N / 2 + 1 + TPB * 2 - 1) / (TPB * 2);
   LAUNCH(k_ci_fold, dim3((unsigned)bx, (unsigned)m.n, (unsigned)B), dim3(TPB), 0, c.stream, in, si, out, so, m,
          c.d_primes, c.d_ci, (int)c.N, inverse ? 1 : 0);
@@ -1642,7 +1658,7 @@ void ntt_core(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     chk_map(c, src, B, ss, mm, "ntt pass input");
     chk_map(c, dst, B, ds, mm, "ntt pass output", true);
     const double elems = (double)N * m.n * B;
-    Prof pf(c, inverse ? "ntt_inv" : "ntt_fwd", 16.0 * elems, 0.5 * elems * logm);
+    Prof pf(c, inverse ? "k_ntt_pass<true>" : "k_ntt_pass<false>", 16.0 * elems, 0.5 * elems * logm);
     if (inverse)
       LAUNCH(k_ntt_pass<true>, grid, dim3(TPB), lds, c.stream, src, ss, dst, ds, mm,
                          c.d_primes, c.d_itw, c.d_itws, logn, logm, s0, col, last);
@@ -1673,7 +1689,7 @@ void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, i
                 size_t src_stride, const LimbMap& m) {
   chk(src, B, src_stride, 0, c.N, "reduce_int input");
   chk_map(c, out, B, out_stride, m, "reduce_int output");
-  Prof pf(c, "reduce_int", 8.0 * c.N * B * (1 + m.n), (double)c.N * B * m.n);
+  Prof pf(c, "k_reduce_int", 8.0 * c.N * B * (1 + m.n), (double)c.N * B * m.n);
   LAUNCH(k_reduce_int, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, src, src_stride,
                      out, out_stride, m, c.d_primes, (int)c.N);
   check_launch();
@@ -1684,7 +1700,7 @@ void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
   chk_map(c, a, B, sa, m, "add a");
   chk_map(c, b, B, sb, m, "add b");
   chk_map(c, o, B, so, m, "add out");
-  Prof pf(c, "add", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  Prof pf(c, "k_add", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
   LAUNCH(k_add, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
@@ -1695,7 +1711,7 @@ void sub(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
   chk_map(c, a, B, sa, m, "sub a");
   chk_map(c, b, B, sb, m, "sub b");
   chk_map(c, o, B, so, m, "sub out");
-  Prof pf(c, "sub", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  Prof pf(c, "k_sub", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
   LAUNCH(k_sub, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
@@ -1706,7 +1722,7 @@ void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
   chk_map(c, a, B, sa, m, "mul a");
   chk_map(c, b, B, sb, m, "mul b");
   chk_map(c, o, B, so, m, "mul out");
-  Prof pf(c, "mul", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  Prof pf(c, "k_mul", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
   LAUNCH(k_mul, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, a, sa, b, sb, o, so, m,
                      c.d_primes, (int)c.N);
   check_launch();
@@ -1718,7 +1734,7 @@ void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* p
   chk(ct, B, sct, 0, ccs + (size_t)limbs * c.N, "mul_ct_pt ciphertext");
   chk(pt, B, spt, 0, (size_t)limbs * c.N, "mul_ct_pt plaintext");
   chk(out, B, so, 0, ocs + (size_t)limbs * c.N, "mul_ct_pt output");
-  Prof pf(c, "mul", 8.0 * c.N * limbs * (4.0 * B + (sct ? 2.0 * B : 2.0)), 2.0 * c.N * B * limbs);
+  Prof pf(c, "k_mul_ct_pt", 8.0 * c.N * limbs * (3.0 * B + (sct ? 2.0 * B : 2.0)), 2.0 * c.N * B * limbs);
   LAUNCH(k_mul_ct_pt, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, ct, sct, ccs, pt, spt, out, so, ocs, limbs,
          c.d_primes, (int)c.N);
   check_launch();
@@ -1729,7 +1745,7 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o,
   chk_map(c, s, B, ss, m, "axpy s");
   chk_map(c, o, B, so, m, "axpy out");
   audit::check(scal, 2 * sizeof(u64) * m.n, "axpy scalars");
-  Prof pf(c, "axpy", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
+  Prof pf(c, "k_axpy_scalar", 24.0 * c.N * B * m.n, (double)c.N * B * m.n);
   LAUNCH(k_axpy_scalar, ew_grid(c.N, m.n, B), dim3(TPB), 0, c.stream, s, ss, scal, o,
                      so, m, c.d_primes, (int)c.N);
   check_launch();
@@ -1745,7 +1761,10 @@ void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const
   chk(a, (B - 1) / a_div + 1, sa, 0, pa + a_cs + (size_t)limbs * c.N, "tensor a");
   chk(b, std::min(B, b_mod), sb, 0, pb + b_cs + (size_t)limbs * c.N, "tensor b");
   chk(o, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
-  Prof pf(c, "tensor", 8.0 * c.N * B * limbs * (4.0 * parts + (accumulate ? 6 : 3)), 4.0 * c.N * B * limbs * parts);
+  // distinct words: each query part and each gallery part once, the outputs
+  const double na = (double)((B - 1) / a_div + 1), nb = (double)std::min(B, b_mod);
+  Prof pf(c, "k_tensor", 8.0 * c.N * limbs * (2.0 * parts * (na + nb) + (accumulate ? 6.0 : 3.0) * B),
+          4.0 * c.N * B * limbs * parts);
   LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, a_cs, a_ps, b, sb, b_mod,
          b_cs, b_ps, parts, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
   check_launch();
@@ -1758,7 +1777,7 @@ void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, i
   const u64 gm = c.ci ? 3 : 1;   // Galois elements are 1 mod M/N
   if ((g0 & gm) != 1 || (g1 & gm) != 1 || g0 >= c.M || g1 >= c.M)
     BM_THROW(BM_EINVAL, "launch check: Galois element");
-  Prof pf(c, "automorphism", 16.0 * c.N * B * rows, 0.0);
+  Prof pf(c, "k_automorphism", 16.0 * c.N * B * rows, 0.0);
   LAUNCH(k_automorphism, ew_grid(c.N, rows, B), dim3(TPB), 0, c.stream, in, si, out, so, g0, g1,
          sel, c.log_n, c.ci ? 2 : 1);
   check_launch();
@@ -1775,7 +1794,7 @@ void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int
     ops += (double)ns * (1 + tb.ext - ns);
     rd += ns;
   }
-  Prof pf(c, "modup", 8.0 * c.N * B * (rd + tb.npairs), ops * c.N * B);
+  Prof pf(c, "k_modup", 8.0 * c.N * B * (rd + tb.npairs), ops * c.N * B);
   LAUNCH(k_modup, ew_grid(c.N, tb.npairs, B), dim3(TPB), 0, c.stream, xc, sx, y, sy, c.d_modup + limbs,
          c.d_primes, (int)c.N);
   check_launch();
@@ -1790,7 +1809,7 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
   chk(key0, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
   chk(key1, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "kip key");
   chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "kip output");
-  Prof pf(c, "kip", 8.0 * c.N * tb.ext * ((double)B * tb.beta + 2.0 * tb.beta + 2.0 * B),
+  Prof pf(c, "k_kip", 8.0 * c.N * tb.ext * ((double)B * tb.beta + 2.0 * tb.beta + 2.0 * B),
           2.0 * c.N * tb.ext * tb.beta * B);
   u64 pm = 0, pms = 0;
   if (dadd) {   // P mod q_{limbs-1}
@@ -1819,14 +1838,26 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   chk(c0_in, B, c0_si, 0, (size_t)limbs * c.N, "autom_sum input");
   chk(c0_out, B, c0_so, 0, (size_t)limbs * c.N, "autom_sum output");
   if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the hoisted kip");
-  const double keys_read = (double)h.A * (h.per_elem ? B : 1) * 2 * tb.beta * tb.ext * c.N;
-  // the c0 half (gathered sum of the rotations) rides in the same launch
-  Prof pf(c, "kip_hoist", 8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2) + 2.0 * c.N * limbs * B),
+  // algorithmic words: every distinct key of the launch once (over the
+  // extended limbs), the digits and the input limbs once, both outputs, and
+  // the c0 half (gathered sum of the rotations) that rides in the same launch
+  std::vector<uint32_t> gs;
+  for (int i = 0; i < h.A * (h.per_elem ? B : 1); ++i) gs.push_back(h.g[i]);
+  std::sort(gs.begin(), gs.end());
+  const double distinct_keys = (double)(std::unique(gs.begin(), gs.end()) - gs.begin());
+  const double keys_read = distinct_keys * 2 * tb.beta * tb.ext * c.N;
+  const bool grouped = !h.per_elem && B > 1 && c.N % (2 * TPB) == 0;
+  static const char* const zb_names[] = {"", "k_kip_hoist_zb<1, 2, 4>", "k_kip_hoist_zb<2, 2, 2>",
+                                         "k_kip_hoist_zb<3, 2, 1>", "k_kip_hoist_zb<4, 2, 1>"};
+  static const char* const el_names[] = {"", "k_kip_hoist<1>", "k_kip_hoist<2>", "k_kip_hoist<3>",
+                                         "k_kip_hoist<4>"};
+  Prof pf(c, (grouped ? zb_names : el_names)[tb.beta],
+          8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2) + 2.0 * c.N * limbs * B),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
   const size_t gx = (c.N + TPB - 1) / TPB;
   AutomArgs am{c0_in, c0_si, c0_out, c0_so, limbs, (int)(gx * limbs * B)};
   if (am.W % 8 != 0) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
-  if (!h.per_elem && B > 1 && c.N % (2 * TPB) == 0) {
+  if (grouped) {
     // shared amounts: elements grouped per thread and amounts per chunk (two
     // elements a thread measured best at the face configuration; the group's
     // second thread finds the key words in L2)
@@ -1865,7 +1896,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
 void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs) {
   chk(uw, B, suw, 0, (size_t)2 * (limbs + c.K) * c.N, "moddown_conv input");
   chk(conv, B, sc, 0, (size_t)2 * limbs * c.N, "moddown_conv output");
-  Prof pf(c, "moddown_conv", 8.0 * c.N * B * (2 * c.K + 2 * limbs),
+  Prof pf(c, "k_moddown_conv", 8.0 * c.N * B * (2 * c.K + 2 * limbs),
           (double)c.N * B * (2 * c.K + 2 * c.K * limbs));
   LAUNCH(k_moddown_conv, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
                      conv, sc, c.d_moddown, limbs, c.d_primes, (int)c.N);
@@ -1880,7 +1911,7 @@ void moddown_finish(const Ctx& c, const u64* uw, size_t suw, const u64* conv, si
   if (add0) chk(add0, B, sadd0, 0, (size_t)limbs * c.N, "moddown_finish add0");
   if (add1) chk(add1, B, sadd1, 0, (size_t)limbs * c.N, "moddown_finish add1");
   chk(out, B, so, 0, (size_t)2 * limbs * c.N, "moddown_finish output");
-  Prof pf(c, "moddown_finish", 8.0 * c.N * B * 2 * limbs * (3 + (add0 ? 1 : 0)),
+  Prof pf(c, "k_moddown_finish", 8.0 * c.N * B * 2 * limbs * (3 + (add0 ? 1 : 0)),
           2.0 * c.N * B * limbs);
   LAUNCH(k_moddown_finish, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, uw, suw,
                      conv, sc, add0, sadd0, add1, sadd1, out, so, c.d_moddown, limbs, c.d_primes,
@@ -1893,7 +1924,7 @@ void rescale_conv(const Ctx& c, const u64* last, size_t sl, size_t last_comp_str
   if (limbs < 2) BM_THROW(BM_EINVAL, "launch check: rescale limbs");
   chk(last, B, sl, 0, (size_t)(comps - 1) * last_comp_stride + c.N, "rescale_conv input");
   chk(t, B, st, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_conv output");
-  Prof pf(c, "rescale_conv", 8.0 * c.N * B * comps * limbs, (double)c.N * B * comps * (limbs - 1));
+  Prof pf(c, "k_rescale_conv", 8.0 * c.N * B * comps * limbs, (double)c.N * B * comps * (limbs - 1));
   LAUNCH(k_rescale_conv, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0, c.stream,
                      last, sl, last_comp_stride, t, st, comps, limbs, c.d_primes, (int)c.N);
   check_launch();
@@ -1905,7 +1936,7 @@ void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t
   chk(in, B, si, 0, (size_t)comps * limbs * c.N, "rescale_finish input");
   chk(t, B, st, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_finish t");
   chk(out, B, so, 0, (size_t)comps * (limbs - 1) * c.N, "rescale_finish output");
-  Prof pf(c, "rescale_finish", 24.0 * c.N * B * comps * (limbs - 1), (double)c.N * B * comps * (limbs - 1));
+  Prof pf(c, "k_rescale_finish", 24.0 * c.N * B * comps * (limbs - 1), (double)c.N * B * comps * (limbs - 1));
   LAUNCH(k_rescale_finish, ew_grid(c.N, comps * (limbs - 1), B), dim3(TPB), 0,
                      c.stream, in, si, t, st, out, so, c.d_rescale, comps, limbs, c.L + 1,
                      c.d_primes, (int)c.N);
@@ -1920,7 +1951,7 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
     const size_t hi = (size_t)((B - 1) / div) * so_hi + (size_t)std::min(B - 1, div - 1) * so_lo;
     chk(out, 1, 0, 0, hi + (size_t)(comps - 1) * out_comp_stride + (size_t)limbs * c.N, "copy_limbs output");
   }
-  Prof pf(c, "copy_limbs", 16.0 * c.N * B * comps * limbs, 0.0);
+  Prof pf(c, "k_copy_limbs", 16.0 * c.N * B * comps * limbs, 0.0);
   LAUNCH(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
                      in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
   check_launch();
@@ -1929,7 +1960,7 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
 void zero(const Ctx& c, u64* out, size_t words) {
   if (words == 0) return;
   chk(out, 1, 0, 0, words, "zero output");
-  Prof pf(c, "zero", 8.0 * words, 0.0);
+  Prof pf(c, "k_zero", 8.0 * words, 0.0);
   const size_t blocks = std::min<size_t>((words + TPB * 4 - 1) / (TPB * 4), 65535);
   LAUNCH(k_zero, dim3((unsigned)blocks), dim3(TPB), 0, c.stream, out, words);
   check_launch();
@@ -1941,7 +1972,7 @@ void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const
   chk(in, scatter ? B : (int)max_idx + 1, si, 0, words, "move_idx input");
   chk(out, scatter ? (int)max_idx + 1 : B, so, 0, words, "move_idx output");
   chk(idx_dev, 1, 0, 0, ((size_t)B + 1) / 2, "move_idx index list");
-  Prof pf(c, "move_idx", 16.0 * words * B, 0.0);
+  Prof pf(c, "k_move_idx", 16.0 * words * B, 0.0);
   const size_t blocks = std::min<size_t>((words + TPB * 4 - 1) / (TPB * 4), 65535);
   LAUNCH(k_move_idx, dim3((unsigned)blocks, 1, (unsigned)B), dim3(TPB), 0, c.stream, in, si, out, so, idx_dev,
          scatter ? 1 : 0, words);
