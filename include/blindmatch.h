@@ -410,6 +410,39 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * returns it with its time per match.  Bits never depend on the choice. */
 int bm_autotune(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g, uint32_t schedule,
                 uint32_t *best_chunk, double *best_ms);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the match
+ * of bm_match on caller-owned device buffers, its intermediate buffers carved
+ * out of a scratch array of BM_NOALLOC_SCRATCH_BYTES that the library holds
+ * once per device for the life of the process.  Nothing is allocated: no
+ * hipMalloc, no hipFree, no pool or allocator call, no memset node.
+ *   q_words: device words[2][q_limbs][N] of the query ciphertext in the
+ *     evaluation domain (what bm_ntt's forward transform gives from the
+ *     coefficient words), scale q_scale, packed for feature length g's d;
+ *   masks: required when the gallery has k > 1 (bm_masks_create or
+ *     bm_masks_import, made beforehand), ignored for k = 1;
+ *   schedule: as bm_match without BM_COMPRESS (BM_EINVAL);
+ *   out_words: device words[G][2][ol][N] in the evaluation domain, G the
+ *     gallery groups and ol = min(out_limbs, or the context default when 0,
+ *     the natural output level): result ciphertext g at g * 2 * ol * N.
+ *     *needed_words receives G * 2 * ol * N; with out_words NULL the call
+ *     only reports that size.  n_out_words must equal it (BM_EINVAL).
+ *   *out_scale receives the results' scale.
+ * Before anything is enqueued the whole sequence of the match is walked on
+ * the host and its scratch need measured; a match that needs more than
+ * BM_NOALLOC_SCRATCH_BYTES fails with BM_ENOMEM and enqueues nothing (a
+ * smaller group chunk, bm_ctx_set_group_chunk, lowers the need).  The words
+ * equal those of bm_match with the same arguments.  Asynchronous on `stream`.
+ * Every call on a device uses that device's one scratch array, whose
+ * contents are left from the previous call (no kernel here reads scratch it
+ * has not written in the same call): calls that overlap on one device -- on
+ * two streams, two threads or two contexts -- race on it and must be
+ * serialised by the caller. */
+#define BM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int bm_match_noalloc(bm_ctx *ctx, const bm_evk *evk, const uint64_t *q_words, uint32_t q_limbs,
+                     double q_scale, const bm_gallery *g, const bm_masks *masks, uint32_t schedule,
+                     uint32_t out_limbs, uint64_t *out_words, size_t n_out_words, size_t *needed_words,
+                     double *out_scale, void *stream);
 /* *groups = result ciphertexts (gallery groups, or ceil(groups / c) when
  * compressed). */
 int bm_result_info(const bm_result *r, uint64_t *groups, uint32_t *limbs, double *scale);

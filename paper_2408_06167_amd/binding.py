@@ -113,6 +113,8 @@ _SIGS = {
     "bm_expand": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "bm_match": (ctypes.c_int, [_P, _P, _P, _P, _P, _u32, _u32, _P, _PP]),
     "bm_match_batch": (ctypes.c_int, [_P, _P, _P, _P, _sz, _u32, _u32, _P, _P]),
+    "bm_match_noalloc": (ctypes.c_int, [_P, _P, _P, _u32, _dbl, _P, _P, _u32, _u32, _P, _sz, ctypes.POINTER(_sz),
+                                        ctypes.POINTER(_dbl), _P]),
     "bm_autotune": (ctypes.c_int, [_P, _P, _P, _P, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_dbl)]),
     "bm_result_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                       ctypes.POINTER(_dbl)]),
@@ -581,6 +583,19 @@ def bm_expand(ctx, evk, q, masks, k):
 def bm_match(ctx, evk, q, gallery, masks=None, schedule=BM_S1, out_limbs=0, stream=None):
     return _op("bm_match", ctx, evk, q, gallery, masks, int(schedule), int(out_limbs),
                ctypes.c_void_p(stream) if stream else None)
+
+
+def bm_match_noalloc(ctx, evk, q_ptr, q_limbs, q_scale, g, masks=None, schedule=BM_S2, out_limbs=0, out_ptr=None,
+                     n_out_words=0, stream=None):
+    """bm_match on device buffers (integer addresses) with the library's
+    scratch array; returns (words the output needs, result scale).  With
+    out_ptr None only the size is reported."""
+    needed, sc = _sz(0), _dbl(0)
+    _check(lib().bm_match_noalloc(ctx, evk, ctypes.c_void_p(q_ptr), int(q_limbs), float(q_scale), g, masks,
+                                  int(schedule), int(out_limbs), ctypes.c_void_p(out_ptr) if out_ptr else None,
+                                  int(n_out_words), ctypes.byref(needed), ctypes.byref(sc),
+                                  ctypes.c_void_p(stream) if stream else None), "bm_match_noalloc", ctx)
+    return needed.value, sc.value
 
 
 def bm_match_batch(ctx, evk, queries, galleries, schedule=BM_S1, out_limbs=0, stream=None):

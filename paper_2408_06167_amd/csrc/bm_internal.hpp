@@ -31,6 +31,8 @@ constexpr int MAX_PRIMES = 24;   // chain + special primes
 constexpr int MAX_LIMBS = 40;    // limb slots of one launch (all ModUp targets of a key switch)
 constexpr int MAX_DIGITS = 16;
 constexpr int MAX_ALPHA = 4;
+// scratch of the no-allocation match, one array per device (see bm_match_noalloc)
+constexpr size_t NOALLOC_SCRATCH_BYTES = BM_NOALLOC_SCRATCH_BYTES;
 
 // ----------------------------------------------------------------- device runtime
 //
@@ -64,6 +66,15 @@ hipError_t end_capture(hipStream_t s, hipGraph_t* g);
 hipError_t graph_instantiate(hipGraphExec_t* e, hipGraph_t g);
 hipError_t graph_destroy(hipGraph_t g);
 hipError_t graph_launch(hipGraphExec_t e, hipStream_t s);
+// Sizing pass of the calling thread: while a SizingScope is alive, kernel
+// launches are skipped (their launch checks still run) and no other HIP call
+// is made, so that a call sequence can be walked on the host to measure the
+// scratch memory it needs before any of it is enqueued.
+bool sizing();
+struct SizingScope {
+  SizingScope();
+  ~SizingScope();
+};
 }  // namespace dev
 
 // ----------------------------------------------------------------- errors
@@ -209,10 +220,16 @@ class DevicePool {
  public:
   explicit DevicePool(int device, std::shared_ptr<const AllocHook> hook = nullptr)
       : device_(device), hook_(std::move(hook)) {}
+  // Arena mode: every block is carved out of [base, base + bytes), a region
+  // the pool does not own (first fit, 256-byte aligned, freed ranges merged);
+  // nothing is ever allocated from HIP or a hook.  An allocation that does not
+  // fit raises BM_ENOMEM.  peak() is the highest end offset handed out.
+  DevicePool(int device, void* base, size_t bytes);
   ~DevicePool();
   void* alloc(size_t bytes);
   void release(void* p, size_t bytes);
   size_t bytes_held() const { return held_; }
+  size_t peak() const { return peak_; }
   void trim();
   // later blocks come from `hook` (null: hipMalloc); cached blocks are freed
   void set_hook(std::shared_ptr<const AllocHook> hook);
@@ -220,6 +237,11 @@ class DevicePool {
  private:
   void* new_block(size_t bytes);
   void free_cached();   // caller holds mu_
+  void* arena_alloc(size_t bytes);
+  void arena_release(void* p, size_t bytes);
+  char* arena_ = nullptr;                 // arena mode when set
+  size_t arena_bytes_ = 0, peak_ = 0;
+  std::map<size_t, size_t> arena_free_;   // offset -> length of the free ranges
   int device_;
   std::shared_ptr<const AllocHook> hook_;
   std::map<void*, std::shared_ptr<const AllocHook>> hooked_;   // block -> the hook that made it
@@ -379,6 +401,9 @@ void ring_decode(const Ctx& c, const double* m, double scale, double* slots);
 // ----------------------------------------------------------------- device kernels (kernels.hip)
 
 namespace kern {
+// device address of the no-allocation scratch array on `device` (the device is
+// made current; looked up once per device, then cached)
+void* noalloc_scratch(int device);
 LimbMap chain_map(int limbs);                        // q_0..q_{limbs-1} at offsets 0..
 LimbMap ext_map(const Ctx& c, int limbs);           // q_0..q_{l-1}, p_0..p_{K-1}
 LimbMap single(int prime, int off);

@@ -177,6 +177,7 @@ int bm_ctx_create(const bm_params* p, int device, bm_ctx** out) {
     c.stream = c.own_stream;
     c.pool.reset(new DevicePool(device));
     build_context_tables(c);
+    (void)kern::noalloc_scratch(device);   // the no-allocation match's scratch, looked up once per device
     *out = h.release();
   });
 }
@@ -1223,6 +1224,60 @@ int bm_match(bm_ctx* ctx, const bm_evk* evk, const bm_ct* q, const bm_gallery* g
     same_ctx(ctx, evk, q, g, masks);
     ctx->c.use_stream(stream);
     match_one(ctx, evk, q, g, masks, schedule, out_limbs, out);
+  });
+}
+
+// The match of bm_match on caller buffers, its scratch carved out of the
+// device's scratch array: walked once on the host (no launch, no HIP call) to
+// measure the scratch it needs and to run every launch check, then enqueued.
+int bm_match_noalloc(bm_ctx* ctx, const bm_evk* evk, const uint64_t* q_words, uint32_t q_limbs, double q_scale,
+                     const bm_gallery* g, const bm_masks* masks, uint32_t schedule, uint32_t out_limbs,
+                     uint64_t* out_words, size_t n_out_words, size_t* needed_words, double* out_scale,
+                     void* stream) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && evk && q_words && g && needed_words, BM_EINVAL, "NULL argument");
+    same_ctx(ctx, evk, g, masks);
+    REQUIRE(!(schedule & BM_COMPRESS), BM_EINVAL, "the no-allocation match does not compress");
+    Ctx& c = ctx->c;
+    const Plan s = bmx::plan(c, schedule, g->k, (int)g->limbs, out_limbs);
+    REQUIRE((int)q_limbs >= s.ql && (int)q_limbs <= c.L + 1, BM_ELEVEL,
+            g->k == 1 ? "query below the gallery level" : "query must sit at least one level above the gallery");
+    const size_t need = (size_t)g->groups * 2 * s.ol * c.N;
+    *needed_words = need;
+    if (!out_words) return;
+    REQUIRE(n_out_words == need, BM_EINVAL, "output must hold groups * 2 * out_limbs * N words");
+    const bm_masks* m = nullptr;
+    double cu_scale = q_scale;
+    if (g->k > 1) {
+      REQUIRE(masks, BM_EINVAL, "a gallery with k > 1 needs masks made beforehand");
+      REQUIRE(masks->d == g->d && masks->k == g->k, BM_EDIM, "masks do not match the gallery shape");
+      m = masks;
+      cu_scale = q_scale * m->scale / (double)c.primes[s.ql - 1].q;
+    }
+    REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
+    c.use_stream(stream);
+    audit::Scoped reg_q(q_words, (size_t)2 * q_limbs * c.N * sizeof(u64));
+    audit::Scoped reg_o(out_words, need * sizeof(u64));
+    void* base = kern::noalloc_scratch(c.device);
+    auto run = [&](bool sizing) {
+      std::shared_ptr<DevicePool> arena = std::make_shared<DevicePool>(c.device, base, NOALLOC_SCRATCH_BYTES);
+      std::swap(c.pool, arena);
+      try {
+        if (sizing) {
+          dev::SizingScope walk;
+          match_body(c, evk, q_words, q_limbs, g, m, nullptr, s, out_words);
+        } else {
+          match_body(c, evk, q_words, q_limbs, g, m, nullptr, s, out_words);
+        }
+      } catch (...) {
+        std::swap(c.pool, arena);
+        throw;
+      }
+      std::swap(c.pool, arena);
+    };
+    run(true);    // BM_ENOMEM (nothing enqueued) when the scratch is too small
+    run(false);
+    if (out_scale) *out_scale = bmx::result_scale(c, s, cu_scale, g->scale);
   });
 }
 

@@ -9,6 +9,14 @@
 namespace bm {
 namespace dev {
 
+namespace {
+thread_local int g_sizing = 0;
+}
+
+bool sizing() { return g_sizing > 0; }
+SizingScope::SizingScope() { ++g_sizing; }
+SizingScope::~SizingScope() { --g_sizing; }
+
 bool dry() {
   static const bool d = [] {
     const char* e = std::getenv("BM_DRY_RUN");
@@ -42,6 +50,7 @@ hipError_t memcpy(void* d, const void* s, size_t bytes, hipMemcpyKind k) {
 }
 
 hipError_t memcpy_async(void* d, const void* s, size_t bytes, hipMemcpyKind k, hipStream_t st) {
+  if (sizing()) return hipSuccess;
   if (dry()) {
     std::memmove(d, s, bytes);
     return hipSuccess;
@@ -49,7 +58,7 @@ hipError_t memcpy_async(void* d, const void* s, size_t bytes, hipMemcpyKind k, h
   return hipMemcpyAsync(d, s, bytes, k, st);
 }
 
-hipError_t stream_sync(hipStream_t s) { return dry() ? hipSuccess : hipStreamSynchronize(s); }
+hipError_t stream_sync(hipStream_t s) { return dry() || sizing() ? hipSuccess : hipStreamSynchronize(s); }
 hipError_t device_sync() { return dry() ? hipSuccess : hipDeviceSynchronize(); }
 
 hipError_t stream_create(hipStream_t* s) {
@@ -75,7 +84,9 @@ hipError_t event_create(hipEvent_t* e, bool timing) {
 }
 
 hipError_t event_destroy(hipEvent_t e) { return dry() ? hipSuccess : hipEventDestroy(e); }
-hipError_t event_record(hipEvent_t e, hipStream_t s) { return dry() ? hipSuccess : hipEventRecord(e, s); }
+hipError_t event_record(hipEvent_t e, hipStream_t s) {
+  return dry() || sizing() ? hipSuccess : hipEventRecord(e, s);
+}
 hipError_t event_sync(hipEvent_t e) { return dry() ? hipSuccess : hipEventSynchronize(e); }
 
 hipError_t event_elapsed(float* ms, hipEvent_t a, hipEvent_t b) {
@@ -87,7 +98,7 @@ hipError_t event_elapsed(float* ms, hipEvent_t a, hipEvent_t b) {
 }
 
 hipError_t event_query(hipEvent_t e) { return dry() ? hipSuccess : hipEventQuery(e); }
-hipError_t last_error() { return dry() ? hipSuccess : hipGetLastError(); }
+hipError_t last_error() { return dry() || sizing() ? hipSuccess : hipGetLastError(); }
 
 hipError_t begin_capture(hipStream_t s) {
   return dry() ? hipSuccess : hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);

@@ -42,9 +42,49 @@ void check(const void* p, size_t bytes, const char* what) {
 }
 }  // namespace audit
 
+DevicePool::DevicePool(int device, void* base, size_t bytes)
+    : arena_((char*)base), arena_bytes_(bytes), device_(device) {
+  if (bytes) arena_free_[0] = bytes;
+}
+
 DevicePool::~DevicePool() {
   std::lock_guard<std::mutex> g(mu_);
-  free_cached();
+  if (!arena_) free_cached();
+}
+
+void* DevicePool::arena_alloc(size_t bytes) {
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  for (auto it = arena_free_.begin(); it != arena_free_.end(); ++it) {
+    if (it->second < need) continue;
+    const size_t off = it->first, len = it->second;
+    arena_free_.erase(it);
+    if (len > need) arena_free_[off + need] = len - need;
+    held_ += need;
+    peak_ = std::max(peak_, off + need);
+    return arena_ + off;
+  }
+  BM_THROW(BM_ENOMEM, "scratch exhausted: " + std::to_string(bytes) + " more bytes needed beyond the " +
+                          std::to_string(arena_bytes_) + "-byte scratch");
+}
+
+void DevicePool::arena_release(void* p, size_t bytes) {
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  size_t off = (size_t)((char*)p - arena_), len = need;
+  held_ -= need;
+  auto next = arena_free_.lower_bound(off);
+  if (next != arena_free_.end() && next->first == off + len) {     // merge with the following range
+    len += next->second;
+    next = arena_free_.erase(next);
+  }
+  if (next != arena_free_.begin()) {                                // and with the preceding one
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      off = prev->first;
+      len += prev->second;
+      arena_free_.erase(prev);
+    }
+  }
+  arena_free_[off] = len;
 }
 
 // Frees the cached blocks, each to the allocator it came from; a caller's
@@ -88,6 +128,7 @@ void* DevicePool::new_block(size_t bytes) {
 
 void* DevicePool::alloc(size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
+  if (arena_) return arena_alloc(bytes);
   auto it = free_.find(bytes);
   if (it != free_.end()) {
     void* p = it->second;
@@ -107,16 +148,21 @@ void* DevicePool::alloc(size_t bytes) {
 
 void DevicePool::release(void* p, size_t bytes) {
   std::lock_guard<std::mutex> g(mu_);
+  if (arena_) {
+    arena_release(p, bytes);
+    return;
+  }
   free_.emplace(bytes, p);
 }
 
 void DevicePool::trim() {
   std::lock_guard<std::mutex> g(mu_);
-  free_cached();
+  if (!arena_) free_cached();
 }
 
 void DevicePool::set_hook(std::shared_ptr<const AllocHook> hook) {
   std::lock_guard<std::mutex> g(mu_);
+  if (arena_) BM_THROW(BM_EINVAL, "an arena pool takes no allocator");
   free_cached();
   hook_ = std::move(hook);
 }

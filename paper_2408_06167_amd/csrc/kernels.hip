@@ -11,6 +11,7 @@
 // limb (and with it the prime, uniform across the block so its constants come
 // from scalar loads) and blockIdx.z the polynomial of the batch.
 #include <algorithm>
+#include <cstdlib>
 
 #include <hip/hip_ext.h>
 
@@ -56,7 +57,7 @@ __device__ __forceinline__ u64 reduce64(u64 a, const PrimeC& p) { return mul_sho
 // with the kernel's execution interval (dispatch latency excluded).
 #define LAUNCH(F, G, BL, L, S, ...)                                                   \
   do {                                                                                \
-    if (dev::dry()) break;                                                            \
+    if (dev::dry() || dev::sizing()) break;                                           \
     if (pf.on)                                                                        \
       hipExtLaunchKernelGGL(F, G, BL, L, S, pf.ev.first, pf.ev.second, 0, __VA_ARGS__); \
     else                                                                              \
@@ -1412,7 +1413,7 @@ inline void chk_map(const Ctx& c, const void* p, int B, size_t st, const LimbMap
 struct Prof {
   bool on;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-  Prof(const Ctx& c, const char* name, double bytes, double ops) : on(c.prof && c.prof->on) {
+  Prof(const Ctx& c, const char* name, double bytes, double ops) : on(c.prof && c.prof->on && !dev::sizing()) {
     if (on) ev = c.prof->begin(name, bytes, ops);
   }
   Prof(const Ctx& c, const std::string& name, double bytes, double ops) : Prof(c, name.c_str(), bytes, ops) {}
@@ -1420,7 +1421,32 @@ struct Prof {
 
 }  // namespace
 
+// Scratch memory of the no-allocation match (bm_match_noalloc): its
+// intermediate buffers are carved out of this array, which every context on a
+// device shares.  In host code `scratch` names a host-side stand-in, never the
+// device memory: kernels get the address from hipGetSymbolAddress.
+static __device__ __align__(256) u64 scratch[NOALLOC_SCRATCH_BYTES / sizeof(u64)];
+
 namespace kern {
+
+void* noalloc_scratch(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> ptrs;   // device -> address of that device's copy
+  std::lock_guard<std::mutex> g(mu);
+  auto it = ptrs.find(device);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  if (dev::dry()) {
+    p = std::malloc(NOALLOC_SCRATCH_BYTES);   // host memory stands in for HBM
+    if (!p) BM_THROW(BM_ENOMEM, "host stand-in of the scratch array");
+  } else {
+    HIP_OK(dev::set_device(device));
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  }
+  audit::add(p, NOALLOC_SCRATCH_BYTES);
+  ptrs[device] = p;
+  return p;
+}
 
 LimbMap chain_map(int limbs) {
   LimbMap m{};

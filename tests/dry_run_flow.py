@@ -448,7 +448,60 @@ def result_outlives_server():
     print("result outlives server ok", flush=True)
 
 
+def noalloc_flow():
+    """The no-allocation match: size query, host-side refusals, a match that
+    needs more scratch than the array holds (refused before any launch), and
+    the launch checks of matches that fit, on host buffers standing in for
+    device ones."""
+    for preset, shapes in ((1, [(16, 1, 0x001), (16, 4, 0x002), (16, 4, 0x402)]),
+                           (2, [(128, 4, 0x102), (16, 1, 0x101), (128, 16, 0x002)])):
+        p = bm.bm_params_preset(preset)
+        ctx = bm.bm_ctx_create(p, 0)
+        rots = set()
+        for d, k, _ in shapes:
+            rots.update(bm.bm_rotations_for(d, k))
+            rots.update(bm.bm_rotations_hoisted(d, k))
+        sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(rots))
+        rng = np.random.default_rng(1)
+        q = np.zeros((2, p.n_q, p.N), dtype=np.uint64)
+        for d, k, s in shapes:
+            X = rng.standard_normal((700, d)).astype(np.float32)
+            g = bm.bm_encrypt_gallery(ctx, pk, X, k, 1, 10)
+            if k == 1:
+                m = None
+            elif s & bm.BM_LEVEL_MIN:           # masks at the scale of the query cut to 4 limbs
+                m = bm.bm_masks_import(ctx, d, k, np.zeros((k, p.N), dtype=np.int64), float(p.chain()[3]))
+            else:
+                m = bm.bm_masks_create(ctx, d, k)
+            need, _ = bm.bm_match_noalloc(ctx, evk, q.ctypes.data, p.n_q, p.scale, g, m, s, 0)
+            out = np.zeros(need, dtype=np.uint64)
+            try:
+                bm.bm_match_noalloc(ctx, evk, q.ctypes.data, p.n_q, p.scale, g, m, s, 0, out.ctypes.data, need)
+                assert not (preset == 2 and k == 16), "a match above the scratch size was accepted"
+            except bm.BMError as e:
+                assert preset == 2 and k == 16 and e.code == bm.BM_ENOMEM, e
+            for bad, code in (((need - 1,), bm.BM_EINVAL),):
+                try:
+                    bm.bm_match_noalloc(ctx, evk, q.ctypes.data, p.n_q, p.scale, g, m, s, 0, out.ctypes.data, *bad)
+                    raise AssertionError("wrong output size accepted")
+                except bm.BMError as e:
+                    assert e.code == code
+            if k > 1:
+                try:
+                    bm.bm_match_noalloc(ctx, evk, q.ctypes.data, p.n_q, p.scale, g, None, s, 0, out.ctypes.data, need)
+                    raise AssertionError("k > 1 without masks accepted")
+                except bm.BMError as e:
+                    assert e.code == bm.BM_EINVAL
+                bm.bm_masks_free(m)
+            bm.bm_gallery_free(g)
+        for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+            f(h)
+        bm.bm_ctx_free(ctx)
+    print("no-allocation match ok", flush=True)
+
+
 if __name__ == "__main__":
+    noalloc_flow()
     result_outlives_server()
     key_import()
     generic_rings()
