@@ -161,7 +161,9 @@ int bm_ctx_set_allocator(bm_ctx *ctx, void *(*alloc_fn)(size_t bytes, void *user
  * counters and brackets every subsequent kernel launch of the context (and of
  * its server lanes) with HIP events on the launch stream; 0 stops.
  * bm_profile_dump waits for the recorded events and writes one text line per
- * kernel class, "name launches total_ms algorithmic_bytes algorithmic_ops",
+ * kernel, "name launches total_ms algorithmic_bytes algorithmic_ops" (the
+ * name is the kernel's symbol with its template arguments and may contain
+ * spaces; the four numbers are the last fields),
  * into buf (NUL-terminated, truncated to cap); *needed receives the full
  * length.  Algorithmic bytes count each distinct input and output word once
  * per launch; ops are modular multiplications (butterflies for the NTT). */

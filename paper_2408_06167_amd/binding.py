@@ -292,7 +292,7 @@ def bm_profile_dump(ctx):
     _check(lib().bm_profile_dump(ctx, buf, need.value + 1, ctypes.byref(need)), "bm_profile_dump", ctx)
     out = {}
     for line in buf.value.decode().splitlines():
-        name, n, ms, b, o = line.split()
+        name, n, ms, b, o = line.rsplit(None, 4)        # kernel names hold spaces
         out[name] = dict(launches=int(n), ms=float(ms), bytes=float(b), ops=float(o))
     return out
 
