@@ -77,7 +77,7 @@ def parse():
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
                          "copy: 1 GiB device copy (counter calibration); ntt: batched NTT throughput")
     ap.add_argument("--scale", type=float, default=1.0, help="gallery size factor for batch/serve")
-    ap.add_argument("--rates", default="5,10,20,40", help="serve: arrival rates (queries/s)")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")
     return ap.parse_args()
 

@@ -399,13 +399,47 @@ int bm_match(bm_ctx *ctx, const bm_evk *evk, const bm_ct *q, const bm_gallery *g
              const bm_masks *masks, uint32_t schedule, uint32_t out_limbs, void *stream,
              bm_result **out);
 /* Many (query, gallery) pairs of possibly different d, k and size in one
- * call: the pairs that share a gallery (up to 16 at a time) run as one
- * batched Alg. 2 pass in which every launch covers query x group pairs.
- * outs[i] receives the result of pair i.  Results are bit-identical to
- * per-pair bm_match. */
+ * call (the batched form of the paper's cluster serving, Sec. 3.5, on one
+ * GPU).  Pairs whose galleries share a shape (d, k, stored limbs) form a
+ * class: the class's distinct queries are expanded in one batch (Alg. 1), and
+ * Alg. 2 runs over every (pair, gallery group) element of the class in passes
+ * of group_chunk elements whose launches mix galleries.  With graphs on
+ * (bm_ctx_set_graphs) the whole batch is captured once as one HIP graph per
+ * combination of pairs and replayed (queries copied into its slots, results
+ * out of its output slot).  outs[i] receives the result of pair i; the
+ * results of one call share one device allocation.  Results are bit-identical
+ * to per-pair bm_match. */
 int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
                    const bm_gallery *const *gs, size_t n_pairs, uint32_t schedule,
                    uint32_t out_limbs, void *stream, bm_result **outs);
+/* Result-invariant kernel knobs: they change speed and scratch size, never
+ * bits.  group_chunk: (query, gallery group) elements per batched Alg. 2 pass
+ * (0: 16 at N = 2^16, 64 below; at most 4096).  kip_variant: shape of the
+ * hoisted key inner product of the rotate-and-sum, 0..4 (0: two elements per
+ * thread and four amounts' key words requested ahead at one digit; the others
+ * trade elements per thread, which share each key word from registers,
+ * against amounts in flight).  ntt_row_views: polynomials x rows per block of
+ * the row passes of the N = 2^16 transforms, 0 (= 16), 4, 8 or 16.  Matches
+ * captured as graphs keep the knobs they were captured with. */
+typedef struct {
+  uint32_t group_chunk;
+  uint32_t kip_variant;
+  uint32_t ntt_row_views;
+} bm_tuning;
+int bm_ctx_set_tuning(bm_ctx *ctx, const bm_tuning *t);
+int bm_ctx_get_tuning(const bm_ctx *ctx, bm_tuning *t);
+/* Autotuner of a batch (the pairs of bm_match_batch, out_limbs as there):
+ * times the batch under each of the n_schedules schedules offered (those
+ * whose keys or levels the inputs lack are skipped), then, under the fastest,
+ * each knob of bm_tuning in turn over its values (coordinate descent),
+ * checking that every setting gives the same words (BM_EDEVICE otherwise).
+ * The winning knobs are left set in the context and returned with the
+ * schedule and the time of one batch in ms.  Timed with HIP events on the
+ * context's own stream, in the launch mode the context is set to (graphs or
+ * eager); graphs captured while tuning are dropped. */
+int bm_autotune_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs, const bm_gallery *const *gs,
+                      size_t n_pairs, const uint32_t *schedules, size_t n_schedules, uint32_t out_limbs,
+                      uint32_t *best_schedule, bm_tuning *best, double *best_ms);
 /* Autotuner of the result-invariant knob `group_chunk` (query x group pairs
  * per batched pass): times bm_match of (q, g) for chunk sizes 1..64 with HIP
  * events on the context's stream, keeps the fastest in the context and

@@ -116,6 +116,10 @@ _SIGS = {
     "bm_match_noalloc": (ctypes.c_int, [_P, _P, _P, _u32, _dbl, _P, _P, _u32, _u32, _P, _sz, ctypes.POINTER(_sz),
                                         ctypes.POINTER(_dbl), _P]),
     "bm_autotune": (ctypes.c_int, [_P, _P, _P, _P, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_dbl)]),
+    "bm_ctx_set_tuning": (ctypes.c_int, [_P, _P]),
+    "bm_ctx_get_tuning": (ctypes.c_int, [_P, _P]),
+    "bm_autotune_batch": (ctypes.c_int, [_P, _P, _P, _P, _sz, _P, _sz, _u32, ctypes.POINTER(_u32), _P,
+                                         ctypes.POINTER(_dbl)]),
     "bm_result_info": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
                                       ctypes.POINTER(_dbl)]),
     "bm_result_export": (ctypes.c_int, [_P, _u64, _P, _sz]),
@@ -607,6 +611,38 @@ def bm_match_batch(ctx, evk, queries, galleries, schedule=BM_S1, out_limbs=0, st
                                 int(out_limbs), ctypes.c_void_p(stream) if stream else None,
                                 ctypes.cast(outs, _P)), "bm_match_batch", ctx)
     return [ctypes.c_void_p(outs[i]) for i in range(n)]
+
+
+class bm_tuning(ctypes.Structure):
+    _fields_ = [("group_chunk", ctypes.c_uint32), ("kip_variant", ctypes.c_uint32),
+                ("ntt_row_views", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return dict(group_chunk=self.group_chunk, kip_variant=self.kip_variant, ntt_row_views=self.ntt_row_views)
+
+
+def bm_ctx_set_tuning(ctx, group_chunk=0, kip_variant=0, ntt_row_views=0):
+    t = bm_tuning(int(group_chunk), int(kip_variant), int(ntt_row_views))
+    _check(lib().bm_ctx_set_tuning(ctx, ctypes.byref(t)), "bm_ctx_set_tuning", ctx)
+
+
+def bm_ctx_get_tuning(ctx):
+    t = bm_tuning()
+    _check(lib().bm_ctx_get_tuning(ctx, ctypes.byref(t)), "bm_ctx_get_tuning", ctx)
+    return t.as_dict()
+
+
+def bm_autotune_batch(ctx, evk, qs, gs, schedules, out_limbs=0):
+    """Returns (schedule, tuning dict, ms per batch); the knobs stay set."""
+    n = len(qs)
+    qa = (ctypes.c_void_p * n)(*[q.value for q in qs])
+    ga = (ctypes.c_void_p * n)(*[g.value for g in gs])
+    sa = (_u32 * len(schedules))(*[int(x) for x in schedules])
+    bs, t, ms = _u32(0), bm_tuning(), _dbl(0)
+    _check(lib().bm_autotune_batch(ctx, evk, ctypes.cast(qa, _P), ctypes.cast(ga, _P), n, ctypes.cast(sa, _P),
+                                   len(schedules), int(out_limbs), ctypes.byref(bs), ctypes.byref(t),
+                                   ctypes.byref(ms)), "bm_autotune_batch", ctx)
+    return bs.value, t.as_dict(), ms.value
 
 
 def bm_autotune(ctx, evk, q, gallery, schedule=BM_S2):

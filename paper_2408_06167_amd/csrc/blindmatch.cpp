@@ -88,7 +88,9 @@ void match_groups(Ctx& c, const bm_evk* evk, const Plan& p, const u64* cu, int n
 }
 
 // Galois elements of a hoisted rotation sum, split into launches of at most
-// HOIST_MAX elements; amounts[z][a] (per_elem) or amounts[0][a] for every element.
+// HOIST_MAX elements; amounts[z][a] (per_elem: list z serves elements z,
+// z + Z, z + 2Z, ... of the batch, Z the number of lists) or amounts[0][a]
+// for every element.
 static std::vector<HoistArgs> hoist_args(const Ctx& c, const bm_evk* evk,
                                          const std::vector<std::vector<long>>& amounts, bool per_elem,
                                          std::vector<const u64*>& keys) {
@@ -101,6 +103,7 @@ static std::vector<HoistArgs> hoist_args(const Ctx& c, const bm_evk* evk,
     HoistArgs h{};
     h.A = std::min(per, A - a0);
     h.per_elem = per_elem ? 1 : 0;
+    h.mod = per_elem ? Z : 1 << 30;
     for (int z = 0; z < Z; ++z)
       for (int a = 0; a < h.A; ++a) {
         const u64 g = ev::galois_for_rotation(c, amounts[z][a0 + a]);
@@ -127,58 +130,68 @@ static std::vector<long> expansion_amounts(u32 d, u32 k, u32 i) {
   return out;
 }
 
-void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
-                    u64* out) {
+void expand_batch(Ctx& c, const bm_evk* evk, const u64* q, size_t qs, size_t qcs, int nq, int qlimbs,
+                  const u64* masks, u32 d, u32 k, u64* out, bool hoist) {
   const size_t N = c.N;
   const int l = qlimbs, nl = qlimbs - 1;
   if (nl < 1) BM_THROW(BM_ELEVEL, "expansion needs two limbs");
-  const size_t ln = (size_t)l * N;
-  DBuf pm(&c, (size_t)k * 2 * ln);
-  kern::mul_ct_pt(c, q, 0, ln, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, (int)k, l);
-  ev::rescale(c, pm.p(), (int)k, 2, l, out);
-  std::vector<std::vector<long>> amounts;
-  for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
-  std::vector<const u64*> keys;
-  const std::vector<HoistArgs> hs = hoist_args(c, evk, amounts, true, keys);
-  ev::rotation_sum_hoisted(c, evk, out, (int)k, nl, hs, keys, out);
-}
-
-void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
-            u64* out) {
-  const size_t N = c.N;
-  const int l = qlimbs, nl = qlimbs - 1;
-  if (nl < 1) BM_THROW(BM_ELEVEL, "expansion needs two limbs");
+  if (nq < 1) return;
   const size_t ln = (size_t)l * N, nln = (size_t)nl * N;
-  const u32 cc = d / k;
-  // Mul(P) of the query by every mask, batched over the k masks
-  DBuf pm(&c, (size_t)k * 2 * ln);
-  kern::mul_ct_pt(c, q, 0, ln, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, (int)k, l);
-  ev::rescale(c, pm.p(), (int)k, 2, l, out);
+  const int E = nq * (int)k;                  // element j k + i: part i of query j
+  // Mul(P) of every query by every mask, then one batched rescale
+  DBuf pm(&c, (size_t)E * 2 * ln);
+  kern::mul_ct_pt(c, q, qs, qcs, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, E, l, (int)k, (int)k);
+  ev::rescale(c, pm.p(), E, 2, l, out);
+  if (hoist) {
+    // the log2 k steps of part i unrolled into one hoisted sum; the amounts
+    // depend on the part only, so list i serves every query's part i
+    std::vector<std::vector<long>> amounts;
+    for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
+    std::vector<const u64*> keys;
+    const std::vector<HoistArgs> hs = hoist_args(c, evk, amounts, true, keys);
+    ev::rotation_sum_hoisted(c, evk, out, E, nl, hs, keys, out);
+    return;
+  }
   // step t: part i adds Rot(., -c 2^t) when bit t of i is 0 and Rot(., +c 2^t)
-  // otherwise; all k parts go in one batch, the sign chosen per element.
-  DBuf tmp(&c, (size_t)k * 2 * nln);
+  // otherwise; bit t of the element index j k + i is bit t of i (k a power of
+  // two), so every element of the batch picks its sign in the same launch
+  const u32 cc = d / k;
+  DBuf tmp(&c, (size_t)E * 2 * nln);
   u64* a = out;
   u64* b = tmp.p();
   for (int t = 0; (1u << t) < k; ++t) {
     const long r = (long)cc << t;
     const u64 gm = ev::galois_for_rotation(c, -r), gp = ev::galois_for_rotation(c, r);
-    ev::rotate2(c, a, (int)k, nl, gm, galois_key(evk, gm), gp, galois_key(evk, gp), t, b, true);
+    ev::rotate2(c, a, E, nl, gm, galois_key(evk, gm), gp, galois_key(evk, gp), t, b, true);
     std::swap(a, b);
   }
-  if (a != out) kern::copy_limbs(c, a, 2 * nln, nln, out, 1, 2 * nln, 0, nln, (int)k, 2, nl);
+  if (a != out) kern::copy_limbs(c, a, 2 * nln, nln, out, 1, 2 * nln, 0, nln, E, 2, nl);
 }
 
-void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
-                 const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
-                 u64* out, size_t out_qstride, bool hoist) {
+void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
+                    u64* out) {
+  expand_batch(c, evk, q, 0, (size_t)qlimbs * c.N, 1, qlimbs, masks, d, k, out, true);
+}
+
+void expand(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
+            u64* out) {
+  expand_batch(c, evk, q, 0, (size_t)qlimbs * c.N, 1, qlimbs, masks, d, k, out, false);
+}
+
+int pass_elems(const Ctx& c) { return c.group_chunk > 0 ? c.group_chunk : (c.N >= 65536 ? 16 : 64); }
+
+void hec3_elems(Ctx& c, const bm_evk* evk, const std::vector<Elem>& el, size_t cu_cs, size_t cu_ps, u32 d, u32 k,
+                int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs, bool hoist, int per_pass) {
   const size_t N = c.N;
   const int nl = l - 1;
   if (nl < 1 || l > lg_store) BM_THROW(BM_ELEVEL, "matching needs two limbs");
   if (rot_limbs < 1 || rot_limbs > nl) BM_THROW(BM_ELEVEL, "rotation limbs out of range");
   if (out_limbs < 1 || out_limbs > rot_limbs) BM_THROW(BM_ELEVEL, "output limbs out of range");
+  if (schedule != BM_S1 && schedule != BM_S2) BM_THROW(BM_EINVAL, "unknown schedule");
+  if (el.empty()) return;
   const size_t ln = (size_t)l * N, nln = (size_t)nl * N, rln = (size_t)rot_limbs * N;
-  const size_t gpart = 2 * (size_t)lg_store * N;   // one stored gallery ciphertext
-  const size_t upart = 2 * ln;                      // one expanded query part
+  const size_t gcs = (size_t)lg_store * N;          // component stride of a stored gallery ciphertext
+  const size_t gpart = 2 * gcs;                      // one stored gallery ciphertext
   const size_t oct = (size_t)2 * out_limbs * N;
   const u32 cc = d / k;
   const int rots = ilog2(cc);
@@ -199,32 +212,37 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
       gks[t] = galois_key(evk, gel[t]);
     }
   }
-  // batch = (query, group) pairs; `chunk` bounds the pairs per pass
-  u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 16 : 64);
-  const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
-  const u64 Bg_max = std::min<u64>(per_q, G);
-  const u64 Bmax = Bg_max * nq;
-  DBuf d3(&c, Bmax * 3 * ln);
-  DBuf acc(&c, Bmax * 2 * nln), acc2(&c, Bmax * 2 * nln);
-  DBuf racc(rot_limbs < nl ? DBuf(&c, Bmax * 2 * rln) : DBuf());
-  for (u64 g0 = 0; g0 < G; g0 += Bg_max) {
-    const int Bg = (int)std::min<u64>(Bg_max, G - g0);
-    const int B = Bg * nq;
-    const u64* gbase = gal + g0 * k * gpart;
+  const int Bmax = (int)std::min<size_t>(per_pass > 0 ? (size_t)per_pass : (size_t)pass_elems(c), el.size());
+  DBuf d3(&c, (size_t)Bmax * 3 * ln);
+  DBuf acc(&c, (size_t)Bmax * 2 * nln), acc2(&c, (size_t)Bmax * 2 * nln);
+  DBuf racc(rot_limbs < nl ? DBuf(&c, (size_t)Bmax * 2 * rln) : DBuf());
+  std::vector<const u64*> av(Bmax), bv(Bmax);
+  std::vector<u64*> ov(Bmax);
+  for (size_t e0 = 0; e0 < el.size(); e0 += (size_t)Bmax) {
+    const int B = (int)std::min<size_t>((size_t)Bmax, el.size() - e0);
+    bool contiguous = true;                          // outputs at ov[0] + z oct
+    for (int z = 0; z < B; ++z) {
+      ov[z] = el[e0 + z].out;
+      contiguous &= ov[z] == ov[0] + (size_t)z * oct;
+    }
+    auto operands = [&](u32 part) {
+      for (int z = 0; z < B; ++z) {
+        av[z] = el[e0 + z].cu + (size_t)part * cu_ps;
+        bv[z] = el[e0 + z].gal + (size_t)part * gpart;
+      }
+    };
     if (schedule == BM_S1) {
       for (u32 i = 0; i < k; ++i) {
-        kern::tensor(c, cu + (size_t)i * upart, cu_stride, Bg, ln, gbase + (size_t)i * gpart,
-                     (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln, B, l, false);
+        operands(i);
+        kern::tensor_ptrs(c, av.data(), cu_cs, 0, bv.data(), gcs, 0, 1, d3.p(), 3 * ln, B, l);
         u64* dst = i == 0 ? acc.p() : acc2.p();
         ev::relin_rescale(c, d3.p(), B, l, rlk, dst);
         if (i > 0) kern::add(c, acc.p(), nln, acc2.p(), nln, acc.p(), nln, 2 * B, kern::chain_map(nl));
       }
-    } else if (schedule == BM_S2) {          // the k tensors summed in one pass
-      kern::tensor(c, cu, cu_stride, Bg, ln, gbase, (size_t)k * gpart, Bg, (size_t)lg_store * N, d3.p(), 3 * ln,
-                   B, l, false, (int)k, upart, gpart);
+    } else {                                        // the k tensors summed in one pass
+      operands(0);
+      kern::tensor_ptrs(c, av.data(), cu_cs, cu_ps, bv.data(), gcs, gpart, (int)k, d3.p(), 3 * ln, B, l);
       ev::relin_rescale(c, d3.p(), B, l, rlk, acc.p());
-    } else {
-      BM_THROW(BM_EINVAL, "unknown schedule");
     }
     u64* a = acc.p();
     u64* b = acc2.p();
@@ -235,9 +253,9 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
     }
     if (hoist) {
       if (!hs.empty()) {
-        // one query at the output level: the sum lands in the result directly
-        if (nq == 1 && rot_limbs == out_limbs) {
-          ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, out + g0 * oct);
+        // outputs side by side at the output level: the sum lands there directly
+        if (contiguous && rot_limbs == out_limbs) {
+          ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, ov[0]);
           continue;
         }
         ev::rotation_sum_hoisted(c, evk, a, B, rot_limbs, hs, hkeys, b);
@@ -249,9 +267,86 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
         std::swap(a, b);
       }
     }
-    kern::copy_limbs(c, a, 2 * rln, rln, out + g0 * oct, Bg, out_qstride, oct, (size_t)out_limbs * N,
-                     B, 2, out_limbs);
+    if (contiguous)
+      kern::copy_limbs(c, a, 2 * rln, rln, ov[0], 1, oct, 0, (size_t)out_limbs * N, B, 2, out_limbs);
+    else
+      kern::copy_ptrs(c, a, 2 * rln, rln, ov.data(), (size_t)out_limbs * N, B, 2, out_limbs);
   }
+}
+
+void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_stride, u32 d, u32 k,
+                 const u64* gal, u64 G, int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs,
+                 u64* out, size_t out_qstride, bool hoist) {
+  const size_t N = c.N, ln = (size_t)l * N;
+  const size_t gpart = 2 * (size_t)lg_store * N, oct = (size_t)2 * out_limbs * N;
+  // passes of Bg groups x nq queries (query-major inside a pass)
+  const u64 per_q = std::max<u64>(1, (u64)pass_elems(c) / (u64)nq);
+  const u64 Bg_max = std::min<u64>(per_q, G);
+  std::vector<Elem> el;
+  el.reserve((size_t)G * nq);
+  for (u64 g0 = 0; g0 < G; g0 += Bg_max) {
+    const u64 Bg = std::min<u64>(Bg_max, G - g0);
+    for (int j = 0; j < nq; ++j)
+      for (u64 gi = 0; gi < Bg; ++gi)
+        el.push_back(Elem{cu + (size_t)j * cu_stride, gal + (g0 + gi) * k * gpart,
+                          out + (size_t)j * out_qstride + (g0 + gi) * oct});
+  }
+  // whole blocks per pass; a last, partial block of groups is a pass of its own
+  const int per_pass = (int)(Bg_max * (u64)nq);
+  const size_t full = (size_t)(G / Bg_max) * (size_t)per_pass;
+  std::vector<Elem> head(el.begin(), el.begin() + full), tail(el.begin() + full, el.end());
+  hec3_elems(c, evk, head, ln, 2 * ln, d, k, lg_store, l, schedule, rot_limbs, out_limbs, hoist, per_pass);
+  hec3_elems(c, evk, tail, ln, 2 * ln, d, k, lg_store, l, schedule, rot_limbs, out_limbs, hoist, per_pass);
+}
+
+void load_queries(Ctx& c, const BatchClass& K, u64* qbuf) {
+  const int ql = K.s.ql;
+  for (size_t j = 0; j < K.queries.size(); ++j)
+    ev::drop(c, K.queries[j]->buf.p(), 1, 2, (int)K.queries[j]->limbs, ql, qbuf + j * 2 * (size_t)ql * c.N);
+}
+
+void class_body(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const BatchClass& K, const bm_gallery* const* gs,
+                const u64* qbuf, u64* out) {
+  const Plan& s = K.s;
+  const bm_gallery& g0 = *K.shape;
+  const size_t N = c.N;
+  const u32 d = g0.d, k = g0.k;
+  const int nq = (int)K.queries.size(), ql = s.ql, t = s.t;
+  const u64* cu = qbuf;
+  size_t cu_cs = (size_t)ql * N, cu_ps = 2 * (size_t)ql * N, cu_stride = 2 * (size_t)ql * N;   // k = 1: ql = t
+  DBuf cub;
+  if (k > 1) {
+    cub = DBuf(&c, (size_t)nq * k * 2 * t * N);
+    expand_batch(c, evk, qbuf, 2 * (size_t)ql * N, (size_t)ql * N, nq, ql, K.masks->pt.p(), d, k, cub.p(), s.hoist);
+    cu = cub.p();
+    cu_cs = (size_t)t * N;
+    cu_ps = 2 * (size_t)t * N;
+    cu_stride = (size_t)k * 2 * t * N;
+  }
+  const size_t gpart = 2 * (size_t)g0.limbs * N;
+  const int hl = s.comp ? s.rot : s.ol;              // limbs of the Alg. 2 outputs
+  const size_t oct = 2 * (size_t)hl * N;
+  size_t tmp_words = 0;                              // compression: the group outputs first
+  std::vector<size_t> tmp_off(K.pairs.size());
+  for (size_t pi = 0; pi < K.pairs.size(); ++pi) {
+    tmp_off[pi] = tmp_words;
+    tmp_words += (size_t)gs[K.pairs[pi]]->groups * oct;
+  }
+  DBuf tmp(s.comp ? DBuf(&c, tmp_words) : DBuf());
+  std::vector<Elem> el;
+  for (size_t pi = 0; pi < K.pairs.size(); ++pi) {
+    const size_t p = K.pairs[pi];
+    const bm_gallery& g = *gs[p];
+    u64* dst = s.comp ? tmp.p() + tmp_off[pi] : out + bp.out_off[p];
+    for (u64 gi = 0; gi < g.groups; ++gi)
+      el.push_back(Elem{cu + (size_t)K.qidx[pi] * cu_stride, g.buf.p() + gi * k * gpart, dst + gi * oct});
+  }
+  hec3_elems(c, evk, el, cu_cs, cu_ps, d, k, (int)g0.limbs, t, s.sched, s.rot, hl, s.hoist);
+  if (s.comp)
+    for (size_t pi = 0; pi < K.pairs.size(); ++pi) {
+      const size_t p = K.pairs[pi];
+      compress(c, evk, tmp.p() + tmp_off[pi], oct, gs[p]->groups, d, k, K.cmask, s.rot, s.ol, out + bp.out_off[p]);
+    }
 }
 
 // Compression method (Sec. 3.4, Prop. 3).  Every group output is multiplied

@@ -49,6 +49,56 @@ void hec3_groups(Ctx& c, const bm_evk* evk, const u64* cu, int nq, size_t cu_str
 // Alg. 1 with its log2 k steps unrolled into one hoisted rotation sum per part
 void expand_hoisted(Ctx& c, const bm_evk* evk, const u64* q, int qlimbs, const u64* masks, u32 d, u32 k,
                     u64* out);
+// Alg. 1 for nq queries in one batch of nq k elements: query j at q + j qs,
+// [2][.][N] with component stride qcs, read at its first qlimbs limbs;
+// out [nq][k][2][qlimbs-1][N].  Plain or hoisted (the part's amounts shared by
+// every query).
+void expand_batch(Ctx& c, const bm_evk* evk, const u64* q, size_t qs, size_t qcs, int nq, int qlimbs,
+                  const u64* masks, u32 d, u32 k, u64* out, bool hoist);
+
+// One (query, gallery group) element of Alg. 2: the query's k expanded parts
+// at cu (part p at cu + p cu_ps, component stride cu_cs), the group's k parts
+// at gal (part p at gal + p gpart, component stride lg_store N), the result
+// [2][out_limbs][N] to out.
+struct Elem {
+  const u64* cu;
+  const u64* gal;
+  u64* out;
+};
+// Alg. 2 for any list of elements of one shape (d, k, stored gallery limbs),
+// in passes of per_pass elements (0: pass_elems) in list order: every launch
+// covers the elements of a pass whatever query and gallery they come from.
+void hec3_elems(Ctx& c, const bm_evk* evk, const std::vector<Elem>& el, size_t cu_cs, size_t cu_ps, u32 d, u32 k,
+                int lg_store, int l, u32 schedule, int rot_limbs, int out_limbs, bool hoist, int per_pass = 0);
+// elements (query x group pairs) per pass: the context's group chunk, else
+// 16 at N = 2^16 and 64 below
+int pass_elems(const Ctx& c);
+
+// A batch of (query, gallery) pairs split into shape classes: the pairs
+// whose galleries share (d, k, stored limbs) share every launch of their
+// class (one expansion batch over the class's distinct queries, Alg. 2 over
+// all of its (pair, gallery group) elements).
+struct BatchClass {
+  const bm_gallery* shape = nullptr;     // a gallery of the class (d, k, stored limbs)
+  Plan s;
+  const bm_masks* masks = nullptr;       // Alg. 1 masks at scale q_{ql-1} (k > 1)
+  const u64* cmask = nullptr;            // compression mask (BM_COMPRESS)
+  std::vector<const bm_ct*> queries;     // distinct queries of the class
+  std::vector<size_t> pairs;             // batch indices
+  std::vector<int> qidx;                 // query of each pair (index into queries)
+};
+struct BatchPlan {
+  std::vector<BatchClass> cls;
+  std::vector<size_t> out_off;           // words: result of pair p at out + out_off[p]
+  std::vector<double> scale;             // result scale of pair p
+  size_t out_words = 0;
+};
+// class K's queries cut to ql limbs, side by side: qbuf [nq][2][ql][N]
+void load_queries(Ctx& c, const BatchClass& K, u64* qbuf);
+// the device work of class K: its queries at qbuf ([nq][2][ql][N]), the
+// result of pair p to out + out_off[p]; gs[p] is pair p's gallery
+void class_body(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const BatchClass& K, const bm_gallery* const* gs,
+                const u64* qbuf, u64* out);
 
 // Compression method: in holds G HE-C^3 outputs [2][rl][N] at stride
 // in_stride; mask [rl..][N] is the score mask at scale q_{rl-1};

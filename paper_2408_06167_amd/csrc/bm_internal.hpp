@@ -133,12 +133,24 @@ struct ModUpTable {                       // one per level (number of chain limb
 };
 
 // Galois elements of a hoisted rotation sum, passed by value to the kernels:
-// g[a] for amount a of every element, or g[z * A + a] per element z.
+// g[a] for amount a of every element, or g[(z % mod) * A + a] per element z
+// (mod = the elements of one amount list, e.g. the k parts of each query).
 constexpr int HOIST_MAX = 256;
 struct HoistArgs {
   uint32_t g[HOIST_MAX];
   int A;
   int per_elem;
+  int mod = 1 << 30;
+};
+
+// Per-element operand addresses of one launch, passed by value: element z of
+// a launch reads or writes at p[z].  A launch covers at most PTR_MAX elements.
+constexpr int PTR_MAX = 64;
+struct PtrTab {
+  const u64* p[PTR_MAX];
+};
+struct OutTab {
+  u64* p[PTR_MAX];
 };
 
 struct ModDownTable {
@@ -229,6 +241,8 @@ class DevicePool {
   void* alloc(size_t bytes);
   void release(void* p, size_t bytes);
   size_t bytes_held() const { return held_; }
+  // of which cached (freed, kept for reuse)
+  size_t bytes_cached() const { return cached_; }
   size_t peak() const { return peak_; }
   void trim();
   // later blocks come from `hook` (null: hipMalloc); cached blocks are freed
@@ -246,7 +260,7 @@ class DevicePool {
   std::shared_ptr<const AllocHook> hook_;
   std::map<void*, std::shared_ptr<const AllocHook>> hooked_;   // block -> the hook that made it
   std::multimap<size_t, void*> free_;
-  size_t held_ = 0;
+  size_t held_ = 0, cached_ = 0;
   std::mutex mu_;
 };
 
@@ -310,6 +324,7 @@ struct GraphEntry {
   std::vector<uint64_t> key;
   std::shared_ptr<DevicePool> pool;
   DBuf q_slot, out_slot;
+  std::vector<DBuf> slots;   // a batch's query slots, one per shape class
   hipGraphExec_t exec = nullptr;
   ~GraphEntry();
 };
@@ -358,6 +373,8 @@ struct Ctx {
   std::string last_error;
   // tuning knobs (result-invariant)
   int group_chunk = 0;             // gallery groups per batched pass (0 = auto)
+  int kip_variant = 0;             // hoisted key inner product: elements x amounts per thread (0 = default)
+  int ntt_views = 0;               // row-pass views per block of the N = 2^16 transforms (0 = 16)
 
   bool owns_tables = true;         // false for a lane sharing another context's tables
   std::shared_ptr<Profiler> prof = std::make_shared<Profiler>();
@@ -429,10 +446,10 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
 // signed integer polynomial [N] -> residues in limbs of m (coefficient domain)
 void reduce_int(const Ctx& c, const int64_t* src, u64* out, size_t out_stride, int B,
                 size_t src_stride, const LimbMap& m);
-// out[z][comp][l] = ct[z][comp][l] * pt[z][l], both components, chain limbs l < limbs
-// (ccs / ocs: component strides; sct = 0 broadcasts one ciphertext)
+// out[z][comp][l] = ct[z / ct_div][comp][l] * pt[z % pt_mod][l], both
+// components, chain limbs l < limbs (ccs / ocs: component strides)
 void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out, size_t so,
-               size_t ocs, int B, int limbs);
+               size_t ocs, int B, int limbs, int ct_div = 1, int pt_mod = 1 << 30);
 // out = a + b, a - b, a * b (general), per limb of m; strides per operand (0 = broadcast)
 void add(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o, size_t so,
          int B, const LimbMap& m);
@@ -443,6 +460,15 @@ void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
 // o_limb += s_limb * scalar[limb] (scalar per limb slot, Shoup pair list)
 void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal /*[n][2] device*/,
                  u64* o, size_t so, int B, const LimbMap& m);
+// tensor products of n elements whose operands sit at a[z] and b[z] (host
+// lists of device addresses; any n, split into launches of PTR_MAX): the
+// same product and part sum as tensor() below, output o + z so
+void tensor_ptrs(const Ctx& c, const u64* const* a, size_t a_cs, size_t a_ps, const u64* const* b, size_t b_cs,
+                 size_t b_ps, int parts, u64* o, size_t so, int n, int limbs);
+// out[z] (host list of device addresses) = `limbs` limbs of both components of
+// in + z si (component strides ics and ocs)
+void copy_ptrs(const Ctx& c, const u64* in, size_t si, size_t ics, u64* const* out, size_t ocs, int n,
+               int comps, int limbs);
 // tensor product (a0,a1) x (b0,b1) -> (d0,d1,d2), optionally accumulated into o;
 // batch element z uses a[z / a_div] and b[z % b_mod]
 // a_cs, b_cs: component strides of the operands (>= limbs * N); with parts > 1

@@ -1119,7 +1119,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   const std::vector<uint64_t> key = {(uint64_t)evk, (uint64_t)evk->rlk.k.p(), (uint64_t)g->buf.p(),
                                      g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
                                      (uint64_t)cmask, schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
-                                     (uint64_t)c.group_chunk};
+                                     (uint64_t)c.group_chunk, (uint64_t)c.kip_variant, (uint64_t)c.ntt_views};
   const u64 n_out = bmx::out_cts(s, g->groups, g->d, g->k);
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
@@ -1152,7 +1152,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
       throw;
     }
     std::swap(c.pool, ne->pool);
-    if (c.graphs.size() >= 8) {
+    if (c.graphs.size() >= 16) {
       HIP_OK(dev::stream_sync(c.stream));
       c.graphs.erase(c.graphs.begin());
     }
@@ -1281,79 +1281,294 @@ int bm_match_noalloc(bm_ctx* ctx, const bm_evk* evk, const uint64_t* q_words, ui
   });
 }
 
-// Several queries against one gallery in one batched Alg. 2 pass: query x
-// group pairs share every launch.  Bit-identical to per-query bm_match.
-static void match_multi(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, int nq,
-                        const bm_gallery* g, uint32_t schedule, uint32_t out_limbs, bm_result** outs) {
+// ---------------------------------------------------------------- batched matching
+//
+// A batch of (query, gallery) pairs of any shapes.  Pairs whose galleries share
+// a shape (d, k, stored limbs) form one class: the class's distinct queries
+// are expanded together (one batch of query x part elements), and Alg. 2 runs
+// over every (pair, gallery group) element of the class in passes of the
+// context's group chunk, whatever gallery an element comes from.  The words
+// are those of per-pair bm_match (every operation is exact and element-wise
+// across a batch).
+
+using bmx::BatchClass;
+using bmx::BatchPlan;
+
+static BatchPlan plan_batch(bm_ctx* ctx, const bm_ct* const* qs, const bm_gallery* const* gs, size_t n,
+                            uint32_t schedule, uint32_t out_limbs) {
   Ctx& c = ctx->c;
-  const Plan s = match_shape(c, qs[0], g, schedule, out_limbs);
-  const uint32_t k = g->k;
-  const size_t N = c.N;
-  const bm_masks* m = k > 1 ? masks_for(ctx, g, nullptr, s.ql) : nullptr;
-  const size_t cu_stride = (size_t)k * 2 * s.t * N;
-  DBuf cu(&c, (size_t)nq * cu_stride);
-  DBuf cut(k > 1 ? DBuf(&c, (size_t)2 * s.ql * N) : DBuf());
-  double cu_scale = 0;
-  for (int j = 0; j < nq; ++j) {
-    const bm_ct* q = qs[j];
-    REQUIRE(q->comps == 2 && q->limbs == qs[0]->limbs && q->scale == qs[0]->scale, BM_ELEVEL,
-            "queries of one gallery differ in level or scale");
-    REQUIRE(!q->query_d || q->query_d == g->d, BM_EDIM, "query packed for another dimension than the gallery");
-    if (k == 1) {
-      ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.t, cu.p() + j * cu_stride);
-      cu_scale = q->scale;
-    } else {
-      const u64* qq = q->buf.p();
-      if ((int)q->limbs > s.ql) {
-        ev::drop(c, q->buf.p(), 1, 2, (int)q->limbs, s.ql, cut.p());
-        qq = cut.p();
-      }
-      (s.hoist ? bmx::expand_hoisted : bmx::expand)(c, evk, qq, s.ql, m->pt.p(), g->d, k,
-                                                    cu.p() + j * cu_stride);
-      cu_scale = q->scale * m->scale / (double)c.primes[s.ql - 1].q;
+  BatchPlan bp;
+  bp.out_off.resize(n);
+  bp.scale.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    const bm_ct* q = qs[i];
+    const bm_gallery* g = gs[i];
+    const Plan s = match_shape(c, q, g, schedule, out_limbs);
+    BatchClass* K = nullptr;
+    for (auto& cl : bp.cls)
+      if (cl.shape->d == g->d && cl.shape->k == g->k && cl.shape->limbs == g->limbs) K = &cl;
+    if (!K) {
+      bp.cls.emplace_back();
+      K = &bp.cls.back();
+      K->shape = g;
+      K->s = s;
+      if (g->k > 1) K->masks = masks_for(ctx, g, nullptr, s.ql);
+      K->cmask = cmask_for(ctx, g, s);
+    }
+    double cu_scale = q->scale;
+    if (g->k > 1) cu_scale = q->scale * K->masks->scale / (double)c.primes[s.ql - 1].q;
+    REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
+    int j = 0;
+    while (j < (int)K->queries.size() && K->queries[j] != q) ++j;
+    if (j == (int)K->queries.size()) K->queries.push_back(q);
+    K->pairs.push_back(i);
+    K->qidx.push_back(j);
+    bp.out_off[i] = bp.out_words;
+    bp.scale[i] = bmx::result_scale(c, s, cu_scale, g->scale);
+    bp.out_words += (size_t)bmx::out_cts(s, g->groups, g->d, g->k) * 2 * s.ol * c.N;
+  }
+  return bp;
+}
+
+static void batch_eager(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const bm_gallery* const* gs, u64* out) {
+  for (const BatchClass& K : bp.cls) {
+    DBuf qb(&c, K.queries.size() * 2 * (size_t)K.s.ql * c.N);
+    bmx::load_queries(c, K, qb.p());
+    bmx::class_body(c, evk, bp, K, gs, qb.p(), out);
+  }
+}
+
+// Replay (capturing on first use) the batch as one HIP graph: the queries are
+// copied into the graph's per-class slots, the results out of its output slot.
+static void batch_graph(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const bm_ct* const* qs,
+                        const bm_gallery* const* gs, size_t n, uint32_t schedule, uint32_t out_limbs, u64* out) {
+  std::vector<uint64_t> key = {0xBA7C4ULL, (uint64_t)evk, (uint64_t)evk->rlk.k.p(), schedule, out_limbs,
+                               (uint64_t)c.stream, (uint64_t)c.group_chunk, (uint64_t)c.kip_variant,
+                               (uint64_t)c.ntt_views, n};
+  for (const BatchClass& K : bp.cls) {
+    key.push_back((uint64_t)(K.masks ? K.masks->pt.p() : nullptr));
+    key.push_back((uint64_t)K.cmask);
+    key.push_back(K.queries.size());
+    for (size_t pi = 0; pi < K.pairs.size(); ++pi) {
+      const bm_gallery* g = gs[K.pairs[pi]];
+      key.insert(key.end(), {K.pairs[pi], (uint64_t)K.qidx[pi], (uint64_t)g->buf.p(), g->groups, g->d, g->k,
+                             g->limbs, qs[K.pairs[pi]]->limbs});
     }
   }
-  REQUIRE(cu_scale == g->scale, BM_ESCALE, "query and gallery scales differ");
-  const size_t per = (size_t)bmx::out_cts(s, g->groups, g->d, k) * 2 * s.ol * N;
-  auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
-  bmx::match_groups(c, evk, s, cu.p(), nq, cu_stride, *g, cmask_for(ctx, g, s), store->p(), per);
-  for (int j = 0; j < nq; ++j) {
-    std::unique_ptr<bm_result> r(new_result(ctx, g, s, bmx::result_scale(c, s, cu_scale, g->scale)));
-    r->store = store;
-    r->off = (size_t)j * per;
-    outs[j] = r.release();
+  GraphEntry* e = nullptr;
+  for (auto& ge : c.graphs)
+    if (ge->key == key) e = ge.get();
+  if (!e) {
+    std::unique_ptr<GraphEntry> ne(new GraphEntry);
+    ne->key = key;
+    ne->pool.reset(new DevicePool(c.device, c.hook));
+    std::swap(c.pool, ne->pool);          // scratch of the capture comes from the graph's pool
+    hipGraph_t graph = nullptr;
+    bool capturing = false;
+    try {
+      for (const BatchClass& K : bp.cls) ne->slots.emplace_back(&c, K.queries.size() * 2 * (size_t)K.s.ql * c.N);
+      ne->out_slot = DBuf(&c, bp.out_words);
+      HIP_OK(dev::begin_capture(c.stream));
+      capturing = true;
+      for (size_t ci = 0; ci < bp.cls.size(); ++ci)
+        bmx::class_body(c, evk, bp, bp.cls[ci], gs, ne->slots[ci].p(), ne->out_slot.p());
+      capturing = false;
+      HIP_OK(dev::end_capture(c.stream, &graph));
+      HIP_OK(dev::graph_instantiate(&ne->exec, graph));
+      HIP_OK(dev::graph_destroy(graph));
+    } catch (...) {
+      if (capturing) {
+        hipGraph_t dead = nullptr;
+        (void)dev::end_capture(c.stream, &dead);
+        if (dead) (void)dev::graph_destroy(dead);
+      }
+      std::swap(c.pool, ne->pool);
+      throw;
+    }
+    std::swap(c.pool, ne->pool);
+    if (c.graphs.size() >= 16) {
+      HIP_OK(dev::stream_sync(c.stream));
+      c.graphs.erase(c.graphs.begin());
+    }
+    c.graphs.push_back(std::move(ne));
+    e = c.graphs.back().get();
+  }
+  for (size_t ci = 0; ci < bp.cls.size(); ++ci) bmx::load_queries(c, bp.cls[ci], e->slots[ci].p());
+  HIP_OK(dev::graph_launch(e->exec, c.stream));
+  // the results: rows of N words, up to 65,535 rows per launch
+  const size_t rows = bp.out_words / c.N;
+  for (size_t r0 = 0; r0 < rows; r0 += 65535) {
+    const int nr = (int)std::min<size_t>(65535, rows - r0);
+    kern::copy_limbs(c, e->out_slot.p() + r0 * c.N, c.N, 0, out + r0 * c.N, 1, c.N, 0, 0, nr, 1, 1);
+  }
+}
+
+static void match_batch_impl(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
+                             size_t n_pairs, uint32_t schedule, uint32_t out_limbs,
+                             std::vector<std::unique_ptr<bm_result>>& res) {
+  Ctx& c = ctx->c;
+  const BatchPlan bp = plan_batch(ctx, qs, gs, n_pairs, schedule, out_limbs);
+  auto store = std::make_shared<DBuf>(&c, bp.out_words);
+  if (c.use_graphs && !c.prof->on)
+    batch_graph(c, evk, bp, qs, gs, n_pairs, schedule, out_limbs, store->p());
+  else
+    batch_eager(c, evk, bp, gs, store->p());
+  res.clear();
+  res.resize(n_pairs);
+  for (const BatchClass& K : bp.cls)
+    for (size_t p : K.pairs) {
+      res[p].reset(new_result(ctx, gs[p], K.s, bp.scale[p]));
+      res[p]->store = store;
+      res[p]->off = bp.out_off[p];
+    }
+}
+
+static void check_pairs(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
+                        size_t n_pairs) {
+  REQUIRE(ctx && evk && qs && gs, BM_EINVAL, "NULL argument");
+  REQUIRE(n_pairs > 0, BM_EINVAL, "empty batch");
+  same_ctx(ctx, evk);
+  for (size_t i = 0; i < n_pairs; ++i) {
+    REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
+    same_ctx(ctx, qs[i], gs[i]);
   }
 }
 
 int bm_match_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
                    size_t n_pairs, uint32_t schedule, uint32_t out_limbs, void* stream, bm_result** outs) {
   return guarded(ctx, [&] {
-    REQUIRE(ctx && evk && qs && gs && outs, BM_EINVAL, "NULL argument");
-    same_ctx(ctx, evk);
+    REQUIRE(outs, BM_EINVAL, "NULL argument");
+    check_pairs(ctx, evk, qs, gs, n_pairs);
     ctx->c.use_stream(stream);
-    for (size_t i = 0; i < n_pairs; ++i) {
-      REQUIRE(qs[i] && gs[i], BM_EINVAL, "NULL pair");
-      same_ctx(ctx, qs[i], gs[i]);
-    }
-    // pairs that share a gallery (and query level) go through one batched pass
-    std::vector<std::unique_ptr<bm_result>> res(n_pairs);
-    std::vector<bool> done(n_pairs, false);
-    const size_t max_q = 16;
-    for (size_t i = 0; i < n_pairs; ++i) {
-      if (done[i]) continue;
-      std::vector<size_t> idx;
-      for (size_t j = i; j < n_pairs && idx.size() < max_q; ++j)
-        if (!done[j] && gs[j] == gs[i] && qs[j]->limbs == qs[i]->limbs) idx.push_back(j);
-      std::vector<const bm_ct*> qv;
-      for (size_t j : idx) qv.push_back(qs[j]);
-      std::vector<bm_result*> rv(idx.size(), nullptr);
-      match_multi(ctx, evk, qv.data(), (int)qv.size(), gs[i], schedule, out_limbs, rv.data());
-      for (size_t a = 0; a < idx.size(); ++a) {
-        res[idx[a]].reset(rv[a]);
-        done[idx[a]] = true;
-      }
-    }
+    std::vector<std::unique_ptr<bm_result>> res;
+    match_batch_impl(ctx, evk, qs, gs, n_pairs, schedule, out_limbs, res);
     for (size_t i = 0; i < n_pairs; ++i) outs[i] = res[i].release();
+  });
+}
+
+int bm_ctx_set_tuning(bm_ctx* ctx, const bm_tuning* t) {
+  return guarded(ctx, [&] {
+    REQUIRE(ctx && t, BM_EINVAL, "NULL argument");
+    REQUIRE(t->group_chunk <= 4096, BM_EINVAL, "group_chunk above 4096");
+    REQUIRE(t->kip_variant <= 4, BM_EINVAL, "kip_variant in 0..4");
+    REQUIRE(t->ntt_row_views == 0 || t->ntt_row_views == 4 || t->ntt_row_views == 8 || t->ntt_row_views == 16,
+            BM_EINVAL, "ntt_row_views: 0, 4, 8 or 16");
+    Ctx& c = ctx->c;
+    c.group_chunk = (int)t->group_chunk;
+    c.kip_variant = (int)t->kip_variant;
+    c.ntt_views = (int)t->ntt_row_views;
+  });
+}
+
+int bm_ctx_get_tuning(const bm_ctx* ctx, bm_tuning* t) {
+  if (!ctx || !t) return BM_EINVAL;
+  t->group_chunk = (uint32_t)ctx->c.group_chunk;
+  t->kip_variant = (uint32_t)ctx->c.kip_variant;
+  t->ntt_row_views = (uint32_t)ctx->c.ntt_views;
+  return BM_OK;
+}
+
+// Times the batch under every schedule offered (skipping those whose keys or
+// levels the inputs lack), then, under the fastest, each result-invariant
+// knob in turn (coordinate descent: group chunk, key inner product variant,
+// row-pass tiling), checking that every knob setting gives the words of the
+// first and last pair that the default setting gave.
+int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
+                      size_t n_pairs, const uint32_t* schedules, size_t n_schedules, uint32_t out_limbs,
+                      uint32_t* best_schedule, bm_tuning* best, double* best_ms) {
+  return guarded(ctx, [&] {
+    check_pairs(ctx, evk, qs, gs, n_pairs);
+    REQUIRE(schedules && n_schedules > 0, BM_EINVAL, "no schedule to tune");
+    Ctx& c = ctx->c;
+    c.use_stream(nullptr);
+    const int s_chunk = c.group_chunk, s_var = c.kip_variant, s_views = c.ntt_views;
+    hipEvent_t ea, eb;
+    HIP_OK(dev::event_create(&ea, true));
+    HIP_OK(dev::event_create(&eb, true));
+    std::vector<std::unique_ptr<bm_result>> res;
+    auto words = [&]() {                       // all groups of the first and last pair
+      std::vector<u64> w;
+      for (size_t p : {(size_t)0, n_pairs - 1}) {
+        const bm_result& r = *res[p];
+        std::vector<u64> h((size_t)r.groups * 2 * r.limbs * c.N);
+        ev::export_coeffs(c, r.p(), (int)(2 * r.groups), (int)r.limbs, h.data());
+        w.insert(w.end(), h.begin(), h.end());
+      }
+      return w;
+    };
+    auto drop = [&] {                          // a candidate's graph and scratch are not kept
+      HIP_OK(dev::stream_sync(c.stream));
+      c.graphs.clear();
+    };
+    auto timed = [&](uint32_t sched) {
+      drop();
+      match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);   // warm-up, capture
+      res.clear();
+      HIP_OK(dev::event_record(ea, c.stream));
+      for (int rep = 0; rep < 2; ++rep) match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);
+      HIP_OK(dev::event_record(eb, c.stream));
+      HIP_OK(dev::event_sync(eb));
+      float ms = 0;
+      HIP_OK(dev::event_elapsed(&ms, ea, eb));
+      return (double)ms / 2;
+    };
+    double bms = 1e30;
+    uint32_t bsched = 0;
+    try {
+      for (size_t i = 0; i < n_schedules; ++i) {
+        double ms;
+        try {
+          ms = timed(schedules[i]);
+        } catch (const Error& e) {
+          if (e.code != BM_ENOKEY && e.code != BM_ELEVEL) throw;
+          continue;                             // this schedule is not available for these inputs
+        }
+        if (ms < bms) {
+          bms = ms;
+          bsched = schedules[i];
+        }
+      }
+      REQUIRE(bsched != 0, BM_ENOKEY, "no offered schedule can run on these inputs");
+      (void)timed(bsched);
+      const std::vector<u64> ref = words();
+      int* knob[3] = {&c.group_chunk, &c.kip_variant, &c.ntt_views};
+      const std::vector<int> values[3] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {16, 8, 4}};
+      for (int kn = 0; kn < 3; ++kn) {
+        int pick = *knob[kn];
+        for (int v : values[kn]) {
+          *knob[kn] = v;
+          const double ms = timed(bsched);
+          if (!dev::dry() && words() != ref)   // (a dry run computes nothing to compare)
+            BM_THROW(BM_EDEVICE, "a result-invariant knob changed the result words");
+          if (ms < bms) {
+            bms = ms;
+            pick = v;
+          }
+        }
+        *knob[kn] = pick;
+      }
+    } catch (...) {
+      res.clear();
+      (void)dev::stream_sync(c.stream);
+      c.graphs.clear();
+      c.group_chunk = s_chunk;
+      c.kip_variant = s_var;
+      c.ntt_views = s_views;
+      (void)dev::event_destroy(ea);
+      (void)dev::event_destroy(eb);
+      throw;
+    }
+    res.clear();
+    drop();
+    (void)dev::event_destroy(ea);
+    (void)dev::event_destroy(eb);
+    if (best_schedule) *best_schedule = bsched;
+    if (best) {
+      best->group_chunk = (uint32_t)c.group_chunk;
+      best->kip_variant = (uint32_t)c.kip_variant;
+      best->ntt_row_views = (uint32_t)c.ntt_views;
+    }
+    if (best_ms) *best_ms = bms;
   });
 }
 

@@ -110,6 +110,7 @@ void DevicePool::free_cached() {
     hooked_.erase(h);
   }
   free_.clear();
+  cached_ = 0;
 }
 
 void* DevicePool::new_block(size_t bytes) {
@@ -133,6 +134,7 @@ void* DevicePool::alloc(size_t bytes) {
   if (it != free_.end()) {
     void* p = it->second;
     free_.erase(it);
+    cached_ -= bytes;
     return p;
   }
   void* p = new_block(bytes);
@@ -153,6 +155,7 @@ void DevicePool::release(void* p, size_t bytes) {
     return;
   }
   free_.emplace(bytes, p);
+  cached_ += bytes;
 }
 
 void DevicePool::trim() {
@@ -191,6 +194,7 @@ GraphEntry::~GraphEntry() {
   if (exec && !dev::dry()) (void)hipGraphExecDestroy(exec);
   q_slot = DBuf();
   out_slot = DBuf();
+  slots.clear();
 }
 
 void Ctx::use_stream(void* s) {
@@ -249,6 +253,8 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->h_modup = h_modup;
   l->h_moddown = h_moddown;
   l->group_chunk = group_chunk;
+  l->kip_variant = kip_variant;
+  l->ntt_views = ntt_views;
   l->owns_tables = false;
   l->prof = prof;
   HIP_OK(dev::set_device(device));

@@ -784,12 +784,12 @@ __global__ void k_mul(const u64* a, size_t sa, const u64* b, size_t sb, u64* o, 
 // out[z][comp][l] = ct[z][comp][l] * pt[z][l] over the chain limbs l < limbs,
 // both components in one launch (blockIdx.y = comp * limbs + l)
 __global__ void k_mul_ct_pt(const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out,
-                            size_t so, size_t ocs, int limbs, const PrimeC* P, int N) {
+                            size_t so, size_t ocs, int limbs, const PrimeC* P, int N, int ct_div, int pt_mod) {
   const int l = blockIdx.y % limbs, comp = blockIdx.y / limbs;
   const PrimeC& pr = P[l];
   const size_t bz = blockIdx.z;
-  const u64* A = ct + bz * sct + comp * ccs + (size_t)l * N;
-  const u64* Bp = pt + bz * spt + (size_t)l * N;
+  const u64* A = ct + (bz / ct_div) * sct + comp * ccs + (size_t)l * N;
+  const u64* Bp = pt + (bz % pt_mod) * spt + (size_t)l * N;
   u64* O = out + bz * so + comp * ocs + (size_t)l * N;
   EW_LOOP O[i] = mul_mod(A[i], Bp[i], pr);
 }
@@ -821,21 +821,21 @@ __global__ void k_reduce_int(const int64_t* src, size_t ss, u64* o, size_t so, L
 }
 
 // (a0, a1) x (b0, b1) -> (a0 b0, a0 b1 + a1 b0, a1 b1); limb slot = chain limb.
-// Batch element z pairs operand a[z / a_div] with operand b[z % b_mod], so one
-// launch can cross several queries with several gallery groups.  a_cs and b_cs
-// are the component strides of the operands (they may hold more limbs than
-// the product uses: an exact level drop on the fly).
-__global__ void k_tensor(const u64* a, size_t sa, int a_div, size_t a_cs, size_t a_ps, const u64* b,
-                         size_t sb, int b_mod, size_t b_cs, size_t b_ps, int parts, u64* o, size_t so,
-                         int limbs, const PrimeC* P, int N, int accumulate) {
+// Batch element z multiplies the operands at A.p[z] and Bt.p[z], so one launch
+// can cross any queries with any gallery groups.  a_cs and b_cs are the
+// component strides of the operands (they may hold more limbs than the product
+// uses: an exact level drop on the fly); with parts > 1 the tensors of the
+// part pairs (a + p a_ps, b + p b_ps) are summed.
+__global__ void k_tensor(PtrTab A, size_t a_cs, size_t a_ps, PtrTab Bt, size_t b_cs, size_t b_ps, int parts, u64* o,
+                         size_t so, int limbs, const PrimeC* P, int N, int accumulate) {
   const int l = blockIdx.y;
   const PrimeC& pr = P[l];
   const u64 q = pr.q;
   const size_t bz = blockIdx.z;
   const size_t ln = (size_t)limbs * N;
-  const u64* A0 = a + (bz / a_div) * sa + (size_t)l * N;
+  const u64* A0 = A.p[bz] + (size_t)l * N;
   const u64* A1 = A0 + a_cs;
-  const u64* B0 = b + (bz % b_mod) * sb + (size_t)l * N;
+  const u64* B0 = Bt.p[bz] + (size_t)l * N;
   const u64* B1 = B0 + b_cs;
   u64* O0 = o + bz * so + (size_t)l * N;
   u64* O1 = O0 + ln;
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ void autom_sum_part(const AutomArgs& am, const HoistA
   u64 acc = accumulate ? O[i] : I[i];
 #pragma unroll 4
   for (int a = 0; a < h.A; ++a) {
-    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    const u32 g = h.g[h.per_elem ? (z % h.mod) * h.A + a : a];
     acc = add_mod(acc, I[autom_src((u32)i, g, log_n, ms)], q);
   }
   O[i] = acc;
@@ -1065,7 +1065,7 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   // uniform across the block), so that no global load sits in front of the
   // key words inside the loop
   __shared__ const u64* kp[HOIST_MAX];
-  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[h.per_elem ? z * h.A + a : a] >> 1];
+  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[h.per_elem ? (z % h.mod) * h.A + a : a] >> 1];
   __syncthreads();
   if (i >= N || t >= ext) return;
   const PrimeC& pr = P[tb.ext_prime[t]];
@@ -1090,7 +1090,7 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
     double kb[BETA], ka[BETA];
   };
   auto load = [&](int a, Words& w) {
-    const u32 g = h.g[h.per_elem ? z * h.A + a : a];
+    const u32 g = h.g[h.per_elem ? (z % h.mod) * h.A + a : a];
     const u32 s = autom_src((u32)i, g, log_n, ms);
     const gdp key = (gdp)kp[a];
 #pragma unroll
@@ -1353,6 +1353,15 @@ __global__ void k_copy_limbs(const u64* in, size_t si, size_t ics, u64* out, int
   for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) O[e] = I[e];
 }
 
+// element z of `in` (stride si) to the address out.p[z]
+__global__ void k_copy_ptrs(const u64* in, size_t si, size_t ics, OutTab out, size_t ocs, int limbs, int N) {
+  const int l = blockIdx.y % limbs, c = blockIdx.y / limbs;
+  const size_t bz = blockIdx.z;
+  const u64* I = in + bz * si + c * ics + (size_t)l * N;
+  u64* O = out.p[bz] + c * ocs + (size_t)l * N;
+  for (int e = blockIdx.x * TPB + threadIdx.x; e < N; e += gridDim.x * TPB) O[e] = I[e];
+}
+
 // in place: residue word <-> bit pattern of its FP64 value (exact below 2^53)
 __global__ void k_words_f64(u64* p, size_t n, int to_f64) {
   for (size_t e = (size_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (size_t)gridDim.x * TPB) {
@@ -1475,6 +1484,9 @@ LimbMap single(int prime, int off) {
 }
 
 
+// row-pass views per block (polynomials x rows): 16 unless tuned to 4 or 8
+static int row_views(const Ctx& c) { return c.ntt_views == 4 || c.ntt_views == 8 ? c.ntt_views : 16; }
+
 // N = 2^12: one 12-stage pass; N = 2^16: 8 column stages then 8 row stages
 // (inverse: rows first).  Row passes take up to 16 polynomials per block.
 void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
@@ -1501,12 +1513,14 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     return;
   }
   // row passes: vz polynomials x R rows per block, R the largest power of two
-  // with vz R <= 16 (whole waves for small batches) and at most 64 KiB of LDS
-  const int vz = B < 16 ? B : 16;
+  // with vz R <= V (whole waves for small batches; V = 16 or the context's
+  // tuning) and at most 64 KiB of LDS
+  const int V = row_views(c);
+  const int vz = B < V ? B : V;
   const size_t view_words = 256 + 16 + 1;   // column views; row views are one word shorter
   auto row_lds = [&](int r) { return ((size_t)vz * r * (view_words - 1) + (size_t)512 * r) * sizeof(u64); };
   int R = 1;
-  while (vz * R * 2 <= 16 && row_lds(2 * R) <= 65536) R *= 2;
+  while (vz * R * 2 <= V && row_lds(2 * R) <= 65536) R *= 2;
   const int Vrow = vz * R;
   const size_t lds_col = ((size_t)16 * view_words + 512) * sizeof(u64);
   const size_t lds_row = row_lds(R);
@@ -1581,11 +1595,12 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
   chk_map(c, tmp, B, ts, mo, "fused ntt scratch", true);
   const double elems = (double)N * m.n * B;
   // launch geometry of ntt_fast's forward passes
-  const int vz = B < 16 ? B : 16;
+  const int V = row_views(c);
+  const int vz = B < V ? B : V;
   const size_t view_words = 256 + 16 + 1;
   auto row_lds = [&](int r) { return ((size_t)vz * r * (view_words - 1) + (size_t)512 * r) * sizeof(u64); };
   int R = 1;
-  while (vz * R * 2 <= 16 && row_lds(2 * R) <= 65536) R *= 2;
+  while (vz * R * 2 <= V && row_lds(2 * R) <= 65536) R *= 2;
   const int Vrow = vz * R;
   const size_t lds_col = ((size_t)16 * view_words + 512) * sizeof(u64);
   const dim3 gcol(N / 256 / 16, (unsigned)m.n, (unsigned)B);
@@ -1755,14 +1770,17 @@ void mul(const Ctx& c, const u64* a, size_t sa, const u64* b, size_t sb, u64* o,
 }
 
 void mul_ct_pt(const Ctx& c, const u64* ct, size_t sct, size_t ccs, const u64* pt, size_t spt, u64* out, size_t so,
-               size_t ocs, int B, int limbs) {
+               size_t ocs, int B, int limbs, int ct_div, int pt_mod) {
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: mul_ct_pt limbs");
-  chk(ct, B, sct, 0, ccs + (size_t)limbs * c.N, "mul_ct_pt ciphertext");
-  chk(pt, B, spt, 0, (size_t)limbs * c.N, "mul_ct_pt plaintext");
+  if (ct_div < 1 || pt_mod < 1) BM_THROW(BM_EINVAL, "launch check: mul_ct_pt divisors");
+  const int n_ct = (B - 1) / ct_div + 1, n_pt = std::min(B, pt_mod);
+  chk(ct, n_ct, sct, 0, ccs + (size_t)limbs * c.N, "mul_ct_pt ciphertext");
+  chk(pt, n_pt, spt, 0, (size_t)limbs * c.N, "mul_ct_pt plaintext");
   chk(out, B, so, 0, ocs + (size_t)limbs * c.N, "mul_ct_pt output");
-  Prof pf(c, "k_mul_ct_pt", 8.0 * c.N * limbs * (3.0 * B + (sct ? 2.0 * B : 2.0)), 2.0 * c.N * B * limbs);
+  const double cts = sct ? (double)n_ct : 1.0, pts = spt ? (double)n_pt : 1.0;
+  Prof pf(c, "k_mul_ct_pt", 8.0 * c.N * limbs * (2.0 * B + 2.0 * cts + pts), 2.0 * c.N * B * limbs);
   LAUNCH(k_mul_ct_pt, ew_grid(c.N, 2 * limbs, B), dim3(TPB), 0, c.stream, ct, sct, ccs, pt, spt, out, so, ocs, limbs,
-         c.d_primes, (int)c.N);
+         c.d_primes, (int)c.N, ct_div, pt_mod);
   check_launch();
 }
 
@@ -1777,23 +1795,54 @@ void axpy_scalar(const Ctx& c, const u64* s, size_t ss, const u64* scal, u64* o,
   check_launch();
 }
 
+void tensor_ptrs(const Ctx& c, const u64* const* a, size_t a_cs, size_t a_ps, const u64* const* b, size_t b_cs,
+                 size_t b_ps, int parts, u64* o, size_t so, int n, int limbs, bool accumulate) {
+  if (parts < 1) BM_THROW(BM_EINVAL, "launch check: tensor parts");
+  if (limbs > c.L + 1 || a_cs < (size_t)limbs * c.N || b_cs < (size_t)limbs * c.N)
+    BM_THROW(BM_EINVAL, "launch check: tensor limbs");
+  const size_t pa = (size_t)(parts - 1) * a_ps, pb = (size_t)(parts - 1) * b_ps;
+  for (int z0 = 0; z0 < n; z0 += PTR_MAX) {
+    const int B = std::min(PTR_MAX, n - z0);
+    PtrTab A{}, Bt{};
+    std::vector<const u64*> da, db;          // distinct operands, for the byte count
+    for (int z = 0; z < B; ++z) {
+      A.p[z] = a[z0 + z];
+      Bt.p[z] = b[z0 + z];
+      chk(A.p[z], 1, 0, 0, pa + a_cs + (size_t)limbs * c.N, "tensor a");
+      chk(Bt.p[z], 1, 0, 0, pb + b_cs + (size_t)limbs * c.N, "tensor b");
+      da.push_back(A.p[z]);
+      db.push_back(Bt.p[z]);
+    }
+    u64* oz = o + (size_t)z0 * so;
+    chk(oz, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
+    std::sort(da.begin(), da.end());
+    std::sort(db.begin(), db.end());
+    const double na = (double)(std::unique(da.begin(), da.end()) - da.begin());
+    const double nb = (double)(std::unique(db.begin(), db.end()) - db.begin());
+    // distinct words: each query part and each gallery part once, the outputs
+    Prof pf(c, "k_tensor", 8.0 * c.N * limbs * (2.0 * parts * (na + nb) + (accumulate ? 6.0 : 3.0) * B),
+            4.0 * c.N * B * limbs * parts);
+    LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, A, a_cs, a_ps, Bt, b_cs, b_ps, parts, oz, so,
+           limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
+    check_launch();
+  }
+}
+
+void tensor_ptrs(const Ctx& c, const u64* const* a, size_t a_cs, size_t a_ps, const u64* const* b, size_t b_cs,
+                 size_t b_ps, int parts, u64* o, size_t so, int n, int limbs) {
+  tensor_ptrs(c, a, a_cs, a_ps, b, b_cs, b_ps, parts, o, so, n, limbs, false);
+}
+
 void tensor(const Ctx& c, const u64* a, size_t sa, int a_div, size_t a_cs, const u64* b, size_t sb,
             int b_mod, size_t b_cs, u64* o, size_t so, int B, int limbs, bool accumulate, int parts, size_t a_ps,
             size_t b_ps) {
   if (a_div < 1 || b_mod < 1 || parts < 1) BM_THROW(BM_EINVAL, "launch check: tensor batch divisors");
-  if (limbs > c.L + 1 || a_cs < (size_t)limbs * c.N || b_cs < (size_t)limbs * c.N)
-    BM_THROW(BM_EINVAL, "launch check: tensor limbs");
-  const size_t pa = (size_t)(parts - 1) * a_ps, pb = (size_t)(parts - 1) * b_ps;
-  chk(a, (B - 1) / a_div + 1, sa, 0, pa + a_cs + (size_t)limbs * c.N, "tensor a");
-  chk(b, std::min(B, b_mod), sb, 0, pb + b_cs + (size_t)limbs * c.N, "tensor b");
-  chk(o, B, so, 0, (size_t)3 * limbs * c.N, "tensor out");
-  // distinct words: each query part and each gallery part once, the outputs
-  const double na = (double)((B - 1) / a_div + 1), nb = (double)std::min(B, b_mod);
-  Prof pf(c, "k_tensor", 8.0 * c.N * limbs * (2.0 * parts * (na + nb) + (accumulate ? 6.0 : 3.0) * B),
-          4.0 * c.N * B * limbs * parts);
-  LAUNCH(k_tensor, ew_grid(c.N, limbs, B), dim3(TPB), 0, c.stream, a, sa, a_div, a_cs, a_ps, b, sb, b_mod,
-         b_cs, b_ps, parts, o, so, limbs, c.d_primes, (int)c.N, accumulate ? 1 : 0);
-  check_launch();
+  std::vector<const u64*> av(B), bv(B);
+  for (int z = 0; z < B; ++z) {
+    av[z] = a + (size_t)(z / a_div) * sa;
+    bv[z] = b + (size_t)(z % b_mod) * sb;
+  }
+  tensor_ptrs(c, av.data(), a_cs, a_ps, bv.data(), b_cs, b_ps, parts, o, so, B, limbs, accumulate);
 }
 
 void automorphism(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, int B, int rows,
@@ -1855,7 +1904,8 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
                size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate) {
   const ModUpTable& tb = c.h_modup[limbs];
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
-  if (h.A < 1 || h.A * (h.per_elem ? B : 1) > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
+  const int lists = h.per_elem ? std::min(B, h.mod) : 1;   // amount lists in h.g
+  if (h.A < 1 || h.mod < 1 || h.A * lists > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: hoisted amounts");
   chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "hoisted kip digits");
   chk(y_own, B, sown, 0, (size_t)limbs * c.N, "hoisted kip input");
   chk(gtab, 1, 0, 0, c.M / 2, "key table");
@@ -1868,37 +1918,51 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   // extended limbs), the digits and the input limbs once, both outputs, and
   // the c0 half (gathered sum of the rotations) that rides in the same launch
   std::vector<uint32_t> gs;
-  for (int i = 0; i < h.A * (h.per_elem ? B : 1); ++i) gs.push_back(h.g[i]);
+  for (int i = 0; i < h.A * lists; ++i) gs.push_back(h.g[i]);
   std::sort(gs.begin(), gs.end());
   const double distinct_keys = (double)(std::unique(gs.begin(), gs.end()) - gs.begin());
   const double keys_read = distinct_keys * 2 * tb.beta * tb.ext * c.N;
   const bool grouped = !h.per_elem && B > 1 && c.N % (2 * TPB) == 0;
-  static const char* const zb_names[] = {"", "k_kip_hoist_zb<1, 2, 4>", "k_kip_hoist_zb<2, 2, 2>",
-                                         "k_kip_hoist_zb<3, 2, 1>", "k_kip_hoist_zb<4, 2, 1>"};
-  static const char* const el_names[] = {"", "k_kip_hoist<1>", "k_kip_hoist<2>", "k_kip_hoist<3>",
-                                         "k_kip_hoist<4>"};
-  Prof pf(c, (grouped ? zb_names : el_names)[tb.beta],
+  // shared amounts: ZB elements per thread (each key word loaded once, used
+  // ZB times) and CH amounts' words requested per chunk; variant 0 is the
+  // default of each digit count (two elements a thread measured best at the
+  // face configuration), the others are the autotuner's alternatives
+  static const int zb_tab[5][5] = {{0}, {2, 1, 3, 2, 4}, {2, 1, 3, 2, 2}, {2, 1, 2, 2, 2}, {2, 1, 2, 2, 2}};
+  static const int ch_tab[5][5] = {{0}, {4, 4, 4, 2, 2}, {2, 2, 2, 1, 2}, {1, 1, 1, 1, 1}, {1, 1, 1, 1, 1}};
+  const int var = c.kip_variant >= 0 && c.kip_variant < 5 ? c.kip_variant : 0;
+  const int ZB = zb_tab[tb.beta][var], CH = ch_tab[tb.beta][var];
+  const std::string pname = grouped ? "k_kip_hoist_zb<" + std::to_string(tb.beta) + ", " + std::to_string(ZB) + ", " +
+                                          std::to_string(CH) + ">"
+                                    : "k_kip_hoist<" + std::to_string(tb.beta) + ">";
+  Prof pf(c, pname,
           8.0 * (keys_read + (double)c.N * tb.ext * B * (tb.beta + 2) + 2.0 * c.N * limbs * B),
           2.0 * c.N * tb.ext * tb.beta * B * h.A);
   const size_t gx = (c.N + TPB - 1) / TPB;
   AutomArgs am{c0_in, c0_si, c0_out, c0_so, limbs, (int)(gx * limbs * B)};
   if (am.W % 8 != 0) BM_THROW(BM_EINVAL, "launch check: autom_sum grid");
   if (grouped) {
-    // shared amounts: elements grouped per thread and amounts per chunk (two
-    // elements a thread measured best at the face configuration; the group's
-    // second thread finds the key words in L2)
-    const int ZB = 2;
     const size_t Wz = (c.N / (2 * TPB)) * tb.ext * (size_t)((B + ZB - 1) / ZB);
     if (Wz % 8 != 0 || Wz + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
 #define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                          \
   LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)(Wz + am.W)), dim3(TPB), 0, c.stream, y, sy, y_own, sown, \
          gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,      \
          accumulate ? 1 : 0, am)
-    switch (tb.beta) {
-      case 1: KIP_HOIST_ZB(1, 2, 4); break;
-      case 2: KIP_HOIST_ZB(2, 2, 2); break;
-      case 3: KIP_HOIST_ZB(3, 2, 1); break;
-      default: KIP_HOIST_ZB(4, 2, 1); break;
+    const int code = tb.beta * 100 + ZB * 10 + CH;
+    switch (code) {
+      case 124: KIP_HOIST_ZB(1, 2, 4); break;
+      case 114: KIP_HOIST_ZB(1, 1, 4); break;
+      case 134: KIP_HOIST_ZB(1, 3, 4); break;
+      case 122: KIP_HOIST_ZB(1, 2, 2); break;
+      case 142: KIP_HOIST_ZB(1, 4, 2); break;
+      case 222: KIP_HOIST_ZB(2, 2, 2); break;
+      case 212: KIP_HOIST_ZB(2, 1, 2); break;
+      case 232: KIP_HOIST_ZB(2, 3, 2); break;
+      case 221: KIP_HOIST_ZB(2, 2, 1); break;
+      case 321: KIP_HOIST_ZB(3, 2, 1); break;
+      case 311: KIP_HOIST_ZB(3, 1, 1); break;
+      case 421: KIP_HOIST_ZB(4, 2, 1); break;
+      case 411: KIP_HOIST_ZB(4, 1, 1); break;
+      default: BM_THROW(BM_EINVAL, "launch check: hoisted kip variant");
     }
 #undef KIP_HOIST_ZB
     check_launch();
@@ -1981,6 +2045,23 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
   LAUNCH(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
                      in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
   check_launch();
+}
+
+void copy_ptrs(const Ctx& c, const u64* in, size_t si, size_t ics, u64* const* out, size_t ocs, int n,
+               int comps, int limbs) {
+  chk(in, n, si, 0, (size_t)(comps - 1) * ics + (size_t)limbs * c.N, "copy_ptrs input");
+  for (int z0 = 0; z0 < n; z0 += PTR_MAX) {
+    const int B = std::min(PTR_MAX, n - z0);
+    OutTab o{};
+    for (int z = 0; z < B; ++z) {
+      o.p[z] = out[z0 + z];
+      chk(o.p[z], 1, 0, 0, (size_t)(comps - 1) * ocs + (size_t)limbs * c.N, "copy_ptrs output");
+    }
+    Prof pf(c, "k_copy_ptrs", 16.0 * c.N * B * comps * limbs, 0.0);
+    LAUNCH(k_copy_ptrs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in + (size_t)z0 * si, si, ics, o,
+           ocs, limbs, (int)c.N);
+    check_launch();
+  }
 }
 
 void zero(const Ctx& c, u64* out, size_t words) {

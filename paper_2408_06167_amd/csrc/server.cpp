@@ -2,15 +2,17 @@
 //
 // Galleries and evaluation keys stay resident in HBM.  A worker thread owns
 // several lanes (each a context sharing the tables, with its own stream and
-// memory pool).  Whenever a lane is free it admits queued requests: all queued
-// queries against the same gallery (up to a batch limit) whose estimated
-// scratch and result memory fit the HBM budget next to the work already in
-// flight.  The admitted queries are expanded (Alg. 1) one by one and then
-// matched together in one batched Alg. 2 pass (query x group pairs share every
-// launch).  Lanes run concurrently on the device, so requests arriving while
-// others execute start as soon as a lane and memory free up.  Every result is
-// the same exact function of its query and gallery whether it ran alone or in
-// a batch.
+// memory pool).  Whenever a lane is free it admits queued requests: the
+// request at the head of the queue and every other queued request whose
+// gallery has the same shape (d, k, stored limbs) -- whatever gallery it
+// targets -- up to a batch limit, as long as the device memory the batch may
+// need fits the HBM budget next to the memory the lanes already hold.  The
+// admitted requests run as one batch: their queries are expanded together
+// (Alg. 1) and Alg. 2 runs over every (request, gallery group) element in
+// passes whose launches mix galleries.  Lanes run concurrently on the device,
+// so requests arriving while others execute start as soon as a lane and
+// memory free up.  Every result is the same exact function of its query and
+// gallery whether it ran alone or in a batch.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -35,7 +37,7 @@ struct bm_server {
   const bm_evk* evk = nullptr;
   uint64_t budget = 0;
   uint32_t schedule = BM_S2;
-  int max_batch = 8;
+  int max_batch = 32;
 
   struct Gal {
     std::unique_ptr<bm_gallery> g;
@@ -57,7 +59,6 @@ struct bm_server {
     std::vector<std::unique_ptr<bm_result>> results;
     uint64_t bytes = 0;
     hipEvent_t done = nullptr;
-    int status = BM_OK;
   };
   std::vector<Lane> lanes;
   std::deque<Req> queue;
@@ -77,74 +78,87 @@ struct bm_server {
   uint64_t batches = 0, batched = 0;
 
   bmx::Plan shape(const bm_gallery& g) const { return bmx::plan(ctx->c, schedule, g.k, (int)g.limbs, 0); }
+  static bool same_shape(const bm_gallery& a, const bm_gallery& b) {
+    return a.d == b.d && a.k == b.k && a.limbs == b.limbs;
+  }
 
-  uint64_t estimate(const bm_gallery& g, int nq) const {
+  // Device memory a batch of the requests `gids` (galleries of one shape) may
+  // allocate: the queries and their expansion, one pass of Alg. 2, the
+  // results (and, with compression, the group outputs before it).
+  uint64_t estimate(const std::vector<uint32_t>& gids) const {
     const Ctx& c = ctx->c;
-    const bmx::Plan p = shape(g);
-    const int t = p.t, ql = p.ql, ol = p.ol;
-    const u64 N = c.N;
-    const u64 l = (u64)t;
+    const bm_gallery& g0 = *galleries[gids[0]].g;
+    const bmx::Plan p = shape(g0);
+    const u64 N = c.N, nq = gids.size(), k = g0.k;
+    const u64 l = (u64)p.t, ql = (u64)p.ql;
     const u64 beta = (l + c.alpha - 1) / c.alpha, ext = l + c.K;
-    u64 chunk = c.group_chunk > 0 ? (u64)c.group_chunk : (u64)(c.N >= 65536 ? 16 : 64);
-    const u64 per_q = std::max<u64>(1, chunk / (u64)nq);
-    const u64 pairs = std::min<u64>(per_q, g.groups) * nq;
+    const u64 qbeta = (ql + c.alpha - 1) / c.alpha, qext = ql + c.K;
+    u64 elems = 0, outs = 0, pre = 0;
+    for (uint32_t gid : gids) {
+      const bm_gallery& g = *galleries[gid].g;
+      elems += g.groups;
+      outs += bmx::out_cts(p, g.groups, g.d, g.k) * 2 * (u64)p.ol * N;
+      if (p.comp) pre += g.groups * 2 * (u64)p.rot * N;
+    }
+    const u64 pass = std::min<u64>((u64)bmx::pass_elems(c), elems);
     const u64 pair_words = (3 + 2 + 2 + 2 + 1 + 2 + 2) * l * N + (beta + 2) * ext * N;
-    const u64 out_words = (u64)nq * bmx::out_cts(p, g.groups, g.d, g.k) * 2 * ol * N;
-    const u64 cu_words = (u64)nq * g.k * 2 * l * N + (g.k > 1 ? g.k * 4 * (u64)ql * N : 0);
-    // compression: the uncompressed outputs, the masked and rescaled copies and one rotation's scratch
-    const u64 comp_words = p.comp ? (u64)nq * g.groups * 2 * (2 * p.rot + p.rot - 1) * N +
-                                        pair_words
-                                  : 0;
-    return 8 * (pairs * pair_words + out_words + cu_words + comp_words);
+    const u64 q_words = nq * 2 * ql * N;
+    const u64 exp_words = k > 1 ? nq * k * (2 * l + 2 * ql + 2 * l) * N + nq * k * (qbeta + 2) * qext * N : 0;
+    return 8 * (pass * pair_words + outs + pre + q_words + exp_words);
+  }
+
+  uint64_t held() const {
+    uint64_t h = 0;
+    for (const Lane& lane : lanes) h += lane.c->pool->bytes_held();
+    return h;
   }
 
   void launch(Lane& lane) {
     Ctx& c = *lane.c;
-    const Gal& G = galleries[lane.reqs[0].gid];
-    const bm_gallery& g = *G.g;
     const int nq = (int)lane.reqs.size();
+    const Gal& G0 = galleries[lane.reqs[0].gid];
+    const bm_gallery& g0 = *G0.g;
     const size_t N = c.N;
-    const bmx::Plan p = shape(g);
-    const int t = p.t, ql = p.ql, ol = p.ol;
-    const size_t cu_stride = (size_t)g.k * 2 * t * N;
-    DBuf cu(&c, (size_t)nq * cu_stride);
-    DBuf cut(g.k > 1 ? DBuf(&c, (size_t)2 * ql * N) : DBuf());
-    double cu_scale = 0;
+    bmx::BatchPlan bp;
+    bp.cls.emplace_back();
+    bmx::BatchClass& K = bp.cls.back();
+    K.shape = &g0;
+    K.s = shape(g0);
+    K.masks = G0.masks;
+    K.cmask = G0.cmask;
+    std::vector<const bm_gallery*> gs(nq);
+    bp.out_off.resize(nq);
+    bp.scale.resize(nq);
     for (int j = 0; j < nq; ++j) {
-      const bm_ct& q = *lane.reqs[j].q;
-      if ((int)q.limbs < ql) BM_THROW(BM_ELEVEL, "query level does not fit the gallery");
-      if (g.k == 1) {                     // exact drop straight into the batch buffer
-        ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, t, cu.p() + j * cu_stride);
-        cu_scale = q.scale;
-      } else {
-        const u64* qq = q.buf.p();
-        if ((int)q.limbs > ql) {
-          ev::drop(c, q.buf.p(), 1, 2, (int)q.limbs, ql, cut.p());
-          qq = cut.p();
-        }
-        (p.hoist ? bmx::expand_hoisted : bmx::expand)(c, evk, qq, ql, G.masks->pt.p(), g.d, g.k,
-                                                      cu.p() + j * cu_stride);
-        cu_scale = q.scale * G.masks->scale / (double)c.primes[ql - 1].q;
-      }
-      if (cu_scale != g.scale) BM_THROW(BM_ESCALE, "query and gallery scales differ");
+      const Req& r = lane.reqs[j];
+      const bm_gallery& g = *galleries[r.gid].g;
+      gs[j] = &g;
+      K.queries.push_back(r.q.get());
+      K.pairs.push_back((size_t)j);
+      K.qidx.push_back(j);
+      const double cu_scale = g.k > 1 ? r.q->scale * K.masks->scale / (double)c.primes[K.s.ql - 1].q : r.q->scale;
+      bp.out_off[j] = bp.out_words;
+      bp.scale[j] = bmx::result_scale(c, K.s, cu_scale, g.scale);
+      bp.out_words += (size_t)bmx::out_cts(K.s, g.groups, g.d, g.k) * 2 * K.s.ol * N;
     }
-    const u64 n_out = bmx::out_cts(p, g.groups, g.d, g.k);
-    const size_t per = (size_t)n_out * 2 * ol * N;
-    auto store = std::make_shared<DBuf>(&c, (size_t)nq * per);
-    bmx::match_groups(c, evk, p, cu.p(), nq, cu_stride, g, G.cmask, store->p(), per);
+    DBuf qb(&c, (size_t)nq * 2 * K.s.ql * N);
+    bmx::load_queries(c, K, qb.p());
+    auto store = std::make_shared<DBuf>(&c, bp.out_words);
+    bmx::class_body(c, evk, bp, K, gs.data(), qb.p(), store->p());
     lane.results.clear();
     for (int j = 0; j < nq; ++j) {
+      const bm_gallery& g = *gs[j];
       std::unique_ptr<bm_result> r(new bm_result);
       r->ctx = ctx;
       r->d = g.d;
       r->k = g.k;
-      r->limbs = (uint32_t)ol;
-      r->groups = n_out;
-      r->packed = p.comp ? g.d / g.k : 0;
+      r->limbs = (uint32_t)K.s.ol;
+      r->groups = bmx::out_cts(K.s, g.groups, g.d, g.k);
+      r->packed = K.s.comp ? g.d / g.k : 0;
       r->n_templates = g.n_templates;
-      r->scale = bmx::result_scale(c, p, cu_scale, g.scale);
+      r->scale = bp.scale[j];
       r->store = store;
-      r->off = (size_t)j * per;
+      r->off = bp.out_off[j];
       lane.results.push_back(std::move(r));
     }
     HIP_OK(dev::event_record(lane.done, c.stream));
@@ -191,26 +205,31 @@ struct bm_server {
         if (lane.busy) continue;
         std::unique_lock<std::mutex> lk(mu);
         if (queue.empty()) break;
-        const uint32_t gid = queue.front().gid;
-        const bm_gallery& g = *galleries[gid].g;
+        const bm_gallery& head = *galleries[queue.front().gid].g;
         std::vector<size_t> pick;
+        std::vector<uint32_t> gids;
         for (size_t i = 0; i < queue.size() && (int)pick.size() < max_batch; ++i)
-          if (queue[i].gid == gid) pick.push_back(i);
-        // shrink the batch until it fits next to the work in flight
-        uint64_t need = estimate(g, (int)pick.size());
-        while (pick.size() > 1 && inflight + need > budget) {
-          pick.pop_back();
-          need = estimate(g, (int)pick.size());
-        }
-        if (inflight + need > budget) {
-          if (inflight == 0) {            // can never fit: reject
-            Req r = std::move(queue.front());
-            queue.pop_front();
-            fail_now(r, BM_EBUDGET);
-            progress = true;
+          if (same_shape(*galleries[queue[i].gid].g, head)) {
+            pick.push_back(i);
+            gids.push_back(queue[i].gid);
           }
-          break;
+        // shrink the batch until what it may allocate fits next to the work
+        // in flight and next to the memory the lanes hold (results still with
+        // their callers included), this lane's cache counted as reusable
+        uint64_t need = estimate(gids);
+        auto fits = [&] {
+          return inflight + need <= budget && held() - lane.c->pool->bytes_cached() + need <= budget;
+        };
+        while (pick.size() > 1 && !fits()) {
+          pick.pop_back();
+          gids.pop_back();
+          need = estimate(gids);
         }
+        // (a request that cannot fit an empty server was refused at submission;
+        // otherwise it waits for work in flight to finish and for results to
+        // be freed by their callers)
+        if (!fits()) break;
+        if (held() + need > budget) lane.c->pool->trim();   // give back this idle lane's cache
         lane.reqs.clear();
         for (size_t k = pick.size(); k-- > 0;) {
           lane.reqs.push_back(std::move(queue[pick[k]]));
@@ -233,7 +252,7 @@ struct bm_server {
       bool any_busy = false;
       for (Lane& lane : lanes) any_busy |= lane.busy;
       if (stop && queue.empty() && !any_busy) return;
-      if (!progress) cv.wait_for(lk, std::chrono::microseconds(any_busy ? 100 : 2000));
+      if (!progress) cv.wait_for(lk, std::chrono::microseconds(any_busy ? 50 : 2000));
     }
   }
 };
@@ -291,9 +310,13 @@ int bm_server_submit(bm_server* s, uint32_t gallery_id, bm_ct* q, uint64_t* tick
   std::unique_lock<std::mutex> lk(s->mu);
   if (gallery_id >= s->galleries.size()) return BM_EINVAL;
   const bm_gallery& g = *s->galleries[gallery_id].g;
-  if (s->estimate(g, 1) > s->budget) return BM_EBUDGET;
+  if (s->estimate({gallery_id}) > s->budget) return BM_EBUDGET;
   if (q->query_d && q->query_d != g.d) return BM_EDIM;
-  if ((int)q->limbs < s->shape(g).ql || q->comps != 2) return BM_ELEVEL;
+  const bmx::Plan p = s->shape(g);
+  if ((int)q->limbs < p.ql || q->comps != 2) return BM_ELEVEL;
+  const bm_masks* m = s->galleries[gallery_id].masks;
+  const double cu_scale = g.k > 1 ? q->scale * m->scale / (double)s->ctx->c.primes[p.ql - 1].q : q->scale;
+  if (cu_scale != g.scale) return BM_ESCALE;
   bm_server::Req r;
   r.ticket = s->next_ticket++;
   r.gid = gallery_id;

@@ -500,7 +500,56 @@ def noalloc_flow():
     print("no-allocation match ok", flush=True)
 
 
+def tuning_flow():
+    """Every kernel variant and row-pass tiling of the tuning knobs at every
+    digit count the hoisted sums meet, the batch autotuner, and a batch of
+    mixed shapes with graphs on and off."""
+    for preset, shapes in ((1, [(16, 1), (16, 4), (8, 8)]), (2, [(16, 1), (128, 4), (64, 2)])):
+        p = bm.bm_params_preset(preset)
+        ctx = bm.bm_ctx_create(p, 0)
+        rots = set()
+        for d, k in shapes:
+            rots.update(bm.bm_rotations_for(d, k))
+            rots.update(bm.bm_rotations_hoisted(d, k))
+        sk, pk, evk = bm.bm_keygen(ctx, 1, sorted(rots))
+        rng = np.random.default_rng(2)
+        qs, gs = [], []
+        for d, k in shapes:
+            for n in (300, 1300):
+                g = bm.bm_encrypt_gallery(ctx, pk, rng.standard_normal((n, d)).astype(np.float32), k, 1, n)
+                for j in range(2):
+                    qs.append(bm.bm_encrypt_query(ctx, pk, rng.standard_normal(d).astype(np.float32), 1, 10 * n + j))
+                    gs.append(g)
+        for var in range(5):
+            for views in (0, 4, 8, 16):
+                bm.bm_ctx_set_tuning(ctx, group_chunk=3, kip_variant=var, ntt_row_views=views)
+                # natural level (hoisted sums at 2 to 4 digits) and minimum level (1 digit)
+                for s in (0x402, 0x502, 0x401):
+                    for r in bm.bm_match_batch(ctx, evk, qs, gs, schedule=s):
+                        bm.bm_result_free(r)
+        for graphs in (0, 1):
+            bm.bm_ctx_set_graphs(ctx, graphs)
+            for r in bm.bm_match_batch(ctx, evk, qs, gs, schedule=0x102, out_limbs=1):
+                bm.bm_result_free(r)
+        bm.bm_ctx_set_graphs(ctx, False)
+        sched, tun, ms = bm.bm_autotune_batch(ctx, evk, qs, gs, [0x102, 0x502, 0x002], out_limbs=0)
+        assert sched in (0x102, 0x502, 0x002), sched
+        assert bm.bm_ctx_get_tuning(ctx) == tun
+        try:
+            bm.bm_autotune_batch(ctx, evk, qs, gs, [0x7777])
+            raise AssertionError("unknown schedule flags accepted")
+        except bm.BMError as e:
+            assert e.code == bm.BM_EINVAL
+        for q in qs:
+            bm.bm_ct_free(q)
+        for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+            f(h)
+        bm.bm_ctx_free(ctx)
+    print("tuning ok", flush=True)
+
+
 if __name__ == "__main__":
+    tuning_flow()
     noalloc_flow()
     result_outlives_server()
     key_import()
