@@ -71,7 +71,9 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one (no HIP graphs)")
     ap.add_argument("--no-ci", action="store_true", help="skip the conjugate-invariant ring figure")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the compressed and conjugate-invariant figures (profiling runs)")
+                    help="skip the compressed, conjugate-invariant and other-workload figures (profiling runs)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the fingerprint, batched and serving summaries")
     ap.add_argument("--workload", default="face", choices=["face", "fingerprint", "batch", "serve", "copy", "ntt"],
                     help="face: 6,144 x 128-dim (default); fingerprint: 1,048,576 x 16-dim; "
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
@@ -151,6 +153,9 @@ def main():
             print("# sweep %s: %.2f ms/match" % (key, sweep[key]), file=sys.stderr, flush=True)
     best = min(sweep, key=sweep.get)
     bk, bs = conf[best]
+    # the result-invariant knobs of the chosen configuration, by the autotuner
+    _, tuning, tuned_ms = bm.bm_autotune_batch(ctx, evk, [q_ct], [gals[bk]], [bs])
+    print("# autotuned knobs %s: %.3f ms/match" % (tuning, tuned_ms), file=sys.stderr, flush=True)
     canon = {key: v for key, v in sweep.items() if not conf[key][1] & (bm.BM_LEVEL_MIN | bm.BM_HOIST)}
     canon_best = min(canon, key=canon.get) if canon else None
 
@@ -272,31 +277,16 @@ def main():
     # headline entry, and the whole match against its compulsory traffic
     roof = None
     if prof:
-        kernels = []
-        for n, e in sorted(prof.items(), key=lambda x: -x[1]["ms"]):
-            avg_s = e["ms"] / e["launches"] / 1e3
-            bpl = e["bytes"] / e["launches"]
-            kernels.append(dict(kernel=n, launches_per_step=round(e["launches"] / args.steps, 2),
-                                avg_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=int(bpl),
-                                achieved_gbs=round(bpl / avg_s / 1e9, 1),
-                                frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
-                                ms_per_step=round(e["ms"] / args.steps, 4)))
-        top = kernels[0]
+        roof = roofline_entries(prof, args.steps)
+        top = roof["kernels"][0]
         e = prof[top["kernel"]]
-        avg_s = e["ms"] / e["launches"] / 1e3
-        gmm = e["ops"] / e["launches"] / avg_s / 1e9
-        roof = dict(bound="hbm", kernel=top["kernel"], achieved=top["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=top["frac"], avg_us=top["avg_us"], launches_per_step=top["launches_per_step"],
-                    algorithmic_bytes_per_launch=top["algorithmic_bytes_per_launch"],
-                    alu_gmodmul=round(gmm, 2), alu_frac=round(gmm / ALU_PEAK_GMODMUL, 4), traffic=None)
         roof["traffic"] = traffic_for(top["kernel"], "k%d_%s" % (bk, sname(bs)), top["algorithmic_bytes_per_launch"])
         # the same kind of arithmetic at its measured register-resident rate
         mrate = measured_butterfly_rate(bm, ctx, params)
         roof["alu_measured_peak_gmodmul"] = round(mrate, 1)
-        roof["alu_frac_measured"] = round(gmm / mrate, 4)
+        roof["alu_frac_measured"] = round(roof["alu_gmodmul"] / mrate, 4)
         step_ms_dev = sum(v["ms"] for v in prof.values()) / args.steps
         roof["kernel_share"] = round(e["ms"] / args.steps / max(step_ms_dev, 1e-9), 3)
-        roof["kernels"] = kernels
         mb = match_compulsory_bytes(params, d, bk, bm.bm_gallery_info(gals[bk])[0], bs, params.out_limbs, bm)
         roof["match"] = dict(compulsory_bytes=int(mb["total"]), parts=mb["parts"], ms_per_step=round(ms_step, 4),
                              achieved_gbs=round(mb["total"] / (ms_step * 1e-3) / 1e9, 1),
@@ -323,6 +313,22 @@ def main():
             print("# cpu oracle (one thread): %s templates/s" % (cpu1 or {}).get("value"),
                   file=sys.stderr, flush=True)
 
+    # ---- the other workloads: fingerprint scale (C3), the mixed batch (C4)
+    # and serving (C5), each a summary in config (their own lines with
+    # --workload fingerprint | batch | serve)
+    others = {}
+    if not args.no_extras and not args.no_workloads:
+        import bench_workloads
+        for key, fn in (("fingerprint", bench_workloads.fingerprint), ("batched", bench_workloads.batch),
+                        ("serving", bench_workloads.serve)):
+            t_w = time.time()
+            try:
+                others[key] = fn(bm, args)
+            except Exception as ex:         # reported, never fatal to the headline line
+                others[key] = {"error": repr(ex)[:400]}
+            print("# workload %s: %.1fs" % (key, time.time() - t_w), file=sys.stderr, flush=True)
+        torch.cuda.set_stream(stream)
+
     out = {
         "metric": "encrypted templates scored/s (N=2^16, 128-dim); p50/p99 query latency",
         "value": round(value, 1),
@@ -339,7 +345,7 @@ def main():
         "config": {
             "workload": "face-scale 1:N match: N=2^16, 8x50-bit chain + 2x51-bit special primes, "
                         "dnum=4, 6144 x 128-dim templates in 24 ciphertexts, one query",
-            "k": bk, "schedule": sname(bs), "templates": n_tmpl, "compressed": compressed,
+            "k": bk, "schedule": sname(bs), "tuning": tuning, "templates": n_tmpl, "compressed": compressed,
             "natural_level_best": ({"config": canon_best, "ms_per_match": round(canon[canon_best], 3),
                                     "templates_per_s": round(n_tmpl / canon[canon_best] * 1e3, 1)}
                                    if canon_best else None),
@@ -358,6 +364,9 @@ def main():
             "conjugate_invariant_ring": ci,
             "host_buffers_pcie_inclusive": pcie,
             "cpu_oracle_single_thread": cpu1,
+            "fingerprint": others.get("fingerprint"),
+            "batched": others.get("batched"),
+            "serving": others.get("serving"),
             "paper_context": "Lattigo CPU, N=8192 real slots, 3 clusters x 2 Xeon Gold 5220 cores: "
                              "6144 x 128-dim matched in 451.67 ms (13,603 templates/s)",
         },
@@ -365,6 +374,31 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def roofline_entries(prof, steps):
+    """The roofline of a profiled run: every kernel on its own (its algorithmic
+    bytes per launch over its average duration, HIP events stamped with each
+    launch's execution interval), the kernel with the most device time as the
+    headline entry."""
+    kernels = []
+    for n, e in sorted(prof.items(), key=lambda x: -x[1]["ms"]):
+        avg_s = e["ms"] / e["launches"] / 1e3
+        bpl = e["bytes"] / e["launches"]
+        kernels.append(dict(kernel=n, launches_per_step=round(e["launches"] / steps, 2),
+                            avg_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=int(bpl),
+                            achieved_gbs=round(bpl / avg_s / 1e9, 1),
+                            frac=round(bpl / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                            ms_per_step=round(e["ms"] / steps, 4)))
+    top = kernels[0]
+    e = prof[top["kernel"]]
+    avg_s = e["ms"] / e["launches"] / 1e3
+    gmm = e["ops"] / e["launches"] / avg_s / 1e9
+    return dict(bound="hbm", kernel=top["kernel"], achieved=top["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=top["frac"], avg_us=top["avg_us"], launches_per_step=top["launches_per_step"],
+                algorithmic_bytes_per_launch=top["algorithmic_bytes_per_launch"],
+                alu_gmodmul=round(gmm, 2), alu_frac=round(gmm / ALU_PEAK_GMODMUL, 4), traffic=None,
+                kernels=kernels)
 
 
 def match_compulsory_bytes(p, d, k, G, schedule, ctx_out_limbs, bm):
@@ -475,7 +509,7 @@ def ci_variant(bm, torch, X, q, d, ks, scheds, known, sptr, graphs, sname, reps=
     return out
 
 
-def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
+def cpu_baseline(k, schedule, X, q, d, budget_s=10.0, max_groups=None):
     """The oracle as it stands on the same workload and schedule, group after
     group until about `budget_s` of CPU time is spent (expansion counted once,
     as in one query), scaled to templates/s."""
@@ -511,7 +545,7 @@ def cpu_baseline(k, schedule, X, q, d, budget_s=10.0):
         ckks.drop_limbs(out, 2)
         dt += time.perf_counter() - t1
         done += min(T, X.shape[0] - g * T)
-        if dt >= budget_s:
+        if dt >= budget_s or (max_groups and g + 1 >= max_groups):
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=round(done / dt, 1), unit="templates/s", cores=cores, kind="oracle",

@@ -41,52 +41,85 @@ def run(args):
 
 
 def fingerprint(bm, args):
+    """1,048,576 x 16-dim templates (1,000 identities), k = 1, 512 ciphertexts:
+    the batch autotuner picks the schedule (natural or minimum level, plain
+    or hoisted rotate-and-sum) and the knobs, the match is timed with HIP
+    events, an eager profiled pass gives the per-kernel roofline, and the
+    oracle runs on 16 of the 512 ciphertexts (extrapolated x32)."""
+    import bench
     from workloads import fingerprint_gallery
+    import torch
     d, k, seed = 16, 1, 0xB11D
     w = fingerprint_gallery(seed=3, d=d, n=1 << 20)
     X, q = w["gallery"], w["query"]
-    torch, stream, ctx, sk, pk, evk = _setup(bm, [(d, k)])
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    params = bm.bm_params_preset(2)
+    ctx = bm.bm_ctx_create(params, 0)
+    rots = sorted(set(bm.bm_rotations_for(d, k)) | set(bm.bm_rotations_hoisted(d, k)))
+    sk, pk, evk = bm.bm_keygen(ctx, seed, rots)
     t0 = time.time()
     gal = bm.bm_encrypt_gallery(ctx, pk, X, k, seed, 1 << 20)
     cq = bm.bm_encrypt_query(ctx, pk, q, seed, 1)
     G, _, _ = bm.bm_gallery_info(gal)
     print("# gallery of %d ciphertexts encrypted in %.1fs" % (G, time.time() - t0), file=sys.stderr, flush=True)
     bm.bm_ctx_set_graphs(ctx, True)
-    out = {}
-    for name, sched in (("S1", 1), ("S1+levelmin", 1 | bm.BM_LEVEL_MIN)):
-        chunk, ms_tuned = bm.bm_autotune(ctx, evk, cq, gal, sched)
+    sched, tuning, _ = bm.bm_autotune_batch(ctx, evk, [cq], [gal], [0x101, 0x501, 0x001])
+    print("# autotuner: schedule %#x, knobs %s" % (sched, tuning), file=sys.stderr, flush=True)
+    steps = max(5, args.steps // 2)
+    bm.bm_result_free(bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream))
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    rs = []
+    t = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        rs.append(bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream))
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    lat = [a.elapsed_time(b) for a, b in ev]
+    scores = bm.bm_decrypt_scores(ctx, sk, rs[-1], X.shape[0])
+    for r in rs:
+        bm.bm_result_free(r)
+    cos = X.astype(np.float64) @ q.astype(np.float64)
+    err = float(np.max(np.abs(scores - cos)))
+    # per-kernel roofline from an eager profiled pass
+    bm.bm_profile_enable(ctx, True)
+    for _ in range(3):
         bm.bm_result_free(bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream))
-        torch.cuda.synchronize()
-        lat = []
-        for _ in range(max(3, args.steps // 4)):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            r = bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            lat.append(e0.elapsed_time(e1))
-            last = r if len(lat) == 1 else (bm.bm_result_free(r) or last)
-        scores = bm.bm_decrypt_scores(ctx, sk, last, X.shape[0])
-        bm.bm_result_free(last)
-        cos = X.astype(np.float64) @ q.astype(np.float64)
-        err = float(np.max(np.abs(scores - cos)))
-        ms = float(np.median(lat))
-        out[name] = dict(ms_per_query=round(ms, 3), templates_per_s=round(X.shape[0] / ms * 1e3, 1),
-                         group_chunk=chunk, max_abs_err=err,
-                         top1_identity_ok=bool(int(bm.bm_top1(scores)[0]) % w["identities"] == w["query_identity"]))
-        print("# %s: %.2f ms/query (chunk %d), err %.1e" % (name, ms, chunk, err), file=sys.stderr, flush=True)
-    best = min(out, key=lambda n: out[n]["ms_per_query"])
-    cpu = None
-    if not args.no_cpu:            # the oracle on a bounded sample of the same gallery and schedule
-        import bench
-        cpu = bench.cpu_baseline(k, 1 | (bm.BM_LEVEL_MIN if "levelmin" in best else 0), X, q, d, budget_s=10.0)
+    torch.cuda.synchronize()
+    prof = bm.bm_profile_dump(ctx)
+    bm.bm_profile_enable(ctx, False)
+    roof = bench.roofline_entries(prof, 3)
+    mb = bench.match_compulsory_bytes(params, d, k, G, sched, params.out_limbs, bm)
+    roof["match"] = dict(compulsory_bytes=int(mb["total"]), parts=mb["parts"], ms_per_query=round(ms, 3),
+                         achieved_gbs=round(mb["total"] / (ms * 1e-3) / 1e9, 1),
+                         frac=round(mb["total"] / (ms * 1e-3) / 1e9 / bench.HBM_PEAK_GBS, 4))
+    out = dict(ms_per_query=round(ms, 3), templates_per_s=round(X.shape[0] / ms * 1e3, 1),
+               step_p50_ms=round(float(np.percentile(lat, 50)), 3), schedule="%#x" % sched, tuning=tuning,
+               max_abs_err_vs_fp64_cosine=err,
+               top1_identity_correct=bool(int(bm.bm_top1(scores)[0]) % w["identities"] == w["query_identity"]),
+               roofline=roof)
+    print("# fingerprint: %.2f ms/query (%s), err %.1e" % (ms, out["schedule"], err), file=sys.stderr, flush=True)
+    if not args.no_cpu:            # the oracle on 16 of the 512 ciphertexts, extrapolated x32
+        cpu = bench.cpu_baseline(k, sched, X, q, d, budget_s=1e9, max_groups=16)
+        cpu["extrapolated"] = "x32 (16 of 512 ciphertexts; the query's work is counted once)"
+        out["cpu_baseline"] = cpu
         print("# cpu oracle: %s templates/s (%s)" % (cpu["value"], cpu["sample"]), file=sys.stderr, flush=True)
-    print(json.dumps({"metric": "encrypted templates scored/s (N=2^16, 16-dim, 1,048,576 templates)",
-                      "value": out[best]["templates_per_s"], "unit": "templates/s", "n_gpus": 1,
-                      "higher_is_better": True, "data": "synthetic", "dtype": "u64",
-                      "config": {"workload": "fingerprint-scale: 1,048,576 x 16-dim, k=1, %d ciphertexts" % G,
-                                 "schedule": best, "variants": out},
-                      "cpu_baseline": cpu}), flush=True)
+    bm.bm_ct_free(cq)
+    bm.bm_gallery_free(gal)
+    for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):
+        f(h)
+    bm.bm_ctx_free(ctx)
+    if args.workload == "fingerprint":
+        print(json.dumps({"metric": "encrypted templates scored/s (N=2^16, 16-dim, 1,048,576 templates)",
+                          "value": out["templates_per_s"], "unit": "templates/s", "n_gpus": 1,
+                          "higher_is_better": True, "data": "synthetic", "dtype": "u64",
+                          "config": {"workload": "fingerprint-scale: 1,048,576 x 16-dim, k=1, %d ciphertexts" % G,
+                                     **{kk: vv for kk, vv in out.items() if kk != "cpu_baseline"}},
+                          "cpu_baseline": out.get("cpu_baseline")}), flush=True)
+    return out
 
 
 def batch(bm, args):
@@ -156,7 +189,7 @@ def batch(bm, args):
 
     reps = max(2, min(args.steps, 5))
     res, keep = {}, {}
-    default = dict(group_chunk=0, kip_variant=0, ntt_row_views=0)
+    default = dict(group_chunk=0, kip_variant=0, ntt_row_views=0, kip_order=0, fused_occupancy=0)
     for name, fn, knobs in (("plain_per_pair_default_knobs", plain, default), ("plain_per_pair", plain, tuning),
                             ("batched", batched, tuning)):
         bm.bm_ctx_set_tuning(ctx, **knobs)
@@ -188,7 +221,8 @@ def batch(bm, args):
                       "speedup_batched_over_plain_default_knobs": round(
                           res["plain_per_pair_default_knobs"]["seconds"] / res["batched"]["seconds"], 3),
                       "batched_equals_plain": same}}
-    print(json.dumps(out), flush=True)
+    if args.workload == "batch":
+        print(json.dumps(out), flush=True)
     for q in qs:
         bm.bm_ct_free(q)
     for g in gals:
@@ -223,20 +257,29 @@ def serve(bm, args):
     sched = 2 | bm.BM_LEVEL_MIN | bm.BM_HOIST
     budget = 64 << 30
     t0 = time.time()
-    srv = bm.bm_server_create(ctx, evk, budget, sched)
     by_d = {16: [], 128: []}
-    sizes, plain_gals = {}, {}
+    sizes, plain_gals, served_gals = {}, {}, {}
     for i, g in enumerate(gl):
-        h = bm.bm_encrypt_gallery(ctx, pk, g["X"], kfor[g["d"]], 0xB11D, 1000000 * (i + 1))
-        # the plain path needs galleries of its own: the server owns the ones added to it
+        # the plain path has galleries of its own: the server owns the ones added to it
         plain_gals[i] = bm.bm_encrypt_gallery(ctx, pk, g["X"], kfor[g["d"]], 0xB11D, 1000000 * (i + 1))
-        gid = bm.bm_server_add_gallery(srv, h)
+        served_gals[i] = bm.bm_encrypt_gallery(ctx, pk, g["X"], kfor[g["d"]], 0xB11D, 1000000 * (i + 1))
+    bm.bm_ctx_set_graphs(ctx, True)
+    rng = np.random.default_rng(55)
+    # knobs tuned once on a sample of the traffic (eight 128-dim requests over
+    # the 128-dim galleries); both paths run with them
+    sample = [i for i, g in enumerate(gl) if g["d"] == 128][:8]
+    tq = [bm.bm_encrypt_query(ctx, pk, normalize(rng.standard_normal(128)), 0xB11D, 900 + i) for i in sample]
+    _, tuning, _ = bm.bm_autotune_batch(ctx, evk, tq, [plain_gals[i] for i in sample], [sched])
+    for h in tq:
+        bm.bm_ct_free(h)
+    srv = bm.bm_server_create(ctx, evk, budget, sched)       # its lanes take the tuned knobs
+    for i, g in enumerate(gl):
+        gid = bm.bm_server_add_gallery(srv, served_gals[i])
         by_d[g["d"]].append((gid, i))
         sizes[gid] = g["X"].shape[0]
     total = sum(sizes.values())
-    print("# %d galleries, %d templates, setup %.1fs" % (len(gl), total, time.time() - t0), file=sys.stderr, flush=True)
-    bm.bm_ctx_set_graphs(ctx, True)
-    rng = np.random.default_rng(55)
+    print("# %d galleries, %d templates, knobs %s, setup %.1fs" % (len(gl), total, tuning, time.time() - t0),
+          file=sys.stderr, flush=True)
 
     def trace(rate):
         t_arr, dims, picks = poisson_arrivals(int(rate * 1000), rate, args.requests)
@@ -344,11 +387,13 @@ def serve(bm, args):
            "config": {"workload": "16 resident galleries (12 x 128-dim at k=4, 4 x 16-dim at k=1), sizes x%.3g, "
                                   "Poisson arrivals, 3:1 mix, %d requests per rate" % (args.scale, args.requests),
                       "templates": total, "schedule": "S2+levelmin+hoist", "hbm_budget_bytes": budget,
+                      "tuning": tuning,
                       "served_by_rate": out, "plain_by_rate": plain,
                       "served_over_plain_templates_per_s": round(out[best]["templates_per_s"]
                                                                  / plain[best_plain]["templates_per_s"], 3),
                       "served_equals_plain_and_within_1e-4": same}}
-    print(json.dumps(res), flush=True)
+    if args.workload == "serve":
+        print(json.dumps(res), flush=True)
     for h in plain_gals.values():
         bm.bm_gallery_free(h)
     for f, h in ((bm.bm_sk_free, sk), (bm.bm_pk_free, pk), (bm.bm_evk_free, evk)):

@@ -419,12 +419,20 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * thread and four amounts' key words requested ahead at one digit; the others
  * trade elements per thread, which share each key word from registers,
  * against amounts in flight).  ntt_row_views: polynomials x rows per block of
- * the row passes of the N = 2^16 transforms, 0 (= 16), 4, 8 or 16.  Matches
- * captured as graphs keep the knobs they were captured with. */
+ * the row passes of the N = 2^16 transforms, 0 (= 16), 4, 8 or 16.
+ * kip_order: block order of that key inner product, 0 (the element groups of
+ * a position block side by side: they share its key words through the
+ * memory-side cache) or 1 (the position blocks of an element group side by
+ * side: its gathered digit words stay in cache).  fused_occupancy: 0, or 4 to
+ * build the fused base-conversion column passes of the N = 2^16 transforms
+ * for four resident blocks per compute unit.  Matches captured as graphs
+ * keep the knobs they were captured with. */
 typedef struct {
   uint32_t group_chunk;
   uint32_t kip_variant;
   uint32_t ntt_row_views;
+  uint32_t kip_order;
+  uint32_t fused_occupancy;
 } bm_tuning;
 int bm_ctx_set_tuning(bm_ctx *ctx, const bm_tuning *t);
 int bm_ctx_get_tuning(const bm_ctx *ctx, bm_tuning *t);

@@ -1119,7 +1119,8 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   const std::vector<uint64_t> key = {(uint64_t)evk, (uint64_t)evk->rlk.k.p(), (uint64_t)g->buf.p(),
                                      g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
                                      (uint64_t)cmask, schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
-                                     (uint64_t)c.group_chunk, (uint64_t)c.kip_variant, (uint64_t)c.ntt_views};
+                                     (uint64_t)c.group_chunk, (uint64_t)c.kip_variant, (uint64_t)c.ntt_views,
+                                     (uint64_t)c.kip_order, (uint64_t)c.fused_occ};
   const u64 n_out = bmx::out_cts(s, g->groups, g->d, g->k);
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
@@ -1344,7 +1345,7 @@ static void batch_graph(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const bm
                         const bm_gallery* const* gs, size_t n, uint32_t schedule, uint32_t out_limbs, u64* out) {
   std::vector<uint64_t> key = {0xBA7C4ULL, (uint64_t)evk, (uint64_t)evk->rlk.k.p(), schedule, out_limbs,
                                (uint64_t)c.stream, (uint64_t)c.group_chunk, (uint64_t)c.kip_variant,
-                               (uint64_t)c.ntt_views, n};
+                               (uint64_t)c.ntt_views, (uint64_t)c.kip_order, (uint64_t)c.fused_occ, n};
   for (const BatchClass& K : bp.cls) {
     key.push_back((uint64_t)(K.masks ? K.masks->pt.p() : nullptr));
     key.push_back((uint64_t)K.cmask);
@@ -1453,10 +1454,14 @@ int bm_ctx_set_tuning(bm_ctx* ctx, const bm_tuning* t) {
     REQUIRE(t->kip_variant <= 4, BM_EINVAL, "kip_variant in 0..4");
     REQUIRE(t->ntt_row_views == 0 || t->ntt_row_views == 4 || t->ntt_row_views == 8 || t->ntt_row_views == 16,
             BM_EINVAL, "ntt_row_views: 0, 4, 8 or 16");
+    REQUIRE(t->kip_order <= 1, BM_EINVAL, "kip_order: 0 or 1");
+    REQUIRE(t->fused_occupancy == 0 || t->fused_occupancy == 4, BM_EINVAL, "fused_occupancy: 0 or 4");
     Ctx& c = ctx->c;
     c.group_chunk = (int)t->group_chunk;
     c.kip_variant = (int)t->kip_variant;
     c.ntt_views = (int)t->ntt_row_views;
+    c.kip_order = (int)t->kip_order;
+    c.fused_occ = (int)t->fused_occupancy;
   });
 }
 
@@ -1465,6 +1470,8 @@ int bm_ctx_get_tuning(const bm_ctx* ctx, bm_tuning* t) {
   t->group_chunk = (uint32_t)ctx->c.group_chunk;
   t->kip_variant = (uint32_t)ctx->c.kip_variant;
   t->ntt_row_views = (uint32_t)ctx->c.ntt_views;
+  t->kip_order = (uint32_t)ctx->c.kip_order;
+  t->fused_occupancy = (uint32_t)ctx->c.fused_occ;
   return BM_OK;
 }
 
@@ -1481,7 +1488,8 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
     REQUIRE(schedules && n_schedules > 0, BM_EINVAL, "no schedule to tune");
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
-    const int s_chunk = c.group_chunk, s_var = c.kip_variant, s_views = c.ntt_views;
+    const int s_chunk = c.group_chunk, s_var = c.kip_variant, s_views = c.ntt_views, s_order = c.kip_order,
+              s_occ = c.fused_occ;
     hipEvent_t ea, eb;
     HIP_OK(dev::event_create(&ea, true));
     HIP_OK(dev::event_create(&eb, true));
@@ -1500,17 +1508,26 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       HIP_OK(dev::stream_sync(c.stream));
       c.graphs.clear();
     };
+    // a setting's time: the best of three timed runs, each of enough batches
+    // to last about 5 ms (short batches are timed over many)
+    int reps = 0;
     auto timed = [&](uint32_t sched) {
       drop();
       match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);   // warm-up, capture
       res.clear();
-      HIP_OK(dev::event_record(ea, c.stream));
-      for (int rep = 0; rep < 2; ++rep) match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);
-      HIP_OK(dev::event_record(eb, c.stream));
-      HIP_OK(dev::event_sync(eb));
-      float ms = 0;
-      HIP_OK(dev::event_elapsed(&ms, ea, eb));
-      return (double)ms / 2;
+      double best_run = 1e30;
+      for (int run = 0; run < 3; ++run) {
+        const int n = reps > 0 ? reps : 1;
+        HIP_OK(dev::event_record(ea, c.stream));
+        for (int rep = 0; rep < n; ++rep) match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);
+        HIP_OK(dev::event_record(eb, c.stream));
+        HIP_OK(dev::event_sync(eb));
+        float ms = 0;
+        HIP_OK(dev::event_elapsed(&ms, ea, eb));
+        best_run = std::min(best_run, (double)ms / n);
+        if (reps == 0) reps = (int)std::min(200.0, std::max(1.0, std::ceil(5.0 / std::max(ms, 1e-3f))));
+      }
+      return best_run;
     };
     double bms = 1e30;
     uint32_t bsched = 0;
@@ -1531,9 +1548,9 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       REQUIRE(bsched != 0, BM_ENOKEY, "no offered schedule can run on these inputs");
       (void)timed(bsched);
       const std::vector<u64> ref = words();
-      int* knob[3] = {&c.group_chunk, &c.kip_variant, &c.ntt_views};
-      const std::vector<int> values[3] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {16, 8, 4}};
-      for (int kn = 0; kn < 3; ++kn) {
+      int* knob[5] = {&c.group_chunk, &c.kip_variant, &c.kip_order, &c.ntt_views, &c.fused_occ};
+      const std::vector<int> values[5] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 4}};
+      for (int kn = 0; kn < 5; ++kn) {
         int pick = *knob[kn];
         for (int v : values[kn]) {
           *knob[kn] = v;
@@ -1554,6 +1571,8 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       c.group_chunk = s_chunk;
       c.kip_variant = s_var;
       c.ntt_views = s_views;
+      c.kip_order = s_order;
+      c.fused_occ = s_occ;
       (void)dev::event_destroy(ea);
       (void)dev::event_destroy(eb);
       throw;
@@ -1567,6 +1586,8 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       best->group_chunk = (uint32_t)c.group_chunk;
       best->kip_variant = (uint32_t)c.kip_variant;
       best->ntt_row_views = (uint32_t)c.ntt_views;
+      best->kip_order = (uint32_t)c.kip_order;
+      best->fused_occupancy = (uint32_t)c.fused_occ;
     }
     if (best_ms) *best_ms = bms;
   });

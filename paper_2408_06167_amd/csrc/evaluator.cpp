@@ -255,6 +255,8 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->group_chunk = group_chunk;
   l->kip_variant = kip_variant;
   l->ntt_views = ntt_views;
+  l->kip_order = kip_order;
+  l->fused_occ = fused_occ;
   l->owns_tables = false;
   l->prof = prof;
   HIP_OK(dev::set_device(device));

@@ -261,8 +261,15 @@ enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 // FUSE = 2: forward row pass that stores through f's epilogue;
 // FUSE = 3: forward row pass that stores the residues as FP64 values;
 // FUSE = 4: as 1, in the conjugate-invariant ring (sources not yet unfolded).
-template <int LOGM, bool INV, int KIND, int FUSE = 0>
-__global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
+// PK / EK fix the prologue kind (f.pro) of a fused column pass and the
+// epilogue kind (f.epi) of a fused row pass at compile time, so that each
+// instantiation holds only the registers of its own prologue or epilogue
+// (0: taken from f at run time).
+// OCC > 0 asks the compiler for OCC resident blocks of 256 threads per CU
+// (a register budget of 512 / OCC per lane, spilling if it must): a tuning
+// alternative for the register-heavy fused column passes.
+template <int LOGM, bool INV, int KIND, int FUSE = 0, int PK = 0, int EK = 0, int OCC = 0>
+__global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
                                                   LimbMap m, const PrimeC* __restrict__ P,
                                                   const double* __restrict__ twf,
@@ -271,6 +278,8 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   static_assert(FUSE == 0 || (!INV && (((FUSE == 1 || FUSE == 4) && KIND == NTT_COL) ||
                                        ((FUSE == 2 || FUSE == 3) && KIND == NTT_ROW))),
                 "fused prologues serve forward column passes, epilogues forward row passes");
+  const int pro = PK ? PK : f.pro;           // compile-time constant in the fused instantiations
+  const int epi = EK ? EK : f.epi;
   constexpr bool PRO = FUSE == 1 || FUSE == 4;
   constexpr int M = 1 << LOGM;
   constexpr int TPV = M / 16;                 // threads per view
@@ -366,7 +375,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
   (void)r0;
   // source a of slot blockIdx.y: limb offset, prime, and the two constants
   auto src_info = [&](int a, int& soff, int& spid, u64& c1, u64& c2) {
-    if (f.pro == 1) {
+    if (pro == 1) {
       const ModUpDigit& dg = f.mu->d[jd];
       soff = spid = dg.src[a];
       c1 = dg.qhatinv[a][0];
@@ -382,16 +391,16 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
     const size_t zz = blockIdx.z;
     S = f.src + (zz / f.s_div) * f.s_hi + (zz % f.s_div) * f.s_lo +
         (FUSE == 4 ? (size_t)ci_col(v) : (size_t)blockIdx.x * 16 + v);
-    if (f.pro == 3) {
+    if (pro == 3) {
       ns = 1;
     } else {
-      jd = f.pro == 1 ? f.mu->pair_j[blockIdx.y] : 0;
-      tt = f.pro == 1 ? f.mu->pair_t[blockIdx.y] : 0;
-      ns = f.pro == 1 ? f.mu->d[jd].nsrc : f.md->K;
+      jd = pro == 1 ? f.mu->pair_j[blockIdx.y] : 0;
+      tt = pro == 1 ? f.mu->pair_t[blockIdx.y] : 0;
+      ns = pro == 1 ? f.mu->d[jd].nsrc : f.md->K;
     }
     int soff = 0, spid;
     u64 c1, c2;
-    if (f.pro != 3) src_info(0, soff, spid, c1, c2);
+    if (pro != 3) src_info(0, soff, spid, c1, c2);
     if constexpr (FUSE == 1) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
@@ -479,7 +488,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
           cc[j] = r < 0.0 ? __dadd_rn(r, ms) : r;
         }
       };
-      if (f.pro == 4) {
+      if (pro == 4) {
         // relinearisation and rescale in one (as in the standard ring, below)
         const ModDownTable& md = *f.md;
         const int li = f.last_pid, ti = m.prime[blockIdx.y];
@@ -520,7 +529,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         for (int a = 0; a < ns; ++a) {
           int soff = 0, spid = f.src_pid;
           u64 c1 = 1, c2 = 1;
-          if (f.pro != 3) src_info(a, soff, spid, c1, c2);
+          if (pro != 3) src_info(a, soff, spid, c1, c2);
           const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
           const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
           double cc[16];
@@ -528,7 +537,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             double p2;
-            if (f.pro == 3) {
+            if (pro == 3) {
               p2 = fred(cc[j], qi, q);
             } else {
               double t1 = fred(fmul_mod(cc[j], c1d, c1q, ms), msi, ms);
@@ -552,10 +561,10 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
         const bool zero = colv == 0 && addr(0, j) == 0;
         if (!zero) x[j] = fred(__dsub_rn(x[j], fmul_mod(xm[j], it, itq, q)), qi, q);
       }
-    } else if (f.pro == 3) {
+    } else if (pro == 3) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) x[j] = fred(u64_to_f(r0[j]), qi, q);
-    } else if (f.pro == 4) {
+    } else if (pro == 4) {
       // relinearisation and rescale in one (see relin_rescale): the special
       // limbs of u and its last chain limb y = u + P d (coefficient domain)
       // give last = (y - conv_last(u_P)) P^-1 mod q_last (exact residue), and
@@ -706,7 +715,7 @@ __global__ void __launch_bounds__(256) k_ntt_fast(const u64* __restrict__ in, si
       if constexpr (FUSE == 2) {
         // out = (minuend - x) w (+ addend), all words exact residues
         const double wd = (double)f.wtab[2 * blockIdx.y], wq = wd / q;
-        if (f.epi == 2) {
+        if (epi == 2) {
           // out = (minuend wm + addend - x) w
           const double wm = (double)f.wmtab[2 * blockIdx.y], wmq = wm / q;
 #pragma unroll
@@ -1152,7 +1161,8 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 template <int BETA, int ZB, int CH>
 __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                                HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
-                               const PrimeC* P, int log_n, int ms, int B, int accumulate, AutomArgs am) {
+                               const PrimeC* P, int log_n, int ms, int B, int accumulate, AutomArgs am,
+                               int order) {
   if ((int)blockIdx.x < am.W) {
     autom_sum_part(am, h, P, log_n, ms, accumulate, (int)blockIdx.x);
     return;
@@ -1163,9 +1173,13 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   // 1-D grid of (limb, position block, element group), element group fastest
   const int gx = N / (2 * TPB);
   const int ZG = (B + ZB - 1) / ZB;
+  // order 0: element groups fastest (the groups of one position block share
+  // its key words through L2); order 1: position blocks fastest (an XCD
+  // works through one element group's positions while its gathered digit
+  // words stay in L2, the key words streaming past)
   const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
-  const int zg = lb % ZG;
-  const int pb = (lb / ZG) % gx;
+  const int zg = order ? (lb / gx) % ZG : lb % ZG;
+  const int pb = order ? lb % gx : (lb / ZG) % gx;
   const int t = lb / (ZG * gx);
   const int i = 2 * (pb * TPB + (int)threadIdx.x);   // positions i, i + 1
   __shared__ const u64* kp[HOIST_MAX];
@@ -1620,20 +1634,45 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
     } else {
       src_words = (double)N * B;
     }
-    Prof pf(c, f.ci ? "k_ntt_fast<8, false, 0, 4>" : "k_ntt_fast<8, false, 0, 1>", 8.0 * (elems + src_words),
-            0.5 * elems * 8 + 2.0 * srcs * elems);
-    if (f.ci)
-      LAUNCH((k_ntt_fast<8, false, NTT_COL, 4>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
-             (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
-    else
-      LAUNCH((k_ntt_fast<8, false, NTT_COL, 1>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr,
-             (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f);
+    // the conversion prologues 1, 2 and 4 hold many registers: with the
+    // fused_occupancy knob they are built for 4 resident blocks per CU
+    const int occ = c.fused_occ == 4 && f.pro != 3 ? 4 : 0;
+    const std::string pname = std::string("k_ntt_fast<8, false, 0, ") + (f.ci ? "4, " : "1, ") +
+                              std::to_string(f.pro) + ", 0, " + std::to_string(occ) + ">";
+    Prof pf(c, pname, 8.0 * (elems + src_words), 0.5 * elems * 8 + 2.0 * srcs * elems);
+#define FUSED_COL(FZ, PKV, OC)                                                                                    \
+  LAUNCH((k_ntt_fast<8, false, NTT_COL, FZ, PKV, 0, OC>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr, \
+         (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f)
+    const int code = (f.ci ? 100 : 0) + f.pro * 10 + occ;
+    switch (code) {
+      case 10: FUSED_COL(1, 1, 0); break;
+      case 20: FUSED_COL(1, 2, 0); break;
+      case 30: FUSED_COL(1, 3, 0); break;
+      case 40: FUSED_COL(1, 4, 0); break;
+      case 14: FUSED_COL(1, 1, 4); break;
+      case 24: FUSED_COL(1, 2, 4); break;
+      case 44: FUSED_COL(1, 4, 4); break;
+      case 110: FUSED_COL(4, 1, 0); break;
+      case 120: FUSED_COL(4, 2, 0); break;
+      case 130: FUSED_COL(4, 3, 0); break;
+      case 140: FUSED_COL(4, 4, 0); break;
+      case 114: FUSED_COL(4, 1, 4); break;
+      case 124: FUSED_COL(4, 2, 4); break;
+      case 144: FUSED_COL(4, 4, 4); break;
+      default: BM_THROW(BM_EINVAL, "launch check: fused column pass kind");
+    }
+#undef FUSED_COL
     check_launch();
   }
   if (f.epi) {
-    Prof pf(c, "k_ntt_fast<8, false, 1, 2>", 8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
-    LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
-           (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
+    Prof pf(c, f.epi == 2 ? "k_ntt_fast<8, false, 1, 2, 0, 2>" : "k_ntt_fast<8, false, 1, 2, 0, 1>",
+            8.0 * elems * (f.add0 || f.add1 ? 4.0 : 3.0), 0.5 * elems * 8 + elems);
+    if (f.epi == 2)
+      LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2, 0, 2>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp,
+             ts, (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
+    else
+      LAUNCH((k_ntt_fast<8, false, NTT_ROW, 2, 0, 1>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp,
+             ts, (u64*)nullptr, (size_t)0, mo, c.d_primes, c.d_twf, c.d_twq, logn, 8, 0, B, vz, f);
   } else if (f64_out) {
     Prof pf(c, "k_ntt_fast<8, false, 1, 3>", 16.0 * elems, 0.5 * elems * 8);
     LAUNCH((k_ntt_fast<8, false, NTT_ROW, 3>), grow, dim3(16 * Vrow), row_lds(R), c.stream, (const u64*)tmp, ts,
@@ -1946,7 +1985,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
 #define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                          \
   LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)(Wz + am.W)), dim3(TPB), 0, c.stream, y, sy, y_own, sown, \
          gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,      \
-         accumulate ? 1 : 0, am)
+         accumulate ? 1 : 0, am, c.kip_order)
     const int code = tb.beta * 100 + ZB * 10 + CH;
     switch (code) {
       case 124: KIP_HOIST_ZB(1, 2, 4); break;

@@ -296,3 +296,38 @@ def test_match_batch_face_scale_mixed(bm, schedule):
         bm.bm_ct_free(q)
     for g in gals:
         bm.bm_gallery_free(g)
+
+
+@pytest.mark.parametrize("schedule", [0x502, 0x402, 0x101])
+def test_tuning_knobs_keep_words(bm, schedule):
+    """Every value of every result-invariant knob (group chunk, hoisted key
+    inner product variant and block order, row-pass tiling, fused-pass
+    occupancy) gives the words of the default setting, at N = 2^16."""
+    ctx = lib_ctx(2)
+    sk, pk, evk = keys(2)
+    p = bm.bm_params_preset(2)
+    rng = np.random.default_rng(47)
+    d, k = (128, 4) if schedule != 0x101 else (16, 1)
+    X = normalize(rng.standard_normal((3000 if k == 4 else 5000, d)))
+    g = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 8800)
+    q = bm.bm_encrypt_query(ctx, pk, X[17], SEED, 88)
+    bm.bm_ctx_set_tuning(ctx)
+    r = bm.bm_match(ctx, evk, q, g, None, schedule=schedule)
+    want = words_of(bm, ctx, r, p.N)
+    bm.bm_result_free(r)
+    settings = [dict(group_chunk=1), dict(group_chunk=2), dict(group_chunk=64)]
+    settings += [dict(kip_variant=v, kip_order=o) for v in range(5) for o in (0, 1)]
+    settings += [dict(ntt_row_views=w) for w in (4, 8, 16)] + [dict(fused_occupancy=4)]
+    settings += [dict(group_chunk=3, kip_variant=2, kip_order=1, ntt_row_views=4, fused_occupancy=4)]
+    try:
+        for st in settings:
+            log("knobs %s schedule %#x" % (st, schedule))
+            bm.bm_ctx_set_tuning(ctx, **st)
+            r = bm.bm_match(ctx, evk, q, g, None, schedule=schedule)
+            for gi, (a, b) in enumerate(zip(words_of(bm, ctx, r, p.N), want)):
+                assert_words_equal(a, b, "knobs %s group %d" % (st, gi))
+            bm.bm_result_free(r)
+    finally:
+        bm.bm_ctx_set_tuning(ctx)
+    bm.bm_ct_free(q)
+    bm.bm_gallery_free(g)
