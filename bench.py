@@ -78,6 +78,9 @@ def parse():
                     help="face: 6,144 x 128-dim (default); fingerprint: 1,048,576 x 16-dim; "
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
                          "copy: 1 GiB device copy (counter calibration); ntt: batched NTT throughput")
+    ap.add_argument("--tuning", default="",
+                    help="fixed knobs group_chunk,kip_variant,ntt_row_views,kip_order,fused_occupancy instead of "
+                         "the autotuner (profiler runs that must launch the same kernels)")
     ap.add_argument("--scale", type=float, default=1.0, help="gallery size factor for batch/serve")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")
@@ -154,8 +157,14 @@ def main():
     best = min(sweep, key=sweep.get)
     bk, bs = conf[best]
     # the result-invariant knobs of the chosen configuration, by the autotuner
-    _, tuning, tuned_ms = bm.bm_autotune_batch(ctx, evk, [q_ct], [gals[bk]], [bs])
-    print("# autotuned knobs %s: %.3f ms/match" % (tuning, tuned_ms), file=sys.stderr, flush=True)
+    if args.tuning:
+        knobs = [int(v) for v in args.tuning.split(",")]
+        bm.bm_ctx_set_tuning(ctx, *knobs)
+        tuning = bm.bm_ctx_get_tuning(ctx)
+        print("# fixed knobs %s" % tuning, file=sys.stderr, flush=True)
+    else:
+        _, tuning, tuned_ms = bm.bm_autotune_batch(ctx, evk, [q_ct], [gals[bk]], [bs])
+        print("# autotuned knobs %s: %.3f ms/match" % (tuning, tuned_ms), file=sys.stderr, flush=True)
     canon = {key: v for key, v in sweep.items() if not conf[key][1] & (bm.BM_LEVEL_MIN | bm.BM_HOIST)}
     canon_best = min(canon, key=canon.get) if canon else None
 
