@@ -164,7 +164,9 @@ struct ModDownTable {
 // Work folded into the two passes of a forward transform at N = 2^16 (see
 // kern::ntt_fused).  The column pass computes its input words on the fly from
 // coefficient-domain sources (prologue), the row pass finishes each output
-// word against a second operand before storing it (epilogue).
+// word against a second operand before storing it (epilogue).  With isrc the
+// sources hold only the row pass of their inverse transform: the column pass
+// finishes it on each source tile before the conversion.
 // Batch element z of a source / minuend / output sits at
 //   base + (z / div) * hi + (z % div) * lo + limb * N.
 struct FuseArgs {
@@ -195,6 +197,9 @@ struct FuseArgs {
   int last_off = -1;             // pro 4: limb offset (in a source component) of the last chain limb
   int last_pid = -1;             // pro 4: its prime
   const u64* wmtab = nullptr;    // epi 2: minuend multipliers
+  int isrc = 0;                  // 1: sources still need their inverse column pass
+  const double* itwf = nullptr;  // isrc: inverse twiddles and their quotients w / q
+  const double* itwq = nullptr;
 };
 
 // ----------------------------------------------------------------- device memory
@@ -439,6 +444,14 @@ void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64);
 void modmul_rate(const Ctx& c, int pid, int blocks, int iters, const u64* seed, u64* out);
 // whether ntt_fused serves this context (N = 2^16)
 bool fused_ok(const Ctx& c);
+// the row pass of the inverse transform at N = 2^16 only (the words a fused
+// column pass with isrc takes as sources)
+void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+                  const LimbMap& m);
+// whether the fused column pass can finish the inverse transform of its
+// sources itself (f.isrc) for prologue kind pro: N = 2^16, outside the
+// conjugate-invariant ring, at most 5 source primes per block
+bool isrc_ok(const Ctx& c, int pro);
 // forward NTT of the words f's prologue computes, into tmp at the slots m.ooff
 // (slot s of element z at tmp + z * ts + m.ooff[s] * N), as FP64 values when
 // f64_out; with an epilogue the finished words go to f.out instead and tmp

@@ -333,6 +333,14 @@ void key_switch(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* ke
   key_switch2(c, x, sx, B, limbs, key, key, 31, add0, sa0, add1, sa1, out, so);
 }
 
+// a fused column pass whose sources hold only their inverse row pass
+static void set_isrc(const Ctx& c, FuseArgs& f, bool on) {
+  if (!on) return;
+  f.isrc = 1;
+  f.itwf = c.d_itwf;
+  f.itwq = c.d_itwq;
+}
+
 // ModUp of every digit of x (evaluation domain) to the extended basis, back
 // in evaluation form: y [B][beta][ext][N] (the digit's own slots unused), the
 // residues held as FP64 values for the key inner products.
@@ -341,8 +349,13 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
   DBuf xc(&c, (size_t)B * limbs * N);
-  // the fused transform unfolds (conjugate-invariant ring) on the fly
-  kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true, kern::fused_ok(c));
+  // the fused transform unfolds (conjugate-invariant ring) on the fly, and
+  // finishes the inverse transform itself where it can (isrc)
+  const bool is = kern::isrc_ok(c, 1);
+  if (is)
+    kern::ntt_inv_rows(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs));
+  else
+    kern::ntt(c, x, sx, xc.p(), (size_t)limbs * N, B, kern::chain_map(limbs), true, kern::fused_ok(c));
   const size_t sy = (size_t)beta * ext * N;
   DBuf y(&c, (size_t)B * sy);
   LimbMap m{};
@@ -359,6 +372,7 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
     f.mu = c.d_modup + limbs;
     f.src = xc.p();
     f.s_hi = (size_t)limbs * N;
+    set_isrc(c, f, is);
     audit::check(xc.p(), (size_t)B * limbs * N * sizeof(u64), "fused modup source");
     kern::ntt_fused(c, f, y.p(), sy, B, m, true);
   } else {
@@ -383,7 +397,11 @@ static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size
       mp.off[mp.n] = mp.ooff[mp.n] = comp * ext + limbs + kk;
       ++mp.n;
     }
-  kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
+  const bool is = kern::isrc_ok(c, 2);
+  if (is)
+    kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
+  else
+    kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
   if (kern::fused_ok(c)) {           // conversion and finish inside the forward transform
@@ -392,6 +410,7 @@ static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size
     f.ci = c.ci ? c.d_ci : nullptr;
     f.md = c.d_moddown;
     f.src = uw;
+    set_isrc(c, f, is);
     f.s_div = f.e_div = 2;           // element 2 z + comp
     f.s_hi = f.m_hi = suw;
     f.s_lo = f.m_lo = (size_t)ext * N;
@@ -483,10 +502,15 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
       ++mp.n;
     }
   }
-  kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
+  const bool is = kern::isrc_ok(c, 4);
+  if (is)
+    kern::ntt_inv_rows(c, uw.p(), suw, uw.p(), suw, B, mp);
+  else
+    kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
   DBuf t(&c, (size_t)B * 2 * nl * N);
   FuseArgs f;
   f.pro = 4;
+  set_isrc(c, f, is);
   f.ci = c.ci ? c.d_ci : nullptr;
   f.md = c.d_moddown;
   f.src = uw.p();
@@ -520,12 +544,17 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out) {
   DBuf last(&c, (size_t)B * comps * N);
   LimbMap m = kern::single(nl, nl);
   m.ooff[0] = 0;
-  kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true, kern::fused_ok(c));
+  const bool is = kern::isrc_ok(c, 3);
+  if (is)
+    kern::ntt_inv_rows(c, in, (size_t)limbs * N, last.p(), N, B * comps, m);
+  else
+    kern::ntt(c, in, (size_t)limbs * N, last.p(), N, B * comps, m, true, kern::fused_ok(c));
   DBuf t(&c, (size_t)B * comps * nl * N);
   if (kern::fused_ok(c)) {           // reduction and finish inside the forward transform
     if (in == out) BM_THROW(BM_EINVAL, "rescale cannot work in place");
     FuseArgs f;
     f.pro = 3;
+    set_isrc(c, f, is);
     f.ci = c.ci ? c.d_ci : nullptr;
     f.src_pid = nl;
     f.src = last.p();

@@ -268,7 +268,9 @@ enum { NTT_COL = 0, NTT_ROW = 1, NTT_ONE = 2 };
 // OCC > 0 asks the compiler for OCC resident blocks of 256 threads per CU
 // (a register budget of 512 / OCC per lane, spilling if it must): a tuning
 // alternative for the register-heavy fused column passes.
-template <int LOGM, bool INV, int KIND, int FUSE = 0, int PK = 0, int EK = 0, int OCC = 0>
+// IS = 1 (FUSE = 1): the sources hold only the row pass of their inverse
+// transform; the block finishes it on each source tile (f.isrc).
+template <int LOGM, bool INV, int KIND, int FUSE = 0, int PK = 0, int EK = 0, int OCC = 0, int IS = 0>
 __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* __restrict__ in, size_t in_stride,
                                                   u64* __restrict__ out, size_t out_stride,
                                                   LimbMap m, const PrimeC* __restrict__ P,
@@ -278,6 +280,7 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
   static_assert(FUSE == 0 || (!INV && (((FUSE == 1 || FUSE == 4) && KIND == NTT_COL) ||
                                        ((FUSE == 2 || FUSE == 3) && KIND == NTT_ROW))),
                 "fused prologues serve forward column passes, epilogues forward row passes");
+  static_assert(IS == 0 || (FUSE == 1 && LOGM == 8), "inverse source passes serve the fused column pass");
   const int pro = PK ? PK : f.pro;           // compile-time constant in the fused instantiations
   const int epi = EK ? EK : f.epi;
   constexpr bool PRO = FUSE == 1 || FUSE == 4;
@@ -401,11 +404,21 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
     int soff = 0, spid;
     u64 c1, c2;
     if (pro != 3) src_info(0, soff, spid, c1, c2);
-    if constexpr (FUSE == 1) {
+    if constexpr (FUSE == 1 && !IS) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) r0[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
     }
   }
+  // IS: source a's prime (source 0 .. is_n - 1 of this block)
+  auto is_pid = [&](int a) {
+    if (pro == 1) return f.mu->d[jd].src[a];
+    if (pro == 2) return f.md->pprime[a];
+    if (pro == 3) return f.src_pid;
+    return a < f.md->K ? f.md->pprime[a] : f.last_pid;
+  };
+  const int is_n = IS ? (pro == 4 ? f.md->K + 1 : ns) : 0;
+  (void)is_pid;
+  (void)is_n;
   // FUSE = 2: the epilogue's operands are requested here as well
   u64 mr[FUSE == 2 ? 16 : 1], ar[FUSE == 2 ? 16 : 1];
   const u64* Ad = nullptr;
@@ -445,12 +458,148 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
       tl[rr * 512 + slot] = W[g];
       tl[rr * 512 + 256 + slot] = WQ[g];
     }
+    if constexpr (IS) {
+      // the inverse twiddles of every source prime, [a][2][256] after the
+      // block's own, in the same order
+      for (int k = t; k < 256 * is_n; k += nthr) {
+        const int slot = k & 255, a = k >> 8;
+        if (slot == 0) continue;
+        const int st = 31 - __clz(slot);
+        const int o = slot - (1 << st);
+        const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+        const size_t g = (size_t)is_pid(a) * N + (1 << st) + b;
+        tl[512 * (a + 1) + slot] = f.itwf[g];
+        tl[512 * (a + 1) + 256 + slot] = f.itwq[g];
+      }
+    }
   }
   if constexpr (PRO) {
     // input word j (coefficient (addr(0, j) * astride + column)) from the sources:
     // ModUp / ModDown: sum_a [X_a q1_a]_{m_a} q2_a mod q (fast base conversion,
     // the bracket the exact residue in [0, m_a)); one limb: X mod q.
-    if constexpr (FUSE == 4) {
+    if constexpr (IS) {
+      // Each source tile first gets the column pass of its inverse transform
+      // (the 8 Gentleman-Sande stages of the first-pass words, times N^-1,
+      // with the word mapping of the inverse column kernel): its words are
+      // then the exact coefficient-domain residues at addr(0, j), the words
+      // the conversion below needs.  Same operations, same words as the
+      // separate inverse column pass.
+      __syncthreads();                          // twiddles staged
+      auto inv_col = [&](double (&w)[16], int a, int spid) {
+        const PrimeC& ps = P[spid];
+        const double qs = (double)ps.q, qsi = __longlong_as_double((long long)ps.pad[1]);
+        const double* ta = tl + 512 * (a + 1);
+        // (a stage's twiddles are read at the stage: the scheduler keeps them
+        // out of the registers of the earlier stages)
+        auto tw1 = [&](int k, int j, double& ww, double& wq) {
+          if (j == 0) __builtin_amdgcn_sched_barrier(0);
+          const int slot = (1 << (4 + k)) + ((j >> (4 - k)) << 4) + u;
+          ww = ta[slot];
+          wq = ta[256 + slot];
+        };
+        fpm::gs_phase16(w, false, qsi, qs, tw1);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(1, j))] = w[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) w[j] = sh[v * VS + pad(addr(0, j))];
+        auto tw0 = [&](int k, int j, double& ww, double& wq) {
+          if (j == 0) __builtin_amdgcn_sched_barrier(0);
+          const int slot = (1 << k) + (j >> (4 - k));
+          ww = ta[slot];
+          wq = ta[256 + slot];
+        };
+        fpm::gs_phase16(w, true, qsi, qs, tw0);
+        const double ni = (double)ps.ninv, niq = __longlong_as_double((long long)ps.pad[2]);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const double r = fred(fmul_mod(w[j], ni, niq, qs), qsi, qs);
+          w[j] = r < 0.0 ? __dadd_rn(r, qs) : r;
+        }
+      };
+      // source a's first-phase words (a = 0 was requested before the staging)
+      auto load = [&](double (&w)[16], int a, size_t soff) {
+        (void)a;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) w[j] = u64_to_f(S[soff * N + (size_t)addr(1, j) * astride]);
+      };
+      if (pro == 3) {
+        double w[16];
+        load(w, 0, 0);
+        inv_col(w, 0, f.src_pid);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = fred(w[j], qi, q);
+      } else if (pro == 4) {
+        // as the pro 4 branch below, from the finished source tiles
+        const ModDownTable& md = *f.md;
+        const int li = f.last_pid, ti = m.prime[blockIdx.y];
+        const double ql = (double)P[li].q, qli = __longlong_as_double((long long)P[li].pad[1]);
+        const double pl = (double)md.pinv[li][0], plq = pl / ql, pt = (double)md.pinv[ti][0], ptq = pt / q;
+        // cl starts from the last limb's word y and takes away each source's
+        // term (congruent to the sum the branch below subtracts at the end,
+        // with the same exact residue once reduced)
+        double cl[16], ci[16];
+        load(cl, md.K, (size_t)f.last_off);
+        inv_col(cl, md.K, li);
+        for (int a = 0; a < md.K; ++a) {
+          const int pid = md.pprime[a];
+          const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+          const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
+          const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
+          double w[16];
+          load(w, a, (size_t)(f.s_off0 + a));
+          inv_col(w, a, pid);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            double t1 = fred(fmul_mod(w[j], c1d, c1q, ms), msi, ms);
+            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+            const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);   // each within q
+            cl[j] = __dsub_rn(cl[j], pL);
+            ci[j] = a == 0 ? pT : __dadd_rn(ci[j], pT);
+          }
+          if (a & 1) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              cl[j] = fred(cl[j], qli, ql);
+              ci[j] = fred(ci[j], qi, q);
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          double last = fmul_mod(fred(cl[j], qli, ql), pl, plq, ql);
+          last = fred(last, qli, ql);
+          last = last < 0.0 ? __dadd_rn(last, ql) : last;               // exact residue mod q_last
+          const double z = __dadd_rn(fmul_mod(fred(ci[j], qi, q), pt, ptq, q), fred(last, qi, q));
+          x[j] = fred(z, qi, q);
+        }
+      } else {
+        for (int a = 0; a < ns; ++a) {
+          int soff, spid;
+          u64 c1, c2;
+          src_info(a, soff, spid, c1, c2);
+          const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+          const double c1d = (double)c1, c2d = (double)c2, c1q = c1d / ms, c2q = c2d / q;
+          double w[16];
+          load(w, a, (size_t)soff);
+          inv_col(w, a, spid);
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            double t1 = fred(fmul_mod(w[j], c1d, c1q, ms), msi, ms);
+            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+            const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
+            x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+          }
+          if (a & 1) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = fred(x[j], qi, q);
+      }
+    } else if constexpr (FUSE == 4) {
       // Conjugate-invariant ring: the sources hold the inverse transform before
       // its unfolding, b (coefficients modulo X^N - iota).  Every word is
       // unfolded with its mirror N - k, c_k = (b_k + iota b_{N-k}) / 2
@@ -580,16 +729,19 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
         const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
         const u64* Sa = S + (size_t)(f.s_off0 + a) * N;
-        u64 r[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) r[j] = a == 0 ? r0[j] : Sa[(size_t)addr(0, j) * astride];
+        for (int h = 0; h < 16; h += 8) {   // eight words in flight at a time
+          u64 r[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
-          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
-          const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);   // each within q
-          cl[j] = a == 0 ? pL : __dadd_rn(cl[j], pL);
-          ci[j] = a == 0 ? pT : __dadd_rn(ci[j], pT);
+          for (int j = 0; j < 8; ++j) r[j] = a == 0 ? r0[h + j] : Sa[(size_t)addr(0, h + j) * astride];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            double t1 = fred(fmul_mod(u64_to_f(r[j]), c1d, c1q, ms), msi, ms);
+            t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+            const double pL = fmul_mod(t1, hl, hlq, ql), pT = fmul_mod(t1, ht, htq, q);   // each within q
+            cl[h + j] = a == 0 ? pL : __dadd_rn(cl[h + j], pL);
+            ci[h + j] = a == 0 ? pT : __dadd_rn(ci[h + j], pT);
+          }
         }
         if (a & 1) {
 #pragma unroll
@@ -610,24 +762,35 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         x[j] = fred(z, qi, q);
       }
     } else {
-      for (int a = 0; a < ns; ++a) {
+      // source a's term of word j: [w (Q/q_a)^-1]_{q_a} (Q/q_a) mod q, |term| <= q
+      auto term = [&](u64 w, double ms, double msi, double c1d, double c1q, double c2d, double c2q) {
+        double t1 = fred(fmul_mod(u64_to_f(w), c1d, c1q, ms), msi, ms);
+        t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
+        return fmul_mod(t1, c2d, c2q, q);
+      };
+      {   // the first source, requested before the twiddle staging (its words die here)
+        int soff, spid;
+        u64 c1, c2;
+        src_info(0, soff, spid, c1, c2);
+        const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
+        const double c1d = (double)c1, c2d = (double)c2;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = term(r0[j], ms, msi, c1d, c1d / ms, c2d, c2d / q);
+      }
+      for (int a = 1; a < ns; ++a) {
         int soff, spid;
         u64 c1, c2;
         src_info(a, soff, spid, c1, c2);
         const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
-        const double c1d = (double)c1, c1q = c1d / ms, c2d = (double)c2, c2q = c2d / q;
-        u64 r[16];
-        if (a >= 1) {
+        const double c1d = (double)c1, c2d = (double)c2, c1q = c1d / ms, c2q = c2d / q;
+        const u64* Sa = S + (size_t)soff * N;
 #pragma unroll
-          for (int j = 0; j < 16; ++j) r[j] = S[((size_t)soff * N) + (size_t)addr(0, j) * astride];
-        }
+        for (int h = 0; h < 16; h += 8) {   // eight words in flight at a time
+          u64 r[8];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          const u64 w = a == 0 ? r0[j] : r[j];
-          double t1 = fred(fmul_mod(u64_to_f(w), c1d, c1q, ms), msi, ms);
-          t1 = t1 < 0.0 ? __dadd_rn(t1, ms) : t1;
-          const double p2 = fmul_mod(t1, c2d, c2q, q);   // |p2| <= q
-          x[j] = a == 0 ? p2 : __dadd_rn(x[j], p2);
+          for (int j = 0; j < 8; ++j) r[j] = Sa[(size_t)addr(0, h + j) * astride];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[h + j] = __dadd_rn(x[h + j], term(r[j], ms, msi, c1d, c1q, c2d, c2q));
         }
         if (a & 1) {
 #pragma unroll
@@ -1504,7 +1667,7 @@ static int row_views(const Ctx& c) { return c.ntt_views == 4 || c.ntt_views == 8
 // N = 2^12: one 12-stage pass; N = 2^16: 8 column stages then 8 row stages
 // (inverse: rows first).  Row passes take up to 16 polynomials per block.
 void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-              const LimbMap& m, const LimbMap& m_out, bool inverse) {
+              const LimbMap& m, const LimbMap& m_out, bool inverse, bool rows_only = false) {
   const int logn = c.log_n;
   const int N = 1 << logn;
   const double elems = (double)N * m.n * B;
@@ -1569,7 +1732,7 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
     row(out, out_stride, out, out_stride, m_out);
   } else {
     row(in, in_stride, out, out_stride, m);
-    col(out, out_stride, out, out_stride, m_out, 1);
+    if (!rows_only) col(out, out_stride, out, out_stride, m_out, 1);
   }
 }
 
@@ -1594,6 +1757,33 @@ void words_f64(const Ctx& c, u64* p, size_t n, bool to_f64) {
   check_launch();
 }
 
+// source primes whose inverse twiddles a fused column pass with isrc stages
+// (the most any of its blocks takes)
+static int isrc_count(const Ctx& c, const FuseArgs& f) {
+  if (f.pro == 3) return 1;
+  if (f.pro == 4) return c.K + 1;
+  if (f.pro == 2) return c.K;
+  int n = 0;
+  const ModUpTable& tb = c.h_modup[(int)(f.mu - c.d_modup)];
+  for (int j = 0; j < tb.beta; ++j) n = std::max(n, tb.d[j].nsrc);
+  return n;
+}
+
+bool isrc_ok(const Ctx& c, int pro) {
+  if (!fused_ok(c) || c.ci) return false;
+  const int n = pro == 3 ? 1 : pro == 4 ? c.K + 1 : pro == 2 ? c.K : c.alpha;
+  return n >= 1 && n <= 5;
+}
+
+void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+                  const LimbMap& m) {
+  if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: inverse row pass needs N = 2^16");
+  if (B <= 0 || m.n <= 0) return;
+  LimbMap m_out = m;
+  for (int i = 0; i < m.n; ++i) m_out.off[i] = m.ooff[i];
+  ntt_fast(c, in, in_stride, out, out_stride, B, m, m_out, true, true);
+}
+
 void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m, bool f64_out) {
   if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: fused transform needs N = 2^16");
   if (B <= 0 || m.n <= 0) return;
@@ -1601,7 +1791,9 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
       ((f.pro == 2 || f.pro == 4) && !f.md) || (f.epi && (!f.mnd || !f.out || !f.wtab)) ||
       (f.epi == 2 && !f.wmtab) || (f.pro == 4 && (f.last_pid < 0 || f.last_pid >= c.nprimes() || f.last_off < 0)) ||
       (c.ci != (f.ci != nullptr)) ||
-      (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))
+      (f.ci && f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())) ||
+      (f.isrc && (!isrc_ok(c, f.pro) || f.itwf != c.d_itwf || f.itwq != c.d_itwq ||
+                  (f.pro == 3 && (f.src_pid < 0 || f.src_pid >= c.nprimes())))))
     BM_THROW(BM_EINVAL, "launch check: fused transform arguments");
   const int logn = 16, N = 1 << logn;
   LimbMap mo = m;
@@ -1637,14 +1829,29 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
     // the conversion prologues 1, 2 and 4 hold many registers: with the
     // fused_occupancy knob they are built for 4 resident blocks per CU
     const int occ = c.fused_occ == 4 && f.pro != 3 ? 4 : 0;
+    const int is = f.isrc ? 1 : 0;
     const std::string pname = std::string("k_ntt_fast<8, false, 0, ") + (f.ci ? "4, " : "1, ") +
-                              std::to_string(f.pro) + ", 0, " + std::to_string(occ) + ">";
-    Prof pf(c, pname, 8.0 * (elems + src_words), 0.5 * elems * 8 + 2.0 * srcs * elems);
+                              std::to_string(f.pro) + ", 0, " + std::to_string(occ) + (is ? ", 1>" : ">");
+    // the inverse column pass of the sources: 8 stages per source word
+    const double is_ops = is ? 0.5 * 8 * (double)N * B * isrc_count(c, f) * m.n : 0.0;
+    Prof pf(c, pname, 8.0 * (elems + src_words), 0.5 * elems * 8 + 2.0 * srcs * elems + is_ops);
+    // IS: the source primes' inverse twiddles follow the block's own in LDS
+    const size_t lds_is = lds_col + (size_t)(is ? isrc_count(c, f) : 0) * 512 * sizeof(double);
 #define FUSED_COL(FZ, PKV, OC)                                                                                    \
   LAUNCH((k_ntt_fast<8, false, NTT_COL, FZ, PKV, 0, OC>), gcol, dim3(256), lds_col, c.stream, (const u64*)nullptr, \
          (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f)
-    const int code = (f.ci ? 100 : 0) + f.pro * 10 + occ;
+#define FUSED_COL_IS(PKV, OC)                                                                                     \
+  LAUNCH((k_ntt_fast<8, false, NTT_COL, 1, PKV, 0, OC, 1>), gcol, dim3(256), lds_is, c.stream, (const u64*)nullptr, \
+         (size_t)0, tmp, ts, mo, c.d_primes, c.d_twf, c.d_twq, logn, 0, 0, B, 1, f)
+    const int code = is * 1000 + (f.ci ? 100 : 0) + f.pro * 10 + occ;
     switch (code) {
+      case 1010: FUSED_COL_IS(1, 0); break;
+      case 1020: FUSED_COL_IS(2, 0); break;
+      case 1030: FUSED_COL_IS(3, 0); break;
+      case 1040: FUSED_COL_IS(4, 0); break;
+      case 1014: FUSED_COL_IS(1, 4); break;
+      case 1024: FUSED_COL_IS(2, 4); break;
+      case 1044: FUSED_COL_IS(4, 4); break;
       case 10: FUSED_COL(1, 1, 0); break;
       case 20: FUSED_COL(1, 2, 0); break;
       case 30: FUSED_COL(1, 3, 0); break;
@@ -1662,6 +1869,7 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
       default: BM_THROW(BM_EINVAL, "launch check: fused column pass kind");
     }
 #undef FUSED_COL
+#undef FUSED_COL_IS
     check_launch();
   }
   if (f.epi) {
