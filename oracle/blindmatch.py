@@ -154,15 +154,16 @@ def expansion_rotations_hoisted(params, d, k):
 
 def expand_hoisted(params, keys, cq, d, k, masks, mask_scale):
     """Alg. 1 with the rotations hoisted (an option of this build): the log2 k
-    rotate-and-add steps of part i unroll to C_i + sum over the non-empty
-    subsets S of Rot(C_i, r_S), evaluated with one ModUp and one ModDown per
-    part (ckks.rotation_sum_hoisted).  Same message as expand(), other bits."""
-    out = []
-    for i in range(k):
-        ci = ckks.rescale(params, ckks.pmul(params, cq, masks[i], mask_scale))
-        out.append(ckks.rotation_sum_hoisted(params, ci, expansion_amounts(params, d, k, i), keys.gks)
-                   if k > 1 else ci)
-    return out
+    rotate-and-add steps of part i unroll to Mul(P)(C_q, mask_i) + the sum
+    over the non-empty subsets S of its rotations by r_S, evaluated on C_q
+    with the mask applied after the key inner products and one ModDown per
+    part (ckks.rotation_sum_masked), then Res.  Same message as expand(),
+    other bits."""
+    if k == 1:
+        return [ckks.rescale(params, ckks.pmul(params, cq, masks[0], mask_scale))]
+    return [ckks.rescale(params, ckks.rotation_sum_masked(params, cq, masks[i], mask_scale,
+                                                          expansion_amounts(params, d, k, i), keys.gks))
+            for i in range(k)]
 
 
 def hec3(params, keys, cu, cs, d, k, schedule, rot_limbs=None, hoist=False):

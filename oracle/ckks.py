@@ -604,6 +604,59 @@ def rotation_sum_hoisted(params, x, amounts, gks):
                       l, x.scale)
 
 
+def rotation_sum_masked(params, x, pt, pt_scale, amounts, gks):
+    """pt x + sum_r Rot(pt x, r) for the integer plaintext pt (Mul(P) then the
+    rotations), evaluated with the plaintext applied after the key inner
+    products (an option of this build): digit ModUp of x_1 once; for every r
+    the key inner product of the automorphism of the extended digits with
+    the key for s(X^g), over Q_l u P, multiplied by phi_g(pt) read over
+    Q_l u P and summed; one ModDown of each sum; the terms without a key
+    switch, pt x_0 + sum_r phi_g(pt x_0) and pt x_1, added in Q_l.  Since
+    phi_g is a ring automorphism, phi_g(pt x) = phi_g(pt) phi_g(x): the same
+    message as Mul(P) followed by the rotations; other rounding, other bits.
+    Returns the result at x's level and scale x.scale * pt_scale (no rescale)."""
+    l = x.limbs
+    qs = params.q[:l]
+    ext = qs + params.p
+    key_limb = list(range(l)) + [len(params.q) + k for k in range(params.K)]
+    beta = -(-l // params.alpha)
+    pt_ext = reduce_int(pt, ext)
+    pt_q = pt_ext[:l]
+    ys = [mod_up_digit(params, x.c[1], l, j) for j in range(beta)]
+    gs = []
+    jobs = []
+    for r in amounts:
+        g = galois_element(params, r)
+        if g not in gks:
+            raise KeyError("no Galois key for rotation %d" % r)
+        gs.append(g)
+        for j in range(beta):
+            yg = automorphism(ys[j], g, ext, params.ring)
+            for t, mod in enumerate(ext):
+                jobs.append((yg[t], gks[g].b[j][key_limb[t]], mod))
+                jobs.append((yg[t], gks[g].a[j][key_limb[t]], mod))
+    prods = iter(polymul_jobs(jobs, params.ring))
+    u = np.zeros((len(ext), params.N), dtype=np.uint64)
+    w = np.zeros((len(ext), params.N), dtype=np.uint64)
+    for g in gs:
+        ur = np.zeros((len(ext), params.N), dtype=np.uint64)
+        wr = np.zeros((len(ext), params.N), dtype=np.uint64)
+        for j in range(beta):
+            for t, mod in enumerate(ext):
+                ur[t] = (ur[t] + next(prods)) % np.uint64(mod)
+                wr[t] = (wr[t] + next(prods)) % np.uint64(mod)
+        pg = automorphism(pt_ext, g, ext, params.ring)
+        u = add(u, mul(pg, ur, ext, params.ring), ext)
+        w = add(w, mul(pg, wr, ext, params.ring), ext)
+    m0 = mul(pt_q, x.c[0], qs, params.ring)
+    c0 = m0.copy()
+    for g in gs:
+        c0 = add(c0, automorphism(m0, g, qs, params.ring), qs)
+    c1 = mul(pt_q, x.c[1], qs, params.ring)
+    return Ciphertext([add(c0, mod_down(params, u, l), qs), add(c1, mod_down(params, w, l), qs)],
+                      l, x.scale * pt_scale)
+
+
 def drop_limbs(x, limbs):
     """Exact level drop: keep the first `limbs` residues."""
     if limbs > x.limbs:

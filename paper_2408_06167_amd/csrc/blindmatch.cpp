@@ -138,20 +138,37 @@ void expand_batch(Ctx& c, const bm_evk* evk, const u64* q, size_t qs, size_t qcs
   if (nq < 1) return;
   const size_t ln = (size_t)l * N, nln = (size_t)nl * N;
   const int E = nq * (int)k;                  // element j k + i: part i of query j
-  // Mul(P) of every query by every mask, then one batched rescale
-  DBuf pm(&c, (size_t)E * 2 * ln);
-  kern::mul_ct_pt(c, q, qs, qcs, masks, (size_t)(c.L + 1) * N, pm.p(), 2 * ln, ln, E, l, (int)k, (int)k);
-  ev::rescale(c, pm.p(), E, 2, l, out);
-  if (hoist) {
-    // the log2 k steps of part i unrolled into one hoisted sum; the amounts
-    // depend on the part only, so list i serves every query's part i
+  if (hoist && k > 1) {
+    // the log2 k steps of part i unrolled into one hoisted sum of the
+    // rotations of Mul(P)(q, mask_i), evaluated on q itself: one ModUp of
+    // every query's c1, the key inner products of all parts' amounts with
+    // each mask applied to them over Q_l u P, one ModDown and Res per part
+    // (the amounts depend on the part only: list i serves every query)
     std::vector<std::vector<long>> amounts;
     for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
     std::vector<const u64*> keys;
     const std::vector<HoistArgs> hs = hoist_args(c, evk, amounts, true, keys);
-    ev::rotation_sum_hoisted(c, evk, out, E, nl, hs, keys, out);
+    if (hs.size() != 1) BM_THROW(BM_EINVAL, "too many hoisted expansion rotations");
+    const ModUpTable& tb = c.h_modup[l];
+    const size_t sy = (size_t)tb.beta * tb.ext * N, suw = (size_t)2 * tb.ext * N;
+    DBuf y = ev::modup_eval(c, q + qcs, qs, nq, l);
+    DBuf uw(&c, (size_t)E * suw), ad(&c, (size_t)E * 2 * ln);
+    const bool fused = kern::fused_ok(c);
+    kern::kip_hoist_mask(c, y.p(), sy, q, qs, qcs, (const u64* const*)evk->gtab.p(), hs[0], keys, masks, uw.p(),
+                         suw, ad.p(), 2 * ln, nq, (int)k, l, fused);
+    if (fused) {
+      ev::moddown_rescale(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, out);
+    } else {
+      DBuf sum(&c, (size_t)E * 2 * ln);
+      ev::moddown_add(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, sum.p(), 2 * ln);
+      ev::rescale(c, sum.p(), E, 2, l, out);
+    }
     return;
   }
+  // Mul(P) of every query by every mask, then one batched rescale
+  DBuf pm(&c, (size_t)E * 2 * ln);
+  kern::mul_ct_pt(c, q, qs, qcs, masks, (size_t)c.mask_limbs() * N, pm.p(), 2 * ln, ln, E, l, (int)k, (int)k);
+  ev::rescale(c, pm.p(), E, 2, l, out);
   // step t: part i adds Rot(., -c 2^t) when bit t of i is 0 and Rot(., +c 2^t)
   // otherwise; bit t of the element index j k + i is bit t of i (k a power of
   // two), so every element of the batch picks its sign in the same launch
@@ -413,7 +430,7 @@ void enroll(Ctx& c, const bm_evk* evk, bm_gallery& g, const u64* const* users, i
     DBuf pm(&c, (size_t)E * uct), x(&c, (size_t)E * ct);
     for (int u = 0; u < U; ++u)
       for (int comp = 0; comp < 2; ++comp)
-        kern::mul(c, users[u0 + u] + comp * (size_t)ul * N, 0, masks, (size_t)(c.L + 1) * N,
+        kern::mul(c, users[u0 + u] + comp * (size_t)ul * N, 0, masks, (size_t)c.mask_limbs() * N,
                   pm.p() + (size_t)u * k * uct + comp * (size_t)ul * N, uct, (int)k, kern::chain_map(ul));
     ev::rescale(c, pm.p(), E, 2, ul, x.p());
     std::vector<u64> amount(E);

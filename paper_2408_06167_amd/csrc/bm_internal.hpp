@@ -390,6 +390,9 @@ struct Ctx {
 
   int nprimes() const { return (int)primes.size(); }
   int pid_special(int k) const { return L + 1 + k; }
+  // limbs of a mask plaintext: every prime (the masked hoisted expansion
+  // reads the special ones)
+  int mask_limbs() const { return L + 1 + K; }
   void use_stream(void* s);
   // A context sharing this one's parameters and device tables, with its own
   // stream and memory pool (work on it overlaps with work on this one).
@@ -529,6 +532,15 @@ void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const
 // launch computes c0_out[z] = c0_in[z] + sum_a phi_{g(z,a)}(c0_in[z]) over
 // `limbs` limbs (accumulate: both outputs are added to; c0_out must not alias
 // c0_in).
+// masked hoisted rotation sums of Alg. 1's parts (k_kip_hoist_mask): per
+// element e = j k + i (part i of query j at x + j sx, c1 at + xcs) the key
+// sums over Q_l u P to uw [E][2][l+K][N] (with dadd: P times the addends added
+// at the last chain limb) and the addends to ad [E][2][limbs][N]; masks
+// [k][L+1+K][N]; h.per_elem with one amount list per part (h.mod = k)
+void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
+                    const u64* const* gtab, const HoistArgs& h, const std::vector<const u64*>& keys,
+                    const u64* masks, u64* uw, size_t suw, u64* ad, size_t sad, int nq, int k, int limbs,
+                    bool dadd);
 void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
                const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
                size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate);
@@ -572,7 +584,7 @@ struct bm_masks {
   bm_ctx* ctx = nullptr;
   uint32_t d = 0, k = 0;
   double scale = 0;
-  bm::DBuf pt;             // [k][L+1][N] evaluation domain
+  bm::DBuf pt;             // [k][L+1+K][N] evaluation domain, every prime
 };
 
 struct bm_ctx {

@@ -919,8 +919,8 @@ static bm_masks* make_masks(bm_ctx* ctx, uint32_t d, uint32_t k, const int64_t* 
   m->d = d;
   m->k = k;
   m->scale = scale;
-  m->pt = DBuf(&c, (size_t)k * (c.L + 1) * c.N);
-  ev::upload_plain(c, coeffs, (int)k, c.L + 1, m->pt.p());
+  m->pt = DBuf(&c, (size_t)k * c.mask_limbs() * c.N);
+  ev::upload_plain(c, coeffs, (int)k, c.mask_limbs(), m->pt.p());
   return m.release();
 }
 
@@ -1125,7 +1125,9 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
     if (ge->key == key) e = ge.get();
-  const size_t qw = (size_t)2 * q->limbs * c.N, ow = (size_t)n_out * 2 * s.ol * c.N;
+  // the graph's query slot holds the query already cut to the ql limbs the
+  // match reads (the copy into it is the level drop)
+  const size_t qw = (size_t)2 * s.ql * c.N, ow = (size_t)n_out * 2 * s.ol * c.N;
   if (!e) {
     std::unique_ptr<GraphEntry> ne(new GraphEntry);
     ne->key = key;
@@ -1138,7 +1140,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
       ne->out_slot = DBuf(&c, ow);
       HIP_OK(dev::begin_capture(c.stream));
       capturing = true;
-      match_body(c, evk, ne->q_slot.p(), q->limbs, g, m, cmask, s, ne->out_slot.p());
+      match_body(c, evk, ne->q_slot.p(), (uint32_t)s.ql, g, m, cmask, s, ne->out_slot.p());
       capturing = false;
       HIP_OK(dev::end_capture(c.stream, &graph));
       HIP_OK(dev::graph_instantiate(&ne->exec, graph));
@@ -1160,7 +1162,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
     c.graphs.push_back(std::move(ne));
     e = c.graphs.back().get();
   }
-  kern::copy_limbs(c, q->buf.p(), qw, qw / 2, e->q_slot.p(), 1, qw, 0, qw / 2, 1, 2, (int)q->limbs);
+  kern::copy_limbs(c, q->buf.p(), 0, (size_t)q->limbs * c.N, e->q_slot.p(), 1, qw, 0, qw / 2, 1, 2, s.ql);
   HIP_OK(dev::graph_launch(e->exec, c.stream));
   kern::copy_limbs(c, e->out_slot.p(), 2 * (size_t)s.ol * c.N, (size_t)s.ol * c.N, out, 1,
                    2 * (size_t)s.ol * c.N, 0, (size_t)s.ol * c.N, (int)n_out, 2, s.ol);

@@ -344,7 +344,7 @@ static void set_isrc(const Ctx& c, FuseArgs& f, bool on) {
 // ModUp of every digit of x (evaluation domain) to the extended basis, back
 // in evaluation form: y [B][beta][ext][N] (the digit's own slots unused), the
 // residues held as FP64 values for the key inner products.
-static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
+DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
   const size_t N = c.N;
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
@@ -385,7 +385,7 @@ static DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
 
 // ModDown of (u, w) [B][2][ext][N] over Q_l u P plus the addends:
 // out = (add0 + ModDown(u), add1 + ModDown(w))
-static void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
+void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
                         size_t sa1, u64* out, size_t so) {
   const size_t N = c.N;
   const int ext = c.h_modup[limbs].ext;
@@ -484,13 +484,26 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
     return;
   }
   const size_t N = c.N, ln = (size_t)limbs * N;
-  const int nl = limbs - 1;
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext;
   const size_t sy = (size_t)tb.beta * ext * N, suw = (size_t)2 * ext * N;
   DBuf y = modup_eval(c, d + 2 * ln, 3 * ln, B, limbs);
   DBuf uw(&c, (size_t)B * suw);
   kern::kip(c, y.p(), sy, d + 2 * ln, 3 * ln, rlk, rlk, 31, uw.p(), suw, B, limbs, d, 3 * ln, ln);
+  moddown_rescale(c, uw.p(), B, limbs, d, 3 * ln, d + ln, 3 * ln, out);
+}
+
+// (add0 + ModDown(u), add1 + ModDown(w)) rescaled, with the words of
+// moddown_add then rescale: uw [B][2][ext][N] holds u + P add0 and w + P add1
+// at the last chain limb (see relin_rescale), the addends are read at their
+// first limbs - 1 limbs, out [B][2][limbs-1][N].
+void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
+                     size_t sa1, u64* out) {
+  const size_t N = c.N;
+  const int nl = limbs - 1;
+  const ModUpTable& tb = c.h_modup[limbs];
+  const int ext = tb.ext;
+  const size_t suw = (size_t)2 * ext * N;
   LimbMap mp{};
   for (int comp = 0; comp < 2; ++comp) {
     mp.prime[mp.n] = nl;
@@ -504,16 +517,16 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
   }
   const bool is = kern::isrc_ok(c, 4);
   if (is)
-    kern::ntt_inv_rows(c, uw.p(), suw, uw.p(), suw, B, mp);
+    kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
   else
-    kern::ntt(c, uw.p(), suw, uw.p(), suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
+    kern::ntt(c, uw, suw, uw, suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
   DBuf t(&c, (size_t)B * 2 * nl * N);
   FuseArgs f;
   f.pro = 4;
   set_isrc(c, f, is);
   f.ci = c.ci ? c.d_ci : nullptr;
   f.md = c.d_moddown;
-  f.src = uw.p();
+  f.src = uw;
   f.s_div = f.e_div = 2;             // element 2 z + comp
   f.s_hi = f.m_hi = suw;
   f.s_lo = f.m_lo = (size_t)ext * N;
@@ -521,19 +534,20 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
   f.last_off = nl;
   f.last_pid = nl;
   f.epi = 2;
-  f.mnd = uw.p();
+  f.mnd = uw;
   f.wmtab = &c.d_moddown->pinv[0][0];
-  f.add0 = d;
-  f.a0_hi = 3 * ln;
-  f.add1 = d + ln;
-  f.a1_hi = 3 * ln;
+  f.add0 = add0;
+  f.a0_hi = sa0;
+  f.add1 = add1;
+  f.a1_hi = sa1;
   f.out = out;
   f.o_hi = (size_t)2 * nl * N;
   f.o_lo = (size_t)nl * N;
   f.wtab = c.d_rescale + (size_t)(limbs - 1) * (c.L + 1) * 2;
-  audit::check(uw.p(), (size_t)B * suw * sizeof(u64), "relin_rescale source");
-  audit::check(d, ((size_t)(B - 1) * 3 * ln + 2 * ln) * sizeof(u64), "relin_rescale addends");
-  audit::check(out, (size_t)B * 2 * nl * N * sizeof(u64), "relin_rescale output");
+  audit::check(uw, (size_t)B * suw * sizeof(u64), "moddown_rescale source");
+  audit::check(add0, ((size_t)(B - 1) * sa0 + (size_t)nl * N) * sizeof(u64), "moddown_rescale addend 0");
+  audit::check(add1, ((size_t)(B - 1) * sa1 + (size_t)nl * N) * sizeof(u64), "moddown_rescale addend 1");
+  audit::check(out, (size_t)B * 2 * nl * N * sizeof(u64), "moddown_rescale output");
   kern::ntt_fused(c, f, t.p(), (size_t)nl * N, 2 * B, kern::chain_map(nl));
 }
 

@@ -26,6 +26,19 @@ void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
 void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out);
 // in: [B][comps][limbs][N] -> out [B][comps][limbs-1][N]
 void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
+// ModUp of every digit of x ([B][limbs][N], stride sx, evaluation domain) to
+// Q_l u P, back in the evaluation domain as FP64 values: [B][beta][l+K][N]
+// (a digit's own slots unused)
+DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs);
+// ModDown of (u, w) [B][2][l+K][N] over Q_l u P plus the addends:
+// out = (add0 + ModDown(u), add1 + ModDown(w)), [B][2][limbs][N] at stride so
+void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1, size_t sa1,
+                 u64* out, size_t so);
+// the same then rescaled, at N = 2^16 in one inverse row pass and one fused
+// transform: uw must hold u + P add0 and w + P add1 at the last chain limb;
+// out [B][2][limbs-1][N]
+void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
+                     size_t sa1, u64* out);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
 // batch element z rotates with (g1, key1) when bit `sel` of z is set, else (g0, key0)

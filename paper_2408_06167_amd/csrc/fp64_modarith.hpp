@@ -49,16 +49,17 @@ __host__ __device__ __forceinline__ double fred(double a, double qi, double q) {
   return __builtin_fma(-__builtin_rint(a * qi), q, a);
 }
 
-// exact conversions for 0 <= v < 2^52
+// exact conversions for 0 <= v < 2^52, through the double 2^52 + v: its
+// exponent field is that of 2^52 and its 52 fraction bits are v, so one OR
+// and one exact subtraction give v as a double, and one exact addition and
+// one AND give it back
 __host__ __device__ __forceinline__ double u64_to_f(uint64_t v) {
 #pragma clang fp contract(off)
-  return __builtin_fma((double)(uint32_t)(v >> 32), 4294967296.0, (double)(uint32_t)v);
+  return __builtin_bit_cast(double, v | 0x4330000000000000ull) - 4503599627370496.0;
 }
 __host__ __device__ __forceinline__ uint64_t f_to_u64(double x) {
 #pragma clang fp contract(off)
-  const uint32_t h = (uint32_t)(x * (1.0 / 4294967296.0));   // truncation: floor for x >= 0
-  const uint32_t l = (uint32_t)__builtin_fma(-(double)h, 4294967296.0, x);
-  return ((uint64_t)h << 32) | l;
+  return __builtin_bit_cast(uint64_t, x + 4503599627370496.0) & 0x000fffffffffffffull;
 }
 
 // the exact residue in [0, q) of an integer-valued double with |a| < 2^53

@@ -485,7 +485,10 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
       // the conversion below needs.  Same operations, same words as the
       // separate inverse column pass.
       __syncthreads();                          // twiddles staged
-      auto inv_col = [&](double (&w)[16], int a, int spid) {
+      // exact: finish with N^-1 and the exact residues in [0, q_a); otherwise
+      // the words stay the stages' output (|w| <= 2 q_a), for a caller that
+      // folds N^-1 into its own constant
+      auto inv_col = [&](double (&w)[16], int a, int spid, bool exact) {
         const PrimeC& ps = P[spid];
         const double qs = (double)ps.q, qsi = __longlong_as_double((long long)ps.pad[1]);
         const double* ta = tl + 512 * (a + 1);
@@ -511,12 +514,22 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
           wq = ta[256 + slot];
         };
         fpm::gs_phase16(w, true, qsi, qs, tw0);
+        if (!exact) return;
         const double ni = (double)ps.ninv, niq = __longlong_as_double((long long)ps.pad[2]);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const double r = fred(fmul_mod(w[j], ni, niq, qs), qsi, qs);
           w[j] = r < 0.0 ? __dadd_rn(r, qs) : r;
         }
+      };
+      // c N^-1 mod m (c < m): the conversion constant that also takes the
+      // transform's N^-1, and its quotient
+      auto with_ninv = [&](double cd, int spid, double& cn, double& cnq) {
+        const PrimeC& ps = P[spid];
+        const double ms = (double)ps.q, msi = __longlong_as_double((long long)ps.pad[1]);
+        double r = fred(fmul_mod(cd, (double)ps.ninv, __longlong_as_double((long long)ps.pad[2]), ms), msi, ms);
+        cn = r < 0.0 ? __dadd_rn(r, ms) : r;
+        cnq = cn / ms;
       };
       // source a's first-phase words (a = 0 was requested before the staging)
       auto load = [&](double (&w)[16], int a, size_t soff) {
@@ -527,7 +540,7 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
       if (pro == 3) {
         double w[16];
         load(w, 0, 0);
-        inv_col(w, 0, f.src_pid);
+        inv_col(w, 0, f.src_pid, true);
 #pragma unroll
         for (int j = 0; j < 16; ++j) x[j] = fred(w[j], qi, q);
       } else if (pro == 4) {
@@ -541,15 +554,16 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         // with the same exact residue once reduced)
         double cl[16], ci[16];
         load(cl, md.K, (size_t)f.last_off);
-        inv_col(cl, md.K, li);
+        inv_col(cl, md.K, li, true);
         for (int a = 0; a < md.K; ++a) {
           const int pid = md.pprime[a];
           const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
-          const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
+          double c1d, c1q;
+          with_ninv((double)md.phatinv[a][0], pid, c1d, c1q);
           const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
           double w[16];
           load(w, a, (size_t)(f.s_off0 + a));
-          inv_col(w, a, pid);
+          inv_col(w, a, pid, false);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             double t1 = fred(fmul_mod(w[j], c1d, c1q, ms), msi, ms);
@@ -580,10 +594,12 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
           u64 c1, c2;
           src_info(a, soff, spid, c1, c2);
           const double ms = (double)P[spid].q, msi = __longlong_as_double((long long)P[spid].pad[1]);
-          const double c1d = (double)c1, c2d = (double)c2, c1q = c1d / ms, c2q = c2d / q;
+          const double c2d = (double)c2, c2q = c2d / q;
+          double c1d, c1q;
+          with_ninv((double)c1, spid, c1d, c1q);
           double w[16];
           load(w, a, (size_t)soff);
-          inv_col(w, a, spid);
+          inv_col(w, a, spid, false);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             double t1 = fred(fmul_mod(w[j], c1d, c1q, ms), msi, ms);
@@ -1313,6 +1329,128 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
   const u64 ru = res(su), rw = res(sw);
   U[i] = accumulate ? add_mod(U[i], ru, q) : ru;
   U[(size_t)ext * N + i] = accumulate ? add_mod(U[(size_t)ext * N + i], rw, q) : rw;
+}
+
+// Masked hoisted rotation sums (Alg. 1 with its rotations hoisted and the
+// masks applied after the key inner products).  Element e = j k + i is part i
+// of query j (x at x + j sx: c0, then c1 at + xcs, `limbs` limbs, evaluation
+// domain); list i of h (h.g[i A + a]) holds part i's amounts; mask i is at
+// masks + i ml N over every prime (ml limbs: the chain, then the specials).
+//   addends (the first WA blocks, limbs < `limbs`):
+//     ad[e][0] = sum over r in {0} u amounts of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1
+//   key sums (the other blocks, every slot t of Q_l u P):
+//     uw[e][c] = sum_a phi_a(mask_i) * sum_d phi_a(y_d[j]) key_{a,d,c}
+//   and, with dadd, P ad[e][c] added at the last chain slot (the form the
+//   fused ModDown and rescale take).
+// One thread per word; the gathers read phi_a(v)[pos] = v[autom_src(pos)].
+template <int BETA>
+__global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
+                                 const u64* const* gtab, HoistArgs h, const u64* masks, int ml, u64* uw,
+                                 size_t suw, u64* ad, size_t sad, const ModUpTable* T, int key_limbs, int L1,
+                                 const PrimeC* P, int log_n, int ms, int E, int k, int WA, int dadd, double pmd) {
+  const int N = 1 << log_n;
+  const int gx = (N + TPB - 1) / TPB;
+  const ModUpTable& tb = *T;
+  const int limbs = tb.limbs;
+  // sum over r in {0} u amounts of mask_i[s_r] x0[s_r] at limb t, and mask_i x1
+  // at pos, as exact residues (every product within 1.25 q, folded every
+  // second one)
+  auto addends = [&](int e, int t, int pos, u64& a0, u64& a1) {
+    const int j = e / k, i = e % k;
+    const PrimeC& pr = P[t];
+    const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
+    const u64* M = masks + ((size_t)i * ml + t) * N;
+    const u64* X0 = x + (size_t)j * sx + (size_t)t * N;
+    const u64* X1 = X0 + xcs;
+    double s = fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X0[pos]), qi, q);
+    for (int a = 0; a < h.A; ++a) {
+      const u32 src = autom_src((u32)pos, h.g[i * h.A + a], log_n, ms);
+      s = __dadd_rn(s, fmul_mod_q(u64_to_f(M[src]), u64_to_f(X0[src]), qi, q));
+      if (a & 1) s = fred(s, qi, q);
+    }
+    double r = fred(s, qi, q);
+    a0 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
+    r = fred(fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X1[pos]), qi, q), qi, q);
+    a1 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
+  };
+  if ((int)blockIdx.x < WA) {
+    const int lb = blockIdx.x;
+    const int pos = (lb % gx) * TPB + threadIdx.x;
+    const int t = (lb / gx) % limbs;
+    const int e = lb / (gx * limbs);
+    if (pos >= N || e >= E) return;
+    u64 a0, a1;
+    addends(e, t, pos, a0, a1);
+    u64* A0 = ad + (size_t)e * sad + (size_t)t * N;
+    A0[pos] = a0;
+    A0[(size_t)limbs * N + pos] = a1;
+    return;
+  }
+  const int ext = tb.ext;
+  // (element, position block, slot), element fastest: the blocks of one slot
+  // and position block share their key words through L2
+  const int lb = (int)blockIdx.x - WA;
+  const int e = lb % E;
+  const int pb = (lb / E) % gx;
+  const int t = lb / (E * gx);
+  const int pos = pb * TPB + threadIdx.x;
+  const int j = e / k, i = e % k;
+  __shared__ const u64* kp[HOIST_MAX];
+  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[i * h.A + a] >> 1];
+  __syncthreads();
+  if (pos >= N || t >= ext) return;
+  const PrimeC& pr = P[tb.ext_prime[t]];
+  const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
+  const int kl = t < limbs ? t : L1 + (t - limbs);          // key limb (and mask limb) of slot t
+  const u64* M = masks + ((size_t)i * ml + kl) * N;
+  const u64* src[BETA];
+  bool own[BETA];
+#pragma unroll
+  for (int d = 0; d < BETA; ++d) {
+    const ModUpDigit& dg = tb.d[d];
+    own[d] = t >= dg.src[0] && t < dg.src[0] + dg.nsrc;
+    src[d] = own[d] ? x + (size_t)j * sx + xcs + (size_t)t * N : y + (size_t)j * sy + ((size_t)d * ext + t) * N;
+  }
+  const size_t ko = (size_t)kl * N + pos, kst = (size_t)key_limbs * N;
+  double su = 0.0, sw = 0.0;
+  for (int a = 0; a < h.A; ++a) {
+    const u32 s = autom_src((u32)pos, h.g[i * h.A + a], log_n, ms);
+    const double* key = (const double*)kp[a];
+    double iu = 0.0, iw = 0.0;
+#pragma unroll
+    for (int d = 0; d < BETA; ++d) {
+      const u64 wv = src[d][s];
+      const double v = own[d] ? u64_to_f(wv) : __longlong_as_double((long long)wv);
+      iu = __dadd_rn(iu, fmul_mod_q(v, key[ko + (size_t)(2 * d) * kst], qi, q));
+      iw = __dadd_rn(iw, fmul_mod_q(v, key[ko + (size_t)(2 * d + 1) * kst], qi, q));
+      if (d & 1) {
+        iu = fred(iu, qi, q);
+        iw = fred(iw, qi, q);
+      }
+    }
+    // the mask word multiplies the reduced inner sums (|.| <= q/2 + 1)
+    const double mw = u64_to_f(M[s]);
+    su = __dadd_rn(su, fmul_mod_q(fred(iu, qi, q), mw, qi, q));
+    sw = __dadd_rn(sw, fmul_mod_q(fred(iw, qi, q), mw, qi, q));
+    if (a & 1) {
+      su = fred(su, qi, q);
+      sw = fred(sw, qi, q);
+    }
+  }
+  if (dadd && t == limbs - 1) {
+    u64 a0, a1;
+    addends(e, t, pos, a0, a1);
+    const double pmq = pmd / q;
+    su = __dadd_rn(fred(su, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
+    sw = __dadd_rn(fred(sw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
+  }
+  auto res = [&](double v) {
+    const double r = fred(v, qi, q);
+    return f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
+  };
+  u64* U = uw + (size_t)e * suw + (size_t)t * N;
+  U[pos] = res(su);
+  U[(size_t)ext * N + pos] = res(sw);
 }
 
 // The same sums when every element uses the same amounts: one thread serves
@@ -2143,6 +2281,55 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
   }
   LAUNCH(k_kip, ew_grid(c.N, tb.ext, B), dim3(TPB), 0, c.stream, y, sy, y_own, sown, key0, key1, sel,
          uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, (int)c.N, dadd, sd, dcs, pm, pms);
+  check_launch();
+}
+
+void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
+                    const u64* const* gtab, const HoistArgs& h, const std::vector<const u64*>& keys,
+                    const u64* masks, u64* uw, size_t suw, u64* ad, size_t sad, int nq, int k, int limbs,
+                    bool dadd) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  if (limbs < 2 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: masked kip level");
+  if (nq < 1 || k < 2 || !h.per_elem || h.mod != k || h.A < 1 || h.A * k > HOIST_MAX)
+    BM_THROW(BM_EINVAL, "launch check: masked kip amounts");
+  if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the masked kip");
+  const int E = nq * k, ml = c.L + 1 + c.K;
+  chk(y, nq, sy, 0, (size_t)tb.beta * tb.ext * c.N, "masked kip digits");
+  chk(x, nq, sx, 0, xcs + (size_t)limbs * c.N, "masked kip input");
+  chk(gtab, 1, 0, 0, c.M / 2, "key table");
+  for (const u64* key : keys) chk(key, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "masked kip key");
+  chk(masks, 1, 0, 0, (size_t)k * ml * c.N, "masked kip masks");
+  chk(uw, E, suw, 0, (size_t)2 * tb.ext * c.N, "masked kip output");
+  chk(ad, E, sad, 0, (size_t)2 * limbs * c.N, "masked kip addends");
+  u64 pm = 0;
+  if (dadd) {   // P mod q_{limbs-1}
+    const u64 ql = c.primes[limbs - 1].q;
+    pm = 1;
+    for (int kk = 0; kk < c.K; ++kk) pm = h_mulmod(pm, c.primes[c.pid_special(kk)].q % ql, ql);
+  }
+  std::vector<uint32_t> gs(h.g, h.g + h.A * k);
+  std::sort(gs.begin(), gs.end());
+  const double distinct_keys = (double)(std::unique(gs.begin(), gs.end()) - gs.begin());
+  // distinct words: the keys once over the extended limbs, the digits and
+  // query limbs once, the masks once, both outputs and the addends
+  Prof pf(c, "k_kip_hoist_mask<" + std::to_string(tb.beta) + ">",
+          8.0 * (distinct_keys * 2 * tb.beta * tb.ext * c.N + (double)c.N * tb.ext * nq * tb.beta +
+                 2.0 * c.N * limbs * nq + (double)k * ml * c.N + 2.0 * c.N * tb.ext * E + 2.0 * c.N * limbs * E),
+          2.0 * c.N * tb.ext * E * h.A * (tb.beta + 1) + (double)c.N * limbs * E * (h.A + 2));
+  const size_t gx = (c.N + TPB - 1) / TPB;
+  const size_t WA = gx * limbs * E, WB = gx * tb.ext * E;
+  if (WA + WB > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: masked kip grid");
+#define KIP_MASK(BETA)                                                                                          \
+  LAUNCH(k_kip_hoist_mask<BETA>, dim3((unsigned)(WA + WB)), dim3(TPB), 0, c.stream, y, sy, x, sx, xcs, gtab, h, \
+         masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n,        \
+         c.ci ? 2 : 1, E, k, (int)WA, dadd ? 1 : 0, (double)pm)
+  switch (tb.beta) {
+    case 1: KIP_MASK(1); break;
+    case 2: KIP_MASK(2); break;
+    case 3: KIP_MASK(3); break;
+    default: KIP_MASK(4); break;
+  }
+#undef KIP_MASK
   check_launch();
 }
 

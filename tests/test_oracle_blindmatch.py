@@ -380,6 +380,47 @@ def test_hoisted_rotation_sum_single_amount_is_a_rotation(tiny_setup):
     assert np.max(np.abs(zh - zp)) < 1e-9
 
 
+def test_masked_rotation_sum_with_unit_plaintext_is_the_hoisted_sum(tiny_setup):
+    """With the plaintext 1 every mask product is the identity, so the masked
+    sum must return the words of the (separately pinned) hoisted rotation sum
+    exactly: a dropped term, a wrong automorphism or a mask read on the wrong
+    primes breaks the equality."""
+    P, keys = tiny_setup
+    rng = np.random.default_rng(12)
+    z = rng.standard_normal(P.n)
+    x = ckks.encrypt(P, keys.pk, ckks.encode(z, P.scale, P.N), 5, P.scale, 4, 3)
+    amounts = sorted(bm.rotations_needed(P, 8, 2))[:2]
+    one = np.zeros(P.N, dtype=np.int64)
+    one[0] = 1
+    m = ckks.rotation_sum_masked(P, x, one, 1.0, amounts, keys.gks)
+    h = ckks.rotation_sum_hoisted(P, x, amounts, keys.gks)
+    assert m.limbs == h.limbs and m.scale == h.scale
+    assert all(np.array_equal(a, b) for a, b in zip(m.c, h.c))
+
+
+def test_masked_rotation_sum_is_mask_then_rotations(tiny_setup):
+    """Slots: pt z + sum_r Rot(pt z, r); the same message as Mul(P) followed
+    by plain rotations, within the key-switch error."""
+    P, keys = tiny_setup
+    rng = np.random.default_rng(13)
+    z = rng.standard_normal(P.n)
+    mslots = (rng.random(P.n) < 0.5).astype(np.float64)
+    x = ckks.encrypt(P, keys.pk, ckks.encode(z, P.scale, P.N), 5, P.scale, 4, 4)
+    qtop = float(P.q[4])
+    pt = ckks.encode(mslots, qtop, P.N)
+    amounts = sorted(bm.rotations_needed(P, 8, 2))[:2]
+    m = ckks.rotation_sum_masked(P, x, pt, qtop, amounts, keys.gks)
+    want = mslots * z
+    for r in amounts:
+        want = want + np.roll(mslots * z, -r)
+    assert np.max(np.abs(ckks.decrypt_decode(P, keys.s, m) - want)) < 1e-9
+    plain = ckks.pmul(P, x, pt, qtop)
+    acc = plain
+    for r in amounts:
+        acc = ckks.hadd(P, acc, ckks.rotate(P, plain, r, keys.gks))
+    assert np.max(np.abs(ckks.decrypt_decode(P, keys.s, m) - ckks.decrypt_decode(P, keys.s, acc))) < 1e-9
+
+
 @pytest.mark.parametrize("d,k,schedule", [(8, 1, bm.S1), (8, 2, bm.S2), (16, 4, bm.S2), (32, 1, bm.S2)])
 def test_hoisted_match_equals_slot_sim(tiny_setup, d, k, schedule):
     """Hoisted schedule: the rotate-and-sum as one hoisted sum of the c - 1
