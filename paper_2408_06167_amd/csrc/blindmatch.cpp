@@ -144,18 +144,21 @@ void expand_batch(Ctx& c, const bm_evk* evk, const u64* q, size_t qs, size_t qcs
     // every query's c1, the key inner products of all parts' amounts with
     // each mask applied to them over Q_l u P, one ModDown and Res per part
     // (the amounts depend on the part only: list i serves every query)
-    std::vector<std::vector<long>> amounts;
-    for (u32 i = 0; i < k; ++i) amounts.push_back(expansion_amounts(d, k, i));
+    std::vector<std::vector<uint32_t>> parts(k);
     std::vector<const u64*> keys;
-    const std::vector<HoistArgs> hs = hoist_args(c, evk, amounts, true, keys);
-    if (hs.size() != 1) BM_THROW(BM_EINVAL, "too many hoisted expansion rotations");
+    for (u32 i = 0; i < k; ++i)
+      for (long r : expansion_amounts(d, k, i)) {
+        const u64 g = ev::galois_for_rotation(c, r);
+        keys.push_back(galois_key(evk, g));                 // BM_ENOKEY when missing
+        parts[i].push_back((uint32_t)g);
+      }
     const ModUpTable& tb = c.h_modup[l];
     const size_t sy = (size_t)tb.beta * tb.ext * N, suw = (size_t)2 * tb.ext * N;
     DBuf y = ev::modup_eval(c, q + qcs, qs, nq, l);
     DBuf uw(&c, (size_t)E * suw), ad(&c, (size_t)E * 2 * ln);
     const bool fused = kern::fused_ok(c);
-    kern::kip_hoist_mask(c, y.p(), sy, q, qs, qcs, (const u64* const*)evk->gtab.p(), hs[0], keys, masks, uw.p(),
-                         suw, ad.p(), 2 * ln, nq, (int)k, l, fused);
+    kern::kip_hoist_mask(c, y.p(), sy, q, qs, qcs, (const u64* const*)evk->gtab.p(), parts, keys, masks, uw.p(),
+                         suw, ad.p(), 2 * ln, nq, l, fused);
     if (fused) {
       ev::moddown_rescale(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, out);
     } else {

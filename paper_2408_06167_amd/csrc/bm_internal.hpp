@@ -536,11 +536,12 @@ void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const
 // element e = j k + i (part i of query j at x + j sx, c1 at + xcs) the key
 // sums over Q_l u P to uw [E][2][l+K][N] (with dadd: P times the addends added
 // at the last chain limb) and the addends to ad [E][2][limbs][N]; masks
-// [k][L+1+K][N]; h.per_elem with one amount list per part (h.mod = k)
+// [k][L+1+K][N]; parts[i] lists part i's Galois elements (k = parts.size(),
+// every list of one length)
 void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
-                    const u64* const* gtab, const HoistArgs& h, const std::vector<const u64*>& keys,
-                    const u64* masks, u64* uw, size_t suw, u64* ad, size_t sad, int nq, int k, int limbs,
-                    bool dadd);
+                    const u64* const* gtab, const std::vector<std::vector<uint32_t>>& parts,
+                    const std::vector<const u64*>& keys, const u64* masks, u64* uw, size_t suw, u64* ad,
+                    size_t sad, int nq, int limbs, bool dadd);
 void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
                const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
                size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate);

@@ -1334,27 +1334,38 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 // Masked hoisted rotation sums (Alg. 1 with its rotations hoisted and the
 // masks applied after the key inner products).  Element e = j k + i is part i
 // of query j (x at x + j sx: c0, then c1 at + xcs, `limbs` limbs, evaluation
-// domain); list i of h (h.g[i A + a]) holds part i's amounts; mask i is at
-// masks + i ml N over every prime (ml limbs: the chain, then the specials).
+// domain); mask i is at masks + i ml N over every prime (ml limbs: the chain,
+// then the specials).  h.g lists the distinct amounts of all parts, u.parts[a]
+// the parts that use amount a (bit i), u.per[i * k1 + n] the n-th amount of
+// part i (k1 = k - 1 amounts a part).
 //   addends (the first WA blocks, limbs < `limbs`):
-//     ad[e][0] = sum over r in {0} u amounts of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1
+//     ad[e][0] = sum over r in {0} u amounts(i) of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1
 //   key sums (the other blocks, every slot t of Q_l u P):
-//     uw[e][c] = sum_a phi_a(mask_i) * sum_d phi_a(y_d[j]) key_{a,d,c}
+//     uw[e][c] = sum over a in amounts(i) of phi_a(mask_i) * sum_d phi_a(y_d[j]) key_{a,d,c}
 //   and, with dadd, P ad[e][c] added at the last chain slot (the form the
 //   fused ModDown and rescale take).
-// One thread per word; the gathers read phi_a(v)[pos] = v[autom_src(pos)].
-template <int BETA>
+// A key-sum thread serves one word of one slot for PG parts of one query: the
+// inner sum of each amount is formed once and multiplied into every part of
+// the group that uses it.  The gathers read phi_a(v)[pos] = v[autom_src(pos)].
+struct MaskUse {
+  uint16_t parts[HOIST_MAX];
+  uint16_t per[HOIST_MAX];
+};
+
+template <int BETA, int PG>
 __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
-                                 const u64* const* gtab, HoistArgs h, const u64* masks, int ml, u64* uw,
-                                 size_t suw, u64* ad, size_t sad, const ModUpTable* T, int key_limbs, int L1,
-                                 const PrimeC* P, int log_n, int ms, int E, int k, int WA, int dadd, double pmd) {
+                                 const u64* const* gtab, HoistArgs h, MaskUse mu, const u64* masks, int ml,
+                                 u64* uw, size_t suw, u64* ad, size_t sad, const ModUpTable* T, int key_limbs,
+                                 int L1, const PrimeC* P, int log_n, int ms, int nq, int k, int WA, int dadd,
+                                 double pmd) {
   const int N = 1 << log_n;
   const int gx = (N + TPB - 1) / TPB;
   const ModUpTable& tb = *T;
   const int limbs = tb.limbs;
-  // sum over r in {0} u amounts of mask_i[s_r] x0[s_r] at limb t, and mask_i x1
-  // at pos, as exact residues (every product within 1.25 q, folded every
-  // second one)
+  const int k1 = k - 1;
+  // sum over r in {0} u amounts(i) of mask_i[s_r] x0[s_r] at limb t, and
+  // mask_i x1 at pos, as exact residues (every product within 1.25 q, folded
+  // every second one)
   auto addends = [&](int e, int t, int pos, u64& a0, u64& a1) {
     const int j = e / k, i = e % k;
     const PrimeC& pr = P[t];
@@ -1363,10 +1374,10 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     const u64* X0 = x + (size_t)j * sx + (size_t)t * N;
     const u64* X1 = X0 + xcs;
     double s = fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X0[pos]), qi, q);
-    for (int a = 0; a < h.A; ++a) {
-      const u32 src = autom_src((u32)pos, h.g[i * h.A + a], log_n, ms);
+    for (int n = 0; n < k1; ++n) {
+      const u32 src = autom_src((u32)pos, h.g[mu.per[i * k1 + n]], log_n, ms);
       s = __dadd_rn(s, fmul_mod_q(u64_to_f(M[src]), u64_to_f(X0[src]), qi, q));
-      if (a & 1) s = fred(s, qi, q);
+      if (n & 1) s = fred(s, qi, q);
     }
     double r = fred(s, qi, q);
     a0 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
@@ -1378,7 +1389,7 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     const int pos = (lb % gx) * TPB + threadIdx.x;
     const int t = (lb / gx) % limbs;
     const int e = lb / (gx * limbs);
-    if (pos >= N || e >= E) return;
+    if (pos >= N || e >= nq * k) return;
     u64 a0, a1;
     addends(e, t, pos, a0, a1);
     u64* A0 = ad + (size_t)e * sad + (size_t)t * N;
@@ -1387,22 +1398,22 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     return;
   }
   const int ext = tb.ext;
-  // (element, position block, slot), element fastest: the blocks of one slot
-  // and position block share their key words through L2
+  const int ngr = (k + PG - 1) / PG;                          // part groups of a query
+  // (query and part group, position block, slot), the first fastest: the
+  // blocks of one slot and position block share their key words through L2
   const int lb = (int)blockIdx.x - WA;
-  const int e = lb % E;
-  const int pb = (lb / E) % gx;
-  const int t = lb / (E * gx);
+  const int jg = lb % (nq * ngr);
+  const int pb = (lb / (nq * ngr)) % gx;
+  const int t = lb / (nq * ngr * gx);
+  const int j = jg / ngr, i0 = (jg % ngr) * PG;
   const int pos = pb * TPB + threadIdx.x;
-  const int j = e / k, i = e % k;
   __shared__ const u64* kp[HOIST_MAX];
-  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[i * h.A + a] >> 1];
+  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
   __syncthreads();
   if (pos >= N || t >= ext) return;
   const PrimeC& pr = P[tb.ext_prime[t]];
   const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
   const int kl = t < limbs ? t : L1 + (t - limbs);          // key limb (and mask limb) of slot t
-  const u64* M = masks + ((size_t)i * ml + kl) * N;
   const u64* src[BETA];
   bool own[BETA];
 #pragma unroll
@@ -1412,45 +1423,86 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     src[d] = own[d] ? x + (size_t)j * sx + xcs + (size_t)t * N : y + (size_t)j * sy + ((size_t)d * ext + t) * N;
   }
   const size_t ko = (size_t)kl * N + pos, kst = (size_t)key_limbs * N;
-  double su = 0.0, sw = 0.0;
-  for (int a = 0; a < h.A; ++a) {
-    const u32 s = autom_src((u32)pos, h.g[i * h.A + a], log_n, ms);
-    const double* key = (const double*)kp[a];
-    double iu = 0.0, iw = 0.0;
+  const unsigned gmask = ((1u << PG) - 1) << i0;
+  double su[PG], sw[PG];
 #pragma unroll
-    for (int d = 0; d < BETA; ++d) {
-      const u64 wv = src[d][s];
-      const double v = own[d] ? u64_to_f(wv) : __longlong_as_double((long long)wv);
-      iu = __dadd_rn(iu, fmul_mod_q(v, key[ko + (size_t)(2 * d) * kst], qi, q));
-      iw = __dadd_rn(iw, fmul_mod_q(v, key[ko + (size_t)(2 * d + 1) * kst], qi, q));
-      if (d & 1) {
-        iu = fred(iu, qi, q);
-        iw = fred(iw, qi, q);
+  for (int p = 0; p < PG; ++p) su[p] = sw[p] = 0.0;
+  // two amounts at a time, every word of both requested before the first
+  // product (a ragged pair repeats the last amount, unused)
+  for (int a0 = 0; a0 < h.A; a0 += 2) {
+    unsigned use[2];
+    u64 v[2][BETA], mw[2][PG];
+    double kb[2][BETA], ka[2][BETA];
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      const int a = a0 + c2 < h.A ? a0 + c2 : h.A - 1;
+      use[c2] = a0 + c2 < h.A ? (unsigned)mu.parts[a] & gmask : 0u;
+      const u32 s = autom_src((u32)pos, h.g[a], log_n, ms);
+      const double* key = (const double*)kp[a];
+#pragma unroll
+      for (int d = 0; d < BETA; ++d) {
+        v[c2][d] = src[d][s];
+        kb[c2][d] = key[ko + (size_t)(2 * d) * kst];
+        ka[c2][d] = key[ko + (size_t)(2 * d + 1) * kst];
+      }
+#pragma unroll
+      for (int p = 0; p < PG; ++p) mw[c2][p] = masks[((size_t)(i0 + p < k ? i0 + p : 0) * ml + kl) * N + s];
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+      if (!use[c2]) continue;
+      double iu = 0.0, iw = 0.0;
+#pragma unroll
+      for (int d = 0; d < BETA; ++d) {
+        const double vd = own[d] ? u64_to_f(v[c2][d]) : __longlong_as_double((long long)v[c2][d]);
+        iu = __dadd_rn(iu, fmul_mod_q(vd, kb[c2][d], qi, q));
+        iw = __dadd_rn(iw, fmul_mod_q(vd, ka[c2][d], qi, q));
+        if (d & 1) {
+          iu = fred(iu, qi, q);
+          iw = fred(iw, qi, q);
+        }
+      }
+      // the mask words multiply the reduced inner sums (|.| <= q/2 + 1)
+      iu = fred(iu, qi, q);
+      iw = fred(iw, qi, q);
+#pragma unroll
+      for (int p = 0; p < PG; ++p) {
+        if ((use[c2] >> (i0 + p)) & 1) {
+          const double m = u64_to_f(mw[c2][p]);
+          su[p] = __dadd_rn(su[p], fmul_mod_q(iu, m, qi, q));
+          sw[p] = __dadd_rn(sw[p], fmul_mod_q(iw, m, qi, q));
+        }
       }
     }
-    // the mask word multiplies the reduced inner sums (|.| <= q/2 + 1)
-    const double mw = u64_to_f(M[s]);
-    su = __dadd_rn(su, fmul_mod_q(fred(iu, qi, q), mw, qi, q));
-    sw = __dadd_rn(sw, fmul_mod_q(fred(iw, qi, q), mw, qi, q));
-    if (a & 1) {
-      su = fred(su, qi, q);
-      sw = fred(sw, qi, q);
+    // at most one product a part per amount: every part's sums folded after
+    // every pair of amounts
+#pragma unroll
+    for (int p = 0; p < PG; ++p) {
+      su[p] = fred(su[p], qi, q);
+      sw[p] = fred(sw[p], qi, q);
     }
-  }
-  if (dadd && t == limbs - 1) {
-    u64 a0, a1;
-    addends(e, t, pos, a0, a1);
-    const double pmq = pmd / q;
-    su = __dadd_rn(fred(su, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
-    sw = __dadd_rn(fred(sw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
   }
   auto res = [&](double v) {
     const double r = fred(v, qi, q);
     return f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
   };
-  u64* U = uw + (size_t)e * suw + (size_t)t * N;
-  U[pos] = res(su);
-  U[(size_t)ext * N + pos] = res(sw);
+#pragma unroll
+  for (int p = 0; p < PG; ++p) {
+    const int i = i0 + p;
+    if (i >= k) break;
+    const int e = j * k + i;
+    double vu = su[p], vw = sw[p];
+    if (dadd && t == limbs - 1) {
+      u64 a0, a1;
+      addends(e, t, pos, a0, a1);
+      const double pmq = pmd / q;
+      vu = __dadd_rn(fred(vu, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
+      vw = __dadd_rn(fred(vw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
+    }
+    u64* U = uw + (size_t)e * suw + (size_t)t * N;
+    U[pos] = res(vu);
+    U[(size_t)ext * N + pos] = res(vw);
+  }
 }
 
 // The same sums when every element uses the same amounts: one thread serves
@@ -2285,14 +2337,30 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
 }
 
 void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
-                    const u64* const* gtab, const HoistArgs& h, const std::vector<const u64*>& keys,
-                    const u64* masks, u64* uw, size_t suw, u64* ad, size_t sad, int nq, int k, int limbs,
-                    bool dadd) {
+                    const u64* const* gtab, const std::vector<std::vector<uint32_t>>& parts,
+                    const std::vector<const u64*>& keys, const u64* masks, u64* uw, size_t suw, u64* ad,
+                    size_t sad, int nq, int limbs, bool dadd) {
   const ModUpTable& tb = c.h_modup[limbs];
+  const int k = (int)parts.size();
   if (limbs < 2 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: masked kip level");
-  if (nq < 1 || k < 2 || !h.per_elem || h.mod != k || h.A < 1 || h.A * k > HOIST_MAX)
-    BM_THROW(BM_EINVAL, "launch check: masked kip amounts");
+  if (nq < 1 || k < 2 || k > 16) BM_THROW(BM_EINVAL, "launch check: masked kip parts");
   if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the masked kip");
+  // distinct Galois elements, the parts that use each, and each part's list
+  HoistArgs h{};
+  MaskUse mu{};
+  const size_t k1 = parts[0].size();
+  if (k1 < 1 || (size_t)k * k1 > HOIST_MAX) BM_THROW(BM_EINVAL, "launch check: masked kip amounts");
+  for (int i = 0; i < k; ++i) {
+    if (parts[i].size() != k1) BM_THROW(BM_EINVAL, "launch check: masked kip amount lists");
+    for (size_t n = 0; n < k1; ++n) {
+      const uint32_t g = parts[i][n];
+      int a = 0;
+      while (a < h.A && h.g[a] != g) ++a;
+      if (a == h.A) h.g[h.A++] = g;
+      mu.parts[a] = (uint16_t)(mu.parts[a] | (1u << i));
+      mu.per[(size_t)i * k1 + n] = (uint16_t)a;
+    }
+  }
   const int E = nq * k, ml = c.L + 1 + c.K;
   chk(y, nq, sy, 0, (size_t)tb.beta * tb.ext * c.N, "masked kip digits");
   chk(x, nq, sx, 0, xcs + (size_t)limbs * c.N, "masked kip input");
@@ -2307,27 +2375,29 @@ void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
     pm = 1;
     for (int kk = 0; kk < c.K; ++kk) pm = h_mulmod(pm, c.primes[c.pid_special(kk)].q % ql, ql);
   }
-  std::vector<uint32_t> gs(h.g, h.g + h.A * k);
-  std::sort(gs.begin(), gs.end());
-  const double distinct_keys = (double)(std::unique(gs.begin(), gs.end()) - gs.begin());
   // distinct words: the keys once over the extended limbs, the digits and
   // query limbs once, the masks once, both outputs and the addends
-  Prof pf(c, "k_kip_hoist_mask<" + std::to_string(tb.beta) + ">",
-          8.0 * (distinct_keys * 2 * tb.beta * tb.ext * c.N + (double)c.N * tb.ext * nq * tb.beta +
+  const int PG = k == 2 ? 2 : 4, ngr = (k + PG - 1) / PG;
+  Prof pf(c, "k_kip_hoist_mask<" + std::to_string(tb.beta) + ", " + std::to_string(PG) + ">",
+          8.0 * ((double)h.A * 2 * tb.beta * tb.ext * c.N + (double)c.N * tb.ext * nq * tb.beta +
                  2.0 * c.N * limbs * nq + (double)k * ml * c.N + 2.0 * c.N * tb.ext * E + 2.0 * c.N * limbs * E),
-          2.0 * c.N * tb.ext * E * h.A * (tb.beta + 1) + (double)c.N * limbs * E * (h.A + 2));
+          2.0 * c.N * tb.ext * nq * ((double)h.A * tb.beta + (double)k * k1) + (double)c.N * limbs * E * (k1 + 2));
   const size_t gx = (c.N + TPB - 1) / TPB;
-  const size_t WA = gx * limbs * E, WB = gx * tb.ext * E;
+  const size_t WA = gx * limbs * E, WB = gx * tb.ext * (size_t)nq * ngr;
   if (WA + WB > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: masked kip grid");
-#define KIP_MASK(BETA)                                                                                          \
-  LAUNCH(k_kip_hoist_mask<BETA>, dim3((unsigned)(WA + WB)), dim3(TPB), 0, c.stream, y, sy, x, sx, xcs, gtab, h, \
-         masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n,        \
-         c.ci ? 2 : 1, E, k, (int)WA, dadd ? 1 : 0, (double)pm)
-  switch (tb.beta) {
-    case 1: KIP_MASK(1); break;
-    case 2: KIP_MASK(2); break;
-    case 3: KIP_MASK(3); break;
-    default: KIP_MASK(4); break;
+#define KIP_MASK(BETA, PGV)                                                                                        \
+  LAUNCH((k_kip_hoist_mask<BETA, PGV>), dim3((unsigned)(WA + WB)), dim3(TPB), 0, c.stream, y, sy, x, sx, xcs, gtab, \
+         h, mu, masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n,      \
+         c.ci ? 2 : 1, nq, k, (int)WA, dadd ? 1 : 0, (double)pm)
+  switch (tb.beta * 10 + PG) {
+    case 12: KIP_MASK(1, 2); break;
+    case 14: KIP_MASK(1, 4); break;
+    case 22: KIP_MASK(2, 2); break;
+    case 24: KIP_MASK(2, 4); break;
+    case 32: KIP_MASK(3, 2); break;
+    case 34: KIP_MASK(3, 4); break;
+    case 42: KIP_MASK(4, 2); break;
+    default: KIP_MASK(4, 4); break;
   }
 #undef KIP_MASK
   check_launch();
