@@ -1384,12 +1384,19 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     r = fred(fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X1[pos]), qi, q), qi, q);
     a1 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
   };
+  // Both parts take (position block, ..., ...) with the position block
+  // slowest and the logical blocks dealt to the 8 XCDs in contiguous ranges
+  // (xcd_block, when the part's block count is a multiple of 8): an aligned
+  // eighth of the positions gathers only from the same eighth of every limb
+  // under any automorphism, so each XCD's L2 holds its own eighth of the
+  // digits, masks and query limbs instead of all of them.
+  const int nA = nq * k;
   if ((int)blockIdx.x < WA) {
-    const int lb = blockIdx.x;
-    const int pos = (lb % gx) * TPB + threadIdx.x;
-    const int t = (lb / gx) % limbs;
-    const int e = lb / (gx * limbs);
-    if (pos >= N || e >= nq * k) return;
+    const int lb = WA % 8 == 0 ? xcd_block((int)blockIdx.x, WA) : (int)blockIdx.x;
+    const int e = lb % nA;
+    const int t = (lb / nA) % limbs;
+    const int pos = (lb / (nA * limbs)) * TPB + threadIdx.x;
+    if (pos >= N) return;
     u64 a0, a1;
     addends(e, t, pos, a0, a1);
     u64* A0 = ad + (size_t)e * sad + (size_t)t * N;
@@ -1399,12 +1406,13 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   }
   const int ext = tb.ext;
   const int ngr = (k + PG - 1) / PG;                          // part groups of a query
-  // (query and part group, position block, slot), the first fastest: the
-  // blocks of one slot and position block share their key words through L2
-  const int lb = (int)blockIdx.x - WA;
+  // (position block, slot, query and part group): the blocks of one position
+  // block and slot, next to each other, share their key words through L2
+  const int WB = (int)gridDim.x - WA;
+  const int lb = WB % 8 == 0 ? xcd_block((int)blockIdx.x - WA, WB) : (int)blockIdx.x - WA;
   const int jg = lb % (nq * ngr);
-  const int pb = (lb / (nq * ngr)) % gx;
-  const int t = lb / (nq * ngr * gx);
+  const int t = (lb / (nq * ngr)) % ext;
+  const int pb = lb / (nq * ngr * ext);
   const int j = jg / ngr, i0 = (jg % ngr) * PG;
   const int pos = pb * TPB + threadIdx.x;
   __shared__ const u64* kp[HOIST_MAX];
