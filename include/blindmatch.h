@@ -423,9 +423,9 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * kip_order: block order of that key inner product, 0 (the element groups of
  * a position block side by side: they share its key words through the
  * memory-side cache) or 1 (the position blocks of an element group side by
- * side: its gathered digit words stay in cache).  fused_occupancy: 0, or 4 to
- * build the fused base-conversion column passes of the N = 2^16 transforms
- * for four resident blocks per compute unit.  Matches captured as graphs
+ * side: its gathered digit words stay in cache).  fused_occupancy: 0, or 3 or 4
+ * to build the fused base-conversion column passes of the N = 2^16
+ * transforms for that many resident blocks per compute unit.  Matches captured as graphs
  * keep the knobs they were captured with. */
 typedef struct {
   uint32_t group_chunk;

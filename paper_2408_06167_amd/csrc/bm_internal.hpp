@@ -197,6 +197,7 @@ struct FuseArgs {
   int last_off = -1;             // pro 4: limb offset (in a source component) of the last chain limb
   int last_pid = -1;             // pro 4: its prime
   const u64* wmtab = nullptr;    // epi 2: minuend multipliers
+  int no_row = 0;                // 1: the column pass only (its words left in tmp)
   int isrc = 0;                  // 1: sources still need their inverse column pass
   const double* itwf = nullptr;  // isrc: inverse twiddles and their quotients w / q
   const double* itwq = nullptr;
@@ -532,6 +533,13 @@ void move_idx(const Ctx& c, const u64* in, size_t si, u64* out, size_t so, const
 // launch computes c0_out[z] = c0_in[z] + sum_a phi_{g(z,a)}(c0_in[z]) over
 // `limbs` limbs (accumulate: both outputs are added to; c0_out must not alias
 // c0_in).
+// key inner product of a plain key switch on whole rows (k_kip_rows, N = 2^16,
+// standard ring): y holds the ModUp column pass's words (u64, pair slots), the
+// row pass of the digits, the products and (slots >= inv_from) the row pass of
+// the inverse transform in one launch; otherwise as kip
+void kip_rows(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
+              const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs, int inv_from,
+              const u64* dadd = nullptr, size_t sd = 0, size_t dcs = 0);
 // masked hoisted rotation sums of Alg. 1's parts (k_kip_hoist_mask): per
 // element e = j k + i (part i of query j at x + j sx, c1 at + xcs) the key
 // sums over Q_l u P to uw [E][2][l+K][N] (with dadd: P times the addends added

@@ -1457,7 +1457,8 @@ int bm_ctx_set_tuning(bm_ctx* ctx, const bm_tuning* t) {
     REQUIRE(t->ntt_row_views == 0 || t->ntt_row_views == 4 || t->ntt_row_views == 8 || t->ntt_row_views == 16,
             BM_EINVAL, "ntt_row_views: 0, 4, 8 or 16");
     REQUIRE(t->kip_order <= 1, BM_EINVAL, "kip_order: 0 or 1");
-    REQUIRE(t->fused_occupancy == 0 || t->fused_occupancy == 4, BM_EINVAL, "fused_occupancy: 0 or 4");
+    REQUIRE(t->fused_occupancy == 0 || t->fused_occupancy == 3 || t->fused_occupancy == 4, BM_EINVAL,
+            "fused_occupancy: 0, 3 or 4");
     Ctx& c = ctx->c;
     c.group_chunk = (int)t->group_chunk;
     c.kip_variant = (int)t->kip_variant;
@@ -1551,7 +1552,7 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       (void)timed(bsched);
       const std::vector<u64> ref = words();
       int* knob[5] = {&c.group_chunk, &c.kip_variant, &c.kip_order, &c.ntt_views, &c.fused_occ};
-      const std::vector<int> values[5] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 4}};
+      const std::vector<int> values[5] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 3, 4}};
       for (int kn = 0; kn < 5; ++kn) {
         int pick = *knob[kn];
         for (int v : values[kn]) {

@@ -344,7 +344,11 @@ static void set_isrc(const Ctx& c, FuseArgs& f, bool on) {
 // ModUp of every digit of x (evaluation domain) to the extended basis, back
 // in evaluation form: y [B][beta][ext][N] (the digit's own slots unused), the
 // residues held as FP64 values for the key inner products.
-DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
+// the key inner product on whole rows (k_kip_rows) serves the plain key
+// switches where the fused transforms finish inverse column passes
+static bool kip_rows_ok(const Ctx& c) { return kern::isrc_ok(c, 1) && kern::isrc_ok(c, 2) && kern::isrc_ok(c, 4); }
+
+DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs, bool col_only) {
   const size_t N = c.N;
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext, beta = tb.beta;
@@ -372,10 +376,12 @@ DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
     f.mu = c.d_modup + limbs;
     f.src = xc.p();
     f.s_hi = (size_t)limbs * N;
+    f.no_row = col_only ? 1 : 0;
     set_isrc(c, f, is);
     audit::check(xc.p(), (size_t)B * limbs * N * sizeof(u64), "fused modup source");
     kern::ntt_fused(c, f, y.p(), sy, B, m, true);
   } else {
+    if (col_only) BM_THROW(BM_EINVAL, "column-pass ModUp needs the fused transforms");
     kern::modup(c, xc.p(), (size_t)limbs * N, y.p(), sy, B, limbs);
     kern::ntt(c, y.p(), sy, y.p(), sy, B, m, false);
     kern::words_f64(c, y.p(), (size_t)B * sy, true);
@@ -386,7 +392,7 @@ DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs) {
 // ModDown of (u, w) [B][2][ext][N] over Q_l u P plus the addends:
 // out = (add0 + ModDown(u), add1 + ModDown(w))
 void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
-                        size_t sa1, u64* out, size_t so) {
+                        size_t sa1, u64* out, size_t so, bool rows_done) {
   const size_t N = c.N;
   const int ext = c.h_modup[limbs].ext;
   const size_t suw = (size_t)2 * ext * N;
@@ -398,10 +404,14 @@ void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0,
       ++mp.n;
     }
   const bool is = kern::isrc_ok(c, 2);
-  if (is)
+  if (rows_done && !is) BM_THROW(BM_EINVAL, "special limbs after their inverse row pass need the fused transforms");
+  if (rows_done) {
+    // the key inner product ran the inverse row pass of the special limbs
+  } else if (is) {
     kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
-  else
+  } else {
     kern::ntt(c, uw, suw, uw, suw, B, mp, true, kern::fused_ok(c));
+  }
   const size_t sc = (size_t)2 * limbs * N;
   DBuf conv(&c, (size_t)B * sc);
   if (kern::fused_ok(c)) {           // conversion and finish inside the forward transform
@@ -441,10 +451,14 @@ void key_switch2(Ctx& c, const u64* x, size_t sx, int B, int limbs, const u64* k
                  int sel, const u64* add0, size_t sa0, const u64* add1, size_t sa1, u64* out, size_t so) {
   const ModUpTable& tb = c.h_modup[limbs];
   const size_t sy = (size_t)tb.beta * tb.ext * c.N, suw = (size_t)2 * tb.ext * c.N;
-  DBuf y = modup_eval(c, x, sx, B, limbs);
+  const bool rows = kip_rows_ok(c);
+  DBuf y = modup_eval(c, x, sx, B, limbs, rows);
   DBuf uw(&c, (size_t)B * suw);
-  kern::kip(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs);
-  moddown_add(c, uw.p(), B, limbs, add0, sa0, add1, sa1, out, so);
+  if (rows)   // digits' row pass, products and the special limbs' inverse row pass in one launch
+    kern::kip_rows(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs, limbs);
+  else
+    kern::kip(c, y.p(), sy, x, sx, key0, key1, sel, uw.p(), suw, B, limbs);
+  moddown_add(c, uw.p(), B, limbs, add0, sa0, add1, sa1, out, so, rows);
 }
 
 void rotation_sum_hoisted(Ctx& c, const bm_evk* evk, const u64* in, int B, int limbs,
@@ -487,10 +501,14 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
   const ModUpTable& tb = c.h_modup[limbs];
   const int ext = tb.ext;
   const size_t sy = (size_t)tb.beta * ext * N, suw = (size_t)2 * ext * N;
-  DBuf y = modup_eval(c, d + 2 * ln, 3 * ln, B, limbs);
+  const bool rows = kip_rows_ok(c);
+  DBuf y = modup_eval(c, d + 2 * ln, 3 * ln, B, limbs, rows);
   DBuf uw(&c, (size_t)B * suw);
-  kern::kip(c, y.p(), sy, d + 2 * ln, 3 * ln, rlk, rlk, 31, uw.p(), suw, B, limbs, d, 3 * ln, ln);
-  moddown_rescale(c, uw.p(), B, limbs, d, 3 * ln, d + ln, 3 * ln, out);
+  if (rows)   // the last chain limb and the special limbs leave in their inverse row pass
+    kern::kip_rows(c, y.p(), sy, d + 2 * ln, 3 * ln, rlk, rlk, 31, uw.p(), suw, B, limbs, limbs - 1, d, 3 * ln, ln);
+  else
+    kern::kip(c, y.p(), sy, d + 2 * ln, 3 * ln, rlk, rlk, 31, uw.p(), suw, B, limbs, d, 3 * ln, ln);
+  moddown_rescale(c, uw.p(), B, limbs, d, 3 * ln, d + ln, 3 * ln, out, rows);
 }
 
 // (add0 + ModDown(u), add1 + ModDown(w)) rescaled, with the words of
@@ -498,7 +516,7 @@ void relin_rescale(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* 
 // at the last chain limb (see relin_rescale), the addends are read at their
 // first limbs - 1 limbs, out [B][2][limbs-1][N].
 void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
-                     size_t sa1, u64* out) {
+                     size_t sa1, u64* out, bool rows_done) {
   const size_t N = c.N;
   const int nl = limbs - 1;
   const ModUpTable& tb = c.h_modup[limbs];
@@ -516,10 +534,14 @@ void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t 
     }
   }
   const bool is = kern::isrc_ok(c, 4);
-  if (is)
+  if (rows_done && !is) BM_THROW(BM_EINVAL, "limbs after their inverse row pass need the fused transforms");
+  if (rows_done) {
+    // the key inner product ran the inverse row pass of these limbs
+  } else if (is) {
     kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
-  else
+  } else {
     kern::ntt(c, uw, suw, uw, suw, B, mp, true, true);   // unfolded on the fly (conjugate-invariant ring)
+  }
   DBuf t(&c, (size_t)B * 2 * nl * N);
   FuseArgs f;
   f.pro = 4;

@@ -29,16 +29,20 @@ void rescale(Ctx& c, const u64* in, int B, int comps, int limbs, u64* out);
 // ModUp of every digit of x ([B][limbs][N], stride sx, evaluation domain) to
 // Q_l u P, back in the evaluation domain as FP64 values: [B][beta][l+K][N]
 // (a digit's own slots unused)
-DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs);
+// (col_only: the fused transform's column pass only, its u64 words left at
+// the pair slots for kern::kip_rows)
+DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs, bool col_only = false);
 // ModDown of (u, w) [B][2][l+K][N] over Q_l u P plus the addends:
 // out = (add0 + ModDown(u), add1 + ModDown(w)), [B][2][limbs][N] at stride so
+// (rows_done: the special limbs already hold the row pass of their inverse
+// transform, left there by kern::kip_rows)
 void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1, size_t sa1,
-                 u64* out, size_t so);
+                 u64* out, size_t so, bool rows_done = false);
 // the same then rescaled, at N = 2^16 in one inverse row pass and one fused
 // transform: uw must hold u + P add0 and w + P add1 at the last chain limb;
 // out [B][2][limbs-1][N]
 void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0, const u64* add1,
-                     size_t sa1, u64* out);
+                     size_t sa1, u64* out, bool rows_done = false);
 // in: [B][2][limbs][N] -> out = Rot_g(in) (+ in when add_input)
 void rotate(Ctx& c, const u64* in, int B, int limbs, u64 g, const u64* key, u64* out, bool add_input);
 // batch element z rotates with (g1, key1) when bit `sel` of z is set, else (g0, key0)

@@ -43,6 +43,13 @@ __host__ __device__ __forceinline__ double fmul_mod_q(double a, double w, double
   return __builtin_fma(-qt, q, hi) + lo;
 }
 
+// Products of fmul_mod_q a running sum may take between folds: each lies
+// within 1.25 q of 0, within 0.875 q when q < 2^50 (the quotient error
+// 0.5 + 3 (a w / q) 2^-53 is then below 0.875), and the sum starts within
+// q/2 + 1 after a fold, so 2 products (q < 2^51: at most 3 q + 1) or 8
+// (q < 2^50: at most 7.5 q + 1 < 2^53) keep every partial sum exact.
+__host__ __device__ __forceinline__ int fold_period(double q) { return q < 1125899906842624.0 ? 8 : 2; }
+
 // a - rint(a fl(1/q)) q for |a| < 2^53: lies in [-q/2 - 1, q/2 + 1]
 __host__ __device__ __forceinline__ double fred(double a, double qi, double q) {
 #pragma clang fp contract(off)

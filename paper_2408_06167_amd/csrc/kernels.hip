@@ -446,17 +446,33 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
   // b = (hi << k) + jj (k = st - 4, jj < 2^k), so they are kept at
   // 2^st + jj * 16 + hi: consecutive lanes, consecutive words.
   if (LOGM == 8) {
-    // consecutive threads fill consecutive slots (conflict-free LDS writes)
-    for (int k = t; k < 256 * R; k += nthr) {
-      const int slot = k & 255, rr = k >> 8;
-      if (slot == 0) continue;
-      const int vb = KIND == NTT_ROW ? (int)blockIdx.x * R + rr : 0;
-      const int st = 31 - __clz(slot);
-      const int o = slot - (1 << st);
-      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
-      const int g = (1 << (s0 + st)) + (vb << st) + b;
-      tl[rr * 512 + slot] = W[g];
-      tl[rr * 512 + 256 + slot] = WQ[g];
+    // consecutive threads fill consecutive slots (conflict-free LDS writes);
+    // four slots a thread at a time, all eight words requested before the
+    // first is stored (a row pass of few polynomials stages up to 16 rows'
+    // twiddles per thread, and one round trip per slot would dominate it)
+    for (int k0 = t; k0 < 256 * R; k0 += 4 * nthr) {
+      double tw[4], twq[4];
+      int at[4];
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const int k = k0 + c4 * nthr;
+        const int slot = k & 255, rr = k >> 8;
+        at[c4] = k < 256 * R && slot != 0 ? rr * 512 + slot : -1;
+        const int vb = KIND == NTT_ROW ? (int)blockIdx.x * R + rr : 0;
+        const int st = 31 - __clz(slot | 1);
+        const int o = slot - (1 << st);
+        const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+        const int g = (1 << (s0 + st)) + (vb << st) + b;
+        tw[c4] = at[c4] >= 0 ? W[g] : 0.0;
+        twq[c4] = at[c4] >= 0 ? WQ[g] : 0.0;
+      }
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        if (at[c4] >= 0) {
+          tl[at[c4]] = tw[c4];
+          tl[at[c4] + 256] = twq[c4];
+        }
+      }
     }
     if constexpr (IS) {
       // the inverse twiddles of every source prime, [a][2][256] after the
@@ -1180,6 +1196,175 @@ __global__ void k_kip(const u64* y, size_t sy, const u64* x, size_t sx, const u6
   }
 }
 
+// The key inner product of a plain key switch at N = 2^16 on whole rows:
+// block (row block, slot t, element block) takes R consecutive rows of vz
+// elements (16 lanes a row, 16 words a lane) and, for every digit, either
+// reads the input limb (the digit's own slots, evaluation domain) or finishes
+// the digit's forward transform here: the row pass over the column-pass words
+// the fused ModUp column pass left in y (u64, slot j ext + t).  Then
+//   u[t] = sum_j y_j[t] b_j,  w[t] = sum_j y_j[t] a_j   (+ P d at the last chain
+//   limb with dadd, as k_kip),
+// and the slots from inv_from on (those the ModDown, or ModDown and rescale,
+// transform back) get the row pass of their inverse transform before they are
+// stored; the others are stored in the evaluation domain.  Same operations
+// as the row pass, k_kip and the inverse row pass one after the other, so the
+// same words.
+__global__ void __launch_bounds__(256) k_kip_rows(const u64* y, size_t sy, const u64* x, size_t sx,
+                                                  const u64* key0, const u64* key1, int sel, u64* uw, size_t suw,
+                                                  const ModUpTable* T, int key_limbs, int L1, const PrimeC* P,
+                                                  const double* twf, const double* twq, const double* itwf,
+                                                  const double* itwq, int B, int vz, const u64* dadd, size_t sd,
+                                                  size_t dcs, double pmd, int inv_from) {
+  constexpr int LOGN = 16, M = 256, VS = M + M / 16;
+  constexpr int N = 1 << LOGN;
+  extern __shared__ u64 sh_raw[];
+  double* sh = reinterpret_cast<double*>(sh_raw);
+  const ModUpTable& tb = *T;
+  const int ext = tb.ext, limbs = tb.limbs;
+  const int th = threadIdx.x;
+  const int V = (int)blockDim.x / 16;
+  const int R = V / vz;
+  const int v = th / 16, u = th % 16;
+  const int ts = blockIdx.y;                                  // slot
+  const int z = blockIdx.z * vz + v % vz;
+  const int row = blockIdx.x * R + v / vz;
+  const bool valid = z < B;
+  const size_t zz = valid ? (size_t)z : 0;
+  const int pid = tb.ext_prime[ts];
+  const PrimeC& pr = P[pid];
+  const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
+  const int kl = ts < limbs ? ts : L1 + (ts - limbs);
+  const bool inv = ts >= inv_from;
+  auto pad = [](int a) { return a + (a >> 4); };
+  // phase p holds word addr(p, j): p = 0, words j 16 + u; p = 1, words 16 u + j
+  auto addr = [&](int p, int j) { return p == 0 ? (j << 4) + u : (u << 4) + j; };
+  double* tl = sh + V * VS;                                   // [R][2][256] forward, then [R][2][256] inverse
+  // four slots a thread at a time, every word requested before the first store
+  const int nst = 256 * R * (inv ? 2 : 1);
+  for (int k0 = th; k0 < nst; k0 += 4 * (int)blockDim.x) {
+    double tw[4], twq[4];
+    int at[4];
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int k = k0 + c4 * (int)blockDim.x;
+      const int slot = k & 255, rr = (k >> 8) % R, iv = (k >> 8) / R;
+      at[c4] = k < nst && slot != 0 ? (iv * R + rr) * 512 + slot : -1;
+      const int vb = blockIdx.x * R + rr;
+      const int st = 31 - __clz(slot | 1);
+      const int o = slot - (1 << st);
+      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+      const size_t g = (size_t)pid * N + (1 << (8 + st)) + (vb << st) + b;
+      tw[c4] = at[c4] >= 0 ? (iv ? itwf[g] : twf[g]) : 0.0;
+      twq[c4] = at[c4] >= 0 ? (iv ? itwq[g] : twq[g]) : 0.0;
+    }
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+      if (at[c4] >= 0) {
+        tl[at[c4]] = tw[c4];
+        tl[at[c4] + 256] = twq[c4];
+      }
+    }
+  }
+  __syncthreads();
+  const double* tlf = tl + (size_t)(v / vz) * 512;
+  const double* tli = tl + (size_t)(R + v / vz) * 512;
+  auto twid = [&](const double* tv, int p, int k, int j, double& w, double& wq) {
+    const int slot = p == 0 ? (1 << k) + (j >> (4 - k)) : (1 << (4 + k)) + ((j >> (4 - k)) << 4) + u;
+    w = tv[slot];
+    wq = tv[256 + slot];
+  };
+  // 16 words of this lane through LDS: written at phase-pf positions, read at pt
+  auto exchange = [&](double (&a)[16], int pf, int pt) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sh[v * VS + pad(addr(pf, j))] = a[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a[j] = sh[v * VS + pad(addr(pt, j))];
+  };
+  const size_t rbase = (size_t)row * M;
+  const double* key = (const double*)(((zz >> sel) & 1) ? key1 : key0);
+  double su[16], sw[16];
+  for (int d = 0; d < tb.beta; ++d) {
+    const ModUpDigit& dg = tb.d[d];
+    const bool own = ts >= dg.src[0] && ts < dg.src[0] + dg.nsrc;
+    double val[16];
+    if (own) {
+      const u64* X = x + zz * sx + (size_t)ts * N + rbase;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) val[j] = u64_to_f(X[addr(1, j)]);
+    } else {
+      const u64* Y = y + zz * sy + ((size_t)d * ext + ts) * N + rbase;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) val[j] = u64_to_f(Y[addr(0, j)]);
+      auto t0 = [&](int k, int j, double& w, double& wq) { twid(tlf, 0, k, j, w, wq); };
+      fpm::ct_phase16(val, false, qi, q, t0);
+      exchange(val, 0, 1);
+      auto t1 = [&](int k, int j, double& w, double& wq) { twid(tlf, 1, k, j, w, wq); };
+      fpm::ct_phase16(val, true, qi, q, t1);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double r = fred(val[j], qi, q);
+        val[j] = r < 0.0 ? __dadd_rn(r, q) : r;
+      }
+    }
+    const double* KB = key + ((size_t)(2 * d) * key_limbs + kl) * N + rbase + (size_t)u * 16;
+    const double* KA = key + ((size_t)(2 * d + 1) * key_limbs + kl) * N + rbase + (size_t)u * 16;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double pu = fmul_mod_q(val[j], KB[j], qi, q), pw = fmul_mod_q(val[j], KA[j], qi, q);
+      su[j] = d == 0 ? pu : __dadd_rn(su[j], pu);
+      sw[j] = d == 0 ? pw : __dadd_rn(sw[j], pw);
+    }
+    if (d & 1) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        su[j] = fred(su[j], qi, q);
+        sw[j] = fred(sw[j], qi, q);
+      }
+    }
+  }
+  if (dadd && ts == limbs - 1) {
+    const u64* D = dadd + zz * sd + (size_t)ts * N + rbase;
+    const double pmq = pmd / q;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      su[j] = __dadd_rn(fred(su[j], qi, q), fmul_mod(u64_to_f(D[addr(1, j)]), pmd, pmq, q));
+      sw[j] = __dadd_rn(fred(sw[j], qi, q), fmul_mod(u64_to_f(D[dcs + addr(1, j)]), pmd, pmq, q));
+    }
+  }
+  // exact residues, then (slots from inv_from on) the inverse row pass, and
+  // the store of each component in the p = 0 order (coalesced)
+  auto finish = [&](double (&a)[16], u64* O) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double r = fred(a[j], qi, q);
+      a[j] = r < 0.0 ? __dadd_rn(r, q) : r;
+    }
+    if (inv) {
+      auto t1 = [&](int k, int j, double& w, double& wq) { twid(tli, 1, k, j, w, wq); };
+      fpm::gs_phase16(a, false, qi, q, t1);
+      exchange(a, 1, 0);
+      auto t0 = [&](int k, int j, double& w, double& wq) { twid(tli, 0, k, j, w, wq); };
+      fpm::gs_phase16(a, true, qi, q, t0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double r = fred(a[j], qi, q);
+        a[j] = r < 0.0 ? __dadd_rn(r, q) : r;
+      }
+    } else {
+      exchange(a, 1, 0);
+    }
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) O[addr(0, j)] = f_to_u64(a[j]);
+    }
+  };
+  u64* U = uw + zz * suw + (size_t)ts * N + rbase;
+  finish(su, U);
+  finish(sw, U + (size_t)ext * N);
+}
+
 // Hoisted key inner products: for element z,
 //   (u, w)[z] = sum_a sum_j phi_{g(z,a)}(y_j[z]) * key_{g(z,a), j}     over Q_l u P,
 // the automorphism read as a gather (an aligned block of consecutive words
@@ -1567,6 +1752,8 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   double su[ZB][2], sw[ZB][2];
 #pragma unroll
   for (int zz = 0; zz < ZB; ++zz) su[zz][0] = su[zz][1] = sw[zz][0] = sw[zz][1] = 0.0;
+  const int fmask = fpm::fold_period(qd) - 1;   // block-uniform: the slot's prime
+  int np = 0;
   for (int a0 = 0; a0 < h.A; a0 += CH) {
     double2 kb[CH][BETA], ka[CH][BETA];
     ulonglong2 v[CH][BETA][ZB];
@@ -1586,8 +1773,8 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
           v[c][j][zz] = zz < nz ? *(const ulonglong2*)(src[j] + zz * zst[j] + (s & ~1u)) : make_ulonglong2(0, 0);
       }
     }
-    // products; the sums are folded back to |s| <= q/2 + 1 after every second
-    // product of the chunk (every product lies within 1.25 q of 0)
+    // products; the sums are folded back to |s| <= q/2 + 1 after every
+    // fold_period(q)-th product (np counts them across chunks)
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       if (a0 + c >= h.A) break;
@@ -1602,24 +1789,17 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
           su[zz][1] = __dadd_rn(su[zz][1], fmul_mod_q(v1, kb[c][j].y, qi, qd));
           sw[zz][0] = __dadd_rn(sw[zz][0], fmul_mod_q(v0, ka[c][j].x, qi, qd));
           sw[zz][1] = __dadd_rn(sw[zz][1], fmul_mod_q(v1, ka[c][j].y, qi, qd));
-          if ((c * BETA + j) & 1) {
+        }
+        if ((++np & fmask) == 0) {
+#pragma unroll
+          for (int zz = 0; zz < ZB; ++zz)
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
               su[zz][e] = fred(su[zz][e], qi, qd);
               sw[zz][e] = fred(sw[zz][e], qi, qd);
             }
-          }
         }
       }
-    }
-    if ((CH * BETA) & 1) {   // an odd chunk ends with one product pending
-#pragma unroll
-      for (int zz = 0; zz < ZB; ++zz)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          su[zz][e] = fred(su[zz][e], qi, qd);
-          sw[zz][e] = fred(sw[zz][e], qi, qd);
-        }
     }
   }
   auto res = [&](double s_) {
@@ -2026,7 +2206,7 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
     }
     // the conversion prologues 1, 2 and 4 hold many registers: with the
     // fused_occupancy knob they are built for 4 resident blocks per CU
-    const int occ = c.fused_occ == 4 && f.pro != 3 ? 4 : 0;
+    const int occ = (c.fused_occ == 4 || c.fused_occ == 3) && f.pro != 3 ? c.fused_occ : 0;
     const int is = f.isrc ? 1 : 0;
     const std::string pname = std::string("k_ntt_fast<8, false, 0, ") + (f.ci ? "4, " : "1, ") +
                               std::to_string(f.pro) + ", 0, " + std::to_string(occ) + (is ? ", 1>" : ">");
@@ -2050,6 +2230,15 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
       case 1014: FUSED_COL_IS(1, 4); break;
       case 1024: FUSED_COL_IS(2, 4); break;
       case 1044: FUSED_COL_IS(4, 4); break;
+      case 1013: FUSED_COL_IS(1, 3); break;
+      case 1023: FUSED_COL_IS(2, 3); break;
+      case 1043: FUSED_COL_IS(4, 3); break;
+      case 13: FUSED_COL(1, 1, 3); break;
+      case 23: FUSED_COL(1, 2, 3); break;
+      case 43: FUSED_COL(1, 4, 3); break;
+      case 113: FUSED_COL(4, 1, 3); break;
+      case 123: FUSED_COL(4, 2, 3); break;
+      case 143: FUSED_COL(4, 4, 3); break;
       case 10: FUSED_COL(1, 1, 0); break;
       case 20: FUSED_COL(1, 2, 0); break;
       case 30: FUSED_COL(1, 3, 0); break;
@@ -2069,6 +2258,10 @@ void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, cons
 #undef FUSED_COL
 #undef FUSED_COL_IS
     check_launch();
+  }
+  if (f.no_row) {
+    if (f.epi) BM_THROW(BM_EINVAL, "launch check: an epilogue needs the row pass");
+    return;
   }
   if (f.epi) {
     Prof pf(c, f.epi == 2 ? "k_ntt_fast<8, false, 1, 2, 0, 2>" : "k_ntt_fast<8, false, 1, 2, 0, 1>",
@@ -2317,6 +2510,47 @@ void modup(const Ctx& c, const u64* xc, size_t sx, u64* y, size_t sy, int B, int
   Prof pf(c, "k_modup", 8.0 * c.N * B * (rd + tb.npairs), ops * c.N * B);
   LAUNCH(k_modup, ew_grid(c.N, tb.npairs, B), dim3(TPB), 0, c.stream, xc, sx, y, sy, c.d_modup + limbs,
          c.d_primes, (int)c.N);
+  check_launch();
+}
+
+void kip_rows(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* key0,
+              const u64* key1, int sel, u64* uw, size_t suw, int B, int limbs, int inv_from, const u64* dadd,
+              size_t sd, size_t dcs) {
+  const ModUpTable& tb = c.h_modup[limbs];
+  if (!fused_ok(c) || c.ci) BM_THROW(BM_EINVAL, "launch check: row-pass key inner product needs N = 2^16");
+  if (limbs < 1 || limbs > c.L + 1 || inv_from < 0 || inv_from > tb.ext)
+    BM_THROW(BM_EINVAL, "launch check: row-pass kip level");
+  if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the row-pass kip");
+  if (B <= 0) return;
+  chk(y, B, sy, 0, (size_t)tb.beta * tb.ext * c.N, "row-pass kip digits");
+  chk(y_own, B, sown, 0, (size_t)limbs * c.N, "row-pass kip input");
+  chk(key0, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "row-pass kip key");
+  chk(key1, 1, 0, 0, (size_t)2 * tb.beta * (c.L + 1 + c.K) * c.N, "row-pass kip key");
+  chk(uw, B, suw, 0, (size_t)2 * tb.ext * c.N, "row-pass kip output");
+  u64 pm = 0;
+  if (dadd) {   // P mod q_{limbs-1}
+    chk(dadd, B, sd, 0, dcs + (size_t)limbs * c.N, "row-pass kip addend");
+    const u64 ql = c.primes[limbs - 1].q;
+    pm = 1;
+    for (int k = 0; k < c.K; ++k) pm = h_mulmod(pm, c.primes[c.pid_special(k)].q % ql, ql);
+  }
+  // geometry of the row passes: vz elements x R rows per block
+  const int V = row_views(c);
+  const int vz = B < V ? B : V;
+  const size_t view_words = 256 + 16;
+  auto lds = [&](int r) { return ((size_t)vz * r * view_words + (size_t)2 * 512 * r) * sizeof(double); };
+  int R = 1;
+  while (vz * R * 2 <= V && lds(2 * R) <= 65536) R *= 2;
+  const dim3 grid((unsigned)(c.N / 256 / R), (unsigned)tb.ext, (unsigned)((B + vz - 1) / vz));
+  const double elems = (double)c.N * tb.ext * B;
+  // distinct words: digits (pairs) and input once, keys once, both outputs
+  Prof pf(c, "k_kip_rows",
+          8.0 * ((double)c.N * B * (tb.npairs + limbs) + 2.0 * tb.beta * tb.ext * c.N * (key0 == key1 ? 1 : 2) +
+                 2.0 * elems),
+          0.5 * c.N * 8 * ((double)tb.npairs * B + 2.0 * (tb.ext - inv_from) * B) + 2.0 * elems * tb.beta);
+  LAUNCH(k_kip_rows, grid, dim3(16 * vz * R), lds(R), c.stream, y, sy, y_own, sown, key0, key1, sel, uw, suw,
+         c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.d_twf, c.d_twq, c.d_itwf, c.d_itwq, B, vz, dadd,
+         sd, dcs, (double)pm, inv_from);
   check_launch();
 }
 

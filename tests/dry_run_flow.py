@@ -521,7 +521,7 @@ def tuning_flow():
                     qs.append(bm.bm_encrypt_query(ctx, pk, rng.standard_normal(d).astype(np.float32), 1, 10 * n + j))
                     gs.append(g)
         for var in range(5):
-            for views, order, occ in ((0, 0, 0), (4, 1, 4), (8, 0, 4), (16, 1, 0)):
+            for views, order, occ in ((0, 0, 0), (4, 1, 4), (8, 0, 3), (16, 1, 0)):
                 bm.bm_ctx_set_tuning(ctx, group_chunk=3, kip_variant=var, ntt_row_views=views, kip_order=order,
                                      fused_occupancy=occ)
                 # natural level (hoisted sums at 2 to 4 digits) and minimum level (1 digit)

@@ -72,4 +72,21 @@ void chk_phase(double* x16, const double* tw, int fold_first, int inverse, doubl
 
 uint64_t chk_residue(double a, double qi, double q) { return residue(a, qi, q); }
 
+// a sum of n products v[i] w[i] folded after every fold_period(q)-th
+// product, as the key inner products of the kernels fold; *maxabs receives
+// the largest |s| the sum held
+uint64_t chk_fsum_period(const double* v, const double* w, size_t n, double qi, double q, double* maxabs) {
+  const int per = fold_period(q);
+  double s = 0.0, m = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    s = s + fmul_mod_q(v[i], w[i], qi, q);
+    m = std::fmax(m, std::fabs(s));
+    if ((int)((i + 1) % per) == 0) s = fred(s, qi, q);
+  }
+  *maxabs = m;
+  return residue(s, qi, q);
+}
+
+int chk_fold_period(double q) { return fold_period(q); }
+
 }  // extern "C"

@@ -77,6 +77,10 @@ def chk(tmp_path_factory):
     lib.chk_fmul_mod.argtypes = [D, D, D, sz, dbl, D]
     lib.chk_fmul_mod_q.argtypes = [D, D, sz, dbl, dbl, D]
     lib.chk_fred.argtypes = [D, sz, dbl, dbl, D]
+    lib.chk_fsum_period.argtypes = [D, D, sz, ctypes.c_double, ctypes.c_double, D]
+    lib.chk_fsum_period.restype = ctypes.c_uint64
+    lib.chk_fold_period.argtypes = [ctypes.c_double]
+    lib.chk_fold_period.restype = ctypes.c_int
     lib.chk_u64_to_f.argtypes = [U, sz, D]
     lib.chk_f_to_u64.argtypes = [D, sz, U]
     lib.chk_facc.argtypes = [D, D, sz, dbl, dbl, D]
@@ -193,6 +197,30 @@ def test_accumulated_products(chk, q):
         r = chk.chk_facc(v_p, w_p, len(v), 1.0 / float(q), float(q), ctypes.byref(m))
         assert r == sum(a * b for a, b in zip(v, w)) % q
         assert m.value <= 3 * q + 1
+
+
+@pytest.mark.parametrize("q", PRIMES)
+def test_fold_period_sums(chk, q):
+    """Sums folded every fold_period(q) products (8 below 2^50, else 2): the
+    exact residue, and every partial sum within 7.5q + 1 (q < 2^50) or
+    3q + 1, below 2^53, at the largest operands and at mixed extremes."""
+    per = chk.chk_fold_period(float(q))
+    assert per == (8 if q < 2 ** 50 else 2)
+    bound = Fraction(15, 2) * q + 1 if per == 8 else 3 * q + 1
+    assert bound < 2 ** 53
+    rng = random.Random(q + 11)
+    cases = [([q - 1] * 64, [q - 1] * 64), ([q - 1] * 9, [q - 2] * 9), ([q // 2] * 16, [q - 1] * 16)]
+    for _ in range(20):
+        n = rng.randrange(1, 65)
+        pick = lambda: rng.choice([0, 1, q - 1, q - 2, q // 2, rng.randrange(q)])   # noqa: E731
+        cases.append(([pick() for _ in range(n)], [pick() for _ in range(n)]))
+    for v, w in cases:
+        v_arr, v_p = _d(v)
+        w_arr, w_p = _d(w)
+        m = ctypes.c_double(0)
+        r = chk.chk_fsum_period(v_p, w_p, len(v), 1.0 / float(q), float(q), ctypes.byref(m))
+        assert r == sum(a * b for a, b in zip(v, w)) % q
+        assert m.value <= bound
 
 
 def _phase_exact(x, tw, inverse, q):
