@@ -451,7 +451,7 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
     // first is stored (a row pass of few polynomials stages up to 16 rows'
     // twiddles per thread, and one round trip per slot would dominate it)
     for (int k0 = t; k0 < 256 * R; k0 += 4 * nthr) {
-      double tw[4], twq[4];
+      double sw_w[4], sw_q[4];   // staged words (names apart from the kernel's twf / twq)
       int at[4];
 #pragma unroll
       for (int c4 = 0; c4 < 4; ++c4) {
@@ -463,14 +463,14 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         const int o = slot - (1 << st);
         const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
         const int g = (1 << (s0 + st)) + (vb << st) + b;
-        tw[c4] = at[c4] >= 0 ? W[g] : 0.0;
-        twq[c4] = at[c4] >= 0 ? WQ[g] : 0.0;
+        sw_w[c4] = at[c4] >= 0 ? W[g] : 0.0;
+        sw_q[c4] = at[c4] >= 0 ? WQ[g] : 0.0;
       }
 #pragma unroll
       for (int c4 = 0; c4 < 4; ++c4) {
         if (at[c4] >= 0) {
-          tl[at[c4]] = tw[c4];
-          tl[at[c4] + 256] = twq[c4];
+          tl[at[c4]] = sw_w[c4];
+          tl[at[c4] + 256] = sw_q[c4];
         }
       }
     }
@@ -572,14 +572,14 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         load(cl, md.K, (size_t)f.last_off);
         inv_col(cl, md.K, li, true);
         for (int a = 0; a < md.K; ++a) {
-          const int pid = md.pprime[a];
-          const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+          const int ppid = md.pprime[a];
+          const double ms = (double)P[ppid].q, msi = __longlong_as_double((long long)P[ppid].pad[1]);
           double c1d, c1q;
-          with_ninv((double)md.phatinv[a][0], pid, c1d, c1q);
+          with_ninv((double)md.phatinv[a][0], ppid, c1d, c1q);
           const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
           double w[16];
           load(w, a, (size_t)(f.s_off0 + a));
-          inv_col(w, a, pid, false);
+          inv_col(w, a, ppid, false);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             double t1 = fred(fmul_mod(w[j], c1d, c1q, ms), msi, ms);
@@ -598,10 +598,10 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          double last = fmul_mod(fred(cl[j], qli, ql), pl, plq, ql);
-          last = fred(last, qli, ql);
-          last = last < 0.0 ? __dadd_rn(last, ql) : last;               // exact residue mod q_last
-          const double z = __dadd_rn(fmul_mod(fred(ci[j], qi, q), pt, ptq, q), fred(last, qi, q));
+          double lw = fmul_mod(fred(cl[j], qli, ql), pl, plq, ql);
+          lw = fred(lw, qli, ql);
+          lw = lw < 0.0 ? __dadd_rn(lw, ql) : lw;                     // exact residue mod q_last
+          const double z = __dadd_rn(fmul_mod(fred(ci[j], qi, q), pt, ptq, q), fred(lw, qi, q));
           x[j] = fred(z, qi, q);
         }
       } else {
@@ -677,11 +677,11 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
         const double pl = (double)md.pinv[li][0], plq = pl / ql, pt = (double)md.pinv[ti][0], ptq = pt / q;
         double cl[16], cc[16];
         for (int a = 0; a < md.K; ++a) {
-          const int pid = md.pprime[a];
-          const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+          const int ppid = md.pprime[a];
+          const double ms = (double)P[ppid].q, msi = __longlong_as_double((long long)P[ppid].pad[1]);
           const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
           const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
-          unfold(f.s_off0 + a, pid, cc);
+          unfold(f.s_off0 + a, ppid, cc);
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
             double t1 = fred(fmul_mod(cc[j], c1d, c1q, ms), msi, ms);
@@ -756,8 +756,8 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
       const double pl = (double)md.pinv[li][0], plq = pl / ql, pt = (double)md.pinv[ti][0], ptq = pt / q;
       double cl[16], ci[16];
       for (int a = 0; a < md.K; ++a) {
-        const int pid = md.pprime[a];
-        const double ms = (double)P[pid].q, msi = __longlong_as_double((long long)P[pid].pad[1]);
+        const int ppid = md.pprime[a];
+        const double ms = (double)P[ppid].q, msi = __longlong_as_double((long long)P[ppid].pad[1]);
         const double c1d = (double)md.phatinv[a][0], c1q = c1d / ms;
         const double hl = (double)md.phat[a][li][0], hlq = hl / ql, ht = (double)md.phat[a][ti][0], htq = ht / q;
         const u64* Sa = S + (size_t)(f.s_off0 + a) * N;
@@ -1242,7 +1242,7 @@ __global__ void __launch_bounds__(256) k_kip_rows(const u64* y, size_t sy, const
   // four slots a thread at a time, every word requested before the first store
   const int nst = 256 * R * (inv ? 2 : 1);
   for (int k0 = th; k0 < nst; k0 += 4 * (int)blockDim.x) {
-    double tw[4], twq[4];
+    double sw_w[4], sw_q[4];   // staged words (names apart from the kernel's twf / twq)
     int at[4];
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
@@ -1254,14 +1254,14 @@ __global__ void __launch_bounds__(256) k_kip_rows(const u64* y, size_t sy, const
       const int o = slot - (1 << st);
       const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
       const size_t g = (size_t)pid * N + (1 << (8 + st)) + (vb << st) + b;
-      tw[c4] = at[c4] >= 0 ? (iv ? itwf[g] : twf[g]) : 0.0;
-      twq[c4] = at[c4] >= 0 ? (iv ? itwq[g] : twq[g]) : 0.0;
+      sw_w[c4] = at[c4] >= 0 ? (iv ? itwf[g] : twf[g]) : 0.0;
+      sw_q[c4] = at[c4] >= 0 ? (iv ? itwq[g] : twq[g]) : 0.0;
     }
 #pragma unroll
     for (int c4 = 0; c4 < 4; ++c4) {
       if (at[c4] >= 0) {
-        tl[at[c4]] = tw[c4];
-        tl[at[c4] + 256] = twq[c4];
+        tl[at[c4]] = sw_w[c4];
+        tl[at[c4] + 256] = sw_q[c4];
       }
     }
   }
