@@ -452,6 +452,10 @@ bool fused_ok(const Ctx& c);
 // column pass with isrc takes as sources)
 void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
                   const LimbMap& m);
+// the column pass of the inverse transform at N = 2^16 only (its input the
+// row pass's output, as ntt_inv_rows leaves it)
+void ntt_inv_cols(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+                  const LimbMap& m);
 // whether the fused column pass can finish the inverse transform of its
 // sources itself (f.isrc) for prologue kind pro: N = 2^16, outside the
 // conjugate-invariant ring, at most 5 source primes per block

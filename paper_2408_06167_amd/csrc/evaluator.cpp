@@ -346,7 +346,7 @@ static void set_isrc(const Ctx& c, FuseArgs& f, bool on) {
 // residues held as FP64 values for the key inner products.
 // the key inner product on whole rows (k_kip_rows) serves the plain key
 // switches where the fused transforms finish inverse column passes
-static bool kip_rows_ok(const Ctx& c) { return kern::isrc_ok(c, 1) && kern::isrc_ok(c, 2) && kern::isrc_ok(c, 4); }
+static bool kip_rows_ok(const Ctx& c) { return kern::fused_ok(c) && !c.ci; }
 
 DBuf modup_eval(Ctx& c, const u64* x, size_t sx, int B, int limbs, bool col_only) {
   const size_t N = c.N;
@@ -404,9 +404,9 @@ void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0,
       ++mp.n;
     }
   const bool is = kern::isrc_ok(c, 2);
-  if (rows_done && !is) BM_THROW(BM_EINVAL, "special limbs after their inverse row pass need the fused transforms");
   if (rows_done) {
     // the key inner product ran the inverse row pass of the special limbs
+    if (!is) kern::ntt_inv_cols(c, uw, suw, uw, suw, B, mp);
   } else if (is) {
     kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
   } else {
@@ -534,9 +534,9 @@ void moddown_rescale(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t 
     }
   }
   const bool is = kern::isrc_ok(c, 4);
-  if (rows_done && !is) BM_THROW(BM_EINVAL, "limbs after their inverse row pass need the fused transforms");
   if (rows_done) {
     // the key inner product ran the inverse row pass of these limbs
+    if (!is) kern::ntt_inv_cols(c, uw, suw, uw, suw, B, mp);
   } else if (is) {
     kern::ntt_inv_rows(c, uw, suw, uw, suw, B, mp);
   } else {

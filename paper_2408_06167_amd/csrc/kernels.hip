@@ -1620,14 +1620,19 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   double su[PG], sw[PG];
 #pragma unroll
   for (int p = 0; p < PG; ++p) su[p] = sw[p] = 0.0;
-  // two amounts at a time, every word of both requested before the first
-  // product (a ragged pair repeats the last amount, unused)
-  for (int a0 = 0; a0 < h.A; a0 += 2) {
-    unsigned use[2];
-    u64 v[2][BETA], mw[2][PG];
-    double kb[2][BETA], ka[2][BETA];
+  // MC amounts at a time, every word of them requested before the first
+  // product (a ragged chunk repeats the last amount, unused); each amount adds
+  // at most one product to a part's sums, which are folded after every
+  // fold_period(q)-th amount (np counts them)
+  constexpr int MC = 2;
+  const int fmask = fpm::fold_period(q) - 1;
+  int np = 0;
+  for (int a0 = 0; a0 < h.A; a0 += MC) {
+    unsigned use[MC];
+    u64 v[MC][BETA], mw[MC][PG];
+    double kb[MC][BETA], ka[MC][BETA];
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
+    for (int c2 = 0; c2 < MC; ++c2) {
       const int a = a0 + c2 < h.A ? a0 + c2 : h.A - 1;
       use[c2] = a0 + c2 < h.A ? (unsigned)mu.parts[a] & gmask : 0u;
       const u32 s = autom_src((u32)pos, h.g[a], log_n, ms);
@@ -1642,37 +1647,39 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
       for (int p = 0; p < PG; ++p) mw[c2][p] = masks[((size_t)(i0 + p < k ? i0 + p : 0) * ml + kl) * N + s];
     }
 #pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-      if (!use[c2]) continue;
-      double iu = 0.0, iw = 0.0;
+    for (int c2 = 0; c2 < MC; ++c2) {
+      if (a0 + c2 >= h.A) break;
+      if (use[c2]) {
+        double iu = 0.0, iw = 0.0;
 #pragma unroll
-      for (int d = 0; d < BETA; ++d) {
-        const double vd = own[d] ? u64_to_f(v[c2][d]) : __longlong_as_double((long long)v[c2][d]);
-        iu = __dadd_rn(iu, fmul_mod_q(vd, kb[c2][d], qi, q));
-        iw = __dadd_rn(iw, fmul_mod_q(vd, ka[c2][d], qi, q));
-        if (d & 1) {
-          iu = fred(iu, qi, q);
-          iw = fred(iw, qi, q);
+        for (int d = 0; d < BETA; ++d) {
+          const double vd = own[d] ? u64_to_f(v[c2][d]) : __longlong_as_double((long long)v[c2][d]);
+          iu = __dadd_rn(iu, fmul_mod_q(vd, kb[c2][d], qi, q));
+          iw = __dadd_rn(iw, fmul_mod_q(vd, ka[c2][d], qi, q));
+          if (d & 1) {
+            iu = fred(iu, qi, q);
+            iw = fred(iw, qi, q);
+          }
+        }
+        // the mask words multiply the reduced inner sums (|.| <= q/2 + 1)
+        iu = fred(iu, qi, q);
+        iw = fred(iw, qi, q);
+#pragma unroll
+        for (int p = 0; p < PG; ++p) {
+          if ((use[c2] >> (i0 + p)) & 1) {
+            const double m = u64_to_f(mw[c2][p]);
+            su[p] = __dadd_rn(su[p], fmul_mod_q(iu, m, qi, q));
+            sw[p] = __dadd_rn(sw[p], fmul_mod_q(iw, m, qi, q));
+          }
         }
       }
-      // the mask words multiply the reduced inner sums (|.| <= q/2 + 1)
-      iu = fred(iu, qi, q);
-      iw = fred(iw, qi, q);
+      if ((++np & fmask) == 0) {
 #pragma unroll
-      for (int p = 0; p < PG; ++p) {
-        if ((use[c2] >> (i0 + p)) & 1) {
-          const double m = u64_to_f(mw[c2][p]);
-          su[p] = __dadd_rn(su[p], fmul_mod_q(iu, m, qi, q));
-          sw[p] = __dadd_rn(sw[p], fmul_mod_q(iw, m, qi, q));
+        for (int p = 0; p < PG; ++p) {
+          su[p] = fred(su[p], qi, q);
+          sw[p] = fred(sw[p], qi, q);
         }
       }
-    }
-    // at most one product a part per amount: every part's sums folded after
-    // every pair of amounts
-#pragma unroll
-    for (int p = 0; p < PG; ++p) {
-      su[p] = fred(su[p], qi, q);
-      sw[p] = fred(sw[p], qi, q);
     }
   }
   auto res = [&](double v) {
@@ -2044,8 +2051,10 @@ static int row_views(const Ctx& c) { return c.ntt_views == 4 || c.ntt_views == 8
 
 // N = 2^12: one 12-stage pass; N = 2^16: 8 column stages then 8 row stages
 // (inverse: rows first).  Row passes take up to 16 polynomials per block.
+// only: 0 both passes; for the inverse transform 1 the row pass only, 2 the
+// column pass only (the input then holds the row pass's output)
 void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
-              const LimbMap& m, const LimbMap& m_out, bool inverse, bool rows_only = false) {
+              const LimbMap& m, const LimbMap& m_out, bool inverse, int only = 0) {
   const int logn = c.log_n;
   const int N = 1 << logn;
   const double elems = (double)N * m.n * B;
@@ -2108,9 +2117,11 @@ void ntt_fast(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t ou
   if (!inverse) {
     col(in, in_stride, out, out_stride, m, 0);
     row(out, out_stride, out, out_stride, m_out);
+  } else if (only == 2) {
+    col(in, in_stride, out, out_stride, m, 1);
   } else {
     row(in, in_stride, out, out_stride, m);
-    if (!rows_only) col(out, out_stride, out, out_stride, m_out, 1);
+    if (only != 1) col(out, out_stride, out, out_stride, m_out, 1);
   }
 }
 
@@ -2159,7 +2170,14 @@ void ntt_inv_rows(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_
   if (B <= 0 || m.n <= 0) return;
   LimbMap m_out = m;
   for (int i = 0; i < m.n; ++i) m_out.off[i] = m.ooff[i];
-  ntt_fast(c, in, in_stride, out, out_stride, B, m, m_out, true, true);
+  ntt_fast(c, in, in_stride, out, out_stride, B, m, m_out, true, 1);
+}
+
+void ntt_inv_cols(const Ctx& c, const u64* in, size_t in_stride, u64* out, size_t out_stride, int B,
+                  const LimbMap& m) {
+  if (!fused_ok(c)) BM_THROW(BM_EINVAL, "launch check: inverse column pass needs N = 2^16");
+  if (B <= 0 || m.n <= 0) return;
+  ntt_fast(c, in, in_stride, out, out_stride, B, m, m, true, 2);
 }
 
 void ntt_fused(const Ctx& c, const FuseArgs& f, u64* tmp, size_t ts, int B, const LimbMap& m, bool f64_out) {
