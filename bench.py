@@ -42,10 +42,10 @@ TRAFFIC = {
     # the face match at k = 4, S2 + minimum level + hoisted: the grouped hoisted
     # key inner product, as the autotuner's two usual variants build it
     ("k_kip_hoist_zb<1, 3, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "2a4d08f65e1922abb8451041bf788456a9b488aa70be3b81874f4b21be67aeb8",
+        "kernels_sha256": "9bf5658362d56370db0f0c36d445e5d48359a7c6578808ea75dbac363d66073b",
         "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 190202651},
     ("k_kip_hoist_zb<1, 2, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "2a4d08f65e1922abb8451041bf788456a9b488aa70be3b81874f4b21be67aeb8",
+        "kernels_sha256": "9bf5658362d56370db0f0c36d445e5d48359a7c6578808ea75dbac363d66073b",
         "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 191327586},
 }
 

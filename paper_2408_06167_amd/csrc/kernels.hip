@@ -1520,8 +1520,8 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 // masks applied after the key inner products).  Element e = j k + i is part i
 // of query j (x at x + j sx: c0, then c1 at + xcs, `limbs` limbs, evaluation
 // domain); mask i is at masks + i ml N over every prime (ml limbs: the chain,
-// then the specials).  h.g lists the distinct amounts of all parts, u.parts[a]
-// the parts that use amount a (bit i), u.per[i * k1 + n] the n-th amount of
+// then the specials).  h.g lists the distinct amounts of all parts, mu.parts[a]
+// the parts that use amount a (bit i), mu.per[i * k1 + n] the n-th amount of
 // part i (k1 = k - 1 amounts a part).
 //   addends (the first WA blocks, limbs < `limbs`):
 //     ad[e][0] = sum over r in {0} u amounts(i) of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1
