@@ -157,10 +157,10 @@ void expand_batch(Ctx& c, const bm_evk* evk, const u64* q, size_t qs, size_t qcs
     DBuf y = ev::modup_eval(c, q + qcs, qs, nq, l);
     DBuf uw(&c, (size_t)E * suw), ad(&c, (size_t)E * 2 * ln);
     const bool fused = kern::fused_ok(c);
-    kern::kip_hoist_mask(c, y.p(), sy, q, qs, qcs, (const u64* const*)evk->gtab.p(), parts, keys, masks, uw.p(),
-                         suw, ad.p(), 2 * ln, nq, l, fused);
+    const bool rows = kern::kip_hoist_mask(c, y.p(), sy, q, qs, qcs, (const u64* const*)evk->gtab.p(), parts, keys,
+                                           masks, uw.p(), suw, ad.p(), 2 * ln, nq, l, fused, fused);
     if (fused) {
-      ev::moddown_rescale(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, out);
+      ev::moddown_rescale(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, out, rows);
     } else {
       DBuf sum(&c, (size_t)E * 2 * ln);
       ev::moddown_add(c, uw.p(), E, l, ad.p(), 2 * ln, ad.p() + ln, 2 * ln, sum.p(), 2 * ln);

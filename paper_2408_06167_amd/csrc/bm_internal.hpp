@@ -549,14 +549,19 @@ void kip_rows(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t so
 // sums over Q_l u P to uw [E][2][l+K][N] (with dadd: P times the addends added
 // at the last chain limb) and the addends to ad [E][2][limbs][N]; masks
 // [k][L+1+K][N]; parts[i] lists part i's Galois elements (k = parts.size(),
-// every list of one length)
-void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
+// every list of one length).  inv_rows (with dadd): the last chain limb and
+// the special limbs of (u, w) may leave in their inverse row pass (N = 2^16,
+// standard ring); the return value says whether they did
+bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
                     const u64* const* gtab, const std::vector<std::vector<uint32_t>>& parts,
                     const std::vector<const u64*>& keys, const u64* masks, u64* uw, size_t suw, u64* ad,
-                    size_t sad, int nq, int limbs, bool dadd);
-void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
+                    size_t sad, int nq, int limbs, bool dadd, bool inv_rows);
+// inv_special: the special limbs of (u, w) may leave in their inverse row
+// pass (the grouped kernel at N = 2^16, a non-accumulating launch); the
+// return value says whether they did
+bool kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
                const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
-               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate);
+               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate, bool inv_special);
 }  // namespace kern
 
 }  // namespace bm

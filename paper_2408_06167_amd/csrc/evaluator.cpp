@@ -469,11 +469,12 @@ void rotation_sum_hoisted(Ctx& c, const bm_evk* evk, const u64* in, int B, int l
   if (hs.empty()) BM_THROW(BM_EINVAL, "no rotation amounts");
   DBuf y = modup_eval(c, in + ln, 2 * ln, B, limbs);
   DBuf uw(&c, (size_t)B * suw), c0(&c, (size_t)B * ln);
+  bool rows = false;   // the special limbs already in their inverse row pass
   for (size_t part = 0; part < hs.size(); ++part) {   // amount lists longer than one launch carries
-    kern::kip_hoist(c, y.p(), sy, in + ln, 2 * ln, (const u64* const*)evk->gtab.p(), hs[part], keys, uw.p(),
-                    suw, in, 2 * ln, c0.p(), ln, B, limbs, part > 0);
+    rows = kern::kip_hoist(c, y.p(), sy, in + ln, 2 * ln, (const u64* const*)evk->gtab.p(), hs[part], keys, uw.p(),
+                           suw, in, 2 * ln, c0.p(), ln, B, limbs, part > 0, hs.size() == 1);
   }
-  moddown_add(c, uw.p(), B, limbs, c0.p(), ln, in + ln, 2 * ln, out, 2 * ln);
+  moddown_add(c, uw.p(), B, limbs, c0.p(), ln, in + ln, 2 * ln, out, 2 * ln, rows);
 }
 
 void relin(Ctx& c, const u64* d, int B, int limbs, const u64* rlk, u64* out) {

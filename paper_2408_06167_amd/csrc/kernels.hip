@@ -1374,6 +1374,14 @@ __global__ void __launch_bounds__(256) k_kip_rows(const u64* y, size_t sy, const
 // share the key words through L2.
 constexpr int HOIST_BETA = 4;   // digits a thread handles (dnum <= 4 at every level)
 
+// The key pointers of the hoisted kernels come from a table staged in LDS;
+// read through these global-space types, their words are loaded with global
+// (not flat) loads, which do not hold up the LDS and scalar-memory waits of
+// the next amounts.
+typedef const __attribute__((address_space(1))) double* gdp;
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) dv2* gd2p;
+
 // XCD-aware block order: the hardware deals workgroups to the 8 XCDs in
 // turn, so workgroup w runs on XCD w mod 8.  Logical block
 // (w mod 8) * (W / 8) + w / 8 gives every XCD one contiguous range of logical
@@ -1456,7 +1464,6 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
     src[j] = own[j] ? x + (size_t)z * sx + (size_t)t * N : y + (size_t)z * sy + ((size_t)j * ext + t) * N;
   }
   const size_t ko = (size_t)kl * N + i, kst = (size_t)key_limbs * N;
-  typedef const __attribute__((address_space(1))) double* gdp;   // the key pointers are global ones
   // words of one amount: digits (gathered), key b and key a words of every digit
   struct Words {
     u64 v[BETA];
@@ -1542,9 +1549,8 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
                                  const u64* const* gtab, HoistArgs h, MaskUse mu, const u64* masks, int ml,
                                  u64* uw, size_t suw, u64* ad, size_t sad, const ModUpTable* T, int key_limbs,
                                  int L1, const PrimeC* P, int log_n, int ms, int nq, int k, int WA, int dadd,
-                                 double pmd) {
+                                 double pmd, const double* itwf, const double* itwq, int inv_from) {
   const int N = 1 << log_n;
-  const int gx = (N + TPB - 1) / TPB;
   const ModUpTable& tb = *T;
   const int limbs = tb.limbs;
   const int k1 = k - 1;
@@ -1571,10 +1577,12 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   };
   // Both parts take (position block, ..., ...) with the position block
   // slowest and the logical blocks dealt to the 8 XCDs in contiguous ranges
-  // (xcd_block, when the part's block count is a multiple of 8): an aligned
-  // eighth of the positions gathers only from the same eighth of every limb
-  // under any automorphism, so each XCD's L2 holds its own eighth of the
-  // digits, masks and query limbs instead of all of them.
+  // (xcd_block, when the part's block count is a multiple of 8): each XCD
+  // takes an aligned eighth of the positions of every slot.  For one
+  // automorphism an aligned eighth gathers from one aligned eighth of every
+  // limb (the automorphisms permute the eighths; rotations keep the two
+  // halves), so each amount's gathers of an XCD stay within one eighth of
+  // the digits, masks and query limbs.
   const int nA = nq * k;
   if ((int)blockIdx.x < WA) {
     const int lb = WA % 8 == 0 ? xcd_block((int)blockIdx.x, WA) : (int)blockIdx.x;
@@ -1600,8 +1608,15 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   const int pb = lb / (nq * ngr * ext);
   const int j = jg / ngr, i0 = (jg % ngr) * PG;
   const int pos = pb * TPB + threadIdx.x;
+  // key pointers and part sets of the amounts in LDS (a part set read from
+  // the kernel arguments inside the loop would be a vector load, whose wait
+  // holds up every word the chunk has requested before it)
   __shared__ const u64* kp[HOIST_MAX];
-  for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
+  __shared__ unsigned up[HOIST_MAX];
+  for (int a = threadIdx.x; a < h.A; a += TPB) {
+    kp[a] = gtab[h.g[a] >> 1];
+    up[a] = mu.parts[a];
+  }
   __syncthreads();
   if (pos >= N || t >= ext) return;
   const PrimeC& pr = P[tb.ext_prime[t]];
@@ -1634,9 +1649,9 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
 #pragma unroll
     for (int c2 = 0; c2 < MC; ++c2) {
       const int a = a0 + c2 < h.A ? a0 + c2 : h.A - 1;
-      use[c2] = a0 + c2 < h.A ? (unsigned)mu.parts[a] & gmask : 0u;
+      use[c2] = a0 + c2 < h.A ? up[a] & gmask : 0u;
       const u32 s = autom_src((u32)pos, h.g[a], log_n, ms);
-      const double* key = (const double*)kp[a];
+      const gdp key = (gdp)kp[a];
 #pragma unroll
       for (int d = 0; d < BETA; ++d) {
         v[c2][d] = src[d][s];
@@ -1686,6 +1701,32 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     const double r = fred(v, qi, q);
     return f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
   };
+  auto canon = [&](double v) {
+    const double r = fred(v, qi, q);
+    return r < 0.0 ? __dadd_rn(r, q) : r;
+  };
+  // inverse row pass of this block's row (block-uniform; N = 2^16, the
+  // block's 256 positions one row of the 256 x 256 view): LDS holds the rows
+  // [PG][2 components][VS], then the row's twiddles [512] (staged after the
+  // sums: staged before them, their words would stay in registers)
+  constexpr int VS = 256 + 16;
+  const bool inv = t >= inv_from;
+  extern __shared__ u64 hm_raw[];
+  double* rsh = reinterpret_cast<double*>(hm_raw);
+  double* ztl = rsh + PG * 2 * VS;
+  if (inv) {
+    const int pid = tb.ext_prime[t];
+    for (int slot = (int)threadIdx.x; slot < 256; slot += TPB) {
+      if (slot == 0) continue;
+      const int st = 31 - __clz(slot);
+      const int o = slot - (1 << st);
+      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+      const size_t g = (size_t)pid * N + (1 << (8 + st)) + (pb << st) + b;
+      ztl[slot] = itwf[g];
+      ztl[256 + slot] = itwq[g];
+    }
+  }
+  auto pad = [](int a_) { return a_ + (a_ >> 4); };
 #pragma unroll
   for (int p = 0; p < PG; ++p) {
     const int i = i0 + p;
@@ -1699,9 +1740,46 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
       vu = __dadd_rn(fred(vu, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
       vw = __dadd_rn(fred(vw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
     }
+    if (inv) {
+      rsh[(p * 2 + 0) * VS + pad((int)threadIdx.x)] = canon(vu);
+      rsh[(p * 2 + 1) * VS + pad((int)threadIdx.x)] = canon(vw);
+      continue;
+    }
     u64* U = uw + (size_t)e * suw + (size_t)t * N;
     U[pos] = res(vu);
     U[(size_t)ext * N + pos] = res(vw);
+  }
+  if (!inv) return;
+  __syncthreads();
+  // row v = (part p, component) of the block, lane u of 16
+  const int v = (int)threadIdx.x >> 4, u = (int)threadIdx.x & 15;
+  const bool act = v < 2 * min(PG, k - i0);
+  double* R = rsh + (act ? v : 0) * VS;
+  auto addr = [&](int p_, int jj) { return p_ == 0 ? (jj << 4) + u : (u << 4) + jj; };
+  auto twid = [&](int p_, int kk, int jj, double& w, double& wq) {
+    const int slot = p_ == 0 ? (1 << kk) + (jj >> (4 - kk)) : (1 << (4 + kk)) + ((jj >> (4 - kk)) << 4) + u;
+    w = ztl[slot];
+    wq = ztl[256 + slot];
+  };
+  double a[16];
+  if (act) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) a[jj] = R[pad(addr(1, jj))];
+    auto t1 = [&](int kk, int jj, double& w, double& wq) { twid(1, kk, jj, w, wq); };
+    fpm::gs_phase16(a, false, qi, q, t1);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) R[pad(addr(1, jj))] = a[jj];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) a[jj] = R[pad(addr(0, jj))];
+    auto t0 = [&](int kk, int jj, double& w, double& wq) { twid(0, kk, jj, w, wq); };
+    fpm::gs_phase16(a, true, qi, q, t0);
+    const int e = j * k + i0 + (v >> 1), comp = v & 1;
+    u64* O = uw + (size_t)e * suw + (size_t)(comp * ext + t) * N + (size_t)pb * 256;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) O[addr(0, jj)] = f_to_u64(canon(a[jj]));
   }
 }
 
@@ -1711,11 +1789,17 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
 // each key word is loaded once and used ZB times from registers, and takes
 // the amounts CH at a time, all their words requested before the first is
 // used (memory latency, not arithmetic, sets the pace of this kernel).
+//
+// With inv_from < ext (N = 2^16: a block's 512 positions are two whole rows
+// of the 256 x 256 view), the slots from inv_from on leave in the row pass
+// of their inverse transform (the words an inverse row pass of the stored
+// sums would give: the rows go through LDS, 16 lanes a row, as in
+// k_kip_rows), so that the ModDown starts at its column pass.
 template <int BETA, int ZB, int CH>
 __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx, const u64* const* gtab,
                                HoistArgs h, u64* uw, size_t suw, const ModUpTable* T, int key_limbs, int L1,
                                const PrimeC* P, int log_n, int ms, int B, int accumulate, AutomArgs am,
-                               int order) {
+                               int order, const double* itwf, const double* itwq, int inv_from) {
   if ((int)blockIdx.x < am.W) {
     autom_sum_part(am, h, P, log_n, ms, accumulate, (int)blockIdx.x);
     return;
@@ -1729,11 +1813,25 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   // order 0: element groups fastest (the groups of one position block share
   // its key words through L2); order 1: position blocks fastest (an XCD
   // works through one element group's positions while its gathered digit
-  // words stay in L2, the key words streaming past)
-  const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
-  const int zg = order ? (lb / gx) % ZG : lb % ZG;
-  const int pb = order ? lb % gx : (lb / ZG) % gx;
-  const int t = lb / (ZG * gx);
+  // words stay in L2, the key words streaming past).  With gx a multiple of
+  // 8, each XCD takes an aligned eighth of the positions of every slot and
+  // element group (that order inside its range), so that the slots whose
+  // rows leave in their inverse row pass, more work a block, are spread over
+  // all XCDs instead of falling on the last ones.
+  const int W = (int)gridDim.x - am.W;
+  const int lb = xcd_block((int)blockIdx.x - am.W, W);
+  int zg, pb, t;
+  if (gx % 8 == 0) {
+    const int g8 = gx / 8, per = W / 8, r = lb % per;
+    const int pl = order ? r % g8 : (r / ZG) % g8;
+    zg = order ? (r / g8) % ZG : r % ZG;
+    t = r / (ZG * g8);
+    pb = (lb / per) * g8 + pl;
+  } else {
+    zg = order ? (lb / gx) % ZG : lb % ZG;
+    pb = order ? lb % gx : (lb / ZG) % gx;
+    t = lb / (ZG * gx);
+  }
   const int i = 2 * (pb * TPB + (int)threadIdx.x);   // positions i, i + 1
   __shared__ const u64* kp[HOIST_MAX];
   for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
@@ -1762,7 +1860,7 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   const int fmask = fpm::fold_period(qd) - 1;   // block-uniform: the slot's prime
   int np = 0;
   for (int a0 = 0; a0 < h.A; a0 += CH) {
-    double2 kb[CH][BETA], ka[CH][BETA];
+    dv2 kb[CH][BETA], ka[CH][BETA];
     ulonglong2 v[CH][BETA][ZB];
     bool swp[CH];
 #pragma unroll
@@ -1770,11 +1868,11 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
       const int a = a0 + c < h.A ? a0 + c : h.A - 1;   // a ragged chunk repeats the last amount, unused
       const u32 s = autom_src((u32)i, h.g[a], log_n, ms);
       swp[c] = s & 1;                                    // position i reads the odd word of the pair
-      const double* key = (const double*)kp[a];
+      const gdp key = (gdp)kp[a];
 #pragma unroll
       for (int j = 0; j < BETA; ++j) {
-        kb[c][j] = *(const double2*)(key + ko + (size_t)(2 * j) * kst);
-        ka[c][j] = *(const double2*)(key + ko + (size_t)(2 * j + 1) * kst);
+        kb[c][j] = *(gd2p)(key + ko + (size_t)(2 * j) * kst);
+        ka[c][j] = *(gd2p)(key + ko + (size_t)(2 * j + 1) * kst);
 #pragma unroll
         for (int zz = 0; zz < ZB; ++zz)
           v[c][j][zz] = zz < nz ? *(const ulonglong2*)(src[j] + zz * zst[j] + (s & ~1u)) : make_ulonglong2(0, 0);
@@ -1809,11 +1907,76 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
       }
     }
   }
-  auto res = [&](double s_) {
-    double r = fred(s_, qi, qd);
-    r = r < 0.0 ? __dadd_rn(r, qd) : r;
-    return f_to_u64(r);
+  auto canon = [&](double s_) {
+    const double r = fred(s_, qi, qd);
+    return r < 0.0 ? __dadd_rn(r, qd) : r;
   };
+  auto res = [&](double s_) { return f_to_u64(canon(s_)); };
+  // inverse row pass of this block's two rows (block-uniform): LDS holds the
+  // rows [ZB][2 components][2 rows][VS] and then the rows' twiddles [2][512]
+  constexpr int VS = 256 + 16;
+  const bool inv = !accumulate && t >= inv_from;
+  if (inv) {
+    extern __shared__ u64 zb_raw[];
+    double* rsh = reinterpret_cast<double*>(zb_raw);
+    double* ztl = rsh + ZB * 4 * VS;
+    const int pid = tb.ext_prime[t];
+    for (int k = threadIdx.x; k < 512; k += TPB) {
+      const int slot = k & 255, rr = k >> 8;
+      if (slot == 0) continue;
+      const int st = 31 - __clz(slot);
+      const int o = slot - (1 << st);
+      const int b = st < 4 ? o : ((o & 15) << (st - 4)) + (o >> 4);
+      const size_t g = (size_t)pid * N + (1 << (8 + st)) + ((2 * pb + rr) << st) + b;
+      ztl[rr * 512 + slot] = itwf[g];
+      ztl[rr * 512 + 256 + slot] = itwq[g];
+    }
+    auto pad = [](int a_) { return a_ + (a_ >> 4); };
+    const int bi = 2 * (int)threadIdx.x, br = bi >> 8, bc = bi & 255;   // row and column in the block
+#pragma unroll
+    for (int zz = 0; zz < ZB; ++zz) {
+      if (zz >= nz) break;
+      double* Ru = rsh + ((zz * 2 + 0) * 2 + br) * VS;
+      double* Rw = rsh + ((zz * 2 + 1) * 2 + br) * VS;
+      Ru[pad(bc)] = canon(su[zz][0]);
+      Ru[pad(bc + 1)] = canon(su[zz][1]);
+      Rw[pad(bc)] = canon(sw[zz][0]);
+      Rw[pad(bc + 1)] = canon(sw[zz][1]);
+    }
+    __syncthreads();
+    // row v = (element zz, component, row) of the block, lane u of 16
+    const int v = (int)threadIdx.x >> 4, u = (int)threadIdx.x & 15;
+    const bool act = v < 4 * nz;
+    double* R = rsh + (act ? v : 0) * VS;
+    const double* tv = ztl + (v & 1) * 512;
+    auto addr = [&](int p_, int j) { return p_ == 0 ? (j << 4) + u : (u << 4) + j; };
+    auto twid = [&](int p_, int k, int j, double& w, double& wq) {
+      const int slot = p_ == 0 ? (1 << k) + (j >> (4 - k)) : (1 << (4 + k)) + ((j >> (4 - k)) << 4) + u;
+      w = tv[slot];
+      wq = tv[256 + slot];
+    };
+    double a[16];
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a[j] = R[pad(addr(1, j))];
+      auto t1 = [&](int k, int j, double& w, double& wq) { twid(1, k, j, w, wq); };
+      fpm::gs_phase16(a, false, qi, qd, t1);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) R[pad(addr(1, j))] = a[j];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) a[j] = R[pad(addr(0, j))];
+      auto t0 = [&](int k, int j, double& w, double& wq) { twid(0, k, j, w, wq); };
+      fpm::gs_phase16(a, true, qi, qd, t0);
+      const int zz = v >> 2, comp = (v >> 1) & 1, rr = v & 1;
+      u64* O = uw + (size_t)(z0 + zz) * suw + (size_t)(comp * ext + t) * N + (size_t)pb * 512 + rr * 256;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) O[addr(0, j)] = f_to_u64(canon(a[j]));
+    }
+    return;
+  }
 #pragma unroll
   for (int zz = 0; zz < ZB; ++zz) {
     if (zz >= nz) break;
@@ -2596,10 +2759,10 @@ void kip(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, c
   check_launch();
 }
 
-void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
+bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
                     const u64* const* gtab, const std::vector<std::vector<uint32_t>>& parts,
                     const std::vector<const u64*>& keys, const u64* masks, u64* uw, size_t suw, u64* ad,
-                    size_t sad, int nq, int limbs, bool dadd) {
+                    size_t sad, int nq, int limbs, bool dadd, bool inv_rows) {
   const ModUpTable& tb = c.h_modup[limbs];
   const int k = (int)parts.size();
   if (limbs < 2 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: masked kip level");
@@ -2645,10 +2808,16 @@ void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
   const size_t gx = (c.N + TPB - 1) / TPB;
   const size_t WA = gx * limbs * E, WB = gx * tb.ext * (size_t)nq * ngr;
   if (WA + WB > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: masked kip grid");
-#define KIP_MASK(BETA, PGV)                                                                                        \
-  LAUNCH((k_kip_hoist_mask<BETA, PGV>), dim3((unsigned)(WA + WB)), dim3(TPB), 0, c.stream, y, sy, x, sx, xcs, gtab, \
-         h, mu, masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n,      \
-         c.ci ? 2 : 1, nq, k, (int)WA, dadd ? 1 : 0, (double)pm)
+  // the last chain limb and the special limbs (those the fused ModDown and
+  // rescale transform back) leave in their inverse row pass: a key-sum
+  // block's 256 positions are one row at N = 2^16
+  const bool inv = inv_rows && dadd && fused_ok(c) && !c.ci;
+  const int inv_from = inv ? limbs - 1 : tb.ext;
+  const size_t mlds = inv ? ((size_t)PG * 2 * (256 + 16) + 512) * sizeof(double) : 0;
+#define KIP_MASK(BETA, PGV)                                                                                          \
+  LAUNCH((k_kip_hoist_mask<BETA, PGV>), dim3((unsigned)(WA + WB)), dim3(TPB), mlds, c.stream, y, sy, x, sx, xcs,    \
+         gtab, h, mu, masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, \
+         c.ci ? 2 : 1, nq, k, (int)WA, dadd ? 1 : 0, (double)pm, c.d_itwf, c.d_itwq, inv_from)
   switch (tb.beta * 10 + PG) {
     case 12: KIP_MASK(1, 2); break;
     case 14: KIP_MASK(1, 4); break;
@@ -2661,11 +2830,12 @@ void kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
   }
 #undef KIP_MASK
   check_launch();
+  return inv;
 }
 
-void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
+bool kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t sown, const u64* const* gtab,
                const HoistArgs& h, const std::vector<const u64*>& keys, u64* uw, size_t suw, const u64* c0_in,
-               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate) {
+               size_t c0_si, u64* c0_out, size_t c0_so, int B, int limbs, bool accumulate, bool inv_special) {
   const ModUpTable& tb = c.h_modup[limbs];
   if (limbs < 1 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: kip level");
   const int lists = h.per_elem ? std::min(B, h.mod) : 1;   // amount lists in h.g
@@ -2707,10 +2877,15 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   if (grouped) {
     const size_t Wz = (c.N / (2 * TPB)) * tb.ext * (size_t)((B + ZB - 1) / ZB);
     if (Wz % 8 != 0 || Wz + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
-#define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                          \
-  LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)(Wz + am.W)), dim3(TPB), 0, c.stream, y, sy, y_own, sown, \
-         gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B,      \
-         accumulate ? 1 : 0, am, c.kip_order)
+    // the special limbs leave in their inverse row pass (two whole rows a
+    // block at N = 2^16; a single launch, not an accumulating one)
+    const bool inv = inv_special && fused_ok(c) && !c.ci && !accumulate;
+    const int inv_from = inv ? limbs : tb.ext;
+    const size_t zlds = inv ? ((size_t)ZB * 4 * (256 + 16) + 1024) * sizeof(double) : 0;
+#define KIP_HOIST_ZB(BETA, ZB_, CH_)                                                                             \
+  LAUNCH((k_kip_hoist_zb<BETA, ZB_, CH_>), dim3((unsigned)(Wz + am.W)), dim3(TPB), zlds, c.stream, y, sy, y_own,    \
+         sown, gtab, h, uw, suw, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, c.ci ? 2 : 1, B, \
+         accumulate ? 1 : 0, am, c.kip_order, c.d_itwf, c.d_itwq, inv_from)
     const int code = tb.beta * 100 + ZB * 10 + CH;
     switch (code) {
       case 124: KIP_HOIST_ZB(1, 2, 4); break;
@@ -2730,7 +2905,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
     }
 #undef KIP_HOIST_ZB
     check_launch();
-    return;
+    return inv;
   }
   const size_t W = gx * tb.ext * B;
   if (W % 8 != 0 || W + am.W > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: hoisted kip grid");
@@ -2745,6 +2920,7 @@ void kip_hoist(const Ctx& c, const u64* y, size_t sy, const u64* y_own, size_t s
   }
 #undef KIP_HOIST
   check_launch();
+  return false;
 }
 
 void moddown_conv(const Ctx& c, const u64* uw, size_t suw, u64* conv, size_t sc, int B, int limbs) {
