@@ -201,6 +201,11 @@ struct FuseArgs {
   int isrc = 0;                  // 1: sources still need their inverse column pass
   const double* itwf = nullptr;  // isrc: inverse twiddles and their quotients w / q
   const double* itwq = nullptr;
+  // epilogue output by reference: the base address is read from device
+  // memory at *out_ref when the kernel runs, the output at base + out_rel
+  // (out itself then only sizes the launch checks)
+  u64* const* out_ref = nullptr;
+  size_t out_rel = 0;
 };
 
 // ----------------------------------------------------------------- device memory
@@ -330,6 +335,8 @@ struct GraphEntry {
   std::vector<uint64_t> key;
   std::shared_ptr<DevicePool> pool;
   DBuf q_slot, out_slot;
+  DBuf out_ref;              // one device word: the replay's output base (by_ref)
+  bool by_ref = false;       // the graph writes its output at *out_ref, not out_slot
   std::vector<DBuf> slots;   // a batch's query slots, one per shape class
   hipGraphExec_t exec = nullptr;
   ~GraphEntry();
@@ -388,6 +395,14 @@ struct Ctx {
   std::shared_ptr<Profiler> prof = std::make_shared<Profiler>();
   bool use_graphs = false;                          // capture and replay matches
   std::vector<std::unique_ptr<GraphEntry>> graphs;  // most recent last
+  // while a match is captured: fused ModDown epilogues whose output lies in
+  // [ref_base, ref_base + ref_words) write it through the device word
+  // ref_dev instead (ref_hits counts them, ref_covered their output words)
+  u64* const* ref_dev = nullptr;
+  const u64* ref_base = nullptr;
+  size_t ref_words = 0;
+  int ref_hits = 0;
+  size_t ref_covered = 0;   // output words those epilogues write
 
   int nprimes() const { return (int)primes.size(); }
   int pid_special(int k) const { return L + 1 + k; }
@@ -523,9 +538,11 @@ void rescale_conv(const Ctx& c, const u64* last, size_t sl, size_t last_comp_str
                   size_t st, int B, int comps, int limbs);
 void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t st, u64* out,
                     size_t so, int B, int comps, int limbs);
-// batch element z is written to out + (z / div) so_hi + (z % div) so_lo
+// batch element z is written to out + (z / div) so_hi + (z % div) so_lo; with
+// ref, the launch also stores ref_val at the device word ref
 void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
-                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs);
+                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs,
+                u64** ref = nullptr, u64* ref_val = nullptr);
 // out[0 .. words) = 0
 void zero(const Ctx& c, u64* out, size_t words);
 // B elements of `words` words: gather out[z] = in[idx[z]] or scatter

@@ -435,6 +435,12 @@ void moddown_add(Ctx& c, u64* uw, int B, int limbs, const u64* add0, size_t sa0,
     f.o_hi = so;
     f.o_lo = (size_t)limbs * N;
     f.wtab = &c.d_moddown->pinv[0][0];
+    if (c.ref_dev && out >= c.ref_base && out < c.ref_base + c.ref_words) {   // a captured match's output
+      f.out_ref = c.ref_dev;
+      f.out_rel = (size_t)(out - c.ref_base);
+      ++c.ref_hits;
+      c.ref_covered += (size_t)B * 2 * limbs * N;
+    }
     audit::check(uw, (size_t)B * suw * sizeof(u64), "fused moddown source");
     if (add0) audit::check(add0, ((size_t)(B - 1) * sa0 + (size_t)limbs * N) * sizeof(u64), "moddown addend 0");
     if (add1) audit::check(add1, ((size_t)(B - 1) * sa1 + (size_t)limbs * N) * sizeof(u64), "moddown addend 1");

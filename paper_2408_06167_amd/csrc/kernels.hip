@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(256, OCC > 0 ? OCC : 1) k_ntt_fast(const u64* 
       const u64* Mn = f.mnd + hi * f.m_hi + lo * f.m_lo + pos;
       Ad = lo == 0 ? (f.add0 ? f.add0 + hi * f.a0_hi + pos : nullptr)
                    : (f.add1 ? f.add1 + hi * f.a1_hi + pos : nullptr);
-      Oe = f.out + hi * f.o_hi + lo * f.o_lo + pos;
+      Oe = (f.out_ref ? *f.out_ref + f.out_rel : f.out) + hi * f.o_hi + lo * f.o_lo + pos;
 #pragma unroll
       for (int j = 0; j < 16; ++j) mr[j] = Mn[addr(0, j)];
       if (Ad) {
@@ -2069,8 +2069,11 @@ __global__ void k_rescale_finish(const u64* in, size_t si, const u64* t, size_t 
 }
 
 // batch element z goes to out + (z / div) * so_hi + (z % div) * so_lo
+// (with ref: one thread also stores ref_val at *ref, the output base a
+// following graph replay reads)
 __global__ void k_copy_limbs(const u64* in, size_t si, size_t ics, u64* out, int div, size_t so_hi,
-                             size_t so_lo, size_t ocs, int limbs, int N) {
+                             size_t so_lo, size_t ocs, int limbs, int N, u64** ref, u64* ref_val) {
+  if (ref && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *ref = ref_val;
   const int l = blockIdx.y % limbs, c = blockIdx.y / limbs;
   const size_t bz = blockIdx.z;
   const u64* I = in + bz * si + c * ics + (size_t)l * N;
@@ -2974,8 +2977,10 @@ void rescale_finish(const Ctx& c, const u64* in, size_t si, const u64* t, size_t
 }
 
 void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u64* out, int div,
-                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs) {
+                size_t so_hi, size_t so_lo, size_t out_comp_stride, int B, int comps, int limbs, u64** ref,
+                u64* ref_val) {
   if (div < 1) BM_THROW(BM_EINVAL, "launch check: copy divisor");
+  if (ref) chk(ref, 1, 0, 0, 1, "copy_limbs reference word");
   chk(in, B, si, 0, (size_t)(comps - 1) * in_comp_stride + (size_t)limbs * c.N, "copy_limbs input");
   {
     const size_t hi = (size_t)((B - 1) / div) * so_hi + (size_t)std::min(B - 1, div - 1) * so_lo;
@@ -2983,7 +2988,7 @@ void copy_limbs(const Ctx& c, const u64* in, size_t si, size_t in_comp_stride, u
   }
   Prof pf(c, "k_copy_limbs", 16.0 * c.N * B * comps * limbs, 0.0);
   LAUNCH(k_copy_limbs, ew_grid(c.N, comps * limbs, B), dim3(TPB), 0, c.stream, in, si,
-                     in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N);
+                     in_comp_stride, out, div, so_hi, so_lo, out_comp_stride, limbs, (int)c.N, ref, ref_val);
   check_launch();
 }
 

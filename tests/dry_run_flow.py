@@ -58,7 +58,7 @@ def flow(preset, shapes, n_templates, hook=None):
                 bm.bm_ct_free(h)
             bm.bm_masks_free(m)
         for s in (1, 2, 1 | bm.BM_LEVEL_MIN, 2 | bm.BM_LEVEL_MIN):
-            bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
+            bm.bm_ctx_set_graphs(ctx, (s & 2) != 0)
             for chunk in (0, 1, 3):
                 bm.bm_ctx_set_group_chunk(ctx, chunk)
                 r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
@@ -71,12 +71,13 @@ def flow(preset, shapes, n_templates, hook=None):
         can_compress = preset in (2, 4) or k == 1
         if d // k <= 32:
             for s in (1 | bm.BM_HOIST, 2 | bm.BM_HOIST | bm.BM_LEVEL_MIN):
-                bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
-                r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
-                bm.bm_decrypt_scores(ctx, sk, r, n_templates)
-                bm.bm_result_free(r)
+                for graphs in (False, True):
+                    bm.bm_ctx_set_graphs(ctx, graphs)
+                    r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
+                    bm.bm_decrypt_scores(ctx, sk, r, n_templates)
+                    bm.bm_result_free(r)
         for s in (2 | bm.BM_COMPRESS, 1 | bm.BM_LEVEL_MIN | bm.BM_COMPRESS):
-            bm.bm_ctx_set_graphs(ctx, s & 2 != 0)
+            bm.bm_ctx_set_graphs(ctx, (s & 2) != 0)
             try:
                 r = bm.bm_match(ctx, evk, q, g, None, schedule=s, out_limbs=0)
             except bm.BMError as e:

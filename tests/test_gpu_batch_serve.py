@@ -58,6 +58,14 @@ def test_graph_replay_equals_eager(bm, preset, d, k, schedule):
                 # eager work and a synchronisation between replays
                 t = bm.bm_op_add(ctx, q, q)
                 bm.bm_ct_free(t)
+        # replays back to back into results that are all alive at once (each
+        # replay's output lands in its own result, none in another's)
+        rs = [bm.bm_match(ctx, evk, q, gal, None, schedule=schedule) for q in queries for _ in range(2)]
+        for n, r in enumerate(rs):
+            for g, (a, b) in enumerate(zip(words_of(bm, ctx, r, p.N), eager[n // 2])):
+                assert_words_equal(a, b, "held replay %d group %d" % (n, g))
+        for r in rs:
+            bm.bm_result_free(r)
     finally:
         bm.bm_ctx_set_graphs(ctx, False)
     for q in queries:
