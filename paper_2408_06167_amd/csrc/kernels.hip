@@ -1813,25 +1813,15 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   // order 0: element groups fastest (the groups of one position block share
   // its key words through L2); order 1: position blocks fastest (an XCD
   // works through one element group's positions while its gathered digit
-  // words stay in L2, the key words streaming past).  With gx a multiple of
-  // 8, each XCD takes an aligned eighth of the positions of every slot and
-  // element group (that order inside its range), so that the slots whose
-  // rows leave in their inverse row pass, more work a block, are spread over
-  // all XCDs instead of falling on the last ones.
-  const int W = (int)gridDim.x - am.W;
-  const int lb = xcd_block((int)blockIdx.x - am.W, W);
-  int zg, pb, t;
-  if (gx % 8 == 0) {
-    const int g8 = gx / 8, per = W / 8, r = lb % per;
-    const int pl = order ? r % g8 : (r / ZG) % g8;
-    zg = order ? (r / g8) % ZG : r % ZG;
-    t = r / (ZG * g8);
-    pb = (lb / per) * g8 + pl;
-  } else {
-    zg = order ? (lb / gx) % ZG : lb % ZG;
-    pb = order ? lb % gx : (lb / ZG) % gx;
-    t = lb / (ZG * gx);
-  }
+  // words stay in L2, the key words streaming past).  The slot is slowest, so
+  // that each XCD gathers from one slot's digits only (over the launch's
+  // amounts, any range of positions gathers from every word of its slot);
+  // dealing every XCD all slots of an eighth of the positions instead
+  // doubled the fetched bytes of this kernel.
+  const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
+  const int zg = order ? (lb / gx) % ZG : lb % ZG;
+  const int pb = order ? lb % gx : (lb / ZG) % gx;
+  const int t = lb / (ZG * gx);
   const int i = 2 * (pb * TPB + (int)threadIdx.x);   // positions i, i + 1
   __shared__ const u64* kp[HOIST_MAX];
   for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];
