@@ -42,11 +42,11 @@ TRAFFIC = {
     # the face match at k = 4, S2 + minimum level + hoisted: the grouped hoisted
     # key inner product, as the autotuner's two usual variants build it
     ("k_kip_hoist_zb<1, 3, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "9bf5658362d56370db0f0c36d445e5d48359a7c6578808ea75dbac363d66073b",
-        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 190202651},
+        "kernels_sha256": "ff0db1fbd24ad74fd085612cb60882d1afdb3fda115b613b4666c9a3c20e6c86",
+        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 192543973},
     ("k_kip_hoist_zb<1, 2, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "9bf5658362d56370db0f0c36d445e5d48359a7c6578808ea75dbac363d66073b",
-        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 191327586},
+        "kernels_sha256": "ff0db1fbd24ad74fd085612cb60882d1afdb3fda115b613b4666c9a3c20e6c86",
+        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 195300986},
 }
 
 
