@@ -42,10 +42,10 @@ TRAFFIC = {
     # the face match at k = 4, S2 + minimum level + hoisted: the grouped hoisted
     # key inner product, as the autotuner's two usual variants build it
     ("k_kip_hoist_zb<1, 3, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "ff0db1fbd24ad74fd085612cb60882d1afdb3fda115b613b4666c9a3c20e6c86",
+        "kernels_sha256": "61d3e3366e0e13b27a57ec0dcad4c39a8c8dd8abe6b81d2450eabee622158a14",
         "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 192543973},
     ("k_kip_hoist_zb<1, 2, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "ff0db1fbd24ad74fd085612cb60882d1afdb3fda115b613b4666c9a3c20e6c86",
+        "kernels_sha256": "61d3e3366e0e13b27a57ec0dcad4c39a8c8dd8abe6b81d2450eabee622158a14",
         "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 195300986},
 }
 
@@ -88,8 +88,9 @@ def parse():
                          "batch: mixed shapes, batched vs per-pair; serve: Poisson arrivals; "
                          "copy: 1 GiB device copy (counter calibration); ntt: batched NTT throughput")
     ap.add_argument("--tuning", default="",
-                    help="fixed knobs group_chunk,kip_variant,ntt_row_views,kip_order,fused_occupancy instead of "
-                         "the autotuner (profiler runs that must launch the same kernels)")
+                    help="fixed knobs group_chunk,kip_variant,ntt_row_views,kip_order,fused_occupancy"
+                         "[,column_sources] instead of the autotuner (profiler runs that must launch the same "
+                         "kernels)")
     ap.add_argument("--scale", type=float, default=1.0, help="gallery size factor for batch/serve")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests per rate")

@@ -189,7 +189,7 @@ def batch(bm, args):
 
     reps = max(2, min(args.steps, 5))
     res, keep = {}, {}
-    default = dict(group_chunk=0, kip_variant=0, ntt_row_views=0, kip_order=0, fused_occupancy=0)
+    default = dict(group_chunk=0, kip_variant=0, ntt_row_views=0, kip_order=0, fused_occupancy=0, column_sources=0)
     for name, fn, knobs in (("plain_per_pair_default_knobs", plain, default), ("plain_per_pair", plain, tuning),
                             ("batched", batched, tuning)):
         bm.bm_ctx_set_tuning(ctx, **knobs)

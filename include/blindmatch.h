@@ -425,14 +425,19 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * memory-side cache) or 1 (the position blocks of an element group side by
  * side: its gathered digit words stay in cache).  fused_occupancy: 0, or 3 or 4
  * to build the fused base-conversion column passes of the N = 2^16
- * transforms for that many resident blocks per compute unit.  Matches captured as graphs
- * keep the knobs they were captured with. */
+ * transforms for that many resident blocks per compute unit.
+ * column_sources: 0, the fused base-conversion column passes (N = 2^16,
+ * standard ring) run the inverse column pass of their source limbs in their
+ * own blocks; 1, a separate inverse column pass transforms each source limb
+ * once before them (fewer launches against less repeated work).  Matches
+ * captured as graphs keep the knobs they were captured with. */
 typedef struct {
   uint32_t group_chunk;
   uint32_t kip_variant;
   uint32_t ntt_row_views;
   uint32_t kip_order;
   uint32_t fused_occupancy;
+  uint32_t column_sources;
 } bm_tuning;
 int bm_ctx_set_tuning(bm_ctx *ctx, const bm_tuning *t);
 int bm_ctx_get_tuning(const bm_ctx *ctx, bm_tuning *t);

@@ -616,14 +616,16 @@ def bm_match_batch(ctx, evk, queries, galleries, schedule=BM_S1, out_limbs=0, st
 class bm_tuning(ctypes.Structure):
     _fields_ = [("group_chunk", ctypes.c_uint32), ("kip_variant", ctypes.c_uint32),
                 ("ntt_row_views", ctypes.c_uint32), ("kip_order", ctypes.c_uint32),
-                ("fused_occupancy", ctypes.c_uint32)]
+                ("fused_occupancy", ctypes.c_uint32), ("column_sources", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
-def bm_ctx_set_tuning(ctx, group_chunk=0, kip_variant=0, ntt_row_views=0, kip_order=0, fused_occupancy=0):
-    t = bm_tuning(int(group_chunk), int(kip_variant), int(ntt_row_views), int(kip_order), int(fused_occupancy))
+def bm_ctx_set_tuning(ctx, group_chunk=0, kip_variant=0, ntt_row_views=0, kip_order=0, fused_occupancy=0,
+                      column_sources=0):
+    t = bm_tuning(int(group_chunk), int(kip_variant), int(ntt_row_views), int(kip_order), int(fused_occupancy),
+                  int(column_sources))
     _check(lib().bm_ctx_set_tuning(ctx, ctypes.byref(t)), "bm_ctx_set_tuning", ctx)
 
 

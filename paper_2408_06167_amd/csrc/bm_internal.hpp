@@ -390,6 +390,7 @@ struct Ctx {
   int ntt_views = 0;               // row-pass views per block of the N = 2^16 transforms (0 = 16)
   int kip_order = 0;               // block order of the grouped hoisted key inner product (0 / 1)
   int fused_occ = 0;               // 4: fused column passes built for 4 resident blocks per CU
+  int col_src = 0;                 // 1: sources' inverse column pass in a launch of its own
 
   bool owns_tables = true;         // false for a lane sharing another context's tables
   std::shared_ptr<Profiler> prof = std::make_shared<Profiler>();

@@ -1120,7 +1120,7 @@ static void match_graph(Ctx& c, const bm_evk* evk, const bm_ct* q, const bm_gall
                                      g->groups, g->k, g->d, g->limbs, (uint64_t)(m ? m->pt.p() : nullptr),
                                      (uint64_t)cmask, schedule, (uint64_t)s.ol, q->limbs, (uint64_t)c.stream,
                                      (uint64_t)c.group_chunk, (uint64_t)c.kip_variant, (uint64_t)c.ntt_views,
-                                     (uint64_t)c.kip_order, (uint64_t)c.fused_occ};
+                                     (uint64_t)c.kip_order, (uint64_t)c.fused_occ, (uint64_t)c.col_src};
   const u64 n_out = bmx::out_cts(s, g->groups, g->d, g->k);
   GraphEntry* e = nullptr;
   for (auto& ge : c.graphs)
@@ -1372,7 +1372,8 @@ static void batch_graph(Ctx& c, const bm_evk* evk, const BatchPlan& bp, const bm
                         const bm_gallery* const* gs, size_t n, uint32_t schedule, uint32_t out_limbs, u64* out) {
   std::vector<uint64_t> key = {0xBA7C4ULL, (uint64_t)evk, (uint64_t)evk->rlk.k.p(), schedule, out_limbs,
                                (uint64_t)c.stream, (uint64_t)c.group_chunk, (uint64_t)c.kip_variant,
-                               (uint64_t)c.ntt_views, (uint64_t)c.kip_order, (uint64_t)c.fused_occ, n};
+                               (uint64_t)c.ntt_views, (uint64_t)c.kip_order, (uint64_t)c.fused_occ,
+                               (uint64_t)c.col_src, n};
   for (const BatchClass& K : bp.cls) {
     key.push_back((uint64_t)(K.masks ? K.masks->pt.p() : nullptr));
     key.push_back((uint64_t)K.cmask);
@@ -1484,12 +1485,14 @@ int bm_ctx_set_tuning(bm_ctx* ctx, const bm_tuning* t) {
     REQUIRE(t->kip_order <= 1, BM_EINVAL, "kip_order: 0 or 1");
     REQUIRE(t->fused_occupancy == 0 || t->fused_occupancy == 3 || t->fused_occupancy == 4, BM_EINVAL,
             "fused_occupancy: 0, 3 or 4");
+    REQUIRE(t->column_sources <= 1, BM_EINVAL, "column_sources: 0 or 1");
     Ctx& c = ctx->c;
     c.group_chunk = (int)t->group_chunk;
     c.kip_variant = (int)t->kip_variant;
     c.ntt_views = (int)t->ntt_row_views;
     c.kip_order = (int)t->kip_order;
     c.fused_occ = (int)t->fused_occupancy;
+    c.col_src = (int)t->column_sources;
   });
 }
 
@@ -1500,14 +1503,16 @@ int bm_ctx_get_tuning(const bm_ctx* ctx, bm_tuning* t) {
   t->ntt_row_views = (uint32_t)ctx->c.ntt_views;
   t->kip_order = (uint32_t)ctx->c.kip_order;
   t->fused_occupancy = (uint32_t)ctx->c.fused_occ;
+  t->column_sources = (uint32_t)ctx->c.col_src;
   return BM_OK;
 }
 
 // Times the batch under every schedule offered (skipping those whose keys or
 // levels the inputs lack), then, under the fastest, each result-invariant
-// knob in turn (coordinate descent: group chunk, key inner product variant,
-// row-pass tiling), checking that every knob setting gives the words of the
-// first and last pair that the default setting gave.
+// knob in turn (coordinate descent: group chunk, key inner product variant
+// and block order, row-pass tiling, fused-pass occupancy, where the source
+// limbs' inverse column pass runs), checking that every knob setting gives
+// the words of the first and last pair that the default setting gave.
 int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, const bm_gallery* const* gs,
                       size_t n_pairs, const uint32_t* schedules, size_t n_schedules, uint32_t out_limbs,
                       uint32_t* best_schedule, bm_tuning* best, double* best_ms) {
@@ -1517,7 +1522,7 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
     Ctx& c = ctx->c;
     c.use_stream(nullptr);
     const int s_chunk = c.group_chunk, s_var = c.kip_variant, s_views = c.ntt_views, s_order = c.kip_order,
-              s_occ = c.fused_occ;
+              s_occ = c.fused_occ, s_src = c.col_src;
     hipEvent_t ea, eb;
     HIP_OK(dev::event_create(&ea, true));
     HIP_OK(dev::event_create(&eb, true));
@@ -1536,15 +1541,16 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       HIP_OK(dev::stream_sync(c.stream));
       c.graphs.clear();
     };
-    // a setting's time: the best of three timed runs, each of enough batches
-    // to last about 5 ms (short batches are timed over many)
+    // a setting's time: the best of five timed runs (three for batches of
+    // 20 ms and more), each of enough batches to last about 5 ms (short
+    // batches are timed over many)
     int reps = 0;
     auto timed = [&](uint32_t sched) {
       drop();
       match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);   // warm-up, capture
       res.clear();
       double best_run = 1e30;
-      for (int run = 0; run < 3; ++run) {
+      for (int run = 0; run < (best_run < 20.0 ? 5 : 3); ++run) {
         const int n = reps > 0 ? reps : 1;
         HIP_OK(dev::event_record(ea, c.stream));
         for (int rep = 0; rep < n; ++rep) match_batch_impl(ctx, evk, qs, gs, n_pairs, sched, out_limbs, res);
@@ -1576,21 +1582,26 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       REQUIRE(bsched != 0, BM_ENOKEY, "no offered schedule can run on these inputs");
       (void)timed(bsched);
       const std::vector<u64> ref = words();
-      int* knob[5] = {&c.group_chunk, &c.kip_variant, &c.kip_order, &c.ntt_views, &c.fused_occ};
-      const std::vector<int> values[5] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 3, 4}};
-      for (int kn = 0; kn < 5; ++kn) {
+      // each knob's values (the current one among them) are timed one after
+      // another and the fastest kept, so that a knob is judged against
+      // measurements of the same moment rather than an earlier best
+      int* knob[6] = {&c.group_chunk, &c.kip_variant, &c.kip_order, &c.ntt_views, &c.fused_occ, &c.col_src};
+      const std::vector<int> values[6] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 3, 4}, {0, 1}};
+      for (int kn = 0; kn < 6; ++kn) {
         int pick = *knob[kn];
+        double pick_ms = 1e30;
         for (int v : values[kn]) {
           *knob[kn] = v;
           const double ms = timed(bsched);
           if (!dev::dry() && words() != ref)   // (a dry run computes nothing to compare)
             BM_THROW(BM_EDEVICE, "a result-invariant knob changed the result words");
-          if (ms < bms) {
-            bms = ms;
+          if (ms < pick_ms) {
+            pick_ms = ms;
             pick = v;
           }
         }
         *knob[kn] = pick;
+        bms = pick_ms;
       }
     } catch (...) {
       res.clear();
@@ -1601,6 +1612,7 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       c.ntt_views = s_views;
       c.kip_order = s_order;
       c.fused_occ = s_occ;
+      c.col_src = s_src;
       (void)dev::event_destroy(ea);
       (void)dev::event_destroy(eb);
       throw;
@@ -1616,6 +1628,7 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       best->ntt_row_views = (uint32_t)c.ntt_views;
       best->kip_order = (uint32_t)c.kip_order;
       best->fused_occupancy = (uint32_t)c.fused_occ;
+      best->column_sources = (uint32_t)c.col_src;
     }
     if (best_ms) *best_ms = bms;
   });

@@ -257,6 +257,7 @@ std::unique_ptr<Ctx> Ctx::make_lane() const {
   l->ntt_views = ntt_views;
   l->kip_order = kip_order;
   l->fused_occ = fused_occ;
+  l->col_src = col_src;
   l->owns_tables = false;
   l->prof = prof;
   HIP_OK(dev::set_device(device));

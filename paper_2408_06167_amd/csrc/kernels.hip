@@ -2315,7 +2315,7 @@ static int isrc_count(const Ctx& c, const FuseArgs& f) {
 }
 
 bool isrc_ok(const Ctx& c, int pro) {
-  if (!fused_ok(c) || c.ci) return false;
+  if (!fused_ok(c) || c.ci || c.col_src == 1) return false;
   const int n = pro == 3 ? 1 : pro == 4 ? c.K + 1 : pro == 2 ? c.K : c.alpha;
   return n >= 1 && n <= 5;
 }

@@ -235,6 +235,8 @@ def input_checks():
         ("rotation without its key", lambda: bm.bm_op_rotate(ctx, evk, a, 3), bm.BM_ENOKEY),
         ("rescale of one limb", lambda: bm.bm_op_rescale(ctx, c1), bm.BM_ELEVEL),
         ("top-1 of no scores", lambda: bm.bm_top1(np.zeros(0)), bm.BM_EINVAL),
+        ("fused occupancy 5", lambda: bm.bm_ctx_set_tuning(ctx, fused_occupancy=5), bm.BM_EINVAL),
+        ("column sources 2", lambda: bm.bm_ctx_set_tuning(ctx, column_sources=2), bm.BM_EINVAL),
     ]
     # handles of another context (its buffers are sized for its own ring)
     ctx2 = bm.bm_ctx_create(bm.bm_params_preset(3), 0)
@@ -522,9 +524,9 @@ def tuning_flow():
                     qs.append(bm.bm_encrypt_query(ctx, pk, rng.standard_normal(d).astype(np.float32), 1, 10 * n + j))
                     gs.append(g)
         for var in range(5):
-            for views, order, occ in ((0, 0, 0), (4, 1, 4), (8, 0, 3), (16, 1, 0)):
+            for views, order, occ, src in ((0, 0, 0, 0), (4, 1, 4, 1), (8, 0, 3, 0), (16, 1, 0, 1)):
                 bm.bm_ctx_set_tuning(ctx, group_chunk=3, kip_variant=var, ntt_row_views=views, kip_order=order,
-                                     fused_occupancy=occ)
+                                     fused_occupancy=occ, column_sources=src)
                 # natural level (hoisted sums at 2 to 4 digits) and minimum level (1 digit)
                 for s in (0x402, 0x502, 0x401):
                     for r in bm.bm_match_batch(ctx, evk, qs, gs, schedule=s):

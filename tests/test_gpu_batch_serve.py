@@ -326,6 +326,7 @@ def test_tuning_knobs_keep_words(bm, schedule):
     settings = [dict(group_chunk=1), dict(group_chunk=2), dict(group_chunk=64)]
     settings += [dict(kip_variant=v, kip_order=o) for v in range(5) for o in (0, 1)]
     settings += [dict(ntt_row_views=w) for w in (4, 8, 16)] + [dict(fused_occupancy=o) for o in (3, 4)]
+    settings += [dict(column_sources=1), dict(column_sources=1, fused_occupancy=3)]
     settings += [dict(group_chunk=3, kip_variant=2, kip_order=1, ntt_row_views=4, fused_occupancy=4)]
     try:
         for st in settings:
