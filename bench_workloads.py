@@ -67,21 +67,28 @@ def fingerprint(bm, args):
     sched, tuning, _ = bm.bm_autotune_batch(ctx, evk, [cq], [gal], [0x101, 0x501, 0x001])
     print("# autotuner: schedule %#x, knobs %s" % (sched, tuning), file=sys.stderr, flush=True)
     steps = max(5, args.steps // 2)
-    bm.bm_result_free(bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream))
+    # each step's result is released once the next step is enqueued (as in
+    # bench.py's timed region), so the steps reuse the pool's result memory
+    prev = None
+    for _ in range(2):
+        r = bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream)
+        if prev is not None:
+            bm.bm_result_free(prev)
+        prev = r
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    rs = []
     t = time.perf_counter()
     for a, b in ev:
         a.record(stream)
-        rs.append(bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream))
+        r = bm.bm_match(ctx, evk, cq, gal, None, schedule=sched, stream=stream.cuda_stream)
         b.record(stream)
+        bm.bm_result_free(prev)
+        prev = r
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t) * 1e3 / steps
     lat = [a.elapsed_time(b) for a, b in ev]
-    scores = bm.bm_decrypt_scores(ctx, sk, rs[-1], X.shape[0])
-    for r in rs:
-        bm.bm_result_free(r)
+    scores = bm.bm_decrypt_scores(ctx, sk, prev, X.shape[0])
+    bm.bm_result_free(prev)
     cos = X.astype(np.float64) @ q.astype(np.float64)
     err = float(np.max(np.abs(scores - cos)))
     # per-kernel roofline from an eager profiled pass

@@ -422,8 +422,11 @@ int bm_match_batch(bm_ctx *ctx, const bm_evk *evk, const bm_ct *const *qs,
  * the row passes of the N = 2^16 transforms, 0 (= 16), 4, 8 or 16.
  * kip_order: block order of that key inner product, 0 (the element groups of
  * a position block side by side: they share its key words through the
- * memory-side cache) or 1 (the position blocks of an element group side by
- * side: its gathered digit words stay in cache).  fused_occupancy: 0, or 3 or 4
+ * memory-side cache), 1 (the position blocks of an element group side by
+ * side: its gathered digit words stay in cache), or 2 and 3 (the element
+ * groups in chunks of 2 or 4, each chunk's groups side by side and its
+ * position blocks one after another: the chunk's digits stay in cache while
+ * each key word serves the chunk).  fused_occupancy: 0, or 3 or 4
  * to build the fused base-conversion column passes of the N = 2^16
  * transforms for that many resident blocks per compute unit.
  * column_sources: 0, the fused base-conversion column passes (N = 2^16,

@@ -1482,7 +1482,7 @@ int bm_ctx_set_tuning(bm_ctx* ctx, const bm_tuning* t) {
     REQUIRE(t->kip_variant <= 4, BM_EINVAL, "kip_variant in 0..4");
     REQUIRE(t->ntt_row_views == 0 || t->ntt_row_views == 4 || t->ntt_row_views == 8 || t->ntt_row_views == 16,
             BM_EINVAL, "ntt_row_views: 0, 4, 8 or 16");
-    REQUIRE(t->kip_order <= 1, BM_EINVAL, "kip_order: 0 or 1");
+    REQUIRE(t->kip_order <= 3, BM_EINVAL, "kip_order: 0 to 3");
     REQUIRE(t->fused_occupancy == 0 || t->fused_occupancy == 3 || t->fused_occupancy == 4, BM_EINVAL,
             "fused_occupancy: 0, 3 or 4");
     REQUIRE(t->column_sources <= 1, BM_EINVAL, "column_sources: 0 or 1");
@@ -1586,7 +1586,8 @@ int bm_autotune_batch(bm_ctx* ctx, const bm_evk* evk, const bm_ct* const* qs, co
       // another and the fastest kept, so that a knob is judged against
       // measurements of the same moment rather than an earlier best
       int* knob[6] = {&c.group_chunk, &c.kip_variant, &c.kip_order, &c.ntt_views, &c.fused_occ, &c.col_src};
-      const std::vector<int> values[6] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1}, {16, 8, 4}, {0, 3, 4}, {0, 1}};
+      const std::vector<int> values[6] = {{8, 16, 32, 64, 128}, {0, 1, 2, 3, 4}, {0, 1, 2, 3}, {16, 8, 4}, {0, 3, 4},
+                                          {0, 1}};
       for (int kn = 0; kn < 6; ++kn) {
         int pick = *knob[kn];
         double pick_ms = 1e30;

@@ -1813,15 +1813,28 @@ __global__ void k_kip_hoist_zb(const u64* y, size_t sy, const u64* x, size_t sx,
   // order 0: element groups fastest (the groups of one position block share
   // its key words through L2); order 1: position blocks fastest (an XCD
   // works through one element group's positions while its gathered digit
-  // words stay in L2, the key words streaming past).  The slot is slowest, so
-  // that each XCD gathers from one slot's digits only (over the launch's
-  // amounts, any range of positions gathers from every word of its slot);
-  // dealing every XCD all slots of an eighth of the positions instead
-  // doubled the fetched bytes of this kernel.
+  // words stay in L2, the key words streaming past); order 2 or 3: the
+  // element groups in chunks of 2 or 4 (when they divide ZG), a chunk's
+  // groups side by side and its position blocks after each other, so that
+  // an XCD's L2 holds the gathered digits of the chunk's elements only while
+  // each key word serves the chunk's groups (many elements: the other orders
+  // re-fetch the digits for every amount, or the keys for every group).
+  // The slot is slowest, so that each XCD gathers from one slot's digits
+  // only (over the launch's amounts, any range of positions gathers from
+  // every word of its slot); dealing every XCD all slots of an eighth of the
+  // positions instead doubled the fetched bytes of this kernel.
   const int lb = xcd_block((int)blockIdx.x - am.W, (int)gridDim.x - am.W);
-  const int zg = order ? (lb / gx) % ZG : lb % ZG;
-  const int pb = order ? lb % gx : (lb / ZG) % gx;
   const int t = lb / (ZG * gx);
+  const int EG = order == 2 ? 2 : order == 3 ? 4 : 0;
+  int zg, pb;
+  if (EG && ZG % EG == 0) {
+    const int r = lb % (ZG * gx);
+    zg = (r / (EG * gx)) * EG + r % EG;
+    pb = (r / EG) % gx;
+  } else {
+    zg = order == 1 ? (lb / gx) % ZG : lb % ZG;
+    pb = order == 1 ? lb % gx : (lb / ZG) % gx;
+  }
   const int i = 2 * (pb * TPB + (int)threadIdx.x);   // positions i, i + 1
   __shared__ const u64* kp[HOIST_MAX];
   for (int a = threadIdx.x; a < h.A; a += TPB) kp[a] = gtab[h.g[a] >> 1];

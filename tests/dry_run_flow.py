@@ -237,6 +237,7 @@ def input_checks():
         ("top-1 of no scores", lambda: bm.bm_top1(np.zeros(0)), bm.BM_EINVAL),
         ("fused occupancy 5", lambda: bm.bm_ctx_set_tuning(ctx, fused_occupancy=5), bm.BM_EINVAL),
         ("column sources 2", lambda: bm.bm_ctx_set_tuning(ctx, column_sources=2), bm.BM_EINVAL),
+        ("key inner product order 4", lambda: bm.bm_ctx_set_tuning(ctx, kip_order=4), bm.BM_EINVAL),
     ]
     # handles of another context (its buffers are sized for its own ring)
     ctx2 = bm.bm_ctx_create(bm.bm_params_preset(3), 0)
@@ -524,7 +525,7 @@ def tuning_flow():
                     qs.append(bm.bm_encrypt_query(ctx, pk, rng.standard_normal(d).astype(np.float32), 1, 10 * n + j))
                     gs.append(g)
         for var in range(5):
-            for views, order, occ, src in ((0, 0, 0, 0), (4, 1, 4, 1), (8, 0, 3, 0), (16, 1, 0, 1)):
+            for views, order, occ, src in ((0, 0, 0, 0), (4, 1, 4, 1), (8, 2, 3, 0), (16, 3, 0, 1)):
                 bm.bm_ctx_set_tuning(ctx, group_chunk=3, kip_variant=var, ntt_row_views=views, kip_order=order,
                                      fused_occupancy=occ, column_sources=src)
                 # natural level (hoisted sums at 2 to 4 digits) and minimum level (1 digit)

@@ -310,13 +310,16 @@ def test_match_batch_face_scale_mixed(bm, schedule):
 def test_tuning_knobs_keep_words(bm, schedule):
     """Every value of every result-invariant knob (group chunk, hoisted key
     inner product variant and block order, row-pass tiling, fused-pass
-    occupancy) gives the words of the default setting, at N = 2^16."""
+    occupancy, where the source limbs' inverse column pass runs) gives the
+    words of the default setting, at N = 2^16.  The 16-dim gallery spans 17
+    ciphertexts, so that a pass of 16 elements has element groups in chunks
+    of 2 and of 4 (block orders 2 and 3) and a ragged last pass."""
     ctx = lib_ctx(2)
     sk, pk, evk = keys(2)
     p = bm.bm_params_preset(2)
     rng = np.random.default_rng(47)
     d, k = (128, 4) if schedule != 0x101 else (16, 1)
-    X = normalize(rng.standard_normal((3000 if k == 4 else 5000, d)))
+    X = normalize(rng.standard_normal((3000 if k == 4 else 33000, d)))
     g = bm.bm_encrypt_gallery(ctx, pk, X, k, SEED, 8800)
     q = bm.bm_encrypt_query(ctx, pk, X[17], SEED, 88)
     bm.bm_ctx_set_tuning(ctx)
@@ -324,7 +327,7 @@ def test_tuning_knobs_keep_words(bm, schedule):
     want = words_of(bm, ctx, r, p.N)
     bm.bm_result_free(r)
     settings = [dict(group_chunk=1), dict(group_chunk=2), dict(group_chunk=64)]
-    settings += [dict(kip_variant=v, kip_order=o) for v in range(5) for o in (0, 1)]
+    settings += [dict(kip_variant=v, kip_order=o) for v in range(5) for o in (0, 1, 2, 3)]
     settings += [dict(ntt_row_views=w) for w in (4, 8, 16)] + [dict(fused_occupancy=o) for o in (3, 4)]
     settings += [dict(column_sources=1), dict(column_sources=1, fused_occupancy=3)]
     settings += [dict(group_chunk=3, kip_variant=2, kip_order=1, ntt_row_views=4, fused_occupancy=4)]
