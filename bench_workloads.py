@@ -64,8 +64,13 @@ def fingerprint(bm, args):
     G, _, _ = bm.bm_gallery_info(gal)
     print("# gallery of %d ciphertexts encrypted in %.1fs" % (G, time.time() - t0), file=sys.stderr, flush=True)
     bm.bm_ctx_set_graphs(ctx, True)
-    sched, tuning, _ = bm.bm_autotune_batch(ctx, evk, [cq], [gal], [0x101, 0x501, 0x001])
-    print("# autotuner: schedule %#x, knobs %s" % (sched, tuning), file=sys.stderr, flush=True)
+    if args.tuning:           # fixed knobs (profiler runs), the schedule given or 0x501
+        bm.bm_ctx_set_tuning(ctx, *[int(v) for v in args.tuning.split(",")])
+        sched, tuning = args.schedule or 0x501, bm.bm_ctx_get_tuning(ctx)
+        print("# fixed: schedule %#x, knobs %s" % (sched, tuning), file=sys.stderr, flush=True)
+    else:
+        sched, tuning, _ = bm.bm_autotune_batch(ctx, evk, [cq], [gal], [0x101, 0x501, 0x001])
+        print("# autotuner: schedule %#x, knobs %s" % (sched, tuning), file=sys.stderr, flush=True)
     steps = max(5, args.steps // 2)
     # each step's result is released once the next step is enqueued (as in
     # bench.py's timed region), so the steps reuse the pool's result memory
