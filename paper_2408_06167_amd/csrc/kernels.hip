@@ -1394,9 +1394,10 @@ __device__ __forceinline__ int xcd_block(int w, int W) { return (w & 7) * (W >> 
 // Runs as the first am.W blocks of a per-element hoisted key inner product
 // launch (the c0 half of the hoisted rotation sum), over a 1-D XCD-aware grid
 // of (element, limb, position block), position block fastest.  The grouped
-// kernel (am.W = 0) forms it in its chain slots' blocks instead: as blocks of
-// their own, the short c0 blocks held the launch's first rounds of slots and
-// cost it a fifth of its time at the face configuration (82 against 65 us).
+// kernel (am.W = 0) forms it in its chain slots' blocks instead, where its
+// gathers overlap the key sums of the other slots' blocks (79.6 against
+// 81.9 us at the face configuration; the c0 sums themselves take about 15 us
+// of the launch either way).
 struct AutomArgs {
   const u64* in;
   size_t si;
