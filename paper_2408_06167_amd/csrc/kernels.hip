@@ -1532,81 +1532,47 @@ __global__ void k_kip_hoist(const u64* y, size_t sy, const u64* x, size_t sx, co
 // of query j (x at x + j sx: c0, then c1 at + xcs, `limbs` limbs, evaluation
 // domain); mask i is at masks + i ml N over every prime (ml limbs: the chain,
 // then the specials).  h.g lists the distinct amounts of all parts, mu.parts[a]
-// the parts that use amount a (bit i), mu.per[i * k1 + n] the n-th amount of
-// part i (k1 = k - 1 amounts a part).
-//   addends (the first WA blocks, limbs < `limbs`):
-//     ad[e][0] = sum over r in {0} u amounts(i) of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1
-//   key sums (the other blocks, every slot t of Q_l u P):
+// the parts that use amount a (bit i).
+//   key sums (every slot t of Q_l u P):
 //     uw[e][c] = sum over a in amounts(i) of phi_a(mask_i) * sum_d phi_a(y_d[j]) key_{a,d,c}
 //   and, with dadd, P ad[e][c] added at the last chain slot (the form the
-//   fused ModDown and rescale take).
-// A key-sum thread serves one word of one slot for PG parts of one query: the
-// inner sum of each amount is formed once and multiplied into every part of
-// the group that uses it.  The gathers read phi_a(v)[pos] = v[autom_src(pos)].
+//   fused ModDown and rescale take);
+//   addends (the chain slots t < `limbs`):
+//     ad[e][0] = sum over r in {0} u amounts(i) of phi_r(mask_i x_0),  ad[e][1] = mask_i x_1.
+// A thread serves one word of one slot for PG parts of one query: the inner
+// sum of each amount is formed once and multiplied into every part of the
+// group that uses it, and at a chain slot the same mask words times the
+// gathered x_0 word go to the addends.  The gathers read
+// phi_a(v)[pos] = v[autom_src(pos)].  (The addends once had blocks of their
+// own, ahead of the key sums: they cost the launch 13 of its 51 us at the
+// face configuration.)
 struct MaskUse {
   uint16_t parts[HOIST_MAX];
-  uint16_t per[HOIST_MAX];
 };
 
 template <int BETA, int PG>
 __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t sx, size_t xcs,
                                  const u64* const* gtab, HoistArgs h, MaskUse mu, const u64* masks, int ml,
                                  u64* uw, size_t suw, u64* ad, size_t sad, const ModUpTable* T, int key_limbs,
-                                 int L1, const PrimeC* P, int log_n, int ms, int nq, int k, int WA, int dadd,
+                                 int L1, const PrimeC* P, int log_n, int ms, int nq, int k, int dadd,
                                  double pmd, const double* itwf, const double* itwq, int inv_from) {
   const int N = 1 << log_n;
   const ModUpTable& tb = *T;
   const int limbs = tb.limbs;
-  const int k1 = k - 1;
-  // sum over r in {0} u amounts(i) of mask_i[s_r] x0[s_r] at limb t, and
-  // mask_i x1 at pos, as exact residues (every product within 1.25 q, folded
-  // every second one)
-  auto addends = [&](int e, int t, int pos, u64& a0, u64& a1) {
-    const int j = e / k, i = e % k;
-    const PrimeC& pr = P[t];
-    const double q = (double)pr.q, qi = __longlong_as_double((long long)pr.pad[1]);
-    const u64* M = masks + ((size_t)i * ml + t) * N;
-    const u64* X0 = x + (size_t)j * sx + (size_t)t * N;
-    const u64* X1 = X0 + xcs;
-    double s = fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X0[pos]), qi, q);
-    for (int n = 0; n < k1; ++n) {
-      const u32 src = autom_src((u32)pos, h.g[mu.per[i * k1 + n]], log_n, ms);
-      s = __dadd_rn(s, fmul_mod_q(u64_to_f(M[src]), u64_to_f(X0[src]), qi, q));
-      if (n & 1) s = fred(s, qi, q);
-    }
-    double r = fred(s, qi, q);
-    a0 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
-    r = fred(fmul_mod_q(u64_to_f(M[pos]), u64_to_f(X1[pos]), qi, q), qi, q);
-    a1 = f_to_u64(r < 0.0 ? __dadd_rn(r, q) : r);
-  };
-  // Both parts take (position block, ..., ...) with the position block
-  // slowest and the logical blocks dealt to the 8 XCDs in contiguous ranges
-  // (xcd_block, when the part's block count is a multiple of 8): each XCD
-  // takes an aligned eighth of the positions of every slot.  For one
+  // The blocks take (position block, slot, query, part group) with the
+  // position block slowest and the logical blocks dealt to the 8 XCDs in
+  // contiguous ranges (xcd_block, when the block count is a multiple of 8):
+  // each XCD takes an aligned eighth of the positions of every slot.  For one
   // automorphism an aligned eighth gathers from one aligned eighth of every
   // limb (the automorphisms permute the eighths; rotations keep the two
   // halves), so each amount's gathers of an XCD stay within one eighth of
   // the digits, masks and query limbs.
-  const int nA = nq * k;
-  if ((int)blockIdx.x < WA) {
-    const int lb = WA % 8 == 0 ? xcd_block((int)blockIdx.x, WA) : (int)blockIdx.x;
-    const int e = lb % nA;
-    const int t = (lb / nA) % limbs;
-    const int pos = (lb / (nA * limbs)) * TPB + threadIdx.x;
-    if (pos >= N) return;
-    u64 a0, a1;
-    addends(e, t, pos, a0, a1);
-    u64* A0 = ad + (size_t)e * sad + (size_t)t * N;
-    A0[pos] = a0;
-    A0[(size_t)limbs * N + pos] = a1;
-    return;
-  }
   const int ext = tb.ext;
   const int ngr = (k + PG - 1) / PG;                          // part groups of a query
   // (position block, slot, query and part group): the blocks of one position
   // block and slot, next to each other, share their key words through L2
-  const int WB = (int)gridDim.x - WA;
-  const int lb = WB % 8 == 0 ? xcd_block((int)blockIdx.x - WA, WB) : (int)blockIdx.x - WA;
+  const int WB = (int)gridDim.x;
+  const int lb = WB % 8 == 0 ? xcd_block((int)blockIdx.x, WB) : (int)blockIdx.x;
   const int jg = lb % (nq * ngr);
   const int t = (lb / (nq * ngr)) % ext;
   const int pb = lb / (nq * ngr * ext);
@@ -1639,6 +1605,20 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   double su[PG], sw[PG];
 #pragma unroll
   for (int p = 0; p < PG; ++p) su[p] = sw[p] = 0.0;
+  // a chain slot's thread also forms the addends of its group's parts at its
+  // position: sa[p] = sum over r in {0} u amounts(i) of mask_i[s_r] x0[s_r]
+  // (the mask words the key sums read, the query's c0 gathered beside them;
+  // every product within 1.25 q, the sums folded with the key sums), and
+  // mask_i x1 after the loop
+  const bool adh = t < limbs;
+  const u64* X0 = x + (size_t)j * sx + (size_t)(adh ? t : 0) * N;
+  double sa[PG];
+#pragma unroll
+  for (int p = 0; p < PG; ++p) {
+    sa[p] = 0.0;
+    if (adh && i0 + p < k)
+      sa[p] = fred(fmul_mod_q(u64_to_f(masks[((size_t)(i0 + p) * ml + t) * N + pos]), u64_to_f(X0[pos]), qi, q), qi, q);
+  }
   // MC amounts at a time, every word of them requested before the first
   // product (a ragged chunk repeats the last amount, unused); each amount adds
   // at most one product to a part's sums, which are folded after every
@@ -1648,13 +1628,14 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
   int np = 0;
   for (int a0 = 0; a0 < h.A; a0 += MC) {
     unsigned use[MC];
-    u64 v[MC][BETA], mw[MC][PG];
+    u64 v[MC][BETA], mw[MC][PG], xv[MC];
     double kb[MC][BETA], ka[MC][BETA];
 #pragma unroll
     for (int c2 = 0; c2 < MC; ++c2) {
       const int a = a0 + c2 < h.A ? a0 + c2 : h.A - 1;
       use[c2] = a0 + c2 < h.A ? up[a] & gmask : 0u;
       const u32 s = autom_src((u32)pos, h.g[a], log_n, ms);
+      xv[c2] = adh ? X0[s] : 0;
       const gdp key = (gdp)kp[a];
 #pragma unroll
       for (int d = 0; d < BETA; ++d) {
@@ -1689,6 +1670,7 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
             const double m = u64_to_f(mw[c2][p]);
             su[p] = __dadd_rn(su[p], fmul_mod_q(iu, m, qi, q));
             sw[p] = __dadd_rn(sw[p], fmul_mod_q(iw, m, qi, q));
+            if (adh) sa[p] = __dadd_rn(sa[p], fmul_mod_q(m, u64_to_f(xv[c2]), qi, q));
           }
         }
       }
@@ -1697,6 +1679,7 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
         for (int p = 0; p < PG; ++p) {
           su[p] = fred(su[p], qi, q);
           sw[p] = fred(sw[p], qi, q);
+          sa[p] = fred(sa[p], qi, q);
         }
       }
     }
@@ -1737,12 +1720,17 @@ __global__ void k_kip_hoist_mask(const u64* y, size_t sy, const u64* x, size_t s
     if (i >= k) break;
     const int e = j * k + i;
     double vu = su[p], vw = sw[p];
-    if (dadd && t == limbs - 1) {
-      u64 a0, a1;
-      addends(e, t, pos, a0, a1);
-      const double pmq = pmd / q;
-      vu = __dadd_rn(fred(vu, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
-      vw = __dadd_rn(fred(vw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
+    if (adh) {   // the addends of part i at limb t: to ad, and P times them at the last chain limb
+      const u64 a0 = res(sa[p]);
+      const u64 a1 = res(fmul_mod_q(u64_to_f(masks[((size_t)i * ml + t) * N + pos]), u64_to_f(X0[xcs + pos]), qi, q));
+      u64* A = ad + (size_t)e * sad + (size_t)t * N;
+      A[pos] = a0;
+      A[(size_t)limbs * N + pos] = a1;
+      if (dadd && t == limbs - 1) {
+        const double pmq = pmd / q;
+        vu = __dadd_rn(fred(vu, qi, q), fmul_mod(u64_to_f(a0), pmd, pmq, q));
+        vw = __dadd_rn(fred(vw, qi, q), fmul_mod(u64_to_f(a1), pmd, pmq, q));
+      }
     }
     if (inv) {
       rsh[(p * 2 + 0) * VS + pad((int)threadIdx.x)] = canon(vu);
@@ -2800,7 +2788,7 @@ bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
   if (limbs < 2 || limbs > c.L + 1) BM_THROW(BM_EINVAL, "launch check: masked kip level");
   if (nq < 1 || k < 2 || k > 16) BM_THROW(BM_EINVAL, "launch check: masked kip parts");
   if (tb.beta < 1 || tb.beta > HOIST_BETA) BM_THROW(BM_EINVAL, "launch check: digits of the masked kip");
-  // distinct Galois elements, the parts that use each, and each part's list
+  // distinct Galois elements and the parts that use each
   HoistArgs h{};
   MaskUse mu{};
   const size_t k1 = parts[0].size();
@@ -2813,7 +2801,6 @@ bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
       while (a < h.A && h.g[a] != g) ++a;
       if (a == h.A) h.g[h.A++] = g;
       mu.parts[a] = (uint16_t)(mu.parts[a] | (1u << i));
-      mu.per[(size_t)i * k1 + n] = (uint16_t)a;
     }
   }
   const int E = nq * k, ml = c.L + 1 + c.K;
@@ -2838,8 +2825,8 @@ bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
                  2.0 * c.N * limbs * nq + (double)k * ml * c.N + 2.0 * c.N * tb.ext * E + 2.0 * c.N * limbs * E),
           2.0 * c.N * tb.ext * nq * ((double)h.A * tb.beta + (double)k * k1) + (double)c.N * limbs * E * (k1 + 2));
   const size_t gx = (c.N + TPB - 1) / TPB;
-  const size_t WA = gx * limbs * E, WB = gx * tb.ext * (size_t)nq * ngr;
-  if (WA + WB > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: masked kip grid");
+  const size_t WB = gx * tb.ext * (size_t)nq * ngr;   // the chain slots' threads form the addends too
+  if (WB > 0x7fffffff) BM_THROW(BM_EINVAL, "launch check: masked kip grid");
   // the last chain limb and the special limbs (those the fused ModDown and
   // rescale transform back) leave in their inverse row pass: a key-sum
   // block's 256 positions are one row at N = 2^16
@@ -2847,9 +2834,9 @@ bool kip_hoist_mask(const Ctx& c, const u64* y, size_t sy, const u64* x, size_t 
   const int inv_from = inv ? limbs - 1 : tb.ext;
   const size_t mlds = inv ? ((size_t)PG * 2 * (256 + 16) + 512) * sizeof(double) : 0;
 #define KIP_MASK(BETA, PGV)                                                                                          \
-  LAUNCH((k_kip_hoist_mask<BETA, PGV>), dim3((unsigned)(WA + WB)), dim3(TPB), mlds, c.stream, y, sy, x, sx, xcs,    \
-         gtab, h, mu, masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n, \
-         c.ci ? 2 : 1, nq, k, (int)WA, dadd ? 1 : 0, (double)pm, c.d_itwf, c.d_itwq, inv_from)
+  LAUNCH((k_kip_hoist_mask<BETA, PGV>), dim3((unsigned)WB), dim3(TPB), mlds, c.stream, y, sy, x, sx, xcs, gtab, h, \
+         mu, masks, ml, uw, suw, ad, sad, c.d_modup + limbs, c.L + 1 + c.K, c.L + 1, c.d_primes, c.log_n,          \
+         c.ci ? 2 : 1, nq, k, dadd ? 1 : 0, (double)pm, c.d_itwf, c.d_itwq, inv_from)
   switch (tb.beta * 10 + PG) {
     case 12: KIP_MASK(1, 2); break;
     case 14: KIP_MASK(1, 4); break;
