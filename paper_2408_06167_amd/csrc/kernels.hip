@@ -1047,15 +1047,32 @@ __global__ void k_tensor(PtrTab A, size_t a_cs, size_t a_ps, PtrTab Bt, size_t b
   const double qd = (double)q, qi = __longlong_as_double((long long)pr.pad[1]);
   EW_LOOP {
     FAcc f0, f1, f2;                      // exact FP64 sums of the products (see FAcc)
-    for (int p = 0; p < parts; ++p) {     // sum of the tensors of `parts` pairs of parts
-      const size_t ao = (size_t)p * a_ps + i, bo = (size_t)p * b_ps + i;
-      const double x0 = u64_to_f(A0[ao]), x1 = u64_to_f(A1[ao]);
-      const double y0 = u64_to_f(B0[bo]), y1 = u64_to_f(B1[bo]);
-      const double y0q = __dmul_rn(y0, qi), y1q = __dmul_rn(y1, qi);
-      f0.add_f(fmul_mod(x0, y0, y0q, qd), qi, qd);
-      f1.add_f(fmul_mod(x0, y1, y1q, qd), qi, qd);
-      f1.add_f(fmul_mod(x1, y0, y0q, qd), qi, qd);
-      f2.add_f(fmul_mod(x1, y1, y1q, qd), qi, qd);
+    // sum of the tensors of `parts` pairs of parts, four parts' words
+    // requested before the first product
+    constexpr int PC = 4;
+    for (int p0 = 0; p0 < parts; p0 += PC) {
+      u64 w[PC][4];
+#pragma unroll
+      for (int c = 0; c < PC; ++c) {
+        const int p = p0 + c < parts ? p0 + c : parts - 1;   // a ragged chunk repeats the last part, unused
+        const size_t ao = (size_t)p * a_ps + i, bo = (size_t)p * b_ps + i;
+        w[c][0] = A0[ao];
+        w[c][1] = A1[ao];
+        w[c][2] = B0[bo];
+        w[c][3] = B1[bo];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // (the scheduler would sink each part's loads to its products)
+#pragma unroll
+      for (int c = 0; c < PC; ++c) {
+        if (p0 + c >= parts) break;
+        const double x0 = u64_to_f(w[c][0]), x1 = u64_to_f(w[c][1]);
+        const double y0 = u64_to_f(w[c][2]), y1 = u64_to_f(w[c][3]);
+        const double y0q = __dmul_rn(y0, qi), y1q = __dmul_rn(y1, qi);
+        f0.add_f(fmul_mod(x0, y0, y0q, qd), qi, qd);
+        f1.add_f(fmul_mod(x0, y1, y1q, qd), qi, qd);
+        f1.add_f(fmul_mod(x1, y0, y0q, qd), qi, qd);
+        f2.add_f(fmul_mod(x1, y1, y1q, qd), qi, qd);
+      }
     }
     u64 d0 = f0.residue(qi, qd), d1 = f1.residue(qi, qd), d2 = f2.residue(qi, qd);
     if (accumulate) {
