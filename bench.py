@@ -42,11 +42,11 @@ TRAFFIC = {
     # the face match at k = 4, S2 + minimum level + hoisted: the grouped hoisted
     # key inner product, as the autotuner's two usual variants build it
     ("k_kip_hoist_zb<1, 3, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "de619e9f2f61e0d2fa4086119af71d91cf76455301501bf186b5c6fb56ae6624",
-        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 207093083},
+        "kernels_sha256": "1f77b813cb8904ca6851426e9c82c0de83ce7c2c575bbc42c828d5f5647dcddd",
+        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 207849277},
     ("k_kip_hoist_zb<1, 2, 4>", "k4_S2+levelmin+hoist"): {
-        "kernels_sha256": "de619e9f2f61e0d2fa4086119af71d91cf76455301501bf186b5c6fb56ae6624",
-        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 228418045},
+        "kernels_sha256": "1f77b813cb8904ca6851426e9c82c0de83ce7c2c575bbc42c828d5f5647dcddd",
+        "algorithmic_bytes_per_launch": 180355072, "bytes_per_launch": 228512294},
 }
 
 
